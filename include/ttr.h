@@ -1,0 +1,150 @@
+/*
+ * ttr.h -- tensor-train (TT) arithmetic on one AMD MI355X (gfx950).
+ *
+ * C ABI of libttr.so.  Every entry point takes plain host structs whose core
+ * pointers are DEVICE pointers (HIP global memory on the handle's device), and
+ * enqueues its kernels on the handle's HIP stream.  No torch or C++ types
+ * appear here.  The operations are those of "Parallel Algorithms for Tensor
+ * Train Arithmetic" (Al Daas, Ballard, Benner):
+ *   sum (§3.2.1), Hadamard product (§3.2.2), inner product (§3.2.3, eq. (4)),
+ *   norms (§3.2.4), orthonormalization (§2.3 Alg. 1; §3.4 Alg. 5) and
+ *   rounding (§2.4 Alg. 2; §3.5 Alg. 6).
+ *
+ * TT layout (§2.1, §3.1).  A TT tensor has N cores; core n (0-based here,
+ * n = 0..N-1) is an R[n] x I[n] x R[n+1] array of doubles with R[0] = R[N] = 1,
+ * stored in the paper's "natural descending" order: entry (a, i, b) at offset
+ *     a + R[n] * (i + I[n] * b).
+ * Both the horizontal unfolding H (R[n] x I[n]R[n+1]) and the vertical
+ * unfolding V (R[n]I[n] x R[n+1]) are then column-major views of the buffer.
+ *
+ * Ownership.  The library never frees caller memory and keeps no caller
+ * pointer after a call returns.  It owns a device workspace attached to the
+ * handle (allocated with hipMalloc on first need, grown on demand, released by
+ * ttr_destroy).  A handle is bound to one device and one stream; use one
+ * handle per host thread.
+ *
+ * Errors.  Every call returns TTR_OK (0) or a TTR_ERR_* code and records a
+ * message readable with ttr_last_error().  Argument errors are detected on the
+ * host before any device work is enqueued.  Calls marked "synchronizes" wait
+ * for the stream before returning.
+ */
+#ifndef TTR_H
+#define TTR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum ttr_status {
+  TTR_OK = 0,
+  TTR_ERR_INVALID_ARG = 1,  /* NULL pointer, rank/size <= 0, R[0] or R[N] != 1, tol < 0 or NaN */
+  TTR_ERR_SHAPE = 2,        /* operands disagree on N or mode sizes */
+  TTR_ERR_CAPACITY = 3,     /* an output core's cap[] is smaller than what the result needs */
+  TTR_ERR_ALLOC = 4,        /* workspace allocation failed */
+  TTR_ERR_HIP = 5,          /* a HIP runtime call failed */
+  TTR_ERR_NUMERICAL = 6,    /* non-finite data or a small factorization that did not converge */
+  TTR_ERR_UNSUPPORTED = 7   /* a rank above the supported maximum (TTR_MAX_RANK) */
+};
+
+enum { TTR_RIGHT = 0, TTR_LEFT = 1 };             /* orthonormalization side (§2.3) */
+enum { TTR_RLR = 0, TTR_LRL = 1 };                 /* rounding sweep order (§4.3.2) */
+enum { TTR_NORM_ORTHO = 0, TTR_NORM_GRAM = 1 };    /* norm method (§3.2.4) */
+enum { TTR_FP64 = 0, TTR_MIXED = 1 };              /* arithmetic of the Gram passes */
+
+/* Largest TT rank the kernels accept. */
+#define TTR_MAX_RANK 64
+
+/* A TT tensor.  All arrays are HOST memory; core[n] are DEVICE pointers.
+ *   N      number of cores (>= 1)
+ *   I      N mode sizes (> 0)
+ *   R      N+1 ranks; R[0] = R[N] = 1.  Output tensors get R overwritten.
+ *   core   N device pointers, core n holding R[n]*I[n]*R[n+1] doubles
+ *   cap    N capacities in doubles of the output cores (ignored for inputs,
+ *          may be NULL there). */
+typedef struct ttr_tt {
+  int32_t N;
+  const int64_t *I;
+  int64_t *R;
+  double **core;
+  const int64_t *cap;
+} ttr_tt;
+
+typedef struct ttr_handle ttr_handle;
+
+/* Creates a handle on HIP device `device` that enqueues on `stream`
+ * (a hipStream_t passed as void*; NULL = the device's null stream). */
+int ttr_create(ttr_handle **h, int device, void *stream);
+int ttr_destroy(ttr_handle *h);
+int ttr_set_stream(ttr_handle *h, void *stream);
+
+/* Z = alpha*X + beta*Y, slice-wise (§3.2.1): first core [alpha X_1, beta Y_1],
+ * interior slices blockdiag(X_n(i), Y_n(i)) with the X block first, last core
+ * [X_N; Y_N]; ranks add.  For N = 1 the single core is alpha X_1 + beta Y_1.
+ * Z's cores must not alias X's or Y's.  Z->R is written.  Asynchronous. */
+int ttr_add(ttr_handle *h, double alpha, const ttr_tt *X, double beta, const ttr_tt *Y, ttr_tt *Z);
+
+/* Z = X .* Y, slice-wise Kronecker products (§3.2.2):
+ * Z_n(i) = X_n(i) (x) Y_n(i), row (a_x, a_y) -> a_x*R^Y + a_y, same for columns;
+ * ranks multiply.  Z->R is written.  Asynchronous. */
+int ttr_hadamard(ttr_handle *h, const ttr_tt *X, const ttr_tt *Y, ttr_tt *Z);
+
+/* *out = <X, Y> by the recursion W_n = sum_i Y_n(i)^T W_{n-1} X_n(i), W_0 = 1
+ * (§3.2.3, eq. (4)).  `out` is host memory.  Synchronizes. */
+int ttr_dot(ttr_handle *h, const ttr_tt *X, const ttr_tt *Y, double *out);
+
+/* *out = ||X|| (§3.2.4).  TTR_NORM_GRAM: sqrt(<X, X>) (fast; cancellation for
+ * small norms of difference tensors).  TTR_NORM_ORTHO: right-orthonormalization
+ * sweep (implicit, X untouched) then ||X_1||_F (§2.3; accurate for small
+ * norms).  Synchronizes. */
+int ttr_norm(ttr_handle *h, const ttr_tt *X, int method, double *out);
+
+/* In-place orthonormalization (§2.3 Alg. 1; explicit factors as in §3.4 Alg. 5).
+ * TTR_RIGHT: H(X_n) row-orthonormal for n >= 2 and core 1 carries the norm;
+ * TTR_LEFT: V(X_n) column-orthonormal for n <= N-1 and core N carries the norm.
+ * The factorizations reveal numerical rank: a link whose unfolding is
+ * numerically rank-deficient (e.g. Y + Y) gets the smaller rank, and X->R is
+ * updated; the tensor is preserved to rounding error.  `prec` is TTR_FP64.
+ * Synchronizes. */
+int ttr_orthogonalize(ttr_handle *h, ttr_tt *X, int side, int prec);
+
+/* Y = rounding of X to relative accuracy tol (§2.4 Alg. 2): ||X - Y|| <= tol ||X||.
+ * TTR_RLR: right-orthonormalization sweep (orthonormal factors kept implicit,
+ * §3.5), threshold delta = tol ||X|| / sqrt(N-1), then left-to-right truncation
+ * with the smallest rank whose Frobenius tail of singular values is <= delta;
+ * output cores 1..N-1 are left-orthonormal.  TTR_LRL: the mirror image.
+ * X is read only; Y's cores need cap[n] >= R[n]*I[n]*R[n+1] of X (always
+ * enough, ranks never grow).  Y->R receives the new ranks; *norm_out (host,
+ * nullable) receives the ||X|| used for delta.  tol = 0 keeps every direction
+ * above rounding level; N = 1 copies.  `prec`: TTR_FP64 or TTR_MIXED.
+ * Synchronizes. */
+int ttr_round(ttr_handle *h, const ttr_tt *X, double tol, int direction, int prec,
+              ttr_tt *Y, double *norm_out);
+
+const char *ttr_status_string(int status);
+const char *ttr_last_error(void);
+
+/* Per-call statistics of the last ttr_round on this handle (host memory):
+ * number of streaming Gram passes, materialization passes, small-factorization
+ * launches, and the singular values met at each link (N-1 links, up to
+ * TTR_MAX_RANK each, descending, zero padded). */
+typedef struct ttr_round_stats {
+  int32_t gram_passes;
+  int32_t apply_passes;
+  int32_t small_launches;
+  int32_t links;
+  double norm;
+  double delta;
+  double sigma[TTR_MAX_RANK * 64];
+  int32_t nsigma[64];
+} ttr_round_stats;
+
+int ttr_get_round_stats(const ttr_handle *h, ttr_round_stats *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TTR_H */

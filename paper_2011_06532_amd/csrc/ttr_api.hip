@@ -1,0 +1,630 @@
+// Host side of libttr: argument checking, workspace, and the sweeps of TT
+// orthonormalization (§2.3 Alg. 1, §3.4 Alg. 5) and TT rounding (§2.4 Alg. 2,
+// §3.5 Alg. 6).  All arithmetic runs in the kernels of ttr_stream.hip and
+// ttr_small.hip; this file only plans launches and reads back the small
+// integer decisions (ranks, pass counts) that size the next launch.
+#include "../../include/ttr.h"
+#include "ttr_internal.h"
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+struct ttr_handle {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  double *ws = nullptr;
+  size_t ws_bytes = 0;
+  int *dec_host = nullptr;  // pinned
+  int *dec_dev = nullptr;
+  double *scal_host = nullptr;  // pinned scalars
+  ttr_round_stats stats;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess) return fail(TTR_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+const double kTau1 = 1e-3;   // pass-1 eigenvalue ratio above which one Gram pass is enough
+const double kTau2 = 1e-12;  // preconditioned eigenvalues below this are rounding noise
+
+int check_tt(const ttr_tt *X, const char *name, int max_rank) {
+  if (!X) return fail(TTR_ERR_INVALID_ARG, std::string(name) + " is NULL");
+  if (X->N < 1) return fail(TTR_ERR_INVALID_ARG, std::string(name) + ": N must be >= 1");
+  if (!X->I || !X->R || !X->core) return fail(TTR_ERR_INVALID_ARG, std::string(name) + ": NULL array");
+  if (X->R[0] != 1 || X->R[X->N] != 1)
+    return fail(TTR_ERR_INVALID_ARG, std::string(name) + ": boundary ranks must be 1");
+  for (int n = 0; n < X->N; ++n) {
+    if (X->I[n] <= 0) return fail(TTR_ERR_INVALID_ARG, std::string(name) + ": mode size must be > 0");
+    if (X->R[n + 1] <= 0) return fail(TTR_ERR_INVALID_ARG, std::string(name) + ": rank must be > 0");
+    if (!X->core[n]) return fail(TTR_ERR_INVALID_ARG, std::string(name) + ": NULL core pointer");
+    if (max_rank > 0 && (X->R[n] > max_rank || X->R[n + 1] > max_rank))
+      return fail(TTR_ERR_UNSUPPORTED, std::string(name) + ": rank above TTR_MAX_RANK");
+  }
+  return TTR_OK;
+}
+
+int check_out(const ttr_tt *Z, const char *name, int N, const int64_t *I) {
+  if (!Z) return fail(TTR_ERR_INVALID_ARG, std::string(name) + " is NULL");
+  if (Z->N != N) return fail(TTR_ERR_SHAPE, std::string(name) + ": N differs");
+  if (!Z->I || !Z->R || !Z->core || !Z->cap) return fail(TTR_ERR_INVALID_ARG, std::string(name) + ": NULL array");
+  for (int n = 0; n < N; ++n) {
+    if (Z->I[n] != I[n]) return fail(TTR_ERR_SHAPE, std::string(name) + ": mode sizes differ");
+    if (!Z->core[n]) return fail(TTR_ERR_INVALID_ARG, std::string(name) + ": NULL core pointer");
+  }
+  return TTR_OK;
+}
+
+int ensure_ws(ttr_handle *h, size_t bytes) {
+  if (bytes <= h->ws_bytes) return TTR_OK;
+  if (h->ws) {
+    HIPCHK(hipStreamSynchronize(h->stream));
+    HIPCHK(hipFree(h->ws));
+    h->ws = nullptr;
+    h->ws_bytes = 0;
+  }
+  if (hipMalloc(&h->ws, bytes) != hipSuccess) {
+    h->ws = nullptr;
+    return fail(TTR_ERR_ALLOC, "workspace allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  h->ws_bytes = bytes;
+  return TTR_OK;
+}
+
+// Workspace carve-up (in doubles).  Every small matrix slot holds RMAX^2.
+constexpr size_t kSlot = (size_t)TTR_RMAX * TTR_RMAX;
+constexpr int kStagesPerCore = 3;
+struct WS {
+  double *partials, *G, *Ra, *Rb, *Gst[3], *Pa, *Pb, *GU, *Wa, *Wb, *scal, *sigma, *Tn, *Bst, *tmp;
+  int *dec;
+  double *T(int n) const { return Tn + (size_t)n * kSlot; }
+  double *B(int n, int j) const { return Bst + ((size_t)n * kStagesPerCore + j) * kSlot; }
+};
+size_t ws_doubles(int N, size_t tmp) {
+  return (size_t)TTR_MAXWG * kSlot + 12 * kSlot + 64 + (size_t)(N + 1) * TTR_RMAX +
+         (size_t)(N + 2) * (1 + kStagesPerCore) * kSlot + tmp + 64;
+}
+WS carve(ttr_handle *h, int N, size_t tmp) {
+  WS w;
+  double *p = h->ws;
+  w.partials = p; p += (size_t)TTR_MAXWG * kSlot;
+  w.G = p; p += kSlot;
+  w.Ra = p; p += kSlot;
+  w.Rb = p; p += kSlot;
+  for (int j = 0; j < 3; ++j) { w.Gst[j] = p; p += kSlot; }
+  w.Pa = p; p += kSlot;
+  w.Pb = p; p += kSlot;
+  w.GU = p; p += kSlot;
+  w.Wa = p; p += kSlot;
+  w.Wb = p; p += kSlot;
+  p += kSlot;  // spare
+  w.scal = p; p += 64;
+  w.sigma = p; p += (size_t)(N + 1) * TTR_RMAX;
+  w.Tn = p; p += (size_t)(N + 2) * kSlot;
+  w.Bst = p; p += (size_t)(N + 2) * kStagesPerCore * kSlot;
+  w.tmp = p; p += tmp;
+  w.dec = h->dec_dev;
+  return w;
+}
+
+int sync_dec(ttr_handle *h) {
+  HIPCHK(hipMemcpyAsync(h->dec_host, h->dec_dev, 16 * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  HIPCHK(hipGetLastError());
+  if (h->dec_host[2] != 0) return fail(TTR_ERR_NUMERICAL, "non-finite data or a small factorization did not converge");
+  return TTR_OK;
+}
+
+int reset_dec(ttr_handle *h) {
+  for (int i = 0; i < 16; ++i) h->dec_host[i] = 0;
+  HIPCHK(hipMemcpyAsync(h->dec_dev, h->dec_host, 16 * sizeof(int), hipMemcpyHostToDevice, h->stream));
+  return TTR_OK;
+}
+
+// Logical sequence of cores: RLR / right side uses the cores as stored; LRL /
+// left side uses the reversed train with transposed slices (the mirror image).
+struct Seq {
+  const ttr_tt *X;
+  int rev;
+  int N() const { return X->N; }
+  int phys(int n) const { return rev ? X->N - 1 - n : n; }
+  CoreView view(int n) const {
+    const int p = phys(n);
+    CoreView cv;
+    cv.X = X->core[p];
+    cv.I = X->I[p];
+    cv.pa = (int)X->R[p];
+    cv.pb = (int)X->R[p + 1];
+    cv.trans = rev;
+    return cv;
+  }
+  // logical rank at logical link l (between logical cores l-1 and l), l = 0..N
+  int64_t rank(int l) const { return rev ? X->R[X->N - l] : X->R[l]; }
+};
+
+// Stage constructors (column-major small matrices)
+Stage st_plain(const double *M, int rows, int cols) {  // M (rows x cols, ld rows)
+  Stage s;
+  s.S = M;
+  s.rows = rows;
+  s.cols = cols;
+  s.sr = 1;
+  s.sc = rows;
+  return s;
+}
+Stage st_trans(const double *M, int rows, int cols) {  // M^T where M is (cols x rows, ld cols)
+  Stage s;
+  s.S = M;
+  s.rows = rows;
+  s.cols = cols;
+  s.sr = cols;
+  s.sc = 1;
+  return s;
+}
+Stages no_stages() {
+  Stages s;
+  s.nl = 0;
+  s.nr = 0;
+  return s;
+}
+
+// The orthonormal factor of one core's orthonormalization QR, kept as stages
+// F_1 ... F_j (F_i is dim[i] x dim[i+1]); dim[0] = left rank of the core.
+struct Factor {
+  int nst = 0;
+  int dim[4] = {0, 0, 0, 0};
+};
+
+// One QR-by-Gram factorization of a tall-skinny unfolding of a logical core,
+// through up to three streaming Gram passes.
+//   LEFT  (orthonormalization sweep): A = H(C)^T with C(i) = base(M(i)); the
+//         stages F_j^T are appended as LEFT stages, pass Gram sum Z Z^T.
+//   RIGHT (truncation sweep): A = V(C'), C'(i) = base(M(i)); the stages F_j are
+//         appended as RIGHT stages, pass Gram sum Z^T Z.
+// `slot(j)` gives the device slot for stage j.  On return: the collapsed R
+// (k x b) in *Rout, the stages recorded in *f.
+template <class SlotFn>
+int qr_by_gram(ttr_handle *h, WS &w, const CoreView &cv, int mode, const Stages &base, int b, SlotFn slot,
+               double *Tdst, Factor *f, double **Rout, int *kout, int *passes) {
+  double *R[2] = {w.Ra, w.Rb};
+  const double *Rc = nullptr;
+  int d = b;
+  f->nst = 0;
+  f->dim[0] = b;
+  Stages st = base;
+  for (int pass = 1; pass <= 3; ++pass) {
+    launch_gram(h->stream, cv, st, mode, w.partials, w.G, 0);
+    ++*passes;
+    QrStepArgs qa;
+    qa.G = w.G;
+    qa.d = d;
+    qa.pass = pass;
+    qa.b = b;
+    qa.Rc = Rc;
+    qa.Fstep = slot(pass - 1);
+    qa.Rnext = R[(pass - 1) & 1];
+    qa.Tdst = Tdst;
+    qa.dec = w.dec;
+    qa.tau1 = kTau1;
+    qa.tau2 = kTau2;
+    launch_qr_step(h->stream, qa);
+    h->stats.small_launches++;
+    int rc = sync_dec(h);
+    if (rc) return rc;
+    const int k = h->dec_host[0];
+    const int done = h->dec_host[1];
+    f->nst = pass;
+    f->dim[pass] = k;
+    if (mode == GRAM_LEFT) st.L[st.nl++] = st_trans(qa.Fstep, k, d);
+    else st.R[st.nr++] = st_plain(qa.Fstep, d, k);
+    Rc = qa.Rnext;
+    d = k;
+    if (done) {
+      *Rout = qa.Rnext;
+      *kout = k;
+      return TTR_OK;
+    }
+  }
+  return fail(TTR_ERR_NUMERICAL, "QR-by-Gram did not settle in three passes");
+}
+
+// Orthonormalization sweep over logical cores N-1..1 (Alg. 1 order), implicit
+// factors as in Alg. 6: for each core the stages of B_n and T_n = R_n^T are
+// kept in the workspace, k[n] is the rank at logical link n.  When `Out` is
+// given, each orthonormal core B_n^T M_n(i) T_{n+1} is written to it (Alg. 5).
+int orth_sweep(ttr_handle *h, WS &w, const Seq &S, std::vector<int> &k, std::vector<Factor> &fac, ttr_tt *Out,
+               int *passes) {
+  const int N = S.N();
+  k.assign(N + 1, 1);
+  fac.assign(N + 1, Factor());
+  for (int n = 0; n <= N; ++n) k[n] = (int)S.rank(n);
+  for (int n = N - 1; n >= 1; --n) {
+    const CoreView cv = S.view(n);
+    const int b = cv.ea();
+    Stages base = no_stages();
+    if (n < N - 1) base.R[base.nr++] = st_plain(w.T(n + 1), cv.eb(), k[n + 1]);
+    double *Rout;
+    int kn;
+    auto slot = [&](int j) { return w.B(n, j); };
+    int rc = qr_by_gram(h, w, cv, GRAM_LEFT, base, b, slot, w.T(n), &fac[n], &Rout, &kn, passes);
+    if (rc) return rc;
+    k[n] = kn;
+    if (Out) {
+      Stages st = no_stages();
+      for (int j = 0; j < fac[n].nst; ++j) st.L[st.nl++] = st_trans(w.B(n, j), fac[n].dim[j + 1], fac[n].dim[j]);
+      if (n < N - 1) st.R[st.nr++] = st_plain(w.T(n + 1), cv.eb(), k[n + 1]);
+      launch_apply(h->stream, cv, st, w.tmp, S.rev);
+      const int pn = S.phys(n);
+      const size_t cnt = (size_t)kn * cv.I * k[n + 1];
+      HIPCHK(hipMemcpyAsync(Out->core[pn], w.tmp, cnt * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+    }
+  }
+  return TTR_OK;
+}
+
+int handle_ok(ttr_handle *h) {
+  if (!h) return fail(TTR_ERR_INVALID_ARG, "handle is NULL");
+  HIPCHK(hipSetDevice(h->device));
+  return TTR_OK;
+}
+
+size_t max_core(const ttr_tt *X) {
+  size_t m = 0;
+  for (int n = 0; n < X->N; ++n) {
+    const size_t c = (size_t)X->R[n] * X->I[n] * X->R[n + 1];
+    if (c > m) m = c;
+  }
+  return m;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ttr_create(ttr_handle **h, int device, void *stream) {
+  if (!h) return fail(TTR_ERR_INVALID_ARG, "h is NULL");
+  int ndev = 0;
+  HIPCHK(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(TTR_ERR_INVALID_ARG, "no such device");
+  HIPCHK(hipSetDevice(device));
+  ttr_handle *p = new ttr_handle();
+  p->device = device;
+  p->stream = (hipStream_t)stream;
+  std::memset(&p->stats, 0, sizeof(p->stats));
+  if (hipHostMalloc((void **)&p->dec_host, 16 * sizeof(int)) != hipSuccess ||
+      hipHostMalloc((void **)&p->scal_host, 16 * sizeof(double)) != hipSuccess ||
+      hipMalloc((void **)&p->dec_dev, 16 * sizeof(int)) != hipSuccess) {
+    delete p;
+    return fail(TTR_ERR_ALLOC, "handle allocation failed");
+  }
+  *h = p;
+  return TTR_OK;
+}
+
+int ttr_destroy(ttr_handle *h) {
+  if (!h) return TTR_OK;
+  (void)hipSetDevice(h->device);
+  (void)hipStreamSynchronize(h->stream);
+  if (h->ws) (void)hipFree(h->ws);
+  if (h->dec_dev) (void)hipFree(h->dec_dev);
+  if (h->dec_host) (void)hipHostFree(h->dec_host);
+  if (h->scal_host) (void)hipHostFree(h->scal_host);
+  delete h;
+  return TTR_OK;
+}
+
+int ttr_set_stream(ttr_handle *h, void *stream) {
+  if (!h) return fail(TTR_ERR_INVALID_ARG, "handle is NULL");
+  h->stream = (hipStream_t)stream;
+  return TTR_OK;
+}
+
+int ttr_add(ttr_handle *h, double alpha, const ttr_tt *X, double beta, const ttr_tt *Y, ttr_tt *Z) {
+  int rc;
+  if ((rc = handle_ok(h))) return rc;
+  if ((rc = check_tt(X, "X", 0))) return rc;
+  if ((rc = check_tt(Y, "Y", 0))) return rc;
+  if (X->N != Y->N) return fail(TTR_ERR_SHAPE, "X and Y differ in N");
+  for (int n = 0; n < X->N; ++n)
+    if (X->I[n] != Y->I[n]) return fail(TTR_ERR_SHAPE, "X and Y differ in mode sizes");
+  if ((rc = check_out(Z, "Z", X->N, X->I))) return rc;
+  const int N = X->N;
+  std::vector<int64_t> R(N + 1, 1);
+  for (int n = 1; n < N; ++n) R[n] = X->R[n] + Y->R[n];
+  for (int n = 0; n < N; ++n) {
+    if (Z->core[n] == X->core[n] || Z->core[n] == Y->core[n]) return fail(TTR_ERR_INVALID_ARG, "Z aliases an input");
+    if (Z->cap[n] < R[n] * X->I[n] * R[n + 1]) return fail(TTR_ERR_CAPACITY, "Z core capacity too small");
+  }
+  for (int n = 0; n < N; ++n)
+    launch_add(h->stream, n, N, alpha, beta, X->core[n], (int)X->R[n], (int)X->R[n + 1], Y->core[n], (int)Y->R[n],
+               (int)Y->R[n + 1], X->I[n], Z->core[n]);
+  HIPCHK(hipGetLastError());
+  for (int n = 0; n <= N; ++n) Z->R[n] = R[n];
+  return TTR_OK;
+}
+
+int ttr_hadamard(ttr_handle *h, const ttr_tt *X, const ttr_tt *Y, ttr_tt *Z) {
+  int rc;
+  if ((rc = handle_ok(h))) return rc;
+  if ((rc = check_tt(X, "X", 0))) return rc;
+  if ((rc = check_tt(Y, "Y", 0))) return rc;
+  if (X->N != Y->N) return fail(TTR_ERR_SHAPE, "X and Y differ in N");
+  for (int n = 0; n < X->N; ++n)
+    if (X->I[n] != Y->I[n]) return fail(TTR_ERR_SHAPE, "X and Y differ in mode sizes");
+  if ((rc = check_out(Z, "Z", X->N, X->I))) return rc;
+  const int N = X->N;
+  std::vector<int64_t> R(N + 1, 1);
+  for (int n = 0; n <= N; ++n) R[n] = X->R[n] * Y->R[n];
+  for (int n = 0; n < N; ++n) {
+    if (Z->core[n] == X->core[n] || Z->core[n] == Y->core[n]) return fail(TTR_ERR_INVALID_ARG, "Z aliases an input");
+    if (Z->cap[n] < R[n] * X->I[n] * R[n + 1]) return fail(TTR_ERR_CAPACITY, "Z core capacity too small");
+  }
+  for (int n = 0; n < N; ++n)
+    launch_hadamard(h->stream, X->core[n], (int)X->R[n], (int)X->R[n + 1], Y->core[n], (int)Y->R[n],
+                    (int)Y->R[n + 1], X->I[n], Z->core[n]);
+  HIPCHK(hipGetLastError());
+  for (int n = 0; n <= N; ++n) Z->R[n] = R[n];
+  return TTR_OK;
+}
+
+int ttr_dot(ttr_handle *h, const ttr_tt *X, const ttr_tt *Y, double *out) {
+  int rc;
+  if ((rc = handle_ok(h))) return rc;
+  if (!out) return fail(TTR_ERR_INVALID_ARG, "out is NULL");
+  if ((rc = check_tt(X, "X", TTR_MAX_RANK))) return rc;
+  if ((rc = check_tt(Y, "Y", TTR_MAX_RANK))) return rc;
+  if (X->N != Y->N) return fail(TTR_ERR_SHAPE, "X and Y differ in N");
+  for (int n = 0; n < X->N; ++n)
+    if (X->I[n] != Y->I[n]) return fail(TTR_ERR_SHAPE, "X and Y differ in mode sizes");
+  const int N = X->N;
+  if ((rc = ensure_ws(h, ws_doubles(N, 0) * sizeof(double)))) return rc;
+  WS w = carve(h, N, 0);
+  h->scal_host[0] = 1.0;
+  HIPCHK(hipMemcpyAsync(w.Wa, h->scal_host, sizeof(double), hipMemcpyHostToDevice, h->stream));
+  double *Wp = w.Wa, *Wn = w.Wb;
+  for (int n = 0; n < N; ++n) {
+    launch_dot_step(h->stream, X->core[n], (int)X->R[n], (int)X->R[n + 1], Y->core[n], (int)Y->R[n],
+                    (int)Y->R[n + 1], X->I[n], Wp, w.partials, Wn);
+    std::swap(Wp, Wn);
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(h->scal_host + 1, Wp, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  *out = h->scal_host[1];
+  return TTR_OK;
+}
+
+int ttr_norm(ttr_handle *h, const ttr_tt *X, int method, double *out) {
+  int rc;
+  if ((rc = handle_ok(h))) return rc;
+  if (!out) return fail(TTR_ERR_INVALID_ARG, "out is NULL");
+  if (method == TTR_NORM_GRAM) {
+    double v;
+    if ((rc = ttr_dot(h, X, X, &v))) return rc;
+    *out = v > 0 ? std::sqrt(v) : 0.0;
+    return TTR_OK;
+  }
+  if (method != TTR_NORM_ORTHO) return fail(TTR_ERR_INVALID_ARG, "unknown norm method");
+  if ((rc = check_tt(X, "X", TTR_MAX_RANK))) return rc;
+  const int N = X->N;
+  if ((rc = ensure_ws(h, ws_doubles(N, 0) * sizeof(double)))) return rc;
+  WS w = carve(h, N, 0);
+  if ((rc = reset_dec(h))) return rc;
+  Seq S{X, 0};
+  std::vector<int> k;
+  std::vector<Factor> fac;
+  int passes = 0;
+  if ((rc = orth_sweep(h, w, S, k, fac, nullptr, &passes))) return rc;
+  // ||X|| = ||C_1||_F with C_1(i) = X_1(i) T_2 (end of §2.3)
+  const CoreView cv = S.view(0);
+  Stages st = no_stages();
+  if (N > 1) st.R[st.nr++] = st_plain(w.T(1), cv.eb(), k[1]);
+  launch_gram(h->stream, cv, st, GRAM_LEFT, w.partials, w.G, 0);
+  launch_sqrt_scalar(h->stream, w.G, w.scal);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(h->scal_host, w.scal, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  *out = h->scal_host[0];
+  return TTR_OK;
+}
+
+int ttr_orthogonalize(ttr_handle *h, ttr_tt *X, int side, int prec) {
+  int rc;
+  if ((rc = handle_ok(h))) return rc;
+  if (side != TTR_RIGHT && side != TTR_LEFT) return fail(TTR_ERR_INVALID_ARG, "side must be TTR_RIGHT or TTR_LEFT");
+  if (prec != TTR_FP64) return fail(TTR_ERR_INVALID_ARG, "ttr_orthogonalize supports TTR_FP64");
+  if ((rc = check_tt(X, "X", TTR_MAX_RANK))) return rc;
+  const int N = X->N;
+  if (N == 1) return TTR_OK;
+  const size_t tmp = max_core(X);
+  if ((rc = ensure_ws(h, ws_doubles(N, tmp) * sizeof(double)))) return rc;
+  WS w = carve(h, N, tmp);
+  if ((rc = reset_dec(h))) return rc;
+  Seq S{X, side == TTR_LEFT};
+  std::vector<int> k;
+  std::vector<Factor> fac;
+  int passes = 0;
+  if ((rc = orth_sweep(h, w, S, k, fac, X, &passes))) return rc;
+  // the first logical core absorbs T_2: C_1(i) = M_1(i) T_2
+  const CoreView cv = S.view(0);
+  Stages st = no_stages();
+  st.R[st.nr++] = st_plain(w.T(1), cv.eb(), k[1]);
+  launch_apply(h->stream, cv, st, w.tmp, S.rev);
+  const int p0 = S.phys(0);
+  HIPCHK(hipMemcpyAsync(X->core[p0], w.tmp, (size_t)cv.I * k[1] * sizeof(double), hipMemcpyDeviceToDevice,
+                        h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  HIPCHK(hipGetLastError());
+  for (int l = 0; l <= N; ++l) {
+    const int pl = S.rev ? N - l : l;
+    X->R[pl] = k[l];
+  }
+  return TTR_OK;
+}
+
+int ttr_round(ttr_handle *h, const ttr_tt *X, double tol, int direction, int prec, ttr_tt *Y, double *norm_out) {
+  int rc;
+  if ((rc = handle_ok(h))) return rc;
+  if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(TTR_ERR_INVALID_ARG, "tol must be finite and >= 0");
+  if (direction != TTR_RLR && direction != TTR_LRL) return fail(TTR_ERR_INVALID_ARG, "unknown direction");
+  if (prec != TTR_FP64 && prec != TTR_MIXED) return fail(TTR_ERR_INVALID_ARG, "unknown precision");
+  if ((rc = check_tt(X, "X", TTR_MAX_RANK))) return rc;
+  if ((rc = check_out(Y, "Y", X->N, X->I))) return rc;
+  const int N = X->N;
+  for (int n = 0; n < N; ++n) {
+    if (Y->core[n] == X->core[n]) return fail(TTR_ERR_INVALID_ARG, "Y aliases X");
+    if (Y->cap[n] < X->R[n] * X->I[n] * X->R[n + 1]) return fail(TTR_ERR_CAPACITY, "Y core capacity too small");
+  }
+  std::memset(&h->stats, 0, sizeof(h->stats));
+  if (N == 1) {
+    HIPCHK(hipMemcpyAsync(Y->core[0], X->core[0], (size_t)X->I[0] * sizeof(double), hipMemcpyDeviceToDevice,
+                          h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    Y->R[0] = Y->R[1] = 1;
+    if (norm_out) *norm_out = NAN;
+    return TTR_OK;
+  }
+  if ((rc = ensure_ws(h, ws_doubles(N, 0) * sizeof(double)))) return rc;
+  WS w = carve(h, N, 0);
+  if ((rc = reset_dec(h))) return rc;
+  const Seq S{X, direction == TTR_LRL};
+  std::vector<int> k;
+  std::vector<Factor> fac;
+  int passes = 0;
+  // Sweep 1: orthonormalization with implicit factors (Alg. 6, first loop).
+  if ((rc = orth_sweep(h, w, S, k, fac, nullptr, &passes))) return rc;
+  // Sweep 2: truncation (Alg. 2 loop / Alg. 6 second loop).  The current core
+  // n is C'_n(i) = [P_n B_n^T] M_n(i) T_{n+1}; its left stages are the
+  // orthonormalization stages of core n with the last one merged into P_n.
+  std::vector<int> L(N + 1, 1);
+  double *Pbuf[2] = {w.Pa, w.Pb};
+  const double *Pcur = nullptr;  // merged last left stage (Lprev x dim)
+  int Lprev = 1;
+  int applies = 0;
+  for (int n = 0; n < N - 1; ++n) {
+    const CoreView cv = S.view(n);
+    const int tr = cv.eb();  // rows of T_{n+1}
+    const int b = k[n + 1];  // columns of A = V(C'_n)
+    Stages base = no_stages();
+    if (n > 0) {
+      const Factor &f = fac[n];
+      for (int j = 0; j + 1 < f.nst; ++j) base.L[base.nl++] = st_trans(w.B(n, j), f.dim[j + 1], f.dim[j]);
+      base.L[base.nl++] = st_plain(Pcur, Lprev, f.dim[f.nst - 1]);
+    }
+    base.R[base.nr++] = st_plain(w.T(n + 1), tr, b);
+    double *Rq;
+    int kq;
+    Factor g;
+    auto slot = [&](int j) { return w.Gst[j]; };
+    rc = qr_by_gram(h, w, cv, GRAM_RIGHT, base, b, slot, nullptr, &g, &Rq, &kq, &passes);
+    if (rc) return rc;
+    const Factor &fn = fac[n + 1];
+    TruncArgs ta;
+    ta.R = Rq;
+    ta.k = kq;
+    ta.b = b;
+    ta.Glast = w.Gst[g.nst - 1];
+    ta.d = g.dim[g.nst - 1];
+    ta.Fn = w.B(n + 1, fn.nst - 1);
+    ta.dn = fn.dim[fn.nst - 1];
+    ta.GU = w.GU;
+    ta.Pnext = Pbuf[n & 1];
+    ta.delta = w.scal + 1;
+    ta.norm = w.scal + 2;
+    ta.first = (n == 0);
+    ta.tol = tol;
+    ta.Nm1 = N - 1;
+    ta.sigma_out = w.sigma + (size_t)n * TTR_RMAX;
+    ta.dec = w.dec;
+    launch_trunc_step(h->stream, ta);
+    h->stats.small_launches++;
+    if ((rc = sync_dec(h))) return rc;
+    const int Ln = h->dec_host[3];
+    L[n + 1] = Ln;
+    // output core n: the same staged chain as the Gram passes, the last
+    // refinement stage merged with U_R[:, :L]
+    Stages st = base;
+    for (int j = 0; j + 1 < g.nst; ++j) st.R[st.nr++] = st_plain(w.Gst[j], g.dim[j], g.dim[j + 1]);
+    st.R[st.nr++] = st_plain(w.GU, ta.d, Ln);
+    launch_apply(h->stream, cv, st, Y->core[S.phys(n)], S.rev);
+    ++applies;
+    Pcur = ta.Pnext;
+    Lprev = Ln;
+  }
+  {
+    const int n = N - 1;
+    const CoreView cv = S.view(n);
+    const Factor &f = fac[n];
+    Stages st = no_stages();
+    for (int j = 0; j + 1 < f.nst; ++j) st.L[st.nl++] = st_trans(w.B(n, j), f.dim[j + 1], f.dim[j]);
+    st.L[st.nl++] = st_plain(Pcur, Lprev, f.dim[f.nst - 1]);
+    launch_apply(h->stream, cv, st, Y->core[S.phys(n)], S.rev);
+    ++applies;
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(h->scal_host, w.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  const int nsig = (N - 1) * TTR_RMAX;
+  std::vector<double> sig(nsig);
+  HIPCHK(hipMemcpyAsync(sig.data(), w.sigma, nsig * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  HIPCHK(hipGetLastError());
+  for (int l = 0; l <= N; ++l) {
+    const int pl = S.rev ? N - l : l;
+    Y->R[pl] = (l == 0 || l == N) ? 1 : L[l];
+  }
+  h->stats.gram_passes = passes;
+  h->stats.apply_passes = applies;
+  h->stats.links = N - 1;
+  h->stats.norm = h->scal_host[2];
+  h->stats.delta = h->scal_host[1];
+  const int nl = (N - 1) < 64 ? (N - 1) : 64;
+  for (int l = 0; l < nl; ++l) {
+    // logical link l+1; stats are reported in physical link order
+    const int pl = S.rev ? (N - 1 - l) - 1 : l;
+    int cnt = 0;
+    for (int j = 0; j < TTR_RMAX; ++j) {
+      h->stats.sigma[pl * TTR_RMAX + j] = sig[(size_t)l * TTR_RMAX + j];
+      if (sig[(size_t)l * TTR_RMAX + j] > 0) cnt = j + 1;
+    }
+    h->stats.nsigma[pl] = cnt;
+  }
+  if (norm_out) *norm_out = h->scal_host[2];
+  return TTR_OK;
+}
+
+const char *ttr_status_string(int status) {
+  switch (status) {
+    case TTR_OK: return "ok";
+    case TTR_ERR_INVALID_ARG: return "invalid argument";
+    case TTR_ERR_SHAPE: return "shape mismatch";
+    case TTR_ERR_CAPACITY: return "output capacity too small";
+    case TTR_ERR_ALLOC: return "allocation failed";
+    case TTR_ERR_HIP: return "HIP runtime error";
+    case TTR_ERR_NUMERICAL: return "numerical failure";
+    case TTR_ERR_UNSUPPORTED: return "unsupported size";
+    default: return "unknown status";
+  }
+}
+
+const char *ttr_last_error(void) { return g_err.c_str(); }
+
+int ttr_get_round_stats(const ttr_handle *h, ttr_round_stats *out) {
+  if (!h || !out) return fail(TTR_ERR_INVALID_ARG, "NULL argument");
+  *out = h->stats;
+  return TTR_OK;
+}
+
+}  // extern "C"

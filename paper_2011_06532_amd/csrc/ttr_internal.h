@@ -1,0 +1,108 @@
+// Internal declarations shared by the host API and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define TTR_RMAX 64          // largest rank the small-matrix kernels hold in LDS
+#define TTR_MAXWG 1024       // most workgroups a streaming pass uses (fixed-order reduction)
+
+// Logical view of one core: slice M(i) is an ea x eb matrix.
+//   trans = 0: M(r, c) = X(r, i, c) of a physical pa x I x pb core (ea = pa, eb = pb)
+//   trans = 1: M(r, c) = X(c, i, r)                                 (ea = pb, eb = pa)
+// Physical layout (a, i, b) -> a + pa*(i + I*b).
+struct CoreView {
+  const double *X;
+  long long I;
+  int pa, pb;
+  int trans;
+  __host__ __device__ int ea() const { return trans ? pb : pa; }
+  __host__ __device__ int eb() const { return trans ? pa : pb; }
+};
+
+// Small dense transforms applied to every slice of a streaming pass, in
+// stages: Z(i) = L_k ... L_1 M(i) R_1 ... R_m.  Left stages are applied first
+// (in order), then right stages (in order), each product rounded on its own.
+// Applying the factors of an ill-conditioned QR one stage at a time (rather
+// than as one collapsed matrix), and identically in every pass that touches
+// the same core, is what keeps the computed orthonormal factors orthonormal.
+//   stage matrix S(r, c) = S[r*sr + c*sc]
+//   left stage:  rows x (current rows) ;  right stage: (current cols) x cols
+struct Stage {
+  const double *S;
+  int rows, cols;
+  long long sr, sc;
+};
+constexpr int kMaxLeft = 4;
+constexpr int kMaxRight = 5;
+struct Stages {
+  int nl, nr;
+  Stage L[kMaxLeft];
+  Stage R[kMaxRight];
+};
+
+enum GramMode { GRAM_LEFT = 0, GRAM_RIGHT = 1 };
+
+// --- streaming kernels (ttr_stream.hip) -----------------------------------
+void launch_add(hipStream_t s, int n, int N, double alpha, double beta, const double *X, int rx0, int rx1,
+                const double *Y, int ry0, int ry1, long long I, double *Z);
+void launch_hadamard(hipStream_t s, const double *X, int rx0, int rx1, const double *Y, int ry0, int ry1,
+                     long long I, double *Z);
+// G (gd x gd, col-major) = sum_i Z(i) Z(i)^T (LEFT, gd = p) or Z(i)^T Z(i) (RIGHT, gd = q).
+// Uses `partials` (TTR_MAXWG * gd * gd doubles).  Returns the workgroup count used.
+int launch_gram(hipStream_t s, const CoreView &cv, const Stages &st, int mode, double *partials, double *G,
+                int mixed);
+// Y(r, i, c) = Z(i)(r, c) into a p x I x q core (trans_out = 0) or its
+// transpose q x I x p (trans_out = 1).
+void launch_apply(hipStream_t s, const CoreView &cv, const Stages &st, double *Y, int trans_out);
+// W (ry1 x rx1) = sum_i Y(i)^T Wp X(i), Wp is ry0 x rx0 col-major.
+void launch_dot_step(hipStream_t s, const double *X, int rx0, int rx1, const double *Y, int ry0, int ry1,
+                     long long I, const double *Wp, double *partials, double *W);
+
+// --- small dense kernels (ttr_small.hip) ----------------------------------
+// One step of QR-by-Gram.  G (d x d) is the Gram of the current staged
+// unfolding A*F_1*...*F_{j-1} (j = pass).  Writes the next stage F_j
+// (d x k, ld d), the collapsed factor Rnext = R_j * Rc (k x b, ld k; Rc = I at
+// pass 1) and, once done, Tdst = Rnext^T (b x k, ld b).
+struct QrStepArgs {
+  const double *G;
+  int d;
+  int pass;            // 1, 2 or 3
+  int b;               // columns of the unfolding
+  const double *Rc;    // d x b (ld d); nullptr at pass 1
+  double *Fstep;       // d x k (ld d)
+  double *Rnext;       // k x b (ld k)
+  double *Tdst;        // when done: Rnext^T (b x k, ld b); may be nullptr
+  int *dec;            // [0] k, [1] done, [2] error flags
+  double tau1, tau2;
+};
+void launch_qr_step(hipStream_t s, const QrStepArgs &a);
+
+// Truncation at one link: SVD of R (k x b), rank L, and the two small factors
+// that carry the result: GU = Glast * U_R[:, :L] (d x L, ld d), the merged last
+// right stage of the output core, and Pnext = Sigma_L V_R[:, :L]^T Fn^T
+// (L x dn, ld L), the merged last left stage of the next core (Fn is the last
+// orthonormalization stage of the next core, dn x b, ld dn).
+struct TruncArgs {
+  const double *R;   // k x b (ld k)
+  int k, b;
+  const double *Glast;  // d x k (ld d)
+  int d;
+  const double *Fn;     // dn x b (ld dn)
+  int dn;
+  double *GU;        // d x L
+  double *Pnext;     // L x dn
+  double *delta;     // device scalar: written at the first link, read afterwards
+  double *norm;      // device scalar
+  int first;
+  double tol;
+  int Nm1;
+  double *sigma_out; // TTR_RMAX values (descending, zero padded)
+  int *dec;          // [3] L, [2] error flags
+};
+void launch_trunc_step(hipStream_t s, const TruncArgs &a);
+
+// Utility: C (m x n, ld m) = A (m x k, ld m) * B (k x n, ld k); one workgroup.
+void launch_small_gemm(hipStream_t s, const double *A, const double *B, double *C, int m, int k, int n);
+// Square root of a 1x1 device value into out (for norms).
+void launch_sqrt_scalar(hipStream_t s, const double *in, double *out);

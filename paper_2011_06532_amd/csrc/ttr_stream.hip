@@ -1,0 +1,467 @@
+// Streaming kernels over TT cores: sum (§3.2.1), Hadamard product (§3.2.2),
+// Gram passes of the tall-skinny unfoldings used by orthonormalization and
+// rounding (§2.3, §2.4, §3.4, §3.5), core x small-matrix application, and the
+// inner-product recursion (§3.2.3, eq. (4)).
+//
+// Core layout (§3.1): entry (a, i, b) of an R0 x I x R1 core at a + R0*(i + I*b).
+// For a fixed b the slices i0..i0+T-1 occupy R0*T contiguous doubles, so a chunk
+// of T slices is read as R1 coalesced panels and staged in LDS.
+#include "ttr_internal.h"
+
+#include <algorithm>
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr size_t kLdsBudget = 60 * 1024;  // bytes of dynamic LDS per workgroup
+
+// ---------------------------------------------------------------------------
+// Sum: one thread per output entry, grid-stride.  Output core n of Z has the
+// X block first (§3.2.1); off-diagonal blocks are explicit zeros.
+// ---------------------------------------------------------------------------
+__global__ void k_add(int n, int N, double alpha, double beta, const double *__restrict__ X, int rx0, int rx1,
+                      const double *__restrict__ Y, int ry0, int ry1, long long I, double *__restrict__ Z) {
+#pragma clang fp contract(off)
+  int zr0, zr1;
+  if (N == 1) {
+    zr0 = 1;
+    zr1 = 1;
+  } else if (n == 0) {
+    zr0 = 1;
+    zr1 = rx1 + ry1;
+  } else if (n == N - 1) {
+    zr0 = rx0 + ry0;
+    zr1 = 1;
+  } else {
+    zr0 = rx0 + ry0;
+    zr1 = rx1 + ry1;
+  }
+  const long long total = (long long)zr0 * I * zr1;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long b = e / ((long long)zr0 * I);
+    const long long rem = e - b * zr0 * I;
+    const long long i = rem / zr0;
+    const int a = (int)(rem - i * zr0);
+    double v;
+    if (N == 1) {
+      // each product rounded on its own, as in the plain definition (no FMA)
+      const double ax = alpha * X[i];
+      const double by = beta * Y[i];
+      v = ax + by;
+    } else if (n == 0) {
+      v = (b < rx1) ? alpha * X[i + I * b] : beta * Y[i + I * (b - rx1)];
+    } else if (n == N - 1) {
+      v = (a < rx0) ? X[a + rx0 * i] : Y[(a - rx0) + ry0 * i];
+    } else if (a < rx0 && b < rx1) {
+      v = X[a + rx0 * (i + I * b)];
+    } else if (a >= rx0 && b >= rx1) {
+      v = Y[(a - rx0) + ry0 * (i + I * (b - rx1))];
+    } else {
+      v = 0.0;
+    }
+    Z[e] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Hadamard: Z(ax*ry0 + ay, i, bx*ry1 + by) = X(ax, i, bx) * Y(ay, i, by).
+// ---------------------------------------------------------------------------
+__global__ void k_hadamard(const double *__restrict__ X, int rx0, int rx1, const double *__restrict__ Y, int ry0,
+                           int ry1, long long I, double *__restrict__ Z) {
+  const int zr0 = rx0 * ry0;
+  const int zr1 = rx1 * ry1;
+  const long long total = (long long)zr0 * I * zr1;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long b = e / ((long long)zr0 * I);
+    const long long rem = e - b * zr0 * I;
+    const long long i = rem / zr0;
+    const int a = (int)(rem - i * zr0);
+    const int ax = a / ry0, ay = a - ax * ry0;
+    const int bx = (int)(b / ry1), by = (int)(b - (long long)bx * ry1);
+    Z[e] = X[ax + rx0 * (i + I * bx)] * Y[ay + ry0 * (i + I * by)];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Chunk staging and the small transforms, shared by the Gram and apply passes.
+// ---------------------------------------------------------------------------
+struct Chunk {
+  const double *Z;  // per-slice matrices, slice t at Z + t*stride, column-major zr x zc
+  int zr, zc;
+  int stride;
+};
+
+__device__ inline void stage_chunk(const CoreView &cv, long long i0, int nt, int T, double *Ms) {
+  const int pa = cv.pa, pb = cv.pb, ea = cv.ea();
+  const long long panel = (long long)pa * nt;
+  const long long total = panel * pb;
+  for (long long e = threadIdx.x; e < total; e += blockDim.x) {
+    const int b = (int)(e / panel);
+    const int rem = (int)(e - (long long)b * panel);
+    const int t = rem / pa;
+    const int a = rem - t * pa;
+    const double v = cv.X[a + (long long)pa * (i0 + t) + (long long)pa * cv.I * b];
+    const int r = cv.trans ? b : a;
+    const int c = cv.trans ? a : b;
+    Ms[(long long)t * pa * pb + r + ea * c] = v;
+  }
+  (void)T;
+}
+
+// Applies the stage list to the nt staged slices: left stages first, then
+// right stages, ping-ponging between two LDS buffers of `buf` doubles per slice.
+__device__ inline Chunk transform_chunk(const CoreView &cv, const Stages &st, int nt, double *Ms, double *B0,
+                                        double *B1, int buf) {
+  const double *cur = Ms;
+  int cr = cv.ea(), cc = cv.eb();
+  int curstride = cv.pa * cv.pb;
+  double *bufs[2] = {B0, B1};
+  int which = 0;
+  for (int j = 0; j < st.nl; ++j) {
+    const Stage S = st.L[j];
+    const int p = S.rows;
+    double *out = bufs[which];
+    const int total = nt * p * cc;
+    for (int e = threadIdx.x; e < total; e += blockDim.x) {
+      const int t = e / (p * cc);
+      const int rem = e - t * p * cc;
+      const int c = rem / p;
+      const int r = rem - c * p;
+      const double *m = cur + (long long)t * curstride + (long long)cr * c;
+      double s = 0.0;
+      for (int k = 0; k < cr; ++k) s += S.S[r * S.sr + k * S.sc] * m[k];
+      out[(long long)t * buf + r + p * c] = s;
+    }
+    __syncthreads();
+    cur = out;
+    curstride = buf;
+    cr = p;
+    which ^= 1;
+  }
+  for (int j = 0; j < st.nr; ++j) {
+    const Stage S = st.R[j];
+    const int q = S.cols;
+    double *out = bufs[which];
+    const int total = nt * cr * q;
+    for (int e = threadIdx.x; e < total; e += blockDim.x) {
+      const int t = e / (cr * q);
+      const int rem = e - t * cr * q;
+      const int c = rem / cr;
+      const int r = rem - c * cr;
+      const double *m = cur + (long long)t * curstride + r;
+      double s = 0.0;
+      for (int k = 0; k < cc; ++k) s += m[(long long)cr * k] * S.S[k * S.sr + c * S.sc];
+      out[(long long)t * buf + r + cr * c] = s;
+    }
+    __syncthreads();
+    cur = out;
+    curstride = buf;
+    cc = q;
+    which ^= 1;
+  }
+  Chunk ch;
+  ch.Z = cur;
+  ch.zr = cr;
+  ch.zc = cc;
+  ch.stride = curstride;
+  return ch;
+}
+
+inline int out_rows(const CoreView &cv, const Stages &st) { return st.nl ? st.L[st.nl - 1].rows : cv.ea(); }
+inline int out_cols(const CoreView &cv, const Stages &st) { return st.nr ? st.R[st.nr - 1].cols : cv.eb(); }
+
+// Largest per-slice intermediate of the stage chain (doubles).
+inline int stage_buf(const CoreView &cv, const Stages &st) {
+  int cr = cv.ea(), cc = cv.eb(), mx = 0;
+  for (int j = 0; j < st.nl; ++j) {
+    cr = st.L[j].rows;
+    mx = std::max(mx, cr * cc);
+  }
+  for (int j = 0; j < st.nr; ++j) {
+    cc = st.R[j].cols;
+    mx = std::max(mx, cr * cc);
+  }
+  return mx;
+}
+
+inline long long per_slice(const CoreView &cv, const Stages &st) {
+  const int nb = (st.nl + st.nr) >= 2 ? 2 : (st.nl + st.nr);
+  return (long long)cv.pa * cv.pb + (long long)nb * stage_buf(cv, st);
+}
+
+inline int chunk_slices(const CoreView &cv, const Stages &st, long long I) {
+  long long T = (long long)(kLdsBudget / sizeof(double)) / std::max(per_slice(cv, st), 1LL);
+  T = std::max(1LL, std::min(T, 64LL));
+  T = std::min(T, std::max(I, 1LL));
+  return (int)T;
+}
+
+inline size_t chunk_lds(const CoreView &cv, const Stages &st, int T) {
+  return (size_t)(per_slice(cv, st) * T) * sizeof(double);
+}
+
+// ---------------------------------------------------------------------------
+// Gram pass: per-workgroup partial G over a contiguous range of slices.
+// Each thread owns up to kMaxOwn entries of the lower triangle.
+// ---------------------------------------------------------------------------
+constexpr int kMaxOwn = (TTR_RMAX * (TTR_RMAX + 1) / 2 + kThreads - 1) / kThreads;
+
+__global__ __launch_bounds__(kThreads) void k_gram(CoreView cv, Stages st, int mode, int T, long long spw, int buf,
+                                                  double *__restrict__ partials) {
+  HIP_DYNAMIC_SHARED(double, smem);
+  const int zr = st.nl ? st.L[st.nl - 1].rows : cv.ea();
+  const int zc = st.nr ? st.R[st.nr - 1].cols : cv.eb();
+  const int gd = (mode == GRAM_LEFT) ? zr : zc;
+  double *Ms = smem;
+  double *B0 = Ms + (long long)T * cv.pa * cv.pb;
+  double *B1 = B0 + (long long)T * buf;
+
+  const int nent = gd * (gd + 1) / 2;
+  int ou[kMaxOwn], ov[kMaxOwn];
+  double acc[kMaxOwn];
+#pragma unroll
+  for (int j = 0; j < kMaxOwn; ++j) {
+    const int e = threadIdx.x + j * kThreads;
+    int u = 0, v = 0;
+    if (e < nent) {
+      u = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+      while (u * (u + 1) / 2 > e) --u;
+      while ((u + 1) * (u + 2) / 2 <= e) ++u;
+      v = e - u * (u + 1) / 2;
+    }
+    ou[j] = u;
+    ov[j] = v;
+    acc[j] = 0.0;
+  }
+
+  const long long beg = (long long)blockIdx.x * spw;
+  const long long end = std::min(beg + spw, cv.I);
+  for (long long i0 = beg; i0 < end; i0 += T) {
+    const int nt = (int)std::min((long long)T, end - i0);
+    stage_chunk(cv, i0, nt, T, Ms);
+    __syncthreads();
+    const Chunk ch = transform_chunk(cv, st, nt, Ms, B0, B1, buf);
+#pragma unroll
+    for (int j = 0; j < kMaxOwn; ++j) {
+      const int e = threadIdx.x + j * kThreads;
+      if (e < nent) {
+        const int u = ou[j], v = ov[j];
+        double s = acc[j];
+        for (int t = 0; t < nt; ++t) {
+          const double *z = ch.Z + (long long)t * ch.stride;
+          if (mode == GRAM_LEFT) {
+            for (int c = 0; c < ch.zc; ++c) s += z[u + ch.zr * c] * z[v + ch.zr * c];
+          } else {
+            const double *zu = z + (long long)ch.zr * u;
+            const double *zv = z + (long long)ch.zr * v;
+            for (int r = 0; r < ch.zr; ++r) s += zu[r] * zv[r];
+          }
+        }
+        acc[j] = s;
+      }
+    }
+    __syncthreads();
+  }
+  double *out = partials + (long long)blockIdx.x * gd * gd;
+#pragma unroll
+  for (int j = 0; j < kMaxOwn; ++j) {
+    const int e = threadIdx.x + j * kThreads;
+    if (e < nent) {
+      out[ou[j] + gd * ov[j]] = acc[j];
+      out[ov[j] + gd * ou[j]] = acc[j];
+    }
+  }
+}
+
+// Fixed-order sum of the per-workgroup partials: G[e] = sum_w partials[w][e].
+__global__ void k_reduce(const double *__restrict__ partials, int nwg, int ne, double *__restrict__ G) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  double s = 0.0;
+  for (int w = 0; w < nwg; ++w) s += partials[(long long)w * ne + e];
+  G[e] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Apply pass: Y(i) = P M(i) Q written as a new core.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_apply(CoreView cv, Stages st, int T, long long spw, int buf,
+                                                   double *__restrict__ Y, int trans_out) {
+  HIP_DYNAMIC_SHARED(double, smem);
+  double *Ms = smem;
+  double *B0 = Ms + (long long)T * cv.pa * cv.pb;
+  double *B1 = B0 + (long long)T * buf;
+  const long long beg = (long long)blockIdx.x * spw;
+  const long long end = std::min(beg + spw, cv.I);
+  const long long I = cv.I;
+  for (long long i0 = beg; i0 < end; i0 += T) {
+    const int nt = (int)std::min((long long)T, end - i0);
+    stage_chunk(cv, i0, nt, T, Ms);
+    __syncthreads();
+    const Chunk ch = transform_chunk(cv, st, nt, Ms, B0, B1, buf);
+    const int p = ch.zr, q = ch.zc;
+    const long long total = (long long)p * nt * q;
+    if (!trans_out) {
+      // output p x I x q: for each column c the chunk is p*nt contiguous doubles
+      const long long panel = (long long)p * nt;
+      for (long long e = threadIdx.x; e < total; e += blockDim.x) {
+        const int c = (int)(e / panel);
+        const int rem = (int)(e - (long long)c * panel);
+        const int t = rem / p;
+        const int r = rem - t * p;
+        Y[r + (long long)p * (i0 + t) + (long long)p * I * c] = ch.Z[(long long)t * ch.stride + r + p * c];
+      }
+    } else {
+      // output q x I x p (transposed slices)
+      const long long panel = (long long)q * nt;
+      for (long long e = threadIdx.x; e < total; e += blockDim.x) {
+        const int r = (int)(e / panel);
+        const int rem = (int)(e - (long long)r * panel);
+        const int t = rem / q;
+        const int c = rem - t * q;
+        Y[c + (long long)q * (i0 + t) + (long long)q * I * r] = ch.Z[(long long)t * ch.stride + r + p * c];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Inner-product step: partial W = sum_i Y(i)^T Wp X(i) (eq. (4)).
+// ---------------------------------------------------------------------------
+constexpr int kMaxOwnFull = (TTR_RMAX * TTR_RMAX + kThreads - 1) / kThreads;
+
+__global__ __launch_bounds__(kThreads) void k_dot_step(const double *__restrict__ X, int rx0, int rx1,
+                                                      const double *__restrict__ Y, int ry0, int ry1, long long I,
+                                                      const double *__restrict__ Wp, int T, long long spw,
+                                                      double *__restrict__ partials) {
+  HIP_DYNAMIC_SHARED(double, smem);
+  double *Xs = smem;                              // T x (rx0 x rx1)
+  double *Ys = Xs + (long long)T * rx0 * rx1;     // T x (ry0 x ry1)
+  double *Zs = Ys + (long long)T * ry0 * ry1;     // T x (ry0 x rx1)
+  const int ne = ry1 * rx1;
+  double acc[kMaxOwnFull];
+#pragma unroll
+  for (int j = 0; j < kMaxOwnFull; ++j) acc[j] = 0.0;
+  CoreView cx{X, I, rx0, rx1, 0};
+  CoreView cy{Y, I, ry0, ry1, 0};
+  const long long beg = (long long)blockIdx.x * spw;
+  const long long end = std::min(beg + spw, I);
+  for (long long i0 = beg; i0 < end; i0 += T) {
+    const int nt = (int)std::min((long long)T, end - i0);
+    stage_chunk(cx, i0, nt, T, Xs);
+    stage_chunk(cy, i0, nt, T, Ys);
+    __syncthreads();
+    const int tz = nt * ry0 * rx1;
+    for (int e = threadIdx.x; e < tz; e += blockDim.x) {
+      const int t = e / (ry0 * rx1);
+      const int rem = e - t * ry0 * rx1;
+      const int c = rem / ry0;
+      const int r = rem - c * ry0;
+      const double *x = Xs + (long long)t * rx0 * rx1 + (long long)rx0 * c;
+      double s = 0.0;
+      for (int k = 0; k < rx0; ++k) s += Wp[r + ry0 * k] * x[k];
+      Zs[(long long)t * ry0 * rx1 + r + ry0 * c] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kMaxOwnFull; ++j) {
+      const int e = threadIdx.x + j * kThreads;
+      if (e < ne) {
+        const int v = e / ry1;
+        const int u = e - v * ry1;
+        double s = acc[j];
+        for (int t = 0; t < nt; ++t) {
+          const double *y = Ys + (long long)t * ry0 * ry1 + (long long)ry0 * u;
+          const double *z = Zs + (long long)t * ry0 * rx1 + (long long)ry0 * v;
+          for (int r = 0; r < ry0; ++r) s += y[r] * z[r];
+        }
+        acc[j] = s;
+      }
+    }
+    __syncthreads();
+  }
+  double *out = partials + (long long)blockIdx.x * ne;
+#pragma unroll
+  for (int j = 0; j < kMaxOwnFull; ++j) {
+    const int e = threadIdx.x + j * kThreads;
+    if (e < ne) out[e] = acc[j];
+  }
+}
+
+int grid_for(long long I, int T) {
+  const long long chunks = (I + T - 1) / T;
+  return (int)std::max(1LL, std::min(chunks, (long long)TTR_MAXWG));
+}
+
+long long slices_per_wg(long long I, int T, int nwg) {
+  long long spw = (I + nwg - 1) / nwg;
+  spw = ((spw + T - 1) / T) * T;
+  return std::max(spw, 1LL);
+}
+
+}  // namespace
+
+void launch_add(hipStream_t s, int n, int N, double alpha, double beta, const double *X, int rx0, int rx1,
+                const double *Y, int ry0, int ry1, long long I, double *Z) {
+  long long total;
+  if (N == 1) total = I;
+  else if (n == 0) total = I * (rx1 + ry1);
+  else if (n == N - 1) total = (long long)(rx0 + ry0) * I;
+  else total = (long long)(rx0 + ry0) * I * (rx1 + ry1);
+  const long long blocks = std::min((total + kThreads - 1) / kThreads, 65536LL);
+  hipLaunchKernelGGL(k_add, dim3((unsigned)std::max(blocks, 1LL)), dim3(kThreads), 0, s, n, N, alpha, beta, X, rx0,
+                     rx1, Y, ry0, ry1, I, Z);
+}
+
+void launch_hadamard(hipStream_t s, const double *X, int rx0, int rx1, const double *Y, int ry0, int ry1, long long I,
+                     double *Z) {
+  const long long total = (long long)rx0 * ry0 * I * rx1 * ry1;
+  const long long blocks = std::min((total + kThreads - 1) / kThreads, 65536LL);
+  hipLaunchKernelGGL(k_hadamard, dim3((unsigned)std::max(blocks, 1LL)), dim3(kThreads), 0, s, X, rx0, rx1, Y, ry0,
+                     ry1, I, Z);
+}
+
+int launch_gram(hipStream_t s, const CoreView &cv, const Stages &st, int mode, double *partials, double *G,
+                int mixed) {
+  (void)mixed;
+  const int T = chunk_slices(cv, st, cv.I);
+  const int nwg = grid_for(cv.I, T);
+  const long long spw = slices_per_wg(cv.I, T, nwg);
+  const int nwg_used = (int)((cv.I + spw - 1) / spw);
+  const size_t lds = chunk_lds(cv, st, T);
+  const int buf = stage_buf(cv, st);
+  hipLaunchKernelGGL(k_gram, dim3(nwg_used), dim3(kThreads), lds, s, cv, st, mode, T, spw, buf, partials);
+  const int gd = (mode == GRAM_LEFT) ? out_rows(cv, st) : out_cols(cv, st);
+  const int ne = gd * gd;
+  hipLaunchKernelGGL(k_reduce, dim3((ne + kThreads - 1) / kThreads), dim3(kThreads), 0, s, partials, nwg_used, ne, G);
+  return nwg_used;
+}
+
+void launch_apply(hipStream_t s, const CoreView &cv, const Stages &st, double *Y, int trans_out) {
+  const int T = chunk_slices(cv, st, cv.I);
+  const int nwg = grid_for(cv.I, T);
+  const long long spw = slices_per_wg(cv.I, T, nwg);
+  const int nwg_used = (int)((cv.I + spw - 1) / spw);
+  const size_t lds = chunk_lds(cv, st, T);
+  const int buf = stage_buf(cv, st);
+  hipLaunchKernelGGL(k_apply, dim3(nwg_used), dim3(kThreads), lds, s, cv, st, T, spw, buf, Y, trans_out);
+}
+
+void launch_dot_step(hipStream_t s, const double *X, int rx0, int rx1, const double *Y, int ry0, int ry1, long long I,
+                     const double *Wp, double *partials, double *W) {
+  const long long per = (long long)rx0 * rx1 + (long long)ry0 * ry1 + (long long)ry0 * rx1;
+  long long T = (long long)(kLdsBudget / sizeof(double)) / std::max(per, 1LL);
+  T = std::max(1LL, std::min(T, 64LL));
+  T = std::min(T, std::max(I, 1LL));
+  const int nwg = grid_for(I, (int)T);
+  const long long spw = slices_per_wg(I, (int)T, nwg);
+  const int nwg_used = (int)((I + spw - 1) / spw);
+  const size_t lds = (size_t)(per * T) * sizeof(double);
+  hipLaunchKernelGGL(k_dot_step, dim3(nwg_used), dim3(kThreads), lds, s, X, rx0, rx1, Y, ry0, ry1, I, Wp, (int)T, spw,
+                     partials);
+  const int ne = ry1 * rx1;
+  hipLaunchKernelGGL(k_reduce, dim3((ne + kThreads - 1) / kThreads), dim3(kThreads), 0, s, partials, nwg_used, ne, W);
+}

@@ -1,0 +1,161 @@
+"""GPU parity of the basic TT operations against the FP64 oracle, through the
+C ABI (libttr.so via its ctypes binding)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+def rand_tt(rng, I, r, scale=1.0):
+    R = [1] + list(r) + [1]
+    return [np.asfortranarray(scale * rng.standard_normal((R[n], I[n], R[n + 1]))) for n in range(len(I))]
+
+
+SHAPES = [
+    ([5, 4, 6], [3, 2]),
+    ([3, 7, 2, 4], [2, 5, 3]),
+    ([6], []),
+    ([4, 1, 5], [2, 2]),                   # I_n = 1
+    ([300, 257, 129], [7, 9]),             # several chunks and a ragged tail
+    ([2000, 3, 1500], [17, 23]),
+]
+
+
+@pytest.fixture(scope="module")
+def h(ttr):
+    hd = ttr.Handle(0)
+    yield hd
+    hd.close()
+
+
+@pytest.mark.parametrize("I,r", SHAPES)
+def test_add_bitwise(ttr, h, I, r):
+    print(f"add I={I} r={r}", flush=True)
+    rng = np.random.default_rng(100)
+    X = rand_tt(rng, I, r)
+    Y = rand_tt(rng, I, [x + 1 for x in r])
+    Z = h.add(1.25, ttr.TT.from_numpy(X), -0.5, ttr.TT.from_numpy(Y)).to_numpy()
+    ref = O.add(1.25, X, -0.5, Y)
+    assert O.ranks(Z) == O.ranks(ref)
+    for z, zr in zip(Z, ref):
+        assert np.array_equal(z, zr)
+
+
+@pytest.mark.parametrize("I,r", SHAPES)
+def test_hadamard_bitwise(ttr, h, I, r):
+    print(f"hadamard I={I} r={r}", flush=True)
+    rng = np.random.default_rng(101)
+    X = rand_tt(rng, I, r)
+    Y = rand_tt(rng, I, [max(1, x - 1) for x in r])
+    Z = h.hadamard(ttr.TT.from_numpy(X), ttr.TT.from_numpy(Y)).to_numpy()
+    ref = O.hadamard(X, Y)
+    assert O.ranks(Z) == O.ranks(ref)
+    for z, zr in zip(Z, ref):
+        assert np.array_equal(z, zr)
+
+
+@pytest.mark.parametrize("I,r", SHAPES)
+def test_dot_and_norms(ttr, h, I, r):
+    print(f"dot/norm I={I} r={r}", flush=True)
+    rng = np.random.default_rng(102)
+    X = rand_tt(rng, I, r)
+    Y = rand_tt(rng, I, [x + 2 for x in r])
+    gx, gy = ttr.TT.from_numpy(X), ttr.TT.from_numpy(Y)
+    ref = O.dot(X, Y)
+    scale = O.norm_ortho(X) * O.norm_ortho(Y)
+    assert abs(h.dot(gx, gy) - ref) <= 1e-12 * scale
+    n = O.norm_ortho(X)
+    assert abs(h.norm(gx, "gram") - n) <= 1e-12 * n
+    assert abs(h.norm(gx, "ortho") - n) <= 1e-12 * n
+
+
+def test_norm_ortho_small_difference(ttr, h):
+    # ||X - (X + 1e-9 Z)|| = 1e-9 ||Z||: the orthonormal route resolves it,
+    # where sqrt(<D, D>) of the difference TT loses it to cancellation (§3.2.4).
+    print("norm of a difference tensor", flush=True)
+    rng = np.random.default_rng(103)
+    I = [50, 60, 40, 30]
+    X = rand_tt(rng, I, [4, 5, 3])
+    Z = rand_tt(rng, I, [2, 2, 2])
+    Xp = O.add(1.0, X, 1e-9, Z)
+    D = O.add(1.0, Xp, -1.0, X)
+    ref = 1e-9 * O.norm_ortho(Z)
+    got = h.norm(ttr.TT.from_numpy(D), "ortho")
+    assert abs(got - ref) <= 1e-6 * ref
+
+
+@pytest.mark.parametrize("side", ["right", "left"])
+@pytest.mark.parametrize("I,r", SHAPES)
+def test_orthogonalize(ttr, h, side, I, r):
+    print(f"orthogonalize {side} I={I} r={r}", flush=True)
+    rng = np.random.default_rng(104)
+    X = rand_tt(rng, I, r, scale=2.0)
+    g = ttr.TT.from_numpy(X)
+    h.orthogonalize(g, side)
+    Y = g.to_numpy()
+    N = len(Y)
+    nrm = O.norm_ortho(X)
+    assert O.diff_norm(Y, X) <= 1e-13 * nrm * max(1, N)
+    if side == "right":
+        for n in range(1, N):
+            Hn = O.H(Y[n])
+            assert np.linalg.norm(Hn @ Hn.T - np.eye(Hn.shape[0])) < 1e-13 * Hn.shape[0]
+    else:
+        for n in range(N - 1):
+            Vn = O.V(Y[n])
+            assert np.linalg.norm(Vn.T @ Vn - np.eye(Vn.shape[1])) < 1e-13 * Vn.shape[1]
+    # generic inputs keep their ranks unless a thin unfolding caps them
+    assert O.ranks(Y) == O.ranks(O.orthogonalize(X, side))
+
+
+def test_orthogonalize_rank_deficient(ttr, h):
+    # Y + Y: every unfolding is exactly rank deficient; the rank-revealing
+    # factorization keeps the numerical rank and preserves the tensor.
+    print("orthogonalize Y+Y", flush=True)
+    rng = np.random.default_rng(105)
+    Yc = rand_tt(rng, [40, 30, 50, 20], [4, 6, 3])
+    X = O.add(1.0, Yc, 1.0, Yc)
+    g = ttr.TT.from_numpy(X)
+    h.orthogonalize(g, "right")
+    Y = g.to_numpy()
+    assert O.ranks(Y) == [1, 4, 6, 3, 1]
+    assert O.diff_norm(Y, X) <= 1e-13 * O.norm_ortho(X) * 4
+    for n in range(1, 4):
+        Hn = O.H(Y[n])
+        assert np.linalg.norm(Hn @ Hn.T - np.eye(Hn.shape[0])) < 1e-12
+
+
+def test_argument_errors(ttr, h):
+    rng = np.random.default_rng(106)
+    X = ttr.TT.from_numpy(rand_tt(rng, [5, 6], [3]))
+    Y = ttr.TT.from_numpy(rand_tt(rng, [5, 7], [3]))
+    with pytest.raises(ttr.TTRError) as e:
+        h.add(1.0, X, 1.0, Y)
+    assert e.value.code == 2  # shape
+    with pytest.raises(ttr.TTRError) as e:
+        h.round(X, -1.0)
+    assert e.value.code == 1
+    with pytest.raises(ttr.TTRError) as e:
+        h.round(X, float("nan"))
+    assert e.value.code == 1
+    small = ttr.TT.empty([5, 6], [1, 1], X.cores[0].device)
+    with pytest.raises(ttr.TTRError) as e:
+        h.round(X, 1e-3, out=small)
+    assert e.value.code == 3  # capacity
+    big = ttr.TT.from_numpy(rand_tt(rng, [3, 3], [65]))
+    with pytest.raises(ttr.TTRError) as e:
+        h.round(big, 1e-3)
+    assert e.value.code == 7
+
+
+def test_nonfinite_input_reports_numerical(ttr, h):
+    rng = np.random.default_rng(107)
+    X = rand_tt(rng, [20, 30, 20], [3, 4])
+    X[1][0, 3, 1] = np.nan
+    with pytest.raises(ttr.TTRError) as e:
+        h.round(ttr.TT.from_numpy(X), 1e-6)
+    assert e.value.code == 6

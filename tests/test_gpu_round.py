@@ -1,0 +1,160 @@
+"""GPU parity of TT rounding (Alg. 2, RLR and LRL) against the FP64 oracle.
+
+Tensors are compared through the oracle's cancellation-free difference norm
+(singular vectors are not unique; App. A makes the tensor and the per-link
+singular values gauge-invariant).  FP64 bar: equal ranks and
+||X~_gpu - X~_oracle|| <= 1e-10 ||X~_oracle||.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-10
+
+
+def rand_tt(rng, I, r, scale=1.0):
+    R = [1] + list(r) + [1]
+    return [np.asfortranarray(scale * rng.standard_normal((R[n], I[n], R[n + 1]))) for n in range(len(I))]
+
+
+@pytest.fixture(scope="module")
+def h(ttr):
+    hd = ttr.Handle(0)
+    yield hd
+    hd.close()
+
+
+def check_round(ttr, h, X, tol, direction, rel=REL, sig_rtol=1e-9):
+    g = ttr.TT.from_numpy(X)
+    Yg, nrm = h.round(g, tol, direction, return_norm=True)
+    got = Yg.to_numpy()
+    ref, info = O.round_tt(X, tol, direction, return_info=True)
+    assert O.ranks(got) == O.ranks(ref), (O.ranks(got), O.ranks(ref))
+    nref = O.norm_ortho(ref)
+    d = O.diff_norm(got, ref)
+    assert d <= rel * max(nref, 1e-300), (d, nref)
+    assert math.isclose(nrm, info["norm"], rel_tol=1e-12)
+    st = h.round_stats()
+    for l, (s_gpu, s_ref) in enumerate(zip(st["sigmas"], info["sigmas"])):
+        k = min(len(s_gpu), len(s_ref))
+        big = np.asarray(s_ref[:k]) > 1e-6 * s_ref[0]
+        assert np.allclose(np.asarray(s_gpu[:k])[big], np.asarray(s_ref[:k])[big], rtol=sig_rtol), l
+    return got, ref
+
+
+@pytest.mark.parametrize("direction", ["RLR", "LRL"])
+def test_round_cfg0_y_plus_y(ttr, h, direction):
+    print(f"round cfg0 Y+Y {direction}", flush=True)
+    d = synth.cfg0()
+    Y = d["Y"]
+    X = O.add(1.0, Y, 1.0, Y)
+    got, ref = check_round(ttr, h, X, d["tol"], direction)
+    assert O.ranks(got) == [1, 5, 5, 5, 1]
+    twoY = O.add(2.0, Y, 0.0, Y)
+    assert O.diff_norm(got, twoY) <= 1e-12 * O.norm_ortho(twoY)
+    # output orthonormality (RLR: left-orthonormal cores 1..N-1)
+    N = len(got)
+    if direction == "RLR":
+        for n in range(N - 1):
+            Vn = O.V(got[n])
+            assert np.linalg.norm(Vn.T @ Vn - np.eye(Vn.shape[1])) < 1e-13 * Vn.shape[1]
+    else:
+        for n in range(1, N):
+            Hn = O.H(got[n])
+            assert np.linalg.norm(Hn @ Hn.T - np.eye(Hn.shape[0])) < 1e-13 * Hn.shape[0]
+
+
+@pytest.mark.parametrize("direction", ["RLR", "LRL"])
+def test_round_cfg1_shape_small_I(ttr, h, direction):
+    # configs[1] structure (N=16, A+B ranks 20 -> 40, scaled) at I = 512
+    print(f"round A+B N=16 I=512 {direction}", flush=True)
+    d = synth.cfg1(I_override=512)
+    X = O.add(1.0, d["A"], 1.0, d["B"])
+    got, ref = check_round(ttr, h, X, d["tol"], direction)
+    assert O.ranks(got)[1:-1] == [40] * 15
+
+
+@pytest.mark.parametrize("direction", ["RLR", "LRL"])
+def test_round_cfg2_shape_small_I(ttr, h, direction):
+    # configs[2] structure: A + B + 1e-6 C (ranks 50) at I = 400
+    print(f"round A+B+1e-6C N=16 I=400 {direction}", flush=True)
+    d = synth.cfg2(I_override=400)
+    X = O.add(1.0, O.add(1.0, d["A"], 1.0, d["B"]), 1.0, d["C"])
+    got, ref = check_round(ttr, h, X, d["tol"], direction, sig_rtol=1e-6)
+    assert O.ranks(got)[1:-1] == [50] * 15
+
+
+@pytest.mark.parametrize("direction", ["RLR", "LRL"])
+def test_round_cfg3_members(ttr, h, direction):
+    # a few members of the batched workload (Y + Y + 1e-9 E), full size
+    shapes = synth.cfg3_shapes(512)
+    for t in (0, 1, 7, 100):
+        I, r = shapes[t]
+        print(f"round Y+Y+E member {t} I={I} r={r} {direction}", flush=True)
+        Yc = synth.random_tt(3, t, "Y", I, r, scaled=True)
+        E = synth.random_tt(3, t, "E", I, [2] * 7, scaled=True, first_core_factor=1e-9)
+        X = O.add(1.0, O.add(1.0, Yc, 1.0, Yc), 1.0, E)
+        got, ref = check_round(ttr, h, X, synth.TOL[3], direction, sig_rtol=1e-6)
+        assert O.ranks(got)[1:-1] == list(r)
+
+
+@pytest.mark.parametrize("tol", [0.5, 1e-2, 1e-5, 1e-9])
+@pytest.mark.parametrize("direction", ["RLR", "LRL"])
+def test_round_graded_spectrum(ttr, h, tol, direction):
+    # content at 1e-3, 1e-6, 1e-9 of the leading part: truncation bites at
+    # different links depending on tol
+    print(f"round graded tol={tol} {direction}", flush=True)
+    rng = np.random.default_rng(200)
+    I = [30, 45, 37, 50, 28]
+    X = rand_tt(rng, I, [5, 6, 6, 4])
+    for eps, r in ((1e-3, [3, 3, 3, 3]), (1e-6, [2, 2, 2, 2]), (1e-9, [2, 3, 2, 2])):
+        Z = rand_tt(rng, I, r)
+        Z[0] = Z[0] * eps
+        X = O.add(1.0, X, 1.0, Z)
+    check_round(ttr, h, X, tol, direction, sig_rtol=1e-5)
+
+
+@pytest.mark.parametrize("direction", ["RLR", "LRL"])
+def test_round_edge_cases(ttr, h, direction):
+    rng = np.random.default_rng(201)
+    print(f"round edge cases {direction}", flush=True)
+    # N = 2 (one link), I_n = 1 modes, tol = 0 on a generic TT, huge tol
+    check_round(ttr, h, rand_tt(rng, [33, 41], [7]), 1e-3, direction)
+    check_round(ttr, h, rand_tt(rng, [7, 1, 9, 1, 5], [3, 3, 4, 2]), 1e-4, direction)
+    check_round(ttr, h, rand_tt(rng, [20, 30, 25], [4, 5]), 0.0, direction)
+    got, ref = check_round(ttr, h, rand_tt(rng, [20, 30, 25], [4, 5]), 10.0, direction)
+    assert O.ranks(got) == [1, 1, 1, 1]
+    # N = 1: copy
+    X1 = rand_tt(rng, [17], [])
+    g = ttr.TT.from_numpy(X1)
+    out = h.round(g, 0.1, direction).to_numpy()
+    assert np.array_equal(out[0], X1[0])
+    # zero tensor: rank-1 zero TT
+    Z = [np.zeros_like(c) for c in rand_tt(rng, [10, 12, 9], [3, 4])]
+    out = h.round(ttr.TT.from_numpy(Z), 1e-3, direction).to_numpy()
+    assert O.ranks(out) == [1, 1, 1, 1]
+    assert all(np.count_nonzero(c) == 0 for c in out)
+
+
+def test_round_error_bound_and_idempotence(ttr, h):
+    print("round bound + idempotence", flush=True)
+    rng = np.random.default_rng(202)
+    I = [60, 70, 50, 40]
+    X = rand_tt(rng, I, [6, 8, 5])
+    Z = rand_tt(rng, I, [3, 3, 3])
+    Z[0] *= 1e-2
+    X = O.add(1.0, X, 1.0, Z)
+    tol = 3e-3
+    g = ttr.TT.from_numpy(X)
+    Yg = h.round(g, tol)
+    Y = Yg.to_numpy()
+    assert O.diff_norm(Y, X) <= tol * O.norm_ortho(X)
+    Y2 = h.round(Yg, 0.0).to_numpy()
+    assert O.ranks(Y2) == O.ranks(Y)
+    assert O.diff_norm(Y2, Y) <= 1e-13 * O.norm_ortho(Y)
