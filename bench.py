@@ -1,0 +1,217 @@
+"""Benchmark: TT rounding of X = A + B (N=16, I=262144, A and B random TTs of
+rank 20, formal ranks 40, ~47 GB of FP64 cores) at relative tolerance 1e-8 on
+one MI355X.
+
+One step = the whole path for this workload on inputs resident in HBM:
+ttr_add(A, B) -> X, then ttr_round(X) (orthonormalization sweep, norm and
+threshold, truncation sweep).  `value` is core-GB/s = bytes of X's cores per
+second of step time.  The JSON line also carries round-only timing, the
+dominant kernel's roofline position (measured with HIP events on the library's
+stream during the timed steps) and the FP64 CPU oracle timed on a bounded
+sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--I 262144]
+"""
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6        # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+RIDGE = FP64_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)   # flop/byte
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in ("ttr_stream.hip", "ttr_small.hip", "ttr_api.hip", "ttr_internal.h"):
+        with open(os.path.join(ROOT, "paper_2011_06532_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def pmc_traffic(kernel_class, per_launch_bytes):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when it is absent or was taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("source_hash") != source_hash():
+        return None
+    ent = d.get("kernels", {}).get(kernel_class)
+    if not ent:
+        return None
+    return ent.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(I_sample, steps=1):
+    """FP64 CPU oracle on a bounded sample: the same workload with I reduced."""
+    import oracle as O
+    import synth
+    from threadpoolctl import threadpool_info
+    d = synth.cfg1(I_override=I_sample)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        X = O.add(1.0, d["A"], 1.0, d["B"])
+        O.round_tt(X, d["tol"], "RLR")
+    dt = (time.perf_counter() - t0) / steps
+    nbytes = O.tt_bytes(X)
+    threads = max([x.get("num_threads", 1) for x in threadpool_info()] or [1])
+    return {
+        "value": round(nbytes / dt / 1e9, 5),
+        "unit": "GB/s",
+        "cores": int(threads),
+        "kind": "oracle",
+        "sample": f"same workload with I={I_sample} instead of 262144 ({nbytes / 1e9:.3f} GB of cores), "
+                  f"add + RLR round, NumPy/OpenBLAS FP64, {dt:.2f} s per step",
+        "ms_per_step": round(dt * 1e3, 2),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--I", type=int, default=262144)
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--direction", default="RLR", choices=["RLR", "LRL"])
+    ap.add_argument("--cpu-sample-I", type=int, default=16384)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is described in DESIGN.md but not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_2011_06532_amd import ttr
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    h = ttr.Handle(0)
+
+    N, r = 16, 20
+    log(f"generating A, B: N={N}, I={args.I}, ranks {r} (host, seeded)")
+    t = time.perf_counter()
+    d = synth.cfg1(I_override=args.I)
+    log(f"  generated in {time.perf_counter() - t:.1f} s; uploading")
+    A = ttr.TT.from_numpy(d["A"])
+    B = ttr.TT.from_numpy(d["B"])
+    del d
+    I = A.I
+    RX = [1] + [A.R[n] + B.R[n] for n in range(1, N)] + [1]
+    caps = [RX[n] * I[n] * RX[n + 1] for n in range(N)]
+    Xbuf = ttr.TT.empty(I, caps)
+    Ybuf = ttr.TT.empty(I, caps)
+    size_x = sum(8 * c for c in caps)
+    tol = synth.TOL[1]
+    torch.cuda.synchronize()
+
+    def step():
+        X = h.add(1.0, A, 1.0, B, out=Xbuf)
+        return X, h.round(X, tol, args.direction, args.prec, out=Ybuf)
+
+    for w in range(args.warmup):
+        log(f"warmup step {w + 1}/{args.warmup}")
+        step()
+    torch.cuda.synchronize()
+
+    h.set_profiling(True)
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        e0, e1, e2 = ev[k]
+        e0.record(stream)
+        X = h.add(1.0, A, 1.0, B, out=Xbuf)
+        e1.record(stream)
+        Y = h.round(X, tol, args.direction, args.prec, out=Ybuf)
+        e2.record(stream)
+        log(f"step {k + 1}/{args.steps}")
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / args.steps
+    prof = h.profile()
+    h.set_profiling(False)
+    st = h.round_stats()
+    ms_step = sum(e0.elapsed_time(e2) for e0, _, e2 in ev) / args.steps
+    ms_round = sum(e1.elapsed_time(e2) for _, e1, e2 in ev) / args.steps
+    ms_add = sum(e0.elapsed_time(e1) for e0, e1, _ in ev) / args.steps
+    ranks_ok = Y.R[1:-1] == [2 * r] * (N - 1)
+
+    # dominant kernel class by time
+    cls = max(("gram", "apply", "add"), key=lambda c: prof[c]["ms"])
+    p = prof[cls]
+    n_launch = max(p["count"], 1)
+    ai = p["flops"] / p["bytes"] if p["bytes"] else 0.0
+    if ai > RIDGE:
+        achieved = p["flops"] / (p["ms"] * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP64_PEAK_TFLOPS, 4)}
+    else:
+        achieved = p["bytes"] / (p["ms"] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4)}
+    roof["traffic"] = pmc_traffic(cls, p["bytes"] / n_launch)
+    roof["kernel"] = {"gram": "k_gram", "apply": "k_apply", "add": "k_add"}[cls]
+    roof["launches"] = p["count"]
+    roof["avg_launch_ms"] = round(p["ms"] / n_launch, 4)
+    roof["algorithmic_bytes_per_launch"] = round(p["bytes"] / n_launch)
+    roof["algorithmic_flops_per_launch"] = round(p["flops"] / n_launch)
+    roof["share_of_step"] = round(p["ms"] / args.steps / ms_step, 3)
+
+    out = {
+        "metric": "TT-round core-GB/s and ms/round, FP64 vs mixed at rel.err <=1e-8, 1 GPU",
+        "value": round(size_x / (ms_step * 1e-3) / 1e9, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.prec == "fp64" else "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": f"X = A + B, N={N}, I={args.I}, A,B random TTs of rank {r} with N(0,1) cores "
+                               f"scaled by 1/sqrt(R_(n-1) I_n), formal ranks {2 * r}, ttr_round tol {tol} "
+                               f"{args.direction} {args.prec}",
+                   "core_bytes_X": size_x},
+        "ms_per_round": round(ms_round, 3),
+        "ms_per_add": round(ms_add, 3),
+        "round_core_GBps": round(size_x / (ms_round * 1e-3) / 1e9, 2),
+        "wall_ms_per_step": round(wall * 1e3, 3),
+        "ranks_ok": ranks_ok,
+        "gram_passes": st["gram_passes"],
+        "apply_passes": st["apply_passes"],
+        "kernel_ms_per_step": {c: round(prof[c]["ms"] / args.steps, 3) for c in prof},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        log(f"cpu_baseline: oracle on I={args.cpu_sample_I}")
+        out["cpu_baseline"] = cpu_baseline(args.cpu_sample_I)
+    h.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

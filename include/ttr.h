@@ -143,6 +143,29 @@ typedef struct ttr_round_stats {
 
 int ttr_get_round_stats(const ttr_handle *h, ttr_round_stats *out);
 
+/* Opt-in kernel timing.  With profiling on, every streaming launch made by the
+ * handle is bracketed by HIP events on the handle's stream and its duration,
+ * count and algorithmic traffic/work are accumulated per kernel class:
+ *   0 Gram pass   bytes = the core read once, flops = the staged slice
+ *                 products plus the (symmetric) Gram accumulation
+ *   1 apply pass  bytes = core read + output core written, flops = products
+ *   2 sum         bytes = both inputs read + output written
+ *   3 Hadamard    bytes = both inputs read + output written, flops = outputs
+ *   4 inner-product step, 5 small dense kernels (one workgroup).
+ * Durations are resolved at the end of each synchronizing call (ttr_dot,
+ * ttr_norm, ttr_orthogonalize, ttr_round) and by ttr_get_profile, which waits
+ * for the stream.  ttr_set_profiling(h, 1) also clears the accumulators. */
+#define TTR_NPROF 6
+typedef struct ttr_profile {
+  int64_t count[TTR_NPROF];
+  double ms[TTR_NPROF];
+  double bytes[TTR_NPROF];
+  double flops[TTR_NPROF];
+} ttr_profile;
+
+int ttr_set_profiling(ttr_handle *h, int on);
+int ttr_get_profile(ttr_handle *h, ttr_profile *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -21,6 +21,16 @@ struct ttr_handle {
   int *dec_dev = nullptr;
   double *scal_host = nullptr;  // pinned scalars
   ttr_round_stats stats;
+  // opt-in kernel timing
+  struct Pending {
+    hipEvent_t a, b;
+    int cls;
+    double bytes, flops;
+  };
+  int profiling = 0;
+  std::vector<hipEvent_t> evpool;
+  std::vector<Pending> pending;
+  ttr_profile prof;
 };
 
 namespace {
@@ -120,6 +130,94 @@ WS carve(ttr_handle *h, int N, size_t tmp) {
   return w;
 }
 
+// --- opt-in kernel timing ------------------------------------------------
+enum { P_GRAM = 0, P_APPLY = 1, P_ADD = 2, P_HAD = 3, P_DOT = 4, P_SMALL = 5 };
+
+hipEvent_t take_event(ttr_handle *h) {
+  if (!h->evpool.empty()) {
+    hipEvent_t e = h->evpool.back();
+    h->evpool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+struct ProfScope {
+  ttr_handle *h;
+  hipEvent_t a = nullptr;
+  int cls;
+  double bytes, flops;
+  ProfScope(ttr_handle *h_, int cls_, double bytes_, double flops_) : h(h_), cls(cls_), bytes(bytes_), flops(flops_) {
+    if (h->profiling) {
+      a = take_event(h);
+      if (a) (void)hipEventRecord(a, h->stream);
+    }
+  }
+  ~ProfScope() {
+    if (!h->profiling || !a) return;
+    hipEvent_t b = take_event(h);
+    if (!b) return;
+    (void)hipEventRecord(b, h->stream);
+    h->pending.push_back({a, b, cls, bytes, flops});
+  }
+};
+
+void prof_resolve(ttr_handle *h) {
+  if (h->pending.empty()) return;
+  (void)hipStreamSynchronize(h->stream);
+  for (auto &p : h->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      h->prof.count[p.cls] += 1;
+      h->prof.ms[p.cls] += ms;
+      h->prof.bytes[p.cls] += p.bytes;
+      h->prof.flops[p.cls] += p.flops;
+    }
+    h->evpool.push_back(p.a);
+    h->evpool.push_back(p.b);
+  }
+  h->pending.clear();
+}
+
+// per-slice flops of a stage chain and the chain's output shape
+double chain_flops(const CoreView &cv, const Stages &st, int *zr, int *zc) {
+  double f = 0.0;
+  int cr = cv.ea(), cc = cv.eb();
+  for (int j = 0; j < st.nl; ++j) {
+    f += 2.0 * st.L[j].rows * cr * cc;
+    cr = st.L[j].rows;
+  }
+  for (int j = 0; j < st.nr; ++j) {
+    f += 2.0 * cr * cc * st.R[j].cols;
+    cc = st.R[j].cols;
+  }
+  *zr = cr;
+  *zc = cc;
+  return f;
+}
+
+void gram(ttr_handle *h, double *partials, double *G, const CoreView &cv, const Stages &st, int mode) {
+  int zr, zc;
+  const double cf = chain_flops(cv, st, &zr, &zc);
+  const double gf = (mode == GRAM_LEFT) ? (double)zr * (zr + 1) * zc : (double)zc * (zc + 1) * zr;
+  int nwg;
+  {
+    ProfScope ps(h, P_GRAM, 8.0 * cv.pa * cv.pb * (double)cv.I, (cf + gf) * (double)cv.I);
+    nwg = launch_gram(h->stream, cv, st, mode, partials, G, 0);
+  }
+  const int gd = (mode == GRAM_LEFT) ? zr : zc;
+  launch_reduce(h->stream, partials, nwg, gd * gd, G);
+}
+
+void apply(ttr_handle *h, const CoreView &cv, const Stages &st, double *Y, int trans_out) {
+  int zr, zc;
+  const double cf = chain_flops(cv, st, &zr, &zc);
+  ProfScope ps(h, P_APPLY, 8.0 * ((double)cv.pa * cv.pb + (double)zr * zc) * (double)cv.I, cf * (double)cv.I);
+  launch_apply(h->stream, cv, st, Y, trans_out);
+}
+
 int sync_dec(ttr_handle *h) {
   HIPCHK(hipMemcpyAsync(h->dec_host, h->dec_dev, 16 * sizeof(int), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
@@ -206,7 +304,7 @@ int qr_by_gram(ttr_handle *h, WS &w, const CoreView &cv, int mode, const Stages 
   f->dim[0] = b;
   Stages st = base;
   for (int pass = 1; pass <= 3; ++pass) {
-    launch_gram(h->stream, cv, st, mode, w.partials, w.G, 0);
+    gram(h, w.partials, w.G, cv, st, mode);
     ++*passes;
     QrStepArgs qa;
     qa.G = w.G;
@@ -220,7 +318,10 @@ int qr_by_gram(ttr_handle *h, WS &w, const CoreView &cv, int mode, const Stages 
     qa.dec = w.dec;
     qa.tau1 = kTau1;
     qa.tau2 = kTau2;
-    launch_qr_step(h->stream, qa);
+    {
+      ProfScope ps(h, P_SMALL, 0.0, 0.0);
+      launch_qr_step(h->stream, qa);
+    }
     h->stats.small_launches++;
     int rc = sync_dec(h);
     if (rc) return rc;
@@ -266,7 +367,7 @@ int orth_sweep(ttr_handle *h, WS &w, const Seq &S, std::vector<int> &k, std::vec
       Stages st = no_stages();
       for (int j = 0; j < fac[n].nst; ++j) st.L[st.nl++] = st_trans(w.B(n, j), fac[n].dim[j + 1], fac[n].dim[j]);
       if (n < N - 1) st.R[st.nr++] = st_plain(w.T(n + 1), cv.eb(), k[n + 1]);
-      launch_apply(h->stream, cv, st, w.tmp, S.rev);
+      apply(h, cv, st, w.tmp, S.rev);
       const int pn = S.phys(n);
       const size_t cnt = (size_t)kn * cv.I * k[n + 1];
       HIPCHK(hipMemcpyAsync(Out->core[pn], w.tmp, cnt * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
@@ -304,6 +405,7 @@ int ttr_create(ttr_handle **h, int device, void *stream) {
   p->device = device;
   p->stream = (hipStream_t)stream;
   std::memset(&p->stats, 0, sizeof(p->stats));
+  std::memset(&p->prof, 0, sizeof(p->prof));
   if (hipHostMalloc((void **)&p->dec_host, 16 * sizeof(int)) != hipSuccess ||
       hipHostMalloc((void **)&p->scal_host, 16 * sizeof(double)) != hipSuccess ||
       hipMalloc((void **)&p->dec_dev, 16 * sizeof(int)) != hipSuccess) {
@@ -322,6 +424,11 @@ int ttr_destroy(ttr_handle *h) {
   if (h->dec_dev) (void)hipFree(h->dec_dev);
   if (h->dec_host) (void)hipHostFree(h->dec_host);
   if (h->scal_host) (void)hipHostFree(h->scal_host);
+  for (auto &p : h->pending) {
+    h->evpool.push_back(p.a);
+    h->evpool.push_back(p.b);
+  }
+  for (hipEvent_t e : h->evpool) (void)hipEventDestroy(e);
   delete h;
   return TTR_OK;
 }
@@ -348,9 +455,13 @@ int ttr_add(ttr_handle *h, double alpha, const ttr_tt *X, double beta, const ttr
     if (Z->core[n] == X->core[n] || Z->core[n] == Y->core[n]) return fail(TTR_ERR_INVALID_ARG, "Z aliases an input");
     if (Z->cap[n] < R[n] * X->I[n] * R[n + 1]) return fail(TTR_ERR_CAPACITY, "Z core capacity too small");
   }
-  for (int n = 0; n < N; ++n)
+  for (int n = 0; n < N; ++n) {
+    const double bytes = 8.0 * X->I[n] * ((double)X->R[n] * X->R[n + 1] + (double)Y->R[n] * Y->R[n + 1] +
+                                         (double)R[n] * R[n + 1]);
+    ProfScope ps(h, P_ADD, bytes, 0.0);
     launch_add(h->stream, n, N, alpha, beta, X->core[n], (int)X->R[n], (int)X->R[n + 1], Y->core[n], (int)Y->R[n],
                (int)Y->R[n + 1], X->I[n], Z->core[n]);
+  }
   HIPCHK(hipGetLastError());
   for (int n = 0; n <= N; ++n) Z->R[n] = R[n];
   return TTR_OK;
@@ -372,9 +483,13 @@ int ttr_hadamard(ttr_handle *h, const ttr_tt *X, const ttr_tt *Y, ttr_tt *Z) {
     if (Z->core[n] == X->core[n] || Z->core[n] == Y->core[n]) return fail(TTR_ERR_INVALID_ARG, "Z aliases an input");
     if (Z->cap[n] < R[n] * X->I[n] * R[n + 1]) return fail(TTR_ERR_CAPACITY, "Z core capacity too small");
   }
-  for (int n = 0; n < N; ++n)
+  for (int n = 0; n < N; ++n) {
+    const double zsz = (double)R[n] * R[n + 1] * X->I[n];
+    const double bytes = 8.0 * (X->I[n] * ((double)X->R[n] * X->R[n + 1] + (double)Y->R[n] * Y->R[n + 1]) + zsz);
+    ProfScope ps(h, P_HAD, bytes, zsz);
     launch_hadamard(h->stream, X->core[n], (int)X->R[n], (int)X->R[n + 1], Y->core[n], (int)Y->R[n],
                     (int)Y->R[n + 1], X->I[n], Z->core[n]);
+  }
   HIPCHK(hipGetLastError());
   for (int n = 0; n <= N; ++n) Z->R[n] = R[n];
   return TTR_OK;
@@ -396,14 +511,20 @@ int ttr_dot(ttr_handle *h, const ttr_tt *X, const ttr_tt *Y, double *out) {
   HIPCHK(hipMemcpyAsync(w.Wa, h->scal_host, sizeof(double), hipMemcpyHostToDevice, h->stream));
   double *Wp = w.Wa, *Wn = w.Wb;
   for (int n = 0; n < N; ++n) {
-    launch_dot_step(h->stream, X->core[n], (int)X->R[n], (int)X->R[n + 1], Y->core[n], (int)Y->R[n],
-                    (int)Y->R[n + 1], X->I[n], Wp, w.partials, Wn);
+    {
+      const double rx0 = X->R[n], rx1 = X->R[n + 1], ry0 = Y->R[n], ry1 = Y->R[n + 1];
+      ProfScope ps(h, P_DOT, 8.0 * X->I[n] * (rx0 * rx1 + ry0 * ry1),
+                   2.0 * X->I[n] * (ry0 * rx0 * rx1 + ry1 * ry0 * rx1));
+      launch_dot_step(h->stream, X->core[n], (int)X->R[n], (int)X->R[n + 1], Y->core[n], (int)Y->R[n],
+                      (int)Y->R[n + 1], X->I[n], Wp, w.partials, Wn);
+    }
     std::swap(Wp, Wn);
   }
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(h->scal_host + 1, Wp, sizeof(double), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   *out = h->scal_host[1];
+  prof_resolve(h);
   return TTR_OK;
 }
 
@@ -432,12 +553,13 @@ int ttr_norm(ttr_handle *h, const ttr_tt *X, int method, double *out) {
   const CoreView cv = S.view(0);
   Stages st = no_stages();
   if (N > 1) st.R[st.nr++] = st_plain(w.T(1), cv.eb(), k[1]);
-  launch_gram(h->stream, cv, st, GRAM_LEFT, w.partials, w.G, 0);
+  gram(h, w.partials, w.G, cv, st, GRAM_LEFT);
   launch_sqrt_scalar(h->stream, w.G, w.scal);
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(h->scal_host, w.scal, sizeof(double), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   *out = h->scal_host[0];
+  prof_resolve(h);
   return TTR_OK;
 }
 
@@ -462,7 +584,7 @@ int ttr_orthogonalize(ttr_handle *h, ttr_tt *X, int side, int prec) {
   const CoreView cv = S.view(0);
   Stages st = no_stages();
   st.R[st.nr++] = st_plain(w.T(1), cv.eb(), k[1]);
-  launch_apply(h->stream, cv, st, w.tmp, S.rev);
+  apply(h, cv, st, w.tmp, S.rev);
   const int p0 = S.phys(0);
   HIPCHK(hipMemcpyAsync(X->core[p0], w.tmp, (size_t)cv.I * k[1] * sizeof(double), hipMemcpyDeviceToDevice,
                         h->stream));
@@ -472,6 +594,7 @@ int ttr_orthogonalize(ttr_handle *h, ttr_tt *X, int side, int prec) {
     const int pl = S.rev ? N - l : l;
     X->R[pl] = k[l];
   }
+  prof_resolve(h);
   return TTR_OK;
 }
 
@@ -549,7 +672,10 @@ int ttr_round(ttr_handle *h, const ttr_tt *X, double tol, int direction, int pre
     ta.Nm1 = N - 1;
     ta.sigma_out = w.sigma + (size_t)n * TTR_RMAX;
     ta.dec = w.dec;
-    launch_trunc_step(h->stream, ta);
+    {
+      ProfScope ps(h, P_SMALL, 0.0, 0.0);
+      launch_trunc_step(h->stream, ta);
+    }
     h->stats.small_launches++;
     if ((rc = sync_dec(h))) return rc;
     const int Ln = h->dec_host[3];
@@ -559,7 +685,7 @@ int ttr_round(ttr_handle *h, const ttr_tt *X, double tol, int direction, int pre
     Stages st = base;
     for (int j = 0; j + 1 < g.nst; ++j) st.R[st.nr++] = st_plain(w.Gst[j], g.dim[j], g.dim[j + 1]);
     st.R[st.nr++] = st_plain(w.GU, ta.d, Ln);
-    launch_apply(h->stream, cv, st, Y->core[S.phys(n)], S.rev);
+    apply(h, cv, st, Y->core[S.phys(n)], S.rev);
     ++applies;
     Pcur = ta.Pnext;
     Lprev = Ln;
@@ -571,7 +697,7 @@ int ttr_round(ttr_handle *h, const ttr_tt *X, double tol, int direction, int pre
     Stages st = no_stages();
     for (int j = 0; j + 1 < f.nst; ++j) st.L[st.nl++] = st_trans(w.B(n, j), f.dim[j + 1], f.dim[j]);
     st.L[st.nl++] = st_plain(Pcur, Lprev, f.dim[f.nst - 1]);
-    launch_apply(h->stream, cv, st, Y->core[S.phys(n)], S.rev);
+    apply(h, cv, st, Y->core[S.phys(n)], S.rev);
     ++applies;
   }
   HIPCHK(hipGetLastError());
@@ -602,6 +728,7 @@ int ttr_round(ttr_handle *h, const ttr_tt *X, double tol, int direction, int pre
     h->stats.nsigma[pl] = cnt;
   }
   if (norm_out) *norm_out = h->scal_host[2];
+  prof_resolve(h);
   return TTR_OK;
 }
 
@@ -620,6 +747,21 @@ const char *ttr_status_string(int status) {
 }
 
 const char *ttr_last_error(void) { return g_err.c_str(); }
+
+int ttr_set_profiling(ttr_handle *h, int on) {
+  if (!h) return fail(TTR_ERR_INVALID_ARG, "handle is NULL");
+  prof_resolve(h);
+  h->profiling = on ? 1 : 0;
+  std::memset(&h->prof, 0, sizeof(h->prof));
+  return TTR_OK;
+}
+
+int ttr_get_profile(ttr_handle *h, ttr_profile *out) {
+  if (!h || !out) return fail(TTR_ERR_INVALID_ARG, "NULL argument");
+  prof_resolve(h);
+  *out = h->prof;
+  return TTR_OK;
+}
 
 int ttr_get_round_stats(const ttr_handle *h, ttr_round_stats *out) {
   if (!h || !out) return fail(TTR_ERR_INVALID_ARG, "NULL argument");

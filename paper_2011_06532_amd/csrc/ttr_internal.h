@@ -48,12 +48,15 @@ void launch_add(hipStream_t s, int n, int N, double alpha, double beta, const do
                 const double *Y, int ry0, int ry1, long long I, double *Z);
 void launch_hadamard(hipStream_t s, const double *X, int rx0, int rx1, const double *Y, int ry0, int ry1,
                      long long I, double *Z);
-// G (gd x gd, col-major) = sum_i Z(i) Z(i)^T (LEFT, gd = p) or Z(i)^T Z(i) (RIGHT, gd = q).
-// Uses `partials` (TTR_MAXWG * gd * gd doubles).  Returns the workgroup count used.
+// Per-workgroup partial Grams sum_i Z(i) Z(i)^T (LEFT, gd = rows of Z) or
+// Z(i)^T Z(i) (RIGHT, gd = cols of Z) into `partials` (TTR_MAXWG * gd * gd
+// doubles).  Returns the workgroup count; launch_reduce then sums the partials
+// in a fixed order into G (gd x gd, column-major).
 int launch_gram(hipStream_t s, const CoreView &cv, const Stages &st, int mode, double *partials, double *G,
                 int mixed);
 // Y(r, i, c) = Z(i)(r, c) into a p x I x q core (trans_out = 0) or its
 // transpose q x I x p (trans_out = 1).
+void launch_reduce(hipStream_t s, const double *partials, int nwg, int ne, double *G);
 void launch_apply(hipStream_t s, const CoreView &cv, const Stages &st, double *Y, int trans_out);
 // W (ry1 x rx1) = sum_i Y(i)^T Wp X(i), Wp is ry0 x rx0 col-major.
 void launch_dot_step(hipStream_t s, const double *X, int rx0, int rx1, const double *Y, int ry0, int ry1,

@@ -169,8 +169,6 @@ __device__ inline Chunk transform_chunk(const CoreView &cv, const Stages &st, in
   return ch;
 }
 
-inline int out_rows(const CoreView &cv, const Stages &st) { return st.nl ? st.L[st.nl - 1].rows : cv.ea(); }
-inline int out_cols(const CoreView &cv, const Stages &st) { return st.nr ? st.R[st.nr - 1].cols : cv.eb(); }
 
 // Largest per-slice intermediate of the stage chain (doubles).
 inline int stage_buf(const CoreView &cv, const Stages &st) {
@@ -434,10 +432,12 @@ int launch_gram(hipStream_t s, const CoreView &cv, const Stages &st, int mode, d
   const size_t lds = chunk_lds(cv, st, T);
   const int buf = stage_buf(cv, st);
   hipLaunchKernelGGL(k_gram, dim3(nwg_used), dim3(kThreads), lds, s, cv, st, mode, T, spw, buf, partials);
-  const int gd = (mode == GRAM_LEFT) ? out_rows(cv, st) : out_cols(cv, st);
-  const int ne = gd * gd;
-  hipLaunchKernelGGL(k_reduce, dim3((ne + kThreads - 1) / kThreads), dim3(kThreads), 0, s, partials, nwg_used, ne, G);
+  (void)G;
   return nwg_used;
+}
+
+void launch_reduce(hipStream_t s, const double *partials, int nwg, int ne, double *G) {
+  hipLaunchKernelGGL(k_reduce, dim3((ne + kThreads - 1) / kThreads), dim3(kThreads), 0, s, partials, nwg, ne, G);
 }
 
 void launch_apply(hipStream_t s, const CoreView &cv, const Stages &st, double *Y, int trans_out) {

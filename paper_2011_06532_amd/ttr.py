@@ -37,7 +37,10 @@ _PREC = {"fp64": TTR_FP64, "mixed": TTR_MIXED}
 SYMBOLS = [
     "ttr_create", "ttr_destroy", "ttr_set_stream", "ttr_add", "ttr_hadamard", "ttr_dot", "ttr_norm",
     "ttr_orthogonalize", "ttr_round", "ttr_status_string", "ttr_last_error", "ttr_get_round_stats",
+    "ttr_set_profiling", "ttr_get_profile",
 ]
+
+PROF_CLASSES = ["gram", "apply", "add", "hadamard", "dot", "small"]
 
 
 class _TTStruct(ctypes.Structure):
@@ -60,6 +63,15 @@ class RoundStats(ctypes.Structure):
         ("delta", ctypes.c_double),
         ("sigma", ctypes.c_double * (TTR_MAX_RANK * 64)),
         ("nsigma", ctypes.c_int32 * 64),
+    ]
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [
+        ("count", ctypes.c_int64 * 6),
+        ("ms", ctypes.c_double * 6),
+        ("bytes", ctypes.c_double * 6),
+        ("flops", ctypes.c_double * 6),
     ]
 
 
@@ -97,6 +109,8 @@ def load(path: str = LIB_PATH):
     lib.ttr_last_error.argtypes = []
     lib.ttr_last_error.restype = ctypes.c_char_p
     lib.ttr_get_round_stats.argtypes = [vp, P(RoundStats)]
+    lib.ttr_set_profiling.argtypes = [vp, ctypes.c_int]
+    lib.ttr_get_profile.argtypes = [vp, P(Profile)]
     for name in SYMBOLS:
         if name not in ("ttr_status_string", "ttr_last_error"):
             getattr(lib, name).restype = ctypes.c_int
@@ -247,6 +261,15 @@ class Handle:
                               ctypes.byref(sy), ctypes.byref(nrm)))
         Y._read_ranks()
         return (Y, nrm.value) if return_norm else Y
+
+    def set_profiling(self, on: bool = True):
+        _check(_lib.ttr_set_profiling(self.h, 1 if on else 0))
+
+    def profile(self) -> dict:
+        pr = Profile()
+        _check(_lib.ttr_get_profile(self.h, ctypes.byref(pr)))
+        return {name: {"count": int(pr.count[i]), "ms": pr.ms[i], "bytes": pr.bytes[i], "flops": pr.flops[i]}
+                for i, name in enumerate(PROF_CLASSES)}
 
     def round_stats(self) -> dict:
         st = RoundStats()
