@@ -7,6 +7,7 @@
 #include "ttr_internal.h"
 
 #include <cmath>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -19,6 +20,8 @@ struct ttr_handle {
   size_t ws_bytes = 0;
   int *dec_host = nullptr;  // pinned
   int *dec_dev = nullptr;
+  double *decf_host = nullptr;  // pinned: per-step doubles (conditioning ratio)
+  double *decf_dev = nullptr;
   double *scal_host = nullptr;  // pinned scalars
   ttr_round_stats stats;
   // opt-in kernel timing
@@ -198,28 +201,90 @@ double chain_flops(const CoreView &cv, const Stages &st, int *zr, int *zc) {
   return f;
 }
 
+const bool g_use_mfma = (std::getenv("TTR_GENERIC_KERNELS") == nullptr);
+
+// A stage on the physical core: transposed views swap roles (Z^T = R^T X L^T).
+Stage st_transpose(const Stage &a) {
+  Stage t;
+  t.S = a.S;
+  t.rows = a.cols;
+  t.cols = a.rows;
+  t.sr = a.sc;
+  t.sc = a.sr;
+  return t;
+}
+
+// Streaming Gram of the chain Z(i) = lefts M(i) rights.  The one-factor forms
+// (the first pass of every factorization, the common case) run on the FP64
+// matrix cores; longer chains run on the staged generic kernel.
 void gram(ttr_handle *h, double *partials, double *G, const CoreView &cv, const Stages &st, int mode) {
   int zr, zc;
   const double cf = chain_flops(cv, st, &zr, &zc);
   const double gf = (mode == GRAM_LEFT) ? (double)zr * (zr + 1) * zc : (double)zc * (zc + 1) * zr;
-  int nwg;
-  {
+  const int gd = (mode == GRAM_LEFT) ? zr : zc;
+  // physical form: trans views transpose the chain and swap the Gram side
+  const bool tr = cv.trans != 0;
+  const int pmode = tr ? (mode == GRAM_LEFT ? GRAM_RIGHT : GRAM_LEFT) : mode;
+  const int pnl = tr ? st.nr : st.nl;
+  const int pnr = tr ? st.nl : st.nr;
+  const double *X = cv.X;
+  int nwg = 0;
+  bool done = false;
+  if (g_use_mfma) {
+    if (pmode == GRAM_LEFT && pnl == 0 && pnr <= 1) {
+      // sum (X Q)(X Q)^T
+      const Stage *q = pnr ? (tr ? &st.L[0] : &st.R[0]) : nullptr;
+      Stage qq;
+      if (q) qq = tr ? st_transpose(*q) : *q;
+      ProfScope ps(h, P_GRAM, 8.0 * cv.pa * cv.pb * (double)cv.I, (cf + gf) * (double)cv.I);
+      nwg = launch_gram_right_factor(h->stream, X, cv.pa, cv.pb, cv.I, q ? qq.S : nullptr, q ? qq.cols : cv.pb,
+                                     q ? qq.sr : 1, q ? qq.sc : cv.pb, partials);
+      done = true;
+    } else if (pmode == GRAM_RIGHT && pnl <= 1 && pnr == 0) {
+      // sum (P X)^T (P X)
+      const Stage *pp = pnl ? (tr ? &st.R[0] : &st.L[0]) : nullptr;
+      Stage ps_;
+      if (pp) ps_ = tr ? st_transpose(*pp) : *pp;
+      ProfScope ps(h, P_GRAM, 8.0 * cv.pa * cv.pb * (double)cv.I, (cf + gf) * (double)cv.I);
+      nwg = launch_gram_left_factor(h->stream, X, cv.pa, cv.pb, cv.I, pp ? ps_.S : nullptr, pp ? ps_.rows : cv.pa,
+                                    pp ? ps_.sr : 1, pp ? ps_.sc : cv.pa, partials);
+      done = true;
+    }
+  }
+  if (!done) {
     ProfScope ps(h, P_GRAM, 8.0 * cv.pa * cv.pb * (double)cv.I, (cf + gf) * (double)cv.I);
     nwg = launch_gram(h->stream, cv, st, mode, partials, G, 0);
   }
-  const int gd = (mode == GRAM_LEFT) ? zr : zc;
   launch_reduce(h->stream, partials, nwg, gd * gd, G);
 }
 
+// Output pass Y(i) = lefts M(i) rights, on the matrix cores when the chain has
+// at most one factor on each side.
 void apply(ttr_handle *h, const CoreView &cv, const Stages &st, double *Y, int trans_out) {
   int zr, zc;
   const double cf = chain_flops(cv, st, &zr, &zc);
   ProfScope ps(h, P_APPLY, 8.0 * ((double)cv.pa * cv.pb + (double)zr * zc) * (double)cv.I, cf * (double)cv.I);
+  const bool tr = cv.trans != 0;
+  if (g_use_mfma && st.nl <= 1 && st.nr <= 1 && trans_out == cv.trans) {
+    // physical: Y_phys = Pp X Qp; trans views: (L M' R)^T = R^T X L^T
+    const Stage *L = st.nl ? &st.L[0] : nullptr;
+    const Stage *R = st.nr ? &st.R[0] : nullptr;
+    const Stage *pl = tr ? R : L;
+    const Stage *pr = tr ? L : R;
+    Stage P, Q;
+    if (pl) P = tr ? st_transpose(*pl) : *pl;
+    if (pr) Q = tr ? st_transpose(*pr) : *pr;
+    launch_apply_mfma(h->stream, cv.X, cv.pa, cv.pb, cv.I, pl ? P.S : nullptr, pl ? P.rows : cv.pa, pl ? P.sr : 1,
+                      pl ? P.sc : cv.pa, pr ? Q.S : nullptr, pr ? Q.cols : cv.pb, pr ? Q.sr : 1,
+                      pr ? Q.sc : cv.pb, Y);
+    return;
+  }
   launch_apply(h->stream, cv, st, Y, trans_out);
 }
 
 int sync_dec(ttr_handle *h) {
   HIPCHK(hipMemcpyAsync(h->dec_host, h->dec_dev, 16 * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipMemcpyAsync(h->decf_host, h->decf_dev, 8 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   HIPCHK(hipGetLastError());
   if (h->dec_host[2] != 0) return fail(TTR_ERR_NUMERICAL, "non-finite data or a small factorization did not converge");
@@ -294,9 +359,13 @@ struct Factor {
 //         appended as RIGHT stages, pass Gram sum Z^T Z.
 // `slot(j)` gives the device slot for stage j.  On return: the collapsed R
 // (k x b) in *Rout, the stages recorded in *f.
+//   tcond: kappa(T)^2 of a single right stage T of `base` in RIGHT mode.  When
+//   finite, the first pass forms G0 without T on the matrix cores and the step
+//   kernel applies G = T^T G0 T; a tightened acceptance test accounts for T.
 template <class SlotFn>
 int qr_by_gram(ttr_handle *h, WS &w, const CoreView &cv, int mode, const Stages &base, int b, SlotFn slot,
-               double *Tdst, Factor *f, double **Rout, int *kout, int *passes) {
+               double *Tdst, Factor *f, double **Rout, int *kout, int *passes, double tcond = -1.0,
+               double *ratio = nullptr) {
   double *R[2] = {w.Ra, w.Rb};
   const double *Rc = nullptr;
   int d = b;
@@ -304,9 +373,27 @@ int qr_by_gram(ttr_handle *h, WS &w, const CoreView &cv, int mode, const Stages 
   f->dim[0] = b;
   Stages st = base;
   for (int pass = 1; pass <= 3; ++pass) {
-    gram(h, w.partials, w.G, cv, st, mode);
-    ++*passes;
     QrStepArgs qa;
+    qa.Tpost = nullptr;
+    qa.tpr = qa.tpc = 0;
+    qa.tsr = qa.tsc = 0;
+    qa.cond_scale = 1.0;
+    qa.ratio_out = (pass == 1) ? h->decf_dev : nullptr;
+    const bool post = (pass == 1 && mode == GRAM_RIGHT && tcond > 0.0 && base.nr == 1 && base.nl <= 1 && g_use_mfma);
+    if (post) {
+      Stages s1 = base;
+      s1.nr = 0;
+      gram(h, w.partials, w.G, cv, s1, mode);
+      qa.Tpost = base.R[0].S;
+      qa.tpr = base.R[0].rows;
+      qa.tpc = base.R[0].cols;
+      qa.tsr = base.R[0].sr;
+      qa.tsc = base.R[0].sc;
+      qa.cond_scale = tcond;
+    } else {
+      gram(h, w.partials, w.G, cv, st, mode);
+    }
+    ++*passes;
     qa.G = w.G;
     qa.d = d;
     qa.pass = pass;
@@ -327,6 +414,7 @@ int qr_by_gram(ttr_handle *h, WS &w, const CoreView &cv, int mode, const Stages 
     if (rc) return rc;
     const int k = h->dec_host[0];
     const int done = h->dec_host[1];
+    if (pass == 1 && ratio) *ratio = h->decf_host[0];
     f->nst = pass;
     f->dim[pass] = k;
     if (mode == GRAM_LEFT) st.L[st.nl++] = st_trans(qa.Fstep, k, d);
@@ -347,10 +435,11 @@ int qr_by_gram(ttr_handle *h, WS &w, const CoreView &cv, int mode, const Stages 
 // kept in the workspace, k[n] is the rank at logical link n.  When `Out` is
 // given, each orthonormal core B_n^T M_n(i) T_{n+1} is written to it (Alg. 5).
 int orth_sweep(ttr_handle *h, WS &w, const Seq &S, std::vector<int> &k, std::vector<Factor> &fac, ttr_tt *Out,
-               int *passes) {
+               int *passes, std::vector<double> *kappa2 = nullptr) {
   const int N = S.N();
   k.assign(N + 1, 1);
   fac.assign(N + 1, Factor());
+  if (kappa2) kappa2->assign(N + 1, -1.0);
   for (int n = 0; n <= N; ++n) k[n] = (int)S.rank(n);
   for (int n = N - 1; n >= 1; --n) {
     const CoreView cv = S.view(n);
@@ -360,9 +449,11 @@ int orth_sweep(ttr_handle *h, WS &w, const Seq &S, std::vector<int> &k, std::vec
     double *Rout;
     int kn;
     auto slot = [&](int j) { return w.B(n, j); };
-    int rc = qr_by_gram(h, w, cv, GRAM_LEFT, base, b, slot, w.T(n), &fac[n], &Rout, &kn, passes);
+    double ratio = -1.0;
+    int rc = qr_by_gram(h, w, cv, GRAM_LEFT, base, b, slot, w.T(n), &fac[n], &Rout, &kn, passes, -1.0, &ratio);
     if (rc) return rc;
     k[n] = kn;
+    if (kappa2 && fac[n].nst == 1) (*kappa2)[n] = ratio;
     if (Out) {
       Stages st = no_stages();
       for (int j = 0; j < fac[n].nst; ++j) st.L[st.nl++] = st_trans(w.B(n, j), fac[n].dim[j + 1], fac[n].dim[j]);
@@ -408,7 +499,9 @@ int ttr_create(ttr_handle **h, int device, void *stream) {
   std::memset(&p->prof, 0, sizeof(p->prof));
   if (hipHostMalloc((void **)&p->dec_host, 16 * sizeof(int)) != hipSuccess ||
       hipHostMalloc((void **)&p->scal_host, 16 * sizeof(double)) != hipSuccess ||
-      hipMalloc((void **)&p->dec_dev, 16 * sizeof(int)) != hipSuccess) {
+      hipMalloc((void **)&p->dec_dev, 16 * sizeof(int)) != hipSuccess ||
+      hipHostMalloc((void **)&p->decf_host, 8 * sizeof(double)) != hipSuccess ||
+      hipMalloc((void **)&p->decf_dev, 8 * sizeof(double)) != hipSuccess) {
     delete p;
     return fail(TTR_ERR_ALLOC, "handle allocation failed");
   }
@@ -422,6 +515,8 @@ int ttr_destroy(ttr_handle *h) {
   (void)hipStreamSynchronize(h->stream);
   if (h->ws) (void)hipFree(h->ws);
   if (h->dec_dev) (void)hipFree(h->dec_dev);
+  if (h->decf_dev) (void)hipFree(h->decf_dev);
+  if (h->decf_host) (void)hipHostFree(h->decf_host);
   if (h->dec_host) (void)hipHostFree(h->dec_host);
   if (h->scal_host) (void)hipHostFree(h->scal_host);
   for (auto &p : h->pending) {
@@ -626,9 +721,10 @@ int ttr_round(ttr_handle *h, const ttr_tt *X, double tol, int direction, int pre
   const Seq S{X, direction == TTR_LRL};
   std::vector<int> k;
   std::vector<Factor> fac;
+  std::vector<double> kappa2;
   int passes = 0;
   // Sweep 1: orthonormalization with implicit factors (Alg. 6, first loop).
-  if ((rc = orth_sweep(h, w, S, k, fac, nullptr, &passes))) return rc;
+  if ((rc = orth_sweep(h, w, S, k, fac, nullptr, &passes, &kappa2))) return rc;
   // Sweep 2: truncation (Alg. 2 loop / Alg. 6 second loop).  The current core
   // n is C'_n(i) = [P_n B_n^T] M_n(i) T_{n+1}; its left stages are the
   // orthonormalization stages of core n with the last one merged into P_n.
@@ -652,7 +748,8 @@ int ttr_round(ttr_handle *h, const ttr_tt *X, double tol, int direction, int pre
     int kq;
     Factor g;
     auto slot = [&](int j) { return w.Gst[j]; };
-    rc = qr_by_gram(h, w, cv, GRAM_RIGHT, base, b, slot, nullptr, &g, &Rq, &kq, &passes);
+    const double tcond = (fac[n + 1].nst == 1) ? kappa2[n + 1] : -1.0;
+    rc = qr_by_gram(h, w, cv, GRAM_RIGHT, base, b, slot, nullptr, &g, &Rq, &kq, &passes, tcond);
     if (rc) return rc;
     const Factor &fn = fac[n + 1];
     TruncArgs ta;
@@ -683,8 +780,15 @@ int ttr_round(ttr_handle *h, const ttr_tt *X, double tol, int direction, int pre
     // output core n: the same staged chain as the Gram passes, the last
     // refinement stage merged with U_R[:, :L]
     Stages st = base;
-    for (int j = 0; j + 1 < g.nst; ++j) st.R[st.nr++] = st_plain(w.Gst[j], g.dim[j], g.dim[j + 1]);
-    st.R[st.nr++] = st_plain(w.GU, ta.d, Ln);
+    if (g.nst == 1) {
+      // one-pass factorization: T and U-hat merge into one right factor
+      launch_small_gemm(h->stream, w.T(n + 1), w.GU, w.Gst[1], tr, b, Ln);
+      st.nr = 0;
+      st.R[st.nr++] = st_plain(w.Gst[1], tr, Ln);
+    } else {
+      for (int j = 0; j + 1 < g.nst; ++j) st.R[st.nr++] = st_plain(w.Gst[j], g.dim[j], g.dim[j + 1]);
+      st.R[st.nr++] = st_plain(w.GU, ta.d, Ln);
+    }
     apply(h, cv, st, Y->core[S.phys(n)], S.rev);
     ++applies;
     Pcur = ta.Pnext;

@@ -59,6 +59,14 @@ int launch_gram(hipStream_t s, const CoreView &cv, const Stages &st, int mode, d
 void launch_reduce(hipStream_t s, const double *partials, int nwg, int ne, double *G);
 void launch_apply(hipStream_t s, const CoreView &cv, const Stages &st, double *Y, int trans_out);
 // W (ry1 x rx1) = sum_i Y(i)^T Wp X(i), Wp is ry0 x rx0 col-major.
+// FP64 MFMA paths (ttr_mfma.hip) on physical cores (a x I x b), dims <= 64.
+int launch_gram_right_factor(hipStream_t s, const double *X, int a, int b, long long I, const double *Q, int q,
+                             long long sQr, long long sQc, double *partials);
+int launch_gram_left_factor(hipStream_t s, const double *X, int a, int b, long long I, const double *P, int p,
+                            long long sPr, long long sPa, double *partials);
+void launch_apply_mfma(hipStream_t s, const double *X, int a, int b, long long I, const double *P, int p,
+                       long long sPr, long long sPa, const double *Q, int q, long long sQr, long long sQc,
+                       double *Y);
 void launch_dot_step(hipStream_t s, const double *X, int rx0, int rx1, const double *Y, int ry0, int ry1,
                      long long I, const double *Wp, double *partials, double *W);
 
@@ -70,6 +78,14 @@ void launch_dot_step(hipStream_t s, const double *X, int rx0, int rx1, const dou
 struct QrStepArgs {
   const double *G;
   int d;
+  // optional post-transform: the input is G0 (tpr x tpr) and the Gram used is
+  // G = T^T G0 T (d = tpc); cond_scale (>= 1) is kappa(T)^2, which tightens
+  // the one-pass acceptance test
+  const double *Tpost;
+  int tpr, tpc;
+  long long tsr, tsc;
+  double cond_scale;
+  double *ratio_out;   // receives t_max / t_min of this pass (may be nullptr)
   int pass;            // 1, 2 or 3
   int b;               // columns of the unfolding
   const double *Rc;    // d x b (ld d); nullptr at pass 1

@@ -142,12 +142,50 @@ __global__ __launch_bounds__(kThreads) void k_qr_step(QrStepArgs a) {
   const int d = a.d;
   if (threadIdx.x == 0) bad = 0;
   __syncthreads();
-  for (int e = threadIdx.x; e < d * d; e += blockDim.x) {
-    const double g = a.G[e];
-    if (!finite(g)) bad = 1;
-    A[e] = g;
-    const int r = e % d, c = e / d;
-    Vm[e] = (r == c) ? 1.0 : 0.0;
+  if (a.Tpost) {
+    // G = T^T G0 T with G0 (m x m), T (m x d): Vm <- G0 T, then A <- T^T Vm
+    const int m = a.tpr;
+    for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+      const double g = a.G[e];
+      if (!finite(g)) bad = 1;
+      A[e] = g;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < m * d; e += blockDim.x) {
+      const int r = e % m, c = e / m;
+      double s = 0.0;
+      for (int k = 0; k < m; ++k) s += A[r + m * k] * a.Tpost[k * a.tsr + c * a.tsc];
+      Vm[r + m * c] = s;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < d * d; e += blockDim.x) {
+      const int r = e % d, c = e / d;
+      double s = 0.0;
+      for (int k = 0; k < m; ++k) s += a.Tpost[k * a.tsr + r * a.tsc] * Vm[k + m * c];
+      A[r + d * c] = s;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < d * d; e += blockDim.x) {
+      const int r = e % d, c = e / d;
+      if (r > c) {  // exact symmetry
+        const double v = 0.5 * (A[r + d * c] + A[c + d * r]);
+        A[r + d * c] = v;
+        A[c + d * r] = v;
+      }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < d * d; e += blockDim.x) {
+      const int r = e % d, c = e / d;
+      Vm[e] = (r == c) ? 1.0 : 0.0;
+    }
+  } else {
+    for (int e = threadIdx.x; e < d * d; e += blockDim.x) {
+      const double g = a.G[e];
+      if (!finite(g)) bad = 1;
+      A[e] = g;
+      const int r = e % d, c = e / d;
+      Vm[e] = (r == c) ? 1.0 : 0.0;
+    }
   }
   __syncthreads();
   if (bad) {
@@ -184,7 +222,9 @@ __global__ __launch_bounds__(kThreads) void k_qr_step(QrStepArgs a) {
       k = 0;  // zero (or non-positive) Gram: no content
       dn = 1;
     } else if (a.pass == 1) {
-      const double shift = (tmin >= a.tau1 * t1) ? 0.0 : 2.0 * d * kU * t1 + 2.0 * (tmin < 0 ? -tmin : 0.0);
+      const double cs = a.cond_scale > 1.0 ? a.cond_scale : 1.0;
+      if (a.ratio_out) *a.ratio_out = (tmin > 0.0) ? t1 / tmin : 1e300;
+      const double shift = (tmin >= a.tau1 * t1 * cs) ? 0.0 : 2.0 * d * kU * t1 + 2.0 * (tmin < 0 ? -tmin : 0.0);
       for (int j = 0; j < d; ++j) {
         const double v = sc[j] + shift;
         rs[j] = sqrt(v);
