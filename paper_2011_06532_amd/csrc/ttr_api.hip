@@ -362,10 +362,19 @@ struct Factor {
 //   tcond: kappa(T)^2 of a single right stage T of `base` in RIGHT mode.  When
 //   finite, the first pass forms G0 without T on the matrix cores and the step
 //   kernel applies G = T^T G0 T; a tightened acceptance test accounts for T.
+// Truncation-sweep context for the step kernel's "no truncation possible" test.
+struct TruncCtx {
+  int check = 0;
+  const double *delta_dev = nullptr;
+  int first = 0;
+  double tol2_nm1 = 0.0;
+  int notrunc = 0;  // out: proved at the accepted one-pass step
+};
+
 template <class SlotFn>
 int qr_by_gram(ttr_handle *h, WS &w, const CoreView &cv, int mode, const Stages &base, int b, SlotFn slot,
                double *Tdst, Factor *f, double **Rout, int *kout, int *passes, double tcond = -1.0,
-               double *ratio = nullptr) {
+               double *ratio = nullptr, TruncCtx *tc = nullptr) {
   double *R[2] = {w.Ra, w.Rb};
   const double *Rc = nullptr;
   int d = b;
@@ -405,6 +414,11 @@ int qr_by_gram(ttr_handle *h, WS &w, const CoreView &cv, int mode, const Stages 
     qa.dec = w.dec;
     qa.tau1 = kTau1;
     qa.tau2 = kTau2;
+    qa.try_chol = 1;
+    qa.notrunc_check = (tc && tc->check) ? 1 : 0;
+    qa.delta_dev = tc ? tc->delta_dev : nullptr;
+    qa.first = tc ? tc->first : 0;
+    qa.tol2_nm1 = tc ? tc->tol2_nm1 : 0.0;
     {
       ProfScope ps(h, P_SMALL, 0.0, 0.0);
       launch_qr_step(h->stream, qa);
@@ -415,6 +429,7 @@ int qr_by_gram(ttr_handle *h, WS &w, const CoreView &cv, int mode, const Stages 
     const int k = h->dec_host[0];
     const int done = h->dec_host[1];
     if (pass == 1 && ratio) *ratio = h->decf_host[0];
+    if (tc) tc->notrunc = (pass == 1 && done) ? h->dec_host[5] : 0;
     f->nst = pass;
     f->dim[pass] = k;
     if (mode == GRAM_LEFT) st.L[st.nl++] = st_trans(qa.Fstep, k, d);
@@ -549,6 +564,8 @@ int ttr_add(ttr_handle *h, double alpha, const ttr_tt *X, double beta, const ttr
   for (int n = 0; n < N; ++n) {
     if (Z->core[n] == X->core[n] || Z->core[n] == Y->core[n]) return fail(TTR_ERR_INVALID_ARG, "Z aliases an input");
     if (Z->cap[n] < R[n] * X->I[n] * R[n + 1]) return fail(TTR_ERR_CAPACITY, "Z core capacity too small");
+    if (R[n] * X->I[n] >= (int64_t)1 << 31 || R[n + 1] >= 65536)
+      return fail(TTR_ERR_UNSUPPORTED, "Z core column above 2^31 entries or rank above 65535");
   }
   for (int n = 0; n < N; ++n) {
     const double bytes = 8.0 * X->I[n] * ((double)X->R[n] * X->R[n + 1] + (double)Y->R[n] * Y->R[n + 1] +
@@ -577,6 +594,8 @@ int ttr_hadamard(ttr_handle *h, const ttr_tt *X, const ttr_tt *Y, ttr_tt *Z) {
   for (int n = 0; n < N; ++n) {
     if (Z->core[n] == X->core[n] || Z->core[n] == Y->core[n]) return fail(TTR_ERR_INVALID_ARG, "Z aliases an input");
     if (Z->cap[n] < R[n] * X->I[n] * R[n + 1]) return fail(TTR_ERR_CAPACITY, "Z core capacity too small");
+    if (R[n] * X->I[n] >= (int64_t)1 << 31 || R[n + 1] >= 65536)
+      return fail(TTR_ERR_UNSUPPORTED, "Z core column above 2^31 entries or rank above 65535");
   }
   for (int n = 0; n < N; ++n) {
     const double zsz = (double)R[n] * R[n + 1] * X->I[n];
@@ -749,7 +768,12 @@ int ttr_round(ttr_handle *h, const ttr_tt *X, double tol, int direction, int pre
     Factor g;
     auto slot = [&](int j) { return w.Gst[j]; };
     const double tcond = (fac[n + 1].nst == 1) ? kappa2[n + 1] : -1.0;
-    rc = qr_by_gram(h, w, cv, GRAM_RIGHT, base, b, slot, nullptr, &g, &Rq, &kq, &passes, tcond);
+    TruncCtx tcx;
+    tcx.check = 1;
+    tcx.delta_dev = w.scal + 1;
+    tcx.first = (n == 0);
+    tcx.tol2_nm1 = tol * tol / (double)(N - 1);
+    rc = qr_by_gram(h, w, cv, GRAM_RIGHT, base, b, slot, nullptr, &g, &Rq, &kq, &passes, tcond, nullptr, &tcx);
     if (rc) return rc;
     const Factor &fn = fac[n + 1];
     TruncArgs ta;
@@ -769,6 +793,8 @@ int ttr_round(ttr_handle *h, const ttr_tt *X, double tol, int direction, int pre
     ta.Nm1 = N - 1;
     ta.sigma_out = w.sigma + (size_t)n * TTR_RMAX;
     ta.dec = w.dec;
+    ta.identity = tcx.notrunc;              // proved L = k: no SVD needed
+    ta.r_orth = (g.nst == 1 && !tcx.notrunc) ? 1 : 0;  // one-pass eigen route: R = t^{1/2} W^T
     {
       ProfScope ps(h, P_SMALL, 0.0, 0.0);
       launch_trunc_step(h->stream, ta);

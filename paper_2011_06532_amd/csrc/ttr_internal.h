@@ -92,8 +92,17 @@ struct QrStepArgs {
   double *Fstep;       // d x k (ld d)
   double *Rnext;       // k x b (ld k)
   double *Tdst;        // when done: Rnext^T (b x k, ld b); may be nullptr
-  int *dec;            // [0] k, [1] done, [2] error flags
+  int *dec;            // [0] k, [1] done, [2] error flags, [4] triangular factors, [5] no truncation proven
   double tau1, tau2;
+  int try_chol;        // pass 1: try the Cholesky route first
+  // truncation sweep only: with the Cholesky route, also prove that no
+  // singular value can be dropped at this link (lambda_min(G) >= 1/||L^{-1}||_F^2
+  // > margin * delta^2); delta is *delta_dev, or at the first link
+  // tol^2 trace(G) / (N-1) = tol2_nm1 * trace(G).
+  int notrunc_check;
+  const double *delta_dev;
+  int first;
+  double tol2_nm1;
 };
 void launch_qr_step(hipStream_t s, const QrStepArgs &a);
 
@@ -118,6 +127,8 @@ struct TruncArgs {
   int Nm1;
   double *sigma_out; // TTR_RMAX values (descending, zero padded)
   int *dec;          // [3] L, [2] error flags
+  int r_orth;        // rows of R are known to be orthogonal (skip the rotations)
+  int identity;      // the step proved L = k: U = I and Sigma V^T = R (no SVD)
 };
 void launch_trunc_step(hipStream_t s, const TruncArgs &a);
 

@@ -96,25 +96,41 @@ __device__ void reduce_gram(const d4 (&G)[NT][NT], int nt, int gd, double *Gs, d
   }
 }
 
+// Loads the operand fragments of one slice: buf[ks][t] = M(t*16 + l%16, ks*4 + l/16)
+// (ROWS16 = true) or M(ks*4 + l/16, t*16 + l%16) (ROWS16 = false), zero outside
+// the a x b slice.  M(alpha, beta) = Xi[alpha + col*beta].
+template <int NT, int KS, bool ROWS16>
+__device__ inline void load_slice(const double *__restrict__ Xi, long long col, int a, int b, int g, int j,
+                                  double (&buf)[KS][NT]) {
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int r = ROWS16 ? t * 16 + j : ks * 4 + g;   // alpha
+      const int c = ROWS16 ? ks * 4 + g : t * 16 + j;   // beta
+      double v = 0.0;
+      if (r < a && c < b) v = Xi[r + col * c];
+      buf[ks][t] = v;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Gram with a right factor: G (a x a) = sum_i (M_i Q)(M_i Q)^T, M_i = X(:, i, :)
 // (a x b), Q (b x q).  The left Gram of the horizontal unfolding of X x_3 Q^T
-// (orthonormalization sweep, §2.3 / Alg. 1).
+// (orthonormalization sweep, §2.3 / Alg. 1).  NT = 16-tiles per dimension,
+// KS = k-steps over b (ceil(b/4)).
 // ---------------------------------------------------------------------------
-template <int NT>
+template <int NT, int KS>
 __global__ __launch_bounds__(kThreads) void k_gram_right_factor(const double *__restrict__ X, int a, int b, long long I,
                                                                 const double *__restrict__ Q, int q, long long sQr,
                                                                 long long sQc, long long spw,
                                                                 double *__restrict__ partials) {
-  constexpr int KSM = NT * 4;
-  __shared__ double frag[NT * KSM * 64];
+  __shared__ double frag[NT * KS * 64];
   __shared__ double Gs[NT * 16 * NT * 16];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, j = lane & 15;
-  const int KS = (b + 3) >> 2;
-  const int ntA = (a + 15) >> 4, ntQ = (q + 15) >> 4;
   // A operand: Q^T (q x b), Q^T(c, beta) = Q(beta, c)
-  build_afrag(frag, Q, q, b, sQc, sQr, NT, KSM);
+  build_afrag(frag, Q, q, b, sQc, sQr, NT, KS);
   __syncthreads();
   d4 G[NT][NT];
 #pragma unroll
@@ -124,65 +140,57 @@ __global__ __launch_bounds__(kThreads) void k_gram_right_factor(const double *__
   const long long beg = (long long)blockIdx.x * spw;
   const long long end = std::min(beg + spw, I);
   const long long col = (long long)a * I;
-  for (long long i = beg + wave; i < end; i += kWaves) {
-    const double *Xi = X + (long long)a * i;
+  double cur[KS][NT], nxt[KS][NT];
+  long long i = beg + wave;
+  if (i < end) load_slice<NT, KS, true>(X + (long long)a * i, col, a, b, g, j, cur);
+  for (; i < end; i += kWaves) {
+    if (i + kWaves < end) load_slice<NT, KS, true>(X + (long long)a * (i + kWaves), col, a, b, g, j, nxt);
     d4 wt[NT][NT];  // [c-tile][alpha-tile]
 #pragma unroll
     for (int u = 0; u < NT; ++u)
 #pragma unroll
       for (int v = 0; v < NT; ++v) wt[u][v] = d4{0.0, 0.0, 0.0, 0.0};
-    for (int ks = 0; ks < KS; ++ks) {
-      const int beta = ks * 4 + g;
-      double bm[NT];
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const int alpha = t * 16 + j;
-        bm[t] = (t < ntA && alpha < a && beta < b) ? Xi[alpha + col * beta] : 0.0;
-      }
+    for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
       for (int cb = 0; cb < NT; ++cb) {
-        if (cb < ntQ) {
-          const double qa = frag[(cb * KSM + ks) * 64 + lane];
+        const double qa = frag[(cb * KS + ks) * 64 + lane];
 #pragma unroll
-          for (int t = 0; t < NT; ++t)
-            if (t < ntA) wt[cb][t] = mfma(qa, bm[t], wt[cb][t]);
-        }
+        for (int t = 0; t < NT; ++t) wt[cb][t] = mfma(qa, cur[ks][t], wt[cb][t]);
       }
-    }
-    // G(alpha, alpha') += sum_c Wt(c, alpha) Wt(c, alpha')
+    // G(alpha, alpha') += sum_c Wt(c, alpha) Wt(c, alpha'); consecutive MFMAs
+    // go to different G tiles
 #pragma unroll
-    for (int u = 0; u < NT; ++u)
+    for (int cb = 0; cb < NT; ++cb)
 #pragma unroll
-      for (int v = 0; v < NT; ++v)
-        if (v <= u && u < ntA) {
+      for (int r = 0; r < 4; ++r)
 #pragma unroll
-          for (int cb = 0; cb < NT; ++cb)
-            if (cb < ntQ) {
+        for (int u = 0; u < NT; ++u)
 #pragma unroll
-              for (int r = 0; r < 4; ++r) G[u][v] = mfma(wt[cb][u][r], wt[cb][v][r], G[u][v]);
-            }
-        }
+          for (int v = 0; v <= u; ++v) G[u][v] = mfma(wt[cb][u][r], wt[cb][v][r], G[u][v]);
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) cur[ks][t] = nxt[ks][t];
   }
-  reduce_gram<NT>(G, ntA, a, Gs, partials + (long long)blockIdx.x * a * a);
+  reduce_gram<NT>(G, NT, a, Gs, partials + (long long)blockIdx.x * a * a);
 }
 
 // ---------------------------------------------------------------------------
 // Gram with a left factor: G0 (b x b) = sum_i (P M_i)^T (P M_i), P (p x a).
 // The Gram of the vertical unfolding of P x_1 X (truncation sweep, §2.4).
+// KS = k-steps over a (ceil(a/4)).
 // ---------------------------------------------------------------------------
-template <int NT>
+template <int NT, int KS>
 __global__ __launch_bounds__(kThreads) void k_gram_left_factor(const double *__restrict__ X, int a, int b, long long I,
                                                                const double *__restrict__ P, int p, long long sPr,
                                                                long long sPa, long long spw,
                                                                double *__restrict__ partials) {
-  constexpr int KSM = NT * 4;
-  __shared__ double frag[NT * KSM * 64];
+  __shared__ double frag[NT * KS * 64];
   __shared__ double Gs[NT * 16 * NT * 16];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, j = lane & 15;
-  const int KS = (a + 3) >> 2;
-  const int ntB = (b + 15) >> 4, ntP = (p + 15) >> 4;
-  build_afrag(frag, P, p, a, sPr, sPa, NT, KSM);
+  build_afrag(frag, P, p, a, sPr, sPa, NT, KS);
   __syncthreads();
   d4 G[NT][NT];
 #pragma unroll
@@ -192,98 +200,83 @@ __global__ __launch_bounds__(kThreads) void k_gram_left_factor(const double *__r
   const long long beg = (long long)blockIdx.x * spw;
   const long long end = std::min(beg + spw, I);
   const long long col = (long long)a * I;
-  for (long long i = beg + wave; i < end; i += kWaves) {
-    const double *Xi = X + (long long)a * i;
+  double cur[KS][NT], nxt[KS][NT];
+  long long i = beg + wave;
+  if (i < end) load_slice<NT, KS, false>(X + (long long)a * i, col, a, b, g, j, cur);
+  for (; i < end; i += kWaves) {
+    if (i + kWaves < end) load_slice<NT, KS, false>(X + (long long)a * (i + kWaves), col, a, b, g, j, nxt);
     d4 y[NT][NT];  // [rho-tile][beta-tile]
 #pragma unroll
     for (int u = 0; u < NT; ++u)
 #pragma unroll
       for (int v = 0; v < NT; ++v) y[u][v] = d4{0.0, 0.0, 0.0, 0.0};
-    for (int ks = 0; ks < KS; ++ks) {
-      const int alpha = ks * 4 + g;
-      double bm[NT];
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const int beta = t * 16 + j;
-        bm[t] = (t < ntB && alpha < a && beta < b) ? Xi[alpha + col * beta] : 0.0;
-      }
+    for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
       for (int rb = 0; rb < NT; ++rb) {
-        if (rb < ntP) {
-          const double pa = frag[(rb * KSM + ks) * 64 + lane];
+        const double pa = frag[(rb * KS + ks) * 64 + lane];
 #pragma unroll
-          for (int t = 0; t < NT; ++t)
-            if (t < ntB) y[rb][t] = mfma(pa, bm[t], y[rb][t]);
-        }
+        for (int t = 0; t < NT; ++t) y[rb][t] = mfma(pa, cur[ks][t], y[rb][t]);
       }
-    }
     // G0(beta, beta') += sum_rho Y(rho, beta) Y(rho, beta')
 #pragma unroll
-    for (int u = 0; u < NT; ++u)
+    for (int rb = 0; rb < NT; ++rb)
 #pragma unroll
-      for (int v = 0; v < NT; ++v)
-        if (v <= u && u < ntB) {
+      for (int r = 0; r < 4; ++r)
 #pragma unroll
-          for (int rb = 0; rb < NT; ++rb)
-            if (rb < ntP) {
+        for (int u = 0; u < NT; ++u)
 #pragma unroll
-              for (int r = 0; r < 4; ++r) G[u][v] = mfma(y[rb][u][r], y[rb][v][r], G[u][v]);
-            }
-        }
+          for (int v = 0; v <= u; ++v) G[u][v] = mfma(y[rb][u][r], y[rb][v][r], G[u][v]);
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) cur[ks][t] = nxt[ks][t];
   }
-  reduce_gram<NT>(G, ntB, b, Gs, partials + (long long)blockIdx.x * b * b);
+  reduce_gram<NT>(G, NT, b, Gs, partials + (long long)blockIdx.x * b * b);
 }
 
 // ---------------------------------------------------------------------------
 // Output pass: Y_i = P M_i Q (p x q) written as a p x I x q core.  P == nullptr
 // means the identity (p = a); Q == nullptr means the identity (q = b).
+// KS = k-steps over b.
 // ---------------------------------------------------------------------------
-template <int NT>
+template <int NT, int KS>
 __global__ __launch_bounds__(kThreads) void k_apply_mfma(const double *__restrict__ X, int a, int b, long long I,
                                                          const double *__restrict__ P, int p, long long sPr,
                                                          long long sPa, const double *__restrict__ Q, int q,
                                                          long long sQr, long long sQc, long long spw,
                                                          double *__restrict__ Y) {
-  constexpr int KSM = NT * 4;
-  __shared__ double fragQ[NT * KSM * 64];
-  __shared__ double fragP[NT * KSM * 64];
+  constexpr int KA = NT * 4;  // k-steps over alpha (whole tiles)
+  __shared__ double fragQ[NT * KS * 64];
+  __shared__ double fragP[NT * KA * 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, j = lane & 15;
-  const int KS = (b + 3) >> 2;
-  const int ntA = (a + 15) >> 4, ntQ = (q + 15) >> 4, ntP = (p + 15) >> 4;
   const bool hasP = (P != nullptr);
-  build_bfrag(fragQ, Q, b, q, sQr, sQc, NT, KSM);
-  if (hasP) build_afrag(fragP, P, p, a, sPr, sPa, NT, KSM);
+  build_bfrag(fragQ, Q, b, q, sQr, sQc, NT, KS);
+  if (hasP) build_afrag(fragP, P, p, a, sPr, sPa, NT, KA);
   __syncthreads();
   const long long beg = (long long)blockIdx.x * spw;
   const long long end = std::min(beg + spw, I);
   const long long col = (long long)a * I;
   const long long ocol = (long long)p * I;
-  for (long long i = beg + wave; i < end; i += kWaves) {
-    const double *Xi = X + (long long)a * i;
+  double cur[KS][NT], nxt[KS][NT];
+  long long i = beg + wave;
+  if (i < end) load_slice<NT, KS, true>(X + (long long)a * i, col, a, b, g, j, cur);
+  for (; i < end; i += kWaves) {
+    if (i + kWaves < end) load_slice<NT, KS, true>(X + (long long)a * (i + kWaves), col, a, b, g, j, nxt);
     d4 w[NT][NT];  // [alpha-tile][c-tile]
 #pragma unroll
     for (int u = 0; u < NT; ++u)
 #pragma unroll
       for (int v = 0; v < NT; ++v) w[u][v] = d4{0.0, 0.0, 0.0, 0.0};
-    for (int ks = 0; ks < KS; ++ks) {
-      const int beta = ks * 4 + g;
-      double am[NT];
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const int alpha = t * 16 + j;
-        am[t] = (t < ntA && alpha < a && beta < b) ? Xi[alpha + col * beta] : 0.0;
-      }
+    for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
       for (int cb = 0; cb < NT; ++cb) {
-        if (cb < ntQ) {
-          const double qb = fragQ[(cb * KSM + ks) * 64 + lane];
+        const double qb = fragQ[(cb * KS + ks) * 64 + lane];
 #pragma unroll
-          for (int t = 0; t < NT; ++t)
-            if (t < ntA) w[t][cb] = mfma(am[t], qb, w[t][cb]);
-        }
+        for (int t = 0; t < NT; ++t) w[t][cb] = mfma(cur[ks][t], qb, w[t][cb]);
       }
-    }
     double *Yi = Y + (long long)p * i;
     if (hasP) {
       d4 y[NT][NT];  // [rho-tile][c-tile]
@@ -293,45 +286,42 @@ __global__ __launch_bounds__(kThreads) void k_apply_mfma(const double *__restric
         for (int v = 0; v < NT; ++v) y[u][v] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int t = 0; t < NT; ++t)
-        if (t < ntA) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
+        for (int r = 0; r < 4; ++r)
 #pragma unroll
-            for (int rb = 0; rb < NT; ++rb)
-              if (rb < ntP) {
-                const double pa = fragP[(rb * KSM + t * 4 + r) * 64 + lane];
+          for (int rb = 0; rb < NT; ++rb) {
+            const double pa = fragP[(rb * KA + t * 4 + r) * 64 + lane];
 #pragma unroll
-                for (int cb = 0; cb < NT; ++cb)
-                  if (cb < ntQ) y[rb][cb] = mfma(pa, w[t][cb][r], y[rb][cb]);
-              }
+            for (int cb = 0; cb < NT; ++cb) y[rb][cb] = mfma(pa, w[t][cb][r], y[rb][cb]);
           }
-        }
 #pragma unroll
       for (int rb = 0; rb < NT; ++rb)
 #pragma unroll
-        for (int cb = 0; cb < NT; ++cb)
-          if (rb < ntP && cb < ntQ) {
-            const int c = cb * 16 + j;
+        for (int cb = 0; cb < NT; ++cb) {
+          const int c = cb * 16 + j;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int rho = rb * 16 + g + 4 * r;
-              if (rho < p && c < q) Yi[rho + ocol * c] = y[rb][cb][r];
-            }
+          for (int r = 0; r < 4; ++r) {
+            const int rho = rb * 16 + g + 4 * r;
+            if (rho < p && c < q) Yi[rho + ocol * c] = y[rb][cb][r];
           }
+        }
     } else {
 #pragma unroll
       for (int t = 0; t < NT; ++t)
 #pragma unroll
-        for (int cb = 0; cb < NT; ++cb)
-          if (t < ntA && cb < ntQ) {
-            const int c = cb * 16 + j;
+        for (int cb = 0; cb < NT; ++cb) {
+          const int c = cb * 16 + j;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int alpha = t * 16 + g + 4 * r;
-              if (alpha < p && c < q) Yi[alpha + ocol * c] = w[t][cb][r];
-            }
+          for (int r = 0; r < 4; ++r) {
+            const int alpha = t * 16 + g + 4 * r;
+            if (alpha < p && c < q) Yi[alpha + ocol * c] = w[t][cb][r];
           }
+        }
     }
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) cur[ks][t] = nxt[ks][t];
   }
 }
 
@@ -355,16 +345,29 @@ int tiles_for(int m) { return (m + 15) / 16; }
 
 }  // namespace
 
+// (NT, KS) dispatch: NT = 16-tiles covering every dimension, KS = k-steps of the
+// contracted slice dimension, KS in {4NT-3, ..., 4NT}.
+#define TTR_KS_CASES(KERNEL, NTV, ...)                                                                  \
+  switch (ks - (4 * NTV - 3)) {                                                                        \
+    case 0: hipLaunchKernelGGL((KERNEL<NTV, 4 * NTV - 3>), dim3(gr.nwg), dim3(kThreads), 0, s, __VA_ARGS__); break; \
+    case 1: hipLaunchKernelGGL((KERNEL<NTV, 4 * NTV - 2>), dim3(gr.nwg), dim3(kThreads), 0, s, __VA_ARGS__); break; \
+    case 2: hipLaunchKernelGGL((KERNEL<NTV, 4 * NTV - 1>), dim3(gr.nwg), dim3(kThreads), 0, s, __VA_ARGS__); break; \
+    default: hipLaunchKernelGGL((KERNEL<NTV, 4 * NTV>), dim3(gr.nwg), dim3(kThreads), 0, s, __VA_ARGS__); break;    \
+  }
+#define TTR_NT_CASES(KERNEL, ...)                       \
+  switch (nt) {                                          \
+    case 1: TTR_KS_CASES(KERNEL, 1, __VA_ARGS__) break;  \
+    case 2: TTR_KS_CASES(KERNEL, 2, __VA_ARGS__) break;  \
+    case 3: TTR_KS_CASES(KERNEL, 3, __VA_ARGS__) break;  \
+    default: TTR_KS_CASES(KERNEL, 4, __VA_ARGS__) break; \
+  }
+
 int launch_gram_right_factor(hipStream_t s, const double *X, int a, int b, long long I, const double *Q, int q,
                              long long sQr, long long sQc, double *partials) {
   const Grid gr = grid_of(I);
   const int nt = std::max({tiles_for(a), tiles_for(b), tiles_for(q)});
-  switch (nt) {
-    case 1: hipLaunchKernelGGL(k_gram_right_factor<1>, dim3(gr.nwg), dim3(kThreads), 0, s, X, a, b, I, Q, q, sQr, sQc, gr.spw, partials); break;
-    case 2: hipLaunchKernelGGL(k_gram_right_factor<2>, dim3(gr.nwg), dim3(kThreads), 0, s, X, a, b, I, Q, q, sQr, sQc, gr.spw, partials); break;
-    case 3: hipLaunchKernelGGL(k_gram_right_factor<3>, dim3(gr.nwg), dim3(kThreads), 0, s, X, a, b, I, Q, q, sQr, sQc, gr.spw, partials); break;
-    default: hipLaunchKernelGGL(k_gram_right_factor<4>, dim3(gr.nwg), dim3(kThreads), 0, s, X, a, b, I, Q, q, sQr, sQc, gr.spw, partials); break;
-  }
+  const int ks = std::max((b + 3) / 4, 4 * nt - 3);
+  TTR_NT_CASES(k_gram_right_factor, X, a, b, I, Q, q, sQr, sQc, gr.spw, partials)
   return gr.nwg;
 }
 
@@ -372,12 +375,8 @@ int launch_gram_left_factor(hipStream_t s, const double *X, int a, int b, long l
                             long long sPr, long long sPa, double *partials) {
   const Grid gr = grid_of(I);
   const int nt = std::max({tiles_for(a), tiles_for(b), tiles_for(p)});
-  switch (nt) {
-    case 1: hipLaunchKernelGGL(k_gram_left_factor<1>, dim3(gr.nwg), dim3(kThreads), 0, s, X, a, b, I, P, p, sPr, sPa, gr.spw, partials); break;
-    case 2: hipLaunchKernelGGL(k_gram_left_factor<2>, dim3(gr.nwg), dim3(kThreads), 0, s, X, a, b, I, P, p, sPr, sPa, gr.spw, partials); break;
-    case 3: hipLaunchKernelGGL(k_gram_left_factor<3>, dim3(gr.nwg), dim3(kThreads), 0, s, X, a, b, I, P, p, sPr, sPa, gr.spw, partials); break;
-    default: hipLaunchKernelGGL(k_gram_left_factor<4>, dim3(gr.nwg), dim3(kThreads), 0, s, X, a, b, I, P, p, sPr, sPa, gr.spw, partials); break;
-  }
+  const int ks = std::max((a + 3) / 4, 4 * nt - 3);
+  TTR_NT_CASES(k_gram_left_factor, X, a, b, I, P, p, sPr, sPa, gr.spw, partials)
   return gr.nwg;
 }
 
@@ -386,10 +385,6 @@ void launch_apply_mfma(hipStream_t s, const double *X, int a, int b, long long I
                        double *Y) {
   const Grid gr = grid_of(I);
   const int nt = std::max({tiles_for(a), tiles_for(b), tiles_for(p), tiles_for(q)});
-  switch (nt) {
-    case 1: hipLaunchKernelGGL(k_apply_mfma<1>, dim3(gr.nwg), dim3(kThreads), 0, s, X, a, b, I, P, p, sPr, sPa, Q, q, sQr, sQc, gr.spw, Y); break;
-    case 2: hipLaunchKernelGGL(k_apply_mfma<2>, dim3(gr.nwg), dim3(kThreads), 0, s, X, a, b, I, P, p, sPr, sPa, Q, q, sQr, sQc, gr.spw, Y); break;
-    case 3: hipLaunchKernelGGL(k_apply_mfma<3>, dim3(gr.nwg), dim3(kThreads), 0, s, X, a, b, I, P, p, sPr, sPa, Q, q, sQr, sQc, gr.spw, Y); break;
-    default: hipLaunchKernelGGL(k_apply_mfma<4>, dim3(gr.nwg), dim3(kThreads), 0, s, X, a, b, I, P, p, sPr, sPa, Q, q, sQr, sQc, gr.spw, Y); break;
-  }
+  const int ks = std::max((b + 3) / 4, 4 * nt - 3);
+  TTR_NT_CASES(k_apply_mfma, X, a, b, I, P, p, sPr, sPa, Q, q, sQr, sQc, gr.spw, Y)
 }

@@ -21,13 +21,25 @@
 
 namespace {
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 1024;   // 16 waves: one-sided Jacobi rotates all column pairs of a round at once
+constexpr int kThreadsQR = 256;  // two-sided Jacobi: cheap barriers matter more than width
+// rows of a rotation handled by one thread: blockDim / (d/2) threads share a
+// pair, so with 256 threads and d <= 64 each owns at most 8
+constexpr int kRows = 8;
 constexpr int kWave = 64;
 constexpr double kU = DBL_EPSILON / 2;  // unit roundoff 2^-53
 
-__device__ inline double wave_sum(double v) {
-  for (int off = kWave / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
-  return __shfl(v, 0, kWave);  // one value for the whole wave
+// Sums of three values over the wave; every lane gets lane 0's result so
+// that branch decisions taken on them are uniform across the wave.
+__device__ inline void wave_sum3(double &a, double &b, double &c) {
+  for (int off = kWave / 2; off >= 1; off >>= 1) {
+    a += __shfl_xor(a, off, kWave);
+    b += __shfl_xor(b, off, kWave);
+    c += __shfl_xor(c, off, kWave);
+  }
+  a = __shfl(a, 0, kWave);
+  b = __shfl(b, 0, kWave);
+  c = __shfl(c, 0, kWave);
 }
 
 // Round-robin (circle) pairing of nn (even) columns: round r, pair k.
@@ -40,6 +52,62 @@ __device__ inline void rr_pair(int r, int k, int nn, int *p, int *q) {
     *p = (r + k) % m;
     *q = (r - k + m) % m;
   }
+}
+
+__device__ inline bool finite(double x) { return x == x && fabs(x) <= DBL_MAX; }
+
+// Fixed-order tree sum over the workgroup (blockDim.x a power of two <= 1024).
+__device__ double block_sum(double v) {
+  __shared__ double red[1024];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ double block_max(double v) {
+  __shared__ double red[1024];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// ||M||_1 (largest column sum of |entries|) or ||M||_inf (largest row sum)
+// of a d x d column-major matrix.
+__device__ double norm1(const double *M, int d) {
+  double v = 0.0;
+  for (int c = threadIdx.x; c < d; c += blockDim.x) {
+    double s = 0.0;
+    for (int r = 0; r < d; ++r) s += fabs(M[r + d * c]);
+    v = fmax(v, s);
+  }
+  return block_max(v);
+}
+__device__ double norminf(const double *M, int d) {
+  double v = 0.0;
+  for (int r = threadIdx.x; r < d; r += blockDim.x) {
+    double s = 0.0;
+    for (int c = 0; c < d; ++c) s += fabs(M[r + d * c]);
+    v = fmax(v, s);
+  }
+  return block_max(v);
+}
+
+__device__ double sumsq(const double *X, int n) {
+  double s = 0.0;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) s += X[e] * X[e];
+  return block_sum(s);
 }
 
 // One-sided Jacobi on A (m x n, column-major, lda = m) in LDS, accumulating the
@@ -55,13 +123,7 @@ __device__ int jacobi_onesided(double *A, int m, int n, double *Vm, int *flag) {
   // Columns at rounding level of the whole matrix (exact null directions of a
   // rank-deficient input) are left alone: their mutual angles are noise and
   // would never settle.
-  __shared__ double fro2;
-  if (threadIdx.x == 0) {
-    double f = 0.0;
-    for (int e = 0; e < m * n; ++e) f += A[e] * A[e];
-    fro2 = f;
-  }
-  __syncthreads();
+  const double fro2 = sumsq(A, m * n);
   const double floor2 = (8.0 * (m + n) * kU) * (8.0 * (m + n) * kU) * fro2;
   for (int sweep = 0; sweep < 40; ++sweep) {
     if (threadIdx.x == 0) *flag = 0;
@@ -74,9 +136,8 @@ __device__ int jacobi_onesided(double *A, int m, int n, double *Vm, int *flag) {
         if (p >= n || q >= n) continue;
         const double ap = lane < m ? A[p * m + lane] : 0.0;
         const double aq = lane < m ? A[q * m + lane] : 0.0;
-        const double alpha = wave_sum(ap * ap);
-        const double beta = wave_sum(aq * aq);
-        const double gamma = wave_sum(ap * aq);
+        double alpha = ap * ap, beta = aq * aq, gamma = ap * aq;
+        wave_sum3(alpha, beta, gamma);
         if (alpha > floor2 && beta > floor2 && fabs(gamma) > tol * sqrt(alpha) * sqrt(beta)) {
           const double zeta = (beta - alpha) / (2.0 * gamma);
           const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
@@ -106,6 +167,122 @@ __device__ int jacobi_onesided(double *A, int m, int n, double *Vm, int *flag) {
   return -1;
 }
 
+// Two-sided cyclic Jacobi for a symmetric A (d x d, column-major, LDS),
+// accumulating the rotations into V (identity on entry): A <- J^T A J,
+// V <- V J.  Each round rotates the disjoint pairs of the round-robin
+// ordering at once: angles from (A_pp, A_qq, A_pq), then all column
+// rotations, then all row rotations.  Off-diagonal entries at rounding level
+// of the matrix (null directions of a rank-deficient Gram) are left alone.
+// Returns the sweep count, or -1 without convergence.  Eigenvalues end on the
+// diagonal of A.
+__device__ int jacobi_sym(double *A, int d, double *V, int *flag) {
+  __shared__ double cs[TTR_RMAX / 2], sn[TTR_RMAX / 2];
+  __shared__ unsigned char pp[TTR_RMAX][TTR_RMAX / 2], qq[TTR_RMAX][TTR_RMAX / 2];
+  const int nn = d + (d & 1);
+  const int npair = nn / 2;
+  const double tol = kU * 4.0 * sqrt((double)(d > 1 ? d : 1));
+  // pair schedule of every round, computed once
+  for (int e = threadIdx.x; e < (nn - 1) * npair; e += blockDim.x) {
+    const int r = e / npair, k = e - r * npair;
+    int p, q;
+    rr_pair(r, k, nn, &p, &q);
+    pp[r][k] = (unsigned char)p;
+    qq[r][k] = (unsigned char)q;
+  }
+  const double fro2 = sumsq(A, d * d);
+  const double floor_abs = 8.0 * d * kU * sqrt(fro2);
+  // thread -> (pair kk, first row r0, row stride rs) for the rotation phases
+  const int lanes_per_pair = blockDim.x / npair;
+  const int kk = threadIdx.x % npair;
+  const int r0 = threadIdx.x / npair;
+  const bool active = r0 < lanes_per_pair;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    if (threadIdx.x == 0) *flag = 0;
+    __syncthreads();
+    for (int r = 0; r < nn - 1; ++r) {
+      if (threadIdx.x < npair) {
+        const int k = threadIdx.x;
+        const int p = pp[r][k], q = qq[r][k];
+        double c = 1.0, s = 0.0;
+        if (p < d && q < d) {
+          const double app = A[p + d * p], aqq = A[q + d * q], apq = A[p + d * q];
+          if (fabs(apq) > floor_abs && fabs(apq) > tol * sqrt(fabs(app)) * sqrt(fabs(aqq))) {
+            const double zeta = (aqq - app) / (2.0 * apq);
+            const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            c = 1.0 / sqrt(1.0 + t * t);
+            s = c * t;
+            *flag = 1;
+          }
+        }
+        cs[k] = c;
+        sn[k] = s;
+      }
+      __syncthreads();
+      // Each thread owns at most kRows rows (columns) of its pair; all its LDS
+      // reads are issued before any arithmetic so their latencies overlap.
+      if (active) {
+        const double s = sn[kk];
+        if (s != 0.0) {
+          const double c = cs[kk];
+          const int p = pp[r][kk], q = qq[r][kk];
+          double *Ap = A + d * p, *Aq = A + d * q, *Vp = V + d * p, *Vq = V + d * q;
+          double ap[kRows], aq[kRows], vp[kRows], vq[kRows];
+#pragma unroll
+          for (int m = 0; m < kRows; ++m) {  // columns: A <- A J, V <- V J
+            const int row = r0 + m * lanes_per_pair;
+            if (row < d) {
+              ap[m] = Ap[row];
+              aq[m] = Aq[row];
+              vp[m] = Vp[row];
+              vq[m] = Vq[row];
+            }
+          }
+#pragma unroll
+          for (int m = 0; m < kRows; ++m) {
+            const int row = r0 + m * lanes_per_pair;
+            if (row < d) {
+              Ap[row] = c * ap[m] - s * aq[m];
+              Aq[row] = s * ap[m] + c * aq[m];
+              Vp[row] = c * vp[m] - s * vq[m];
+              Vq[row] = s * vp[m] + c * vq[m];
+            }
+          }
+        }
+      }
+      __syncthreads();
+      if (active) {
+        const double s = sn[kk];
+        if (s != 0.0) {
+          const double c = cs[kk];
+          const int p = pp[r][kk], q = qq[r][kk];
+          double ap[kRows], aq[kRows];
+#pragma unroll
+          for (int m = 0; m < kRows; ++m) {  // rows: A <- J^T A
+            const int col = r0 + m * lanes_per_pair;
+            if (col < d) {
+              ap[m] = A[p + d * col];
+              aq[m] = A[q + d * col];
+            }
+          }
+#pragma unroll
+          for (int m = 0; m < kRows; ++m) {
+            const int col = r0 + m * lanes_per_pair;
+            if (col < d) {
+              A[p + d * col] = c * ap[m] - s * aq[m];
+              A[q + d * col] = s * ap[m] + c * aq[m];
+            }
+          }
+        }
+      }
+      __syncthreads();
+    }
+    const int any = *flag;
+    __syncthreads();
+    if (!any) return sweep + 1;
+  }
+  return -1;
+}
+
 // Descending ranks of key[0..n): perm[rank] = j.  Ties keep index order.
 __device__ void sort_desc(const double *key, int n, int *perm) {
   for (int j = threadIdx.x; j < n; j += blockDim.x) {
@@ -117,7 +294,60 @@ __device__ void sort_desc(const double *key, int n, int *perm) {
   __syncthreads();
 }
 
-__device__ inline bool finite(double x) { return x == x && fabs(x) <= DBL_MAX; }
+
+
+// Cholesky G = L L^T of the symmetric d x d matrix in A (LDS), in place (lower
+// triangle; the strict upper part is zeroed), then L^{-1} into Vm by forward
+// substitution, one column per thread.  Returns false when a pivot is not
+// positive.  With G symmetric, ||G||_2 <= ||G||_1 and
+// ||G^{-1}||_2 <= ||G^{-1}||_1 <= ||L^{-1}||_inf ||L^{-1}||_1, so
+// *kappa = ||G||_1 ||L^{-1}||_1 ||L^{-1}||_inf bounds kappa_2(G) from above and
+// *lmin_lb = 1 / min(||L^{-1}||_F^2, ||L^{-1}||_1 ||L^{-1}||_inf) bounds
+// lambda_min(G) from below.
+__device__ bool chol_inv(double *A, double *Vm, int d, double *kappa, double *lmin_lb) {
+  __shared__ int ok;
+  const double g1 = norm1(A, d);
+  if (threadIdx.x == 0) ok = 1;
+  __syncthreads();
+  for (int j = 0; j < d; ++j) {
+    if (threadIdx.x == 0) {
+      const double pv = A[j + d * j];
+      if (!(pv > 0.0)) ok = 0;
+      else A[j + d * j] = sqrt(pv);
+    }
+    __syncthreads();
+    if (!ok) return false;
+    const double ljj = A[j + d * j];
+    for (int r = j + 1 + threadIdx.x; r < d; r += blockDim.x) A[r + d * j] /= ljj;
+    __syncthreads();
+    // trailing update of the lower triangle: A(r, c) -= L(r, j) L(c, j), c <= r
+    const int n = d - j - 1;
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+      const int r = j + 1 + e % n, c = j + 1 + e / n;
+      if (c <= r) A[r + d * c] -= A[r + d * j] * A[c + d * j];
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < d * d; e += blockDim.x) {
+    const int r = e % d, c = e / d;
+    if (r < c) A[e] = 0.0;
+  }
+  __syncthreads();
+  // L^{-1}: column c solves L x = e_c
+  for (int c = threadIdx.x; c < d; c += blockDim.x) {
+    for (int r = 0; r < d; ++r) {
+      double v = (r == c) ? 1.0 : 0.0;
+      for (int k = c; k < r; ++k) v -= A[r + d * k] * Vm[k + d * c];
+      Vm[r + d * c] = (r < c) ? 0.0 : v / A[r + d * r];
+    }
+  }
+  __syncthreads();
+  const double lf2 = sumsq(Vm, d * d);
+  const double l1 = norm1(Vm, d), li = norminf(Vm, d);
+  *kappa = g1 * l1 * li;
+  *lmin_lb = 1.0 / fmin(lf2, l1 * li);
+  return true;
+}
 
 // ---------------------------------------------------------------------------
 // QR-by-Gram step.  Input: G = Gram of the current staged unfolding
@@ -131,9 +361,10 @@ __device__ inline bool finite(double x) { return x == x && fabs(x) <= DBL_MAX; }
 //           rounding noise of a rank-deficient unfolding), F = W_k t_k^{-1/2};
 //           done when t_k >= tau1 t_1 (or at pass 3).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_qr_step(QrStepArgs a) {
+__global__ __launch_bounds__(kThreadsQR) void k_qr_step(QrStepArgs a) {
   __shared__ double A[TTR_RMAX * TTR_RMAX];
   __shared__ double Vm[TTR_RMAX * TTR_RMAX];
+  __shared__ double Bf[TTR_RMAX * TTR_RMAX];
   __shared__ double lam[TTR_RMAX];
   __shared__ double sc[TTR_RMAX];
   __shared__ double rs[TTR_RMAX];
@@ -150,18 +381,22 @@ __global__ __launch_bounds__(kThreads) void k_qr_step(QrStepArgs a) {
       if (!finite(g)) bad = 1;
       A[e] = g;
     }
+    for (int e = threadIdx.x; e < m * d; e += blockDim.x) {
+      const int r = e % m, c = e / m;
+      Bf[r + m * c] = a.Tpost[r * a.tsr + c * a.tsc];
+    }
     __syncthreads();
     for (int e = threadIdx.x; e < m * d; e += blockDim.x) {
       const int r = e % m, c = e / m;
       double s = 0.0;
-      for (int k = 0; k < m; ++k) s += A[r + m * k] * a.Tpost[k * a.tsr + c * a.tsc];
+      for (int k = 0; k < m; ++k) s += A[r + m * k] * Bf[k + m * c];
       Vm[r + m * c] = s;
     }
     __syncthreads();
     for (int e = threadIdx.x; e < d * d; e += blockDim.x) {
       const int r = e % d, c = e / d;
       double s = 0.0;
-      for (int k = 0; k < m; ++k) s += a.Tpost[k * a.tsr + r * a.tsc] * Vm[k + m * c];
+      for (int k = 0; k < m; ++k) s += Bf[k + m * r] * Vm[k + m * c];
       A[r + d * c] = s;
     }
     __syncthreads();
@@ -196,13 +431,59 @@ __global__ __launch_bounds__(kThreads) void k_qr_step(QrStepArgs a) {
     }
     return;
   }
-  const int sweeps = jacobi_onesided(A, d, d, Vm, &flag);
-  // A = G V: eigenvalue j is the Rayleigh quotient v_j^T G v_j = v_j . A(:, j)
-  for (int j = threadIdx.x; j < d; j += blockDim.x) {
-    double s = 0.0;
-    for (int r = 0; r < d; ++r) s += Vm[j * d + r] * A[j * d + r];
-    lam[j] = s;
+  if (a.try_chol && a.pass == 1) {
+    // One-pass attempt by Cholesky, G = L L^T: F = L^{-T}, R = L^T, T = L.
+    // Accepted when kappa(G) (bounded by ||G||_F ||L^{-1}||_F^2, scaled by
+    // kappa(T)^2 when G came through a post-transform) is at most 1/tau1, and,
+    // in the truncation sweep, when no singular value can fall below delta.
+    __shared__ int accept;
+    for (int e = threadIdx.x; e < d * d; e += blockDim.x) Bf[e] = A[e];  // keep G for a fallback
+    double trace_part = 0.0;
+    for (int j = threadIdx.x; j < d; j += blockDim.x) trace_part += A[j + d * j];
+    const double trG = block_sum(trace_part);
+    double kappa = 0.0, lmin_lb = 0.0;
+    const bool ok = chol_inv(A, Vm, d, &kappa, &lmin_lb);
+    if (threadIdx.x == 0) {
+      int acc = ok && (kappa == kappa) && kappa * (a.cond_scale > 1.0 ? a.cond_scale : 1.0) * a.tau1 <= 1.0;
+      int notrunc = 0;
+      if (acc && a.notrunc_check) {
+        const double dl = a.first ? sqrt(a.tol2_nm1 * trG) : *a.delta_dev;
+        notrunc = (lmin_lb > 4.0 * dl * dl);
+        acc = notrunc;
+      }
+      if (a.ratio_out) *a.ratio_out = ok ? kappa : 1e300;
+      accept = acc;
+      a.dec[5] = notrunc;
+    }
+    __syncthreads();
+    if (accept) {
+      // A holds L (lower), Vm holds L^{-1} (lower)
+      const int b = a.b;  // == d at pass 1
+      for (int e = threadIdx.x; e < d * d; e += blockDim.x) {
+        const int r = e % d, c = e / d;
+        a.Fstep[r + d * c] = Vm[c + d * r];       // F = L^{-T}
+        a.Rnext[r + d * c] = A[c + d * r];        // R = L^T
+        if (a.Tdst) a.Tdst[r + b * c] = A[r + d * c];  // T = L
+      }
+      if (threadIdx.x == 0) {
+        a.dec[0] = d;
+        a.dec[1] = 1;
+        a.dec[4] = 1;  // triangular factors
+      }
+      return;
+    }
+    // fall back: G again for the eigen route
+    for (int e = threadIdx.x; e < d * d; e += blockDim.x) {
+      A[e] = Bf[e];
+      const int r = e % d, c = e / d;
+      Vm[e] = (r == c) ? 1.0 : 0.0;
+    }
+    __syncthreads();
   }
+  if (threadIdx.x == 0) a.dec[5] = 0;
+  if (threadIdx.x == 0) a.dec[4] = 0;
+  const int sweeps = jacobi_sym(A, d, Vm, &flag);
+  for (int j = threadIdx.x; j < d; j += blockDim.x) lam[j] = A[j + d * j];
   __syncthreads();
   sort_desc(lam, d, perm);
   // sorted eigenvectors into A (no longer needed), sorted eigenvalues into sc
@@ -267,12 +548,16 @@ __global__ __launch_bounds__(kThreads) void k_qr_step(QrStepArgs a) {
     a.Fstep[r + d * c] = A[r + d * c] * sc[c];
   }
   // Rnext (k x b) = diag(rs) W[:, :k]^T Rc (d x b)
+  if (a.Rc) {
+    for (int e = threadIdx.x; e < d * b; e += blockDim.x) Bf[e] = a.Rc[e];
+    __syncthreads();
+  }
   for (int e = threadIdx.x; e < k * b; e += blockDim.x) {
     const int r = e % k, c = e / k;
     double s;
     if (a.Rc) {
       s = 0.0;
-      for (int j = 0; j < d; ++j) s += A[j + d * r] * a.Rc[j + d * c];
+      for (int j = 0; j < d; ++j) s += A[j + d * r] * Bf[j + d * c];
     } else {
       s = A[c + d * r];
     }
@@ -299,13 +584,39 @@ __global__ __launch_bounds__(kThreads) void k_trunc_step(TruncArgs a) {
   __shared__ int perm[TTR_RMAX];
   __shared__ int flag, LL;
   const int k = a.k, b = a.b;
+  if (a.identity) {
+    // no truncation possible (proved by the step kernel): U = I, Sigma V^T = R
+    const double n2 = sumsq(a.R, k * b);
+    if (threadIdx.x == 0) {
+      if (a.first) {
+        const double nrm = sqrt(n2);
+        *a.norm = nrm;
+        *a.delta = (a.Nm1 > 0) ? a.tol * nrm / sqrt((double)a.Nm1) : 0.0;
+      }
+      for (int j = 0; j < TTR_RMAX; ++j) a.sigma_out[j] = 0.0;
+      a.dec[3] = k;
+    }
+    const int d = a.d;
+    for (int e = threadIdx.x; e < d * k; e += blockDim.x) a.GU[e] = a.Glast[e];
+    if (a.Pnext) {
+      const int dn = a.dn;
+      for (int e = threadIdx.x; e < k * dn; e += blockDim.x) {
+        const int l = e % k, r = e / k;
+        double s = 0.0;
+        for (int j = 0; j < b; ++j) s += a.R[l + k * j] * a.Fn[r + dn * j];
+        a.Pnext[l + k * r] = s;
+      }
+    }
+    return;
+  }
   for (int e = threadIdx.x; e < b * k; e += blockDim.x) {
     const int r = e % b, c = e / b;     // A(r, c) = R(c, r)
     A[r + b * c] = a.R[c + k * r];
   }
   for (int e = threadIdx.x; e < k * k; e += blockDim.x) Um[e] = (e % k == e / k) ? 1.0 : 0.0;
   __syncthreads();
-  const int sweeps = jacobi_onesided(A, b, k, Um, &flag);
+  // rows of R already orthogonal (one-pass eigen route, R = t^{1/2} W^T): no rotations needed
+  const int sweeps = a.r_orth ? 1 : jacobi_onesided(A, b, k, Um, &flag);
   for (int j = threadIdx.x; j < k; j += blockDim.x) {
     double s = 0.0;
     for (int r = 0; r < b; ++r) s += A[r + b * j] * A[r + b * j];
@@ -380,7 +691,7 @@ __global__ void k_sqrt_scalar(const double *in, double *out) {
 }  // namespace
 
 void launch_qr_step(hipStream_t s, const QrStepArgs &a) {
-  hipLaunchKernelGGL(k_qr_step, dim3(1), dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL(k_qr_step, dim3(1), dim3(kThreadsQR), 0, s, a);
 }
 
 void launch_trunc_step(hipStream_t s, const TruncArgs &a) {

@@ -16,33 +16,22 @@ constexpr int kThreads = 256;
 constexpr size_t kLdsBudget = 60 * 1024;  // bytes of dynamic LDS per workgroup
 
 // ---------------------------------------------------------------------------
-// Sum: one thread per output entry, grid-stride.  Output core n of Z has the
-// X block first (§3.2.1); off-diagonal blocks are explicit zeros.
+// Sum: output column b of core n (blockIdx.y) is zr0*I contiguous doubles;
+// thread e of the column holds entry (a, i) = (e mod zr0, e div zr0).  The X
+// block comes first (§3.2.1); off-diagonal blocks are explicit zeros.
 // ---------------------------------------------------------------------------
 __global__ void k_add(int n, int N, double alpha, double beta, const double *__restrict__ X, int rx0, int rx1,
-                      const double *__restrict__ Y, int ry0, int ry1, long long I, double *__restrict__ Z) {
+                      const double *__restrict__ Y, int ry0, int ry1, int I, double *__restrict__ Z) {
 #pragma clang fp contract(off)
-  int zr0, zr1;
-  if (N == 1) {
-    zr0 = 1;
-    zr1 = 1;
-  } else if (n == 0) {
-    zr0 = 1;
-    zr1 = rx1 + ry1;
-  } else if (n == N - 1) {
-    zr0 = rx0 + ry0;
-    zr1 = 1;
-  } else {
-    zr0 = rx0 + ry0;
-    zr1 = rx1 + ry1;
-  }
-  const long long total = (long long)zr0 * I * zr1;
-  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (long long)gridDim.x * blockDim.x) {
-    const long long b = e / ((long long)zr0 * I);
-    const long long rem = e - b * zr0 * I;
-    const long long i = rem / zr0;
-    const int a = (int)(rem - i * zr0);
+  int zr0;
+  if (N == 1 || n == 0) zr0 = 1;
+  else zr0 = rx0 + ry0;
+  const int b = blockIdx.y;
+  const int colsz = zr0 * I;
+  const long long zoff = (long long)colsz * b;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < colsz; e += gridDim.x * blockDim.x) {
+    const int i = e / zr0;
+    const int a = e - i * zr0;
     double v;
     if (N == 1) {
       // each product rounded on its own, as in the plain definition (no FMA)
@@ -50,37 +39,38 @@ __global__ void k_add(int n, int N, double alpha, double beta, const double *__r
       const double by = beta * Y[i];
       v = ax + by;
     } else if (n == 0) {
-      v = (b < rx1) ? alpha * X[i + I * b] : beta * Y[i + I * (b - rx1)];
+      v = (b < rx1) ? alpha * X[i + (long long)I * b] : beta * Y[i + (long long)I * (b - rx1)];
     } else if (n == N - 1) {
-      v = (a < rx0) ? X[a + rx0 * i] : Y[(a - rx0) + ry0 * i];
+      v = (a < rx0) ? X[a + rx0 * (long long)i] : Y[(a - rx0) + ry0 * (long long)i];
     } else if (a < rx0 && b < rx1) {
-      v = X[a + rx0 * (i + I * b)];
+      v = X[a + (long long)rx0 * (i + (long long)I * b)];
     } else if (a >= rx0 && b >= rx1) {
-      v = Y[(a - rx0) + ry0 * (i + I * (b - rx1))];
+      v = Y[(a - rx0) + (long long)ry0 * (i + (long long)I * (b - rx1))];
     } else {
       v = 0.0;
     }
-    Z[e] = v;
+    Z[zoff + e] = v;
   }
 }
 
 // ---------------------------------------------------------------------------
-// Hadamard: Z(ax*ry0 + ay, i, bx*ry1 + by) = X(ax, i, bx) * Y(ay, i, by).
+// Hadamard: Z(ax*ry0 + ay, i, bx*ry1 + by) = X(ax, i, bx) * Y(ay, i, by);
+// output column b = bx*ry1 + by per blockIdx.y.
 // ---------------------------------------------------------------------------
 __global__ void k_hadamard(const double *__restrict__ X, int rx0, int rx1, const double *__restrict__ Y, int ry0,
-                           int ry1, long long I, double *__restrict__ Z) {
+                           int ry1, int I, double *__restrict__ Z) {
   const int zr0 = rx0 * ry0;
-  const int zr1 = rx1 * ry1;
-  const long long total = (long long)zr0 * I * zr1;
-  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (long long)gridDim.x * blockDim.x) {
-    const long long b = e / ((long long)zr0 * I);
-    const long long rem = e - b * zr0 * I;
-    const long long i = rem / zr0;
-    const int a = (int)(rem - i * zr0);
+  const int b = blockIdx.y;
+  const int bx = b / ry1, by = b - bx * ry1;
+  const int colsz = zr0 * I;
+  const long long zoff = (long long)colsz * b;
+  const double *Xb = X + (long long)rx0 * I * bx;
+  const double *Yb = Y + (long long)ry0 * I * by;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < colsz; e += gridDim.x * blockDim.x) {
+    const int i = e / zr0;
+    const int a = e - i * zr0;
     const int ax = a / ry0, ay = a - ax * ry0;
-    const int bx = (int)(b / ry1), by = (int)(b - (long long)bx * ry1);
-    Z[e] = X[ax + rx0 * (i + I * bx)] * Y[ay + ry0 * (i + I * by)];
+    Z[zoff + e] = Xb[ax + rx0 * (long long)i] * Yb[ay + ry0 * (long long)i];
   }
 }
 
@@ -274,12 +264,26 @@ __global__ __launch_bounds__(kThreads) void k_gram(CoreView cv, Stages st, int m
 }
 
 // Fixed-order sum of the per-workgroup partials: G[e] = sum_w partials[w][e].
-__global__ void k_reduce(const double *__restrict__ partials, int nwg, int ne, double *__restrict__ G) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= ne) return;
+// A block handles 16 entries; its 16 x 16 threads each sum one contiguous
+// segment of the partials, and the 16 segment sums are added in order.
+constexpr int kRedEnt = 16, kRedSeg = 16;
+__global__ __launch_bounds__(kRedEnt *kRedSeg) void k_reduce(const double *__restrict__ partials, int nwg, int ne,
+                                                             double *__restrict__ G) {
+  __shared__ double part[kRedSeg][kRedEnt];
+  const int le = threadIdx.x % kRedEnt, seg = threadIdx.x / kRedEnt;
+  const int e = blockIdx.x * kRedEnt + le;
+  const int per = (nwg + kRedSeg - 1) / kRedSeg;
+  const int w0 = seg * per, w1 = min(nwg, w0 + per);
   double s = 0.0;
-  for (int w = 0; w < nwg; ++w) s += partials[(long long)w * ne + e];
-  G[e] = s;
+  if (e < ne)
+    for (int w = w0; w < w1; ++w) s += partials[(long long)w * ne + e];
+  part[seg][le] = s;
+  __syncthreads();
+  if (seg == 0 && e < ne) {
+    double t = 0.0;
+    for (int k = 0; k < kRedSeg; ++k) t += part[k][le];
+    G[e] = t;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -404,22 +408,23 @@ long long slices_per_wg(long long I, int T, int nwg) {
 
 void launch_add(hipStream_t s, int n, int N, double alpha, double beta, const double *X, int rx0, int rx1,
                 const double *Y, int ry0, int ry1, long long I, double *Z) {
-  long long total;
-  if (N == 1) total = I;
-  else if (n == 0) total = I * (rx1 + ry1);
-  else if (n == N - 1) total = (long long)(rx0 + ry0) * I;
-  else total = (long long)(rx0 + ry0) * I * (rx1 + ry1);
-  const long long blocks = std::min((total + kThreads - 1) / kThreads, 65536LL);
-  hipLaunchKernelGGL(k_add, dim3((unsigned)std::max(blocks, 1LL)), dim3(kThreads), 0, s, n, N, alpha, beta, X, rx0,
-                     rx1, Y, ry0, ry1, I, Z);
+  int zr0, zr1;
+  if (N == 1) zr0 = zr1 = 1;
+  else if (n == 0) { zr0 = 1; zr1 = rx1 + ry1; }
+  else if (n == N - 1) { zr0 = rx0 + ry0; zr1 = 1; }
+  else { zr0 = rx0 + ry0; zr1 = rx1 + ry1; }
+  const long long colsz = (long long)zr0 * I;
+  const long long bx = std::min((colsz + kThreads - 1) / kThreads, 4096LL);
+  hipLaunchKernelGGL(k_add, dim3((unsigned)std::max(bx, 1LL), (unsigned)zr1), dim3(kThreads), 0, s, n, N, alpha, beta,
+                     X, rx0, rx1, Y, ry0, ry1, (int)I, Z);
 }
 
 void launch_hadamard(hipStream_t s, const double *X, int rx0, int rx1, const double *Y, int ry0, int ry1, long long I,
                      double *Z) {
-  const long long total = (long long)rx0 * ry0 * I * rx1 * ry1;
-  const long long blocks = std::min((total + kThreads - 1) / kThreads, 65536LL);
-  hipLaunchKernelGGL(k_hadamard, dim3((unsigned)std::max(blocks, 1LL)), dim3(kThreads), 0, s, X, rx0, rx1, Y, ry0,
-                     ry1, I, Z);
+  const long long colsz = (long long)rx0 * ry0 * I;
+  const long long bx = std::min((colsz + kThreads - 1) / kThreads, 4096LL);
+  hipLaunchKernelGGL(k_hadamard, dim3((unsigned)std::max(bx, 1LL), (unsigned)(rx1 * ry1)), dim3(kThreads), 0, s, X,
+                     rx0, rx1, Y, ry0, ry1, (int)I, Z);
 }
 
 int launch_gram(hipStream_t s, const CoreView &cv, const Stages &st, int mode, double *partials, double *G,
@@ -437,7 +442,8 @@ int launch_gram(hipStream_t s, const CoreView &cv, const Stages &st, int mode, d
 }
 
 void launch_reduce(hipStream_t s, const double *partials, int nwg, int ne, double *G) {
-  hipLaunchKernelGGL(k_reduce, dim3((ne + kThreads - 1) / kThreads), dim3(kThreads), 0, s, partials, nwg, ne, G);
+  hipLaunchKernelGGL(k_reduce, dim3((ne + kRedEnt - 1) / kRedEnt), dim3(kRedEnt * kRedSeg), 0, s, partials, nwg, ne,
+                     G);
 }
 
 void launch_apply(hipStream_t s, const CoreView &cv, const Stages &st, double *Y, int trans_out) {
@@ -462,6 +468,5 @@ void launch_dot_step(hipStream_t s, const double *X, int rx0, int rx1, const dou
   const size_t lds = (size_t)(per * T) * sizeof(double);
   hipLaunchKernelGGL(k_dot_step, dim3(nwg_used), dim3(kThreads), lds, s, X, rx0, rx1, Y, ry0, ry1, I, Wp, (int)T, spw,
                      partials);
-  const int ne = ry1 * rx1;
-  hipLaunchKernelGGL(k_reduce, dim3((ne + kThreads - 1) / kThreads), dim3(kThreads), 0, s, partials, nwg_used, ne, W);
+  launch_reduce(s, partials, nwg_used, ry1 * rx1, W);
 }
