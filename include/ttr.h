@@ -145,17 +145,20 @@ int ttr_get_round_stats(const ttr_handle *h, ttr_round_stats *out);
 
 /* Opt-in kernel timing.  With profiling on, every streaming launch made by the
  * handle is bracketed by HIP events on the handle's stream and its duration,
- * count and algorithmic traffic/work are accumulated per kernel class:
- *   0 Gram pass   bytes = the core read once, flops = the staged slice
- *                 products plus the (symmetric) Gram accumulation
- *   1 apply pass  bytes = core read + output core written, flops = products
- *   2 sum         bytes = both inputs read + output written
- *   3 Hadamard    bytes = both inputs read + output written, flops = outputs
- *   4 inner-product step, 5 small dense kernels (one workgroup).
- * Durations are resolved at the end of each synchronizing call (ttr_dot,
- * ttr_norm, ttr_orthogonalize, ttr_round) and by ttr_get_profile, which waits
- * for the stream.  ttr_set_profiling(h, 1) also clears the accumulators. */
-#define TTR_NPROF 6
+ * count and algorithmic traffic/work are accumulated per kernel:
+ *   0 k_gram_right_factor  Gram pass with a right factor (orthonormalization)
+ *   1 k_gram_left_factor   Gram pass with a left factor (truncation)
+ *   2 k_gram               staged generic Gram pass (refinement passes)
+ *   3 k_apply_mfma         output pass, matrix cores
+ *   4 k_apply              staged generic output pass
+ *   5 k_add  6 k_hadamard  7 k_dot_step  8 small one-workgroup kernels
+ * Gram passes: bytes = the core read once, flops = the slice products plus the
+ * symmetric Gram accumulation; output passes: bytes = core read + output
+ * written, flops = the slice products; sum/Hadamard: bytes = inputs read +
+ * output written.  Durations are resolved at the end of each synchronizing
+ * call and by ttr_get_profile, which waits for the stream.
+ * ttr_set_profiling(h, 1) also clears the accumulators. */
+#define TTR_NPROF 9
 typedef struct ttr_profile {
   int64_t count[TTR_NPROF];
   double ms[TTR_NPROF];

@@ -134,7 +134,7 @@ WS carve(ttr_handle *h, int N, size_t tmp) {
 }
 
 // --- opt-in kernel timing ------------------------------------------------
-enum { P_GRAM = 0, P_APPLY = 1, P_ADD = 2, P_HAD = 3, P_DOT = 4, P_SMALL = 5 };
+enum { P_GRAM_R = 0, P_GRAM_L = 1, P_GRAM_G = 2, P_APPLY = 3, P_APPLY_G = 4, P_ADD = 5, P_HAD = 6, P_DOT = 7, P_SMALL = 8 };
 
 hipEvent_t take_event(ttr_handle *h) {
   if (!h->evpool.empty()) {
@@ -204,6 +204,7 @@ double chain_flops(const CoreView &cv, const Stages &st, int *zr, int *zc) {
 const bool g_use_mfma = (std::getenv("TTR_GENERIC_KERNELS") == nullptr);
 
 // A stage on the physical core: transposed views swap roles (Z^T = R^T X L^T).
+// transposes swap lower <-> upper: "lower" 1 = lower, 2 = upper
 Stage st_transpose(const Stage &a) {
   Stage t;
   t.S = a.S;
@@ -211,6 +212,7 @@ Stage st_transpose(const Stage &a) {
   t.cols = a.rows;
   t.sr = a.sc;
   t.sc = a.sr;
+  t.lower = (a.lower == 1) ? 2 : (a.lower == 2 ? 1 : 0);
   return t;
 }
 
@@ -236,23 +238,23 @@ void gram(ttr_handle *h, double *partials, double *G, const CoreView &cv, const 
       const Stage *q = pnr ? (tr ? &st.L[0] : &st.R[0]) : nullptr;
       Stage qq;
       if (q) qq = tr ? st_transpose(*q) : *q;
-      ProfScope ps(h, P_GRAM, 8.0 * cv.pa * cv.pb * (double)cv.I, (cf + gf) * (double)cv.I);
+      ProfScope ps(h, P_GRAM_R, 8.0 * cv.pa * cv.pb * (double)cv.I, (cf + gf) * (double)cv.I);
       nwg = launch_gram_right_factor(h->stream, X, cv.pa, cv.pb, cv.I, q ? qq.S : nullptr, q ? qq.cols : cv.pb,
-                                     q ? qq.sr : 1, q ? qq.sc : cv.pb, partials);
+                                     q ? qq.sr : 1, q ? qq.sc : cv.pb, (q && qq.lower == 1) ? 1 : 0, partials);
       done = true;
     } else if (pmode == GRAM_RIGHT && pnl <= 1 && pnr == 0) {
       // sum (P X)^T (P X)
       const Stage *pp = pnl ? (tr ? &st.R[0] : &st.L[0]) : nullptr;
       Stage ps_;
       if (pp) ps_ = tr ? st_transpose(*pp) : *pp;
-      ProfScope ps(h, P_GRAM, 8.0 * cv.pa * cv.pb * (double)cv.I, (cf + gf) * (double)cv.I);
+      ProfScope ps(h, P_GRAM_L, 8.0 * cv.pa * cv.pb * (double)cv.I, (cf + gf) * (double)cv.I);
       nwg = launch_gram_left_factor(h->stream, X, cv.pa, cv.pb, cv.I, pp ? ps_.S : nullptr, pp ? ps_.rows : cv.pa,
-                                    pp ? ps_.sr : 1, pp ? ps_.sc : cv.pa, partials);
+                                    pp ? ps_.sr : 1, pp ? ps_.sc : cv.pa, (pp && ps_.lower == 2) ? 1 : 0, partials);
       done = true;
     }
   }
   if (!done) {
-    ProfScope ps(h, P_GRAM, 8.0 * cv.pa * cv.pb * (double)cv.I, (cf + gf) * (double)cv.I);
+    ProfScope ps(h, P_GRAM_G, 8.0 * cv.pa * cv.pb * (double)cv.I, (cf + gf) * (double)cv.I);
     nwg = launch_gram(h->stream, cv, st, mode, partials, G, 0);
   }
   launch_reduce(h->stream, partials, nwg, gd * gd, G);
@@ -263,9 +265,10 @@ void gram(ttr_handle *h, double *partials, double *G, const CoreView &cv, const 
 void apply(ttr_handle *h, const CoreView &cv, const Stages &st, double *Y, int trans_out) {
   int zr, zc;
   const double cf = chain_flops(cv, st, &zr, &zc);
-  ProfScope ps(h, P_APPLY, 8.0 * ((double)cv.pa * cv.pb + (double)zr * zc) * (double)cv.I, cf * (double)cv.I);
+  const double abytes = 8.0 * ((double)cv.pa * cv.pb + (double)zr * zc) * (double)cv.I;
   const bool tr = cv.trans != 0;
   if (g_use_mfma && st.nl <= 1 && st.nr <= 1 && trans_out == cv.trans) {
+    ProfScope ps(h, P_APPLY, abytes, cf * (double)cv.I);
     // physical: Y_phys = Pp X Qp; trans views: (L M' R)^T = R^T X L^T
     const Stage *L = st.nl ? &st.L[0] : nullptr;
     const Stage *R = st.nr ? &st.R[0] : nullptr;
@@ -279,6 +282,7 @@ void apply(ttr_handle *h, const CoreView &cv, const Stages &st, double *Y, int t
                       pr ? Q.sc : cv.pb, Y);
     return;
   }
+  ProfScope ps(h, P_APPLY_G, abytes, cf * (double)cv.I);
   launch_apply(h->stream, cv, st, Y, trans_out);
 }
 
@@ -319,8 +323,9 @@ struct Seq {
 };
 
 // Stage constructors (column-major small matrices)
-Stage st_plain(const double *M, int rows, int cols) {  // M (rows x cols, ld rows)
+Stage st_plain(const double *M, int rows, int cols, int lower = 0) {  // M (rows x cols, ld rows)
   Stage s;
+  s.lower = lower;
   s.S = M;
   s.rows = rows;
   s.cols = cols;
@@ -330,6 +335,7 @@ Stage st_plain(const double *M, int rows, int cols) {  // M (rows x cols, ld row
 }
 Stage st_trans(const double *M, int rows, int cols) {  // M^T where M is (cols x rows, ld cols)
   Stage s;
+  s.lower = 0;
   s.S = M;
   s.rows = rows;
   s.cols = cols;
@@ -349,6 +355,7 @@ Stages no_stages() {
 struct Factor {
   int nst = 0;
   int dim[4] = {0, 0, 0, 0};
+  int tri = 0;  // one-pass Cholesky route: T = L lower triangular, F = L^{-T}
 };
 
 // One QR-by-Gram factorization of a tall-skinny unfolding of a logical core,
@@ -430,6 +437,7 @@ int qr_by_gram(ttr_handle *h, WS &w, const CoreView &cv, int mode, const Stages 
     const int done = h->dec_host[1];
     if (pass == 1 && ratio) *ratio = h->decf_host[0];
     if (tc) tc->notrunc = (pass == 1 && done) ? h->dec_host[5] : 0;
+    f->tri = (pass == 1 && done) ? h->dec_host[4] : 0;
     f->nst = pass;
     f->dim[pass] = k;
     if (mode == GRAM_LEFT) st.L[st.nl++] = st_trans(qa.Fstep, k, d);
@@ -460,7 +468,7 @@ int orth_sweep(ttr_handle *h, WS &w, const Seq &S, std::vector<int> &k, std::vec
     const CoreView cv = S.view(n);
     const int b = cv.ea();
     Stages base = no_stages();
-    if (n < N - 1) base.R[base.nr++] = st_plain(w.T(n + 1), cv.eb(), k[n + 1]);
+    if (n < N - 1) base.R[base.nr++] = st_plain(w.T(n + 1), cv.eb(), k[n + 1], fac[n + 1].tri ? 1 : 0);
     double *Rout;
     int kn;
     auto slot = [&](int j) { return w.B(n, j); };

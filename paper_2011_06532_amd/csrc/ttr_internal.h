@@ -32,6 +32,7 @@ struct Stage {
   const double *S;
   int rows, cols;
   long long sr, sc;
+  int lower;  // S is lower triangular (S(r, c) = 0 for c > r); 0 when unknown
 };
 constexpr int kMaxLeft = 4;
 constexpr int kMaxRight = 5;
@@ -60,10 +61,11 @@ void launch_reduce(hipStream_t s, const double *partials, int nwg, int ne, doubl
 void launch_apply(hipStream_t s, const CoreView &cv, const Stages &st, double *Y, int trans_out);
 // W (ry1 x rx1) = sum_i Y(i)^T Wp X(i), Wp is ry0 x rx0 col-major.
 // FP64 MFMA paths (ttr_mfma.hip) on physical cores (a x I x b), dims <= 64.
+// tri: the factor is triangular (Q lower / P upper), zero fragments are skipped.
 int launch_gram_right_factor(hipStream_t s, const double *X, int a, int b, long long I, const double *Q, int q,
-                             long long sQr, long long sQc, double *partials);
+                             long long sQr, long long sQc, int tri, double *partials);
 int launch_gram_left_factor(hipStream_t s, const double *X, int a, int b, long long I, const double *P, int p,
-                            long long sPr, long long sPa, double *partials);
+                            long long sPr, long long sPa, int tri, double *partials);
 void launch_apply_mfma(hipStream_t s, const double *X, int a, int b, long long I, const double *P, int p,
                        long long sPr, long long sPa, const double *Q, int q, long long sQr, long long sQc,
                        double *Y);

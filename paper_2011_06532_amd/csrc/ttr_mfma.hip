@@ -123,7 +123,7 @@ __device__ inline void load_slice(const double *__restrict__ Xi, long long col, 
 template <int NT, int KS>
 __global__ __launch_bounds__(kThreads) void k_gram_right_factor(const double *__restrict__ X, int a, int b, long long I,
                                                                 const double *__restrict__ Q, int q, long long sQr,
-                                                                long long sQc, long long spw,
+                                                                long long sQc, int tri, long long spw,
                                                                 double *__restrict__ partials) {
   __shared__ double frag[NT * KS * 64];
   __shared__ double Gs[NT * 16 * NT * 16];
@@ -154,20 +154,24 @@ __global__ __launch_bounds__(kThreads) void k_gram_right_factor(const double *__
     for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
       for (int cb = 0; cb < NT; ++cb) {
+        // lower-triangular Q: Q^T(c, beta) = 0 for beta < c, so k-steps below 4 cb vanish
+        if (tri && ks < 4 * cb) continue;
         const double qa = frag[(cb * KS + ks) * 64 + lane];
 #pragma unroll
         for (int t = 0; t < NT; ++t) wt[cb][t] = mfma(qa, cur[ks][t], wt[cb][t]);
       }
     // G(alpha, alpha') += sum_c Wt(c, alpha) Wt(c, alpha'); consecutive MFMAs
-    // go to different G tiles
+    // go to different G tiles; k-steps past q are zero padding
 #pragma unroll
     for (int cb = 0; cb < NT; ++cb)
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
+      for (int r = 0; r < 4; ++r) {
+        if (cb * 16 + 4 * r >= q) continue;
 #pragma unroll
         for (int u = 0; u < NT; ++u)
 #pragma unroll
           for (int v = 0; v <= u; ++v) G[u][v] = mfma(wt[cb][u][r], wt[cb][v][r], G[u][v]);
+      }
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
@@ -184,7 +188,7 @@ __global__ __launch_bounds__(kThreads) void k_gram_right_factor(const double *__
 template <int NT, int KS>
 __global__ __launch_bounds__(kThreads) void k_gram_left_factor(const double *__restrict__ X, int a, int b, long long I,
                                                                const double *__restrict__ P, int p, long long sPr,
-                                                               long long sPa, long long spw,
+                                                               long long sPa, int tri, long long spw,
                                                                double *__restrict__ partials) {
   __shared__ double frag[NT * KS * 64];
   __shared__ double Gs[NT * 16 * NT * 16];
@@ -214,19 +218,23 @@ __global__ __launch_bounds__(kThreads) void k_gram_left_factor(const double *__r
     for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
       for (int rb = 0; rb < NT; ++rb) {
+        // upper-triangular P: P(rho, alpha) = 0 for alpha < rho
+        if (tri && ks < 4 * rb) continue;
         const double pa = frag[(rb * KS + ks) * 64 + lane];
 #pragma unroll
         for (int t = 0; t < NT; ++t) y[rb][t] = mfma(pa, cur[ks][t], y[rb][t]);
       }
-    // G0(beta, beta') += sum_rho Y(rho, beta) Y(rho, beta')
+    // G0(beta, beta') += sum_rho Y(rho, beta) Y(rho, beta'); rows past p are padding
 #pragma unroll
     for (int rb = 0; rb < NT; ++rb)
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
+      for (int r = 0; r < 4; ++r) {
+        if (rb * 16 + 4 * r >= p) continue;
 #pragma unroll
         for (int u = 0; u < NT; ++u)
 #pragma unroll
           for (int v = 0; v <= u; ++v) G[u][v] = mfma(y[rb][u][r], y[rb][v][r], G[u][v]);
+      }
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
@@ -287,13 +295,15 @@ __global__ __launch_bounds__(kThreads) void k_apply_mfma(const double *__restric
 #pragma unroll
       for (int t = 0; t < NT; ++t)
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
+        for (int r = 0; r < 4; ++r) {
+          if (t * 16 + 4 * r >= a) continue;  // rows of W past a are padding
 #pragma unroll
           for (int rb = 0; rb < NT; ++rb) {
             const double pa = fragP[(rb * KA + t * 4 + r) * 64 + lane];
 #pragma unroll
             for (int cb = 0; cb < NT; ++cb) y[rb][cb] = mfma(pa, w[t][cb][r], y[rb][cb]);
           }
+        }
 #pragma unroll
       for (int rb = 0; rb < NT; ++rb)
 #pragma unroll
@@ -363,20 +373,20 @@ int tiles_for(int m) { return (m + 15) / 16; }
   }
 
 int launch_gram_right_factor(hipStream_t s, const double *X, int a, int b, long long I, const double *Q, int q,
-                             long long sQr, long long sQc, double *partials) {
+                             long long sQr, long long sQc, int tri, double *partials) {
   const Grid gr = grid_of(I);
   const int nt = std::max({tiles_for(a), tiles_for(b), tiles_for(q)});
   const int ks = std::max((b + 3) / 4, 4 * nt - 3);
-  TTR_NT_CASES(k_gram_right_factor, X, a, b, I, Q, q, sQr, sQc, gr.spw, partials)
+  TTR_NT_CASES(k_gram_right_factor, X, a, b, I, Q, q, sQr, sQc, tri, gr.spw, partials)
   return gr.nwg;
 }
 
 int launch_gram_left_factor(hipStream_t s, const double *X, int a, int b, long long I, const double *P, int p,
-                            long long sPr, long long sPa, double *partials) {
+                            long long sPr, long long sPa, int tri, double *partials) {
   const Grid gr = grid_of(I);
   const int nt = std::max({tiles_for(a), tiles_for(b), tiles_for(p)});
   const int ks = std::max((a + 3) / 4, 4 * nt - 3);
-  TTR_NT_CASES(k_gram_left_factor, X, a, b, I, P, p, sPr, sPa, gr.spw, partials)
+  TTR_NT_CASES(k_gram_left_factor, X, a, b, I, P, p, sPr, sPa, tri, gr.spw, partials)
   return gr.nwg;
 }
 

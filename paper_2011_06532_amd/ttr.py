@@ -40,7 +40,8 @@ SYMBOLS = [
     "ttr_set_profiling", "ttr_get_profile",
 ]
 
-PROF_CLASSES = ["gram", "apply", "add", "hadamard", "dot", "small"]
+PROF_CLASSES = ["k_gram_right_factor", "k_gram_left_factor", "k_gram", "k_apply_mfma", "k_apply", "k_add",
+                "k_hadamard", "k_dot_step", "small"]
 
 
 class _TTStruct(ctypes.Structure):
@@ -68,10 +69,10 @@ class RoundStats(ctypes.Structure):
 
 class Profile(ctypes.Structure):
     _fields_ = [
-        ("count", ctypes.c_int64 * 6),
-        ("ms", ctypes.c_double * 6),
-        ("bytes", ctypes.c_double * 6),
-        ("flops", ctypes.c_double * 6),
+        ("count", ctypes.c_int64 * 9),
+        ("ms", ctypes.c_double * 9),
+        ("bytes", ctypes.c_double * 9),
+        ("flops", ctypes.c_double * 9),
     ]
 
 
