@@ -35,7 +35,7 @@ def log(msg):
 
 def source_hash():
     h = hashlib.sha256()
-    for f in ("ttr_stream.hip", "ttr_small.hip", "ttr_api.hip", "ttr_internal.h"):
+    for f in ("ttr_stream.hip", "ttr_small.hip", "ttr_mfma.hip", "ttr_api.hip", "ttr_internal.h"):
         with open(os.path.join(ROOT, "paper_2011_06532_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

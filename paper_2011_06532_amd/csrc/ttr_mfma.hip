@@ -255,9 +255,15 @@ __global__ __launch_bounds__(kThreads) void k_apply_mfma(const double *__restric
                                                          long long sQr, long long sQc, long long spw,
                                                          double *__restrict__ Y) {
   constexpr int KA = NT * 4;  // k-steps over alpha (whole tiles)
+  // per-wave staging of one output slice (NT <= 3): the tile registers are
+  // written to LDS and each output column leaves as one contiguous run
+  constexpr bool kStage = (NT <= 3);
+  constexpr int LD = NT * 16 + 1;
   __shared__ double fragQ[NT * KS * 64];
   __shared__ double fragP[NT * KA * 64];
+  __shared__ double Ys[kStage ? kWaves * LD * NT * 16 : 1];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double *Yw = Ys + (kStage ? wave * LD * NT * 16 : 0);
   const int g = lane >> 4, j = lane & 15;
   const bool hasP = (P != nullptr);
   build_bfrag(fragQ, Q, b, q, sQr, sQc, NT, KS);
@@ -304,29 +310,65 @@ __global__ __launch_bounds__(kThreads) void k_apply_mfma(const double *__restric
             for (int cb = 0; cb < NT; ++cb) y[rb][cb] = mfma(pa, w[t][cb][r], y[rb][cb]);
           }
         }
+      if (kStage) {
 #pragma unroll
-      for (int rb = 0; rb < NT; ++rb)
+        for (int rb = 0; rb < NT; ++rb)
 #pragma unroll
-        for (int cb = 0; cb < NT; ++cb) {
-          const int c = cb * 16 + j;
+          for (int cb = 0; cb < NT; ++cb)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int rho = rb * 16 + g + 4 * r;
-            if (rho < p && c < q) Yi[rho + ocol * c] = y[rb][cb][r];
+            for (int r = 0; r < 4; ++r) Yw[(rb * 16 + g + 4 * r) + LD * (cb * 16 + j)] = y[rb][cb][r];
+      } else {
+#pragma unroll
+        for (int rb = 0; rb < NT; ++rb)
+#pragma unroll
+          for (int cb = 0; cb < NT; ++cb) {
+            const int c = cb * 16 + j;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int rho = rb * 16 + g + 4 * r;
+              if (rho < p && c < q) Yi[rho + ocol * c] = y[rb][cb][r];
+            }
           }
-        }
+      }
     } else {
+      if (kStage) {
 #pragma unroll
-      for (int t = 0; t < NT; ++t)
+        for (int t = 0; t < NT; ++t)
 #pragma unroll
-        for (int cb = 0; cb < NT; ++cb) {
-          const int c = cb * 16 + j;
+          for (int cb = 0; cb < NT; ++cb)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int alpha = t * 16 + g + 4 * r;
-            if (alpha < p && c < q) Yi[alpha + ocol * c] = w[t][cb][r];
+            for (int r = 0; r < 4; ++r) Yw[(t * 16 + g + 4 * r) + LD * (cb * 16 + j)] = w[t][cb][r];
+      } else {
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+          for (int cb = 0; cb < NT; ++cb) {
+            const int c = cb * 16 + j;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int alpha = t * 16 + g + 4 * r;
+              if (alpha < p && c < q) Yi[alpha + ocol * c] = w[t][cb][r];
+            }
           }
+      }
+    }
+    if (kStage) {
+      // the wave's LDS writes complete before its reads (same wave, in order)
+      __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+      int rho = lane, c = 0;
+      while (rho >= p) {
+        rho -= p;
+        ++c;
+      }
+      for (; c < q;) {
+        Yi[rho + ocol * c] = Yw[rho + LD * c];
+        rho += 64;
+        while (rho >= p) {
+          rho -= p;
+          ++c;
         }
+      }
+      __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     }
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks)
