@@ -148,17 +148,21 @@ int ttr_get_round_stats(const ttr_handle *h, ttr_round_stats *out);
  * count and algorithmic traffic/work are accumulated per kernel:
  *   0 k_gram_right_factor  Gram pass with a right factor (orthonormalization)
  *   1 k_gram_left_factor   Gram pass with a left factor (truncation)
- *   2 k_gram               staged generic Gram pass (refinement passes)
+ *   2 k_gram               staged generic Gram pass (longer factor chains)
  *   3 k_apply_mfma         output pass, matrix cores
  *   4 k_apply              staged generic output pass
  *   5 k_add  6 k_hadamard  7 k_dot_step  8 small one-workgroup kernels
+ *   9 k_gram_fac           refinement Gram pass on a materialized core
+ *  10 k_apply_fac2         output pass with two right factors (refined core)
+ *  11 k_gram_right_factor  as 0, FP32 matrix cores (TTR_MIXED first pass)
+ *  12 k_gram_left_factor   as 1, FP32 matrix cores (TTR_MIXED first pass)
  * Gram passes: bytes = the core read once, flops = the slice products plus the
  * symmetric Gram accumulation; output passes: bytes = core read + output
  * written, flops = the slice products; sum/Hadamard: bytes = inputs read +
  * output written.  Durations are resolved at the end of each synchronizing
  * call and by ttr_get_profile, which waits for the stream.
  * ttr_set_profiling(h, 1) also clears the accumulators. */
-#define TTR_NPROF 9
+#define TTR_NPROF 13
 typedef struct ttr_profile {
   int64_t count[TTR_NPROF];
   double ms[TTR_NPROF];

@@ -101,16 +101,18 @@ int ensure_ws(ttr_handle *h, size_t bytes) {
 constexpr size_t kSlot = (size_t)TTR_RMAX * TTR_RMAX;
 constexpr int kStagesPerCore = 3;
 struct WS {
-  double *partials, *G, *Ra, *Rb, *Gst[3], *Pa, *Pb, *GU, *Wa, *Wb, *scal, *sigma, *Tn, *Bst, *tmp;
+  double *partials, *G, *Ra, *Rb, *Gst[3], *Pa, *Pb, *GU, *Wa, *Wb, *scal, *sigma, *Tn, *Bst, *tmp, *matA, *matB;
   int *dec;
   double *T(int n) const { return Tn + (size_t)n * kSlot; }
   double *B(int n, int j) const { return Bst + ((size_t)n * kStagesPerCore + j) * kSlot; }
 };
-size_t ws_doubles(int N, size_t tmp) {
+// tmp: staging for an explicit output core; mat: each of the two buffers that
+// hold materialized cores of ill-conditioned factorizations
+size_t ws_doubles(int N, size_t tmp, size_t mat = 0) {
   return (size_t)TTR_MAXWG * kSlot + 12 * kSlot + 64 + (size_t)(N + 1) * TTR_RMAX +
-         (size_t)(N + 2) * (1 + kStagesPerCore) * kSlot + tmp + 64;
+         (size_t)(N + 2) * (1 + kStagesPerCore) * kSlot + tmp + 2 * mat + 64;
 }
-WS carve(ttr_handle *h, int N, size_t tmp) {
+WS carve(ttr_handle *h, int N, size_t tmp, size_t mat = 0) {
   WS w;
   double *p = h->ws;
   w.partials = p; p += (size_t)TTR_MAXWG * kSlot;
@@ -129,12 +131,17 @@ WS carve(ttr_handle *h, int N, size_t tmp) {
   w.Tn = p; p += (size_t)(N + 2) * kSlot;
   w.Bst = p; p += (size_t)(N + 2) * kStagesPerCore * kSlot;
   w.tmp = p; p += tmp;
+  w.matA = mat ? p : nullptr; p += mat;
+  w.matB = mat ? p : nullptr; p += mat;
   w.dec = h->dec_dev;
   return w;
 }
 
 // --- opt-in kernel timing ------------------------------------------------
-enum { P_GRAM_R = 0, P_GRAM_L = 1, P_GRAM_G = 2, P_APPLY = 3, P_APPLY_G = 4, P_ADD = 5, P_HAD = 6, P_DOT = 7, P_SMALL = 8 };
+enum {
+  P_GRAM_R = 0, P_GRAM_L = 1, P_GRAM_G = 2, P_APPLY = 3, P_APPLY_G = 4, P_ADD = 5, P_HAD = 6, P_DOT = 7, P_SMALL = 8,
+  P_GRAM_FAC = 9, P_APPLY_FAC2 = 10, P_GRAM_R32 = 11, P_GRAM_L32 = 12
+};
 
 hipEvent_t take_event(ttr_handle *h) {
   if (!h->evpool.empty()) {
@@ -217,13 +224,18 @@ Stage st_transpose(const Stage &a) {
 }
 
 // Streaming Gram of the chain Z(i) = lefts M(i) rights.  The one-factor forms
-// (the first pass of every factorization, the common case) run on the FP64
-// matrix cores; longer chains run on the staged generic kernel.
-void gram(ttr_handle *h, double *partials, double *G, const CoreView &cv, const Stages &st, int mode) {
+// (the first pass of every factorization, the common case) run on the matrix
+// cores, in FP32 when `f32` asks for it (*ran_f32 reports whether it did);
+// the one-right-factor RIGHT form of a materialized core (refinement passes)
+// runs on the FP64 matrix cores; longer chains run on the staged generic
+// kernel.
+void gram(ttr_handle *h, double *partials, double *G, const CoreView &cv, const Stages &st, int mode, int f32 = 0,
+          bool *ran_f32 = nullptr) {
   int zr, zc;
   const double cf = chain_flops(cv, st, &zr, &zc);
   const double gf = (mode == GRAM_LEFT) ? (double)zr * (zr + 1) * zc : (double)zc * (zc + 1) * zr;
   const int gd = (mode == GRAM_LEFT) ? zr : zc;
+  const double bytes = 8.0 * cv.pa * cv.pb * (double)cv.I, flops = (cf + gf) * (double)cv.I;
   // physical form: trans views transpose the chain and swap the Gram side
   const bool tr = cv.trans != 0;
   const int pmode = tr ? (mode == GRAM_LEFT ? GRAM_RIGHT : GRAM_LEFT) : mode;
@@ -232,36 +244,56 @@ void gram(ttr_handle *h, double *partials, double *G, const CoreView &cv, const 
   const double *X = cv.X;
   int nwg = 0;
   bool done = false;
+  if (ran_f32) *ran_f32 = false;
   if (g_use_mfma) {
     if (pmode == GRAM_LEFT && pnl == 0 && pnr <= 1) {
       // sum (X Q)(X Q)^T
       const Stage *q = pnr ? (tr ? &st.L[0] : &st.R[0]) : nullptr;
       Stage qq;
       if (q) qq = tr ? st_transpose(*q) : *q;
-      ProfScope ps(h, P_GRAM_R, 8.0 * cv.pa * cv.pb * (double)cv.I, (cf + gf) * (double)cv.I);
+      ProfScope ps(h, f32 ? P_GRAM_R32 : P_GRAM_R, bytes, flops);
       nwg = launch_gram_right_factor(h->stream, X, cv.pa, cv.pb, cv.I, q ? qq.S : nullptr, q ? qq.cols : cv.pb,
-                                     q ? qq.sr : 1, q ? qq.sc : cv.pb, (q && qq.lower == 1) ? 1 : 0, partials);
+                                     q ? qq.sr : 1, q ? qq.sc : cv.pb, (q && qq.lower == 1) ? 1 : 0, f32, partials);
       done = true;
+      if (ran_f32) *ran_f32 = f32 != 0;
     } else if (pmode == GRAM_RIGHT && pnl <= 1 && pnr == 0) {
       // sum (P X)^T (P X)
       const Stage *pp = pnl ? (tr ? &st.R[0] : &st.L[0]) : nullptr;
       Stage ps_;
       if (pp) ps_ = tr ? st_transpose(*pp) : *pp;
-      ProfScope ps(h, P_GRAM_L, 8.0 * cv.pa * cv.pb * (double)cv.I, (cf + gf) * (double)cv.I);
+      ProfScope ps(h, f32 ? P_GRAM_L32 : P_GRAM_L, bytes, flops);
       nwg = launch_gram_left_factor(h->stream, X, cv.pa, cv.pb, cv.I, pp ? ps_.S : nullptr, pp ? ps_.rows : cv.pa,
-                                    pp ? ps_.sr : 1, pp ? ps_.sc : cv.pa, (pp && ps_.lower == 2) ? 1 : 0, partials);
+                                    pp ? ps_.sr : 1, pp ? ps_.sc : cv.pa, (pp && ps_.lower == 2) ? 1 : 0, f32,
+                                    partials);
+      done = true;
+      if (ran_f32) *ran_f32 = f32 != 0;
+    } else if (mode == GRAM_RIGHT && st.nl == 0 && st.nr == 1) {
+      // logical sum (M Q)^T (M Q), M the (possibly transposed) slice
+      const Stage &q = st.R[0];
+      ProfScope ps(h, P_GRAM_FAC, bytes, flops);
+      nwg = launch_gram_fac(h->stream, X, cv.pa, cv.pb, cv.I, cv.trans, q.S, q.cols, q.sr, q.sc, q.lower == 1 ? 1 : 0,
+                            partials);
+      done = true;
+    } else if (mode == GRAM_LEFT && st.nl == 1 && st.nr == 0) {
+      // logical sum (L M)(L M)^T = sum (M^T L^T)^T (M^T L^T): the same kernel on
+      // the transposed slice with Q = L^T
+      const Stage &l = st.L[0];
+      ProfScope ps(h, P_GRAM_FAC, bytes, flops);
+      nwg = launch_gram_fac(h->stream, X, cv.pa, cv.pb, cv.I, !cv.trans, l.S, l.rows, l.sc, l.sr, l.lower == 2 ? 1 : 0,
+                            partials);
       done = true;
     }
   }
   if (!done) {
-    ProfScope ps(h, P_GRAM_G, 8.0 * cv.pa * cv.pb * (double)cv.I, (cf + gf) * (double)cv.I);
+    ProfScope ps(h, P_GRAM_G, bytes, flops);
     nwg = launch_gram(h->stream, cv, st, mode, partials, G, 0);
   }
   launch_reduce(h->stream, partials, nwg, gd * gd, G);
 }
 
 // Output pass Y(i) = lefts M(i) rights, on the matrix cores when the chain has
-// at most one factor on each side.
+// at most one factor on each side, or is two right factors on a materialized
+// core.
 void apply(ttr_handle *h, const CoreView &cv, const Stages &st, double *Y, int trans_out) {
   int zr, zc;
   const double cf = chain_flops(cv, st, &zr, &zc);
@@ -280,6 +312,22 @@ void apply(ttr_handle *h, const CoreView &cv, const Stages &st, double *Y, int t
     launch_apply_mfma(h->stream, cv.X, cv.pa, cv.pb, cv.I, pl ? P.S : nullptr, pl ? P.rows : cv.pa, pl ? P.sr : 1,
                       pl ? P.sc : cv.pa, pr ? Q.S : nullptr, pr ? Q.cols : cv.pb, pr ? Q.sr : 1,
                       pr ? Q.sc : cv.pb, Y);
+    return;
+  }
+  if (g_use_mfma && st.nl == 0 && st.nr == 2 && trans_out == cv.trans) {
+    ProfScope ps(h, P_APPLY_FAC2, abytes, cf * (double)cv.I);
+    const Stage &q1 = st.R[0], &q2 = st.R[1];
+    launch_apply_fac2(h->stream, cv.X, cv.pa, cv.pb, cv.I, cv.trans, q1.S, q1.cols, q1.sr, q1.sc,
+                      q1.lower == 1 ? 1 : 0, q2.S, q2.cols, q2.sr, q2.sc, Y);
+    return;
+  }
+  if (g_use_mfma && st.nl == 2 && st.nr == 0 && trans_out == cv.trans) {
+    // L2 L1 M = (M^T L1^T L2^T)^T: the transposed slice with Q1 = L1^T, Q2 = L2^T,
+    // written transposed back
+    ProfScope ps(h, P_APPLY_FAC2, abytes, cf * (double)cv.I);
+    const Stage &l1 = st.L[0], &l2 = st.L[1];
+    launch_apply_fac2(h->stream, cv.X, cv.pa, cv.pb, cv.I, !cv.trans, l1.S, l1.rows, l1.sc, l1.sr,
+                      l1.lower == 2 ? 1 : 0, l2.S, l2.rows, l2.sc, l2.sr, Y);
     return;
   }
   ProfScope ps(h, P_APPLY_G, abytes, cf * (double)cv.I);
@@ -356,6 +404,7 @@ struct Factor {
   int nst = 0;
   int dim[4] = {0, 0, 0, 0};
   int tri = 0;  // one-pass Cholesky route: T = L lower triangular, F = L^{-T}
+  int mat = 0;  // stages apply to the materialized core M(i) T_{n+1}, not to M(i)
 };
 
 // One QR-by-Gram factorization of a tall-skinny unfolding of a logical core,
@@ -378,16 +427,46 @@ struct TruncCtx {
   int notrunc = 0;  // out: proved at the accepted one-pass step
 };
 
+// Precision plan of one factorization.
+//   FP64 (TTR_FP64): every Gram pass in FP64; a pass settles when the Gram's
+//     condition number is at most 1/kTau1 (orthonormality to ~1e-13).
+//   Mixed (TTR_MIXED): the first pass forms the Gram on the FP32 matrix cores
+//     (FP32 products and accumulation); refinement passes are FP64.  A pass
+//     settles when u * kappa(G) <= kTauMix for the unit roundoff u of the
+//     arithmetic that formed G, i.e. the factor is orthonormal to ~kTauMix.
+//     The tensor itself is not affected by this choice: every factor R is the
+//     exact inverse of the basis change applied to the core, in FP64.
+struct Prec {
+  int mixed = 0;
+};
+const double kU64 = 1.1102230246251565e-16;  // 2^-53
+const double kU32 = 5.9604644775390625e-08;  // 2^-24
+const double kTauMix = 1e-5;
+
+// Bound on the rounding error of a streamed Gram, relative to its trace:
+// sequential accumulations per entry (slices per wave times the contracted
+// length), the fixed-order cross-wave/workgroup sums and the products.
+double gram_err(const CoreView &cv, int contracted, double u) {
+  const long long nwg = std::min<long long>(TTR_MAXWG, std::max<long long>(1, (cv.I + 63) / 64));
+  const long long spw = (cv.I + nwg - 1) / nwg;
+  const double nacc = (double)((spw + 3) / 4) * contracted + 4.0 + (double)nwg + 2.0;
+  return 2.0 * nacc * u;
+}
+
 template <class SlotFn>
 int qr_by_gram(ttr_handle *h, WS &w, const CoreView &cv, int mode, const Stages &base, int b, SlotFn slot,
                double *Tdst, Factor *f, double **Rout, int *kout, int *passes, double tcond = -1.0,
-               double *ratio = nullptr, TruncCtx *tc = nullptr) {
+               double *ratio = nullptr, TruncCtx *tc = nullptr, Prec pr = Prec(), double *mat = nullptr,
+               CoreView *cv_out = nullptr, int *materialized = nullptr) {
   double *R[2] = {w.Ra, w.Rb};
   const double *Rc = nullptr;
   int d = b;
   f->nst = 0;
   f->dim[0] = b;
   Stages st = base;
+  CoreView cvp = cv;  // the core the current stages apply to
+  if (cv_out) *cv_out = cv;
+  if (materialized) *materialized = 0;
   for (int pass = 1; pass <= 3; ++pass) {
     QrStepArgs qa;
     qa.Tpost = nullptr;
@@ -396,20 +475,25 @@ int qr_by_gram(ttr_handle *h, WS &w, const CoreView &cv, int mode, const Stages 
     qa.cond_scale = 1.0;
     qa.ratio_out = (pass == 1) ? h->decf_dev : nullptr;
     const bool post = (pass == 1 && mode == GRAM_RIGHT && tcond > 0.0 && base.nr == 1 && base.nl <= 1 && g_use_mfma);
+    bool f32 = false;
+    int zr, zc;
     if (post) {
       Stages s1 = base;
       s1.nr = 0;
-      gram(h, w.partials, w.G, cv, s1, mode);
+      gram(h, w.partials, w.G, cvp, s1, mode, pr.mixed, &f32);
       qa.Tpost = base.R[0].S;
       qa.tpr = base.R[0].rows;
       qa.tpc = base.R[0].cols;
       qa.tsr = base.R[0].sr;
       qa.tsc = base.R[0].sc;
       qa.cond_scale = tcond;
+      chain_flops(cvp, s1, &zr, &zc);
     } else {
-      gram(h, w.partials, w.G, cv, st, mode);
+      gram(h, w.partials, w.G, cvp, st, mode, (pass == 1) ? pr.mixed : 0, &f32);
+      chain_flops(cvp, st, &zr, &zc);
     }
     ++*passes;
+    const double u = f32 ? kU32 : kU64;
     qa.G = w.G;
     qa.d = d;
     qa.pass = pass;
@@ -419,8 +503,10 @@ int qr_by_gram(ttr_handle *h, WS &w, const CoreView &cv, int mode, const Stages 
     qa.Rnext = R[(pass - 1) & 1];
     qa.Tdst = Tdst;
     qa.dec = w.dec;
-    qa.tau1 = kTau1;
+    qa.tau1 = pr.mixed ? u / kTauMix : kTau1;
     qa.tau2 = kTau2;
+    qa.ugram = u;
+    qa.gerr = gram_err(cvp, mode == GRAM_LEFT ? zc : zr, u);
     qa.try_chol = 1;
     qa.notrunc_check = (tc && tc->check) ? 1 : 0;
     qa.delta_dev = tc ? tc->delta_dev : nullptr;
@@ -440,6 +526,24 @@ int qr_by_gram(ttr_handle *h, WS &w, const CoreView &cv, int mode, const Stages 
     f->tri = (pass == 1 && done) ? h->dec_host[4] : 0;
     f->nst = pass;
     f->dim[pass] = k;
+    const bool can_mat = (mode == GRAM_RIGHT) ? (base.nl <= 1 && base.nr <= 1) : (base.nl == 0 && base.nr <= 1);
+    if (!done && pass == 1 && mat && base.nl + base.nr > 0 && can_mat && g_use_mfma) {
+      // The first pass did not settle: materialize the base chain once, so
+      // that the refinement Gram passes and the output pass read one core
+      // and apply the refinement stages to bitwise the same data.
+      Stages sb = base;
+      apply(h, cv, sb, mat, cv.trans);
+      int mr, mc;
+      chain_flops(cv, base, &mr, &mc);
+      cvp.X = mat;
+      cvp.I = cv.I;
+      cvp.trans = cv.trans;
+      cvp.pa = cv.trans ? mc : mr;
+      cvp.pb = cv.trans ? mr : mc;
+      st = no_stages();
+      if (cv_out) *cv_out = cvp;
+      if (materialized) *materialized = 1;
+    }
     if (mode == GRAM_LEFT) st.L[st.nl++] = st_trans(qa.Fstep, k, d);
     else st.R[st.nr++] = st_plain(qa.Fstep, d, k);
     Rc = qa.Rnext;
@@ -458,7 +562,7 @@ int qr_by_gram(ttr_handle *h, WS &w, const CoreView &cv, int mode, const Stages 
 // kept in the workspace, k[n] is the rank at logical link n.  When `Out` is
 // given, each orthonormal core B_n^T M_n(i) T_{n+1} is written to it (Alg. 5).
 int orth_sweep(ttr_handle *h, WS &w, const Seq &S, std::vector<int> &k, std::vector<Factor> &fac, ttr_tt *Out,
-               int *passes, std::vector<double> *kappa2 = nullptr) {
+               int *passes, std::vector<double> *kappa2 = nullptr, Prec pr = Prec()) {
   const int N = S.N();
   k.assign(N + 1, 1);
   fac.assign(N + 1, Factor());
@@ -473,15 +577,19 @@ int orth_sweep(ttr_handle *h, WS &w, const Seq &S, std::vector<int> &k, std::vec
     int kn;
     auto slot = [&](int j) { return w.B(n, j); };
     double ratio = -1.0;
-    int rc = qr_by_gram(h, w, cv, GRAM_LEFT, base, b, slot, w.T(n), &fac[n], &Rout, &kn, passes, -1.0, &ratio);
+    CoreView cvm;
+    int materialized = 0;
+    int rc = qr_by_gram(h, w, cv, GRAM_LEFT, base, b, slot, w.T(n), &fac[n], &Rout, &kn, passes, -1.0, &ratio,
+                        nullptr, pr, w.matA, &cvm, &materialized);
     if (rc) return rc;
+    fac[n].mat = materialized;
     k[n] = kn;
     if (kappa2 && fac[n].nst == 1) (*kappa2)[n] = ratio;
     if (Out) {
       Stages st = no_stages();
       for (int j = 0; j < fac[n].nst; ++j) st.L[st.nl++] = st_trans(w.B(n, j), fac[n].dim[j + 1], fac[n].dim[j]);
-      if (n < N - 1) st.R[st.nr++] = st_plain(w.T(n + 1), cv.eb(), k[n + 1]);
-      apply(h, cv, st, w.tmp, S.rev);
+      if (n < N - 1 && !materialized) st.R[st.nr++] = st_plain(w.T(n + 1), cv.eb(), k[n + 1]);
+      apply(h, materialized ? cvm : cv, st, w.tmp, S.rev);
       const int pn = S.phys(n);
       const size_t cnt = (size_t)kn * cv.I * k[n + 1];
       HIPCHK(hipMemcpyAsync(Out->core[pn], w.tmp, cnt * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
@@ -663,8 +771,9 @@ int ttr_norm(ttr_handle *h, const ttr_tt *X, int method, double *out) {
   if (method != TTR_NORM_ORTHO) return fail(TTR_ERR_INVALID_ARG, "unknown norm method");
   if ((rc = check_tt(X, "X", TTR_MAX_RANK))) return rc;
   const int N = X->N;
-  if ((rc = ensure_ws(h, ws_doubles(N, 0) * sizeof(double)))) return rc;
-  WS w = carve(h, N, 0);
+  const size_t mat = max_core(X);
+  if ((rc = ensure_ws(h, ws_doubles(N, 0, mat) * sizeof(double)))) return rc;
+  WS w = carve(h, N, 0, mat);
   if ((rc = reset_dec(h))) return rc;
   Seq S{X, 0};
   std::vector<int> k;
@@ -694,8 +803,8 @@ int ttr_orthogonalize(ttr_handle *h, ttr_tt *X, int side, int prec) {
   const int N = X->N;
   if (N == 1) return TTR_OK;
   const size_t tmp = max_core(X);
-  if ((rc = ensure_ws(h, ws_doubles(N, tmp) * sizeof(double)))) return rc;
-  WS w = carve(h, N, tmp);
+  if ((rc = ensure_ws(h, ws_doubles(N, tmp, tmp) * sizeof(double)))) return rc;
+  WS w = carve(h, N, tmp, tmp);
   if ((rc = reset_dec(h))) return rc;
   Seq S{X, side == TTR_LEFT};
   std::vector<int> k;
@@ -742,16 +851,20 @@ int ttr_round(ttr_handle *h, const ttr_tt *X, double tol, int direction, int pre
     if (norm_out) *norm_out = NAN;
     return TTR_OK;
   }
-  if ((rc = ensure_ws(h, ws_doubles(N, 0) * sizeof(double)))) return rc;
-  WS w = carve(h, N, 0);
+  // scratch for one materialized core of the truncation sweep (L_{n-1} x I_n x R_n <= R_{n-1} I_n R_n)
+  const size_t mat = max_core(X);
+  if ((rc = ensure_ws(h, ws_doubles(N, 0, mat) * sizeof(double)))) return rc;
+  WS w = carve(h, N, 0, mat);
   if ((rc = reset_dec(h))) return rc;
   const Seq S{X, direction == TTR_LRL};
+  Prec pr;
+  pr.mixed = (prec == TTR_MIXED);
   std::vector<int> k;
   std::vector<Factor> fac;
   std::vector<double> kappa2;
   int passes = 0;
   // Sweep 1: orthonormalization with implicit factors (Alg. 6, first loop).
-  if ((rc = orth_sweep(h, w, S, k, fac, nullptr, &passes, &kappa2))) return rc;
+  if ((rc = orth_sweep(h, w, S, k, fac, nullptr, &passes, &kappa2, pr))) return rc;
   // Sweep 2: truncation (Alg. 2 loop / Alg. 6 second loop).  The current core
   // n is C'_n(i) = [P_n B_n^T] M_n(i) T_{n+1}; its left stages are the
   // orthonormalization stages of core n with the last one merged into P_n.
@@ -761,7 +874,7 @@ int ttr_round(ttr_handle *h, const ttr_tt *X, double tol, int direction, int pre
   int Lprev = 1;
   int applies = 0;
   for (int n = 0; n < N - 1; ++n) {
-    const CoreView cv = S.view(n);
+    CoreView cv = S.view(n);
     const int tr = cv.eb();  // rows of T_{n+1}
     const int b = k[n + 1];  // columns of A = V(C'_n)
     Stages base = no_stages();
@@ -771,17 +884,43 @@ int ttr_round(ttr_handle *h, const ttr_tt *X, double tol, int direction, int pre
       base.L[base.nl++] = st_plain(Pcur, Lprev, f.dim[f.nst - 1]);
     }
     base.R[base.nr++] = st_plain(w.T(n + 1), tr, b);
+    // T folded into the chain already: the core was materialized in sweep 1
+    bool tfold = false;
+    if (fac[n].mat) {
+      // sweep 1 refined this core on C_n = M_n T_{n+1}: rebuild C_n bitwise as
+      // it was (same kernel, same inputs), then C'_n = lefts C_n, so that this
+      // sweep applies the refinement stages to the data they were measured on
+      Stages s1 = no_stages();
+      s1.R[s1.nr++] = base.R[0];
+      apply(h, cv, s1, w.matA, cv.trans);
+      CoreView cva = cv;
+      cva.X = w.matA;
+      if (cv.trans) cva.pa = b; else cva.pb = b;
+      Stages s2 = no_stages();
+      for (int j = 0; j < base.nl; ++j) s2.L[s2.nl++] = base.L[j];
+      apply(h, cva, s2, w.matB, cv.trans);
+      int zr, zc;
+      chain_flops(cva, s2, &zr, &zc);
+      cv.X = w.matB;
+      cv.pa = cv.trans ? zc : zr;
+      cv.pb = cv.trans ? zr : zc;
+      base = no_stages();
+      tfold = true;
+    }
     double *Rq;
     int kq;
     Factor g;
     auto slot = [&](int j) { return w.Gst[j]; };
-    const double tcond = (fac[n + 1].nst == 1) ? kappa2[n + 1] : -1.0;
+    const double tcond = (fac[n + 1].nst == 1 && !tfold) ? kappa2[n + 1] : -1.0;
     TruncCtx tcx;
     tcx.check = 1;
     tcx.delta_dev = w.scal + 1;
     tcx.first = (n == 0);
     tcx.tol2_nm1 = tol * tol / (double)(N - 1);
-    rc = qr_by_gram(h, w, cv, GRAM_RIGHT, base, b, slot, nullptr, &g, &Rq, &kq, &passes, tcond, nullptr, &tcx);
+    CoreView cvm;
+    int materialized = 0;
+    rc = qr_by_gram(h, w, cv, GRAM_RIGHT, base, b, slot, nullptr, &g, &Rq, &kq, &passes, tcond, nullptr, &tcx, pr,
+                    tfold ? nullptr : w.matA, &cvm, &materialized);
     if (rc) return rc;
     const Factor &fn = fac[n + 1];
     TruncArgs ta;
@@ -813,8 +952,10 @@ int ttr_round(ttr_handle *h, const ttr_tt *X, double tol, int direction, int pre
     L[n + 1] = Ln;
     // output core n: the same staged chain as the Gram passes, the last
     // refinement stage merged with U_R[:, :L]
-    Stages st = base;
-    if (g.nst == 1) {
+    Stages st = materialized ? no_stages() : base;
+    if (g.nst == 1 && tfold) {
+      st.R[st.nr++] = st_plain(w.GU, ta.d, Ln);
+    } else if (g.nst == 1) {
       // one-pass factorization: T and U-hat merge into one right factor
       launch_small_gemm(h->stream, w.T(n + 1), w.GU, w.Gst[1], tr, b, Ln);
       st.nr = 0;
@@ -823,7 +964,7 @@ int ttr_round(ttr_handle *h, const ttr_tt *X, double tol, int direction, int pre
       for (int j = 0; j + 1 < g.nst; ++j) st.R[st.nr++] = st_plain(w.Gst[j], g.dim[j], g.dim[j + 1]);
       st.R[st.nr++] = st_plain(w.GU, ta.d, Ln);
     }
-    apply(h, cv, st, Y->core[S.phys(n)], S.rev);
+    apply(h, materialized ? cvm : cv, st, Y->core[S.phys(n)], S.rev);
     ++applies;
     Pcur = ta.Pnext;
     Lprev = Ln;

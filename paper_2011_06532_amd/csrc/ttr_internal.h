@@ -60,15 +60,25 @@ int launch_gram(hipStream_t s, const CoreView &cv, const Stages &st, int mode, d
 void launch_reduce(hipStream_t s, const double *partials, int nwg, int ne, double *G);
 void launch_apply(hipStream_t s, const CoreView &cv, const Stages &st, double *Y, int trans_out);
 // W (ry1 x rx1) = sum_i Y(i)^T Wp X(i), Wp is ry0 x rx0 col-major.
-// FP64 MFMA paths (ttr_mfma.hip) on physical cores (a x I x b), dims <= 64.
+// Matrix-core paths (ttr_mfma.hip) on physical cores (a x I x b), dims <= 64.
 // tri: the factor is triangular (Q lower / P upper), zero fragments are skipped.
+// f32: the mixed-precision first pass (FP32 products and accumulation).
 int launch_gram_right_factor(hipStream_t s, const double *X, int a, int b, long long I, const double *Q, int q,
-                             long long sQr, long long sQc, int tri, double *partials);
+                             long long sQr, long long sQc, int tri, int f32, double *partials);
 int launch_gram_left_factor(hipStream_t s, const double *X, int a, int b, long long I, const double *P, int p,
-                            long long sPr, long long sPa, int tri, double *partials);
+                            long long sPr, long long sPa, int tri, int f32, double *partials);
 void launch_apply_mfma(hipStream_t s, const double *X, int a, int b, long long I, const double *P, int p,
                        long long sPr, long long sPa, const double *Q, int q, long long sQr, long long sQc,
                        double *Y);
+// On the slice S_i = M_i (trans = 0) or M_i^T (trans = 1), sa x sb:
+//   launch_gram_fac:   partial Grams of sum_i (S_i Q)^T (S_i Q), Q sb x q
+//   launch_apply_fac2: Y_i = S_i Q1 Q2 written as sa x I x q2 (trans = 0) or
+//                      q2 x I x sa (trans = 1); tri: Q1 lower triangular
+int launch_gram_fac(hipStream_t s, const double *X, int a, int b, long long I, int trans, const double *Q, int q,
+                    long long sQr, long long sQc, int tri, double *partials);
+void launch_apply_fac2(hipStream_t s, const double *X, int a, int b, long long I, int trans, const double *Q1,
+                       int q1, long long s1r, long long s1c, int tri, const double *Q2, int q2, long long s2r,
+                       long long s2c, double *Y);
 void launch_dot_step(hipStream_t s, const double *X, int rx0, int rx1, const double *Y, int ry0, int ry1,
                      long long I, const double *Wp, double *partials, double *W);
 
@@ -95,7 +105,12 @@ struct QrStepArgs {
   double *Rnext;       // k x b (ld k)
   double *Tdst;        // when done: Rnext^T (b x k, ld b); may be nullptr
   int *dec;            // [0] k, [1] done, [2] error flags, [4] triangular factors, [5] no truncation proven
+  // tau1: one pass is enough (and a refinement pass settles) when the Gram's
+  // condition number, scaled by cond_scale, is at most 1/tau1; tau2: rank
+  // revealing cut of the refinement passes
   double tau1, tau2;
+  double ugram;        // unit roundoff of the arithmetic that formed G (FP64 or FP32)
+  double gerr;         // |G_computed - G| <= gerr * trace(G), for the no-truncation proof
   int try_chol;        // pass 1: try the Cholesky route first
   // truncation sweep only: with the Cholesky route, also prove that no
   // singular value can be dropped at this link (lambda_min(G) >= 1/||L^{-1}||_F^2

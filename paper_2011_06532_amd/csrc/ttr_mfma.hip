@@ -22,19 +22,39 @@
 #include "ttr_internal.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;
 constexpr int kWaves = 4;
 
-__device__ inline d4 mfma(double a, double b, d4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+// Arithmetic of a matrix-core chain.  Both 16x16x4 forms take operands the
+// same way (lane l supplies A[l%16][k0 + l/16] and B[k0 + l/16][l%16]); they
+// differ in where the result lands: register r of lane l holds row
+// row(l/16, r) of column l%16.
+struct F64 {
+  using T = double;
+  using V = d4;
+  __device__ static V mma(double a, double b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  __host__ __device__ static constexpr int row(int g, int r) { return 4 * r + g; }
+};
+struct F32 {
+  using T = float;
+  using V = f4;
+  __device__ static V mma(float a, float b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __host__ __device__ static constexpr int row(int g, int r) { return 4 * g + r; }
+};
+
+__device__ inline d4 mfma(double a, double b, d4 c) { return F64::mma(a, b, c); }
 
 // A-operand fragments of S (rows x cols): frag[(t*KS + ks)*64 + l] = S(t*16 + l%16, ks*4 + l/16).
 // S(r, c) = S[r*sr + c*sc]; S == nullptr means the identity.  Zero outside.
-__device__ void build_afrag(double *frag, const double *S, int rows, int cols, long long sr, long long sc, int nt,
+template <class T = double>
+__device__ void build_afrag(T *frag, const double *S, int rows, int cols, long long sr, long long sc, int nt,
                             int KS) {
   const int total = nt * KS * 64;
   for (int e = threadIdx.x; e < total; e += blockDim.x) {
@@ -45,12 +65,13 @@ __device__ void build_afrag(double *frag, const double *S, int rows, int cols, l
     const int c = ks * 4 + (l >> 4);
     double v = 0.0;
     if (r < rows && c < cols) v = S ? S[r * sr + c * sc] : (r == c ? 1.0 : 0.0);
-    frag[e] = v;
+    frag[e] = (T)v;
   }
 }
 
 // B-operand fragments of S (rows x cols): frag[(t*KS + ks)*64 + l] = S(ks*4 + l/16, t*16 + l%16).
-__device__ void build_bfrag(double *frag, const double *S, int rows, int cols, long long sr, long long sc, int nt,
+template <class T = double>
+__device__ void build_bfrag(T *frag, const double *S, int rows, int cols, long long sr, long long sc, int nt,
                             int KS) {
   const int total = nt * KS * 64;
   for (int e = threadIdx.x; e < total; e += blockDim.x) {
@@ -61,14 +82,15 @@ __device__ void build_bfrag(double *frag, const double *S, int rows, int cols, l
     const int c = t * 16 + (l & 15);
     double v = 0.0;
     if (r < rows && c < cols) v = S ? S[r * sr + c * sc] : (r == c ? 1.0 : 0.0);
-    frag[e] = v;
+    frag[e] = (T)v;
   }
 }
 
 // Adds this wave's Gram tiles (lower block triangle, tile (u, v) with u >= v)
-// into the workgroup's dense gd x gd matrix in LDS, waves in a fixed order.
-template <int NT>
-__device__ void reduce_gram(const d4 (&G)[NT][NT], int nt, int gd, double *Gs, double *out) {
+// into the workgroup's dense gd x gd matrix in LDS (FP64), waves in a fixed
+// order.
+template <int NT, class A>
+__device__ void reduce_gram(const typename A::V (&G)[NT][NT], int nt, int gd, double *Gs, double *out) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, j = lane & 15;
   for (int e = threadIdx.x; e < gd * gd; e += blockDim.x) Gs[e] = 0.0;
@@ -82,9 +104,9 @@ __device__ void reduce_gram(const d4 (&G)[NT][NT], int nt, int gd, double *Gs, d
           if (v <= u && u < nt) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-              const int row = u * 16 + g + 4 * r;
+              const int row = u * 16 + A::row(g, r);
               const int col = v * 16 + j;
-              if (row < gd && col < gd && row >= col) Gs[row + gd * col] += G[u][v][r];
+              if (row < gd && col < gd && row >= col) Gs[row + gd * col] += (double)G[u][v][r];
             }
           }
     }
@@ -98,10 +120,11 @@ __device__ void reduce_gram(const d4 (&G)[NT][NT], int nt, int gd, double *Gs, d
 
 // Loads the operand fragments of one slice: buf[ks][t] = M(t*16 + l%16, ks*4 + l/16)
 // (ROWS16 = true) or M(ks*4 + l/16, t*16 + l%16) (ROWS16 = false), zero outside
-// the a x b slice.  M(alpha, beta) = Xi[alpha + col*beta].
-template <int NT, int KS, bool ROWS16>
+// the a x b slice.  M(alpha, beta) = Xi[alpha + col*beta].  Data are FP64 in
+// memory; T = float rounds them on load.
+template <int NT, int KS, bool ROWS16, class T = double>
 __device__ inline void load_slice(const double *__restrict__ Xi, long long col, int a, int b, int g, int j,
-                                  double (&buf)[KS][NT]) {
+                                  T (&buf)[KS][NT]) {
 #pragma unroll
   for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
@@ -110,7 +133,7 @@ __device__ inline void load_slice(const double *__restrict__ Xi, long long col, 
       const int c = ROWS16 ? ks * 4 + g : t * 16 + j;   // beta
       double v = 0.0;
       if (r < a && c < b) v = Xi[r + col * c];
-      buf[ks][t] = v;
+      buf[ks][t] = (T)v;
     }
 }
 
@@ -118,66 +141,81 @@ __device__ inline void load_slice(const double *__restrict__ Xi, long long col, 
 // Gram with a right factor: G (a x a) = sum_i (M_i Q)(M_i Q)^T, M_i = X(:, i, :)
 // (a x b), Q (b x q).  The left Gram of the horizontal unfolding of X x_3 Q^T
 // (orthonormalization sweep, §2.3 / Alg. 1).  NT = 16-tiles per dimension,
-// KS = k-steps over b (ceil(b/4)).
+// KS = k-steps over b (ceil(b/4)).  A = F64, or F32 for the mixed-precision
+// first pass (slices and Q rounded to FP32, FP32 accumulation per wave).
 // ---------------------------------------------------------------------------
-template <int NT, int KS>
+template <int NT, int KS, class A>
 __global__ __launch_bounds__(kThreads) void k_gram_right_factor(const double *__restrict__ X, int a, int b, long long I,
                                                                 const double *__restrict__ Q, int q, long long sQr,
                                                                 long long sQc, int tri, long long spw,
                                                                 double *__restrict__ partials) {
-  __shared__ double frag[NT * KS * 64];
+  using T = typename A::T;
+  using V = typename A::V;
+  __shared__ T frag[NT * KS * 64];
   __shared__ double Gs[NT * 16 * NT * 16];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, j = lane & 15;
   // A operand: Q^T (q x b), Q^T(c, beta) = Q(beta, c)
-  build_afrag(frag, Q, q, b, sQc, sQr, NT, KS);
+  build_afrag<T>(frag, Q, q, b, sQc, sQr, NT, KS);
   __syncthreads();
-  d4 G[NT][NT];
+  V G[NT][NT];
 #pragma unroll
   for (int u = 0; u < NT; ++u)
 #pragma unroll
-    for (int v = 0; v < NT; ++v) G[u][v] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int v = 0; v < NT; ++v) G[u][v] = V{0, 0, 0, 0};
   const long long beg = (long long)blockIdx.x * spw;
   const long long end = std::min(beg + spw, I);
   const long long col = (long long)a * I;
-  double cur[KS][NT], nxt[KS][NT];
+  // register prefetch of the next slice, except where it would spill (FP64,
+  // NT = 4).  The prefetch holds the raw FP64 loads; FP32 rounding happens when
+  // the slice becomes current, so the loads stay in flight across the products.
+  constexpr bool PF = (NT <= 3) || sizeof(T) == 4;
+  T cur[KS][NT];
+  double nxt[KS][NT];  // used only with PF
   long long i = beg + wave;
-  if (i < end) load_slice<NT, KS, true>(X + (long long)a * i, col, a, b, g, j, cur);
+  if constexpr (PF)
+    if (i < end) load_slice<NT, KS, true, T>(X + (long long)a * i, col, a, b, g, j, cur);
   for (; i < end; i += kWaves) {
-    if (i + kWaves < end) load_slice<NT, KS, true>(X + (long long)a * (i + kWaves), col, a, b, g, j, nxt);
-    d4 wt[NT][NT];  // [c-tile][alpha-tile]
+    if constexpr (PF) {
+      if (i + kWaves < end) load_slice<NT, KS, true>(X + (long long)a * (i + kWaves), col, a, b, g, j, nxt);
+    } else {
+      load_slice<NT, KS, true, T>(X + (long long)a * i, col, a, b, g, j, cur);
+    }
+    V wt[NT][NT];  // [c-tile][alpha-tile]
 #pragma unroll
     for (int u = 0; u < NT; ++u)
 #pragma unroll
-      for (int v = 0; v < NT; ++v) wt[u][v] = d4{0.0, 0.0, 0.0, 0.0};
+      for (int v = 0; v < NT; ++v) wt[u][v] = V{0, 0, 0, 0};
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
       for (int cb = 0; cb < NT; ++cb) {
         // lower-triangular Q: Q^T(c, beta) = 0 for beta < c, so k-steps below 4 cb vanish
         if (tri && ks < 4 * cb) continue;
-        const double qa = frag[(cb * KS + ks) * 64 + lane];
+        const T qa = frag[(cb * KS + ks) * 64 + lane];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) wt[cb][t] = mfma(qa, cur[ks][t], wt[cb][t]);
+        for (int t = 0; t < NT; ++t) wt[cb][t] = A::mma(qa, cur[ks][t], wt[cb][t]);
       }
-    // G(alpha, alpha') += sum_c Wt(c, alpha) Wt(c, alpha'); consecutive MFMAs
-    // go to different G tiles; k-steps past q are zero padding
+    // G(alpha, alpha') += sum_c Wt(c, alpha) Wt(c, alpha'); register r of tile
+    // (cb, .) holds rows c = cb*16 + row(g, r); rows past q are zero padding
 #pragma unroll
     for (int cb = 0; cb < NT; ++cb)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        if (cb * 16 + 4 * r >= q) continue;
+        if (cb * 16 + A::row(0, r) >= q) continue;
 #pragma unroll
         for (int u = 0; u < NT; ++u)
 #pragma unroll
-          for (int v = 0; v <= u; ++v) G[u][v] = mfma(wt[cb][u][r], wt[cb][v][r], G[u][v]);
+          for (int v = 0; v <= u; ++v) G[u][v] = A::mma(wt[cb][u][r], wt[cb][v][r], G[u][v]);
       }
+    if constexpr (PF) {
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks)
+      for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
-      for (int t = 0; t < NT; ++t) cur[ks][t] = nxt[ks][t];
+        for (int t = 0; t < NT; ++t) cur[ks][t] = (T)nxt[ks][t];
+    }
   }
-  reduce_gram<NT>(G, NT, a, Gs, partials + (long long)blockIdx.x * a * a);
+  reduce_gram<NT, A>(G, NT, a, Gs, partials + (long long)blockIdx.x * a * a);
 }
 
 // ---------------------------------------------------------------------------
@@ -185,85 +223,93 @@ __global__ __launch_bounds__(kThreads) void k_gram_right_factor(const double *__
 // The Gram of the vertical unfolding of P x_1 X (truncation sweep, §2.4).
 // KS = k-steps over a (ceil(a/4)).
 // ---------------------------------------------------------------------------
-template <int NT, int KS>
+template <int NT, int KS, class A>
 __global__ __launch_bounds__(kThreads) void k_gram_left_factor(const double *__restrict__ X, int a, int b, long long I,
                                                                const double *__restrict__ P, int p, long long sPr,
                                                                long long sPa, int tri, long long spw,
                                                                double *__restrict__ partials) {
-  __shared__ double frag[NT * KS * 64];
+  using T = typename A::T;
+  using V = typename A::V;
+  __shared__ T frag[NT * KS * 64];
   __shared__ double Gs[NT * 16 * NT * 16];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, j = lane & 15;
-  build_afrag(frag, P, p, a, sPr, sPa, NT, KS);
+  build_afrag<T>(frag, P, p, a, sPr, sPa, NT, KS);
   __syncthreads();
-  d4 G[NT][NT];
+  V G[NT][NT];
 #pragma unroll
   for (int u = 0; u < NT; ++u)
 #pragma unroll
-    for (int v = 0; v < NT; ++v) G[u][v] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int v = 0; v < NT; ++v) G[u][v] = V{0, 0, 0, 0};
   const long long beg = (long long)blockIdx.x * spw;
   const long long end = std::min(beg + spw, I);
   const long long col = (long long)a * I;
-  double cur[KS][NT], nxt[KS][NT];
+  // register prefetch of the next slice, except where it would spill (FP64,
+  // NT = 4).  The prefetch holds the raw FP64 loads; FP32 rounding happens when
+  // the slice becomes current, so the loads stay in flight across the products.
+  constexpr bool PF = (NT <= 3) || sizeof(T) == 4;
+  T cur[KS][NT];
+  double nxt[KS][NT];  // used only with PF
   long long i = beg + wave;
-  if (i < end) load_slice<NT, KS, false>(X + (long long)a * i, col, a, b, g, j, cur);
+  if constexpr (PF)
+    if (i < end) load_slice<NT, KS, false, T>(X + (long long)a * i, col, a, b, g, j, cur);
   for (; i < end; i += kWaves) {
-    if (i + kWaves < end) load_slice<NT, KS, false>(X + (long long)a * (i + kWaves), col, a, b, g, j, nxt);
-    d4 y[NT][NT];  // [rho-tile][beta-tile]
+    if constexpr (PF) {
+      if (i + kWaves < end) load_slice<NT, KS, false>(X + (long long)a * (i + kWaves), col, a, b, g, j, nxt);
+    } else {
+      load_slice<NT, KS, false, T>(X + (long long)a * i, col, a, b, g, j, cur);
+    }
+    V y[NT][NT];  // [rho-tile][beta-tile]
 #pragma unroll
     for (int u = 0; u < NT; ++u)
 #pragma unroll
-      for (int v = 0; v < NT; ++v) y[u][v] = d4{0.0, 0.0, 0.0, 0.0};
+      for (int v = 0; v < NT; ++v) y[u][v] = V{0, 0, 0, 0};
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
       for (int rb = 0; rb < NT; ++rb) {
         // upper-triangular P: P(rho, alpha) = 0 for alpha < rho
         if (tri && ks < 4 * rb) continue;
-        const double pa = frag[(rb * KS + ks) * 64 + lane];
+        const T pa = frag[(rb * KS + ks) * 64 + lane];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) y[rb][t] = mfma(pa, cur[ks][t], y[rb][t]);
+        for (int t = 0; t < NT; ++t) y[rb][t] = A::mma(pa, cur[ks][t], y[rb][t]);
       }
     // G0(beta, beta') += sum_rho Y(rho, beta) Y(rho, beta'); rows past p are padding
 #pragma unroll
     for (int rb = 0; rb < NT; ++rb)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        if (rb * 16 + 4 * r >= p) continue;
+        if (rb * 16 + A::row(0, r) >= p) continue;
 #pragma unroll
         for (int u = 0; u < NT; ++u)
 #pragma unroll
-          for (int v = 0; v <= u; ++v) G[u][v] = mfma(y[rb][u][r], y[rb][v][r], G[u][v]);
+          for (int v = 0; v <= u; ++v) G[u][v] = A::mma(y[rb][u][r], y[rb][v][r], G[u][v]);
       }
+    if constexpr (PF) {
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks)
+      for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
-      for (int t = 0; t < NT; ++t) cur[ks][t] = nxt[ks][t];
+        for (int t = 0; t < NT; ++t) cur[ks][t] = (T)nxt[ks][t];
+    }
   }
-  reduce_gram<NT>(G, NT, b, Gs, partials + (long long)blockIdx.x * b * b);
+  reduce_gram<NT, A>(G, NT, b, Gs, partials + (long long)blockIdx.x * b * b);
 }
 
 // ---------------------------------------------------------------------------
 // Output pass: Y_i = P M_i Q (p x q) written as a p x I x q core.  P == nullptr
 // means the identity (p = a); Q == nullptr means the identity (q = b).
-// KS = k-steps over b.
+// KS = k-steps over b.  With NT <= 3 two waves share each SIMD, so one wave's
+// loads and stores overlap the other's matrix-core work.
 // ---------------------------------------------------------------------------
 template <int NT, int KS>
-__global__ __launch_bounds__(kThreads) void k_apply_mfma(const double *__restrict__ X, int a, int b, long long I,
-                                                         const double *__restrict__ P, int p, long long sPr,
-                                                         long long sPa, const double *__restrict__ Q, int q,
-                                                         long long sQr, long long sQc, long long spw,
-                                                         double *__restrict__ Y) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NT <= 3 ? 2 : 1, NT <= 3 ? 2 : 1)))
+void k_apply_mfma(const double *__restrict__ X, int a, int b, long long I, const double *__restrict__ P, int p,
+                  long long sPr, long long sPa, const double *__restrict__ Q, int q, long long sQr, long long sQc,
+                  long long spw, double *__restrict__ Y) {
   constexpr int KA = NT * 4;  // k-steps over alpha (whole tiles)
-  // per-wave staging of one output slice (NT <= 3): the tile registers are
-  // written to LDS and each output column leaves as one contiguous run
-  constexpr bool kStage = (NT <= 3);
-  constexpr int LD = NT * 16 + 1;
   __shared__ double fragQ[NT * KS * 64];
   __shared__ double fragP[NT * KA * 64];
-  __shared__ double Ys[kStage ? kWaves * LD * NT * 16 : 1];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  double *Yw = Ys + (kStage ? wave * LD * NT * 16 : 0);
   const int g = lane >> 4, j = lane & 15;
   const bool hasP = (P != nullptr);
   build_bfrag(fragQ, Q, b, q, sQr, sQc, NT, KS);
@@ -273,11 +319,9 @@ __global__ __launch_bounds__(kThreads) void k_apply_mfma(const double *__restric
   const long long end = std::min(beg + spw, I);
   const long long col = (long long)a * I;
   const long long ocol = (long long)p * I;
-  double cur[KS][NT], nxt[KS][NT];
-  long long i = beg + wave;
-  if (i < end) load_slice<NT, KS, true>(X + (long long)a * i, col, a, b, g, j, cur);
-  for (; i < end; i += kWaves) {
-    if (i + kWaves < end) load_slice<NT, KS, true>(X + (long long)a * (i + kWaves), col, a, b, g, j, nxt);
+  double cur[KS][NT];
+  for (long long i = beg + wave; i < end; i += kWaves) {
+    load_slice<NT, KS, true>(X + (long long)a * i, col, a, b, g, j, cur);
     d4 w[NT][NT];  // [alpha-tile][c-tile]
 #pragma unroll
     for (int u = 0; u < NT; ++u)
@@ -310,70 +354,199 @@ __global__ __launch_bounds__(kThreads) void k_apply_mfma(const double *__restric
             for (int cb = 0; cb < NT; ++cb) y[rb][cb] = mfma(pa, w[t][cb][r], y[rb][cb]);
           }
         }
-      if (kStage) {
 #pragma unroll
-        for (int rb = 0; rb < NT; ++rb)
+      for (int rb = 0; rb < NT; ++rb)
 #pragma unroll
-          for (int cb = 0; cb < NT; ++cb)
+        for (int cb = 0; cb < NT; ++cb) {
+          const int c = cb * 16 + j;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) Yw[(rb * 16 + g + 4 * r) + LD * (cb * 16 + j)] = y[rb][cb][r];
-      } else {
-#pragma unroll
-        for (int rb = 0; rb < NT; ++rb)
-#pragma unroll
-          for (int cb = 0; cb < NT; ++cb) {
-            const int c = cb * 16 + j;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int rho = rb * 16 + g + 4 * r;
-              if (rho < p && c < q) Yi[rho + ocol * c] = y[rb][cb][r];
-            }
+          for (int r = 0; r < 4; ++r) {
+            const int rho = rb * 16 + g + 4 * r;
+            if (rho < p && c < q) Yi[rho + ocol * c] = y[rb][cb][r];
           }
-      }
-    } else {
-      if (kStage) {
-#pragma unroll
-        for (int t = 0; t < NT; ++t)
-#pragma unroll
-          for (int cb = 0; cb < NT; ++cb)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) Yw[(t * 16 + g + 4 * r) + LD * (cb * 16 + j)] = w[t][cb][r];
-      } else {
-#pragma unroll
-        for (int t = 0; t < NT; ++t)
-#pragma unroll
-          for (int cb = 0; cb < NT; ++cb) {
-            const int c = cb * 16 + j;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int alpha = t * 16 + g + 4 * r;
-              if (alpha < p && c < q) Yi[alpha + ocol * c] = w[t][cb][r];
-            }
-          }
-      }
-    }
-    if (kStage) {
-      // the wave's LDS writes complete before its reads (same wave, in order)
-      __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-      int rho = lane, c = 0;
-      while (rho >= p) {
-        rho -= p;
-        ++c;
-      }
-      for (; c < q;) {
-        Yi[rho + ocol * c] = Yw[rho + LD * c];
-        rho += 64;
-        while (rho >= p) {
-          rho -= p;
-          ++c;
         }
-      }
-      __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    } else {
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int cb = 0; cb < NT; ++cb) {
+          const int c = cb * 16 + j;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int alpha = t * 16 + g + 4 * r;
+            if (alpha < p && c < q) Yi[alpha + ocol * c] = w[t][cb][r];
+          }
+        }
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Refinement passes on a materialized core (truncation sweep, §2.4, when the
+// first Gram pass could not settle the factorization).  The slice seen is
+// S_i = M_i (TR = false, a x b) or M_i^T (TR = true, b x a); sa x sb below.
+//
+// k_gram_fac: G (q x q) = sum_i (S_i Q)^T (S_i Q), Q (sb x q).
+// k_apply_fac2: Y_i = S_i Q1 Q2 (sa x q2), written as an sa x I x q2 core
+//   (TR = false) or as its transpose q2 x I x sa (TR = true).
+// The first product is W = S Q1 in k_gram_fac and W^T = Q1^T S^T in
+// k_apply_fac2: the same operands with A and B exchanged, which the matrix
+// cores round identically, so the output pass applies exactly the stage whose
+// orthonormality the Gram pass measured.
+// ---------------------------------------------------------------------------
+template <int NT, int KS, bool TR>
+__global__ __launch_bounds__(kThreads) void k_gram_fac(const double *__restrict__ X, int a, int b, long long I,
+                                                       const double *__restrict__ Q, int q, long long sQr,
+                                                       long long sQc, int tri, long long spw,
+                                                       double *__restrict__ partials) {
+  constexpr bool PF = (NT <= 3);  // register prefetch of the next slice
+  __shared__ double frag[NT * KS * 64];
+  __shared__ double Gs[NT * 16 * NT * 16];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, j = lane & 15;
+  const int sa = TR ? b : a, sb = TR ? a : b;
+  build_bfrag(frag, Q, sb, q, sQr, sQc, NT, KS);
+  __syncthreads();
+  d4 G[NT][NT];
+#pragma unroll
+  for (int u = 0; u < NT; ++u)
+#pragma unroll
+    for (int v = 0; v < NT; ++v) G[u][v] = d4{0.0, 0.0, 0.0, 0.0};
+  const long long beg = (long long)blockIdx.x * spw;
+  const long long end = std::min(beg + spw, I);
+  const long long col = (long long)a * I;
+  // cur[ks][t] = S(16t + j, 4ks + g)
+  double cur[KS][NT], nxt[KS][NT];  // nxt is used only with PF
+  long long i = beg + wave;
+  if constexpr (PF)
+    if (i < end) load_slice<NT, KS, !TR>(X + (long long)a * i, col, a, b, g, j, cur);
+  for (; i < end; i += kWaves) {
+    if constexpr (PF) {
+      if (i + kWaves < end)
+        load_slice<NT, KS, !TR>(X + (long long)a * (i + kWaves), col, a, b, g, j, nxt);
+    } else {
+      load_slice<NT, KS, !TR>(X + (long long)a * i, col, a, b, g, j, cur);
+    }
+    d4 w[NT][NT];  // [s-tile][c-tile]
+#pragma unroll
+    for (int u = 0; u < NT; ++u)
+#pragma unroll
+      for (int v = 0; v < NT; ++v) w[u][v] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
-      for (int t = 0; t < NT; ++t) cur[ks][t] = nxt[ks][t];
+      for (int cb = 0; cb < NT; ++cb) {
+        if (tri && ks < 4 * cb) continue;  // lower-triangular Q
+        const double qb = frag[(cb * KS + ks) * 64 + lane];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) w[t][cb] = mfma(cur[ks][t], qb, w[t][cb]);
+      }
+    // G(c, c') += sum_s W(s, c) W(s, c'); register r of tile (t, .) holds rows
+    // s = 16t + 4r + g; rows past sa are padding
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (t * 16 + 4 * r >= sa) continue;
+#pragma unroll
+        for (int u = 0; u < NT; ++u)
+#pragma unroll
+          for (int v = 0; v <= u; ++v) G[u][v] = mfma(w[t][u][r], w[t][v][r], G[u][v]);
+      }
+    if constexpr (PF) {
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) cur[ks][t] = nxt[ks][t];
+    }
+  }
+  reduce_gram<NT, F64>(G, NT, q, Gs, partials + (long long)blockIdx.x * q * q);
+}
+
+template <int NT, int KS, bool TR>
+__global__ __launch_bounds__(kThreads) void k_apply_fac2(const double *__restrict__ X, int a, int b, long long I,
+                                                         const double *__restrict__ Q1, int q1, long long s1r,
+                                                         long long s1c, int tri, const double *__restrict__ Q2,
+                                                         int q2, long long s2r, long long s2c, long long spw,
+                                                         double *__restrict__ Y) {
+  constexpr bool PF = (NT <= 3);
+  constexpr int KC = NT * 4;  // k-steps over the columns of Q1 (whole tiles)
+  __shared__ double frag1[NT * KS * 64];
+  __shared__ double frag2[NT * KC * 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, j = lane & 15;
+  const int sa = TR ? b : a, sb = TR ? a : b;
+  // A operands: Q1^T (q1 x sb) and Q2^T (q2 x q1)
+  build_afrag(frag1, Q1, q1, sb, s1c, s1r, NT, KS);
+  build_afrag(frag2, Q2, q2, q1, s2c, s2r, NT, KC);
+  __syncthreads();
+  const long long beg = (long long)blockIdx.x * spw;
+  const long long end = std::min(beg + spw, I);
+  const long long col = (long long)a * I;
+  // output addressing: element (s, c2) of slice i
+  const long long ostep_s = TR ? (long long)q2 * I : 1;
+  const long long ostep_c = TR ? 1 : (long long)sa * I;
+  const long long oslice = TR ? q2 : sa;
+  double cur[KS][NT], nxt[KS][NT];  // nxt is used only with PF
+  long long i = beg + wave;
+  if constexpr (PF)
+    if (i < end) load_slice<NT, KS, !TR>(X + (long long)a * i, col, a, b, g, j, cur);
+  for (; i < end; i += kWaves) {
+    if constexpr (PF) {
+      if (i + kWaves < end)
+        load_slice<NT, KS, !TR>(X + (long long)a * (i + kWaves), col, a, b, g, j, nxt);
+    } else {
+      load_slice<NT, KS, !TR>(X + (long long)a * i, col, a, b, g, j, cur);
+    }
+    d4 wt[NT][NT];  // [c-tile][s-tile]: W^T = Q1^T S^T
+#pragma unroll
+    for (int u = 0; u < NT; ++u)
+#pragma unroll
+      for (int v = 0; v < NT; ++v) wt[u][v] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+      for (int cb = 0; cb < NT; ++cb) {
+        if (tri && ks < 4 * cb) continue;
+        const double qa = frag1[(cb * KS + ks) * 64 + lane];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) wt[cb][t] = mfma(qa, cur[ks][t], wt[cb][t]);
+      }
+    d4 yt[NT][NT];  // [c2-tile][s-tile]: Y^T = Q2^T W^T
+#pragma unroll
+    for (int u = 0; u < NT; ++u)
+#pragma unroll
+      for (int v = 0; v < NT; ++v) yt[u][v] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int cb = 0; cb < NT; ++cb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (cb * 16 + 4 * r >= q1) continue;
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+          const double qa = frag2[(u * KC + cb * 4 + r) * 64 + lane];
+#pragma unroll
+          for (int t = 0; t < NT; ++t) yt[u][t] = mfma(qa, wt[cb][t][r], yt[u][t]);
+        }
+      }
+    double *Yi = Y + oslice * i;
+#pragma unroll
+    for (int u = 0; u < NT; ++u)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int sidx = t * 16 + j;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int c2 = u * 16 + 4 * r + g;
+          if (sidx < sa && c2 < q2) Yi[ostep_s * sidx + ostep_c * c2] = yt[u][t][r];
+        }
+      }
+    if constexpr (PF) {
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) cur[ks][t] = nxt[ks][t];
+    }
   }
 }
 
@@ -398,37 +571,55 @@ int tiles_for(int m) { return (m + 15) / 16; }
 }  // namespace
 
 // (NT, KS) dispatch: NT = 16-tiles covering every dimension, KS = k-steps of the
-// contracted slice dimension, KS in {4NT-3, ..., 4NT}.
-#define TTR_KS_CASES(KERNEL, NTV, ...)                                                                  \
-  switch (ks - (4 * NTV - 3)) {                                                                        \
-    case 0: hipLaunchKernelGGL((KERNEL<NTV, 4 * NTV - 3>), dim3(gr.nwg), dim3(kThreads), 0, s, __VA_ARGS__); break; \
-    case 1: hipLaunchKernelGGL((KERNEL<NTV, 4 * NTV - 2>), dim3(gr.nwg), dim3(kThreads), 0, s, __VA_ARGS__); break; \
-    case 2: hipLaunchKernelGGL((KERNEL<NTV, 4 * NTV - 1>), dim3(gr.nwg), dim3(kThreads), 0, s, __VA_ARGS__); break; \
-    default: hipLaunchKernelGGL((KERNEL<NTV, 4 * NTV>), dim3(gr.nwg), dim3(kThreads), 0, s, __VA_ARGS__); break;    \
+// contracted slice dimension, KS in {4NT-3, ..., 4NT}.  `f` receives both as
+// std::integral_constant values.
+template <int NTV, class F>
+void ks_cases(int ks, F &&f) {
+  switch (ks - (4 * NTV - 3)) {
+    case 0: f(std::integral_constant<int, NTV>{}, std::integral_constant<int, 4 * NTV - 3>{}); break;
+    case 1: f(std::integral_constant<int, NTV>{}, std::integral_constant<int, 4 * NTV - 2>{}); break;
+    case 2: f(std::integral_constant<int, NTV>{}, std::integral_constant<int, 4 * NTV - 1>{}); break;
+    default: f(std::integral_constant<int, NTV>{}, std::integral_constant<int, 4 * NTV>{}); break;
   }
-#define TTR_NT_CASES(KERNEL, ...)                       \
-  switch (nt) {                                          \
-    case 1: TTR_KS_CASES(KERNEL, 1, __VA_ARGS__) break;  \
-    case 2: TTR_KS_CASES(KERNEL, 2, __VA_ARGS__) break;  \
-    case 3: TTR_KS_CASES(KERNEL, 3, __VA_ARGS__) break;  \
-    default: TTR_KS_CASES(KERNEL, 4, __VA_ARGS__) break; \
+}
+template <class F>
+void nt_ks(int nt, int ks, F &&f) {
+  switch (nt) {
+    case 1: ks_cases<1>(ks, f); break;
+    case 2: ks_cases<2>(ks, f); break;
+    case 3: ks_cases<3>(ks, f); break;
+    default: ks_cases<4>(ks, f); break;
   }
+}
+#define TTR_LAUNCH(...) hipLaunchKernelGGL((__VA_ARGS__), dim3(gr.nwg), dim3(kThreads), 0, s,
 
 int launch_gram_right_factor(hipStream_t s, const double *X, int a, int b, long long I, const double *Q, int q,
-                             long long sQr, long long sQc, int tri, double *partials) {
+                             long long sQr, long long sQc, int tri, int f32, double *partials) {
   const Grid gr = grid_of(I);
   const int nt = std::max({tiles_for(a), tiles_for(b), tiles_for(q)});
   const int ks = std::max((b + 3) / 4, 4 * nt - 3);
-  TTR_NT_CASES(k_gram_right_factor, X, a, b, I, Q, q, sQr, sQc, tri, gr.spw, partials)
+  nt_ks(nt, ks, [&](auto NTc, auto KSc) {
+    constexpr int NTV = decltype(NTc)::value, KSV = decltype(KSc)::value;
+    if (f32)
+      TTR_LAUNCH(k_gram_right_factor<NTV, KSV, F32>) X, a, b, I, Q, q, sQr, sQc, tri, gr.spw, partials);
+    else
+      TTR_LAUNCH(k_gram_right_factor<NTV, KSV, F64>) X, a, b, I, Q, q, sQr, sQc, tri, gr.spw, partials);
+  });
   return gr.nwg;
 }
 
 int launch_gram_left_factor(hipStream_t s, const double *X, int a, int b, long long I, const double *P, int p,
-                            long long sPr, long long sPa, int tri, double *partials) {
+                            long long sPr, long long sPa, int tri, int f32, double *partials) {
   const Grid gr = grid_of(I);
   const int nt = std::max({tiles_for(a), tiles_for(b), tiles_for(p)});
   const int ks = std::max((a + 3) / 4, 4 * nt - 3);
-  TTR_NT_CASES(k_gram_left_factor, X, a, b, I, P, p, sPr, sPa, tri, gr.spw, partials)
+  nt_ks(nt, ks, [&](auto NTc, auto KSc) {
+    constexpr int NTV = decltype(NTc)::value, KSV = decltype(KSc)::value;
+    if (f32)
+      TTR_LAUNCH(k_gram_left_factor<NTV, KSV, F32>) X, a, b, I, P, p, sPr, sPa, tri, gr.spw, partials);
+    else
+      TTR_LAUNCH(k_gram_left_factor<NTV, KSV, F64>) X, a, b, I, P, p, sPr, sPa, tri, gr.spw, partials);
+  });
   return gr.nwg;
 }
 
@@ -438,5 +629,40 @@ void launch_apply_mfma(hipStream_t s, const double *X, int a, int b, long long I
   const Grid gr = grid_of(I);
   const int nt = std::max({tiles_for(a), tiles_for(b), tiles_for(p), tiles_for(q)});
   const int ks = std::max((b + 3) / 4, 4 * nt - 3);
-  TTR_NT_CASES(k_apply_mfma, X, a, b, I, P, p, sPr, sPa, Q, q, sQr, sQc, gr.spw, Y)
+  nt_ks(nt, ks, [&](auto NTc, auto KSc) {
+    constexpr int NTV = decltype(NTc)::value, KSV = decltype(KSc)::value;
+    TTR_LAUNCH(k_apply_mfma<NTV, KSV>) X, a, b, I, P, p, sPr, sPa, Q, q, sQr, sQc, gr.spw, Y);
+  });
+}
+
+int launch_gram_fac(hipStream_t s, const double *X, int a, int b, long long I, int trans, const double *Q, int q,
+                    long long sQr, long long sQc, int tri, double *partials) {
+  const Grid gr = grid_of(I);
+  const int sb = trans ? a : b;
+  const int nt = std::max({tiles_for(a), tiles_for(b), tiles_for(q)});
+  const int ks = std::max((sb + 3) / 4, 4 * nt - 3);
+  nt_ks(nt, ks, [&](auto NTc, auto KSc) {
+    constexpr int NTV = decltype(NTc)::value, KSV = decltype(KSc)::value;
+    if (trans)
+      TTR_LAUNCH(k_gram_fac<NTV, KSV, true>) X, a, b, I, Q, q, sQr, sQc, tri, gr.spw, partials);
+    else
+      TTR_LAUNCH(k_gram_fac<NTV, KSV, false>) X, a, b, I, Q, q, sQr, sQc, tri, gr.spw, partials);
+  });
+  return gr.nwg;
+}
+
+void launch_apply_fac2(hipStream_t s, const double *X, int a, int b, long long I, int trans, const double *Q1,
+                       int q1, long long s1r, long long s1c, int tri, const double *Q2, int q2, long long s2r,
+                       long long s2c, double *Y) {
+  const Grid gr = grid_of(I);
+  const int sb = trans ? a : b;
+  const int nt = std::max({tiles_for(a), tiles_for(b), tiles_for(q1), tiles_for(q2)});
+  const int ks = std::max((sb + 3) / 4, 4 * nt - 3);
+  nt_ks(nt, ks, [&](auto NTc, auto KSc) {
+    constexpr int NTV = decltype(NTc)::value, KSV = decltype(KSc)::value;
+    if (trans)
+      TTR_LAUNCH(k_apply_fac2<NTV, KSV, true>) X, a, b, I, Q1, q1, s1r, s1c, tri, Q2, q2, s2r, s2c, gr.spw, Y);
+    else
+      TTR_LAUNCH(k_apply_fac2<NTV, KSV, false>) X, a, b, I, Q1, q1, s1r, s1c, tri, Q2, q2, s2r, s2c, gr.spw, Y);
+  });
 }

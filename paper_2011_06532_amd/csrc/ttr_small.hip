@@ -431,24 +431,43 @@ __global__ __launch_bounds__(kThreadsQR) void k_qr_step(QrStepArgs a) {
     }
     return;
   }
-  if (a.try_chol && a.pass == 1) {
-    // One-pass attempt by Cholesky, G = L L^T: F = L^{-T}, R = L^T, T = L.
-    // Accepted when kappa(G) (bounded by ||G||_F ||L^{-1}||_F^2, scaled by
-    // kappa(T)^2 when G came through a post-transform) is at most 1/tau1, and,
-    // in the truncation sweep, when no singular value can fall below delta.
+  if (a.try_chol) {
+    // Attempt by Cholesky, G = L L^T: F = L^{-T}, R = L^T Rc (T = L at pass 1).
+    // Accepted when kappa(G) (bounded by Gershgorin or ||G||_1 ||L^{-1}||_1
+    // ||L^{-1}||_inf, scaled by kappa(T)^2 when G came through a post-transform)
+    // is at most 1/tau1, and, at the first pass of the truncation sweep, when
+    // no singular value can fall below delta.  At a refinement pass G is close
+    // to the identity and this is the second step of CholeskyQR2.
     __shared__ int accept;
     for (int e = threadIdx.x; e < d * d; e += blockDim.x) Bf[e] = A[e];  // keep G for a fallback
     double trace_part = 0.0;
     for (int j = threadIdx.x; j < d; j += blockDim.x) trace_part += A[j + d * j];
     const double trG = block_sum(trace_part);
+    // Gershgorin: every eigenvalue of G lies in [min_r (G_rr - off_r), max_r (G_rr + off_r)],
+    // off_r = sum_{c != r} |G_rc|; tight for the near-diagonal Grams of
+    // well-conditioned unfoldings
+    double glo = DBL_MAX, ghi = 0.0;
+    for (int r = threadIdx.x; r < d; r += blockDim.x) {
+      double off = 0.0;
+      for (int c = 0; c < d; ++c)
+        if (c != r) off += fabs(A[r + d * c]);
+      glo = fmin(glo, A[r + d * r] - off);
+      ghi = fmax(ghi, A[r + d * r] + off);
+    }
+    const double gmin = -block_max(-glo), gmax = block_max(ghi);
     double kappa = 0.0, lmin_lb = 0.0;
     const bool ok = chol_inv(A, Vm, d, &kappa, &lmin_lb);
+    if (gmin > 0.0) {
+      kappa = fmin(kappa, gmax / gmin);
+      lmin_lb = fmax(lmin_lb, gmin);
+    }
     if (threadIdx.x == 0) {
       int acc = ok && (kappa == kappa) && kappa * (a.cond_scale > 1.0 ? a.cond_scale : 1.0) * a.tau1 <= 1.0;
       int notrunc = 0;
-      if (acc && a.notrunc_check) {
+      if (acc && a.notrunc_check && a.pass == 1) {
         const double dl = a.first ? sqrt(a.tol2_nm1 * trG) : *a.delta_dev;
-        notrunc = (lmin_lb > 4.0 * dl * dl);
+        const double cs = a.cond_scale > 1.0 ? a.cond_scale : 1.0;
+        notrunc = (lmin_lb - a.gerr * cs * trG > 4.0 * dl * dl);
         acc = notrunc;
       }
       if (a.ratio_out) *a.ratio_out = ok ? kappa : 1e300;
@@ -459,16 +478,31 @@ __global__ __launch_bounds__(kThreadsQR) void k_qr_step(QrStepArgs a) {
     if (accept) {
       // A holds L (lower), Vm holds L^{-1} (lower)
       const int b = a.b;  // == d at pass 1
-      for (int e = threadIdx.x; e < d * d; e += blockDim.x) {
-        const int r = e % d, c = e / d;
-        a.Fstep[r + d * c] = Vm[c + d * r];       // F = L^{-T}
-        a.Rnext[r + d * c] = A[c + d * r];        // R = L^T
-        if (a.Tdst) a.Tdst[r + b * c] = A[r + d * c];  // T = L
+      if (!a.Rc) {
+        for (int e = threadIdx.x; e < d * d; e += blockDim.x) {
+          const int r = e % d, c = e / d;
+          a.Fstep[r + d * c] = Vm[c + d * r];            // F = L^{-T}
+          a.Rnext[r + d * c] = A[c + d * r];             // R = L^T
+          if (a.Tdst) a.Tdst[r + b * c] = A[r + d * c];  // T = L
+        }
+      } else {
+        for (int e = threadIdx.x; e < d * d; e += blockDim.x) {
+          const int r = e % d, c = e / d;
+          a.Fstep[r + d * c] = Vm[c + d * r];  // F = L^{-T}
+        }
+        // R = L^T Rc (d x b), and T = R^T
+        for (int e = threadIdx.x; e < d * b; e += blockDim.x) {
+          const int r = e % d, c = e / d;
+          double v = 0.0;
+          for (int j = r; j < d; ++j) v += A[j + d * r] * a.Rc[j + d * c];
+          a.Rnext[r + d * c] = v;
+          if (a.Tdst) a.Tdst[c + b * r] = v;
+        }
       }
       if (threadIdx.x == 0) {
         a.dec[0] = d;
         a.dec[1] = 1;
-        a.dec[4] = 1;  // triangular factors
+        a.dec[4] = a.Rc ? 0 : 1;  // triangular factors (first pass only)
       }
       return;
     }
@@ -505,7 +539,7 @@ __global__ __launch_bounds__(kThreadsQR) void k_qr_step(QrStepArgs a) {
     } else if (a.pass == 1) {
       const double cs = a.cond_scale > 1.0 ? a.cond_scale : 1.0;
       if (a.ratio_out) *a.ratio_out = (tmin > 0.0) ? t1 / tmin : 1e300;
-      const double shift = (tmin >= a.tau1 * t1 * cs) ? 0.0 : 2.0 * d * kU * t1 + 2.0 * (tmin < 0 ? -tmin : 0.0);
+      const double shift = (tmin >= a.tau1 * t1 * cs) ? 0.0 : 2.0 * d * a.ugram * t1 + 2.0 * (tmin < 0 ? -tmin : 0.0);
       for (int j = 0; j < d; ++j) {
         const double v = sc[j] + shift;
         rs[j] = sqrt(v);

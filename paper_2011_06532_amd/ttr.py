@@ -41,7 +41,9 @@ SYMBOLS = [
 ]
 
 PROF_CLASSES = ["k_gram_right_factor", "k_gram_left_factor", "k_gram", "k_apply_mfma", "k_apply", "k_add",
-                "k_hadamard", "k_dot_step", "small"]
+                "k_hadamard", "k_dot_step", "small", "k_gram_fac", "k_apply_fac2", "k_gram_right_factor_f32",
+                "k_gram_left_factor_f32"]
+NPROF = len(PROF_CLASSES)  # TTR_NPROF
 
 
 class _TTStruct(ctypes.Structure):
@@ -69,10 +71,10 @@ class RoundStats(ctypes.Structure):
 
 class Profile(ctypes.Structure):
     _fields_ = [
-        ("count", ctypes.c_int64 * 9),
-        ("ms", ctypes.c_double * 9),
-        ("bytes", ctypes.c_double * 9),
-        ("flops", ctypes.c_double * 9),
+        ("count", ctypes.c_int64 * NPROF),
+        ("ms", ctypes.c_double * NPROF),
+        ("bytes", ctypes.c_double * NPROF),
+        ("flops", ctypes.c_double * NPROF),
     ]
 
 
