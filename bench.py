@@ -21,6 +21,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -57,6 +59,20 @@ def pmc_traffic(kernel_class, per_launch_bytes):
     if not ent:
         return None
     return ent.get("hbm_bytes_per_launch")
+
+
+def sample_entries(cores, R, I, idx):
+    """Entries X(i_1, ..., i_N) at the rows of idx, as products of slices
+    (the cores' slices are gathered on the device, multiplied on the host)."""
+    import numpy as np
+    S, N = idx.shape
+    v = np.ones((S, 1))
+    for n in range(N):
+        r0, r1 = R[n], R[n + 1]
+        t3 = cores[n][: r0 * I[n] * r1].view(r1, I[n], r0)      # [b][i][a]
+        sl = t3[:, idx[:, n], :].permute(1, 2, 0).cpu().numpy()  # [s][a][b]
+        v = np.einsum("sa,sab->sb", v, sl)
+    return v[:, 0]
 
 
 def cpu_baseline(I_sample, steps=1):
@@ -106,6 +122,7 @@ def main():
     ap.add_argument("--direction", default="RLR", choices=["RLR", "LRL"])
     ap.add_argument("--cpu-sample-I", type=int, default=16384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision rounds")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="only run a plain device-to-device copy of this many GiB (counter calibration)")
     args = ap.parse_args()
@@ -176,6 +193,38 @@ def main():
     ms_round = sum(e1.elapsed_time(e2) for _, e1, e2 in ev) / args.steps
     ms_add = sum(e0.elapsed_time(e1) for e0, e1, _ in ev) / args.steps
     ranks_ok = Y.R[1:-1] == [2 * r] * (N - 1)
+    Yf = [c.clone() for c in Y.cores]
+    ranks_fp64 = list(Y.R)
+
+    # the same rounding in mixed precision (FP32 first Gram passes), timed the
+    # same way, and its result compared with the FP64 one through TT inner
+    # products on the device
+    mixed = None
+    if args.prec == "fp64" and not args.no_mixed:
+        log("mixed precision rounds")
+        for w in range(args.warmup):
+            Ym = h.round(Xbuf, tol, args.direction, "mixed", out=Ybuf)
+        torch.cuda.synchronize()
+        evm = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        for k in range(args.steps):
+            evm[k][0].record(stream)
+            Ym = h.round(Xbuf, tol, args.direction, "mixed", out=Ybuf)
+            evm[k][1].record(stream)
+        torch.cuda.synchronize()
+        ms_mixed = sum(a.elapsed_time(b) for a, b in evm) / args.steps
+        # entrywise agreement with the FP64 result on sampled multi-indices
+        # (a norm of the difference would cancel at this size)
+        idx = np.random.default_rng(7).integers(0, args.I, size=(256, N))
+        ef = sample_entries(Yf, ranks_fp64, I, idx)
+        em = sample_entries(Ym.cores, list(Ym.R), I, idx)
+        rel = float(np.max(np.abs(em - ef)) / np.sqrt(np.mean(ef * ef)))
+        mixed = {"ms_per_round": round(ms_mixed, 3),
+                 "round_core_GBps": round(size_x / (ms_mixed * 1e-3) / 1e9, 2),
+                 "speedup_vs_fp64": round(ms_round / ms_mixed, 3),
+                 "ranks_equal": list(Ym.R) == ranks_fp64,
+                 "max_entry_diff_vs_fp64": rel,
+                 "entries_sampled": int(idx.shape[0])}
 
     # dominant kernel by time
     cls = max((c for c in prof if c != "small"), key=lambda c: prof[c]["ms"])
@@ -222,9 +271,11 @@ def main():
         "ranks_ok": ranks_ok,
         "gram_passes": st["gram_passes"],
         "apply_passes": st["apply_passes"],
-        "kernel_ms_per_step": {c: round(prof[c]["ms"] / args.steps, 3) for c in prof},
+        "kernel_ms_per_step": {c: round(prof[c]["ms"] / args.steps, 3) for c in prof if prof[c]["count"]},
         "roofline": roof,
     }
+    if mixed:
+        out["mixed"] = mixed
     if not args.no_cpu_baseline:
         log(f"cpu_baseline: oracle on I={args.cpu_sample_I}")
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_I)

@@ -123,6 +123,42 @@ int ttr_orthogonalize(ttr_handle *h, ttr_tt *X, int side, int prec);
 int ttr_round(ttr_handle *h, const ttr_tt *X, double tol, int direction, int prec,
               ttr_tt *Y, double *norm_out);
 
+/* Batched rounding (the batched form of §2.4 Alg. 2): Y[t] = rounding of X[t]
+ * to relative accuracy tol[t], t = 0..count-1, for tensors of uneven mode
+ * sizes and ranks that share the number of cores N (2 <= N <= 16), RLR order.
+ * Arithmetic, accuracy and `prec` are those of ttr_round.  The decisions that
+ * ttr_round takes on the host (ranks, whether a factorization has settled) are
+ * taken on the device, so the whole call is one fixed sequence of batched
+ * launches; it is captured once into a HIP graph and every later call with the
+ * same arguments (pointers, shapes, tolerances) replays it with one launch.
+ * Asynchronous: no host synchronization once the plan exists.
+ *   ranks_dev  DEVICE array of count*(N+1) int64: the ranks of Y[t] at
+ *              ranks_dev[t*(N+1) .. t*(N+1)+N]; ranks_dev[t*(N+1)] is -1 when a
+ *              small factorization of tensor t failed (non-finite data).
+ *              Y[t].R (host) is not written.
+ *   tune       nonzero: when the plan is built, time the captured graph for a
+ *              few slices-per-workgroup and grid-cap settings on this batch and
+ *              keep the fastest (ttr_get_batch_plan reports them).
+ * Building a plan allocates its device workspace and synchronizes; the plan
+ * of the previous batch on the handle is released.  X and Y are not copied:
+ * the graph reads and writes the given core pointers when replayed. */
+int ttr_round_batched(ttr_handle *h, int count, const ttr_tt *X, const double *tol, int direction, int prec,
+                      ttr_tt *Y, int64_t *ranks_dev, int tune);
+
+typedef struct ttr_batch_plan {
+  int32_t count;           /* tensors in the cached plan (0: none) */
+  int32_t spw_target;      /* slices per workgroup chosen */
+  int32_t grid_cap;        /* persistent grid cap chosen (0: one workgroup per item) */
+  int32_t graph_nodes;     /* launches in the captured graph */
+  int64_t workspace_bytes;
+  int32_t candidates;      /* autotuner candidates timed */
+  int32_t cand_spw[16];
+  int32_t cand_grid[16];
+  double cand_ms[16];      /* one replay of each candidate's graph */
+} ttr_batch_plan;
+
+int ttr_get_batch_plan(const ttr_handle *h, ttr_batch_plan *out);
+
 const char *ttr_status_string(int status);
 const char *ttr_last_error(void);
 

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libttr.so")
-SOURCES = ["ttr_api.hip", "ttr_stream.hip", "ttr_small.hip", "ttr_mfma.hip"]
+SOURCES = ["ttr_api.hip", "ttr_stream.hip", "ttr_small.hip", "ttr_mfma.hip", "ttr_batch.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

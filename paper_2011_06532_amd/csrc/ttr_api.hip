@@ -3,8 +3,7 @@
 // §3.5 Alg. 6).  All arithmetic runs in the kernels of ttr_stream.hip and
 // ttr_small.hip; this file only plans launches and reads back the small
 // integer decisions (ranks, pass counts) that size the next launch.
-#include "../../include/ttr.h"
-#include "ttr_internal.h"
+#include "ttr_host.h"
 
 #include <cmath>
 #include <cstdlib>
@@ -12,29 +11,6 @@
 #include <cstring>
 #include <string>
 #include <vector>
-
-struct ttr_handle {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  double *ws = nullptr;
-  size_t ws_bytes = 0;
-  int *dec_host = nullptr;  // pinned
-  int *dec_dev = nullptr;
-  double *decf_host = nullptr;  // pinned: per-step doubles (conditioning ratio)
-  double *decf_dev = nullptr;
-  double *scal_host = nullptr;  // pinned scalars
-  ttr_round_stats stats;
-  // opt-in kernel timing
-  struct Pending {
-    hipEvent_t a, b;
-    int cls;
-    double bytes, flops;
-  };
-  int profiling = 0;
-  std::vector<hipEvent_t> evpool;
-  std::vector<Pending> pending;
-  ttr_profile prof;
-};
 
 namespace {
 
@@ -44,6 +20,12 @@ int fail(int code, const std::string &msg) {
   g_err = msg;
   return code;
 }
+
+}  // namespace
+
+int ttr_fail(int code, const std::string &msg) { return fail(code, msg); }
+
+namespace {
 
 #define HIPCHK(expr)                                                                      \
   do {                                                                                    \
@@ -650,6 +632,7 @@ int ttr_destroy(ttr_handle *h) {
   if (h->decf_host) (void)hipHostFree(h->decf_host);
   if (h->dec_host) (void)hipHostFree(h->dec_host);
   if (h->scal_host) (void)hipHostFree(h->scal_host);
+  ttr_batch_release(h);
   for (auto &p : h->pending) {
     h->evpool.push_back(p.a);
     h->evpool.push_back(p.b);

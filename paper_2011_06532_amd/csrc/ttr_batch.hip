@@ -1,0 +1,1029 @@
+// Batched TT rounding (Alg. 2, RLR; §2.4, §3.5): many independent tensors of
+// uneven mode sizes and ranks rounded by one captured HIP graph.
+//
+// The single-tensor path (ttr_api.hip) plans every launch on the host from
+// the small decisions of the previous step (ranks, whether a factorization
+// has settled).  Here those decisions stay on the device: before every step a
+// one-thread-per-tensor planner kernel (kp_plan) reads them from the tensor's
+// state and writes the operands of the next batched launch, and a tensor
+// whose factorization has settled simply has its items switched off.  The
+// launch sequence is therefore fixed for a given batch shape (at most three
+// Gram passes per factorization), contains no host synchronization, and is
+// captured once into a hipGraph that later calls replay with one launch.
+//
+// The arithmetic is the single path's: QR-by-Gram with the Cholesky route
+// and the shifted eigen route (k_qr_step), refinement passes on materialized
+// cores, the truncation step (k_trunc_step), the same matrix-core bodies for
+// every streaming pass.  Streaming launches cover one core index of every
+// tensor, split into (tensor, workgroup) items per tile class; workgroups walk
+// the items persistently when the grid is capped.  The autotuner times the
+// captured graph for a few slices-per-workgroup and grid-cap settings on the
+// actual batch and keeps the fastest.
+#include "ttr_host.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace {
+
+constexpr int kBMaxN = 16;  // cores per tensor in a batched call
+constexpr double kU64 = 1.1102230246251565e-16;
+constexpr double kU32 = 5.9604644775390625e-08;
+constexpr double kTau1 = 1e-3;
+constexpr double kTau2 = 1e-12;
+constexpr double kTauMix = 1e-5;
+
+// Per-tensor state in device memory.  The static part is written by the host
+// when the plan is built; the rest is the device-side record of the decisions.
+struct BState {
+  // static
+  int N, f32;
+  double tol;
+  long long I[kBMaxN];
+  int R[kBMaxN + 1];
+  long long spw[kBMaxN];
+  int nwg[kBMaxN];
+  const double *X[kBMaxN];
+  double *Y[kBMaxN];
+  double *partials, *G, *Ra, *Rb, *Gst[3], *P[2], *GU, *Qm, *scal, *sigma, *matA, *matB;
+  double *T[kBMaxN + 1];
+  double *B[kBMaxN][3];
+  int *dec;
+  double *decf;
+  int64_t *ranks;
+  // orthonormalization sweep, per core
+  int k[kBMaxN + 1];
+  int nst[kBMaxN], dim[kBMaxN][4], tri[kBMaxN];
+  double kappa2[kBMaxN + 1];
+  int L[kBMaxN + 1];
+  // the factorization in progress
+  int done, passes, kcur, notrunc, tfold, gnst;
+  int gdim[4];
+  const double *src;  // orthonormalization: the refinement passes' core
+  int sa, sb;
+  double *csrc;       // truncation: the materialized core C'_n
+  int ca, cb;
+  double *ebuf;       // truncation: C'_n G_1 for a third pass
+  const double *Pcur;
+  int Lprev;
+};
+
+enum Op {
+  S1_G1, S1_Q1, S1_M1, S1_G2, S1_Q2, S1_M2, S1_G3, S1_Q3, S1_END,
+  S2_P1, S2_P2, S2_P3, S2_G1, S2_Q1, S2_M1, S2_G2, S2_Q2, S2_M2, S2_G3, S2_Q3, S2_TR, S2_O1, S2_O2,
+  S3_P, S3_O, FIN
+};
+
+__device__ double gram_err_dev(long long spw, int contracted, double u, int nwg) {
+  const double nacc = (double)((spw + 3) / 4) * contracted + 4.0 + (double)nwg + 2.0;
+  return 2.0 * nacc * u;
+}
+
+__device__ void set_core(BDesc &e, const BState &S, int n, const double *X, int a, int b) {
+  e.active = 1;
+  e.X = X;
+  e.a = a;
+  e.b = b;
+  e.I = S.I[n];
+  e.spw = S.spw[n];
+  e.nwg = S.nwg[n];
+  e.tri = 0;
+}
+
+__device__ void set_gram_out(BDesc &e, const BState &S, int gd) {
+  e.out = S.partials;
+  e.ne = gd * gd;
+  e.G = S.G;
+}
+
+__device__ QrStepArgs qr_args(const BState &S, int pass, int d, int b, const double *Rc, double *Fstep, double *Rnext,
+                              double *Tdst, int f32pass, int contracted, int n) {
+  QrStepArgs q;
+  q.G = S.G;
+  q.d = d;
+  q.Tpost = nullptr;
+  q.tpr = q.tpc = 0;
+  q.tsr = q.tsc = 0;
+  q.cond_scale = 1.0;
+  q.ratio_out = (pass == 1) ? S.decf : nullptr;
+  q.pass = pass;
+  q.b = b;
+  q.Rc = Rc;
+  q.Fstep = Fstep;
+  q.Rnext = Rnext;
+  q.Tdst = Tdst;
+  q.dec = S.dec;
+  const double u = f32pass ? kU32 : kU64;
+  q.tau1 = S.f32 ? u / kTauMix : kTau1;
+  q.tau2 = kTau2;
+  q.ugram = u;
+  q.gerr = gram_err_dev(S.spw[n], contracted, u, S.nwg[n]);
+  q.try_chol = 1;
+  q.notrunc_check = 0;
+  q.delta_dev = nullptr;
+  q.first = 0;
+  q.tol2_nm1 = 0.0;
+  return q;
+}
+
+// One step of the plan for tensor t.  d / d2 receive the operands of the
+// streaming launch(es) that follow, qa / ta / ga those of the small kernels,
+// act[t] switches the one-workgroup-per-tensor kernels on.
+__global__ void kp_plan(BState *St, int count, int op, int n, BDesc *d, BDesc *d2, QrStepArgs *qa, TruncArgs *ta,
+                        SmallGemmArgs *ga, int *act) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  BState &S = St[t];
+  BDesc e, e2;
+  e.active = 0;
+  e2.active = 0;
+  int a_on = 0;
+  const int N = S.N;
+  switch (op) {
+    // ---- orthonormalization sweep, core n (N-1 .. 1) -----------------------
+    case S1_G1: {
+      S.done = 0;
+      S.passes = 0;
+      set_core(e, S, n, S.X[n], S.R[n], S.R[n + 1]);
+      if (n < N - 1) {
+        e.Q = S.T[n + 1];
+        e.q = S.k[n + 1];
+        e.sQr = 1;
+        e.sQc = S.R[n + 1];
+        e.tri = S.tri[n + 1];
+      } else {
+        e.Q = nullptr;
+        e.q = S.R[n + 1];
+        e.sQr = 1;
+        e.sQc = S.R[n + 1];
+      }
+      set_gram_out(e, S, S.R[n]);
+    } break;
+    case S1_Q1: {
+      const int zc = (n < N - 1) ? S.k[n + 1] : S.R[n + 1];
+      qa[t] = qr_args(S, 1, S.R[n], S.R[n], nullptr, S.B[n][0], S.Ra, S.T[n], S.f32, zc, n);
+      a_on = 1;
+    } break;
+    case S1_M1: {
+      S.passes = 1;
+      S.kcur = S.dec[0];
+      S.done = S.dec[1];
+      S.kappa2[n] = S.decf[0];
+      S.nst[n] = 1;
+      S.dim[n][0] = S.R[n];
+      S.dim[n][1] = S.kcur;
+      S.tri[n] = S.done ? S.dec[4] : 0;
+      if (!S.done) {
+        if (n < N - 1) {
+          set_core(e, S, n, S.X[n], S.R[n], S.R[n + 1]);
+          e.P = nullptr;
+          e.p = S.R[n];
+          e.sPr = 1;
+          e.sPa = S.R[n];
+          e.Q = S.T[n + 1];
+          e.q = S.k[n + 1];
+          e.sQr = 1;
+          e.sQc = S.R[n + 1];
+          e.out = S.matA;
+          S.src = S.matA;
+          S.sa = S.R[n];
+          S.sb = S.k[n + 1];
+        } else {
+          S.src = S.X[n];
+          S.sa = S.R[n];
+          S.sb = S.R[n + 1];
+        }
+      }
+    } break;
+    case S1_G2:
+    case S1_G3: {
+      if (!S.done) {
+        const int j = (op == S1_G2) ? 0 : 1;  // stage whose transpose is applied
+        const double *src = (op == S1_G2) ? S.src : S.matB;
+        const int sa = (op == S1_G2) ? S.sa : S.dim[n][1];
+        set_core(e, S, n, src, sa, S.sb);
+        e.Q = S.B[n][j];
+        e.q = S.dim[n][j + 1];
+        e.sQr = 1;
+        e.sQc = S.dim[n][j];
+        set_gram_out(e, S, e.q);
+      }
+    } break;
+    case S1_Q2:
+    case S1_Q3: {
+      if (!S.done) {
+        const int pass = (op == S1_Q2) ? 2 : 3;
+        const double *Rc = (pass == 2) ? S.Ra : S.Rb;
+        double *Rn = (pass == 2) ? S.Rb : S.Ra;
+        qa[t] = qr_args(S, pass, S.dim[n][pass - 1], S.R[n], Rc, S.B[n][pass - 1], Rn, S.T[n], 0, S.sb, n);
+        a_on = 1;
+      }
+    } break;
+    case S1_M2: {
+      if (!S.done) {
+        S.passes = 2;
+        S.kcur = S.dec[0];
+        S.done = S.dec[1];
+        S.nst[n] = 2;
+        S.dim[n][2] = S.kcur;
+        if (!S.done) {
+          // D = F_1^T C for the third pass
+          set_core(e, S, n, S.src, S.sa, S.sb);
+          e.P = S.B[n][0];
+          e.p = S.dim[n][1];
+          e.sPr = S.dim[n][0];
+          e.sPa = 1;
+          e.Q = nullptr;
+          e.q = S.sb;
+          e.sQr = 1;
+          e.sQc = S.sb;
+          e.out = S.matB;
+        }
+      }
+    } break;
+    case S1_END: {
+      if (!S.done && S.passes == 2) {
+        S.passes = 3;
+        S.kcur = S.dec[0];
+        if (!S.dec[1]) S.dec[2] |= 4;
+        S.nst[n] = 3;
+        S.dim[n][3] = S.kcur;
+      }
+      S.k[n] = S.kcur;
+    } break;
+    // ---- truncation sweep, core n (0 .. N-2) -------------------------------
+    case S2_P1: {
+      S.done = 0;
+      S.passes = 0;
+      S.tfold = (n >= 1 && S.nst[n] >= 2);
+      if (n == 0) {
+        S.Pcur = nullptr;
+        S.Lprev = 1;
+      }
+      if (S.tfold) {
+        // C_n = M_n T_{n+1}, bitwise as the orthonormalization sweep built it
+        set_core(e, S, n, S.X[n], S.R[n], S.R[n + 1]);
+        e.P = nullptr;
+        e.p = S.R[n];
+        e.sPr = 1;
+        e.sPa = S.R[n];
+        e.Q = S.T[n + 1];
+        e.q = S.k[n + 1];
+        e.sQr = 1;
+        e.sQc = S.R[n + 1];
+        e.out = S.matA;
+      }
+    } break;
+    case S2_P2: {
+      if (S.tfold && S.nst[n] == 3) {
+        set_core(e, S, n, S.matA, S.R[n], S.k[n + 1]);
+        e.P = S.B[n][0];
+        e.p = S.dim[n][1];
+        e.sPr = S.dim[n][0];
+        e.sPa = 1;
+        e.Q = nullptr;
+        e.q = S.k[n + 1];
+        e.sQr = 1;
+        e.sQc = S.k[n + 1];
+        e.out = S.matB;
+      }
+    } break;
+    case S2_P3: {
+      if (S.tfold) {
+        // C'_n = P F_j^T (...) on the materialized core: the transposed slice
+        // with Q1 = F_j and Q2 = P^T
+        const int j = S.nst[n] - 2;
+        const double *src = (j == 0) ? S.matA : S.matB;
+        double *dst = (j == 0) ? S.matB : S.matA;
+        set_core(e2, S, n, src, S.dim[n][j], S.k[n + 1]);
+        e2.Q = S.B[n][j];
+        e2.q = S.dim[n][j + 1];
+        e2.sQr = 1;
+        e2.sQc = S.dim[n][j];
+        e2.Q2 = S.Pcur;
+        e2.q2 = S.Lprev;
+        e2.s2r = S.Lprev;
+        e2.s2c = 1;
+        e2.out = dst;
+        S.csrc = dst;
+        S.ca = S.Lprev;
+        S.cb = S.k[n + 1];
+      }
+    } break;
+    case S2_G1: {
+      if (S.tfold) {
+        set_core(e, S, n, S.csrc, S.ca, S.cb);
+        e.P = nullptr;
+        e.p = S.ca;
+        e.sPr = 1;
+        e.sPa = S.ca;
+        set_gram_out(e, S, S.cb);
+      } else {
+        set_core(e, S, n, S.X[n], S.R[n], S.R[n + 1]);
+        e.P = (n > 0) ? S.Pcur : nullptr;
+        e.p = (n > 0) ? S.Lprev : S.R[n];
+        e.sPr = 1;
+        e.sPa = e.p;
+        set_gram_out(e, S, S.R[n + 1]);
+      }
+    } break;
+    case S2_Q1: {
+      const int b = S.k[n + 1];
+      const int zr = S.tfold ? S.ca : ((n > 0) ? S.Lprev : S.R[n]);
+      QrStepArgs q = qr_args(S, 1, b, b, nullptr, S.Gst[0], S.Ra, nullptr, S.f32, zr, n);
+      if (!S.tfold) {
+        q.Tpost = S.T[n + 1];
+        q.tpr = S.R[n + 1];
+        q.tpc = b;
+        q.tsr = 1;
+        q.tsc = S.R[n + 1];
+        // kappa(T)^2 when T is a one-pass factor; otherwise the one-pass test
+        // is switched off and the refinement passes settle the factorization
+        q.cond_scale = (S.nst[n + 1] == 1) ? S.kappa2[n + 1] : 1e300;
+      }
+      q.notrunc_check = 1;
+      q.delta_dev = S.scal + 1;
+      q.first = (n == 0);
+      q.tol2_nm1 = S.tol * S.tol / (double)(N - 1);
+      qa[t] = q;
+      a_on = 1;
+    } break;
+    case S2_M1: {
+      S.passes = 1;
+      S.kcur = S.dec[0];
+      S.done = S.dec[1];
+      S.notrunc = S.done ? S.dec[5] : 0;
+      S.gnst = 1;
+      S.gdim[0] = S.k[n + 1];
+      S.gdim[1] = S.kcur;
+      if (!S.done && !S.tfold) {
+        // C'_n = P M_n T_{n+1}
+        set_core(e, S, n, S.X[n], S.R[n], S.R[n + 1]);
+        e.P = (n > 0) ? S.Pcur : nullptr;
+        e.p = (n > 0) ? S.Lprev : S.R[n];
+        e.sPr = 1;
+        e.sPa = e.p;
+        e.Q = S.T[n + 1];
+        e.q = S.k[n + 1];
+        e.sQr = 1;
+        e.sQc = S.R[n + 1];
+        e.out = S.matA;
+        S.csrc = S.matA;
+        S.ca = e.p;
+        S.cb = S.k[n + 1];
+      }
+    } break;
+    case S2_G2:
+    case S2_G3: {
+      if (!S.done) {
+        const int j = (op == S2_G2) ? 0 : 1;
+        const double *src = (j == 0) ? S.csrc : S.ebuf;
+        set_core(e, S, n, src, S.ca, S.gdim[j]);
+        e.Q = S.Gst[j];
+        e.q = S.gdim[j + 1];
+        e.sQr = 1;
+        e.sQc = S.gdim[j];
+        set_gram_out(e, S, e.q);
+      }
+    } break;
+    case S2_Q2:
+    case S2_Q3: {
+      if (!S.done) {
+        const int pass = (op == S2_Q2) ? 2 : 3;
+        const double *Rc = (pass == 2) ? S.Ra : S.Rb;
+        double *Rn = (pass == 2) ? S.Rb : S.Ra;
+        qa[t] = qr_args(S, pass, S.gdim[pass - 1], S.k[n + 1], Rc, S.Gst[pass - 1], Rn, nullptr, 0, S.ca, n);
+        a_on = 1;
+      }
+    } break;
+    case S2_M2: {
+      if (!S.done) {
+        S.passes = 2;
+        S.kcur = S.dec[0];
+        S.done = S.dec[1];
+        S.gnst = 2;
+        S.gdim[2] = S.kcur;
+        if (!S.done) {
+          // E = C'_n G_1 for the third pass
+          set_core(e, S, n, S.csrc, S.ca, S.cb);
+          e.P = nullptr;
+          e.p = S.ca;
+          e.sPr = 1;
+          e.sPa = S.ca;
+          e.Q = S.Gst[0];
+          e.q = S.gdim[1];
+          e.sQr = 1;
+          e.sQc = S.cb;
+          S.ebuf = (S.csrc == S.matA) ? S.matB : S.matA;
+          e.out = S.ebuf;
+        }
+      }
+    } break;
+    case S2_TR: {
+      if (!S.done && S.passes == 2) {
+        S.passes = 3;
+        S.kcur = S.dec[0];
+        if (!S.dec[1]) S.dec[2] |= 4;
+        S.gnst = 3;
+        S.gdim[3] = S.kcur;
+      }
+      TruncArgs a;
+      a.R = (S.gnst == 2) ? S.Rb : S.Ra;
+      a.k = S.kcur;
+      a.b = S.k[n + 1];
+      a.Glast = S.Gst[S.gnst - 1];
+      a.d = S.gdim[S.gnst - 1];
+      const int fn = S.nst[n + 1] - 1;
+      a.Fn = S.B[n + 1][fn];
+      a.dn = S.dim[n + 1][fn];
+      a.GU = S.GU;
+      a.Pnext = S.P[n & 1];
+      a.delta = S.scal + 1;
+      a.norm = S.scal + 2;
+      a.first = (n == 0);
+      a.tol = S.tol;
+      a.Nm1 = N - 1;
+      a.sigma_out = S.sigma + (size_t)n * TTR_RMAX;
+      a.dec = S.dec;
+      a.r_orth = (S.gnst == 1 && !S.notrunc) ? 1 : 0;
+      a.identity = S.notrunc;
+      ta[t] = a;
+      a_on = 1;
+    } break;
+    case S2_O1: {
+      S.L[n + 1] = S.dec[3];
+      if (S.gnst == 1 && !S.tfold) {
+        SmallGemmArgs g;
+        g.A = S.T[n + 1];
+        g.B = S.GU;
+        g.C = S.Qm;
+        g.m = S.R[n + 1];
+        g.k = S.k[n + 1];
+        g.n = S.L[n + 1];
+        ga[t] = g;
+        a_on = 1;
+      }
+    } break;
+    case S2_O2: {
+      const int Ln = S.L[n + 1];
+      if (S.gnst == 1 && !S.tfold) {
+        set_core(e, S, n, S.X[n], S.R[n], S.R[n + 1]);
+        e.P = (n > 0) ? S.Pcur : nullptr;
+        e.p = (n > 0) ? S.Lprev : S.R[n];
+        e.sPr = 1;
+        e.sPa = e.p;
+        e.Q = S.Qm;
+        e.q = Ln;
+        e.sQr = 1;
+        e.sQc = S.R[n + 1];
+        e.out = S.Y[n];
+      } else if (S.gnst == 1) {
+        set_core(e, S, n, S.csrc, S.ca, S.cb);
+        e.P = nullptr;
+        e.p = S.ca;
+        e.sPr = 1;
+        e.sPa = S.ca;
+        e.Q = S.GU;
+        e.q = Ln;
+        e.sQr = 1;
+        e.sQc = S.cb;
+        e.out = S.Y[n];
+      } else {
+        const int j = S.gnst - 2;  // 0: C'_n with G_1, 1: E with G_2
+        set_core(e2, S, n, (j == 0) ? S.csrc : S.ebuf, S.ca, S.gdim[j]);
+        e2.Q = S.Gst[j];
+        e2.q = S.gdim[j + 1];
+        e2.sQr = 1;
+        e2.sQc = S.gdim[j];
+        e2.Q2 = S.GU;
+        e2.q2 = Ln;
+        e2.s2r = 1;
+        e2.s2c = S.gdim[j + 1];
+        e2.out = S.Y[n];
+      }
+      S.Pcur = S.P[n & 1];
+      S.Lprev = Ln;
+    } break;
+    // ---- last core -----------------------------------------------------------
+    case S3_P: {
+      if (S.nst[n] == 3) {
+        set_core(e, S, n, S.X[n], S.R[n], S.R[n + 1]);
+        e.P = S.B[n][0];
+        e.p = S.dim[n][1];
+        e.sPr = S.dim[n][0];
+        e.sPa = 1;
+        e.Q = nullptr;
+        e.q = S.R[n + 1];
+        e.sQr = 1;
+        e.sQc = S.R[n + 1];
+        e.out = S.matB;
+      }
+    } break;
+    case S3_O: {
+      const int ns = S.nst[n];
+      if (ns == 1) {
+        set_core(e, S, n, S.X[n], S.R[n], S.R[n + 1]);
+        e.P = S.Pcur;
+        e.p = S.Lprev;
+        e.sPr = 1;
+        e.sPa = S.Lprev;
+        e.Q = nullptr;
+        e.q = S.R[n + 1];
+        e.sQr = 1;
+        e.sQc = S.R[n + 1];
+        e.out = S.Y[n];
+      } else {
+        const int j = ns - 2;
+        set_core(e2, S, n, (j == 0) ? S.X[n] : S.matB, S.dim[n][j], S.R[n + 1]);
+        e2.Q = S.B[n][j];
+        e2.q = S.dim[n][j + 1];
+        e2.sQr = 1;
+        e2.sQc = S.dim[n][j];
+        e2.Q2 = S.Pcur;
+        e2.q2 = S.Lprev;
+        e2.s2r = S.Lprev;
+        e2.s2c = 1;
+        e2.out = S.Y[n];
+      }
+    } break;
+    case FIN: {
+      const int bad = S.dec[2] != 0;
+      S.ranks[0] = bad ? -1 : 1;
+      for (int l = 1; l < N; ++l) S.ranks[l] = S.L[l];
+      S.ranks[N] = 1;
+    } break;
+  }
+  d[t] = e;
+  d2[t] = e2;
+  act[t] = a_on;
+}
+
+__global__ void kp_init(BState *St, int count) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  BState &S = St[t];
+  for (int i = 0; i < 16; ++i) S.dec[i] = 0;
+  for (int i = 0; i < 8; ++i) S.decf[i] = 0.0;
+  for (int n = 0; n <= S.N; ++n) {
+    S.k[n] = S.R[n];
+    S.L[n] = 1;
+    S.kappa2[n] = -1.0;
+  }
+  for (int n = 0; n < S.N; ++n) {
+    S.nst[n] = 1;
+    S.tri[n] = 0;
+    for (int j = 0; j < 4; ++j) S.dim[n][j] = 0;
+  }
+  S.Pcur = nullptr;
+  S.Lprev = 1;
+  S.done = 0;
+  S.passes = 0;
+}
+
+// Fixed-order sum of each active tensor's partial Grams (as k_reduce).
+constexpr int kRedEnt = 16, kRedSeg = 16;
+__global__ __launch_bounds__(kRedEnt *kRedSeg) void kb_reduce(const BDesc *__restrict__ d) {
+  const BDesc &e = d[blockIdx.y];
+  if (!e.active) return;
+  const int ne = e.ne, nwg = e.nwg;
+  if ((int)blockIdx.x * kRedEnt >= ne) return;
+  __shared__ double part[kRedSeg][kRedEnt];
+  const int le = threadIdx.x % kRedEnt, seg = threadIdx.x / kRedEnt;
+  const int en = blockIdx.x * kRedEnt + le;
+  const int per = (nwg + kRedSeg - 1) / kRedSeg;
+  const int w0 = seg * per, w1 = min(nwg, w0 + per);
+  double s = 0.0;
+  if (en < ne)
+    for (int w = w0; w < w1; ++w) s += e.out[(long long)w * ne + en];
+  part[seg][le] = s;
+  __syncthreads();
+  if (seg == 0 && en < ne) {
+    double tt = 0.0;
+    for (int k = 0; k < kRedSeg; ++k) tt += part[k][le];
+    e.G[en] = tt;
+  }
+}
+
+}  // namespace
+
+void launch_reduce_batched(hipStream_t s, int count, const BDesc *d) {
+  hipLaunchKernelGGL(kb_reduce, dim3(TTR_RMAX * TTR_RMAX / kRedEnt, count), dim3(kRedEnt * kRedSeg), 0, s, d);
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+struct BatchPlan {
+  // signature of the batch this plan was built for
+  std::vector<long long> sig;
+  int count = 0, N = 0, prec = 0;
+  // device memory
+  void *mem = nullptr;
+  size_t mem_bytes = 0;
+  BState *St = nullptr;
+  BDesc *d = nullptr, *d2 = nullptr;
+  QrStepArgs *qa = nullptr;
+  TruncArgs *ta = nullptr;
+  SmallGemmArgs *ga = nullptr;
+  int *act = nullptr;
+  WGItem *items = nullptr;
+  // item lists per (tile class 1..4, core)
+  std::vector<int> off, cnt;  // index (c-1)*N + n
+  std::vector<int> classes;   // tile class of each tensor
+  // schedule
+  int spw_target = 64, grid_cap = 0;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int nodes = 0;
+  std::vector<double> tuned_ms;
+  std::vector<int> tuned_spw, tuned_grid;
+};
+
+namespace {
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+void free_plan(BatchPlan *p) {
+  if (!p) return;
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->cap) (void)hipStreamDestroy(p->cap);
+  if (p->mem) (void)hipFree(p->mem);
+  delete p;
+}
+
+struct Grid1 {
+  int nwg;
+  long long spw;
+};
+Grid1 grid_for_core(long long I, int target) {
+  long long nwg = (I + target - 1) / target;
+  nwg = std::max(1LL, std::min(nwg, (long long)TTR_MAXWG));
+  Grid1 g;
+  g.spw = std::max(1LL, (I + nwg - 1) / nwg);
+  g.nwg = (int)((I + g.spw - 1) / g.spw);
+  return g;
+}
+
+int tiles(int m) { return (m + 15) / 16; }
+
+// The launches of one plan step for core n.
+void heavy(BatchPlan *P, hipStream_t s, int op, int n) {
+  const int f32 = (P->prec == TTR_MIXED);
+  auto each_class = [&](auto &&fn) {
+    for (int c = 1; c <= 4; ++c) {
+      const int k = (c - 1) * P->N + n;
+      const int ni = P->cnt[k];
+      if (ni == 0) continue;
+      const int grid = P->grid_cap > 0 ? std::min(ni, P->grid_cap) : ni;
+      fn(c, P->items + P->off[k], ni, grid);
+    }
+  };
+  switch (op) {
+    case S1_G1:
+      each_class([&](int c, const WGItem *it, int ni, int g) {
+        launch_gram_right_factor_batched(s, c, f32, P->d, it, ni, g);
+      });
+      launch_reduce_batched(s, P->count, P->d);
+      break;
+    case S2_G1:
+      each_class([&](int c, const WGItem *it, int ni, int g) {
+        launch_gram_left_factor_batched(s, c, f32, P->d, it, ni, g);
+      });
+      launch_reduce_batched(s, P->count, P->d);
+      break;
+    case S1_G2:
+    case S1_G3:
+    case S2_G2:
+    case S2_G3: {
+      const int tr = (op == S1_G2 || op == S1_G3) ? 1 : 0;
+      each_class([&](int c, const WGItem *it, int ni, int g) { launch_gram_fac_batched(s, c, tr, P->d, it, ni, g); });
+      launch_reduce_batched(s, P->count, P->d);
+    } break;
+    case S1_Q1:
+    case S1_Q2:
+    case S1_Q3:
+    case S2_Q1:
+    case S2_Q2:
+    case S2_Q3:
+      launch_qr_step_batched(s, P->count, P->qa, P->act);
+      break;
+    case S1_M1:
+    case S1_M2:
+    case S2_P1:
+    case S2_P2:
+    case S2_M1:
+    case S2_M2:
+    case S3_P:
+      each_class([&](int c, const WGItem *it, int ni, int g) { launch_apply_mfma_batched(s, c, P->d, it, ni, g); });
+      break;
+    case S2_P3:
+      each_class([&](int c, const WGItem *it, int ni, int g) { launch_apply_fac2_batched(s, c, 1, P->d2, it, ni, g); });
+      break;
+    case S2_TR:
+      launch_trunc_step_batched(s, P->count, P->ta, P->act);
+      break;
+    case S2_O1:
+      launch_small_gemm_batched(s, P->count, P->ga, P->act);
+      break;
+    case S2_O2:
+    case S3_O: {
+      const int tr = (op == S3_O) ? 1 : 0;
+      each_class([&](int c, const WGItem *it, int ni, int g) { launch_apply_mfma_batched(s, c, P->d, it, ni, g); });
+      each_class([&](int c, const WGItem *it, int ni, int g) { launch_apply_fac2_batched(s, c, tr, P->d2, it, ni, g); });
+    } break;
+    default:
+      break;
+  }
+}
+
+void step(BatchPlan *P, hipStream_t s, int op, int n) {
+  const int threads = 64;
+  hipLaunchKernelGGL(kp_plan, dim3((P->count + threads - 1) / threads), dim3(threads), 0, s, P->St, P->count, op, n,
+                     P->d, P->d2, P->qa, P->ta, P->ga, P->act);
+  heavy(P, s, op, n);
+}
+
+// The whole rounding of the batch, enqueued on s.
+void enqueue(BatchPlan *P, hipStream_t s) {
+  const int N = P->N;
+  hipLaunchKernelGGL(kp_init, dim3((P->count + 63) / 64), dim3(64), 0, s, P->St, P->count);
+  for (int n = N - 1; n >= 1; --n)
+    for (int op = S1_G1; op <= S1_END; ++op) step(P, s, op, n);
+  for (int n = 0; n <= N - 2; ++n)
+    for (int op = S2_P1; op <= S2_O2; ++op) step(P, s, op, n);
+  step(P, s, S3_P, N - 1);
+  step(P, s, S3_O, N - 1);
+  step(P, s, FIN, N - 1);
+}
+
+// Item lists for a slices-per-workgroup target; also refreshes the static
+// per-core grid of every tensor in the state array (host copy in `st`).
+int build_items(BatchPlan *P, std::vector<BState> &st, int target) {
+  const int N = P->N;
+  std::vector<WGItem> items;
+  P->off.assign(4 * N, 0);
+  P->cnt.assign(4 * N, 0);
+  for (int t = 0; t < P->count; ++t)
+    for (int n = 0; n < N; ++n) {
+      const Grid1 g = grid_for_core(st[t].I[n], target);
+      st[t].spw[n] = g.spw;
+      st[t].nwg[n] = g.nwg;
+    }
+  for (int c = 1; c <= 4; ++c)
+    for (int n = 0; n < N; ++n) {
+      const int k = (c - 1) * N + n;
+      P->off[k] = (int)items.size();
+      for (int t = 0; t < P->count; ++t) {
+        if (P->classes[t] != c) continue;
+        for (int w = 0; w < st[t].nwg[n]; ++w) items.push_back({t, w});
+      }
+      P->cnt[k] = (int)items.size() - P->off[k];
+    }
+  TTR_HIPCHK(hipMemcpy(P->items, items.data(), items.size() * sizeof(WGItem), hipMemcpyHostToDevice));
+  TTR_HIPCHK(hipMemcpy(P->St, st.data(), st.size() * sizeof(BState), hipMemcpyHostToDevice));
+  return TTR_OK;
+}
+
+int capture(BatchPlan *P) {
+  if (P->exec) {
+    (void)hipGraphExecDestroy(P->exec);
+    P->exec = nullptr;
+  }
+  if (P->graph) {
+    (void)hipGraphDestroy(P->graph);
+    P->graph = nullptr;
+  }
+  TTR_HIPCHK(hipStreamBeginCapture(P->cap, hipStreamCaptureModeThreadLocal));
+  enqueue(P, P->cap);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(P->cap, &g);
+  if (e != hipSuccess) return ttr_fail(TTR_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+  P->graph = g;
+  size_t nn = 0;
+  TTR_HIPCHK(hipGraphGetNodes(g, nullptr, &nn));
+  P->nodes = (int)nn;
+  TTR_HIPCHK(hipGraphInstantiate(&P->exec, g, nullptr, nullptr, 0));
+  return TTR_OK;
+}
+
+// Times one replay of the captured graph (after one warm replay).
+int time_graph(BatchPlan *P, hipStream_t s, double *ms) {
+  hipEvent_t a, b;
+  TTR_HIPCHK(hipEventCreate(&a));
+  TTR_HIPCHK(hipEventCreate(&b));
+  TTR_HIPCHK(hipGraphLaunch(P->exec, s));
+  TTR_HIPCHK(hipEventRecord(a, s));
+  TTR_HIPCHK(hipGraphLaunch(P->exec, s));
+  TTR_HIPCHK(hipEventRecord(b, s));
+  TTR_HIPCHK(hipEventSynchronize(b));
+  float f = 0.f;
+  TTR_HIPCHK(hipEventElapsedTime(&f, a, b));
+  *ms = f;
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return TTR_OK;
+}
+
+}  // namespace
+
+void ttr_batch_release(ttr_handle *h) {
+  if (!h) return;
+  free_plan(h->plan);
+  h->plan = nullptr;
+}
+
+extern "C" {
+
+int ttr_round_batched(ttr_handle *h, int count, const ttr_tt *X, const double *tol, int direction, int prec,
+                      ttr_tt *Y, int64_t *ranks_dev, int tune) {
+  if (!h) return ttr_fail(TTR_ERR_INVALID_ARG, "handle is NULL");
+  TTR_HIPCHK(hipSetDevice(h->device));
+  if (count < 1) return ttr_fail(TTR_ERR_INVALID_ARG, "count must be >= 1");
+  if (!X || !Y || !tol || !ranks_dev) return ttr_fail(TTR_ERR_INVALID_ARG, "NULL argument");
+  if (direction != TTR_RLR) return ttr_fail(TTR_ERR_UNSUPPORTED, "batched rounding supports TTR_RLR");
+  if (prec != TTR_FP64 && prec != TTR_MIXED) return ttr_fail(TTR_ERR_INVALID_ARG, "unknown precision");
+  const int N = X[0].N;
+  if (N < 2 || N > kBMaxN) return ttr_fail(TTR_ERR_INVALID_ARG, "batched rounding needs 2 <= N <= 16");
+  // validate and build the signature
+  std::vector<long long> sig;
+  sig.push_back(count);
+  sig.push_back(N);
+  sig.push_back(prec);
+  sig.push_back((long long)(intptr_t)ranks_dev);
+  for (int t = 0; t < count; ++t) {
+    const ttr_tt &x = X[t], &y = Y[t];
+    if (x.N != N || y.N != N) return ttr_fail(TTR_ERR_SHAPE, "all tensors of a batch need the same N");
+    if (!x.I || !x.R || !x.core || !y.I || !y.R || !y.core || !y.cap)
+      return ttr_fail(TTR_ERR_INVALID_ARG, "NULL array in a batch member");
+    if (!(tol[t] >= 0.0) || !std::isfinite(tol[t])) return ttr_fail(TTR_ERR_INVALID_ARG, "tol must be finite and >= 0");
+    if (x.R[0] != 1 || x.R[N] != 1) return ttr_fail(TTR_ERR_INVALID_ARG, "boundary ranks must be 1");
+    for (int n = 0; n < N; ++n) {
+      if (x.I[n] <= 0 || x.R[n + 1] <= 0) return ttr_fail(TTR_ERR_INVALID_ARG, "sizes and ranks must be > 0");
+      if (x.R[n] > TTR_MAX_RANK || x.R[n + 1] > TTR_MAX_RANK)
+        return ttr_fail(TTR_ERR_UNSUPPORTED, "rank above TTR_MAX_RANK");
+      if (y.I[n] != x.I[n]) return ttr_fail(TTR_ERR_SHAPE, "output mode sizes differ");
+      if (!x.core[n] || !y.core[n]) return ttr_fail(TTR_ERR_INVALID_ARG, "NULL core pointer");
+      if (y.core[n] == x.core[n]) return ttr_fail(TTR_ERR_INVALID_ARG, "Y aliases X");
+      if (y.cap[n] < x.R[n] * x.I[n] * x.R[n + 1]) return ttr_fail(TTR_ERR_CAPACITY, "Y core capacity too small");
+      sig.push_back(x.I[n]);
+      sig.push_back(x.R[n + 1]);
+      sig.push_back((long long)(intptr_t)x.core[n]);
+      sig.push_back((long long)(intptr_t)y.core[n]);
+    }
+    long long tb;
+    std::memcpy(&tb, &tol[t], sizeof tb);
+    sig.push_back(tb);
+  }
+  BatchPlan *P = h->plan;
+  if (!P || P->sig != sig) {
+    free_plan(P);
+    h->plan = nullptr;
+    P = new BatchPlan();
+    h->plan = P;
+    P->count = count;
+    P->N = N;
+    P->prec = prec;
+    // per-tensor workspace layout (doubles)
+    const size_t slot = (size_t)TTR_RMAX * TTR_RMAX;
+    std::vector<size_t> tws(count), tmat(count);
+    std::vector<int> maxnwg(count);
+    size_t total = 0, max_items = 0;
+    P->classes.resize(count);
+    for (int t = 0; t < count; ++t) {
+      size_t mc = 0;
+      int mr = 1, mw = 1;
+      for (int n = 0; n < N; ++n) {
+        mc = std::max(mc, (size_t)(X[t].R[n] * X[t].I[n] * X[t].R[n + 1]));
+        mr = std::max(mr, (int)std::max(X[t].R[n], X[t].R[n + 1]));
+        mw = std::max(mw, grid_for_core(X[t].I[n], 16).nwg);  // the smallest target bounds the partials
+        max_items += (size_t)grid_for_core(X[t].I[n], 16).nwg;
+      }
+      P->classes[t] = std::min(4, tiles(mr));
+      maxnwg[t] = mw;
+      tmat[t] = align_up(mc);
+      tws[t] = align_up((size_t)mw * slot) + 11 * slot + 64 + (size_t)(N + 1) * TTR_RMAX + (size_t)(N + 1) * slot +
+               (size_t)3 * N * slot + 2 * tmat[t];
+      tws[t] = align_up(tws[t]);
+      total += tws[t];
+    }
+    const size_t hdr = align_up(count * sizeof(BState)) + 2 * align_up(count * sizeof(BDesc)) +
+                       align_up(count * sizeof(QrStepArgs)) + align_up(count * sizeof(TruncArgs)) +
+                       align_up(count * sizeof(SmallGemmArgs)) + align_up(count * sizeof(int)) +
+                       align_up(max_items * sizeof(WGItem)) + align_up((size_t)count * 24 * sizeof(int)) +
+                       align_up((size_t)count * 8 * sizeof(double));
+    P->mem_bytes = hdr + total * sizeof(double);
+    if (hipMalloc(&P->mem, P->mem_bytes) != hipSuccess) {
+      P->mem = nullptr;
+      ttr_batch_release(h);
+      return ttr_fail(TTR_ERR_ALLOC, "batched workspace allocation of " + std::to_string(P->mem_bytes) + " bytes failed");
+    }
+    char *c = (char *)P->mem;
+    P->St = (BState *)c; c += align_up(count * sizeof(BState));
+    P->d = (BDesc *)c; c += align_up(count * sizeof(BDesc));
+    P->d2 = (BDesc *)c; c += align_up(count * sizeof(BDesc));
+    P->qa = (QrStepArgs *)c; c += align_up(count * sizeof(QrStepArgs));
+    P->ta = (TruncArgs *)c; c += align_up(count * sizeof(TruncArgs));
+    P->ga = (SmallGemmArgs *)c; c += align_up(count * sizeof(SmallGemmArgs));
+    P->act = (int *)c; c += align_up(count * sizeof(int));
+    P->items = (WGItem *)c; c += align_up(max_items * sizeof(WGItem));
+    int *decs = (int *)c; c += align_up((size_t)count * 24 * sizeof(int));
+    double *decfs = (double *)c; c += align_up((size_t)count * 8 * sizeof(double));
+    double *w = (double *)c;
+    std::vector<BState> st(count);
+    for (int t = 0; t < count; ++t) {
+      BState &S = st[t];
+      std::memset(&S, 0, sizeof S);
+      S.N = N;
+      S.f32 = (prec == TTR_MIXED);
+      S.tol = tol[t];
+      for (int n = 0; n < N; ++n) {
+        S.I[n] = X[t].I[n];
+        S.X[n] = X[t].core[n];
+        S.Y[n] = Y[t].core[n];
+      }
+      for (int n = 0; n <= N; ++n) S.R[n] = (int)X[t].R[n];
+      double *p = w;
+      S.partials = p; p += align_up((size_t)maxnwg[t] * slot);
+      S.G = p; p += slot;
+      S.Ra = p; p += slot;
+      S.Rb = p; p += slot;
+      for (int j = 0; j < 3; ++j) { S.Gst[j] = p; p += slot; }
+      for (int j = 0; j < 2; ++j) { S.P[j] = p; p += slot; }
+      S.GU = p; p += slot;
+      S.Qm = p; p += slot;
+      S.scal = p; p += 64;
+      S.sigma = p; p += (size_t)(N + 1) * TTR_RMAX;
+      for (int n = 0; n <= N; ++n) { S.T[n] = p; p += slot; }
+      for (int n = 0; n < N; ++n)
+        for (int j = 0; j < 3; ++j) { S.B[n][j] = p; p += slot; }
+      S.matA = p; p += tmat[t];
+      S.matB = p; p += tmat[t];
+      S.dec = decs + (size_t)t * 24;
+      S.decf = decfs + (size_t)t * 8;
+      S.ranks = ranks_dev + (size_t)t * (N + 1);
+      w += tws[t];
+    }
+    TTR_HIPCHK(hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking));
+    // autotuner: slices per workgroup x grid cap, each candidate captured and
+    // its graph replay timed on the batch itself
+    const int spws[] = {32, 64, 128, 256};
+    const int caps[] = {0, 2048};
+    double best = 1e300;
+    int bspw = 64, bcap = 0;
+    if (tune) {
+      for (int sp : spws)
+        for (int cp : caps) {
+          P->grid_cap = cp;
+          int rc = build_items(P, st, sp);
+          if (rc) return rc;
+          if ((rc = capture(P))) return rc;
+          double ms = 0.0;
+          if ((rc = time_graph(P, h->stream, &ms))) return rc;
+          P->tuned_ms.push_back(ms);
+          P->tuned_spw.push_back(sp);
+          P->tuned_grid.push_back(cp);
+          if (ms < best) {
+            best = ms;
+            bspw = sp;
+            bcap = cp;
+          }
+        }
+    }
+    P->spw_target = bspw;
+    P->grid_cap = bcap;
+    int rc = build_items(P, st, bspw);
+    if (rc) return rc;
+    if ((rc = capture(P))) return rc;
+    P->sig = sig;  // only a complete plan is reused
+  }
+  TTR_HIPCHK(hipGraphLaunch(P->exec, h->stream));
+  return TTR_OK;
+}
+
+int ttr_get_batch_plan(const ttr_handle *h, ttr_batch_plan *out) {
+  if (!h || !out) return ttr_fail(TTR_ERR_INVALID_ARG, "NULL argument");
+  std::memset(out, 0, sizeof *out);
+  const BatchPlan *P = h->plan;
+  if (!P) return TTR_OK;
+  out->count = P->count;
+  out->spw_target = P->spw_target;
+  out->grid_cap = P->grid_cap;
+  out->graph_nodes = P->nodes;
+  out->workspace_bytes = (int64_t)P->mem_bytes;
+  const int nc = std::min<int>((int)P->tuned_ms.size(), 16);
+  out->candidates = nc;
+  for (int i = 0; i < nc; ++i) {
+    out->cand_spw[i] = P->tuned_spw[i];
+    out->cand_grid[i] = P->tuned_grid[i];
+    out->cand_ms[i] = P->tuned_ms[i];
+  }
+  return TTR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,47 @@
+// Host-side definitions shared by the C ABI (ttr_api.hip) and the batched
+// rounding (ttr_batch.hip).
+#pragma once
+
+#include "../../include/ttr.h"
+#include "ttr_internal.h"
+
+#include <string>
+#include <vector>
+
+struct BatchPlan;  // ttr_batch.hip
+
+struct ttr_handle {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  double *ws = nullptr;
+  size_t ws_bytes = 0;
+  int *dec_host = nullptr;  // pinned
+  int *dec_dev = nullptr;
+  double *decf_host = nullptr;  // pinned: per-step doubles (conditioning ratio)
+  double *decf_dev = nullptr;
+  double *scal_host = nullptr;  // pinned scalars
+  ttr_round_stats stats;
+  // opt-in kernel timing
+  struct Pending {
+    hipEvent_t a, b;
+    int cls;
+    double bytes, flops;
+  };
+  int profiling = 0;
+  std::vector<hipEvent_t> evpool;
+  std::vector<Pending> pending;
+  ttr_profile prof;
+  // batched rounding: the cached plan (workspace, item lists, captured graph)
+  BatchPlan *plan = nullptr;
+};
+
+// Records `msg` for ttr_last_error() and returns `code`.
+int ttr_fail(int code, const std::string &msg);
+// Frees the batched plan of a handle (ttr_destroy).
+void ttr_batch_release(ttr_handle *h);
+
+#define TTR_HIPCHK(expr)                                                                              \
+  do {                                                                                                \
+    hipError_t e_ = (expr);                                                                           \
+    if (e_ != hipSuccess) return ttr_fail(TTR_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)

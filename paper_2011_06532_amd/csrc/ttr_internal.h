@@ -151,5 +151,57 @@ void launch_trunc_step(hipStream_t s, const TruncArgs &a);
 
 // Utility: C (m x n, ld m) = A (m x k, ld m) * B (k x n, ld k); one workgroup.
 void launch_small_gemm(hipStream_t s, const double *A, const double *B, double *C, int m, int k, int n);
+// --- batched streaming launches ---------------------------------------------
+// One TT's operands for a batched streaming launch, written on the device by
+// the batched planner (ttr_batch.hip).  Fields unused by a kernel are ignored.
+struct BDesc {
+  int active;
+  int a, b;               // physical slice dims of X
+  long long I, spw;       // slices, slices per workgroup
+  int nwg;                // workgroups of this TT (= ceil(I / spw))
+  int tri;                // first factor triangular (see the single launchers)
+  const double *X;
+  const double *P;        // left factor (output pass)
+  int p;
+  long long sPr, sPa;
+  const double *Q;        // (first) right factor
+  int q;
+  long long sQr, sQc;
+  const double *Q2;       // second right factor (two-factor output pass)
+  int q2;
+  long long s2r, s2c;
+  double *out;            // Gram partials (nwg x ne) or the output core
+  int ne;                 // Gram entries (reduce)
+  double *G;              // reduce target
+};
+struct WGItem {
+  int tt, wg;
+};
+// The items of one tile class (NT) and one core: workgroup `blockIdx.x` walks
+// items blockIdx.x, blockIdx.x + gridDim.x, ... (persistent when the grid is
+// smaller than the item count).  f32 / trans select the variants as in the
+// single launchers.
+void launch_gram_right_factor_batched(hipStream_t s, int nt, int f32, const BDesc *d, const WGItem *items, int nitems,
+                                      int grid);
+void launch_gram_left_factor_batched(hipStream_t s, int nt, int f32, const BDesc *d, const WGItem *items, int nitems,
+                                     int grid);
+void launch_apply_mfma_batched(hipStream_t s, int nt, const BDesc *d, const WGItem *items, int nitems, int grid);
+void launch_gram_fac_batched(hipStream_t s, int nt, int trans, const BDesc *d, const WGItem *items, int nitems,
+                             int grid);
+void launch_apply_fac2_batched(hipStream_t s, int nt, int trans, const BDesc *d, const WGItem *items, int nitems,
+                               int grid);
+// Sum of each active TT's partials (d[t].out, d[t].nwg x d[t].ne) into d[t].G.
+void launch_reduce_batched(hipStream_t s, int count, const BDesc *d);
+
+// Batched forms (one workgroup per item, skipped where active[item] == 0);
+// the argument arrays live in device memory.
+struct SmallGemmArgs {
+  const double *A, *B;
+  double *C;
+  int m, k, n;
+};
+void launch_qr_step_batched(hipStream_t s, int count, const QrStepArgs *args, const int *active);
+void launch_trunc_step_batched(hipStream_t s, int count, const TruncArgs *args, const int *active);
+void launch_small_gemm_batched(hipStream_t s, int count, const SmallGemmArgs *args, const int *active);
 // Square root of a 1x1 device value into out (for norms).
 void launch_sqrt_scalar(hipStream_t s, const double *in, double *out);

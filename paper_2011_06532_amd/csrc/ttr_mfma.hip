@@ -145,7 +145,7 @@ __device__ inline void load_slice(const double *__restrict__ Xi, long long col, 
 // first pass (slices and Q rounded to FP32, FP32 accumulation per wave).
 // ---------------------------------------------------------------------------
 template <int NT, int KS, class A>
-__global__ __launch_bounds__(kThreads) void k_gram_right_factor(const double *__restrict__ X, int a, int b, long long I,
+__device__ __forceinline__ void gram_right_factor_body(const int wg, const double *__restrict__ X, int a, int b, long long I,
                                                                 const double *__restrict__ Q, int q, long long sQr,
                                                                 long long sQc, int tri, long long spw,
                                                                 double *__restrict__ partials) {
@@ -163,7 +163,7 @@ __global__ __launch_bounds__(kThreads) void k_gram_right_factor(const double *__
   for (int u = 0; u < NT; ++u)
 #pragma unroll
     for (int v = 0; v < NT; ++v) G[u][v] = V{0, 0, 0, 0};
-  const long long beg = (long long)blockIdx.x * spw;
+  const long long beg = (long long)wg * spw;
   const long long end = std::min(beg + spw, I);
   const long long col = (long long)a * I;
   // register prefetch of the next slice, except where it would spill (FP64,
@@ -215,7 +215,15 @@ __global__ __launch_bounds__(kThreads) void k_gram_right_factor(const double *__
         for (int t = 0; t < NT; ++t) cur[ks][t] = (T)nxt[ks][t];
     }
   }
-  reduce_gram<NT, A>(G, NT, a, Gs, partials + (long long)blockIdx.x * a * a);
+  reduce_gram<NT, A>(G, NT, a, Gs, partials + (long long)wg * a * a);
+}
+
+template <int NT, int KS, class A>
+__global__ __launch_bounds__(kThreads) void k_gram_right_factor(const double *__restrict__ X, int a, int b, long long I,
+                                                                const double *__restrict__ Q, int q, long long sQr,
+                                                                long long sQc, int tri, long long spw,
+                                                                double *__restrict__ partials) {
+  gram_right_factor_body<NT, KS, A>(blockIdx.x, X, a, b, I, Q, q, sQr, sQc, tri, spw, partials);
 }
 
 // ---------------------------------------------------------------------------
@@ -224,16 +232,29 @@ __global__ __launch_bounds__(kThreads) void k_gram_right_factor(const double *__
 // KS = k-steps over a (ceil(a/4)).
 // ---------------------------------------------------------------------------
 template <int NT, int KS, class A>
-__global__ __launch_bounds__(kThreads) void k_gram_left_factor(const double *__restrict__ X, int a, int b, long long I,
+__device__ __forceinline__ void gram_left_factor_body(const int wg, const double *__restrict__ X, int a, int b, long long I,
                                                                const double *__restrict__ P, int p, long long sPr,
                                                                long long sPa, int tri, long long spw,
                                                                double *__restrict__ partials) {
   using T = typename A::T;
   using V = typename A::V;
+  // The product contracts over alpha, which the operand layout puts on the
+  // slow lane index; read directly, every load would touch 16 columns.  So
+  // slices are read coalesced (16 consecutive alpha per lane group) and turned
+  // through a per-wave LDS tile (STAGE).  FP64 at NT = 4 does not fit in LDS
+  // and reads the operand layout directly.
+  constexpr bool STAGE = (NT <= 3) || sizeof(T) == 4;
+  constexpr int KB = 4 * NT;                     // k-steps of 4 columns covering b
+  constexpr int LDT = NT * 16 + 1;               // staging tile leading dimension
+  constexpr int TILE = LDT * NT * 16;            // staging tile per wave (elements of T)
+  constexpr int GS_BYTES = NT * 16 * NT * 16 * 8;
+  constexpr int ST_BYTES = STAGE ? kWaves * TILE * (int)sizeof(T) : 0;
   __shared__ T frag[NT * KS * 64];
-  __shared__ double Gs[NT * 16 * NT * 16];
+  __shared__ __align__(16) char smem[GS_BYTES > ST_BYTES ? GS_BYTES : ST_BYTES];
+  double *Gs = reinterpret_cast<double *>(smem);  // after the slice loop only
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, j = lane & 15;
+  T *Ls = reinterpret_cast<T *>(smem) + (STAGE ? wave * TILE : 0);
   build_afrag<T>(frag, P, p, a, sPr, sPa, NT, KS);
   __syncthreads();
   V G[NT][NT];
@@ -241,21 +262,32 @@ __global__ __launch_bounds__(kThreads) void k_gram_left_factor(const double *__r
   for (int u = 0; u < NT; ++u)
 #pragma unroll
     for (int v = 0; v < NT; ++v) G[u][v] = V{0, 0, 0, 0};
-  const long long beg = (long long)blockIdx.x * spw;
+  const long long beg = (long long)wg * spw;
   const long long end = std::min(beg + spw, I);
   const long long col = (long long)a * I;
-  // register prefetch of the next slice, except where it would spill (FP64,
-  // NT = 4).  The prefetch holds the raw FP64 loads; FP32 rounding happens when
-  // the slice becomes current, so the loads stay in flight across the products.
-  constexpr bool PF = (NT <= 3) || sizeof(T) == 4;
-  T cur[KS][NT];
-  double nxt[KS][NT];  // used only with PF
+  T cur[KS][NT];  // cur[ks][t] = M(4 ks + g, 16 t + j)
+  // STAGE: raw coalesced loads of the next slice, nx[kb][ta] = M(16 ta + j, 4 kb + g),
+  // kept in flight across the products
+  double nx[STAGE ? KB : 1][NT];
   long long i = beg + wave;
-  if constexpr (PF)
-    if (i < end) load_slice<NT, KS, false, T>(X + (long long)a * i, col, a, b, g, j, cur);
+  if constexpr (STAGE)
+    if (i < end) load_slice<NT, KB, true>(X + (long long)a * i, col, a, b, g, j, nx);
   for (; i < end; i += kWaves) {
-    if constexpr (PF) {
-      if (i + kWaves < end) load_slice<NT, KS, false>(X + (long long)a * (i + kWaves), col, a, b, g, j, nxt);
+    if constexpr (STAGE) {
+      // nx -> LDS (alpha + LDT beta) -> cur; one wave owns the tile and its LDS
+      // operations complete in order
+      __asm__ volatile("" ::: "memory");
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+        for (int ta = 0; ta < NT; ++ta) Ls[(16 * ta + j) + LDT * (4 * kb + g)] = (T)nx[kb][ta];
+      __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) cur[ks][t] = Ls[(4 * ks + g) + LDT * (16 * t + j)];
+      __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+      if (i + kWaves < end) load_slice<NT, KB, true>(X + (long long)a * (i + kWaves), col, a, b, g, j, nx);
     } else {
       load_slice<NT, KS, false, T>(X + (long long)a * i, col, a, b, g, j, cur);
     }
@@ -285,14 +317,17 @@ __global__ __launch_bounds__(kThreads) void k_gram_left_factor(const double *__r
 #pragma unroll
           for (int v = 0; v <= u; ++v) G[u][v] = A::mma(y[rb][u][r], y[rb][v][r], G[u][v]);
       }
-    if constexpr (PF) {
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-        for (int t = 0; t < NT; ++t) cur[ks][t] = (T)nxt[ks][t];
-    }
   }
-  reduce_gram<NT, A>(G, NT, b, Gs, partials + (long long)blockIdx.x * b * b);
+  __syncthreads();  // every wave is done with its staging tile before Gs reuses it
+  reduce_gram<NT, A>(G, NT, b, Gs, partials + (long long)wg * b * b);
+}
+
+template <int NT, int KS, class A>
+__global__ __launch_bounds__(kThreads) void k_gram_left_factor(const double *__restrict__ X, int a, int b, long long I,
+                                                               const double *__restrict__ P, int p, long long sPr,
+                                                               long long sPa, int tri, long long spw,
+                                                               double *__restrict__ partials) {
+  gram_left_factor_body<NT, KS, A>(blockIdx.x, X, a, b, I, P, p, sPr, sPa, tri, spw, partials);
 }
 
 // ---------------------------------------------------------------------------
@@ -302,8 +337,7 @@ __global__ __launch_bounds__(kThreads) void k_gram_left_factor(const double *__r
 // loads and stores overlap the other's matrix-core work.
 // ---------------------------------------------------------------------------
 template <int NT, int KS>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NT <= 3 ? 2 : 1, NT <= 3 ? 2 : 1)))
-void k_apply_mfma(const double *__restrict__ X, int a, int b, long long I, const double *__restrict__ P, int p,
+__device__ __forceinline__ void apply_mfma_body(const int wg, const double *__restrict__ X, int a, int b, long long I, const double *__restrict__ P, int p,
                   long long sPr, long long sPa, const double *__restrict__ Q, int q, long long sQr, long long sQc,
                   long long spw, double *__restrict__ Y) {
   constexpr int KA = NT * 4;  // k-steps over alpha (whole tiles)
@@ -315,7 +349,7 @@ void k_apply_mfma(const double *__restrict__ X, int a, int b, long long I, const
   build_bfrag(fragQ, Q, b, q, sQr, sQc, NT, KS);
   if (hasP) build_afrag(fragP, P, p, a, sPr, sPa, NT, KA);
   __syncthreads();
-  const long long beg = (long long)blockIdx.x * spw;
+  const long long beg = (long long)wg * spw;
   const long long end = std::min(beg + spw, I);
   const long long col = (long long)a * I;
   const long long ocol = (long long)p * I;
@@ -381,6 +415,13 @@ void k_apply_mfma(const double *__restrict__ X, int a, int b, long long I, const
   }
 }
 
+template <int NT, int KS>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NT <= 3 ? 2 : 1, NT <= 3 ? 2 : 1))) void k_apply_mfma(const double *__restrict__ X, int a, int b, long long I, const double *__restrict__ P, int p,
+                  long long sPr, long long sPa, const double *__restrict__ Q, int q, long long sQr, long long sQc,
+                  long long spw, double *__restrict__ Y) {
+  apply_mfma_body<NT, KS>(blockIdx.x, X, a, b, I, P, p, sPr, sPa, Q, q, sQr, sQc, spw, Y);
+}
+
 // ---------------------------------------------------------------------------
 // Refinement passes on a materialized core (truncation sweep, §2.4, when the
 // first Gram pass could not settle the factorization).  The slice seen is
@@ -395,7 +436,7 @@ void k_apply_mfma(const double *__restrict__ X, int a, int b, long long I, const
 // orthonormality the Gram pass measured.
 // ---------------------------------------------------------------------------
 template <int NT, int KS, bool TR>
-__global__ __launch_bounds__(kThreads) void k_gram_fac(const double *__restrict__ X, int a, int b, long long I,
+__device__ __forceinline__ void gram_fac_body(const int wg, const double *__restrict__ X, int a, int b, long long I,
                                                        const double *__restrict__ Q, int q, long long sQr,
                                                        long long sQc, int tri, long long spw,
                                                        double *__restrict__ partials) {
@@ -412,7 +453,7 @@ __global__ __launch_bounds__(kThreads) void k_gram_fac(const double *__restrict_
   for (int u = 0; u < NT; ++u)
 #pragma unroll
     for (int v = 0; v < NT; ++v) G[u][v] = d4{0.0, 0.0, 0.0, 0.0};
-  const long long beg = (long long)blockIdx.x * spw;
+  const long long beg = (long long)wg * spw;
   const long long end = std::min(beg + spw, I);
   const long long col = (long long)a * I;
   // cur[ks][t] = S(16t + j, 4ks + g)
@@ -460,11 +501,19 @@ __global__ __launch_bounds__(kThreads) void k_gram_fac(const double *__restrict_
         for (int t = 0; t < NT; ++t) cur[ks][t] = nxt[ks][t];
     }
   }
-  reduce_gram<NT, F64>(G, NT, q, Gs, partials + (long long)blockIdx.x * q * q);
+  reduce_gram<NT, F64>(G, NT, q, Gs, partials + (long long)wg * q * q);
 }
 
 template <int NT, int KS, bool TR>
-__global__ __launch_bounds__(kThreads) void k_apply_fac2(const double *__restrict__ X, int a, int b, long long I,
+__global__ __launch_bounds__(kThreads) void k_gram_fac(const double *__restrict__ X, int a, int b, long long I,
+                                                       const double *__restrict__ Q, int q, long long sQr,
+                                                       long long sQc, int tri, long long spw,
+                                                       double *__restrict__ partials) {
+  gram_fac_body<NT, KS, TR>(blockIdx.x, X, a, b, I, Q, q, sQr, sQc, tri, spw, partials);
+}
+
+template <int NT, int KS, bool TR>
+__device__ __forceinline__ void apply_fac2_body(const int wg, const double *__restrict__ X, int a, int b, long long I,
                                                          const double *__restrict__ Q1, int q1, long long s1r,
                                                          long long s1c, int tri, const double *__restrict__ Q2,
                                                          int q2, long long s2r, long long s2c, long long spw,
@@ -480,7 +529,7 @@ __global__ __launch_bounds__(kThreads) void k_apply_fac2(const double *__restric
   build_afrag(frag1, Q1, q1, sb, s1c, s1r, NT, KS);
   build_afrag(frag2, Q2, q2, q1, s2c, s2r, NT, KC);
   __syncthreads();
-  const long long beg = (long long)blockIdx.x * spw;
+  const long long beg = (long long)wg * spw;
   const long long end = std::min(beg + spw, I);
   const long long col = (long long)a * I;
   // output addressing: element (s, c2) of slice i
@@ -548,6 +597,59 @@ __global__ __launch_bounds__(kThreads) void k_apply_fac2(const double *__restric
         for (int t = 0; t < NT; ++t) cur[ks][t] = nxt[ks][t];
     }
   }
+}
+
+template <int NT, int KS, bool TR>
+__global__ __launch_bounds__(kThreads) void k_apply_fac2(const double *__restrict__ X, int a, int b, long long I,
+                                                         const double *__restrict__ Q1, int q1, long long s1r,
+                                                         long long s1c, int tri, const double *__restrict__ Q2,
+                                                         int q2, long long s2r, long long s2c, long long spw,
+                                                         double *__restrict__ Y) {
+  apply_fac2_body<NT, KS, TR>(blockIdx.x, X, a, b, I, Q1, q1, s1r, s1c, tri, Q2, q2, s2r, s2c, spw, Y);
+}
+
+// ---------------------------------------------------------------------------
+// Batched forms: the same bodies over a list of (TT, workgroup) items, with
+// each TT's operands in a device descriptor.  KS = 4 NT covers every
+// contracted dimension of the tile class (padding k-steps are zero).
+// ---------------------------------------------------------------------------
+#define TTR_ITEMS_LOOP(BODY)                                                   \
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {                    \
+    const WGItem w = items[it];                                                \
+    const BDesc &e = d[w.tt];                                                  \
+    if (e.active && w.wg < e.nwg) { BODY; }                                    \
+    __syncthreads();                                                           \
+  }
+
+template <int NT, class A>
+__global__ __launch_bounds__(kThreads) void kb_gram_right_factor(const BDesc *__restrict__ d,
+                                                                 const WGItem *__restrict__ items, int nitems) {
+  TTR_ITEMS_LOOP((gram_right_factor_body<NT, 4 * NT, A>(w.wg, e.X, e.a, e.b, e.I, e.Q, e.q, e.sQr, e.sQc, e.tri,
+                                                        e.spw, e.out)))
+}
+template <int NT, class A>
+__global__ __launch_bounds__(kThreads) void kb_gram_left_factor(const BDesc *__restrict__ d,
+                                                                const WGItem *__restrict__ items, int nitems) {
+  TTR_ITEMS_LOOP((gram_left_factor_body<NT, 4 * NT, A>(w.wg, e.X, e.a, e.b, e.I, e.P, e.p, e.sPr, e.sPa, e.tri,
+                                                       e.spw, e.out)))
+}
+template <int NT>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NT <= 2 ? 2 : 1, NT <= 2 ? 2 : 1)))
+void kb_apply_mfma(const BDesc *__restrict__ d, const WGItem *__restrict__ items, int nitems) {
+  TTR_ITEMS_LOOP((apply_mfma_body<NT, 4 * NT>(w.wg, e.X, e.a, e.b, e.I, e.P, e.p, e.sPr, e.sPa, e.Q, e.q, e.sQr,
+                                              e.sQc, e.spw, e.out)))
+}
+template <int NT, bool TR>
+__global__ __launch_bounds__(kThreads) void kb_gram_fac(const BDesc *__restrict__ d, const WGItem *__restrict__ items,
+                                                        int nitems) {
+  TTR_ITEMS_LOOP((gram_fac_body<NT, 4 * NT, TR>(w.wg, e.X, e.a, e.b, e.I, e.Q, e.q, e.sQr, e.sQc, e.tri, e.spw,
+                                                e.out)))
+}
+template <int NT, bool TR>
+__global__ __launch_bounds__(kThreads) void kb_apply_fac2(const BDesc *__restrict__ d,
+                                                          const WGItem *__restrict__ items, int nitems) {
+  TTR_ITEMS_LOOP((apply_fac2_body<NT, 4 * NT, TR>(w.wg, e.X, e.a, e.b, e.I, e.Q, e.q, e.sQr, e.sQc, e.tri, e.Q2,
+                                                  e.q2, e.s2r, e.s2c, e.spw, e.out)))
 }
 
 struct Grid {
@@ -664,5 +766,61 @@ void launch_apply_fac2(hipStream_t s, const double *X, int a, int b, long long I
       TTR_LAUNCH(k_apply_fac2<NTV, KSV, true>) X, a, b, I, Q1, q1, s1r, s1c, tri, Q2, q2, s2r, s2c, gr.spw, Y);
     else
       TTR_LAUNCH(k_apply_fac2<NTV, KSV, false>) X, a, b, I, Q1, q1, s1r, s1c, tri, Q2, q2, s2r, s2c, gr.spw, Y);
+  });
+}
+
+// --- batched launchers ------------------------------------------------------
+template <class F>
+void nt_only(int nt, F &&f) {
+  switch (nt) {
+    case 1: f(std::integral_constant<int, 1>{}); break;
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 3: f(std::integral_constant<int, 3>{}); break;
+    default: f(std::integral_constant<int, 4>{}); break;
+  }
+}
+#define TTR_BLAUNCH(...) hipLaunchKernelGGL((__VA_ARGS__), dim3(grid), dim3(kThreads), 0, s, d, items, nitems)
+
+void launch_gram_right_factor_batched(hipStream_t s, int nt, int f32, const BDesc *d, const WGItem *items, int nitems,
+                                      int grid) {
+  if (nitems <= 0) return;
+  nt_only(nt, [&](auto NTc) {
+    constexpr int NTV = decltype(NTc)::value;
+    if (f32) TTR_BLAUNCH(kb_gram_right_factor<NTV, F32>);
+    else TTR_BLAUNCH(kb_gram_right_factor<NTV, F64>);
+  });
+}
+void launch_gram_left_factor_batched(hipStream_t s, int nt, int f32, const BDesc *d, const WGItem *items, int nitems,
+                                     int grid) {
+  if (nitems <= 0) return;
+  nt_only(nt, [&](auto NTc) {
+    constexpr int NTV = decltype(NTc)::value;
+    if (f32) TTR_BLAUNCH(kb_gram_left_factor<NTV, F32>);
+    else TTR_BLAUNCH(kb_gram_left_factor<NTV, F64>);
+  });
+}
+void launch_apply_mfma_batched(hipStream_t s, int nt, const BDesc *d, const WGItem *items, int nitems, int grid) {
+  if (nitems <= 0) return;
+  nt_only(nt, [&](auto NTc) {
+    constexpr int NTV = decltype(NTc)::value;
+    TTR_BLAUNCH(kb_apply_mfma<NTV>);
+  });
+}
+void launch_gram_fac_batched(hipStream_t s, int nt, int trans, const BDesc *d, const WGItem *items, int nitems,
+                             int grid) {
+  if (nitems <= 0) return;
+  nt_only(nt, [&](auto NTc) {
+    constexpr int NTV = decltype(NTc)::value;
+    if (trans) TTR_BLAUNCH(kb_gram_fac<NTV, true>);
+    else TTR_BLAUNCH(kb_gram_fac<NTV, false>);
+  });
+}
+void launch_apply_fac2_batched(hipStream_t s, int nt, int trans, const BDesc *d, const WGItem *items, int nitems,
+                               int grid) {
+  if (nitems <= 0) return;
+  nt_only(nt, [&](auto NTc) {
+    constexpr int NTV = decltype(NTc)::value;
+    if (trans) TTR_BLAUNCH(kb_apply_fac2<NTV, true>);
+    else TTR_BLAUNCH(kb_apply_fac2<NTV, false>);
   });
 }

@@ -361,7 +361,7 @@ __device__ bool chol_inv(double *A, double *Vm, int d, double *kappa, double *lm
 //           rounding noise of a rank-deficient unfolding), F = W_k t_k^{-1/2};
 //           done when t_k >= tau1 t_1 (or at pass 3).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreadsQR) void k_qr_step(QrStepArgs a) {
+__device__ void qr_step_body(const QrStepArgs a) {
   __shared__ double A[TTR_RMAX * TTR_RMAX];
   __shared__ double Vm[TTR_RMAX * TTR_RMAX];
   __shared__ double Bf[TTR_RMAX * TTR_RMAX];
@@ -610,7 +610,7 @@ __global__ __launch_bounds__(kThreadsQR) void k_qr_step(QrStepArgs a) {
 // the Frobenius-tail rule, GU = Glast U_R[:, :L] and
 // Pnext = Sigma_L V_R[:, :L]^T Fn^T.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_trunc_step(TruncArgs a) {
+__device__ void trunc_step_body(const TruncArgs a) {
   __shared__ double A[TTR_RMAX * TTR_RMAX];   // R^T, b x k
   __shared__ double Um[TTR_RMAX * TTR_RMAX];  // k x k rotations = U_R
   __shared__ double sv[TTR_RMAX];
@@ -706,13 +706,34 @@ __global__ __launch_bounds__(kThreads) void k_trunc_step(TruncArgs a) {
   }
 }
 
-__global__ void k_small_gemm(const double *A, const double *B, double *C, int m, int k, int n) {
+__device__ void small_gemm_body(const double *A, const double *B, double *C, int m, int k, int n) {
   for (int e = threadIdx.x; e < m * n; e += blockDim.x) {
     const int r = e % m, c = e / m;
     double s = 0.0;
     for (int j = 0; j < k; ++j) s += A[r + m * j] * B[j + k * c];
     C[r + m * c] = s;
   }
+}
+
+__global__ __launch_bounds__(kThreadsQR) void k_qr_step(QrStepArgs a) { qr_step_body(a); }
+__global__ __launch_bounds__(kThreads) void k_trunc_step(TruncArgs a) { trunc_step_body(a); }
+__global__ void k_small_gemm(const double *A, const double *B, double *C, int m, int k, int n) {
+  small_gemm_body(A, B, C, m, k, n);
+}
+
+// Batched forms: workgroup t handles item t when active[t] is set.
+__global__ __launch_bounds__(kThreadsQR) void kb_qr_step(const QrStepArgs *args, const int *active) {
+  if (!active[blockIdx.x]) return;
+  qr_step_body(args[blockIdx.x]);
+}
+__global__ __launch_bounds__(kThreads) void kb_trunc_step(const TruncArgs *args, const int *active) {
+  if (!active[blockIdx.x]) return;
+  trunc_step_body(args[blockIdx.x]);
+}
+__global__ void kb_small_gemm(const SmallGemmArgs *args, const int *active) {
+  if (!active[blockIdx.x]) return;
+  const SmallGemmArgs g = args[blockIdx.x];
+  small_gemm_body(g.A, g.B, g.C, g.m, g.k, g.n);
 }
 
 __global__ void k_sqrt_scalar(const double *in, double *out) {
@@ -734,6 +755,16 @@ void launch_trunc_step(hipStream_t s, const TruncArgs &a) {
 
 void launch_small_gemm(hipStream_t s, const double *A, const double *B, double *C, int m, int k, int n) {
   hipLaunchKernelGGL(k_small_gemm, dim3(1), dim3(kThreads), 0, s, A, B, C, m, k, n);
+}
+
+void launch_qr_step_batched(hipStream_t s, int count, const QrStepArgs *args, const int *active) {
+  hipLaunchKernelGGL(kb_qr_step, dim3(count), dim3(kThreadsQR), 0, s, args, active);
+}
+void launch_trunc_step_batched(hipStream_t s, int count, const TruncArgs *args, const int *active) {
+  hipLaunchKernelGGL(kb_trunc_step, dim3(count), dim3(kThreads), 0, s, args, active);
+}
+void launch_small_gemm_batched(hipStream_t s, int count, const SmallGemmArgs *args, const int *active) {
+  hipLaunchKernelGGL(kb_small_gemm, dim3(count), dim3(kThreads), 0, s, args, active);
 }
 
 void launch_sqrt_scalar(hipStream_t s, const double *in, double *out) {

@@ -27,6 +27,7 @@ TTR_RLR, TTR_LRL = 0, 1
 TTR_NORM_ORTHO, TTR_NORM_GRAM = 0, 1
 TTR_FP64, TTR_MIXED = 0, 1
 TTR_MAX_RANK = 64
+TTR_ERR_NUMERICAL = 6
 
 _DIR = {"RLR": TTR_RLR, "LRL": TTR_LRL}
 _SIDE = {"right": TTR_RIGHT, "left": TTR_LEFT}
@@ -37,7 +38,7 @@ _PREC = {"fp64": TTR_FP64, "mixed": TTR_MIXED}
 SYMBOLS = [
     "ttr_create", "ttr_destroy", "ttr_set_stream", "ttr_add", "ttr_hadamard", "ttr_dot", "ttr_norm",
     "ttr_orthogonalize", "ttr_round", "ttr_status_string", "ttr_last_error", "ttr_get_round_stats",
-    "ttr_set_profiling", "ttr_get_profile",
+    "ttr_set_profiling", "ttr_get_profile", "ttr_round_batched", "ttr_get_batch_plan",
 ]
 
 PROF_CLASSES = ["k_gram_right_factor", "k_gram_left_factor", "k_gram", "k_apply_mfma", "k_apply", "k_add",
@@ -53,6 +54,20 @@ class _TTStruct(ctypes.Structure):
         ("R", ctypes.POINTER(ctypes.c_int64)),
         ("core", ctypes.POINTER(ctypes.c_void_p)),
         ("cap", ctypes.POINTER(ctypes.c_int64)),
+    ]
+
+
+class BatchPlan(ctypes.Structure):
+    _fields_ = [
+        ("count", ctypes.c_int32),
+        ("spw_target", ctypes.c_int32),
+        ("grid_cap", ctypes.c_int32),
+        ("graph_nodes", ctypes.c_int32),
+        ("workspace_bytes", ctypes.c_int64),
+        ("candidates", ctypes.c_int32),
+        ("cand_spw", ctypes.c_int32 * 16),
+        ("cand_grid", ctypes.c_int32 * 16),
+        ("cand_ms", ctypes.c_double * 16),
     ]
 
 
@@ -114,6 +129,9 @@ def load(path: str = LIB_PATH):
     lib.ttr_get_round_stats.argtypes = [vp, P(RoundStats)]
     lib.ttr_set_profiling.argtypes = [vp, ctypes.c_int]
     lib.ttr_get_profile.argtypes = [vp, P(Profile)]
+    lib.ttr_round_batched.argtypes = [vp, ctypes.c_int, tt, P(ctypes.c_double), ctypes.c_int, ctypes.c_int, tt,
+                                      vp, ctypes.c_int]
+    lib.ttr_get_batch_plan.argtypes = [vp, P(BatchPlan)]
     for name in SYMBOLS:
         if name not in ("ttr_status_string", "ttr_last_error"):
             getattr(lib, name).restype = ctypes.c_int
@@ -264,6 +282,46 @@ class Handle:
                               ctypes.byref(sy), ctypes.byref(nrm)))
         Y._read_ranks()
         return (Y, nrm.value) if return_norm else Y
+
+    def round_batched(self, Xs: Sequence[TT], tols, prec: str = "fp64", outs: Optional[Sequence[TT]] = None,
+                      ranks=None, tune: bool = False):
+        """Rounds every X in Xs (same N, RLR) with one replay of a captured
+        graph.  Returns (Ys, ranks) where ranks is a device int64 tensor of
+        shape (count, N+1); Ys[t].R is filled only by `sync_ranks`."""
+        import torch
+        count = len(Xs)
+        N = Xs[0].N
+        if outs is None:
+            outs = [TT.empty(X.I, [X.R[n] * X.I[n] * X.R[n + 1] for n in range(N)], X.cores[0].device)
+                    for X in Xs]
+        if ranks is None:
+            ranks = torch.zeros((count, N + 1), dtype=torch.int64, device=Xs[0].cores[0].device)
+        if not isinstance(tols, (list, tuple)):
+            tols = [float(tols)] * count
+        xs = (_TTStruct * count)(*[X._struct() for X in Xs])
+        ys = (_TTStruct * count)(*[Y._struct() for Y in outs])
+        tl = (ctypes.c_double * count)(*[float(t) for t in tols])
+        self._batch_keep = (xs, ys, tl, Xs, outs)  # the arrays must outlive the call
+        _check(_lib.ttr_round_batched(self.h, count, xs, tl, _DIR["RLR"], _PREC[prec], ys,
+                                      ctypes.c_void_p(ranks.data_ptr()), 1 if tune else 0))
+        return outs, ranks
+
+    @staticmethod
+    def sync_ranks(Ys: Sequence[TT], ranks):
+        """Copies the device ranks of a batched call into the Y objects."""
+        r = ranks.cpu().tolist()
+        for Y, rr in zip(Ys, r):
+            if rr[0] < 0:
+                raise TTRError(TTR_ERR_NUMERICAL, "a small factorization of a batch member failed")
+            Y.R = [int(x) for x in rr]
+
+    def batch_plan(self) -> dict:
+        bp = BatchPlan()
+        _check(_lib.ttr_get_batch_plan(self.h, ctypes.byref(bp)))
+        return {"count": bp.count, "spw_target": bp.spw_target, "grid_cap": bp.grid_cap,
+                "graph_nodes": bp.graph_nodes, "workspace_bytes": bp.workspace_bytes,
+                "candidates": [{"spw": bp.cand_spw[i], "grid": bp.cand_grid[i], "ms": bp.cand_ms[i]}
+                               for i in range(bp.candidates)]}
 
     def set_profiling(self, on: bool = True):
         _check(_lib.ttr_set_profiling(self.h, 1 if on else 0))
