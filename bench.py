@@ -75,6 +75,62 @@ def sample_entries(cores, R, I, idx):
     return v[:, 0]
 
 
+def bench_batched(h, ttr, torch, steps, count=512):
+    """512 independent Y + Y + 1e-9 E tensors (N=8, I_n log-uniform in
+    [64, 4096], ranks 2r+2 with r uniform in 1..31), tol 1e-7: one replay of the
+    batched graph against one ttr_round call per tensor."""
+    import synth
+    shapes = synth.cfg3_shapes(count)
+    log(f"batched: generating {count} tensors")
+    Xs = []
+    for t, (I, r) in enumerate(shapes):
+        Y = ttr.TT.from_numpy(synth.random_tt(3, t, "Y", I, r, scaled=True))
+        E = ttr.TT.from_numpy(synth.random_tt(3, t, "E", I, [2] * 7, scaled=True, first_core_factor=1e-9))
+        Xs.append(h.add(1.0, h.add(1.0, Y, 1.0, Y), 1.0, E))
+    torch.cuda.synchronize()
+    nbytes = sum(8 * X.R[n] * X.I[n] * X.R[n + 1] for X in Xs for n in range(X.N))
+    expect = [[1] + list(r) + [1] for _, r in shapes]
+    tol = synth.TOL[3]
+    out = {"tensors": count, "core_bytes": nbytes}
+    stream = torch.cuda.current_stream()
+    for prec in ("fp64", "mixed"):
+        log(f"batched {prec}: plan + autotune")
+        Ys, ranks = h.round_batched(Xs, tol, prec, tune=True)
+        torch.cuda.synchronize()
+        plan = h.batch_plan()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            Ys, ranks = h.round_batched(Xs, tol, prec, outs=Ys, ranks=ranks)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        rk = ranks.cpu().tolist()
+        res = {"ms_per_batch": round(ms, 3), "core_GBps": round(nbytes / (ms * 1e-3) / 1e9, 2),
+               "ranks_ok": rk == expect, "spw_target": plan["spw_target"], "grid_cap": plan["grid_cap"],
+               "graph_nodes": plan["graph_nodes"],
+               "autotune": [[c["spw"], c["grid"], round(c["ms"], 3)] for c in plan["candidates"]]}
+        # one launch sequence per tensor (the single path, host-planned)
+        log(f"batched {prec}: one ttr_round per tensor")
+        outs1 = [ttr.TT.empty(X.I, [X.R[n] * X.I[n] * X.R[n + 1] for n in range(X.N)]) for X in Xs]
+        for X, Y1 in zip(Xs, outs1):
+            h.round(X, tol, "RLR", prec, out=Y1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        same = True
+        for X, Y1, r in zip(Xs, outs1, expect):
+            Y1 = h.round(X, tol, "RLR", prec, out=Y1)
+            same = same and (Y1.R == r)
+        torch.cuda.synchronize()
+        ms1 = (time.perf_counter() - t0) * 1e3
+        res["ms_one_launch_sequence_per_tensor"] = round(ms1, 3)
+        res["speedup_vs_per_tensor"] = round(ms1 / ms, 2)
+        res["per_tensor_ranks_ok"] = same
+        out[prec] = res
+    del Xs
+    return out
+
+
 def cpu_baseline(I_sample, steps=1):
     """FP64 CPU oracle on a bounded sample: the same workload with I reduced."""
     import oracle as O
@@ -123,6 +179,7 @@ def main():
     ap.add_argument("--cpu-sample-I", type=int, default=16384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision rounds")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched rounding of 512 tensors")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="only run a plain device-to-device copy of this many GiB (counter calibration)")
     args = ap.parse_args()
@@ -225,6 +282,7 @@ def main():
                  "ranks_equal": list(Ym.R) == ranks_fp64,
                  "max_entry_diff_vs_fp64": rel,
                  "entries_sampled": int(idx.shape[0])}
+        del Ym
 
     # dominant kernel by time
     cls = max((c for c in prof if c != "small"), key=lambda c: prof[c]["ms"])
@@ -276,6 +334,10 @@ def main():
     }
     if mixed:
         out["mixed"] = mixed
+    if not args.no_batched:
+        del A, B, Xbuf, Ybuf, X, Y, Yf
+        torch.cuda.empty_cache()
+        out["batched"] = bench_batched(h, ttr, torch, args.steps)
     if not args.no_cpu_baseline:
         log(f"cpu_baseline: oracle on I={args.cpu_sample_I}")
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_I)

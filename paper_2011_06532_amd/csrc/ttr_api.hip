@@ -385,8 +385,9 @@ Stages no_stages() {
 struct Factor {
   int nst = 0;
   int dim[4] = {0, 0, 0, 0};
-  int tri = 0;  // one-pass Cholesky route: T = L lower triangular, F = L^{-T}
-  int mat = 0;  // stages apply to the materialized core M(i) T_{n+1}, not to M(i)
+  int tri = 0;    // one-pass Cholesky route: T = L lower triangular, F = L^{-T}
+  int mat = 0;    // stages apply to the materialized core M(i) T_{n+1}, not to M(i)
+  int rorth = 0;  // one-pass eigen route: the rows of R are mutually orthogonal
 };
 
 // One QR-by-Gram factorization of a tall-skinny unfolding of a logical core,
@@ -506,6 +507,7 @@ int qr_by_gram(ttr_handle *h, WS &w, const CoreView &cv, int mode, const Stages 
     if (pass == 1 && ratio) *ratio = h->decf_host[0];
     if (tc) tc->notrunc = (pass == 1 && done) ? h->dec_host[5] : 0;
     f->tri = (pass == 1 && done) ? h->dec_host[4] : 0;
+    f->rorth = (pass == 1 && done) ? h->dec_host[6] : 0;
     f->nst = pass;
     f->dim[pass] = k;
     const bool can_mat = (mode == GRAM_RIGHT) ? (base.nl <= 1 && base.nr <= 1) : (base.nl == 0 && base.nr <= 1);
@@ -924,7 +926,7 @@ int ttr_round(ttr_handle *h, const ttr_tt *X, double tol, int direction, int pre
     ta.sigma_out = w.sigma + (size_t)n * TTR_RMAX;
     ta.dec = w.dec;
     ta.identity = tcx.notrunc;              // proved L = k: no SVD needed
-    ta.r_orth = (g.nst == 1 && !tcx.notrunc) ? 1 : 0;  // one-pass eigen route: R = t^{1/2} W^T
+    ta.r_orth = (g.nst == 1 && !tcx.notrunc && g.rorth) ? 1 : 0;  // one-pass eigen route: R = t^{1/2} W^T
     {
       ProfScope ps(h, P_SMALL, 0.0, 0.0);
       launch_trunc_step(h->stream, ta);

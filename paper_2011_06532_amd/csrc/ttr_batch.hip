@@ -61,7 +61,7 @@ struct BState {
   double kappa2[kBMaxN + 1];
   int L[kBMaxN + 1];
   // the factorization in progress
-  int done, passes, kcur, notrunc, tfold, gnst;
+  int done, passes, kcur, notrunc, rorth, tfold, gnst;
   int gdim[4];
   const double *src;  // orthonormalization: the refinement passes' core
   int sa, sb;
@@ -357,6 +357,7 @@ __global__ void kp_plan(BState *St, int count, int op, int n, BDesc *d, BDesc *d
       S.kcur = S.dec[0];
       S.done = S.dec[1];
       S.notrunc = S.done ? S.dec[5] : 0;
+      S.rorth = S.done ? S.dec[6] : 0;
       S.gnst = 1;
       S.gdim[0] = S.k[n + 1];
       S.gdim[1] = S.kcur;
@@ -449,7 +450,7 @@ __global__ void kp_plan(BState *St, int count, int op, int n, BDesc *d, BDesc *d
       a.Nm1 = N - 1;
       a.sigma_out = S.sigma + (size_t)n * TTR_RMAX;
       a.dec = S.dec;
-      a.r_orth = (S.gnst == 1 && !S.notrunc) ? 1 : 0;
+      a.r_orth = (S.gnst == 1 && !S.notrunc && S.rorth) ? 1 : 0;
       a.identity = S.notrunc;
       ta[t] = a;
       a_on = 1;
@@ -633,7 +634,7 @@ struct BatchPlan {
   WGItem *items = nullptr;
   // item lists per (tile class 1..4, core)
   std::vector<int> off, cnt;  // index (c-1)*N + n
-  std::vector<int> classes;   // tile class of each tensor
+  std::vector<int> classes;   // tile class of each (tensor, core): classes[t*N + n]
   // schedule
   int spw_target = 64, grid_cap = 0;
   hipStream_t cap = nullptr;
@@ -780,7 +781,7 @@ int build_items(BatchPlan *P, std::vector<BState> &st, int target) {
       const int k = (c - 1) * N + n;
       P->off[k] = (int)items.size();
       for (int t = 0; t < P->count; ++t) {
-        if (P->classes[t] != c) continue;
+        if (P->classes[(size_t)t * N + n] != c) continue;
         for (int w = 0; w < st[t].nwg[n]; ++w) items.push_back({t, w});
       }
       P->cnt[k] = (int)items.size() - P->off[k];
@@ -894,17 +895,19 @@ int ttr_round_batched(ttr_handle *h, int count, const ttr_tt *X, const double *t
     std::vector<size_t> tws(count), tmat(count);
     std::vector<int> maxnwg(count);
     size_t total = 0, max_items = 0;
-    P->classes.resize(count);
+    P->classes.resize((size_t)count * N);
     for (int t = 0; t < count; ++t) {
       size_t mc = 0;
-      int mr = 1, mw = 1;
+      int mw = 1;
       for (int n = 0; n < N; ++n) {
         mc = std::max(mc, (size_t)(X[t].R[n] * X[t].I[n] * X[t].R[n + 1]));
-        mr = std::max(mr, (int)std::max(X[t].R[n], X[t].R[n + 1]));
         mw = std::max(mw, grid_for_core(X[t].I[n], 16).nwg);  // the smallest target bounds the partials
         max_items += (size_t)grid_for_core(X[t].I[n], 16).nwg;
+        // every operand of a step on core n (ranks R_n, R_{n+1} and the
+        // smaller ranks derived from them) fits the tiles of the larger one
+        const int mr = (int)std::max(X[t].R[n], X[t].R[n + 1]);
+        P->classes[(size_t)t * N + n] = std::min(4, tiles(mr));
       }
-      P->classes[t] = std::min(4, tiles(mr));
       maxnwg[t] = mw;
       tmat[t] = align_up(mc);
       tws[t] = align_up((size_t)mw * slot) + 11 * slot + 64 + (size_t)(N + 1) * TTR_RMAX + (size_t)(N + 1) * slot +

@@ -104,7 +104,8 @@ struct QrStepArgs {
   double *Fstep;       // d x k (ld d)
   double *Rnext;       // k x b (ld k)
   double *Tdst;        // when done: Rnext^T (b x k, ld b); may be nullptr
-  int *dec;            // [0] k, [1] done, [2] error flags, [4] triangular factors, [5] no truncation proven
+  int *dec;            // [0] k, [1] done, [2] error flags, [4] triangular factors, [5] no truncation
+                       // proven, [6] settled at the first pass with mutually orthogonal rows of R
   // tau1: one pass is enough (and a refinement pass settles) when the Gram's
   // condition number, scaled by cond_scale, is at most 1/tau1; tau2: rank
   // revealing cut of the refinement passes

@@ -349,6 +349,73 @@ __device__ bool chol_inv(double *A, double *Vm, int d, double *kappa, double *lm
   return true;
 }
 
+// Pivoted Cholesky of the d x d symmetric A (full storage, overwritten), the
+// rank-revealing form: pivots in order perm[0..k), A(i, j) (i >= j, j < k)
+// holds L with G(perm, perm) ~= L L^T; stops once the largest remaining
+// diagonal entry is at most tau times the largest initial one.  Returns k.
+__device__ int pivoted_chol(double *A, int d, double tau, int *perm) {
+  __shared__ int piv, stop;
+  __shared__ double dmax0;
+  for (int i = threadIdx.x; i < d; i += blockDim.x) perm[i] = i;
+  double m = 0.0;
+  for (int i = threadIdx.x; i < d; i += blockDim.x) m = fmax(m, A[i + d * i]);
+  m = block_max(m);
+  if (threadIdx.x == 0) dmax0 = m;
+  __syncthreads();
+  int k = d;
+  for (int j = 0; j < d; ++j) {
+    if (threadIdx.x == 0) {
+      int p = j;
+      double v = A[j + d * j];
+      for (int i = j + 1; i < d; ++i)
+        if (A[i + d * i] > v) {
+          v = A[i + d * i];
+          p = i;
+        }
+      piv = p;
+      stop = !(v > tau * dmax0);
+    }
+    __syncthreads();
+    if (stop) {
+      k = j;
+      break;
+    }
+    const int p = piv;
+    if (p != j) {
+      // symmetric interchange j <-> p, including the rows of L computed so far
+      for (int c = threadIdx.x; c < d; c += blockDim.x) {
+        const double t = A[j + d * c];
+        A[j + d * c] = A[p + d * c];
+        A[p + d * c] = t;
+      }
+      __syncthreads();
+      for (int r = threadIdx.x; r < d; r += blockDim.x) {
+        const double t = A[r + d * j];
+        A[r + d * j] = A[r + d * p];
+        A[r + d * p] = t;
+      }
+      if (threadIdx.x == 0) {
+        const int t = perm[j];
+        perm[j] = perm[p];
+        perm[p] = t;
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) A[j + d * j] = sqrt(A[j + d * j]);
+    __syncthreads();
+    const double ljj = A[j + d * j];
+    for (int i = j + 1 + threadIdx.x; i < d; i += blockDim.x) A[i + d * j] /= ljj;
+    __syncthreads();
+    const int n = d - j - 1;
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+      const int r = j + 1 + e % n, c = j + 1 + e / n;
+      A[r + d * c] -= A[r + d * j] * A[c + d * j];
+    }
+    __syncthreads();
+  }
+  return k;
+}
+
 // ---------------------------------------------------------------------------
 // QR-by-Gram step.  Input: G = Gram of the current staged unfolding
 // A F_1 ... F_{j-1} and the collapsed factor Rc with A = (A F_1...F_{j-1}) Rc.
@@ -428,6 +495,7 @@ __device__ void qr_step_body(const QrStepArgs a) {
       a.dec[2] |= 1;
       a.dec[1] = 1;
       a.dec[0] = 1;
+      a.dec[6] = 0;
     }
     return;
   }
@@ -438,7 +506,7 @@ __device__ void qr_step_body(const QrStepArgs a) {
     // is at most 1/tau1, and, at the first pass of the truncation sweep, when
     // no singular value can fall below delta.  At a refinement pass G is close
     // to the identity and this is the second step of CholeskyQR2.
-    __shared__ int accept;
+    __shared__ int accept, kap_ok;
     for (int e = threadIdx.x; e < d * d; e += blockDim.x) Bf[e] = A[e];  // keep G for a fallback
     double trace_part = 0.0;
     for (int j = threadIdx.x; j < d; j += blockDim.x) trace_part += A[j + d * j];
@@ -463,6 +531,7 @@ __device__ void qr_step_body(const QrStepArgs a) {
     }
     if (threadIdx.x == 0) {
       int acc = ok && (kappa == kappa) && kappa * (a.cond_scale > 1.0 ? a.cond_scale : 1.0) * a.tau1 <= 1.0;
+      kap_ok = acc;
       int notrunc = 0;
       if (acc && a.notrunc_check && a.pass == 1) {
         const double dl = a.first ? sqrt(a.tol2_nm1 * trG) : *a.delta_dev;
@@ -503,8 +572,100 @@ __device__ void qr_step_body(const QrStepArgs a) {
         a.dec[0] = d;
         a.dec[1] = 1;
         a.dec[4] = a.Rc ? 0 : 1;  // triangular factors (first pass only)
+        a.dec[6] = 0;
       }
       return;
+    }
+    if (!kap_ok && a.pass == 1) {
+      // Shifted CholeskyQR: G + sI = L L^T with s ~ d u trace(G) gives A L^{-T}
+      // the singular values sqrt(lambda / (lambda + s)), as the shifted eigen
+      // route would, at the cost of one factorization; the next pass refines.
+      const double shift = 2.0 * d * a.ugram * trG;
+      for (int e = threadIdx.x; e < d * d; e += blockDim.x) {
+        const int r = e % d, c = e / d;
+        A[e] = Bf[e] + ((r == c) ? shift : 0.0);
+      }
+      __syncthreads();
+      double kap2 = 0.0, lmin2 = 0.0;
+      const bool ok2 = (shift > 0.0) && chol_inv(A, Vm, d, &kap2, &lmin2);
+      if (ok2) {
+        for (int e = threadIdx.x; e < d * d; e += blockDim.x) {
+          const int r = e % d, c = e / d;
+          a.Fstep[r + d * c] = Vm[c + d * r];  // F = L^{-T}
+          a.Rnext[r + d * c] = A[c + d * r];   // R = L^T (Rc = I at the first pass)
+        }
+        if (threadIdx.x == 0) {
+          if (a.ratio_out) *a.ratio_out = 1e300;
+          a.dec[0] = d;
+          a.dec[1] = 0;
+          a.dec[4] = 0;
+          a.dec[5] = 0;
+          a.dec[6] = 0;
+        }
+        return;
+      }
+    }
+    if (a.pass >= 2) {
+      // Refinement pass: rank-revealing pivoted Cholesky of G (close to the
+      // identity on the directions that carry content, at rounding level on
+      // the null directions of a rank-deficient unfolding).
+      for (int e = threadIdx.x; e < d * d; e += blockDim.x) A[e] = Bf[e];
+      __syncthreads();
+      const int k = pivoted_chol(A, d, a.tau2, perm);
+      if (k > 0) {
+      // X = L11^{-1} (k x k lower, ld d) by forward substitution, one column per thread
+      for (int c = threadIdx.x; c < k; c += blockDim.x) {
+        for (int r = 0; r < k; ++r) {
+          double v = (r == c) ? 1.0 : 0.0;
+          for (int m = c; m < r; ++m) v -= A[r + d * m] * Vm[m + d * c];
+          Vm[r + d * c] = (r < c) ? 0.0 : v / A[r + d * r];
+        }
+      }
+      __syncthreads();
+      // conditioning of the kept part: ||G11||_1 ||X||_1 ||X||_inf
+      double g1 = 0.0, x1 = 0.0, xi = 0.0;
+      for (int c = threadIdx.x; c < k; c += blockDim.x) {
+        double sg = 0.0, sx = 0.0;
+        for (int r = 0; r < k; ++r) {
+          sg += fabs(Bf[perm[r] + d * perm[c]]);
+          sx += fabs(Vm[r + d * c]);
+        }
+        g1 = fmax(g1, sg);
+        x1 = fmax(x1, sx);
+      }
+      for (int r = threadIdx.x; r < k; r += blockDim.x) {
+        double sx = 0.0;
+        for (int c = 0; c < k; ++c) sx += fabs(Vm[r + d * c]);
+        xi = fmax(xi, sx);
+      }
+      g1 = block_max(g1);
+      x1 = block_max(x1);
+      xi = block_max(xi);
+      const int dn = (a.pass >= 3 || g1 * x1 * xi * a.tau1 <= 1.0) ? 1 : 0;
+      // F (d x k): F(perm[i], c) = X(c, i);  R' (k x d): R'(c, perm[j]) = L(j, c)
+      for (int e = threadIdx.x; e < d * k; e += blockDim.x) a.Fstep[e] = 0.0;
+      __syncthreads();
+      for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
+        const int i = e % k, c = e / k;
+        a.Fstep[perm[i] + d * c] = (c >= i) ? Vm[c + d * i] : 0.0;
+      }
+      const int b = a.b;
+      for (int e = threadIdx.x; e < k * b; e += blockDim.x) {
+        const int c = e % k, col = e / k;
+        double v = 0.0;
+        for (int j = c; j < d; ++j) v += A[j + d * c] * a.Rc[perm[j] + d * col];
+        a.Rnext[c + k * col] = v;
+        if (dn && a.Tdst) a.Tdst[col + b * c] = v;
+      }
+      if (threadIdx.x == 0) {
+        a.dec[0] = k;
+        a.dec[1] = dn;
+        a.dec[4] = 0;
+        a.dec[6] = 0;
+      }
+      return;
+      }
+      // a zero Gram: the eigen route below returns the rank-1 zero factor
     }
     // fall back: G again for the eigen route
     for (int e = threadIdx.x; e < d * d; e += blockDim.x) {
@@ -573,6 +734,7 @@ __device__ void qr_step_body(const QrStepArgs a) {
     if (threadIdx.x == 0) {
       a.dec[0] = 1;
       a.dec[1] = 1;
+      a.dec[6] = 1;
     }
     return;
   }
@@ -602,6 +764,7 @@ __device__ void qr_step_body(const QrStepArgs a) {
   if (threadIdx.x == 0) {
     a.dec[0] = k;
     a.dec[1] = done;
+    a.dec[6] = (a.pass == 1 && done) ? 1 : 0;  // R = t^{1/2} W^T: rows mutually orthogonal
   }
 }
 
@@ -618,8 +781,38 @@ __device__ void trunc_step_body(const TruncArgs a) {
   __shared__ int perm[TTR_RMAX];
   __shared__ int flag, LL;
   const int k = a.k, b = a.b;
-  if (a.identity) {
-    // no truncation possible (proved by the step kernel): U = I, Sigma V^T = R
+  int ident = a.identity;
+  if (!ident && k == b && k > 0) {
+    // R upper triangular (Cholesky-based factorizations): sigma_min(R) >=
+    // 1 / ||R^{-1}||_F, so no direction can be dropped when that bound exceeds
+    // 2 delta (the Frobenius tail of any truncation would exceed delta).
+    __shared__ int tri_ok;
+    if (threadIdx.x == 0) tri_ok = 1;
+    __syncthreads();
+    for (int e = threadIdx.x; e < k * k; e += blockDim.x)
+      if (e % k > e / k && a.R[e] != 0.0) tri_ok = 0;
+    __syncthreads();
+    if (tri_ok) {
+      for (int c = threadIdx.x; c < k; c += blockDim.x)
+        for (int r = k - 1; r >= 0; --r) {
+          if (r > c) {
+            A[r + k * c] = 0.0;
+            continue;
+          }
+          double v = (r == c) ? 1.0 : 0.0;
+          for (int m = r + 1; m <= c; ++m) v -= a.R[r + k * m] * A[m + k * c];
+          A[r + k * c] = v / a.R[r + k * r];
+        }
+      __syncthreads();
+      const double xf2 = sumsq(A, k * k);
+      const double n2 = sumsq(a.R, k * k);
+      const double dl2 = a.first ? ((a.Nm1 > 0) ? a.tol * a.tol * n2 / (double)a.Nm1 : 0.0) : (*a.delta) * (*a.delta);
+      ident = (xf2 > 0.0 && finite(xf2) && 1.0 / xf2 > 4.0 * dl2) ? 1 : 0;
+      __syncthreads();
+    }
+  }
+  if (ident) {
+    // no truncation possible (proved here or by the step kernel): U = I, Sigma V^T = R
     const double n2 = sumsq(a.R, k * b);
     if (threadIdx.x == 0) {
       if (a.first) {
