@@ -144,7 +144,7 @@ __device__ inline void load_slice(const double *__restrict__ Xi, long long col, 
 // KS = k-steps over b (ceil(b/4)).  A = F64, or F32 for the mixed-precision
 // first pass (slices and Q rounded to FP32, FP32 accumulation per wave).
 // ---------------------------------------------------------------------------
-template <int NT, int KS, class A>
+template <int NT, int KS, class A, bool GD = false>
 __device__ __forceinline__ void gram_right_factor_body(const int wg, const double *__restrict__ X, int a, int b, long long I,
                                                                 const double *__restrict__ Q, int q, long long sQr,
                                                                 long long sQc, int tri, long long spw,
@@ -155,6 +155,9 @@ __device__ __forceinline__ void gram_right_factor_body(const int wg, const doubl
   __shared__ double Gs[NT * 16 * NT * 16];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, j = lane & 15;
+  // GD: the dimensions are known only at run time (batched launches); skip
+  // k-steps and 16-tiles past them
+  const int ksr = (b + 3) / 4, ntq = (q + 15) / 16, nta = (a + 15) / 16;
   // A operand: Q^T (q x b), Q^T(c, beta) = Q(beta, c)
   build_afrag<T>(frag, Q, q, b, sQc, sQr, NT, KS);
   __syncthreads();
@@ -191,10 +194,11 @@ __device__ __forceinline__ void gram_right_factor_body(const int wg, const doubl
 #pragma unroll
       for (int cb = 0; cb < NT; ++cb) {
         // lower-triangular Q: Q^T(c, beta) = 0 for beta < c, so k-steps below 4 cb vanish
-        if (tri && ks < 4 * cb) continue;
+        if ((tri && ks < 4 * cb) || (GD && (ks >= ksr || cb >= ntq))) continue;
         const T qa = frag[(cb * KS + ks) * 64 + lane];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) wt[cb][t] = A::mma(qa, cur[ks][t], wt[cb][t]);
+        for (int t = 0; t < NT; ++t)
+          if (!GD || t < nta) wt[cb][t] = A::mma(qa, cur[ks][t], wt[cb][t]);
       }
     // G(alpha, alpha') += sum_c Wt(c, alpha) Wt(c, alpha'); register r of tile
     // (cb, .) holds rows c = cb*16 + row(g, r); rows past q are zero padding
@@ -206,7 +210,8 @@ __device__ __forceinline__ void gram_right_factor_body(const int wg, const doubl
 #pragma unroll
         for (int u = 0; u < NT; ++u)
 #pragma unroll
-          for (int v = 0; v <= u; ++v) G[u][v] = A::mma(wt[cb][u][r], wt[cb][v][r], G[u][v]);
+          for (int v = 0; v <= u; ++v)
+            if (!GD || u < nta) G[u][v] = A::mma(wt[cb][u][r], wt[cb][v][r], G[u][v]);
       }
     if constexpr (PF) {
 #pragma unroll
@@ -231,7 +236,7 @@ __global__ __launch_bounds__(kThreads) void k_gram_right_factor(const double *__
 // The Gram of the vertical unfolding of P x_1 X (truncation sweep, §2.4).
 // KS = k-steps over a (ceil(a/4)).
 // ---------------------------------------------------------------------------
-template <int NT, int KS, class A>
+template <int NT, int KS, class A, bool GD = false>
 __device__ __forceinline__ void gram_left_factor_body(const int wg, const double *__restrict__ X, int a, int b, long long I,
                                                                const double *__restrict__ P, int p, long long sPr,
                                                                long long sPa, int tri, long long spw,
@@ -254,6 +259,7 @@ __device__ __forceinline__ void gram_left_factor_body(const int wg, const double
   double *Gs = reinterpret_cast<double *>(smem);  // after the slice loop only
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, j = lane & 15;
+  const int ksr = (a + 3) / 4, ntp = (p + 15) / 16, ntb = (b + 15) / 16;  // GD: run-time extents
   T *Ls = reinterpret_cast<T *>(smem) + (STAGE ? wave * TILE : 0);
   build_afrag<T>(frag, P, p, a, sPr, sPa, NT, KS);
   __syncthreads();
@@ -301,10 +307,11 @@ __device__ __forceinline__ void gram_left_factor_body(const int wg, const double
 #pragma unroll
       for (int rb = 0; rb < NT; ++rb) {
         // upper-triangular P: P(rho, alpha) = 0 for alpha < rho
-        if (tri && ks < 4 * rb) continue;
+        if ((tri && ks < 4 * rb) || (GD && (ks >= ksr || rb >= ntp))) continue;
         const T pa = frag[(rb * KS + ks) * 64 + lane];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) y[rb][t] = A::mma(pa, cur[ks][t], y[rb][t]);
+        for (int t = 0; t < NT; ++t)
+          if (!GD || t < ntb) y[rb][t] = A::mma(pa, cur[ks][t], y[rb][t]);
       }
     // G0(beta, beta') += sum_rho Y(rho, beta) Y(rho, beta'); rows past p are padding
 #pragma unroll
@@ -315,7 +322,8 @@ __device__ __forceinline__ void gram_left_factor_body(const int wg, const double
 #pragma unroll
         for (int u = 0; u < NT; ++u)
 #pragma unroll
-          for (int v = 0; v <= u; ++v) G[u][v] = A::mma(y[rb][u][r], y[rb][v][r], G[u][v]);
+          for (int v = 0; v <= u; ++v)
+            if (!GD || u < ntb) G[u][v] = A::mma(y[rb][u][r], y[rb][v][r], G[u][v]);
       }
   }
   __syncthreads();  // every wave is done with its staging tile before Gs reuses it
@@ -336,7 +344,7 @@ __global__ __launch_bounds__(kThreads) void k_gram_left_factor(const double *__r
 // KS = k-steps over b.  With NT <= 3 two waves share each SIMD, so one wave's
 // loads and stores overlap the other's matrix-core work.
 // ---------------------------------------------------------------------------
-template <int NT, int KS>
+template <int NT, int KS, bool GD = false>
 __device__ __forceinline__ void apply_mfma_body(const int wg, const double *__restrict__ X, int a, int b, long long I, const double *__restrict__ P, int p,
                   long long sPr, long long sPa, const double *__restrict__ Q, int q, long long sQr, long long sQc,
                   long long spw, double *__restrict__ Y) {
@@ -345,6 +353,7 @@ __device__ __forceinline__ void apply_mfma_body(const int wg, const double *__re
   __shared__ double fragP[NT * KA * 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, j = lane & 15;
+  const int ksr = (b + 3) / 4, ntq = (q + 15) / 16, nta = (a + 15) / 16, ntp = (p + 15) / 16;  // GD
   const bool hasP = (P != nullptr);
   build_bfrag(fragQ, Q, b, q, sQr, sQc, NT, KS);
   if (hasP) build_afrag(fragP, P, p, a, sPr, sPa, NT, KA);
@@ -365,9 +374,11 @@ __device__ __forceinline__ void apply_mfma_body(const int wg, const double *__re
     for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
       for (int cb = 0; cb < NT; ++cb) {
+        if (GD && (ks >= ksr || cb >= ntq)) continue;
         const double qb = fragQ[(cb * KS + ks) * 64 + lane];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) w[t][cb] = mfma(cur[ks][t], qb, w[t][cb]);
+        for (int t = 0; t < NT; ++t)
+          if (!GD || t < nta) w[t][cb] = mfma(cur[ks][t], qb, w[t][cb]);
       }
     double *Yi = Y + (long long)p * i;
     if (hasP) {
@@ -383,9 +394,11 @@ __device__ __forceinline__ void apply_mfma_body(const int wg, const double *__re
           if (t * 16 + 4 * r >= a) continue;  // rows of W past a are padding
 #pragma unroll
           for (int rb = 0; rb < NT; ++rb) {
+            if (GD && rb >= ntp) continue;
             const double pa = fragP[(rb * KA + t * 4 + r) * 64 + lane];
 #pragma unroll
-            for (int cb = 0; cb < NT; ++cb) y[rb][cb] = mfma(pa, w[t][cb][r], y[rb][cb]);
+            for (int cb = 0; cb < NT; ++cb)
+              if (!GD || cb < ntq) y[rb][cb] = mfma(pa, w[t][cb][r], y[rb][cb]);
           }
         }
 #pragma unroll
@@ -435,7 +448,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NT <= 
 // cores round identically, so the output pass applies exactly the stage whose
 // orthonormality the Gram pass measured.
 // ---------------------------------------------------------------------------
-template <int NT, int KS, bool TR>
+template <int NT, int KS, bool TR, bool GD = false>
 __device__ __forceinline__ void gram_fac_body(const int wg, const double *__restrict__ X, int a, int b, long long I,
                                                        const double *__restrict__ Q, int q, long long sQr,
                                                        long long sQc, int tri, long long spw,
@@ -445,6 +458,7 @@ __device__ __forceinline__ void gram_fac_body(const int wg, const double *__rest
   __shared__ double Gs[NT * 16 * NT * 16];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, j = lane & 15;
+  const int ksr = ((TR ? a : b) + 3) / 4, ntq = (q + 15) / 16, ntsa = ((TR ? b : a) + 15) / 16;  // GD
   const int sa = TR ? b : a, sb = TR ? a : b;
   build_bfrag(frag, Q, sb, q, sQr, sQc, NT, KS);
   __syncthreads();
@@ -477,10 +491,11 @@ __device__ __forceinline__ void gram_fac_body(const int wg, const double *__rest
     for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
       for (int cb = 0; cb < NT; ++cb) {
-        if (tri && ks < 4 * cb) continue;  // lower-triangular Q
+        if ((tri && ks < 4 * cb) || (GD && (ks >= ksr || cb >= ntq))) continue;  // lower-triangular Q
         const double qb = frag[(cb * KS + ks) * 64 + lane];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) w[t][cb] = mfma(cur[ks][t], qb, w[t][cb]);
+        for (int t = 0; t < NT; ++t)
+          if (!GD || t < ntsa) w[t][cb] = mfma(cur[ks][t], qb, w[t][cb]);
       }
     // G(c, c') += sum_s W(s, c) W(s, c'); register r of tile (t, .) holds rows
     // s = 16t + 4r + g; rows past sa are padding
@@ -492,7 +507,8 @@ __device__ __forceinline__ void gram_fac_body(const int wg, const double *__rest
 #pragma unroll
         for (int u = 0; u < NT; ++u)
 #pragma unroll
-          for (int v = 0; v <= u; ++v) G[u][v] = mfma(w[t][u][r], w[t][v][r], G[u][v]);
+          for (int v = 0; v <= u; ++v)
+            if (!GD || u < ntq) G[u][v] = mfma(w[t][u][r], w[t][v][r], G[u][v]);
       }
     if constexpr (PF) {
 #pragma unroll
@@ -512,7 +528,7 @@ __global__ __launch_bounds__(kThreads) void k_gram_fac(const double *__restrict_
   gram_fac_body<NT, KS, TR>(blockIdx.x, X, a, b, I, Q, q, sQr, sQc, tri, spw, partials);
 }
 
-template <int NT, int KS, bool TR>
+template <int NT, int KS, bool TR, bool GD = false>
 __device__ __forceinline__ void apply_fac2_body(const int wg, const double *__restrict__ X, int a, int b, long long I,
                                                          const double *__restrict__ Q1, int q1, long long s1r,
                                                          long long s1c, int tri, const double *__restrict__ Q2,
@@ -524,6 +540,8 @@ __device__ __forceinline__ void apply_fac2_body(const int wg, const double *__re
   __shared__ double frag2[NT * KC * 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, j = lane & 15;
+  const int ksr = ((TR ? a : b) + 3) / 4, ntq1 = (q1 + 15) / 16, ntq2 = (q2 + 15) / 16;  // GD
+  const int ntsa = ((TR ? b : a) + 15) / 16;
   const int sa = TR ? b : a, sb = TR ? a : b;
   // A operands: Q1^T (q1 x sb) and Q2^T (q2 x q1)
   build_afrag(frag1, Q1, q1, sb, s1c, s1r, NT, KS);
@@ -556,10 +574,11 @@ __device__ __forceinline__ void apply_fac2_body(const int wg, const double *__re
     for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
       for (int cb = 0; cb < NT; ++cb) {
-        if (tri && ks < 4 * cb) continue;
+        if ((tri && ks < 4 * cb) || (GD && (ks >= ksr || cb >= ntq1))) continue;
         const double qa = frag1[(cb * KS + ks) * 64 + lane];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) wt[cb][t] = mfma(qa, cur[ks][t], wt[cb][t]);
+        for (int t = 0; t < NT; ++t)
+          if (!GD || t < ntsa) wt[cb][t] = mfma(qa, cur[ks][t], wt[cb][t]);
       }
     d4 yt[NT][NT];  // [c2-tile][s-tile]: Y^T = Q2^T W^T
 #pragma unroll
@@ -573,9 +592,11 @@ __device__ __forceinline__ void apply_fac2_body(const int wg, const double *__re
         if (cb * 16 + 4 * r >= q1) continue;
 #pragma unroll
         for (int u = 0; u < NT; ++u) {
+          if (GD && u >= ntq2) continue;
           const double qa = frag2[(u * KC + cb * 4 + r) * 64 + lane];
 #pragma unroll
-          for (int t = 0; t < NT; ++t) yt[u][t] = mfma(qa, wt[cb][t][r], yt[u][t]);
+          for (int t = 0; t < NT; ++t)
+            if (!GD || t < ntsa) yt[u][t] = mfma(qa, wt[cb][t][r], yt[u][t]);
         }
       }
     double *Yi = Y + oslice * i;
@@ -624,31 +645,31 @@ __global__ __launch_bounds__(kThreads) void k_apply_fac2(const double *__restric
 template <int NT, class A>
 __global__ __launch_bounds__(kThreads) void kb_gram_right_factor(const BDesc *__restrict__ d,
                                                                  const WGItem *__restrict__ items, int nitems) {
-  TTR_ITEMS_LOOP((gram_right_factor_body<NT, 4 * NT, A>(w.wg, e.X, e.a, e.b, e.I, e.Q, e.q, e.sQr, e.sQc, e.tri,
+  TTR_ITEMS_LOOP((gram_right_factor_body<NT, 4 * NT, A, true>(w.wg, e.X, e.a, e.b, e.I, e.Q, e.q, e.sQr, e.sQc, e.tri,
                                                         e.spw, e.out)))
 }
 template <int NT, class A>
 __global__ __launch_bounds__(kThreads) void kb_gram_left_factor(const BDesc *__restrict__ d,
                                                                 const WGItem *__restrict__ items, int nitems) {
-  TTR_ITEMS_LOOP((gram_left_factor_body<NT, 4 * NT, A>(w.wg, e.X, e.a, e.b, e.I, e.P, e.p, e.sPr, e.sPa, e.tri,
+  TTR_ITEMS_LOOP((gram_left_factor_body<NT, 4 * NT, A, true>(w.wg, e.X, e.a, e.b, e.I, e.P, e.p, e.sPr, e.sPa, e.tri,
                                                        e.spw, e.out)))
 }
 template <int NT>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NT <= 2 ? 2 : 1, NT <= 2 ? 2 : 1)))
 void kb_apply_mfma(const BDesc *__restrict__ d, const WGItem *__restrict__ items, int nitems) {
-  TTR_ITEMS_LOOP((apply_mfma_body<NT, 4 * NT>(w.wg, e.X, e.a, e.b, e.I, e.P, e.p, e.sPr, e.sPa, e.Q, e.q, e.sQr,
+  TTR_ITEMS_LOOP((apply_mfma_body<NT, 4 * NT, true>(w.wg, e.X, e.a, e.b, e.I, e.P, e.p, e.sPr, e.sPa, e.Q, e.q, e.sQr,
                                               e.sQc, e.spw, e.out)))
 }
 template <int NT, bool TR>
 __global__ __launch_bounds__(kThreads) void kb_gram_fac(const BDesc *__restrict__ d, const WGItem *__restrict__ items,
                                                         int nitems) {
-  TTR_ITEMS_LOOP((gram_fac_body<NT, 4 * NT, TR>(w.wg, e.X, e.a, e.b, e.I, e.Q, e.q, e.sQr, e.sQc, e.tri, e.spw,
+  TTR_ITEMS_LOOP((gram_fac_body<NT, 4 * NT, TR, true>(w.wg, e.X, e.a, e.b, e.I, e.Q, e.q, e.sQr, e.sQc, e.tri, e.spw,
                                                 e.out)))
 }
 template <int NT, bool TR>
 __global__ __launch_bounds__(kThreads) void kb_apply_fac2(const BDesc *__restrict__ d,
                                                           const WGItem *__restrict__ items, int nitems) {
-  TTR_ITEMS_LOOP((apply_fac2_body<NT, 4 * NT, TR>(w.wg, e.X, e.a, e.b, e.I, e.Q, e.q, e.sQr, e.sQc, e.tri, e.Q2,
+  TTR_ITEMS_LOOP((apply_fac2_body<NT, 4 * NT, TR, true>(w.wg, e.X, e.a, e.b, e.I, e.Q, e.q, e.sQr, e.sQc, e.tri, e.Q2,
                                                   e.q2, e.s2r, e.s2c, e.spw, e.out)))
 }
 
