@@ -54,8 +54,11 @@ enum { TTR_RLR = 0, TTR_LRL = 1 };                 /* rounding sweep order (§4.
 enum { TTR_NORM_ORTHO = 0, TTR_NORM_GRAM = 1 };    /* norm method (§3.2.4) */
 enum { TTR_FP64 = 0, TTR_MIXED = 1 };              /* arithmetic of the Gram passes */
 
-/* Largest TT rank the kernels accept. */
+/* Largest TT rank of the matrix-core tiled kernels (every entry point). */
 #define TTR_MAX_RANK 64
+/* Largest rank ttr_round accepts: ranks 65..256 take a GEMM-based path
+ * (TTR_RLR only; FP64 arithmetic also for TTR_MIXED). */
+#define TTR_MAX_RANK_LARGE 256
 
 /* A TT tensor.  All arrays are HOST memory; core[n] are DEVICE pointers.
  *   N      number of cores (>= 1)
@@ -116,7 +119,8 @@ int ttr_orthogonalize(ttr_handle *h, ttr_tt *X, int side, int prec);
  * with the smallest rank whose Frobenius tail of singular values is <= delta;
  * output cores 1..N-1 are left-orthonormal.  TTR_LRL: the mirror image.
  * X is read only; Y's cores need cap[n] >= R[n]*I[n]*R[n+1] of X (always
- * enough, ranks never grow).  Y->R receives the new ranks; *norm_out (host,
+ * enough, ranks never grow).  Ranks up to TTR_MAX_RANK_LARGE; above
+ * TTR_MAX_RANK only TTR_RLR (TTR_ERR_UNSUPPORTED otherwise).  Y->R receives the new ranks; *norm_out (host,
  * nullable) receives the ||X|| used for delta.  tol = 0 keeps every direction
  * above rounding level; N = 1 copies.  `prec`: TTR_FP64 or TTR_MIXED.
  * Synchronizes. */

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libttr.so")
-SOURCES = ["ttr_api.hip", "ttr_stream.hip", "ttr_small.hip", "ttr_mfma.hip", "ttr_batch.hip"]
+SOURCES = ["ttr_api.hip", "ttr_stream.hip", "ttr_small.hip", "ttr_mfma.hip", "ttr_batch.hip", "ttr_large.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -27,7 +27,7 @@ def build(verbose: bool = True) -> str:
         subprocess.run(cmd, check=True)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lrocblas"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

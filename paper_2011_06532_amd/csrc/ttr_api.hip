@@ -5,6 +5,7 @@
 // integer decisions (ranks, pass counts) that size the next launch.
 #include "ttr_host.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstdio>
@@ -635,6 +636,7 @@ int ttr_destroy(ttr_handle *h) {
   if (h->dec_host) (void)hipHostFree(h->dec_host);
   if (h->scal_host) (void)hipHostFree(h->scal_host);
   ttr_batch_release(h);
+  ttr_large_release(h);
   for (auto &p : h->pending) {
     h->evpool.push_back(p.a);
     h->evpool.push_back(p.b);
@@ -820,14 +822,24 @@ int ttr_round(ttr_handle *h, const ttr_tt *X, double tol, int direction, int pre
   if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(TTR_ERR_INVALID_ARG, "tol must be finite and >= 0");
   if (direction != TTR_RLR && direction != TTR_LRL) return fail(TTR_ERR_INVALID_ARG, "unknown direction");
   if (prec != TTR_FP64 && prec != TTR_MIXED) return fail(TTR_ERR_INVALID_ARG, "unknown precision");
-  if ((rc = check_tt(X, "X", TTR_MAX_RANK))) return rc;
+  if ((rc = check_tt(X, "X", TTR_MAX_RANK_LARGE))) return rc;
   if ((rc = check_out(Y, "Y", X->N, X->I))) return rc;
   const int N = X->N;
+  int64_t rmax = 1;
   for (int n = 0; n < N; ++n) {
     if (Y->core[n] == X->core[n]) return fail(TTR_ERR_INVALID_ARG, "Y aliases X");
     if (Y->cap[n] < X->R[n] * X->I[n] * X->R[n + 1]) return fail(TTR_ERR_CAPACITY, "Y core capacity too small");
+    rmax = std::max(rmax, X->R[n + 1]);
   }
   std::memset(&h->stats, 0, sizeof(h->stats));
+  if (rmax > TTR_MAX_RANK && N > 1) {
+    // ranks above the tiled kernels' range: the GEMM-based path (RLR, FP64)
+    if (direction != TTR_RLR) return fail(TTR_ERR_UNSUPPORTED, "ranks above TTR_MAX_RANK support TTR_RLR");
+    if ((rc = reset_dec(h))) return rc;
+    rc = ttr_round_large(h, X, tol, Y, norm_out);
+    prof_resolve(h);
+    return rc;
+  }
   if (N == 1) {
     HIPCHK(hipMemcpyAsync(Y->core[0], X->core[0], (size_t)X->I[0] * sizeof(double), hipMemcpyDeviceToDevice,
                           h->stream));

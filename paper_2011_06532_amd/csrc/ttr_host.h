@@ -9,6 +9,7 @@
 #include <vector>
 
 struct BatchPlan;  // ttr_batch.hip
+struct LargeCtx;   // ttr_large.hip
 
 struct ttr_handle {
   int device = 0;
@@ -33,12 +34,18 @@ struct ttr_handle {
   ttr_profile prof;
   // batched rounding: the cached plan (workspace, item lists, captured graph)
   BatchPlan *plan = nullptr;
+  // ranks above 64: library handle and workspace of the GEMM-based path
+  LargeCtx *large = nullptr;
 };
 
 // Records `msg` for ttr_last_error() and returns `code`.
 int ttr_fail(int code, const std::string &msg);
 // Frees the batched plan of a handle (ttr_destroy).
 void ttr_batch_release(ttr_handle *h);
+// Frees the large-rank path's resources of a handle (ttr_destroy).
+void ttr_large_release(ttr_handle *h);
+// Rounding for ranks 65..256 (RLR, FP64), see ttr_large.hip.
+int ttr_round_large(ttr_handle *h, const ttr_tt *X, double tol, ttr_tt *Y, double *norm_out);
 
 #define TTR_HIPCHK(expr)                                                                              \
   do {                                                                                                \

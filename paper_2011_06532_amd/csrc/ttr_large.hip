@@ -1,0 +1,917 @@
+// TT rounding for ranks above the register/LDS-tiled range (64 < R <= 256):
+// the same algorithm as the single-tensor path (§2.4 Alg. 2, RLR; QR-by-Gram
+// for the tall-skinny QRs of §3.3-§3.5), with every streaming product written
+// as a plain GEMM or SYRK on a contiguous unfolding and every small
+// factorization done by one workgroup on matrices held in device memory.
+//
+// Unfoldings of a core M (a x I x b, entry (i1, i, i2) at i1 + a*(i + I*i2)):
+//   V(M) = (a*I) x b, H(M) = a x (I*b), both column-major views of the buffer.
+// Products used:
+//   C = M x_3 T^T        V(C) = V(M) T              (dgemm)
+//   D = F^T x_1 C        H(D) = F^T H(C)            (dgemm)
+//   LEFT Gram            H(Z) H(Z)^T                (dsyrk, lower)
+//   RIGHT Gram           V(Z)^T V(Z)                (dsyrk, lower)
+// Every refinement stage is applied to a materialized core, and the
+// truncation sweep rebuilds the orthonormalization sweep's intermediates with
+// the same calls, so each stage is applied to bitwise the data its Gram was
+// measured on.
+//
+// Small factorizations (d <= 256): Cholesky with Gershgorin / norm bounds,
+// shifted Cholesky (first pass), rank-revealing pivoted Cholesky (refinement
+// passes), and a one-sided Jacobi SVD for the truncation, all in one
+// 1024-thread workgroup over device-memory scratch (L2-resident).
+#include "ttr_host.h"
+
+#include <rocblas/rocblas.h>
+
+#include <algorithm>
+#include <array>
+#include <cfloat>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace {
+
+constexpr int kLT = 1024;   // threads of the one-workgroup kernels
+constexpr int kLMax = 256;  // largest rank of this path
+constexpr double kU = 1.1102230246251565e-16;
+constexpr double kTau1 = 1e-3;
+constexpr double kTau2 = 1e-12;
+
+__device__ inline bool lfinite(double x) { return x == x && fabs(x) <= DBL_MAX; }
+
+__device__ double lsum(double v) {
+  __shared__ double red[kLT];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ double lmax(double v) {
+  __shared__ double red[kLT];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// Right-looking Cholesky of the d x d symmetric A (device memory, ld d) in
+// place, lower triangle (strict upper zeroed).  False if a pivot is not positive.
+__device__ bool lchol(double *A, int d) {
+  __shared__ int ok;
+  if (threadIdx.x == 0) ok = 1;
+  __syncthreads();
+  for (int j = 0; j < d; ++j) {
+    if (threadIdx.x == 0) {
+      const double pv = A[j + (size_t)d * j];
+      if (!(pv > 0.0)) ok = 0;
+      else A[j + (size_t)d * j] = sqrt(pv);
+    }
+    __syncthreads();
+    if (!ok) return false;
+    const double ljj = A[j + (size_t)d * j];
+    for (int r = j + 1 + threadIdx.x; r < d; r += blockDim.x) A[r + (size_t)d * j] /= ljj;
+    __syncthreads();
+    const int n = d - j - 1;
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+      const int r = j + 1 + e % n, c = j + 1 + e / n;
+      if (c <= r) A[r + (size_t)d * c] -= A[r + (size_t)d * j] * A[c + (size_t)d * j];
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < d * d; e += blockDim.x)
+    if (e % d < e / d) A[e] = 0.0;
+  __syncthreads();
+  return true;
+}
+
+// X = L^{-1} (k x k lower, ld d) for the lower-triangular L in A (ld d).
+__device__ void linv(const double *A, double *X, int k, int d) {
+  for (int c = threadIdx.x; c < k; c += blockDim.x)
+    for (int r = 0; r < k; ++r) {
+      double v = (r == c) ? 1.0 : 0.0;
+      for (int m = c; m < r; ++m) v -= A[r + (size_t)d * m] * X[m + (size_t)d * c];
+      X[r + (size_t)d * c] = (r < c) ? 0.0 : v / A[r + (size_t)d * r];
+    }
+  __syncthreads();
+}
+
+// ||M||_1, ||M||_inf and ||M||_F^2 of the k x k matrix M (ld d).
+__device__ void lnorms(const double *M, int k, int d, double *n1, double *ni, double *f2) {
+  double a1 = 0.0, ai = 0.0, af = 0.0;
+  for (int c = threadIdx.x; c < k; c += blockDim.x) {
+    double s = 0.0, t = 0.0;
+    for (int r = 0; r < k; ++r) {
+      s += fabs(M[r + (size_t)d * c]);
+      t += fabs(M[c + (size_t)d * r]);
+      af += M[r + (size_t)d * c] * M[r + (size_t)d * c];
+    }
+    a1 = fmax(a1, s);
+    ai = fmax(ai, t);
+  }
+  *n1 = lmax(a1);
+  *ni = lmax(ai);
+  *f2 = lsum(af);
+}
+
+// Rank-revealing pivoted Cholesky (as in the d <= 64 kernels), A in device memory.
+__device__ int lpivchol(double *A, int d, double tau, int *perm) {
+  __shared__ int piv, stop;
+  __shared__ double dmax0;
+  for (int i = threadIdx.x; i < d; i += blockDim.x) perm[i] = i;
+  double m = 0.0;
+  for (int i = threadIdx.x; i < d; i += blockDim.x) m = fmax(m, A[i + (size_t)d * i]);
+  m = lmax(m);
+  if (threadIdx.x == 0) dmax0 = m;
+  __syncthreads();
+  int k = d;
+  for (int j = 0; j < d; ++j) {
+    if (threadIdx.x == 0) {
+      int p = j;
+      double v = A[j + (size_t)d * j];
+      for (int i = j + 1; i < d; ++i)
+        if (A[i + (size_t)d * i] > v) {
+          v = A[i + (size_t)d * i];
+          p = i;
+        }
+      piv = p;
+      stop = !(v > tau * dmax0);
+    }
+    __syncthreads();
+    if (stop) {
+      k = j;
+      break;
+    }
+    const int p = piv;
+    if (p != j) {
+      for (int c = threadIdx.x; c < d; c += blockDim.x) {
+        const double t = A[j + (size_t)d * c];
+        A[j + (size_t)d * c] = A[p + (size_t)d * c];
+        A[p + (size_t)d * c] = t;
+      }
+      __syncthreads();
+      for (int r = threadIdx.x; r < d; r += blockDim.x) {
+        const double t = A[r + (size_t)d * j];
+        A[r + (size_t)d * j] = A[r + (size_t)d * p];
+        A[r + (size_t)d * p] = t;
+      }
+      if (threadIdx.x == 0) {
+        const int t = perm[j];
+        perm[j] = perm[p];
+        perm[p] = t;
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) A[j + (size_t)d * j] = sqrt(A[j + (size_t)d * j]);
+    __syncthreads();
+    const double ljj = A[j + (size_t)d * j];
+    for (int i = j + 1 + threadIdx.x; i < d; i += blockDim.x) A[i + (size_t)d * j] /= ljj;
+    __syncthreads();
+    const int n = d - j - 1;
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+      const int r = j + 1 + e % n, c = j + 1 + e / n;
+      A[r + (size_t)d * c] -= A[r + (size_t)d * j] * A[c + (size_t)d * j];
+    }
+    __syncthreads();
+  }
+  return k;
+}
+
+struct LStepArgs {
+  const double *G;     // d x d, lower triangle (dsyrk)
+  int d, pass, b;
+  const double *Rc;    // d x b (ld d), nullptr at the first pass
+  double *Fstep;       // d x k (ld d)
+  double *Rnext;       // k x b (ld k)
+  double *Tdst;        // b x k (ld b) once settled, or nullptr
+  int *dec;            // [0] k, [1] settled, [2] error flags, [5] no truncation proven
+  double tau1, tau2, ugram, gerr;
+  int notrunc_check;
+  const double *delta_dev;
+  int first;
+  double tol2_nm1;
+  double *W0, *W1;     // d x d scratch
+  int *perm;           // d scratch
+};
+
+// One QR-by-Gram step (the d <= 64 step's Cholesky-based routes).
+__global__ __launch_bounds__(kLT) void lk_step(LStepArgs a) {
+  const int d = a.d;
+  double *A = a.W0, *X = a.W1;
+  __shared__ int bad, accept;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  for (int e = threadIdx.x; e < d * d; e += blockDim.x) {
+    const int r = e % d, c = e / d;
+    const double g = (r >= c) ? a.G[e] : a.G[c + (size_t)d * r];
+    if (!lfinite(g)) bad = 1;
+    A[e] = g;
+  }
+  __syncthreads();
+  if (bad) {
+    if (threadIdx.x == 0) {
+      a.dec[2] |= 1;
+      a.dec[0] = 1;
+      a.dec[1] = 1;
+    }
+    return;
+  }
+  double tp = 0.0, glo = DBL_MAX, ghi = 0.0;
+  for (int r = threadIdx.x; r < d; r += blockDim.x) {
+    double off = 0.0;
+    for (int c = 0; c < d; ++c)
+      if (c != r) off += fabs(A[r + (size_t)d * c]);
+    tp += A[r + (size_t)d * r];
+    glo = fmin(glo, A[r + (size_t)d * r] - off);
+    ghi = fmax(ghi, A[r + (size_t)d * r] + off);
+  }
+  const double trG = lsum(tp), gmin = -lmax(-glo), gmax = lmax(ghi);
+  double g1 = 0.0;
+  for (int c = threadIdx.x; c < d; c += blockDim.x) {
+    double s = 0.0;
+    for (int r = 0; r < d; ++r) s += fabs(A[r + (size_t)d * c]);
+    g1 = fmax(g1, s);
+  }
+  g1 = lmax(g1);
+  const bool ok = lchol(A, d);
+  double kappa = 1e300, lmin_lb = 0.0;
+  if (ok) {
+    linv(A, X, d, d);
+    double x1, xi, xf;
+    lnorms(X, d, d, &x1, &xi, &xf);
+    kappa = g1 * x1 * xi;
+    lmin_lb = 1.0 / fmin(xf, x1 * xi);
+    if (gmin > 0.0) {
+      kappa = fmin(kappa, gmax / gmin);
+      lmin_lb = fmax(lmin_lb, gmin);
+    }
+  }
+  if (threadIdx.x == 0) {
+    int acc = ok && kappa == kappa && kappa * a.tau1 <= 1.0;
+    int nt = 0;
+    if (acc && a.notrunc_check && a.pass == 1) {
+      const double dl = a.first ? sqrt(a.tol2_nm1 * trG) : *a.delta_dev;
+      nt = (lmin_lb - a.gerr * trG > 4.0 * dl * dl);
+    }
+    accept = acc;
+    a.dec[5] = nt;
+  }
+  __syncthreads();
+  const int b = a.b;
+  if (accept) {
+    for (int e = threadIdx.x; e < d * d; e += blockDim.x) {
+      const int r = e % d, c = e / d;
+      a.Fstep[r + (size_t)d * c] = X[c + (size_t)d * r];  // F = L^{-T}
+    }
+    // R = L^T Rc (L^T at the first pass), T = R^T
+    for (int e = threadIdx.x; e < d * b; e += blockDim.x) {
+      const int r = e % d, col = e / d;
+      double v = 0.0;
+      if (a.Rc) {
+        for (int j = r; j < d; ++j) v += A[j + (size_t)d * r] * a.Rc[j + (size_t)d * col];
+      } else {
+        v = A[col + (size_t)d * r];
+      }
+      a.Rnext[r + (size_t)d * col] = v;
+      if (a.Tdst) a.Tdst[col + (size_t)b * r] = v;
+    }
+    if (threadIdx.x == 0) {
+      a.dec[0] = d;
+      a.dec[1] = 1;
+    }
+    return;
+  }
+  // restore G
+  for (int e = threadIdx.x; e < d * d; e += blockDim.x) {
+    const int r = e % d, c = e / d;
+    A[e] = (r >= c) ? a.G[e] : a.G[c + (size_t)d * r];
+  }
+  __syncthreads();
+  if (a.pass == 1) {
+    // shifted CholeskyQR: the next pass refines
+    const double shift = 2.0 * d * a.ugram * trG;
+    for (int j = threadIdx.x; j < d; j += blockDim.x) A[j + (size_t)d * j] += shift;
+    __syncthreads();
+    if (shift > 0.0 && lchol(A, d)) {
+      linv(A, X, d, d);
+      for (int e = threadIdx.x; e < d * d; e += blockDim.x) {
+        const int r = e % d, c = e / d;
+        a.Fstep[r + (size_t)d * c] = X[c + (size_t)d * r];
+        a.Rnext[r + (size_t)d * c] = A[c + (size_t)d * r];
+      }
+      if (threadIdx.x == 0) {
+        a.dec[0] = d;
+        a.dec[1] = 0;
+        a.dec[5] = 0;
+      }
+      return;
+    }
+    // a Gram too far from positive definite for the shift: pivoted below
+    for (int e = threadIdx.x; e < d * d; e += blockDim.x) {
+      const int r = e % d, c = e / d;
+      A[e] = (r >= c) ? a.G[e] : a.G[c + (size_t)d * r];
+    }
+    __syncthreads();
+  }
+  // rank-revealing pivoted Cholesky
+  int k = lpivchol(A, d, a.tau2, a.perm);
+  if (k == 0) {
+    // zero Gram: rank 1, zero factor
+    for (int e = threadIdx.x; e < d; e += blockDim.x) a.Fstep[e] = (e == 0) ? 1.0 : 0.0;
+    for (int e = threadIdx.x; e < b; e += blockDim.x) {
+      a.Rnext[e] = 0.0;
+      if (a.Tdst) a.Tdst[e] = 0.0;
+    }
+    if (threadIdx.x == 0) {
+      a.dec[0] = 1;
+      a.dec[1] = 1;
+      a.dec[5] = 0;
+    }
+    return;
+  }
+  linv(A, X, k, d);
+  double x1, xi, xf, gk = 0.0;
+  lnorms(X, k, d, &x1, &xi, &xf);
+  for (int c = threadIdx.x; c < k; c += blockDim.x) {
+    double s = 0.0;
+    for (int r = 0; r < k; ++r) {
+      const int pr = a.perm[r], pc = a.perm[c];
+      s += fabs((pr >= pc) ? a.G[pr + (size_t)d * pc] : a.G[pc + (size_t)d * pr]);
+    }
+    gk = fmax(gk, s);
+  }
+  gk = lmax(gk);
+  const int dn = (a.pass >= 3 || (a.pass >= 2 && gk * x1 * xi * a.tau1 <= 1.0)) ? 1 : 0;
+  for (int e = threadIdx.x; e < d * k; e += blockDim.x) a.Fstep[e] = 0.0;
+  __syncthreads();
+  for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
+    const int i = e % k, c = e / k;
+    a.Fstep[a.perm[i] + (size_t)d * c] = (c >= i) ? X[c + (size_t)d * i] : 0.0;
+  }
+  for (int e = threadIdx.x; e < k * b; e += blockDim.x) {
+    const int c = e % k, col = e / k;
+    double v = 0.0;
+    for (int j = c; j < d; ++j) {
+      const double rj = a.Rc ? a.Rc[a.perm[j] + (size_t)d * col] : (a.perm[j] == col ? 1.0 : 0.0);
+      v += A[j + (size_t)d * c] * rj;
+    }
+    a.Rnext[c + (size_t)k * col] = v;
+    if (dn && a.Tdst) a.Tdst[col + (size_t)b * c] = v;
+  }
+  if (threadIdx.x == 0) {
+    a.dec[0] = k;
+    a.dec[1] = dn;
+    a.dec[5] = 0;
+  }
+}
+
+struct LTruncArgs {
+  const double *R;      // k x b (ld k)
+  int k, b;
+  const double *Glast;  // d x k (ld d)
+  int d;
+  const double *Fn;     // dn x b (ld dn)
+  int dn;
+  double *GU;           // d x L
+  double *Pnext;        // L x dn
+  double *delta, *norm;
+  int first;
+  double tol;
+  int Nm1;
+  double *sigma_out;    // TTR_RMAX values
+  int *dec;             // [3] L, [2] error flags
+  int identity;
+  double *W0, *W1;      // scratch: W0 b x k (R^T), W1 k x k
+  double *sv;           // k
+  int *perm;            // k
+};
+
+__device__ inline void lrr_pair(int r, int kq, int nn, int *p, int *q) {
+  if (kq == 0) {
+    *p = r;
+    *q = nn - 1;
+  } else {
+    const int m = nn - 1;
+    *p = (r + kq) % m;
+    *q = (r - kq + m) % m;
+  }
+}
+
+// Truncation (Alg. 2 inner step): SVD of R by one-sided Jacobi on R^T, the
+// Frobenius-tail rank, GU = Glast U_L and Pnext = Sigma_L V_L^T Fn^T.
+__global__ __launch_bounds__(kLT) void lk_trunc(LTruncArgs a) {
+  const int k = a.k, b = a.b, d = a.d;
+  double *A = a.W0, *U = a.W1;
+  __shared__ int ident, flag, LL;
+  if (threadIdx.x == 0) ident = a.identity;
+  __syncthreads();
+  if (!ident && k == b) {
+    // upper-triangular R: sigma_min >= 1 / ||R^{-1}||_F proves that nothing can be dropped
+    __shared__ int tri_ok;
+    if (threadIdx.x == 0) tri_ok = 1;
+    __syncthreads();
+    for (int e = threadIdx.x; e < k * k; e += blockDim.x)
+      if (e % k > e / k && a.R[e] != 0.0) tri_ok = 0;
+    __syncthreads();
+    if (tri_ok) {
+      for (int c = threadIdx.x; c < k; c += blockDim.x)
+        for (int r = k - 1; r >= 0; --r) {
+          if (r > c) {
+            U[r + (size_t)k * c] = 0.0;
+            continue;
+          }
+          double v = (r == c) ? 1.0 : 0.0;
+          for (int m = r + 1; m <= c; ++m) v -= a.R[r + (size_t)k * m] * U[m + (size_t)k * c];
+          U[r + (size_t)k * c] = v / a.R[r + (size_t)k * r];
+        }
+      __syncthreads();
+      double xf = 0.0, rf = 0.0;
+      for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
+        xf += U[e] * U[e];
+        rf += a.R[e] * a.R[e];
+      }
+      xf = lsum(xf);
+      rf = lsum(rf);
+      if (threadIdx.x == 0) {
+        const double dl2 = a.first ? ((a.Nm1 > 0) ? a.tol * a.tol * rf / (double)a.Nm1 : 0.0) : (*a.delta) * (*a.delta);
+        ident = (xf > 0.0 && lfinite(xf) && 1.0 / xf > 4.0 * dl2) ? 1 : 0;
+      }
+      __syncthreads();
+    }
+  }
+  if (ident) {
+    double n2 = 0.0;
+    for (int e = threadIdx.x; e < k * b; e += blockDim.x) n2 += a.R[e] * a.R[e];
+    n2 = lsum(n2);
+    if (threadIdx.x == 0) {
+      if (a.first) {
+        const double nrm = sqrt(n2);
+        *a.norm = nrm;
+        *a.delta = (a.Nm1 > 0) ? a.tol * nrm / sqrt((double)a.Nm1) : 0.0;
+      }
+      for (int j = 0; j < TTR_RMAX; ++j) a.sigma_out[j] = 0.0;
+      a.dec[3] = k;
+    }
+    for (int e = threadIdx.x; e < d * k; e += blockDim.x) a.GU[e] = a.Glast[e];
+    for (int e = threadIdx.x; e < k * a.dn; e += blockDim.x) {
+      const int l = e % k, r = e / k;
+      double s = 0.0;
+      for (int j = 0; j < b; ++j) s += a.R[l + (size_t)k * j] * a.Fn[r + (size_t)a.dn * j];
+      a.Pnext[l + (size_t)k * r] = s;
+    }
+    return;
+  }
+  for (int e = threadIdx.x; e < b * k; e += blockDim.x) {
+    const int r = e % b, c = e / b;
+    A[r + (size_t)b * c] = a.R[c + (size_t)k * r];
+  }
+  for (int e = threadIdx.x; e < k * k; e += blockDim.x) U[e] = (e % k == e / k) ? 1.0 : 0.0;
+  __syncthreads();
+  double f2 = 0.0;
+  for (int e = threadIdx.x; e < b * k; e += blockDim.x) f2 += A[e] * A[e];
+  f2 = lsum(f2);
+  const double tol = kU * 4.0 * sqrt((double)(b > 1 ? b : 1));
+  const double floor2 = (8.0 * (b + k) * kU) * (8.0 * (b + k) * kU) * f2;
+  const int nn = k + (k & 1), npair = nn / 2;
+  constexpr int TPP = 8;  // threads per column pair (kLT / TPP >= 128 pairs)
+  const int pair = threadIdx.x / TPP, sub = threadIdx.x % TPP;
+  int sweeps = -1;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    if (threadIdx.x == 0) flag = 0;
+    __syncthreads();
+    for (int r = 0; r < nn - 1; ++r) {
+      int p = 0, q = 0;
+      const bool mine = pair < npair;
+      if (mine) lrr_pair(r, pair, nn, &p, &q);
+      const bool act = mine && p < k && q < k;
+      double al = 0.0, be = 0.0, ga = 0.0;
+      if (act)
+        for (int j = sub; j < b; j += TPP) {
+          const double ap = A[j + (size_t)b * p], aq = A[j + (size_t)b * q];
+          al += ap * ap;
+          be += aq * aq;
+          ga += ap * aq;
+        }
+      for (int off = 1; off < TPP; off <<= 1) {
+        al += __shfl_xor(al, off, 64);
+        be += __shfl_xor(be, off, 64);
+        ga += __shfl_xor(ga, off, 64);
+      }
+      if (act && al > floor2 && be > floor2 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
+        const double zeta = (be - al) / (2.0 * ga);
+        const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / sqrt(1.0 + t * t);
+        const double s = c * t;
+        for (int j = sub; j < b; j += TPP) {
+          const double ap = A[j + (size_t)b * p], aq = A[j + (size_t)b * q];
+          A[j + (size_t)b * p] = c * ap - s * aq;
+          A[j + (size_t)b * q] = s * ap + c * aq;
+        }
+        for (int j = sub; j < k; j += TPP) {
+          const double up = U[j + (size_t)k * p], uq = U[j + (size_t)k * q];
+          U[j + (size_t)k * p] = c * up - s * uq;
+          U[j + (size_t)k * q] = s * up + c * uq;
+        }
+        if (sub == 0) flag = 1;
+      }
+      __syncthreads();
+    }
+    const int any = flag;
+    __syncthreads();
+    if (!any) {
+      sweeps = sweep + 1;
+      break;
+    }
+  }
+  for (int j = threadIdx.x; j < k; j += blockDim.x) {
+    double s = 0.0;
+    for (int r = 0; r < b; ++r) s += A[r + (size_t)b * j] * A[r + (size_t)b * j];
+    a.sv[j] = sqrt(s);
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < k; j += blockDim.x) {
+    int rank = 0;
+    for (int i = 0; i < k; ++i)
+      if (a.sv[i] > a.sv[j] || (a.sv[i] == a.sv[j] && i < j)) ++rank;
+    a.perm[rank] = j;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (sweeps < 0) a.dec[2] |= 2;
+    if (a.first) {
+      double n2 = 0.0;
+      for (int j = k - 1; j >= 0; --j) n2 += a.sv[a.perm[j]] * a.sv[a.perm[j]];
+      const double nrm = sqrt(n2);
+      *a.norm = nrm;
+      *a.delta = (a.Nm1 > 0) ? a.tol * nrm / sqrt((double)a.Nm1) : 0.0;
+    }
+    const double delta = *a.delta;
+    double tail = 0.0;
+    int L = k;
+    for (int j = k - 1; j >= 1; --j) {
+      const double s = a.sv[a.perm[j]];
+      tail += s * s;
+      if (sqrt(tail) <= delta) L = j;
+      else break;
+    }
+    LL = L;
+    for (int j = 0; j < TTR_RMAX; ++j) a.sigma_out[j] = (j < k) ? a.sv[a.perm[j]] : 0.0;
+    a.dec[3] = L;
+  }
+  __syncthreads();
+  const int L = LL;
+  for (int e = threadIdx.x; e < d * L; e += blockDim.x) {
+    const int r = e % d, c = e / d;
+    const int pc = a.perm[c];
+    double s = 0.0;
+    for (int j = 0; j < k; ++j) s += a.Glast[r + (size_t)d * j] * U[j + (size_t)k * pc];
+    a.GU[r + (size_t)d * c] = s;
+  }
+  for (int e = threadIdx.x; e < L * a.dn; e += blockDim.x) {
+    const int l = e % L, r = e / L;
+    const int pc = a.perm[l];
+    double s = 0.0;
+    for (int j = 0; j < b; ++j) s += A[j + (size_t)b * pc] * a.Fn[r + (size_t)a.dn * j];
+    a.Pnext[l + (size_t)L * r] = s;
+  }
+}
+
+// --- host -------------------------------------------------------------------
+constexpr size_t kSlotL = (size_t)kLMax * kLMax;
+
+struct LWS {
+  double *tC, *tA, *tB;  // materialized cores (max core each)
+  double *G, *Ra, *Rb, *Gst[3], *P[2], *GU, *W0, *W1, *scal, *sigma, *sv;
+  std::vector<double *> T;                 // N+1 slots
+  std::vector<std::array<double *, 3>> B;  // N x 3 slots
+  int *perm;
+};
+
+}  // namespace
+
+struct LargeCtx {
+  rocblas_handle rb = nullptr;
+  double *mem = nullptr;
+  size_t bytes = 0;
+};
+
+void ttr_large_release(ttr_handle *h) {
+  if (!h || !h->large) return;
+  LargeCtx *c = h->large;
+  if (c->rb) rocblas_destroy_handle(c->rb);
+  if (c->mem) (void)hipFree(c->mem);
+  delete c;
+  h->large = nullptr;
+}
+
+namespace {
+
+#define RBCHK(expr)                                                                           \
+  do {                                                                                        \
+    rocblas_status s_ = (expr);                                                               \
+    if (s_ != rocblas_status_success)                                                         \
+      return ttr_fail(TTR_ERR_HIP, std::string(#expr) + ": " + rocblas_status_to_string(s_)); \
+  } while (0)
+
+struct Large {
+  ttr_handle *h;
+  rocblas_handle rb;
+  LWS w;
+  int passes = 0, applies = 0;
+
+  // C (m x n, ld ldc) = op(A) op(B), op(A) m x k
+  int gemm(bool ta, bool tb, long long m, long long n, long long k, const double *A, long long lda, const double *B,
+           long long ldb, double *C, long long ldc) {
+    const double one = 1.0, zero = 0.0;
+    RBCHK(rocblas_dgemm(rb, ta ? rocblas_operation_transpose : rocblas_operation_none,
+                        tb ? rocblas_operation_transpose : rocblas_operation_none, (rocblas_int)m, (rocblas_int)n,
+                        (rocblas_int)k, &one, A, (rocblas_int)lda, B, (rocblas_int)ldb, &zero, C, (rocblas_int)ldc));
+    return TTR_OK;
+  }
+  // G (n x n, lower) = Z Z^T (Z n x k, ld n) or Z^T Z (Z k x n, ld k)
+  int syrk(bool trans, long long n, long long k, const double *Z, long long ldz, double *G) {
+    const double one = 1.0, zero = 0.0;
+    RBCHK(rocblas_dsyrk(rb, rocblas_fill_lower, trans ? rocblas_operation_transpose : rocblas_operation_none,
+                        (rocblas_int)n, (rocblas_int)k, &one, Z, (rocblas_int)ldz, &zero, G, (rocblas_int)n));
+    ++passes;
+    return TTR_OK;
+  }
+  int sync_dec() {
+    TTR_HIPCHK(hipMemcpyAsync(h->dec_host, h->dec_dev, 16 * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    TTR_HIPCHK(hipStreamSynchronize(h->stream));
+    TTR_HIPCHK(hipGetLastError());
+    if (h->dec_host[2] != 0)
+      return ttr_fail(TTR_ERR_NUMERICAL, "non-finite data or a small factorization did not converge");
+    return TTR_OK;
+  }
+  int step(const double *Rc, int d, int b, int pass, double *F, double *Rn, double *Tdst, double gerr, int check,
+           int first, double tol2_nm1) {
+    LStepArgs a;
+    a.G = w.G;
+    a.d = d;
+    a.pass = pass;
+    a.b = b;
+    a.Rc = Rc;
+    a.Fstep = F;
+    a.Rnext = Rn;
+    a.Tdst = Tdst;
+    a.dec = h->dec_dev;
+    a.tau1 = kTau1;
+    a.tau2 = kTau2;
+    a.ugram = kU;
+    a.gerr = gerr;
+    a.notrunc_check = check;
+    a.delta_dev = w.scal + 1;
+    a.first = first;
+    a.tol2_nm1 = tol2_nm1;
+    a.W0 = w.W0;
+    a.W1 = w.W1;
+    a.perm = w.perm;
+    hipLaunchKernelGGL(lk_step, dim3(1), dim3(kLT), 0, h->stream, a);
+    h->stats.small_launches++;
+    return sync_dec();
+  }
+};
+
+// rounding of a Gram entry summed over nacc products (any summation order)
+double gerr_of(long long nacc) { return 2.0 * ((double)nacc + 16.0) * kU; }
+
+}  // namespace
+
+// Rounding of X (ranks up to 256, RLR) into Y; arithmetic in FP64.
+int ttr_round_large(ttr_handle *h, const ttr_tt *X, double tol, ttr_tt *Y, double *norm_out) {
+  const int N = X->N;
+  size_t mc = 0;
+  for (int n = 0; n < N; ++n) mc = std::max(mc, (size_t)(X->R[n] * X->I[n] * X->R[n + 1]));
+  mc = (mc + 63) & ~(size_t)63;
+  const size_t need = ((size_t)(N + 1) + 3 * (size_t)N + 13) * kSlotL + 64 + (size_t)(N + 1) * TTR_RMAX + kLMax +
+                      kLMax + 3 * mc + 64;
+  if (!h->large) h->large = new LargeCtx();
+  LargeCtx *ctx = h->large;
+  if (!ctx->rb) RBCHK(rocblas_create_handle(&ctx->rb));
+  RBCHK(rocblas_set_stream(ctx->rb, h->stream));
+  RBCHK(rocblas_set_pointer_mode(ctx->rb, rocblas_pointer_mode_host));
+  if (ctx->bytes < need * sizeof(double)) {
+    if (ctx->mem) {
+      TTR_HIPCHK(hipStreamSynchronize(h->stream));
+      TTR_HIPCHK(hipFree(ctx->mem));
+      ctx->mem = nullptr;
+      ctx->bytes = 0;
+    }
+    if (hipMalloc(&ctx->mem, need * sizeof(double)) != hipSuccess) {
+      ctx->mem = nullptr;
+      return ttr_fail(TTR_ERR_ALLOC, "workspace allocation of " + std::to_string(need * sizeof(double)) + " bytes failed");
+    }
+    ctx->bytes = need * sizeof(double);
+  }
+  Large L;
+  L.h = h;
+  L.rb = ctx->rb;
+  LWS &w = L.w;
+  double *p = ctx->mem;
+  auto take = [&](size_t n) {
+    double *q = p;
+    p += n;
+    return q;
+  };
+  w.G = take(kSlotL);
+  w.Ra = take(kSlotL);
+  w.Rb = take(kSlotL);
+  for (int j = 0; j < 3; ++j) w.Gst[j] = take(kSlotL);
+  for (int j = 0; j < 2; ++j) w.P[j] = take(kSlotL);
+  w.GU = take(kSlotL);
+  w.W0 = take(kSlotL);
+  w.W1 = take(kSlotL);
+  w.scal = take(64);
+  w.sigma = take((size_t)(N + 1) * TTR_RMAX);
+  w.sv = take(kLMax);
+  w.perm = reinterpret_cast<int *>(take(kLMax));
+  w.T.resize(N + 1);
+  w.B.resize(N);
+  for (int n = 0; n <= N; ++n) w.T[n] = take(kSlotL);
+  for (int n = 0; n < N; ++n)
+    for (int j = 0; j < 3; ++j) w.B[n][j] = take(kSlotL);
+  w.tC = take(mc);
+  w.tA = take(mc);
+  w.tB = take(mc);
+  for (int i = 0; i < 16; ++i) h->dec_host[i] = 0;
+  TTR_HIPCHK(hipMemcpyAsync(h->dec_dev, h->dec_host, 16 * sizeof(int), hipMemcpyHostToDevice, h->stream));
+
+  std::vector<int> k(N + 1), nst(N, 1);
+  std::vector<std::array<int, 4>> dim(N);
+  for (int n = 0; n <= N; ++n) k[n] = (int)X->R[n];
+  int rc;
+  // ---- sweep 1: right-to-left orthonormalization with implicit factors ----
+  for (int n = N - 1; n >= 1; --n) {
+    const long long a = X->R[n], b = X->R[n + 1], In = X->I[n];
+    const double *src = X->core[n];
+    long long sc = b;
+    if (n < N - 1) {  // C = M x_3 T_{n+1}^T
+      if ((rc = L.gemm(false, false, a * In, k[n + 1], b, X->core[n], a * In, w.T[n + 1], b, w.tC, a * In))) return rc;
+      src = w.tC;
+      sc = k[n + 1];
+    }
+    double *bufs[2] = {w.tA, w.tB};
+    double *R[2] = {w.Ra, w.Rb};
+    const double *cur = src;
+    long long crow = a;
+    dim[n][0] = (int)a;
+    int pass = 1;
+    for (;; ++pass) {
+      if ((rc = L.syrk(false, crow, In * sc, cur, crow, w.G))) return rc;
+      const double ge = gerr_of(In * sc);
+      if ((rc = L.step(pass == 1 ? nullptr : R[pass & 1], (int)crow, (int)a, pass, w.B[n][pass - 1],
+                       R[(pass - 1) & 1], w.T[n], ge, 0, 0, 0.0)))
+        return rc;
+      const int kk = h->dec_host[0];
+      dim[n][pass] = kk;
+      if (h->dec_host[1]) break;
+      // D = F_pass^T H(cur)
+      if ((rc = L.gemm(true, false, kk, In * sc, crow, w.B[n][pass - 1], crow, cur, crow, bufs[(pass - 1) & 1], kk)))
+        return rc;
+      cur = bufs[(pass - 1) & 1];
+      crow = kk;
+    }
+    nst[n] = pass;
+    k[n] = dim[n][pass];
+  }
+  // ---- sweep 2: left-to-right truncation --------------------------------------
+  std::vector<int> Lr(N + 1, 1);
+  const double *Pcur = nullptr;
+  int Lprev = 1;
+  for (int n = 0; n < N - 1; ++n) {
+    const long long a = X->R[n], b = X->R[n + 1], In = X->I[n];
+    // C_n = M_n x_3 T_{n+1}^T, then the left stages F_1^T .. F_{nst-1}^T and P
+    if ((rc = L.gemm(false, false, a * In, k[n + 1], b, X->core[n], a * In, w.T[n + 1], b, w.tC, a * In))) return rc;
+    const long long cc = k[n + 1];
+    const double *cur = w.tC;
+    long long crow = a;
+    double *bufs[2] = {w.tA, w.tB};
+    int nb = 0;  // next buffer index (matches the orthonormalization sweep's order)
+    if (n >= 1) {
+      for (int j = 1; j < nst[n]; ++j) {
+        if ((rc = L.gemm(true, false, dim[n][j], In * cc, crow, w.B[n][j - 1], crow, cur, crow, bufs[(j - 1) & 1],
+                         dim[n][j])))
+          return rc;
+        cur = bufs[(j - 1) & 1];
+        crow = dim[n][j];
+        nb = j & 1;
+      }
+      double *out = (cur == w.tC) ? w.tA : ((cur == w.tA) ? w.tB : w.tA);
+      if ((rc = L.gemm(false, false, Lprev, In * cc, crow, Pcur, Lprev, cur, crow, out, Lprev))) return rc;
+      cur = out;
+      crow = Lprev;
+    }
+    (void)nb;
+    // QR-by-Gram of V(C'_n) ((crow I) x cc)
+    double *R[2] = {w.Ra, w.Rb};
+    int g = 1;
+    int gd[4];
+    gd[0] = (int)cc;
+    const double *E = cur;
+    int notrunc = 0;
+    for (;; ++g) {
+      if ((rc = L.syrk(true, gd[g - 1], crow * In, E, crow * In, w.G))) return rc;
+      const double ge = gerr_of(crow * In);
+      if ((rc = L.step(g == 1 ? nullptr : R[g & 1], gd[g - 1], (int)cc, g, w.Gst[g - 1], R[(g - 1) & 1], nullptr, ge,
+                       1, n == 0, tol * tol / (double)(N - 1))))
+        return rc;
+      gd[g] = h->dec_host[0];
+      if (g == 1) notrunc = h->dec_host[5];
+      if (h->dec_host[1]) break;
+      // E <- V(E) G_g
+      double *out = (E == w.tA) ? w.tB : w.tA;
+      if (E == w.tC) out = w.tA;
+      if ((rc = L.gemm(false, false, crow * In, gd[g], gd[g - 1], E, crow * In, w.Gst[g - 1], gd[g - 1], out, crow * In)))
+        return rc;
+      E = out;
+    }
+    // truncation
+    LTruncArgs ta;
+    ta.R = R[(g - 1) & 1];
+    ta.k = gd[g];
+    ta.b = (int)cc;
+    ta.Glast = w.Gst[g - 1];
+    ta.d = gd[g - 1];
+    ta.Fn = w.B[n + 1][nst[n + 1] - 1];
+    ta.dn = dim[n + 1][nst[n + 1] - 1];
+    ta.GU = w.GU;
+    ta.Pnext = w.P[n & 1];
+    ta.delta = w.scal + 1;
+    ta.norm = w.scal + 2;
+    ta.first = (n == 0);
+    ta.tol = tol;
+    ta.Nm1 = N - 1;
+    ta.sigma_out = w.sigma + (size_t)n * TTR_RMAX;
+    ta.dec = h->dec_dev;
+    ta.identity = (g == 1) ? notrunc : 0;
+    ta.W0 = w.W0;
+    ta.W1 = w.W1;
+    ta.sv = w.sv;
+    ta.perm = w.perm;
+    hipLaunchKernelGGL(lk_trunc, dim3(1), dim3(kLT), 0, h->stream, ta);
+    h->stats.small_launches++;
+    if ((rc = L.sync_dec())) return rc;
+    const int Ln = h->dec_host[3];
+    Lr[n + 1] = Ln;
+    // output core n: V(Y_n) = V(E) GU
+    if ((rc = L.gemm(false, false, crow * In, Ln, gd[g - 1], E, crow * In, w.GU, gd[g - 1], Y->core[n], crow * In)))
+      return rc;
+    ++L.applies;
+    Pcur = w.P[n & 1];
+    Lprev = Ln;
+  }
+  {
+    // last core: P F_{nst-1}^T .. F_1^T H(M_N)
+    const int n = N - 1;
+    const long long a = X->R[n], In = X->I[n], cc = X->R[n + 1];
+    const double *cur = X->core[n];
+    long long crow = a;
+    double *bufs[2] = {w.tA, w.tB};
+    for (int j = 1; j < nst[n]; ++j) {
+      if ((rc = L.gemm(true, false, dim[n][j], In * cc, crow, w.B[n][j - 1], crow, cur, crow, bufs[(j - 1) & 1],
+                       dim[n][j])))
+        return rc;
+      cur = bufs[(j - 1) & 1];
+      crow = dim[n][j];
+    }
+    if ((rc = L.gemm(false, false, Lprev, In * cc, crow, Pcur, Lprev, cur, crow, Y->core[n], Lprev))) return rc;
+    ++L.applies;
+  }
+  TTR_HIPCHK(hipGetLastError());
+  TTR_HIPCHK(hipMemcpyAsync(h->scal_host, w.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  const int nsig = (N - 1) * TTR_RMAX;
+  std::vector<double> sig(nsig);
+  TTR_HIPCHK(hipMemcpyAsync(sig.data(), w.sigma, nsig * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  TTR_HIPCHK(hipStreamSynchronize(h->stream));
+  for (int l = 0; l <= N; ++l) Y->R[l] = (l == 0 || l == N) ? 1 : Lr[l];
+  h->stats.gram_passes = L.passes;
+  h->stats.apply_passes = L.applies;
+  h->stats.links = N - 1;
+  h->stats.norm = h->scal_host[2];
+  h->stats.delta = h->scal_host[1];
+  const int nl = (N - 1) < 64 ? (N - 1) : 64;
+  for (int l = 0; l < nl; ++l) {
+    int cnt = 0;
+    for (int j = 0; j < TTR_RMAX; ++j) {
+      h->stats.sigma[l * TTR_RMAX + j] = sig[(size_t)l * TTR_RMAX + j];
+      if (sig[(size_t)l * TTR_RMAX + j] > 0) cnt = j + 1;
+    }
+    h->stats.nsigma[l] = cnt;
+  }
+  if (norm_out) *norm_out = h->scal_host[2];
+  return TTR_OK;
+}
