@@ -1,7 +1,7 @@
 // TT rounding for ranks above the register/LDS-tiled range (64 < R <= 256):
 // the same algorithm as the single-tensor path (§2.4 Alg. 2, RLR; QR-by-Gram
 // for the tall-skinny QRs of §3.3-§3.5), with every streaming product written
-// as a plain GEMM or SYRK on a contiguous unfolding and every small
+// as a plain GEMM on a contiguous unfolding and every small
 // factorization done by one workgroup on matrices held in device memory.
 //
 // Unfoldings of a core M (a x I x b, entry (i1, i, i2) at i1 + a*(i + I*i2)):
@@ -9,8 +9,8 @@
 // Products used:
 //   C = M x_3 T^T        V(C) = V(M) T              (dgemm)
 //   D = F^T x_1 C        H(D) = F^T H(C)            (dgemm)
-//   LEFT Gram            H(Z) H(Z)^T                (dsyrk, lower)
-//   RIGHT Gram           V(Z)^T V(Z)                (dsyrk, lower)
+//   LEFT Gram            H(Z) H(Z)^T                (chunked dgemm + reduction)
+//   RIGHT Gram           V(Z)^T V(Z)                (chunked dgemm + reduction)
 // Every refinement stage is applied to a materialized core, and the
 // truncation sweep rebuilds the orthonormalization sweep's intermediates with
 // the same calls, so each stage is applied to bitwise the data its Gram was
@@ -191,7 +191,7 @@ __device__ int lpivchol(double *A, int d, double tau, int *perm) {
 }
 
 struct LStepArgs {
-  const double *G;     // d x d, lower triangle (dsyrk)
+  const double *G;     // d x d (its lower triangle is read)
   int d, pass, b;
   const double *Rc;    // d x b (ld d), nullptr at the first pass
   double *Fstep;       // d x k (ld d)
@@ -486,46 +486,71 @@ __global__ __launch_bounds__(kLT) void lk_trunc(LTruncArgs a) {
   const double tol = kU * 4.0 * sqrt((double)(b > 1 ? b : 1));
   const double floor2 = (8.0 * (b + k) * kU) * (8.0 * (b + k) * kU) * f2;
   const int nn = k + (k & 1), npair = nn / 2;
-  constexpr int TPP = 8;  // threads per column pair (kLT / TPP >= 128 pairs)
-  const int pair = threadIdx.x / TPP, sub = threadIdx.x % TPP;
+  // 16 threads per column pair, 16 rows each, loads issued together; the 128
+  // pairs of a round take two passes of the 64 pair groups
+  constexpr int TPP = 16, RPT = kLMax / TPP, GROUPS = kLT / TPP;
+  const int grp = threadIdx.x / TPP, sub = threadIdx.x % TPP;
   int sweeps = -1;
   for (int sweep = 0; sweep < 60; ++sweep) {
     if (threadIdx.x == 0) flag = 0;
     __syncthreads();
     for (int r = 0; r < nn - 1; ++r) {
-      int p = 0, q = 0;
-      const bool mine = pair < npair;
-      if (mine) lrr_pair(r, pair, nn, &p, &q);
-      const bool act = mine && p < k && q < k;
-      double al = 0.0, be = 0.0, ga = 0.0;
-      if (act)
-        for (int j = sub; j < b; j += TPP) {
-          const double ap = A[j + (size_t)b * p], aq = A[j + (size_t)b * q];
-          al += ap * ap;
-          be += aq * aq;
-          ga += ap * aq;
+      for (int pass = 0; pass * GROUPS < npair; ++pass) {
+        const int pair = grp + pass * GROUPS;
+        int p = 0, q = 0;
+        const bool mine = pair < npair;
+        if (mine) lrr_pair(r, pair, nn, &p, &q);
+        const bool act = mine && p < k && q < k;
+        double ap[RPT], aq[RPT];
+#pragma unroll
+        for (int t = 0; t < RPT; ++t) {
+          const int j = sub + TPP * t;
+          const bool in = act && j < b;
+          ap[t] = in ? A[j + (size_t)b * p] : 0.0;
+          aq[t] = in ? A[j + (size_t)b * q] : 0.0;
         }
-      for (int off = 1; off < TPP; off <<= 1) {
-        al += __shfl_xor(al, off, 64);
-        be += __shfl_xor(be, off, 64);
-        ga += __shfl_xor(ga, off, 64);
-      }
-      if (act && al > floor2 && be > floor2 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
-        const double zeta = (be - al) / (2.0 * ga);
-        const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double c = 1.0 / sqrt(1.0 + t * t);
-        const double s = c * t;
-        for (int j = sub; j < b; j += TPP) {
-          const double ap = A[j + (size_t)b * p], aq = A[j + (size_t)b * q];
-          A[j + (size_t)b * p] = c * ap - s * aq;
-          A[j + (size_t)b * q] = s * ap + c * aq;
+        double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+        for (int t = 0; t < RPT; ++t) {
+          al += ap[t] * ap[t];
+          be += aq[t] * aq[t];
+          ga += ap[t] * aq[t];
         }
-        for (int j = sub; j < k; j += TPP) {
-          const double up = U[j + (size_t)k * p], uq = U[j + (size_t)k * q];
-          U[j + (size_t)k * p] = c * up - s * uq;
-          U[j + (size_t)k * q] = s * up + c * uq;
+        for (int off = 1; off < TPP; off <<= 1) {
+          al += __shfl_xor(al, off, 64);
+          be += __shfl_xor(be, off, 64);
+          ga += __shfl_xor(ga, off, 64);
         }
-        if (sub == 0) flag = 1;
+        if (act && al > floor2 && be > floor2 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
+          const double zeta = (be - al) / (2.0 * ga);
+          const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double c = 1.0 / sqrt(1.0 + t * t);
+          const double s = c * t;
+#pragma unroll
+          for (int u = 0; u < RPT; ++u) {
+            const int j = sub + TPP * u;
+            if (j < b) {
+              A[j + (size_t)b * p] = c * ap[u] - s * aq[u];
+              A[j + (size_t)b * q] = s * ap[u] + c * aq[u];
+            }
+          }
+          double up[RPT], uq[RPT];
+#pragma unroll
+          for (int u = 0; u < RPT; ++u) {
+            const int j = sub + TPP * u;
+            up[u] = (j < k) ? U[j + (size_t)k * p] : 0.0;
+            uq[u] = (j < k) ? U[j + (size_t)k * q] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < RPT; ++u) {
+            const int j = sub + TPP * u;
+            if (j < k) {
+              U[j + (size_t)k * p] = c * up[u] - s * uq[u];
+              U[j + (size_t)k * q] = s * up[u] + c * uq[u];
+            }
+          }
+          if (sub == 0) flag = 1;
+        }
       }
       __syncthreads();
     }
@@ -591,10 +616,12 @@ __global__ __launch_bounds__(kLT) void lk_trunc(LTruncArgs a) {
 
 // --- host -------------------------------------------------------------------
 constexpr size_t kSlotL = (size_t)kLMax * kLMax;
+constexpr int kChunks = 256;  // chunk Grams per streamed Gram
 
 struct LWS {
   double *tC, *tA, *tB;  // materialized cores (max core each)
   double *G, *Ra, *Rb, *Gst[3], *P[2], *GU, *W0, *W1, *scal, *sigma, *sv;
+  double *part;  // kChunks chunk Grams
   std::vector<double *> T;                 // N+1 slots
   std::vector<std::array<double *, 3>> B;  // N x 3 slots
   int *perm;
@@ -641,11 +668,29 @@ struct Large {
                         (rocblas_int)k, &one, A, (rocblas_int)lda, B, (rocblas_int)ldb, &zero, C, (rocblas_int)ldc));
     return TTR_OK;
   }
-  // G (n x n, lower) = Z Z^T (Z n x k, ld n) or Z^T Z (Z k x n, ld k)
-  int syrk(bool trans, long long n, long long k, const double *Z, long long ldz, double *G) {
+  // G (n x n) = Z Z^T (trans = false: Z n x k, ld ldz) or Z^T Z (trans = true:
+  // Z k x n, ld ldz).  k is in the millions and n <= 256, so the sum over k is
+  // split into chunks: one strided-batched GEMM gives the chunk Grams, and the
+  // fixed-order reduction adds them.
+  int gram(bool trans, long long n, long long k, const double *Z, long long ldz, double *G) {
     const double one = 1.0, zero = 0.0;
-    RBCHK(rocblas_dsyrk(rb, rocblas_fill_lower, trans ? rocblas_operation_transpose : rocblas_operation_none,
-                        (rocblas_int)n, (rocblas_int)k, &one, Z, (rocblas_int)ldz, &zero, G, (rocblas_int)n));
+    long long S = std::min<long long>(kChunks, std::max<long long>(1, k / 2048));
+    const long long ks = (k + S - 1) / S;
+    const long long full = k / ks, rem = k - full * ks;
+    const long long nn = n * n;
+    const rocblas_operation tA = trans ? rocblas_operation_transpose : rocblas_operation_none;
+    const rocblas_operation tB = trans ? rocblas_operation_none : rocblas_operation_transpose;
+    const long long step = trans ? ks : ks * ldz;  // offset between chunks
+    if (full > 0)
+      RBCHK(rocblas_dgemm_strided_batched(rb, tA, tB, (rocblas_int)n, (rocblas_int)n, (rocblas_int)ks, &one, Z,
+                                          (rocblas_int)ldz, step, Z, (rocblas_int)ldz, step, &zero, w.part,
+                                          (rocblas_int)n, nn, (rocblas_int)full));
+    if (rem > 0) {
+      const double *Zr = Z + full * step;
+      RBCHK(rocblas_dgemm(rb, tA, tB, (rocblas_int)n, (rocblas_int)n, (rocblas_int)rem, &one, Zr, (rocblas_int)ldz, Zr,
+                          (rocblas_int)ldz, &zero, w.part + full * nn, (rocblas_int)n));
+    }
+    launch_reduce(h->stream, w.part, (int)(full + (rem > 0)), (int)nn, G);
     ++passes;
     return TTR_OK;
   }
@@ -697,8 +742,8 @@ int ttr_round_large(ttr_handle *h, const ttr_tt *X, double tol, ttr_tt *Y, doubl
   size_t mc = 0;
   for (int n = 0; n < N; ++n) mc = std::max(mc, (size_t)(X->R[n] * X->I[n] * X->R[n + 1]));
   mc = (mc + 63) & ~(size_t)63;
-  const size_t need = ((size_t)(N + 1) + 3 * (size_t)N + 13) * kSlotL + 64 + (size_t)(N + 1) * TTR_RMAX + kLMax +
-                      kLMax + 3 * mc + 64;
+  const size_t need = ((size_t)(N + 1) + 3 * (size_t)N + 13 + kChunks) * kSlotL + 64 + (size_t)(N + 1) * TTR_RMAX +
+                      kLMax + kLMax + 3 * mc + 64;
   if (!h->large) h->large = new LargeCtx();
   LargeCtx *ctx = h->large;
   if (!ctx->rb) RBCHK(rocblas_create_handle(&ctx->rb));
@@ -744,6 +789,7 @@ int ttr_round_large(ttr_handle *h, const ttr_tt *X, double tol, ttr_tt *Y, doubl
   for (int n = 0; n <= N; ++n) w.T[n] = take(kSlotL);
   for (int n = 0; n < N; ++n)
     for (int j = 0; j < 3; ++j) w.B[n][j] = take(kSlotL);
+  w.part = take((size_t)kChunks * kSlotL);
   w.tC = take(mc);
   w.tA = take(mc);
   w.tB = take(mc);
@@ -771,7 +817,7 @@ int ttr_round_large(ttr_handle *h, const ttr_tt *X, double tol, ttr_tt *Y, doubl
     dim[n][0] = (int)a;
     int pass = 1;
     for (;; ++pass) {
-      if ((rc = L.syrk(false, crow, In * sc, cur, crow, w.G))) return rc;
+      if ((rc = L.gram(false, crow, In * sc, cur, crow, w.G))) return rc;
       const double ge = gerr_of(In * sc);
       if ((rc = L.step(pass == 1 ? nullptr : R[pass & 1], (int)crow, (int)a, pass, w.B[n][pass - 1],
                        R[(pass - 1) & 1], w.T[n], ge, 0, 0, 0.0)))
@@ -824,7 +870,7 @@ int ttr_round_large(ttr_handle *h, const ttr_tt *X, double tol, ttr_tt *Y, doubl
     const double *E = cur;
     int notrunc = 0;
     for (;; ++g) {
-      if ((rc = L.syrk(true, gd[g - 1], crow * In, E, crow * In, w.G))) return rc;
+      if ((rc = L.gram(true, gd[g - 1], crow * In, E, crow * In, w.G))) return rc;
       const double ge = gerr_of(crow * In);
       if ((rc = L.step(g == 1 ? nullptr : R[g & 1], gd[g - 1], (int)cc, g, w.Gst[g - 1], R[(g - 1) & 1], nullptr, ge,
                        1, n == 0, tol * tol / (double)(N - 1))))
