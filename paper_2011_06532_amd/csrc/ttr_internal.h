@@ -65,8 +65,9 @@ void launch_apply(hipStream_t s, const CoreView &cv, const Stages &st, double *Y
 // f32: the mixed-precision first pass (FP32 products and accumulation).
 int launch_gram_right_factor(hipStream_t s, const double *X, int a, int b, long long I, const double *Q, int q,
                              long long sQr, long long sQc, int tri, int f32, double *partials);
+// Yout (FP64 only, may be nullptr): also writes P X_i as a p x I x b core.
 int launch_gram_left_factor(hipStream_t s, const double *X, int a, int b, long long I, const double *P, int p,
-                            long long sPr, long long sPa, int tri, int f32, double *partials);
+                            long long sPr, long long sPa, int tri, int f32, double *partials, double *Yout = nullptr);
 void launch_apply_mfma(hipStream_t s, const double *X, int a, int b, long long I, const double *P, int p,
                        long long sPr, long long sPa, const double *Q, int q, long long sQr, long long sQc,
                        double *Y);

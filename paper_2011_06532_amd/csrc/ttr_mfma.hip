@@ -137,6 +137,33 @@ __device__ inline void load_slice(const double *__restrict__ Xi, long long col, 
     }
 }
 
+// Writes a wave's result tiles as an nrow x ncol block of one output slice:
+// register r of tile (u, c) holds row 16u + row(g, r), column 16c + j; column
+// c of the slice starts at Yi + ocol * c with its rows contiguous.  Each
+// 16-column tile goes through the wave's LDS buffer Lw (ld LDP) so that the
+// stores leave as runs of consecutive rows, not 16 scattered 32-byte pieces.
+template <int NT, class A, class VT>
+__device__ inline void store_tiles(const VT (&y)[NT][NT], int nrow, int ncol, double *__restrict__ Yi, long long ocol,
+                                   double *Lw, int LDP, int lane, int g, int j) {
+#pragma unroll
+  for (int c = 0; c < NT; ++c) {
+    if (c * 16 >= ncol) break;
+    __asm__ volatile("" ::: "memory");
+#pragma unroll
+    for (int u = 0; u < NT; ++u)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Lw[(u * 16 + A::row(g, r)) + LDP * j] = (double)y[u][c][r];
+    // one wave owns Lw and its LDS operations complete in order
+    __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    const int nc = min(16, ncol - c * 16);
+    for (int e = lane; e < nrow * nc; e += 64) {
+      const int rr = e % nrow, jj = e / nrow;
+      Yi[rr + ocol * (c * 16 + jj)] = Lw[rr + LDP * jj];
+    }
+    __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Gram with a right factor: G (a x a) = sum_i (M_i Q)(M_i Q)^T, M_i = X(:, i, :)
 // (a x b), Q (b x q).  The left Gram of the horizontal unfolding of X x_3 Q^T
@@ -236,13 +263,16 @@ __global__ __launch_bounds__(kThreads) void k_gram_right_factor(const double *__
 // The Gram of the vertical unfolding of P x_1 X (truncation sweep, §2.4).
 // KS = k-steps over a (ceil(a/4)).
 // ---------------------------------------------------------------------------
-template <int NT, int KS, class A, bool GD = false>
+template <int NT, int KS, class A, bool GD = false, bool ST = false>
 __device__ __forceinline__ void gram_left_factor_body(const int wg, const double *__restrict__ X, int a, int b, long long I,
                                                                const double *__restrict__ P, int p, long long sPr,
                                                                long long sPa, int tri, long long spw,
-                                                               double *__restrict__ partials) {
+                                                               double *__restrict__ partials,
+                                                               double *__restrict__ Yout = nullptr) {
   using T = typename A::T;
   using V = typename A::V;
+  // ST: the product Y_i = P M_i is also written, as a p x I x b core (FP64), for
+  // the output pass that follows to reuse.
   // The product contracts over alpha, which the operand layout puts on the
   // slow lane index; read directly, every load would touch 16 columns.  So
   // slices are read coalesced (16 consecutive alpha per lane group) and turned
@@ -257,6 +287,7 @@ __device__ __forceinline__ void gram_left_factor_body(const int wg, const double
   __shared__ T frag[NT * KS * 64];
   __shared__ __align__(16) char smem[GS_BYTES > ST_BYTES ? GS_BYTES : ST_BYTES];
   double *Gs = reinterpret_cast<double *>(smem);  // after the slice loop only
+  __shared__ double Lys[(ST && !STAGE) ? kWaves * LDT * 16 : 1];  // product staging (FP64, NT = 4)
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, j = lane & 15;
   const int ksr = (a + 3) / 4, ntp = (p + 15) / 16, ntb = (b + 15) / 16;  // GD: run-time extents
@@ -313,6 +344,12 @@ __device__ __forceinline__ void gram_left_factor_body(const int wg, const double
         for (int t = 0; t < NT; ++t)
           if (!GD || t < ntb) y[rb][t] = A::mma(pa, cur[ks][t], y[rb][t]);
       }
+    if constexpr (ST) {
+      // the slice's staging tile has been read into cur: reuse it (or the
+      // dedicated buffer when slices are not staged)
+      double *Lw = STAGE ? reinterpret_cast<double *>(Ls) : Lys + wave * LDT * 16;
+      store_tiles<NT, A>(y, p, b, Yout + (long long)p * i, (long long)p * I, Lw, LDT, lane, g, j);
+    }
     // G0(beta, beta') += sum_rho Y(rho, beta) Y(rho, beta'); rows past p are padding
 #pragma unroll
     for (int rb = 0; rb < NT; ++rb)
@@ -330,12 +367,13 @@ __device__ __forceinline__ void gram_left_factor_body(const int wg, const double
   reduce_gram<NT, A>(G, NT, b, Gs, partials + (long long)wg * b * b);
 }
 
-template <int NT, int KS, class A>
+template <int NT, int KS, class A, bool ST = false>
 __global__ __launch_bounds__(kThreads) void k_gram_left_factor(const double *__restrict__ X, int a, int b, long long I,
                                                                const double *__restrict__ P, int p, long long sPr,
                                                                long long sPa, int tri, long long spw,
-                                                               double *__restrict__ partials) {
-  gram_left_factor_body<NT, KS, A>(blockIdx.x, X, a, b, I, P, p, sPr, sPa, tri, spw, partials);
+                                                               double *__restrict__ partials,
+                                                               double *__restrict__ Yout) {
+  gram_left_factor_body<NT, KS, A, false, ST>(blockIdx.x, X, a, b, I, P, p, sPr, sPa, tri, spw, partials, Yout);
 }
 
 // ---------------------------------------------------------------------------
@@ -355,6 +393,9 @@ __device__ __forceinline__ void apply_mfma_body(const int wg, const double *__re
   const int g = lane >> 4, j = lane & 15;
   const int ksr = (b + 3) / 4, ntq = (q + 15) / 16, nta = (a + 15) / 16, ntp = (p + 15) / 16;  // GD
   const bool hasP = (P != nullptr);
+  constexpr int LDP = NT * 16 + 1;
+  __shared__ double Lst[kWaves * LDP * 16];
+  double *Lw = Lst + wave * LDP * 16;
   build_bfrag(fragQ, Q, b, q, sQr, sQc, NT, KS);
   if (hasP) build_afrag(fragP, P, p, a, sPr, sPa, NT, KA);
   __syncthreads();
@@ -401,29 +442,9 @@ __device__ __forceinline__ void apply_mfma_body(const int wg, const double *__re
               if (!GD || cb < ntq) y[rb][cb] = mfma(pa, w[t][cb][r], y[rb][cb]);
           }
         }
-#pragma unroll
-      for (int rb = 0; rb < NT; ++rb)
-#pragma unroll
-        for (int cb = 0; cb < NT; ++cb) {
-          const int c = cb * 16 + j;
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int rho = rb * 16 + g + 4 * r;
-            if (rho < p && c < q) Yi[rho + ocol * c] = y[rb][cb][r];
-          }
-        }
+      store_tiles<NT, F64>(y, p, q, Yi, ocol, Lw, LDP, lane, g, j);
     } else {
-#pragma unroll
-      for (int t = 0; t < NT; ++t)
-#pragma unroll
-        for (int cb = 0; cb < NT; ++cb) {
-          const int c = cb * 16 + j;
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int alpha = t * 16 + g + 4 * r;
-            if (alpha < p && c < q) Yi[alpha + ocol * c] = w[t][cb][r];
-          }
-        }
+      store_tiles<NT, F64>(w, p, q, Yi, ocol, Lw, LDP, lane, g, j);
     }
   }
 }
@@ -732,16 +753,18 @@ int launch_gram_right_factor(hipStream_t s, const double *X, int a, int b, long 
 }
 
 int launch_gram_left_factor(hipStream_t s, const double *X, int a, int b, long long I, const double *P, int p,
-                            long long sPr, long long sPa, int tri, int f32, double *partials) {
+                            long long sPr, long long sPa, int tri, int f32, double *partials, double *Yout) {
   const Grid gr = grid_of(I);
   const int nt = std::max({tiles_for(a), tiles_for(b), tiles_for(p)});
   const int ks = std::max((a + 3) / 4, 4 * nt - 3);
   nt_ks(nt, ks, [&](auto NTc, auto KSc) {
     constexpr int NTV = decltype(NTc)::value, KSV = decltype(KSc)::value;
     if (f32)
-      TTR_LAUNCH(k_gram_left_factor<NTV, KSV, F32>) X, a, b, I, P, p, sPr, sPa, tri, gr.spw, partials);
+      TTR_LAUNCH(k_gram_left_factor<NTV, KSV, F32>) X, a, b, I, P, p, sPr, sPa, tri, gr.spw, partials, nullptr);
+    else if (Yout)
+      TTR_LAUNCH(k_gram_left_factor<NTV, KSV, F64, true>) X, a, b, I, P, p, sPr, sPa, tri, gr.spw, partials, Yout);
     else
-      TTR_LAUNCH(k_gram_left_factor<NTV, KSV, F64>) X, a, b, I, P, p, sPr, sPa, tri, gr.spw, partials);
+      TTR_LAUNCH(k_gram_left_factor<NTV, KSV, F64>) X, a, b, I, P, p, sPr, sPa, tri, gr.spw, partials, nullptr);
   });
   return gr.nwg;
 }
