@@ -53,6 +53,60 @@ __global__ void k_add(int n, int N, double alpha, double beta, const double *__r
   }
 }
 
+// The same sum for even ranks (and even I on the first core), two
+// consecutive rows at a time with 16-byte loads and stores.  A pair never
+// straddles the X / Y / zero blocks because the block sizes are even.  The
+// row/slice split of the pair index uses a float reciprocal with an exact
+// integer correction (pair counts per column stay below 2^24).
+__global__ void k_add_pairs(int n, int N, double alpha, double beta, const double *__restrict__ X, int rx0, int rx1,
+                            const double *__restrict__ Y, int ry0, int ry1, int I, double *__restrict__ Z) {
+#pragma clang fp contract(off)
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  const int zr0 = (n == 0) ? 1 : rx0 + ry0;
+  const int b = blockIdx.y;
+  const int npair = (zr0 * I) / 2;
+  const int hr = zr0 / 2;  // pairs per slice column (0 on the first core: pairs run along i)
+  const float inv = (n == 0) ? 0.f : 1.0f / (float)hr;
+  d2 *Zb = reinterpret_cast<d2 *>(Z + (long long)zr0 * I * b);
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < npair; e += gridDim.x * blockDim.x) {
+    d2 v;
+    if (n == 0) {
+      // first core (1 x I x (rx1 + ry1)): column b is alpha X(0, :, b) or beta Y(0, :, b - rx1)
+      const int i = 2 * e;
+      if (b < rx1) {
+        const d2 x = *reinterpret_cast<const d2 *>(X + i + (long long)I * b);
+        v = d2{alpha * x.x, alpha * x.y};
+      } else {
+        const d2 y = *reinterpret_cast<const d2 *>(Y + i + (long long)I * (b - rx1));
+        v = d2{beta * y.x, beta * y.y};
+      }
+    } else {
+      int i = (int)((float)e * inv);
+      int a2 = e - i * hr;
+      while (a2 < 0) {
+        --i;
+        a2 += hr;
+      }
+      while (a2 >= hr) {
+        ++i;
+        a2 -= hr;
+      }
+      const int a = 2 * a2;
+      if (n == N - 1) {
+        v = (a < rx0) ? *reinterpret_cast<const d2 *>(X + a + (long long)rx0 * i)
+                      : *reinterpret_cast<const d2 *>(Y + (a - rx0) + (long long)ry0 * i);
+      } else if (a < rx0 && b < rx1) {
+        v = *reinterpret_cast<const d2 *>(X + a + (long long)rx0 * (i + (long long)I * b));
+      } else if (a >= rx0 && b >= rx1) {
+        v = *reinterpret_cast<const d2 *>(Y + (a - rx0) + (long long)ry0 * (i + (long long)I * (b - rx1)));
+      } else {
+        v = d2{0.0, 0.0};
+      }
+    }
+    Zb[e] = v;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Hadamard: Z(ax*ry0 + ay, i, bx*ry1 + by) = X(ax, i, bx) * Y(ay, i, by);
 // output column b = bx*ry1 + by per blockIdx.y.
@@ -414,6 +468,13 @@ void launch_add(hipStream_t s, int n, int N, double alpha, double beta, const do
   else if (n == N - 1) { zr0 = rx0 + ry0; zr1 = 1; }
   else { zr0 = rx0 + ry0; zr1 = rx1 + ry1; }
   const long long colsz = (long long)zr0 * I;
+  const bool pairs = N > 1 && (n == 0 ? (I % 2 == 0) : (rx0 % 2 == 0 && ry0 % 2 == 0)) && colsz / 2 < (1LL << 24);
+  if (pairs) {
+    const long long bx = std::min((colsz / 2 + kThreads - 1) / kThreads, 4096LL);
+    hipLaunchKernelGGL(k_add_pairs, dim3((unsigned)std::max(bx, 1LL), (unsigned)zr1), dim3(kThreads), 0, s, n, N,
+                       alpha, beta, X, rx0, rx1, Y, ry0, ry1, (int)I, Z);
+    return;
+  }
   const long long bx = std::min((colsz + kThreads - 1) / kThreads, 4096LL);
   hipLaunchKernelGGL(k_add, dim3((unsigned)std::max(bx, 1LL), (unsigned)zr1), dim3(kThreads), 0, s, n, N, alpha, beta,
                      X, rx0, rx1, Y, ry0, ry1, (int)I, Z);

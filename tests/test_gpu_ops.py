@@ -45,6 +45,22 @@ def test_add_bitwise(ttr, h, I, r):
         assert np.array_equal(z, zr)
 
 
+@pytest.mark.parametrize("I,rx,ry", [([64, 50, 32, 80], [4, 6, 2], [2, 4, 8]),
+                                     ([33, 50, 32, 81], [4, 6, 2], [2, 4, 8]),
+                                     ([40, 40], [20], [20])])
+def test_add_bitwise_even_ranks(ttr, h, I, rx, ry):
+    # even ranks (and even I on the first core) take the paired 16-byte kernel
+    print(f"add even ranks I={I} rx={rx} ry={ry}", flush=True)
+    rng = np.random.default_rng(108)
+    X = rand_tt(rng, I, rx)
+    Y = rand_tt(rng, I, ry)
+    Z = h.add(0.75, ttr.TT.from_numpy(X), -1.5, ttr.TT.from_numpy(Y)).to_numpy()
+    ref = O.add(0.75, X, -1.5, Y)
+    assert O.ranks(Z) == O.ranks(ref)
+    for z, zr in zip(Z, ref):
+        assert np.array_equal(z, zr)
+
+
 @pytest.mark.parametrize("I,r", SHAPES)
 def test_hadamard_bitwise(ttr, h, I, r):
     print(f"hadamard I={I} r={r}", flush=True)
