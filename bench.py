@@ -37,9 +37,11 @@ def log(msg):
 
 def source_hash():
     h = hashlib.sha256()
-    for f in ("ttr_stream.hip", "ttr_small.hip", "ttr_mfma.hip", "ttr_api.hip", "ttr_internal.h"):
-        with open(os.path.join(ROOT, "paper_2011_06532_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    d = os.path.join(ROOT, "paper_2011_06532_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -291,7 +293,7 @@ def main():
     ai = p["flops"] / p["bytes"] if p["bytes"] else 0.0
     if ai > RIDGE:
         achieved = p["flops"] / (p["ms"] * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+        roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP64_PEAK_TFLOPS, 4)}
     else:
         achieved = p["bytes"] / (p["ms"] * 1e-3) / 1e9

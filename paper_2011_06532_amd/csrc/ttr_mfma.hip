@@ -156,9 +156,18 @@ __device__ inline void store_tiles(const VT (&y)[NT][NT], int nrow, int ncol, do
     // one wave owns Lw and its LDS operations complete in order
     __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     const int nc = min(16, ncol - c * 16);
+    // element e = lane + 64 m of the tile is (row e % nrow, column e / nrow):
+    // one division up front, then steps of 64 = q nrow + rem
+    const int q = 64 / nrow, rem = 64 - q * nrow;
+    int rr = lane % nrow, jj = lane / nrow;
     for (int e = lane; e < nrow * nc; e += 64) {
-      const int rr = e % nrow, jj = e / nrow;
       Yi[rr + ocol * (c * 16 + jj)] = Lw[rr + LDP * jj];
+      rr += rem;
+      jj += q;
+      if (rr >= nrow) {
+        rr -= nrow;
+        ++jj;
+      }
     }
     __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
   }
