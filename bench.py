@@ -77,7 +77,7 @@ def sample_entries(cores, R, I, idx):
     return v[:, 0]
 
 
-def bench_batched(h, ttr, torch, steps, count=512):
+def bench_batched(h, ttr, torch, steps, count=512, per_tensor=True):
     """512 independent Y + Y + 1e-9 E tensors (N=8, I_n log-uniform in
     [64, 4096], ranks 2r+2 with r uniform in 1..31), tol 1e-7: one replay of the
     batched graph against one ttr_round call per tensor."""
@@ -112,6 +112,9 @@ def bench_batched(h, ttr, torch, steps, count=512):
                "ranks_ok": rk == expect, "spw_target": plan["spw_target"], "grid_cap": plan["grid_cap"],
                "graph_nodes": plan["graph_nodes"],
                "autotune": [[c["spw"], c["grid"], round(c["ms"], 3)] for c in plan["candidates"]]}
+        out[prec] = res
+        if not per_tensor:
+            continue
         # one launch sequence per tensor (the single path, host-planned)
         log(f"batched {prec}: one ttr_round per tensor")
         outs1 = [ttr.TT.empty(X.I, [X.R[n] * X.I[n] * X.R[n + 1] for n in range(X.N)]) for X in Xs]
@@ -170,6 +173,57 @@ def copy_calibration(gib):
     print(json.dumps({"copy_bytes_each_way": n * 8, "copies": 3}), flush=True)
 
 
+def bench_large(h, ttr, torch, steps):
+    """Hadamard product of two random TTs (N=10, I=16384, ranks 16 with 2^-b
+    rank weights) -> formal ranks 256 (68.7 GB of cores), then ttr_round at tol
+    1e-8: the rank 65..256 path."""
+    import synth
+    torch.cuda.empty_cache()   # blocks cached by the earlier legs are returned to the device
+    log("large: generating A, B (N=10, I=16384, ranks 16)")
+    d = synth.cfg4()
+    A = ttr.TT.from_numpy(d["A"])
+    B = ttr.TT.from_numpy(d["B"])
+    tol = d["tol"]
+    del d
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    X = h.hadamard(A, B)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    X = h.hadamard(A, B, out=X)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_had = e0.elapsed_time(e1)
+    nbytes = sum(8 * X.R[n] * X.I[n] * X.R[n + 1] for n in range(X.N))
+    log("large: warm-up round")
+    Y = h.round(X, tol, "RLR", "fp64")
+    torch.cuda.synchronize()
+    ts = []
+    for k in range(max(1, min(steps, 3))):
+        e0.record(stream)
+        Y = h.round(X, tol, "RLR", "fp64", out=Y)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+        log(f"large: round {k + 1}: {ts[-1]:.1f} ms")
+    st = h.round_stats()
+    idx = np.random.default_rng(5).integers(0, X.I[0], size=(128, X.N))
+    ex = sample_entries(X.cores, X.R, X.I, idx)
+    ey = sample_entries(Y.cores, Y.R, Y.I, idx)
+    ms = sum(ts) / len(ts)
+    out = {"workload": "A * B (Hadamard), N=10, I=16384, A,B random TTs of rank 16 with 2^-b rank weights, "
+                       "formal ranks 256, ttr_round tol 1e-8 RLR fp64",
+           "core_bytes_X": nbytes, "ms_hadamard": round(ms_had, 3),
+           "hadamard_GBps": round(nbytes / (ms_had * 1e-3) / 1e9, 1),
+           "ms_per_round": round(ms, 3), "round_core_GBps": round(nbytes / (ms * 1e-3) / 1e9, 2),
+           "rounds": len(ts), "ranks": list(Y.R), "gram_passes": st["gram_passes"],
+           "rel_rms_entry_diff_vs_X": float(np.sqrt(np.mean((ex - ey) ** 2) / np.mean(ex ** 2))),
+           "entries_sampled": int(idx.shape[0])}
+    del X, Y, A, B
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -182,6 +236,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision rounds")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched rounding of 512 tensors")
+    ap.add_argument("--no-large", action="store_true", help="skip the Hadamard -> rank-256 rounding")
+    ap.add_argument("--leg", default="all", choices=["all", "batched", "large"],
+                    help="batched / large: run only that leg (for profiling) and print its JSON object")
+    ap.add_argument("--no-per-tensor", action="store_true",
+                    help="batched leg: skip the one-ttr_round-per-tensor comparison")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="only run a plain device-to-device copy of this many GiB (counter calibration)")
     args = ap.parse_args()
@@ -202,6 +261,15 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     h = ttr.Handle(0)
+
+    if args.leg != "all":
+        if args.leg == "batched":
+            res = bench_batched(h, ttr, torch, args.steps, per_tensor=not args.no_per_tensor)
+        else:
+            res = bench_large(h, ttr, torch, args.steps)
+        h.close()
+        print(json.dumps({"leg": args.leg, args.leg: res}), flush=True)
+        return
 
     N, r = 16, 20
     log(f"generating A, B: N={N}, I={args.I}, ranks {r} (host, seeded)")
@@ -339,7 +407,12 @@ def main():
     if not args.no_batched:
         del A, B, Xbuf, Ybuf, X, Y, Yf
         torch.cuda.empty_cache()
-        out["batched"] = bench_batched(h, ttr, torch, args.steps)
+        out["batched"] = bench_batched(h, ttr, torch, args.steps, per_tensor=not args.no_per_tensor)
+    if not args.no_large:
+        if args.no_batched:
+            del A, B, Xbuf, Ybuf, X, Y, Yf
+            torch.cuda.empty_cache()
+        out["large"] = bench_large(h, ttr, torch, args.steps)
     if not args.no_cpu_baseline:
         log(f"cpu_baseline: oracle on I={args.cpu_sample_I}")
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_I)

@@ -297,9 +297,10 @@ void apply(ttr_handle *h, const CoreView &cv, const Stages &st, double *Y, int t
     Stage P, Q;
     if (pl) P = tr ? st_transpose(*pl) : *pl;
     if (pr) Q = tr ? st_transpose(*pr) : *pr;
+    const int tri = ((pr && Q.lower == 1) ? 1 : 0) | ((pl && P.lower == 2) ? 2 : 0);
     launch_apply_mfma(h->stream, cv.X, cv.pa, cv.pb, cv.I, pl ? P.S : nullptr, pl ? P.rows : cv.pa, pl ? P.sr : 1,
                       pl ? P.sc : cv.pa, pr ? Q.S : nullptr, pr ? Q.cols : cv.pb, pr ? Q.sr : 1,
-                      pr ? Q.sc : cv.pb, Y);
+                      pr ? Q.sc : cv.pb, tri, Y);
     return;
   }
   if (g_use_mfma && st.nl == 0 && st.nr == 2 && trans_out == cv.trans) {

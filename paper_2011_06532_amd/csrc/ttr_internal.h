@@ -68,8 +68,10 @@ int launch_gram_right_factor(hipStream_t s, const double *X, int a, int b, long 
 // Yout (FP64 only, may be nullptr): also writes P X_i as a p x I x b core.
 int launch_gram_left_factor(hipStream_t s, const double *X, int a, int b, long long I, const double *P, int p,
                             long long sPr, long long sPa, int tri, int f32, double *partials, double *Yout = nullptr);
+// tri: bit 0 = Q lower triangular, bit 1 = P upper triangular (their
+// vanishing k-steps are skipped).
 void launch_apply_mfma(hipStream_t s, const double *X, int a, int b, long long I, const double *P, int p,
-                       long long sPr, long long sPa, const double *Q, int q, long long sQr, long long sQc,
+                       long long sPr, long long sPa, const double *Q, int q, long long sQr, long long sQc, int tri,
                        double *Y);
 // On the slice S_i = M_i (trans = 0) or M_i^T (trans = 1), sa x sb:
 //   launch_gram_fac:   partial Grams of sum_i (S_i Q)^T (S_i Q), Q sb x q

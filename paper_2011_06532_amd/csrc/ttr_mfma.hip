@@ -137,39 +137,101 @@ __device__ inline void load_slice(const double *__restrict__ Xi, long long col, 
     }
 }
 
-// Writes a wave's result tiles as an nrow x ncol block of one output slice:
-// register r of tile (u, c) holds row 16u + row(g, r), column 16c + j; column
-// c of the slice starts at Yi + ocol * c with its rows contiguous.  Each
-// 16-column tile goes through the wave's LDS buffer Lw (ld LDP) so that the
-// stores leave as runs of consecutive rows, not 16 scattered 32-byte pieces.
+// Products that contract over alpha (the fast index of a slice) take their
+// k-steps in "pair order": k-step ks covers alpha = 8 (ks/2) + 2 g + ks%2, so a
+// lane holds two consecutive alpha of one column and reads them with one
+// 16-byte load (V2: a even and a 16-byte aligned core).  Any order of the
+// contraction index is valid as long as both operands use it.
+__device__ __host__ inline int pair_alpha(int ks, int g) { return 8 * (ks >> 1) + 2 * g + (ks & 1); }
+
+// buf[ks][t] = M(pair_alpha(ks, g), 16t + j), zero outside the a x b slice.
+template <int NT, int KP, bool V2, class T = double>
+__device__ inline void load_slice_pairs(const double *__restrict__ Xi, long long col, int a, int b, int g, int j,
+                                        T (&buf)[KP][NT]) {
+#pragma unroll
+  for (int kk = 0; kk < KP / 2; ++kk)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int r = 8 * kk + 2 * g, c = 16 * t + j;
+      double v0 = 0.0, v1 = 0.0;
+      if (V2) {
+        // a even: r < a implies r + 1 < a
+        if (r < a && c < b) {
+          const double2 v = *reinterpret_cast<const double2 *>(Xi + r + col * c);
+          v0 = v.x;
+          v1 = v.y;
+        }
+      } else {
+        if (r < a && c < b) v0 = Xi[r + col * c];
+        if (r + 1 < a && c < b) v1 = Xi[r + 1 + col * c];
+      }
+      buf[2 * kk][t] = (T)v0;
+      buf[2 * kk + 1][t] = (T)v1;
+    }
+}
+
+// A-operand fragments of S (rows x cols) with the column index in pair order:
+// frag[(t*KP + ks)*64 + l] = S(t*16 + l%16, pair_alpha(ks, l/16)).
+template <class T = double>
+__device__ void build_afrag_pairs(T *frag, const double *S, int rows, int cols, long long sr, long long sc, int nt,
+                                  int KP) {
+  const int total = nt * KP * 64;
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    const int l = e & 63;
+    const int ks = (e >> 6) % KP;
+    const int t = (e >> 6) / KP;
+    const int r = t * 16 + (l & 15);
+    const int c = pair_alpha(ks, l >> 4);
+    double v = 0.0;
+    if (r < rows && c < cols) v = S ? S[r * sr + c * sc] : (r == c ? 1.0 : 0.0);
+    frag[e] = (T)v;
+  }
+}
+
+// Writes column tile c (columns 16c..16c+15) of an nrow x ncol block of one
+// output slice, held as NT accumulator tiles: register r of yc[u] holds row
+// 16u + row(g, r), column 16c + j; column c of the slice starts at Yi + ocol*c
+// with its rows contiguous.  The tile goes through the wave's LDS buffer Lw
+// (ld LDP) so that the stores leave as runs of consecutive rows, not 16
+// scattered 32-byte pieces.
+template <int NT, class A, class VT>
+__device__ inline void store_col(const VT (&yc)[NT], int c, int nrow, int ncol, double *__restrict__ Yi,
+                                 long long ocol, double *Lw, int LDP, int lane, int g, int j) {
+  __asm__ volatile("" ::: "memory");
+#pragma unroll
+  for (int u = 0; u < NT; ++u)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Lw[(u * 16 + A::row(g, r)) + LDP * j] = (double)yc[u][r];
+  // one wave owns Lw and its LDS operations complete in order
+  __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  const int nc = min(16, ncol - c * 16);
+  // element e = lane + 64 m of the tile is (row e % nrow, column e / nrow):
+  // one division up front, then steps of 64 = q nrow + rem
+  const int q = 64 / nrow, rem = 64 - q * nrow;
+  int rr = lane % nrow, jj = lane / nrow;
+  for (int e = lane; e < nrow * nc; e += 64) {
+    Yi[rr + ocol * (c * 16 + jj)] = Lw[rr + LDP * jj];
+    rr += rem;
+    jj += q;
+    if (rr >= nrow) {
+      rr -= nrow;
+      ++jj;
+    }
+  }
+  __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+}
+
+// All column tiles of an nrow x ncol result y[u][c], one after the other.
 template <int NT, class A, class VT>
 __device__ inline void store_tiles(const VT (&y)[NT][NT], int nrow, int ncol, double *__restrict__ Yi, long long ocol,
                                    double *Lw, int LDP, int lane, int g, int j) {
 #pragma unroll
   for (int c = 0; c < NT; ++c) {
     if (c * 16 >= ncol) break;
-    __asm__ volatile("" ::: "memory");
+    VT yc[NT];
 #pragma unroll
-    for (int u = 0; u < NT; ++u)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) Lw[(u * 16 + A::row(g, r)) + LDP * j] = (double)y[u][c][r];
-    // one wave owns Lw and its LDS operations complete in order
-    __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-    const int nc = min(16, ncol - c * 16);
-    // element e = lane + 64 m of the tile is (row e % nrow, column e / nrow):
-    // one division up front, then steps of 64 = q nrow + rem
-    const int q = 64 / nrow, rem = 64 - q * nrow;
-    int rr = lane % nrow, jj = lane / nrow;
-    for (int e = lane; e < nrow * nc; e += 64) {
-      Yi[rr + ocol * (c * 16 + jj)] = Lw[rr + LDP * jj];
-      rr += rem;
-      jj += q;
-      if (rr >= nrow) {
-        rr -= nrow;
-        ++jj;
-      }
-    }
-    __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    for (int u = 0; u < NT; ++u) yc[u] = y[u][c];
+    store_col<NT, A>(yc, c, nrow, ncol, Yi, ocol, Lw, LDP, lane, g, j);
   }
 }
 
@@ -205,10 +267,12 @@ __device__ __forceinline__ void gram_right_factor_body(const int wg, const doubl
   const long long beg = (long long)wg * spw;
   const long long end = std::min(beg + spw, I);
   const long long col = (long long)a * I;
-  // register prefetch of the next slice, except where it would spill (FP64,
-  // NT = 4).  The prefetch holds the raw FP64 loads; FP32 rounding happens when
-  // the slice becomes current, so the loads stay in flight across the products.
-  constexpr bool PF = (NT <= 3) || sizeof(T) == 4;
+  // register prefetch of the next slice for FP32 and NT <= 2.  FP64 at NT = 3
+  // runs two waves per SIMD without it (measured faster than one wave with
+  // it: the other wave's products cover the load latency).  The prefetch holds
+  // the raw FP64 loads; FP32 rounding happens when the slice becomes current,
+  // so the loads stay in flight across the products.
+  constexpr bool PF = (NT <= 2) || sizeof(T) == 4;
   T cur[KS][NT];
   double nxt[KS][NT];  // used only with PF
   long long i = beg + wave;
@@ -220,26 +284,26 @@ __device__ __forceinline__ void gram_right_factor_body(const int wg, const doubl
     } else {
       load_slice<NT, KS, true, T>(X + (long long)a * i, col, a, b, g, j, cur);
     }
-    V wt[NT][NT];  // [c-tile][alpha-tile]
+    // one 16-row band of Wt at a time: its Gram contribution is complete on
+    // its own, so only NT accumulator tiles of Wt are live (this keeps the
+    // FP64 kernel at two waves per SIMD)
 #pragma unroll
-    for (int u = 0; u < NT; ++u)
+    for (int cb = 0; cb < NT; ++cb) {
+      if (GD && cb >= ntq) continue;
+      V wt[NT];  // Wt(c, alpha), c in band cb, one tile per alpha-tile
 #pragma unroll
-      for (int v = 0; v < NT; ++v) wt[u][v] = V{0, 0, 0, 0};
+      for (int t = 0; t < NT; ++t) wt[t] = V{0, 0, 0, 0};
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-      for (int cb = 0; cb < NT; ++cb) {
+      for (int ks = 0; ks < KS; ++ks) {
         // lower-triangular Q: Q^T(c, beta) = 0 for beta < c, so k-steps below 4 cb vanish
-        if ((tri && ks < 4 * cb) || (GD && (ks >= ksr || cb >= ntq))) continue;
+        if ((tri && ks < 4 * cb) || (GD && ks >= ksr)) continue;
         const T qa = frag[(cb * KS + ks) * 64 + lane];
 #pragma unroll
         for (int t = 0; t < NT; ++t)
-          if (!GD || t < nta) wt[cb][t] = A::mma(qa, cur[ks][t], wt[cb][t]);
+          if (!GD || t < nta) wt[t] = A::mma(qa, cur[ks][t], wt[t]);
       }
-    // G(alpha, alpha') += sum_c Wt(c, alpha) Wt(c, alpha'); register r of tile
-    // (cb, .) holds rows c = cb*16 + row(g, r); rows past q are zero padding
-#pragma unroll
-    for (int cb = 0; cb < NT; ++cb)
+      // G(alpha, alpha') += sum_c Wt(c, alpha) Wt(c, alpha'); register r holds
+      // rows c = cb*16 + row(g, r); rows past q are zero padding
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         if (cb * 16 + A::row(0, r) >= q) continue;
@@ -247,8 +311,9 @@ __device__ __forceinline__ void gram_right_factor_body(const int wg, const doubl
         for (int u = 0; u < NT; ++u)
 #pragma unroll
           for (int v = 0; v <= u; ++v)
-            if (!GD || u < nta) G[u][v] = A::mma(wt[cb][u][r], wt[cb][v][r], G[u][v]);
+            if (!GD || u < nta) G[u][v] = A::mma(wt[u][r], wt[v][r], G[u][v]);
       }
+    }
     if constexpr (PF) {
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks)
@@ -260,7 +325,7 @@ __device__ __forceinline__ void gram_right_factor_body(const int wg, const doubl
 }
 
 template <int NT, int KS, class A>
-__global__ __launch_bounds__(kThreads) void k_gram_right_factor(const double *__restrict__ X, int a, int b, long long I,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NT <= 3 ? 2 : 1, NT <= 3 ? 2 : 1))) void k_gram_right_factor(const double *__restrict__ X, int a, int b, long long I,
                                                                 const double *__restrict__ Q, int q, long long sQr,
                                                                 long long sQc, int tri, long long spw,
                                                                 double *__restrict__ partials) {
@@ -282,26 +347,19 @@ __device__ __forceinline__ void gram_left_factor_body(const int wg, const double
   using V = typename A::V;
   // ST: the product Y_i = P M_i is also written, as a p x I x b core (FP64), for
   // the output pass that follows to reuse.
-  // The product contracts over alpha, which the operand layout puts on the
-  // slow lane index; read directly, every load would touch 16 columns.  So
-  // slices are read coalesced (16 consecutive alpha per lane group) and turned
-  // through a per-wave LDS tile (STAGE).  FP64 at NT = 4 does not fit in LDS
-  // and reads the operand layout directly.
-  constexpr bool STAGE = (NT <= 3) || sizeof(T) == 4;
-  constexpr int KB = 4 * NT;                     // k-steps of 4 columns covering b
-  constexpr int LDT = NT * 16 + 1;               // staging tile leading dimension
-  constexpr int TILE = LDT * NT * 16;            // staging tile per wave (elements of T)
-  constexpr int GS_BYTES = NT * 16 * NT * 16 * 8;
-  constexpr int ST_BYTES = STAGE ? kWaves * TILE * (int)sizeof(T) : 0;
-  __shared__ T frag[NT * KS * 64];
-  __shared__ __align__(16) char smem[GS_BYTES > ST_BYTES ? GS_BYTES : ST_BYTES];
-  double *Gs = reinterpret_cast<double *>(smem);  // after the slice loop only
-  __shared__ double Lys[(ST && !STAGE) ? kWaves * LDT * 16 : 1];  // product staging (FP64, NT = 4)
+  // The product contracts over alpha, the fast index of a slice: its k-steps
+  // run in pair order, so the slices are read with 16-byte loads straight
+  // into the operand layout.
+  constexpr int KP = (KS + 1) & ~1;   // k-steps over alpha (pair order covers 8 alpha per two steps)
+  constexpr int LDT = NT * 16 + 1;    // product staging tile leading dimension (ST)
+  __shared__ T frag[NT * KP * 64];
+  __shared__ double Gs[NT * 16 * NT * 16];
+  __shared__ double Lys[ST ? kWaves * LDT * 16 : 1];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, j = lane & 15;
-  const int ksr = (a + 3) / 4, ntp = (p + 15) / 16, ntb = (b + 15) / 16;  // GD: run-time extents
-  T *Ls = reinterpret_cast<T *>(smem) + (STAGE ? wave * TILE : 0);
-  build_afrag<T>(frag, P, p, a, sPr, sPa, NT, KS);
+  const int kpr = 2 * ((a + 7) / 8), ntp = (p + 15) / 16, ntb = (b + 15) / 16;  // GD: run-time extents
+  const bool v2 = ((a & 1) == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
+  build_afrag_pairs<T>(frag, P, p, a, sPr, sPa, NT, KP);
   __syncthreads();
   V G[NT][NT];
 #pragma unroll
@@ -311,73 +369,102 @@ __device__ __forceinline__ void gram_left_factor_body(const int wg, const double
   const long long beg = (long long)wg * spw;
   const long long end = std::min(beg + spw, I);
   const long long col = (long long)a * I;
-  T cur[KS][NT];  // cur[ks][t] = M(4 ks + g, 16 t + j)
-  // STAGE: raw coalesced loads of the next slice, nx[kb][ta] = M(16 ta + j, 4 kb + g),
-  // kept in flight across the products
-  double nx[STAGE ? KB : 1][NT];
+  // register prefetch of the next slice (raw FP64 loads, rounded when the
+  // slice becomes current) for FP32 and NT <= 2; FP64 at NT = 3 runs two waves
+  // per SIMD instead
+  constexpr bool PF = (NT <= 2) || sizeof(T) == 4;
+  T cur[KP][NT];
+  double nxt[PF ? KP : 1][NT];
   long long i = beg + wave;
-  if constexpr (STAGE)
-    if (i < end) load_slice<NT, KB, true>(X + (long long)a * i, col, a, b, g, j, nx);
-  for (; i < end; i += kWaves) {
-    if constexpr (STAGE) {
-      // nx -> LDS (alpha + LDT beta) -> cur; one wave owns the tile and its LDS
-      // operations complete in order
-      __asm__ volatile("" ::: "memory");
-#pragma unroll
-      for (int kb = 0; kb < KB; ++kb)
-#pragma unroll
-        for (int ta = 0; ta < NT; ++ta) Ls[(16 * ta + j) + LDT * (4 * kb + g)] = (T)nx[kb][ta];
-      __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-        for (int t = 0; t < NT; ++t) cur[ks][t] = Ls[(4 * ks + g) + LDT * (16 * t + j)];
-      __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-      if (i + kWaves < end) load_slice<NT, KB, true>(X + (long long)a * (i + kWaves), col, a, b, g, j, nx);
-    } else {
-      load_slice<NT, KS, false, T>(X + (long long)a * i, col, a, b, g, j, cur);
+  if constexpr (PF) {
+    if (i < end) {
+      if (v2) load_slice_pairs<NT, KP, true, T>(X + (long long)a * i, col, a, b, g, j, cur);
+      else load_slice_pairs<NT, KP, false, T>(X + (long long)a * i, col, a, b, g, j, cur);
     }
-    V y[NT][NT];  // [rho-tile][beta-tile]
+  }
+  for (; i < end; i += kWaves) {
+    if constexpr (PF) {
+      if (i + kWaves < end) {
+        const double *Xn = X + (long long)a * (i + kWaves);
+        if (v2) load_slice_pairs<NT, KP, true>(Xn, col, a, b, g, j, nxt);
+        else load_slice_pairs<NT, KP, false>(Xn, col, a, b, g, j, nxt);
+      }
+    } else {
+      if (v2) load_slice_pairs<NT, KP, true, T>(X + (long long)a * i, col, a, b, g, j, cur);
+      else load_slice_pairs<NT, KP, false, T>(X + (long long)a * i, col, a, b, g, j, cur);
+    }
+    if constexpr (ST) {
+      // the whole product is kept for the store
+      V y[NT][NT];  // [rho-tile][beta-tile]
 #pragma unroll
-    for (int u = 0; u < NT; ++u)
+      for (int u = 0; u < NT; ++u)
 #pragma unroll
-      for (int v = 0; v < NT; ++v) y[u][v] = V{0, 0, 0, 0};
+        for (int v = 0; v < NT; ++v) y[u][v] = V{0, 0, 0, 0};
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks)
+      for (int ks = 0; ks < KP; ++ks)
+#pragma unroll
+        for (int rb = 0; rb < NT; ++rb) {
+          // upper-triangular P: P(rho, alpha) = 0 for alpha < rho
+          if ((tri && ks < 4 * rb) || (GD && (ks >= kpr || rb >= ntp))) continue;
+          const T pa = frag[(rb * KP + ks) * 64 + lane];
+#pragma unroll
+          for (int t = 0; t < NT; ++t)
+            if (!GD || t < ntb) y[rb][t] = A::mma(pa, cur[ks][t], y[rb][t]);
+        }
+      store_tiles<NT, A>(y, p, b, Yout + (long long)p * i, (long long)p * I, Lys + wave * LDT * 16, LDT, lane, g, j);
+      // G0(beta, beta') += sum_rho Y(rho, beta) Y(rho, beta'); rows past p are padding
+#pragma unroll
+      for (int rb = 0; rb < NT; ++rb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (rb * 16 + A::row(0, r) >= p) continue;
+#pragma unroll
+          for (int u = 0; u < NT; ++u)
+#pragma unroll
+            for (int v = 0; v <= u; ++v)
+              if (!GD || u < ntb) G[u][v] = A::mma(y[rb][u][r], y[rb][v][r], G[u][v]);
+        }
+    } else {
+      // one 16-row band of Y = P M at a time: its Gram contribution is
+      // complete on its own, so only NT accumulator tiles of Y are live
 #pragma unroll
       for (int rb = 0; rb < NT; ++rb) {
-        // upper-triangular P: P(rho, alpha) = 0 for alpha < rho
-        if ((tri && ks < 4 * rb) || (GD && (ks >= ksr || rb >= ntp))) continue;
-        const T pa = frag[(rb * KS + ks) * 64 + lane];
+        if (GD && rb >= ntp) continue;
+        V y[NT];  // Y(rho, beta), rho in band rb, one tile per beta-tile
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
-          if (!GD || t < ntb) y[rb][t] = A::mma(pa, cur[ks][t], y[rb][t]);
+        for (int t = 0; t < NT; ++t) y[t] = V{0, 0, 0, 0};
+#pragma unroll
+        for (int ks = 0; ks < KP; ++ks) {
+          // upper-triangular P: P(rho, alpha) = 0 for alpha < rho
+          if ((tri && ks < 4 * rb) || (GD && ks >= kpr)) continue;
+          const T pa = frag[(rb * KP + ks) * 64 + lane];
+#pragma unroll
+          for (int t = 0; t < NT; ++t)
+            if (!GD || t < ntb) y[t] = A::mma(pa, cur[ks][t], y[t]);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (rb * 16 + A::row(0, r) >= p) continue;
+#pragma unroll
+          for (int u = 0; u < NT; ++u)
+#pragma unroll
+            for (int v = 0; v <= u; ++v)
+              if (!GD || u < ntb) G[u][v] = A::mma(y[u][r], y[v][r], G[u][v]);
+        }
       }
-    if constexpr (ST) {
-      // the slice's staging tile has been read into cur: reuse it (or the
-      // dedicated buffer when slices are not staged)
-      double *Lw = STAGE ? reinterpret_cast<double *>(Ls) : Lys + wave * LDT * 16;
-      store_tiles<NT, A>(y, p, b, Yout + (long long)p * i, (long long)p * I, Lw, LDT, lane, g, j);
     }
-    // G0(beta, beta') += sum_rho Y(rho, beta) Y(rho, beta'); rows past p are padding
+    if constexpr (PF) {
 #pragma unroll
-    for (int rb = 0; rb < NT; ++rb)
+      for (int ks = 0; ks < KP; ++ks)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        if (rb * 16 + A::row(0, r) >= p) continue;
-#pragma unroll
-        for (int u = 0; u < NT; ++u)
-#pragma unroll
-          for (int v = 0; v <= u; ++v)
-            if (!GD || u < ntb) G[u][v] = A::mma(y[rb][u][r], y[rb][v][r], G[u][v]);
-      }
+        for (int t = 0; t < NT; ++t) cur[ks][t] = (T)nxt[ks][t];
+    }
   }
-  __syncthreads();  // every wave is done with its staging tile before Gs reuses it
   reduce_gram<NT, A>(G, NT, b, Gs, partials + (long long)wg * b * b);
 }
 
 template <int NT, int KS, class A, bool ST = false>
-__global__ __launch_bounds__(kThreads) void k_gram_left_factor(const double *__restrict__ X, int a, int b, long long I,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NT <= 3 ? 2 : 1, NT <= 3 ? 2 : 1))) void k_gram_left_factor(const double *__restrict__ X, int a, int b, long long I,
                                                                const double *__restrict__ P, int p, long long sPr,
                                                                long long sPa, int tri, long long spw,
                                                                double *__restrict__ partials,
@@ -391,10 +478,10 @@ __global__ __launch_bounds__(kThreads) void k_gram_left_factor(const double *__r
 // KS = k-steps over b.  With NT <= 3 two waves share each SIMD, so one wave's
 // loads and stores overlap the other's matrix-core work.
 // ---------------------------------------------------------------------------
-template <int NT, int KS, bool GD = false>
+template <int NT, int KS, bool GD = false, bool BAND = GD>
 __device__ __forceinline__ void apply_mfma_body(const int wg, const double *__restrict__ X, int a, int b, long long I, const double *__restrict__ P, int p,
                   long long sPr, long long sPa, const double *__restrict__ Q, int q, long long sQr, long long sQc,
-                  long long spw, double *__restrict__ Y) {
+                  int tri, long long spw, double *__restrict__ Y) {
   constexpr int KA = NT * 4;  // k-steps over alpha (whole tiles)
   __shared__ double fragQ[NT * KS * 64];
   __shared__ double fragP[NT * KA * 64];
@@ -402,6 +489,7 @@ __device__ __forceinline__ void apply_mfma_body(const int wg, const double *__re
   const int g = lane >> 4, j = lane & 15;
   const int ksr = (b + 3) / 4, ntq = (q + 15) / 16, nta = (a + 15) / 16, ntp = (p + 15) / 16;  // GD
   const bool hasP = (P != nullptr);
+  const bool triQ = (tri & 1) != 0, triP = (tri & 2) != 0;
   constexpr int LDP = NT * 16 + 1;
   __shared__ double Lst[kWaves * LDP * 16];
   double *Lw = Lst + wave * LDP * 16;
@@ -412,48 +500,108 @@ __device__ __forceinline__ void apply_mfma_body(const int wg, const double *__re
   const long long end = std::min(beg + spw, I);
   const long long col = (long long)a * I;
   const long long ocol = (long long)p * I;
+  // register prefetch of the next slice where registers allow (NT <= 3; the
+  // batched form keeps two waves per SIMD instead)
+  constexpr bool PF = (NT <= 3) && !GD;
   double cur[KS][NT];
-  for (long long i = beg + wave; i < end; i += kWaves) {
-    load_slice<NT, KS, true>(X + (long long)a * i, col, a, b, g, j, cur);
-    d4 w[NT][NT];  // [alpha-tile][c-tile]
-#pragma unroll
-    for (int u = 0; u < NT; ++u)
-#pragma unroll
-      for (int v = 0; v < NT; ++v) w[u][v] = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-      for (int cb = 0; cb < NT; ++cb) {
-        if (GD && (ks >= ksr || cb >= ntq)) continue;
-        const double qb = fragQ[(cb * KS + ks) * 64 + lane];
-#pragma unroll
-        for (int t = 0; t < NT; ++t)
-          if (!GD || t < nta) w[t][cb] = mfma(cur[ks][t], qb, w[t][cb]);
-      }
+  double nxt[PF ? KS : 1][NT];
+  long long i = beg + wave;
+  if constexpr (PF)
+    if (i < end) load_slice<NT, KS, true>(X + (long long)a * i, col, a, b, g, j, cur);
+  for (; i < end; i += kWaves) {
+    if constexpr (PF) {
+      if (i + kWaves < end) load_slice<NT, KS, true>(X + (long long)a * (i + kWaves), col, a, b, g, j, nxt);
+    } else {
+      load_slice<NT, KS, true>(X + (long long)a * i, col, a, b, g, j, cur);
+    }
     double *Yi = Y + (long long)p * i;
-    if (hasP) {
-      d4 y[NT][NT];  // [rho-tile][c-tile]
+    if constexpr (!BAND) {
+      // the whole W = M Q, then the whole Y = P W: long runs of independent
+      // matrix-core products between the LDS round trips of the stores
+      d4 w[NT][NT];  // [alpha-tile][c-tile]
 #pragma unroll
       for (int u = 0; u < NT; ++u)
 #pragma unroll
-        for (int v = 0; v < NT; ++v) y[u][v] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int v = 0; v < NT; ++v) w[u][v] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int t = 0; t < NT; ++t)
+      for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          if (t * 16 + 4 * r >= a) continue;  // rows of W past a are padding
+        for (int cb = 0; cb < NT; ++cb) {
+          if (triQ && ks < 4 * cb) continue;
+          const double qb = fragQ[(cb * KS + ks) * 64 + lane];
 #pragma unroll
-          for (int rb = 0; rb < NT; ++rb) {
-            if (GD && rb >= ntp) continue;
-            const double pa = fragP[(rb * KA + t * 4 + r) * 64 + lane];
-#pragma unroll
-            for (int cb = 0; cb < NT; ++cb)
-              if (!GD || cb < ntq) y[rb][cb] = mfma(pa, w[t][cb][r], y[rb][cb]);
-          }
+          for (int t = 0; t < NT; ++t) w[t][cb] = mfma(cur[ks][t], qb, w[t][cb]);
         }
-      store_tiles<NT, F64>(y, p, q, Yi, ocol, Lw, LDP, lane, g, j);
+      if (hasP) {
+        d4 y[NT][NT];  // [rho-tile][c-tile]
+#pragma unroll
+        for (int u = 0; u < NT; ++u)
+#pragma unroll
+          for (int v = 0; v < NT; ++v) y[u][v] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            if (t * 16 + 4 * r >= a) continue;  // rows of W past a are padding
+#pragma unroll
+            for (int rb = 0; rb < NT; ++rb) {
+              if (triP && t < rb) continue;
+              const double pa = fragP[(rb * KA + t * 4 + r) * 64 + lane];
+#pragma unroll
+              for (int cb = 0; cb < NT; ++cb) y[rb][cb] = mfma(pa, w[t][cb][r], y[rb][cb]);
+            }
+          }
+        store_tiles<NT, F64>(y, p, q, Yi, ocol, Lw, LDP, lane, g, j);
+      } else {
+        store_tiles<NT, F64>(w, p, q, Yi, ocol, Lw, LDP, lane, g, j);
+      }
     } else {
-      store_tiles<NT, F64>(w, p, q, Yi, ocol, Lw, LDP, lane, g, j);
+    // one 16-column band of the output at a time: Y(:, band) = P M Q(:, band)
+    // needs only that band of W = M Q, so few accumulator tiles are live
+    // (the batched form, whose run-time extents keep more registers busy)
+#pragma unroll
+    for (int cb = 0; cb < NT; ++cb) {
+      if (cb * 16 >= q) break;
+      d4 w[NT];  // W(alpha, c), c in band cb, one tile per alpha-tile
+#pragma unroll
+      for (int t = 0; t < NT; ++t) w[t] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        // lower-triangular Q: Q(beta, c) = 0 for beta < c, so k-steps below 4 cb vanish
+        if ((triQ && ks < 4 * cb) || (GD && ks >= ksr)) continue;
+        const double qb = fragQ[(cb * KS + ks) * 64 + lane];
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+          if (!GD || t < nta) w[t] = mfma(cur[ks][t], qb, w[t]);
+      }
+      if (hasP) {
+        d4 y[NT];  // Y(rho, c), c in band cb, one tile per rho-tile
+#pragma unroll
+        for (int u = 0; u < NT; ++u) y[u] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            if (t * 16 + 4 * r >= a) continue;  // rows of W past a are padding
+#pragma unroll
+            for (int rb = 0; rb < NT; ++rb) {
+              // upper-triangular P: P(rho, alpha) = 0 for alpha < rho
+              if ((GD && rb >= ntp) || (triP && t < rb)) continue;
+              const double pa = fragP[(rb * KA + t * 4 + r) * 64 + lane];
+              y[rb] = mfma(pa, w[t][r], y[rb]);
+            }
+          }
+        store_col<NT, F64>(y, cb, p, q, Yi, ocol, Lw, LDP, lane, g, j);
+      } else {
+        store_col<NT, F64>(w, cb, p, q, Yi, ocol, Lw, LDP, lane, g, j);
+      }
+    }
+    }
+    if constexpr (PF) {
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) cur[ks][t] = nxt[ks][t];
     }
   }
 }
@@ -461,8 +609,8 @@ __device__ __forceinline__ void apply_mfma_body(const int wg, const double *__re
 template <int NT, int KS>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NT <= 3 ? 2 : 1, NT <= 3 ? 2 : 1))) void k_apply_mfma(const double *__restrict__ X, int a, int b, long long I, const double *__restrict__ P, int p,
                   long long sPr, long long sPa, const double *__restrict__ Q, int q, long long sQr, long long sQc,
-                  long long spw, double *__restrict__ Y) {
-  apply_mfma_body<NT, KS>(blockIdx.x, X, a, b, I, P, p, sPr, sPa, Q, q, sQr, sQc, spw, Y);
+                  int tri, long long spw, double *__restrict__ Y) {
+  apply_mfma_body<NT, KS>(blockIdx.x, X, a, b, I, P, p, sPr, sPa, Q, q, sQr, sQc, tri, spw, Y);
 }
 
 // ---------------------------------------------------------------------------
@@ -685,10 +833,10 @@ __global__ __launch_bounds__(kThreads) void kb_gram_left_factor(const BDesc *__r
                                                        e.spw, e.out)))
 }
 template <int NT>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NT <= 2 ? 2 : 1, NT <= 2 ? 2 : 1)))
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NT <= 3 ? 2 : 1, NT <= 3 ? 2 : 1)))
 void kb_apply_mfma(const BDesc *__restrict__ d, const WGItem *__restrict__ items, int nitems) {
   TTR_ITEMS_LOOP((apply_mfma_body<NT, 4 * NT, true>(w.wg, e.X, e.a, e.b, e.I, e.P, e.p, e.sPr, e.sPa, e.Q, e.q, e.sQr,
-                                              e.sQc, e.spw, e.out)))
+                                              e.sQc, 0, e.spw, e.out)))
 }
 template <int NT, bool TR>
 __global__ __launch_bounds__(kThreads) void kb_gram_fac(const BDesc *__restrict__ d, const WGItem *__restrict__ items,
@@ -779,14 +927,14 @@ int launch_gram_left_factor(hipStream_t s, const double *X, int a, int b, long l
 }
 
 void launch_apply_mfma(hipStream_t s, const double *X, int a, int b, long long I, const double *P, int p,
-                       long long sPr, long long sPa, const double *Q, int q, long long sQr, long long sQc,
+                       long long sPr, long long sPa, const double *Q, int q, long long sQr, long long sQc, int tri,
                        double *Y) {
   const Grid gr = grid_of(I);
   const int nt = std::max({tiles_for(a), tiles_for(b), tiles_for(p), tiles_for(q)});
   const int ks = std::max((b + 3) / 4, 4 * nt - 3);
   nt_ks(nt, ks, [&](auto NTc, auto KSc) {
     constexpr int NTV = decltype(NTc)::value, KSV = decltype(KSc)::value;
-    TTR_LAUNCH(k_apply_mfma<NTV, KSV>) X, a, b, I, P, p, sPr, sPa, Q, q, sQr, sQc, gr.spw, Y);
+    TTR_LAUNCH(k_apply_mfma<NTV, KSV>) X, a, b, I, P, p, sPr, sPa, Q, q, sQr, sQc, tri, gr.spw, Y);
   });
 }
 
