@@ -68,44 +68,93 @@ __device__ double lmax(double v) {
   return r;
 }
 
-// Right-looking Cholesky of the d x d symmetric A (device memory, ld d) in
-// place, lower triangle (strict upper zeroed).  False if a pivot is not positive.
-__device__ bool lchol(double *A, int d) {
-  __shared__ int ok;
-  if (threadIdx.x == 0) ok = 1;
+// Block-wide argmax: the largest v, the smallest p among equal v; the result
+// is returned in every thread.
+__device__ void largmax(double *v, int *p) {
+  __shared__ double wv[kLT / 64];
+  __shared__ int wp[kLT / 64];
+  double bv = *v;
+  int bp = *p;
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_xor(bv, off, 64);
+    const int op = __shfl_xor(bp, off, 64);
+    if (ov > bv || (ov == bv && op < bp)) {
+      bv = ov;
+      bp = op;
+    }
+  }
+  const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    wv[wave] = bv;
+    wp[wave] = bp;
+  }
   __syncthreads();
+  bv = wv[0];
+  bp = wp[0];
+  for (int w = 1; w < nw; ++w)
+    if (wv[w] > bv || (wv[w] == bv && wp[w] < bp)) {
+      bv = wv[w];
+      bp = wp[w];
+    }
+  __syncthreads();
+  *v = bv;
+  *p = bp;
+}
+
+// Right-looking Cholesky of the d x d symmetric A (device memory, ld d) in
+// place, lower triangle (strict upper zeroed).  False if a pivot is not
+// positive.  One barrier per column: step j updates the trailing lower
+// triangle with the unscaled column j (L(r,j) L(c,j) = A(r,j) A(c,j) / A(j,j))
+// and scales column j-1, which no thread reads during step j.  Threads run as
+// 32 rows x (blockDim/32) columns, so the row updates of a column coalesce.
+__device__ bool lchol(double *A, int d) {
+  const int tr = threadIdx.x & 31, tc = threadIdx.x >> 5, nc = blockDim.x >> 5;
+  double lprev = 0.0;
   for (int j = 0; j < d; ++j) {
-    if (threadIdx.x == 0) {
-      const double pv = A[j + (size_t)d * j];
-      if (!(pv > 0.0)) ok = 0;
-      else A[j + (size_t)d * j] = sqrt(pv);
+    const double pv = A[j + (size_t)d * j];
+    if (!(pv > 0.0)) return false;  // the same value in every thread
+    if (j > 0)
+      for (int r = j - 1 + threadIdx.x; r < d; r += blockDim.x)
+        A[r + (size_t)d * (j - 1)] = (r == j - 1) ? lprev : A[r + (size_t)d * (j - 1)] / lprev;
+    const double rp = 1.0 / pv;
+    for (int c = j + 1 + tc; c < d; c += nc) {
+      const double acj = A[c + (size_t)d * j] * rp;
+      for (int r = c + tr; r < d; r += 32) A[r + (size_t)d * c] -= A[r + (size_t)d * j] * acj;
     }
-    __syncthreads();
-    if (!ok) return false;
-    const double ljj = A[j + (size_t)d * j];
-    for (int r = j + 1 + threadIdx.x; r < d; r += blockDim.x) A[r + (size_t)d * j] /= ljj;
-    __syncthreads();
-    const int n = d - j - 1;
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-      const int r = j + 1 + e % n, c = j + 1 + e / n;
-      if (c <= r) A[r + (size_t)d * c] -= A[r + (size_t)d * j] * A[c + (size_t)d * j];
-    }
+    lprev = sqrt(pv);
     __syncthreads();
   }
+  if (threadIdx.x == 0) A[(d - 1) + (size_t)d * (d - 1)] = lprev;
   for (int e = threadIdx.x; e < d * d; e += blockDim.x)
     if (e % d < e / d) A[e] = 0.0;
   __syncthreads();
   return true;
 }
 
-// X = L^{-1} (k x k lower, ld d) for the lower-triangular L in A (ld d).
+// X = L^{-1} (k x k lower, ld d) for the lower-triangular L in A (ld d):
+// column-oriented forward substitution on all right-hand sides at once, one
+// barrier per column of L.  Step m eliminates with row m of X (scaled on the
+// fly); the row itself is scaled one step later, when no thread reads it.
 __device__ void linv(const double *A, double *X, int k, int d) {
-  for (int c = threadIdx.x; c < k; c += blockDim.x)
-    for (int r = 0; r < k; ++r) {
-      double v = (r == c) ? 1.0 : 0.0;
-      for (int m = c; m < r; ++m) v -= A[r + (size_t)d * m] * X[m + (size_t)d * c];
-      X[r + (size_t)d * c] = (r < c) ? 0.0 : v / A[r + (size_t)d * r];
+  const int tr = threadIdx.x & 31, tc = threadIdx.x >> 5, nc = blockDim.x >> 5;
+  for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
+    const int r = e % k, c = e / k;
+    X[r + (size_t)d * c] = (r == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  double pprev = 0.0;
+  for (int m = 0; m < k; ++m) {
+    const double pm = 1.0 / A[m + (size_t)d * m];
+    if (m > 0)
+      for (int c = threadIdx.x; c < m; c += blockDim.x) X[(m - 1) + (size_t)d * c] *= pprev;
+    for (int c = tc; c <= m; c += nc) {
+      const double xm = X[m + (size_t)d * c] * pm;
+      for (int r = m + 1 + tr; r < k; r += 32) X[r + (size_t)d * c] -= A[r + (size_t)d * m] * xm;
     }
+    pprev = pm;
+    __syncthreads();
+  }
+  for (int c = threadIdx.x; c < k; c += blockDim.x) X[(k - 1) + (size_t)d * c] *= pprev;
   __syncthreads();
 }
 
@@ -139,18 +188,24 @@ __device__ int lpivchol(double *A, int d, double tau, int *perm) {
   __syncthreads();
   int k = d;
   for (int j = 0; j < d; ++j) {
-    if (threadIdx.x == 0) {
-      int p = j;
-      double v = A[j + (size_t)d * j];
-      for (int i = j + 1; i < d; ++i)
-        if (A[i + (size_t)d * i] > v) {
-          v = A[i + (size_t)d * i];
+    {
+      // the largest remaining diagonal entry, the first one among ties
+      double v = -DBL_MAX;
+      int p = d;
+      for (int i = j + threadIdx.x; i < d; i += blockDim.x) {
+        const double di = A[i + (size_t)d * i];
+        if (di > v) {
+          v = di;
           p = i;
         }
-      piv = p;
-      stop = !(v > tau * dmax0);
+      }
+      largmax(&v, &p);
+      if (threadIdx.x == 0) {
+        piv = p;
+        stop = !(v > tau * dmax0) || p >= d;
+      }
+      __syncthreads();
     }
-    __syncthreads();
     if (stop) {
       k = j;
       break;
@@ -381,73 +436,58 @@ __global__ __launch_bounds__(kLT) void lk_step(LStepArgs a) {
 struct LTruncArgs {
   const double *R;      // k x b (ld k)
   int k, b;
-  const double *Glast;  // d x k (ld d)
-  int d;
-  const double *Fn;     // dn x b (ld dn)
-  int dn;
-  double *GU;           // d x L
-  double *Pnext;        // L x dn
   double *delta, *norm;
   int first;
   double tol;
   int Nm1;
   double *sigma_out;    // TTR_RMAX values
-  int *dec;             // [3] L, [2] error flags
-  int identity;
-  double *W0, *W1;      // scratch: W0 b x k (R^T), W1 k x k
+  int *dec;             // [3] L, [2] error flags, [7] no truncation (set by lk_trunc_setup)
+  int identity;         // no truncation already proven by the first Gram pass
+  double *W0, *W1;      // scratch: W0 b x k (R^T, then A), W1 k x k (U)
+  double *thr;          // [0] Jacobi rotation threshold, [1] column-norm floor
   double *sv;           // k
   int *perm;            // k
+  double *Up, *Ap;      // gathered U(:, perm[0:L]) (k x L), A(:, perm[0:L]) (b x L)
 };
 
-__device__ inline void lrr_pair(int r, int kq, int nn, int *p, int *q) {
-  if (kq == 0) {
-    *p = r;
-    *q = nn - 1;
-  } else {
-    const int m = nn - 1;
-    *p = (r + kq) % m;
-    *q = (r - kq + m) % m;
+// Truncation (Alg. 2 inner step), part 1.  Decides whether the SVD of R can
+// be skipped (no singular value can fall below delta); if so sets the norm
+// and threshold at the first link and dec[3] = k, dec[7] = 1.  Otherwise sets
+// up the one-sided Jacobi SVD of R: W0 = A = R^T (b x k), W1 = U = I (k x k),
+// and the rotation thresholds.
+__global__ __launch_bounds__(kLT) void lk_trunc_setup(LTruncArgs a) {
+  const int k = a.k, b = a.b;
+  __shared__ int ident, tri_ok;
+  if (threadIdx.x == 0) {
+    ident = a.identity;
+    tri_ok = 1;
   }
-}
-
-// Truncation (Alg. 2 inner step): SVD of R by one-sided Jacobi on R^T, the
-// Frobenius-tail rank, GU = Glast U_L and Pnext = Sigma_L V_L^T Fn^T.
-__global__ __launch_bounds__(kLT) void lk_trunc(LTruncArgs a) {
-  const int k = a.k, b = a.b, d = a.d;
-  double *A = a.W0, *U = a.W1;
-  __shared__ int ident, flag, LL;
-  if (threadIdx.x == 0) ident = a.identity;
   __syncthreads();
   if (!ident && k == b) {
     // upper-triangular R: sigma_min >= 1 / ||R^{-1}||_F proves that nothing can be dropped
-    __shared__ int tri_ok;
-    if (threadIdx.x == 0) tri_ok = 1;
-    __syncthreads();
     for (int e = threadIdx.x; e < k * k; e += blockDim.x)
       if (e % k > e / k && a.R[e] != 0.0) tri_ok = 0;
     __syncthreads();
     if (tri_ok) {
-      for (int c = threadIdx.x; c < k; c += blockDim.x)
-        for (int r = k - 1; r >= 0; --r) {
-          if (r > c) {
-            U[r + (size_t)k * c] = 0.0;
-            continue;
-          }
-          double v = (r == c) ? 1.0 : 0.0;
-          for (int m = r + 1; m <= c; ++m) v -= a.R[r + (size_t)k * m] * U[m + (size_t)k * c];
-          U[r + (size_t)k * c] = v / a.R[r + (size_t)k * r];
-        }
-      __syncthreads();
-      double xf = 0.0, rf = 0.0;
+      // ||R^{-1}||_F = ||(R^T)^{-1}||_F, R^T lower triangular
       for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
-        xf += U[e] * U[e];
-        rf += a.R[e] * a.R[e];
+        const int r = e % k, c = e / k;
+        a.W0[r + (size_t)k * c] = a.R[c + (size_t)k * r];
       }
+      __syncthreads();
+      bool okd = true;
+      for (int j = 0; j < k; ++j) okd = okd && (a.R[j + (size_t)k * j] != 0.0);
+      double xf = 0.0, rf = 0.0;
+      if (okd) {
+        linv(a.W0, a.W1, k, k);
+        for (int e = threadIdx.x; e < k * k; e += blockDim.x) xf += a.W1[e] * a.W1[e];
+      }
+      for (int e = threadIdx.x; e < k * k; e += blockDim.x) rf += a.R[e] * a.R[e];
       xf = lsum(xf);
       rf = lsum(rf);
       if (threadIdx.x == 0) {
         const double dl2 = a.first ? ((a.Nm1 > 0) ? a.tol * a.tol * rf / (double)a.Nm1 : 0.0) : (*a.delta) * (*a.delta);
-        ident = (xf > 0.0 && lfinite(xf) && 1.0 / xf > 4.0 * dl2) ? 1 : 0;
+        ident = (okd && xf > 0.0 && lfinite(xf) && 1.0 / xf > 4.0 * dl2) ? 1 : 0;
       }
       __syncthreads();
     }
@@ -464,103 +504,132 @@ __global__ __launch_bounds__(kLT) void lk_trunc(LTruncArgs a) {
       }
       for (int j = 0; j < TTR_RMAX; ++j) a.sigma_out[j] = 0.0;
       a.dec[3] = k;
-    }
-    for (int e = threadIdx.x; e < d * k; e += blockDim.x) a.GU[e] = a.Glast[e];
-    for (int e = threadIdx.x; e < k * a.dn; e += blockDim.x) {
-      const int l = e % k, r = e / k;
-      double s = 0.0;
-      for (int j = 0; j < b; ++j) s += a.R[l + (size_t)k * j] * a.Fn[r + (size_t)a.dn * j];
-      a.Pnext[l + (size_t)k * r] = s;
+      a.dec[7] = 1;
     }
     return;
   }
   for (int e = threadIdx.x; e < b * k; e += blockDim.x) {
     const int r = e % b, c = e / b;
-    A[r + (size_t)b * c] = a.R[c + (size_t)k * r];
+    a.W0[r + (size_t)b * c] = a.R[c + (size_t)k * r];
   }
-  for (int e = threadIdx.x; e < k * k; e += blockDim.x) U[e] = (e % k == e / k) ? 1.0 : 0.0;
-  __syncthreads();
+  for (int e = threadIdx.x; e < k * k; e += blockDim.x) a.W1[e] = (e % k == e / k) ? 1.0 : 0.0;
   double f2 = 0.0;
-  for (int e = threadIdx.x; e < b * k; e += blockDim.x) f2 += A[e] * A[e];
+  for (int e = threadIdx.x; e < b * k; e += blockDim.x) f2 += a.R[e] * a.R[e];
   f2 = lsum(f2);
-  const double tol = kU * 4.0 * sqrt((double)(b > 1 ? b : 1));
-  const double floor2 = (8.0 * (b + k) * kU) * (8.0 * (b + k) * kU) * f2;
-  const int nn = k + (k & 1), npair = nn / 2;
-  // 16 threads per column pair, 16 rows each, loads issued together; the 128
-  // pairs of a round take two passes of the 64 pair groups
-  constexpr int TPP = 16, RPT = kLMax / TPP, GROUPS = kLT / TPP;
-  const int grp = threadIdx.x / TPP, sub = threadIdx.x % TPP;
-  int sweeps = -1;
-  for (int sweep = 0; sweep < 60; ++sweep) {
-    if (threadIdx.x == 0) flag = 0;
+  if (threadIdx.x == 0) {
+    a.thr[0] = kU * 4.0 * sqrt((double)(b > 1 ? b : 1));
+    a.thr[1] = (8.0 * (b + k) * kU) * (8.0 * (b + k) * kU) * f2;
+    a.dec[7] = 0;
+  }
+}
+
+__device__ inline void lrr_pair(int r, int kq, int nn, int *p, int *q) {
+  if (kq == 0) {
+    *p = r;
+    *q = nn - 1;
+  } else {
+    const int m = nn - 1;
+    *p = (r + kq) % m;
+    *q = (r - kq + m) % m;
+  }
+}
+
+// One round of the block one-sided Jacobi SVD of A (b x k): the k columns form
+// nbp (even) blocks of kJW; round `round` of the round-robin pairs block P
+// with block Q in workgroup `pair`, which orthogonalizes the 2 kJW columns
+// jointly in LDS (inner one-sided Jacobi sweeps, rotations also applied to
+// the same columns of U) and writes them back.  A pair of columns is rotated
+// when |a_p^T a_q| > thr[0] ||a_p|| ||a_q|| and both squared norms exceed
+// thr[1].  *flag is set when any rotation was applied.
+constexpr int kJW = 8;
+constexpr int kJT = 256;
+__global__ __launch_bounds__(kJT) void lk_jacobi_round(double *__restrict__ A, double *__restrict__ U, int b, int k,
+                                                       int nbp, int round, const double *__restrict__ thr,
+                                                       int *__restrict__ flag) {
+  constexpr int NC = 2 * kJW;
+  __shared__ double As[NC][kLMax];
+  __shared__ double Us[NC][kLMax];
+  __shared__ int rotated, any;
+  int P, Q;
+  lrr_pair(round, blockIdx.x, nbp, &P, &Q);
+  auto gcol = [&](int l) { return l < kJW ? P * kJW + l : Q * kJW + (l - kJW); };
+  for (int e = threadIdx.x; e < NC * b; e += blockDim.x) {
+    const int l = e / b, r = e % b, c = gcol(l);
+    As[l][r] = (c < k) ? A[r + (size_t)b * c] : 0.0;
+  }
+  for (int e = threadIdx.x; e < NC * k; e += blockDim.x) {
+    const int l = e / k, r = e % k, c = gcol(l);
+    Us[l][r] = (c < k) ? U[r + (size_t)k * c] : 0.0;
+  }
+  if (threadIdx.x == 0) any = 0;
+  const double tol = thr[0], floor2 = thr[1];
+  // 8 column pairs per inner round, 32 threads per pair
+  const int lp = threadIdx.x >> 5, sub = threadIdx.x & 31;
+  __syncthreads();
+  for (int sw = 0; sw < 6; ++sw) {
+    if (threadIdx.x == 0) rotated = 0;
     __syncthreads();
-    for (int r = 0; r < nn - 1; ++r) {
-      for (int pass = 0; pass * GROUPS < npair; ++pass) {
-        const int pair = grp + pass * GROUPS;
-        int p = 0, q = 0;
-        const bool mine = pair < npair;
-        if (mine) lrr_pair(r, pair, nn, &p, &q);
-        const bool act = mine && p < k && q < k;
-        double ap[RPT], aq[RPT];
-#pragma unroll
-        for (int t = 0; t < RPT; ++t) {
-          const int j = sub + TPP * t;
-          const bool in = act && j < b;
-          ap[t] = in ? A[j + (size_t)b * p] : 0.0;
-          aq[t] = in ? A[j + (size_t)b * q] : 0.0;
+    for (int rr = 0; rr < NC - 1; ++rr) {
+      int p, q;
+      lrr_pair(rr, lp, NC, &p, &q);
+      const bool act = gcol(p) < k && gcol(q) < k;
+      double al = 0.0, be = 0.0, ga = 0.0;
+      if (act)
+        for (int r = sub; r < b; r += 32) {
+          const double x = As[p][r], y = As[q][r];
+          al += x * x;
+          be += y * y;
+          ga += x * y;
         }
-        double al = 0.0, be = 0.0, ga = 0.0;
-#pragma unroll
-        for (int t = 0; t < RPT; ++t) {
-          al += ap[t] * ap[t];
-          be += aq[t] * aq[t];
-          ga += ap[t] * aq[t];
+      for (int off = 1; off < 32; off <<= 1) {
+        al += __shfl_xor(al, off, 64);
+        be += __shfl_xor(be, off, 64);
+        ga += __shfl_xor(ga, off, 64);
+      }
+      if (act && al > floor2 && be > floor2 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
+        const double zeta = (be - al) / (2.0 * ga);
+        const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / sqrt(1.0 + t * t);
+        const double sn = c * t;
+        for (int r = sub; r < b; r += 32) {
+          const double x = As[p][r], y = As[q][r];
+          As[p][r] = c * x - sn * y;
+          As[q][r] = sn * x + c * y;
         }
-        for (int off = 1; off < TPP; off <<= 1) {
-          al += __shfl_xor(al, off, 64);
-          be += __shfl_xor(be, off, 64);
-          ga += __shfl_xor(ga, off, 64);
+        for (int r = sub; r < k; r += 32) {
+          const double x = Us[p][r], y = Us[q][r];
+          Us[p][r] = c * x - sn * y;
+          Us[q][r] = sn * x + c * y;
         }
-        if (act && al > floor2 && be > floor2 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
-          const double zeta = (be - al) / (2.0 * ga);
-          const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double c = 1.0 / sqrt(1.0 + t * t);
-          const double s = c * t;
-#pragma unroll
-          for (int u = 0; u < RPT; ++u) {
-            const int j = sub + TPP * u;
-            if (j < b) {
-              A[j + (size_t)b * p] = c * ap[u] - s * aq[u];
-              A[j + (size_t)b * q] = s * ap[u] + c * aq[u];
-            }
-          }
-          double up[RPT], uq[RPT];
-#pragma unroll
-          for (int u = 0; u < RPT; ++u) {
-            const int j = sub + TPP * u;
-            up[u] = (j < k) ? U[j + (size_t)k * p] : 0.0;
-            uq[u] = (j < k) ? U[j + (size_t)k * q] : 0.0;
-          }
-#pragma unroll
-          for (int u = 0; u < RPT; ++u) {
-            const int j = sub + TPP * u;
-            if (j < k) {
-              U[j + (size_t)k * p] = c * up[u] - s * uq[u];
-              U[j + (size_t)k * q] = s * up[u] + c * uq[u];
-            }
-          }
-          if (sub == 0) flag = 1;
-        }
+        if (sub == 0) rotated = 1;
       }
       __syncthreads();
     }
-    const int any = flag;
+    const int rot = rotated;
+    if (rot && threadIdx.x == 0) any = 1;
     __syncthreads();
-    if (!any) {
-      sweeps = sweep + 1;
-      break;
-    }
+    if (!rot) break;
   }
+  for (int e = threadIdx.x; e < NC * b; e += blockDim.x) {
+    const int l = e / b, r = e % b, c = gcol(l);
+    if (c < k) A[r + (size_t)b * c] = As[l][r];
+  }
+  for (int e = threadIdx.x; e < NC * k; e += blockDim.x) {
+    const int l = e / k, r = e % k, c = gcol(l);
+    if (c < k) U[r + (size_t)k * c] = Us[l][r];
+  }
+  if (threadIdx.x == 0 && any) *flag = 1;
+}
+
+// Truncation, part 3 (after the Jacobi sweeps): singular values (column norms
+// of A = R^T U = V Sigma), their descending order, the rank L (smallest with
+// Frobenius tail <= delta), the norm and threshold at the first link, and the
+// gathered columns Up = U(:, perm[0:L]), Ap = A(:, perm[0:L]) for the two
+// products GU = Glast Up and Pnext = Ap^T Fn^T.
+__global__ __launch_bounds__(kLT) void lk_trunc_finish(LTruncArgs a) {
+  const int k = a.k, b = a.b;
+  const double *A = a.W0, *U = a.W1;
+  __shared__ int LL;
   for (int j = threadIdx.x; j < k; j += blockDim.x) {
     double s = 0.0;
     for (int r = 0; r < b; ++r) s += A[r + (size_t)b * j] * A[r + (size_t)b * j];
@@ -575,7 +644,6 @@ __global__ __launch_bounds__(kLT) void lk_trunc(LTruncArgs a) {
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    if (sweeps < 0) a.dec[2] |= 2;
     if (a.first) {
       double n2 = 0.0;
       for (int j = k - 1; j >= 0; --j) n2 += a.sv[a.perm[j]] * a.sv[a.perm[j]];
@@ -598,19 +666,13 @@ __global__ __launch_bounds__(kLT) void lk_trunc(LTruncArgs a) {
   }
   __syncthreads();
   const int L = LL;
-  for (int e = threadIdx.x; e < d * L; e += blockDim.x) {
-    const int r = e % d, c = e / d;
-    const int pc = a.perm[c];
-    double s = 0.0;
-    for (int j = 0; j < k; ++j) s += a.Glast[r + (size_t)d * j] * U[j + (size_t)k * pc];
-    a.GU[r + (size_t)d * c] = s;
+  for (int e = threadIdx.x; e < k * L; e += blockDim.x) {
+    const int r = e % k, c = e / k;
+    a.Up[e] = U[r + (size_t)k * a.perm[c]];
   }
-  for (int e = threadIdx.x; e < L * a.dn; e += blockDim.x) {
-    const int l = e % L, r = e / L;
-    const int pc = a.perm[l];
-    double s = 0.0;
-    for (int j = 0; j < b; ++j) s += A[j + (size_t)b * pc] * a.Fn[r + (size_t)a.dn * j];
-    a.Pnext[l + (size_t)L * r] = s;
+  for (int e = threadIdx.x; e < b * L; e += blockDim.x) {
+    const int r = e % b, c = e / b;
+    a.Ap[e] = A[r + (size_t)b * a.perm[c]];
   }
 }
 
@@ -620,7 +682,7 @@ constexpr int kChunks = 256;  // chunk Grams per streamed Gram
 
 struct LWS {
   double *tC, *tA, *tB;  // materialized cores (max core each)
-  double *G, *Ra, *Rb, *Gst[3], *P[2], *GU, *W0, *W1, *scal, *sigma, *sv;
+  double *G, *Ra, *Rb, *Gst[3], *P[2], *GU, *W0, *W1, *Up, *Ap, *scal, *sigma, *sv;
   double *part;  // kChunks chunk Grams
   std::vector<double *> T;                 // N+1 slots
   std::vector<std::array<double *, 3>> B;  // N x 3 slots
@@ -702,6 +764,25 @@ struct Large {
       return ttr_fail(TTR_ERR_NUMERICAL, "non-finite data or a small factorization did not converge");
     return TTR_OK;
   }
+  // One-sided Jacobi SVD of A = W0 (b x k) with U = W1: sweeps of block
+  // rounds until a sweep applies no rotation.
+  int jacobi(long long b, int k) {
+    int *flag = reinterpret_cast<int *>(w.scal + 16);
+    const int nbp = std::max(2, 2 * ((k + 2 * kJW - 1) / (2 * kJW)));
+    for (int sweep = 0; sweep < 60; ++sweep) {
+      TTR_HIPCHK(hipMemsetAsync(flag, 0, sizeof(int), h->stream));
+      for (int r = 0; r < nbp - 1; ++r)
+        hipLaunchKernelGGL(lk_jacobi_round, dim3(nbp / 2), dim3(kJT), 0, h->stream, w.W0, w.W1, (int)b, k, nbp, r,
+                           w.scal + 8, flag);
+      TTR_HIPCHK(hipGetLastError());
+      h->stats.small_launches += nbp - 1;
+      int f = 0;
+      TTR_HIPCHK(hipMemcpyAsync(&f, flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+      TTR_HIPCHK(hipStreamSynchronize(h->stream));
+      if (!f) return TTR_OK;
+    }
+    return ttr_fail(TTR_ERR_NUMERICAL, "the truncation SVD did not converge");
+  }
   int step(const double *Rc, int d, int b, int pass, double *F, double *Rn, double *Tdst, double gerr, int check,
            int first, double tol2_nm1) {
     LStepArgs a;
@@ -742,7 +823,7 @@ int ttr_round_large(ttr_handle *h, const ttr_tt *X, double tol, ttr_tt *Y, doubl
   size_t mc = 0;
   for (int n = 0; n < N; ++n) mc = std::max(mc, (size_t)(X->R[n] * X->I[n] * X->R[n + 1]));
   mc = (mc + 63) & ~(size_t)63;
-  const size_t need = ((size_t)(N + 1) + 3 * (size_t)N + 13 + kChunks) * kSlotL + 64 + (size_t)(N + 1) * TTR_RMAX +
+  const size_t need = ((size_t)(N + 1) + 3 * (size_t)N + 15 + kChunks) * kSlotL + 64 + (size_t)(N + 1) * TTR_RMAX +
                       kLMax + kLMax + 3 * mc + 64;
   if (!h->large) h->large = new LargeCtx();
   LargeCtx *ctx = h->large;
@@ -780,6 +861,8 @@ int ttr_round_large(ttr_handle *h, const ttr_tt *X, double tol, ttr_tt *Y, doubl
   w.GU = take(kSlotL);
   w.W0 = take(kSlotL);
   w.W1 = take(kSlotL);
+  w.Up = take(kSlotL);
+  w.Ap = take(kSlotL);
   w.scal = take(64);
   w.sigma = take((size_t)(N + 1) * TTR_RMAX);
   w.sv = take(kLMax);
@@ -885,17 +968,16 @@ int ttr_round_large(ttr_handle *h, const ttr_tt *X, double tol, ttr_tt *Y, doubl
         return rc;
       E = out;
     }
-    // truncation
+    // truncation: SVD of R (k x cc) unless no singular value can fall below delta
+    const int kq = gd[g], dq = gd[g - 1];
+    const double *Rq = R[(g - 1) & 1];
+    const double *Fn = w.B[n + 1][nst[n + 1] - 1];
+    const int dn = dim[n + 1][nst[n + 1] - 1];
+    double *Pn = w.P[n & 1];
     LTruncArgs ta;
-    ta.R = R[(g - 1) & 1];
-    ta.k = gd[g];
+    ta.R = Rq;
+    ta.k = kq;
     ta.b = (int)cc;
-    ta.Glast = w.Gst[g - 1];
-    ta.d = gd[g - 1];
-    ta.Fn = w.B[n + 1][nst[n + 1] - 1];
-    ta.dn = dim[n + 1][nst[n + 1] - 1];
-    ta.GU = w.GU;
-    ta.Pnext = w.P[n & 1];
     ta.delta = w.scal + 1;
     ta.norm = w.scal + 2;
     ta.first = (n == 0);
@@ -906,15 +988,35 @@ int ttr_round_large(ttr_handle *h, const ttr_tt *X, double tol, ttr_tt *Y, doubl
     ta.identity = (g == 1) ? notrunc : 0;
     ta.W0 = w.W0;
     ta.W1 = w.W1;
+    ta.thr = w.scal + 8;
     ta.sv = w.sv;
     ta.perm = w.perm;
-    hipLaunchKernelGGL(lk_trunc, dim3(1), dim3(kLT), 0, h->stream, ta);
+    ta.Up = w.Up;
+    ta.Ap = w.Ap;
+    hipLaunchKernelGGL(lk_trunc_setup, dim3(1), dim3(kLT), 0, h->stream, ta);
     h->stats.small_launches++;
     if ((rc = L.sync_dec())) return rc;
-    const int Ln = h->dec_host[3];
+    int Ln;
+    const double *GU;
+    if (h->dec_host[7]) {
+      // L = k: U = I, Pnext = R Fn^T
+      Ln = kq;
+      GU = w.Gst[g - 1];
+      if ((rc = L.gemm(false, true, kq, dn, cc, Rq, kq, Fn, dn, Pn, kq))) return rc;
+    } else {
+      if ((rc = L.jacobi(cc, kq))) return rc;
+      hipLaunchKernelGGL(lk_trunc_finish, dim3(1), dim3(kLT), 0, h->stream, ta);
+      h->stats.small_launches++;
+      if ((rc = L.sync_dec())) return rc;
+      Ln = h->dec_host[3];
+      // GU = Glast U(:, perm[0:L]) (dq x L); Pnext = Sigma_L V_L^T Fn^T = A(:, perm[0:L])^T Fn^T
+      if ((rc = L.gemm(false, false, dq, Ln, kq, w.Gst[g - 1], dq, w.Up, kq, w.GU, dq))) return rc;
+      if ((rc = L.gemm(true, true, Ln, dn, cc, w.Ap, cc, Fn, dn, Pn, Ln))) return rc;
+      GU = w.GU;
+    }
     Lr[n + 1] = Ln;
     // output core n: V(Y_n) = V(E) GU
-    if ((rc = L.gemm(false, false, crow * In, Ln, gd[g - 1], E, crow * In, w.GU, gd[g - 1], Y->core[n], crow * In)))
+    if ((rc = L.gemm(false, false, crow * In, Ln, dq, E, crow * In, GU, dq, Y->core[n], crow * In)))
       return rc;
     ++L.applies;
     Pcur = w.P[n & 1];
