@@ -478,7 +478,29 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NT <= 
 // KS = k-steps over b.  With NT <= 3 two waves share each SIMD, so one wave's
 // loads and stores overlap the other's matrix-core work.
 // ---------------------------------------------------------------------------
-template <int NT, int KS, bool GD = false, bool BAND = GD>
+// Writes the tiles yt[u] of column band c of the transpose of an nrow x ncol
+// block of one output slice: register r of yt[u] in lane (g, j) holds
+// Y(16u + j, 16c + 4r + g).  The sixteen lanes of a lane group hold sixteen
+// consecutive rows of one column, so every store leaves as 128-byte runs,
+// with no staging.
+template <int NT>
+__device__ inline void store_t_band(const d4 (&yt)[NT], int c, int nrow, int ncol, double *__restrict__ Yi,
+                                    long long ocol, int g, int j) {
+#pragma unroll
+  for (int u = 0; u < NT; ++u) {
+    const int row = 16 * u + j;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int cc = 16 * c + 4 * r + g;
+      if (row < nrow && cc < ncol) Yi[row + ocol * cc] = yt[u][r];
+    }
+  }
+}
+
+// The output products are formed transposed, Y^T = (M Q)^T P^T (or Q^T M^T
+// without P): swapping the operands of the last product turns the result
+// registers into column runs (store_t_band).
+template <int NT, int KS, bool GD = false>
 __device__ __forceinline__ void apply_mfma_body(const int wg, const double *__restrict__ X, int a, int b, long long I, const double *__restrict__ P, int p,
                   long long sPr, long long sPa, const double *__restrict__ Q, int q, long long sQr, long long sQc,
                   int tri, long long spw, double *__restrict__ Y) {
@@ -487,12 +509,9 @@ __device__ __forceinline__ void apply_mfma_body(const int wg, const double *__re
   __shared__ double fragP[NT * KA * 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, j = lane & 15;
-  const int ksr = (b + 3) / 4, ntq = (q + 15) / 16, nta = (a + 15) / 16, ntp = (p + 15) / 16;  // GD
+  const int ksr = (b + 3) / 4, nta = (a + 15) / 16, ntp = (p + 15) / 16;  // GD
   const bool hasP = (P != nullptr);
   const bool triQ = (tri & 1) != 0, triP = (tri & 2) != 0;
-  constexpr int LDP = NT * 16 + 1;
-  __shared__ double Lst[kWaves * LDP * 16];
-  double *Lw = Lst + wave * LDP * 16;
   build_bfrag(fragQ, Q, b, q, sQr, sQc, NT, KS);
   if (hasP) build_afrag(fragP, P, p, a, sPr, sPa, NT, KA);
   __syncthreads();
@@ -500,9 +519,9 @@ __device__ __forceinline__ void apply_mfma_body(const int wg, const double *__re
   const long long end = std::min(beg + spw, I);
   const long long col = (long long)a * I;
   const long long ocol = (long long)p * I;
-  // register prefetch of the next slice where registers allow (NT <= 3; the
-  // batched form keeps two waves per SIMD instead)
-  constexpr bool PF = (NT <= 3) && !GD;
+  // register prefetch of the next slice where it fits without spilling (the
+  // batched form keeps its registers for the run-time extents)
+  constexpr bool PF = (NT <= 2 || (NT == 3 && KS <= 11)) && !GD;
   double cur[KS][NT];
   double nxt[PF ? KS : 1][NT];
   long long i = beg + wave;
@@ -515,69 +534,28 @@ __device__ __forceinline__ void apply_mfma_body(const int wg, const double *__re
       load_slice<NT, KS, true>(X + (long long)a * i, col, a, b, g, j, cur);
     }
     double *Yi = Y + (long long)p * i;
-    if constexpr (!BAND) {
-      // the whole W = M Q, then the whole Y = P W: long runs of independent
-      // matrix-core products between the LDS round trips of the stores
-      d4 w[NT][NT];  // [alpha-tile][c-tile]
-#pragma unroll
-      for (int u = 0; u < NT; ++u)
-#pragma unroll
-        for (int v = 0; v < NT; ++v) w[u][v] = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-        for (int cb = 0; cb < NT; ++cb) {
-          if (triQ && ks < 4 * cb) continue;
-          const double qb = fragQ[(cb * KS + ks) * 64 + lane];
-#pragma unroll
-          for (int t = 0; t < NT; ++t) w[t][cb] = mfma(cur[ks][t], qb, w[t][cb]);
-        }
-      if (hasP) {
-        d4 y[NT][NT];  // [rho-tile][c-tile]
-#pragma unroll
-        for (int u = 0; u < NT; ++u)
-#pragma unroll
-          for (int v = 0; v < NT; ++v) y[u][v] = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int t = 0; t < NT; ++t)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            if (t * 16 + 4 * r >= a) continue;  // rows of W past a are padding
-#pragma unroll
-            for (int rb = 0; rb < NT; ++rb) {
-              if (triP && t < rb) continue;
-              const double pa = fragP[(rb * KA + t * 4 + r) * 64 + lane];
-#pragma unroll
-              for (int cb = 0; cb < NT; ++cb) y[rb][cb] = mfma(pa, w[t][cb][r], y[rb][cb]);
-            }
-          }
-        store_tiles<NT, F64>(y, p, q, Yi, ocol, Lw, LDP, lane, g, j);
-      } else {
-        store_tiles<NT, F64>(w, p, q, Yi, ocol, Lw, LDP, lane, g, j);
-      }
-    } else {
     // one 16-column band of the output at a time: Y(:, band) = P M Q(:, band)
-    // needs only that band of W = M Q, so few accumulator tiles are live
-    // (the batched form, whose run-time extents keep more registers busy)
+    // needs only that band of W = M Q, so few accumulator tiles are live and
+    // the next slice's prefetch fits beside them
 #pragma unroll
     for (int cb = 0; cb < NT; ++cb) {
       if (cb * 16 >= q) break;
-      d4 w[NT];  // W(alpha, c), c in band cb, one tile per alpha-tile
-#pragma unroll
-      for (int t = 0; t < NT; ++t) w[t] = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        // lower-triangular Q: Q(beta, c) = 0 for beta < c, so k-steps below 4 cb vanish
-        if ((triQ && ks < 4 * cb) || (GD && ks >= ksr)) continue;
-        const double qb = fragQ[(cb * KS + ks) * 64 + lane];
-#pragma unroll
-        for (int t = 0; t < NT; ++t)
-          if (!GD || t < nta) w[t] = mfma(cur[ks][t], qb, w[t]);
-      }
       if (hasP) {
-        d4 y[NT];  // Y(rho, c), c in band cb, one tile per rho-tile
+        d4 w[NT];  // W(alpha, c), c in band cb, one tile per alpha-tile
 #pragma unroll
-        for (int u = 0; u < NT; ++u) y[u] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int t = 0; t < NT; ++t) w[t] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+          // lower-triangular Q: Q(beta, c) = 0 for beta < c, so k-steps below 4 cb vanish
+          if ((triQ && ks < 4 * cb) || (GD && ks >= ksr)) continue;
+          const double qb = fragQ[(cb * KS + ks) * 64 + lane];
+#pragma unroll
+          for (int t = 0; t < NT; ++t)
+            if (!GD || t < nta) w[t] = mfma(cur[ks][t], qb, w[t]);
+        }
+        d4 yt[NT];  // Y^T tiles (c-band cb, rho-tile)
+#pragma unroll
+        for (int u = 0; u < NT; ++u) yt[u] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int t = 0; t < NT; ++t)
 #pragma unroll
@@ -588,14 +566,24 @@ __device__ __forceinline__ void apply_mfma_body(const int wg, const double *__re
               // upper-triangular P: P(rho, alpha) = 0 for alpha < rho
               if ((GD && rb >= ntp) || (triP && t < rb)) continue;
               const double pa = fragP[(rb * KA + t * 4 + r) * 64 + lane];
-              y[rb] = mfma(pa, w[t][r], y[rb]);
+              yt[rb] = mfma(w[t][r], pa, yt[rb]);
             }
           }
-        store_col<NT, F64>(y, cb, p, q, Yi, ocol, Lw, LDP, lane, g, j);
+        store_t_band<NT>(yt, cb, p, q, Yi, ocol, g, j);
       } else {
-        store_col<NT, F64>(w, cb, p, q, Yi, ocol, Lw, LDP, lane, g, j);
+        d4 wt[NT];  // W^T tiles (c-band cb, alpha-tile)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) wt[t] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+          if ((triQ && ks < 4 * cb) || (GD && ks >= ksr)) continue;
+          const double qb = fragQ[(cb * KS + ks) * 64 + lane];
+#pragma unroll
+          for (int t = 0; t < NT; ++t)
+            if (!GD || t < nta) wt[t] = mfma(qb, cur[ks][t], wt[t]);
+        }
+        store_t_band<NT>(wt, cb, p, q, Yi, ocol, g, j);
       }
-    }
     }
     if constexpr (PF) {
 #pragma unroll
@@ -856,10 +844,16 @@ struct Grid {
   long long spw;
 };
 
-Grid grid_of(long long I) {
-  // about 16 slices per wave at least, at most TTR_MAXWG workgroups
+// FP64 kernels run two workgroups per CU: 512 workgroups cover the 256 CUs
+// once, and the fixed-order reduction that follows a Gram pass then reads half
+// the partial Grams of TTR_MAXWG (measured faster for FP64; the FP32 Gram
+// kernels keep TTR_MAXWG).
+constexpr long long kWgF64 = 512;
+
+Grid grid_of(long long I, long long cap = kWgF64) {
+  // about 16 slices per wave at least, at most `cap` workgroups
   long long nwg = (I + 16 * kWaves - 1) / (16 * kWaves);
-  nwg = std::max(1LL, std::min(nwg, (long long)TTR_MAXWG));
+  nwg = std::max(1LL, std::min(nwg, std::min(cap, (long long)TTR_MAXWG)));
   long long spw = (I + nwg - 1) / nwg;
   Grid g;
   g.spw = std::max(1LL, spw);
@@ -896,7 +890,7 @@ void nt_ks(int nt, int ks, F &&f) {
 
 int launch_gram_right_factor(hipStream_t s, const double *X, int a, int b, long long I, const double *Q, int q,
                              long long sQr, long long sQc, int tri, int f32, double *partials) {
-  const Grid gr = grid_of(I);
+  const Grid gr = grid_of(I, f32 ? TTR_MAXWG : kWgF64);
   const int nt = std::max({tiles_for(a), tiles_for(b), tiles_for(q)});
   const int ks = std::max((b + 3) / 4, 4 * nt - 3);
   nt_ks(nt, ks, [&](auto NTc, auto KSc) {
@@ -911,7 +905,7 @@ int launch_gram_right_factor(hipStream_t s, const double *X, int a, int b, long 
 
 int launch_gram_left_factor(hipStream_t s, const double *X, int a, int b, long long I, const double *P, int p,
                             long long sPr, long long sPa, int tri, int f32, double *partials, double *Yout) {
-  const Grid gr = grid_of(I);
+  const Grid gr = grid_of(I, f32 ? TTR_MAXWG : kWgF64);
   const int nt = std::max({tiles_for(a), tiles_for(b), tiles_for(p)});
   const int ks = std::max((a + 3) / 4, 4 * nt - 3);
   nt_ks(nt, ks, [&](auto NTc, auto KSc) {

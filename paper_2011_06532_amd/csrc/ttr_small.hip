@@ -56,29 +56,30 @@ __device__ inline void rr_pair(int r, int k, int nn, int *p, int *q) {
 
 __device__ inline bool finite(double x) { return x == x && fabs(x) <= DBL_MAX; }
 
-// Fixed-order tree sum over the workgroup (blockDim.x a power of two <= 1024).
+// Fixed-order sum over the workgroup (blockDim.x a multiple of 64, <= 1024):
+// a butterfly within each wave (every lane ends with bitwise the same value,
+// the two operands of each addition being the same in both lanes), then the
+// wave results in wave order.  Every thread returns the result.
 __device__ double block_sum(double v) {
-  __shared__ double red[1024];
-  red[threadIdx.x] = v;
+  __shared__ double red[16];
+  for (int off = kWave / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+  const int wave = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  if (threadIdx.x % kWave == 0) red[wave] = v;
   __syncthreads();
-  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-    __syncthreads();
-  }
-  const double r = red[0];
+  double r = red[0];
+  for (int w = 1; w < nw; ++w) r += red[w];
   __syncthreads();
   return r;
 }
 
 __device__ double block_max(double v) {
-  __shared__ double red[1024];
-  red[threadIdx.x] = v;
+  __shared__ double red[16];
+  for (int off = kWave / 2; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, kWave));
+  const int wave = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  if (threadIdx.x % kWave == 0) red[wave] = v;
   __syncthreads();
-  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-    if (threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
-    __syncthreads();
-  }
-  const double r = red[0];
+  double r = red[0];
+  for (int w = 1; w < nw; ++w) r = fmax(r, red[w]);
   __syncthreads();
   return r;
 }
@@ -296,52 +297,68 @@ __device__ void sort_desc(const double *key, int n, int *perm) {
 
 
 
+// X = L^{-1} (k x k, ld d) for the lower-triangular L in A (ld d), both in
+// LDS: column-oriented forward substitution on all right-hand sides at once,
+// one barrier per column of L.  Step m eliminates with row m of X (scaled on
+// the fly); the row itself is scaled one step later, when no thread reads it.
+__device__ void lower_inv(const double *A, double *X, int k, int d) {
+  const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4, nc = blockDim.x >> 4;
+  for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
+    const int r = e % k, c = e / k;
+    X[r + d * c] = (r == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  double pprev = 0.0;
+  for (int m = 0; m < k; ++m) {
+    const double pm = 1.0 / A[m + d * m];
+    if (m > 0)
+      for (int c = threadIdx.x; c < m; c += blockDim.x) X[(m - 1) + d * c] *= pprev;
+    for (int c = tc; c <= m; c += nc) {
+      const double xm = X[m + d * c] * pm;
+      for (int r = m + 1 + tr; r < k; r += 16) X[r + d * c] -= A[r + d * m] * xm;
+    }
+    pprev = pm;
+    __syncthreads();
+  }
+  for (int c = threadIdx.x; c < k; c += blockDim.x) X[(k - 1) + d * c] *= pprev;
+  __syncthreads();
+}
+
 // Cholesky G = L L^T of the symmetric d x d matrix in A (LDS), in place (lower
 // triangle; the strict upper part is zeroed), then L^{-1} into Vm by forward
-// substitution, one column per thread.  Returns false when a pivot is not
-// positive.  With G symmetric, ||G||_2 <= ||G||_1 and
+// substitution; both take one barrier per column.  Returns false when a pivot
+// is not positive.  With G symmetric, ||G||_2 <= ||G||_1 and
 // ||G^{-1}||_2 <= ||G^{-1}||_1 <= ||L^{-1}||_inf ||L^{-1}||_1, so
 // *kappa = ||G||_1 ||L^{-1}||_1 ||L^{-1}||_inf bounds kappa_2(G) from above and
 // *lmin_lb = 1 / min(||L^{-1}||_F^2, ||L^{-1}||_1 ||L^{-1}||_inf) bounds
 // lambda_min(G) from below.
 __device__ bool chol_inv(double *A, double *Vm, int d, double *kappa, double *lmin_lb) {
-  __shared__ int ok;
   const double g1 = norm1(A, d);
-  if (threadIdx.x == 0) ok = 1;
-  __syncthreads();
+  // threads as 16 rows x (blockDim/16) columns of the trailing updates
+  const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4, nc = blockDim.x >> 4;
+  // Cholesky, one barrier per column: step j updates the trailing lower
+  // triangle with the unscaled column j (L(r,j) L(c,j) = A(r,j) A(c,j) / A(j,j))
+  // and scales column j-1, which no thread reads during step j
+  double lprev = 0.0;
   for (int j = 0; j < d; ++j) {
-    if (threadIdx.x == 0) {
-      const double pv = A[j + d * j];
-      if (!(pv > 0.0)) ok = 0;
-      else A[j + d * j] = sqrt(pv);
+    const double pv = A[j + d * j];
+    if (!(pv > 0.0)) return false;  // the same value in every thread
+    if (j > 0)
+      for (int r = j - 1 + threadIdx.x; r < d; r += blockDim.x)
+        A[r + d * (j - 1)] = (r == j - 1) ? lprev : A[r + d * (j - 1)] / lprev;
+    const double rp = 1.0 / pv;
+    for (int c = j + 1 + tc; c < d; c += nc) {
+      const double acj = A[c + d * j] * rp;
+      for (int r = c + tr; r < d; r += 16) A[r + d * c] -= A[r + d * j] * acj;
     }
-    __syncthreads();
-    if (!ok) return false;
-    const double ljj = A[j + d * j];
-    for (int r = j + 1 + threadIdx.x; r < d; r += blockDim.x) A[r + d * j] /= ljj;
-    __syncthreads();
-    // trailing update of the lower triangle: A(r, c) -= L(r, j) L(c, j), c <= r
-    const int n = d - j - 1;
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-      const int r = j + 1 + e % n, c = j + 1 + e / n;
-      if (c <= r) A[r + d * c] -= A[r + d * j] * A[c + d * j];
-    }
+    lprev = sqrt(pv);
     __syncthreads();
   }
-  for (int e = threadIdx.x; e < d * d; e += blockDim.x) {
-    const int r = e % d, c = e / d;
-    if (r < c) A[e] = 0.0;
-  }
+  if (threadIdx.x == 0) A[(d - 1) + d * (d - 1)] = lprev;
+  for (int e = threadIdx.x; e < d * d; e += blockDim.x)
+    if (e % d < e / d) A[e] = 0.0;
   __syncthreads();
-  // L^{-1}: column c solves L x = e_c
-  for (int c = threadIdx.x; c < d; c += blockDim.x) {
-    for (int r = 0; r < d; ++r) {
-      double v = (r == c) ? 1.0 : 0.0;
-      for (int k = c; k < r; ++k) v -= A[r + d * k] * Vm[k + d * c];
-      Vm[r + d * c] = (r < c) ? 0.0 : v / A[r + d * r];
-    }
-  }
-  __syncthreads();
+  lower_inv(A, Vm, d, d);
   const double lf2 = sumsq(Vm, d * d);
   const double l1 = norm1(Vm, d), li = norminf(Vm, d);
   *kappa = g1 * l1 * li;
@@ -364,16 +381,24 @@ __device__ int pivoted_chol(double *A, int d, double tau, int *perm) {
   __syncthreads();
   int k = d;
   for (int j = 0; j < d; ++j) {
-    if (threadIdx.x == 0) {
-      int p = j;
-      double v = A[j + d * j];
-      for (int i = j + 1; i < d; ++i)
-        if (A[i + d * i] > v) {
-          v = A[i + d * i];
-          p = i;
+    if (threadIdx.x < kWave) {
+      // wave 0: the largest remaining diagonal entry (d <= 64), the first
+      // one among ties
+      const int i = j + threadIdx.x;
+      double v = (i < d) ? A[i + d * i] : -DBL_MAX;
+      int p = (i < d) ? i : d;
+      for (int off = kWave / 2; off >= 1; off >>= 1) {
+        const double ov = __shfl_xor(v, off, kWave);
+        const int op = __shfl_xor(p, off, kWave);
+        if (ov > v || (ov == v && op < p)) {
+          v = ov;
+          p = op;
         }
-      piv = p;
-      stop = !(v > tau * dmax0);
+      }
+      if (threadIdx.x == 0) {
+        piv = p;
+        stop = !(v > tau * dmax0) || p >= d;
+      }
     }
     __syncthreads();
     if (stop) {
@@ -613,15 +638,8 @@ __device__ void qr_step_body(const QrStepArgs a) {
       __syncthreads();
       const int k = pivoted_chol(A, d, a.tau2, perm);
       if (k > 0) {
-      // X = L11^{-1} (k x k lower, ld d) by forward substitution, one column per thread
-      for (int c = threadIdx.x; c < k; c += blockDim.x) {
-        for (int r = 0; r < k; ++r) {
-          double v = (r == c) ? 1.0 : 0.0;
-          for (int m = c; m < r; ++m) v -= A[r + d * m] * Vm[m + d * c];
-          Vm[r + d * c] = (r < c) ? 0.0 : v / A[r + d * r];
-        }
-      }
-      __syncthreads();
+      // X = L11^{-1} (k x k lower, ld d)
+      lower_inv(A, Vm, k, d);
       // conditioning of the kept part: ||G11||_1 ||X||_1 ||X||_inf
       double g1 = 0.0, x1 = 0.0, xi = 0.0;
       for (int c = threadIdx.x; c < k; c += blockDim.x) {
