@@ -619,12 +619,14 @@ __device__ __forceinline__ void gram_fac_body(const int wg, const double *__rest
                                                        const double *__restrict__ Q, int q, long long sQr,
                                                        long long sQc, int tri, long long spw,
                                                        double *__restrict__ partials) {
-  constexpr bool PF = (NT <= 3);  // register prefetch of the next slice
+  // two waves per SIMD without a register prefetch (NT >= 3), as the Gram
+  // kernels of the first passes
+  constexpr bool PF = (NT <= 2);
   __shared__ double frag[NT * KS * 64];
   __shared__ double Gs[NT * 16 * NT * 16];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, j = lane & 15;
-  const int ksr = ((TR ? a : b) + 3) / 4, ntq = (q + 15) / 16, ntsa = ((TR ? b : a) + 15) / 16;  // GD
+  const int ksr = ((TR ? a : b) + 3) / 4, ntq = (q + 15) / 16;  // GD
   const int sa = TR ? b : a, sb = TR ? a : b;
   build_bfrag(frag, Q, sb, q, sQr, sQc, NT, KS);
   __syncthreads();
@@ -637,7 +639,7 @@ __device__ __forceinline__ void gram_fac_body(const int wg, const double *__rest
   const long long end = std::min(beg + spw, I);
   const long long col = (long long)a * I;
   // cur[ks][t] = S(16t + j, 4ks + g)
-  double cur[KS][NT], nxt[KS][NT];  // nxt is used only with PF
+  double cur[KS][NT], nxt[PF ? KS : 1][NT];
   long long i = beg + wave;
   if constexpr (PF)
     if (i < end) load_slice<NT, KS, !TR>(X + (long long)a * i, col, a, b, g, j, cur);
@@ -648,25 +650,23 @@ __device__ __forceinline__ void gram_fac_body(const int wg, const double *__rest
     } else {
       load_slice<NT, KS, !TR>(X + (long long)a * i, col, a, b, g, j, cur);
     }
-    d4 w[NT][NT];  // [s-tile][c-tile]
+    // one 16-row band of W = S Q at a time: its Gram contribution is complete
+    // on its own
 #pragma unroll
-    for (int u = 0; u < NT; ++u)
+    for (int t = 0; t < NT; ++t) {
+      if (t * 16 >= sa) break;
+      d4 w[NT];  // W(s, c), s in band t, one tile per c-tile
 #pragma unroll
-      for (int v = 0; v < NT; ++v) w[u][v] = d4{0.0, 0.0, 0.0, 0.0};
+      for (int cb = 0; cb < NT; ++cb) w[cb] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks)
+      for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
-      for (int cb = 0; cb < NT; ++cb) {
-        if ((tri && ks < 4 * cb) || (GD && (ks >= ksr || cb >= ntq))) continue;  // lower-triangular Q
-        const double qb = frag[(cb * KS + ks) * 64 + lane];
-#pragma unroll
-        for (int t = 0; t < NT; ++t)
-          if (!GD || t < ntsa) w[t][cb] = mfma(cur[ks][t], qb, w[t][cb]);
-      }
-    // G(c, c') += sum_s W(s, c) W(s, c'); register r of tile (t, .) holds rows
-    // s = 16t + 4r + g; rows past sa are padding
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
+        for (int cb = 0; cb < NT; ++cb) {
+          if ((tri && ks < 4 * cb) || (GD && (ks >= ksr || cb >= ntq))) continue;  // lower-triangular Q
+          w[cb] = mfma(cur[ks][t], frag[(cb * KS + ks) * 64 + lane], w[cb]);
+        }
+      // G(c, c') += sum_s W(s, c) W(s, c'); register r holds rows s = 16t + 4r + g;
+      // rows past sa are padding
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         if (t * 16 + 4 * r >= sa) continue;
@@ -674,8 +674,9 @@ __device__ __forceinline__ void gram_fac_body(const int wg, const double *__rest
         for (int u = 0; u < NT; ++u)
 #pragma unroll
           for (int v = 0; v <= u; ++v)
-            if (!GD || u < ntq) G[u][v] = mfma(w[t][u][r], w[t][v][r], G[u][v]);
+            if (!GD || u < ntq) G[u][v] = mfma(w[u][r], w[v][r], G[u][v]);
       }
+    }
     if constexpr (PF) {
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks)
@@ -687,7 +688,7 @@ __device__ __forceinline__ void gram_fac_body(const int wg, const double *__rest
 }
 
 template <int NT, int KS, bool TR>
-__global__ __launch_bounds__(kThreads) void k_gram_fac(const double *__restrict__ X, int a, int b, long long I,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NT <= 3 ? 2 : 1, NT <= 3 ? 2 : 1))) void k_gram_fac(const double *__restrict__ X, int a, int b, long long I,
                                                        const double *__restrict__ Q, int q, long long sQr,
                                                        long long sQc, int tri, long long spw,
                                                        double *__restrict__ partials) {
@@ -700,14 +701,14 @@ __device__ __forceinline__ void apply_fac2_body(const int wg, const double *__re
                                                          long long s1c, int tri, const double *__restrict__ Q2,
                                                          int q2, long long s2r, long long s2c, long long spw,
                                                          double *__restrict__ Y) {
-  constexpr bool PF = (NT <= 3);
+  // register prefetch of the next slice where it fits without spilling
+  constexpr bool PF = (NT <= 2 || (NT == 3 && (TR || KS <= 10))) && !GD;
   constexpr int KC = NT * 4;  // k-steps over the columns of Q1 (whole tiles)
   __shared__ double frag1[NT * KS * 64];
   __shared__ double frag2[NT * KC * 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, j = lane & 15;
   const int ksr = ((TR ? a : b) + 3) / 4, ntq1 = (q1 + 15) / 16, ntq2 = (q2 + 15) / 16;  // GD
-  const int ntsa = ((TR ? b : a) + 15) / 16;
   const int sa = TR ? b : a, sb = TR ? a : b;
   // A operands: Q1^T (q1 x sb) and Q2^T (q2 x q1)
   build_afrag(frag1, Q1, q1, sb, s1c, s1r, NT, KS);
@@ -720,7 +721,7 @@ __device__ __forceinline__ void apply_fac2_body(const int wg, const double *__re
   const long long ostep_s = TR ? (long long)q2 * I : 1;
   const long long ostep_c = TR ? 1 : (long long)sa * I;
   const long long oslice = TR ? q2 : sa;
-  double cur[KS][NT], nxt[KS][NT];  // nxt is used only with PF
+  double cur[KS][NT], nxt[PF ? KS : 1][NT];
   long long i = beg + wave;
   if constexpr (PF)
     if (i < end) load_slice<NT, KS, !TR>(X + (long long)a * i, col, a, b, g, j, cur);
@@ -731,52 +732,45 @@ __device__ __forceinline__ void apply_fac2_body(const int wg, const double *__re
     } else {
       load_slice<NT, KS, !TR>(X + (long long)a * i, col, a, b, g, j, cur);
     }
-    d4 wt[NT][NT];  // [c-tile][s-tile]: W^T = Q1^T S^T
-#pragma unroll
-    for (int u = 0; u < NT; ++u)
-#pragma unroll
-      for (int v = 0; v < NT; ++v) wt[u][v] = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-      for (int cb = 0; cb < NT; ++cb) {
-        if ((tri && ks < 4 * cb) || (GD && (ks >= ksr || cb >= ntq1))) continue;
-        const double qa = frag1[(cb * KS + ks) * 64 + lane];
-#pragma unroll
-        for (int t = 0; t < NT; ++t)
-          if (!GD || t < ntsa) wt[cb][t] = mfma(qa, cur[ks][t], wt[cb][t]);
-      }
-    d4 yt[NT][NT];  // [c2-tile][s-tile]: Y^T = Q2^T W^T
-#pragma unroll
-    for (int u = 0; u < NT; ++u)
-#pragma unroll
-      for (int v = 0; v < NT; ++v) yt[u][v] = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int cb = 0; cb < NT; ++cb)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        if (cb * 16 + 4 * r >= q1) continue;
-#pragma unroll
-        for (int u = 0; u < NT; ++u) {
-          if (GD && u >= ntq2) continue;
-          const double qa = frag2[(u * KC + cb * 4 + r) * 64 + lane];
-#pragma unroll
-          for (int t = 0; t < NT; ++t)
-            if (!GD || t < ntsa) yt[u][t] = mfma(qa, wt[cb][t][r], yt[u][t]);
-        }
-      }
     double *Yi = Y + oslice * i;
+    // one 16-row band of S at a time (rows s of the output): few accumulator
+    // tiles are live
 #pragma unroll
-    for (int u = 0; u < NT; ++u)
+    for (int t = 0; t < NT; ++t) {
+      if (t * 16 >= sa) break;
+      d4 wt[NT];  // W^T = Q1^T S^T tiles (c-tile, s-band t)
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const int sidx = t * 16 + j;
+      for (int u = 0; u < NT; ++u) wt[u] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int cb = 0; cb < NT; ++cb) {
+          if ((tri && ks < 4 * cb) || (GD && (ks >= ksr || cb >= ntq1))) continue;
+          wt[cb] = mfma(frag1[(cb * KS + ks) * 64 + lane], cur[ks][t], wt[cb]);
+        }
+      d4 yt[NT];  // Y^T = Q2^T W^T tiles (c2-tile, s-band t)
+#pragma unroll
+      for (int u = 0; u < NT; ++u) yt[u] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int cb = 0; cb < NT; ++cb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (cb * 16 + 4 * r >= q1) continue;
+#pragma unroll
+          for (int u = 0; u < NT; ++u) {
+            if (GD && u >= ntq2) continue;
+            yt[u] = mfma(frag2[(u * KC + cb * 4 + r) * 64 + lane], wt[cb][r], yt[u]);
+          }
+        }
+      const int sidx = t * 16 + j;
+#pragma unroll
+      for (int u = 0; u < NT; ++u)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int c2 = u * 16 + 4 * r + g;
-          if (sidx < sa && c2 < q2) Yi[ostep_s * sidx + ostep_c * c2] = yt[u][t][r];
+          if (sidx < sa && c2 < q2) Yi[ostep_s * sidx + ostep_c * c2] = yt[u][r];
         }
-      }
+    }
     if constexpr (PF) {
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks)
@@ -787,7 +781,7 @@ __device__ __forceinline__ void apply_fac2_body(const int wg, const double *__re
 }
 
 template <int NT, int KS, bool TR>
-__global__ __launch_bounds__(kThreads) void k_apply_fac2(const double *__restrict__ X, int a, int b, long long I,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NT <= 3 ? 2 : 1, NT <= 3 ? 2 : 1))) void k_apply_fac2(const double *__restrict__ X, int a, int b, long long I,
                                                          const double *__restrict__ Q1, int q1, long long s1r,
                                                          long long s1c, int tri, const double *__restrict__ Q2,
                                                          int q2, long long s2r, long long s2c, long long spw,
