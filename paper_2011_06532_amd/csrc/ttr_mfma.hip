@@ -595,7 +595,7 @@ __device__ __forceinline__ void apply_mfma_body(const int wg, const double *__re
 }
 
 template <int NT, int KS>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NT <= 3 ? 2 : 1, NT <= 3 ? 2 : 1))) void k_apply_mfma(const double *__restrict__ X, int a, int b, long long I, const double *__restrict__ P, int p,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NT <= 3 || KS <= 13 ? 2 : 1, NT <= 3 || KS <= 13 ? 2 : 1))) void k_apply_mfma(const double *__restrict__ X, int a, int b, long long I, const double *__restrict__ P, int p,
                   long long sPr, long long sPa, const double *__restrict__ Q, int q, long long sQr, long long sQc,
                   int tri, long long spw, double *__restrict__ Y) {
   apply_mfma_body<NT, KS>(blockIdx.x, X, a, b, I, P, p, sPr, sPa, Q, q, sQr, sQc, tri, spw, Y);
@@ -781,7 +781,7 @@ __device__ __forceinline__ void apply_fac2_body(const int wg, const double *__re
 }
 
 template <int NT, int KS, bool TR>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NT <= 3 ? 2 : 1, NT <= 3 ? 2 : 1))) void k_apply_fac2(const double *__restrict__ X, int a, int b, long long I,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NT <= 3 || (TR && KS <= 14) ? 2 : 1, NT <= 3 || (TR && KS <= 14) ? 2 : 1))) void k_apply_fac2(const double *__restrict__ X, int a, int b, long long I,
                                                          const double *__restrict__ Q1, int q1, long long s1r,
                                                          long long s1c, int tri, const double *__restrict__ Q2,
                                                          int q2, long long s2r, long long s2c, long long spw,
