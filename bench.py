@@ -35,13 +35,17 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+# the sources that define the streaming kernels whose counters
+# profiles/pmc_traffic.json records, and the host code that launches them
+TRAFFIC_SOURCES = ("ttr_api.hip", "ttr_host.h", "ttr_internal.h", "ttr_mfma.hip", "ttr_stream.hip")
+
+
 def source_hash():
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2011_06532_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".h")):
-            with open(os.path.join(d, f), "rb") as fh:
-                h.update(fh.read())
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
