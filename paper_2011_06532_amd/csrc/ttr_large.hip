@@ -101,61 +101,166 @@ __device__ void largmax(double *v, int *p) {
   *p = bp;
 }
 
-// Right-looking Cholesky of the d x d symmetric A (device memory, ld d) in
-// place, lower triangle (strict upper zeroed).  False if a pivot is not
-// positive.  One barrier per column: step j updates the trailing lower
-// triangle with the unscaled column j (L(r,j) L(c,j) = A(r,j) A(c,j) / A(j,j))
-// and scales column j-1, which no thread reads during step j.  Threads run as
-// 32 rows x (blockDim/32) columns, so the row updates of a column coalesce.
-__device__ bool lchol(double *A, int d) {
-  const int tr = threadIdx.x & 31, tc = threadIdx.x >> 5, nc = blockDim.x >> 5;
-  double lprev = 0.0;
-  for (int j = 0; j < d; ++j) {
-    const double pv = A[j + (size_t)d * j];
-    if (!(pv > 0.0)) return false;  // the same value in every thread
-    if (j > 0)
-      for (int r = j - 1 + threadIdx.x; r < d; r += blockDim.x)
-        A[r + (size_t)d * (j - 1)] = (r == j - 1) ? lprev : A[r + (size_t)d * (j - 1)] / lprev;
-    const double rp = 1.0 / pv;
-    for (int c = j + 1 + tc; c < d; c += nc) {
-      const double acj = A[c + (size_t)d * j] * rp;
-      for (int r = c + tr; r < d; r += 32) A[r + (size_t)d * c] -= A[r + (size_t)d * j] * acj;
+constexpr int kNB = 16;                        // panel width of the blocked factorizations (registers: 1024-thread blocks leave 128 per lane)
+constexpr int kLdsB = kLMax * (kNB + 1);       // doubles of LDS they use (panel or block row)
+
+// v from lane `lane` (uniform) of the wave, as a wave-uniform value.
+__device__ inline double bcast(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// Blocked right-looking Cholesky of the d x d symmetric A (device memory, ld
+// d; lower triangle read) in place, strict upper part zeroed.  False if a
+// pivot is not positive.  Per 16-column panel: wave 0 factors the diagonal
+// block in registers (lane r holds row r; the pivot column is broadcast lane
+// by lane), the rows below solve against it in parallel (one row per
+// thread), and the trailing lower triangle takes the panel's rank-16 update
+// with the panel held in LDS (S, kLdsB doubles).  Three barriers per panel.
+__device__ bool lchol(double *A, int d, double *S) {
+  __shared__ double Dk[kNB * kNB];
+  __shared__ int okf;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (threadIdx.x == 0) okf = 1;
+  for (int k0 = 0; k0 < d; k0 += kNB) {
+    const int nb = min(kNB, d - k0), k1 = k0 + nb;
+    if (wave == 0) {
+      const int r = lane;
+      double a[kNB];
+#pragma unroll
+      for (int c = 0; c < kNB; ++c)
+        a[c] = (r < nb && c <= r) ? A[(k0 + r) + (size_t)d * (k0 + c)] : 0.0;
+      bool ok = true;
+#pragma unroll
+      for (int j = 0; j < kNB; ++j) {
+        if (j < nb) {
+          const double pv = bcast(a[j], j);
+          if (!(pv > 0.0)) ok = false;
+          const double sq = sqrt(pv);
+          const double l = (r == j) ? sq : ((r > j) ? a[j] / sq : 0.0);
+          a[j] = l;
+#pragma unroll
+          for (int c = j + 1; c < kNB; ++c) {
+            const double lc = bcast(l, c);
+            if (r >= c) a[c] -= l * lc;
+          }
+        }
+      }
+      if (r < kNB)
+#pragma unroll
+        for (int c = 0; c < kNB; ++c) Dk[r + kNB * c] = (c <= r && r < nb) ? a[c] : 0.0;
+      if (r < nb)
+#pragma unroll
+        for (int c = 0; c < kNB; ++c)
+          if (c <= r) A[(k0 + r) + (size_t)d * (k0 + c)] = a[c];
+      if (r == 0 && !ok) okf = 0;
     }
-    lprev = sqrt(pv);
+    __syncthreads();
+    if (!okf) return false;
+    // panel below: L(i, k0:k1) = A(i, k0:k1) L_kk^{-T}, one row per thread
+    // (d - k1 < blockDim: a single pass, so the reads of L_kk stay in the
+    // loop body instead of being hoisted into registers)
+    if (const int i = k1 + threadIdx.x; i < d) {
+      double x[kNB];
+#pragma unroll
+      for (int c = 0; c < kNB; ++c) {
+        double v = (c < nb) ? A[i + (size_t)d * (k0 + c)] : 0.0;
+#pragma unroll
+        for (int m = 0; m < c; ++m) v -= x[m] * Dk[c + kNB * m];
+        x[c] = (c < nb) ? v / Dk[c + kNB * c] : 0.0;
+      }
+#pragma unroll
+      for (int c = 0; c < kNB; ++c) {
+        if (c < nb) A[i + (size_t)d * (k0 + c)] = x[c];
+        S[(i - k1) * (kNB + 1) + c] = x[c];
+      }
+    }
+    __syncthreads();
+    // trailing update of the lower triangle: A(r, c) -= L(r, panel) L(c, panel)^T
+    {
+      const int tr = threadIdx.x & 31, tc = threadIdx.x >> 5, nc = blockDim.x >> 5;
+      for (int c = k1 + tc; c < d; c += nc) {
+        double pc[kNB];
+#pragma unroll
+        for (int t = 0; t < kNB; ++t) pc[t] = S[(c - k1) * (kNB + 1) + t];
+        for (int r = c + tr; r < d; r += 32) {
+          const double *pr = S + (r - k1) * (kNB + 1);
+          double acc = 0.0;
+#pragma unroll
+          for (int t = 0; t < kNB; ++t) acc += pr[t] * pc[t];
+          A[r + (size_t)d * c] -= acc;
+        }
+      }
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) A[(d - 1) + (size_t)d * (d - 1)] = lprev;
   for (int e = threadIdx.x; e < d * d; e += blockDim.x)
     if (e % d < e / d) A[e] = 0.0;
   __syncthreads();
   return true;
 }
 
-// X = L^{-1} (k x k lower, ld d) for the lower-triangular L in A (ld d):
-// column-oriented forward substitution on all right-hand sides at once, one
-// barrier per column of L.  Step m eliminates with row m of X (scaled on the
-// fly); the row itself is scaled one step later, when no thread reads it.
-__device__ void linv(const double *A, double *X, int k, int d) {
-  const int tr = threadIdx.x & 31, tc = threadIdx.x >> 5, nc = blockDim.x >> 5;
+// X = L^{-1} (k x k lower, ld d) for the lower-triangular L in A (ld d).
+// The diagonal 16-blocks are inverted by one wave each in registers (forward
+// substitution on all columns at once, rows broadcast lane by lane); then
+// block row i: X(i, 0:i) = -X_ii (L(i, 0:i) X(0:i, 0:i)), the inner product
+// staged in LDS (S, kLdsB doubles).  Two barriers per block row.
+__device__ void linv(const double *A, double *X, int k, int d, double *S) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nblk = (k + kNB - 1) / kNB;
   for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
     const int r = e % k, c = e / k;
-    X[r + (size_t)d * c] = (r == c) ? 1.0 : 0.0;
+    if (r < c) X[r + (size_t)d * c] = 0.0;
+  }
+  // nblk <= 16 = the waves of the workgroup: one block per wave
+  if (const int bw = wave; bw < nblk) {
+    const int b0 = bw * kNB, nb = min(kNB, k - b0);
+    const int r = lane;
+    double l[kNB], x[kNB];
+#pragma unroll
+    for (int c = 0; c < kNB; ++c) {
+      l[c] = (r < nb && c <= r) ? A[(b0 + r) + (size_t)d * (b0 + c)] : 0.0;
+      x[c] = (r == c) ? 1.0 : 0.0;
+    }
+#pragma unroll
+    for (int m = 0; m < kNB; ++m) {
+      if (m < nb) {
+        const double pm = 1.0 / bcast(l[m], m);
+#pragma unroll
+        for (int c = 0; c <= m; ++c) {
+          const double xm = bcast(x[c], m) * pm;  // row m of X, final
+          if (r > m) x[c] -= l[m] * xm;
+          else if (r == m) x[c] = xm;
+        }
+      }
+    }
+    if (r < nb)
+#pragma unroll
+      for (int c = 0; c < kNB; ++c)
+        if (c <= r) X[(b0 + r) + (size_t)d * (b0 + c)] = x[c];
   }
   __syncthreads();
-  double pprev = 0.0;
-  for (int m = 0; m < k; ++m) {
-    const double pm = 1.0 / A[m + (size_t)d * m];
-    if (m > 0)
-      for (int c = threadIdx.x; c < m; c += blockDim.x) X[(m - 1) + (size_t)d * c] *= pprev;
-    for (int c = tc; c <= m; c += nc) {
-      const double xm = X[m + (size_t)d * c] * pm;
-      for (int r = m + 1 + tr; r < k; r += 32) X[r + (size_t)d * c] -= A[r + (size_t)d * m] * xm;
-    }
-    pprev = pm;
+  const int tr = threadIdx.x & 31, tcg = threadIdx.x >> 5, ng = blockDim.x >> 5;
+  for (int bi = 1; bi < nblk; ++bi) {
+    const int i0 = bi * kNB, ni = min(kNB, k - i0);
+    // T(r, c) = sum_{m = c}^{i0 - 1} L(i0 + r, m) X(m, c), c < i0
+    for (int c = tcg; c < i0; c += ng)
+      if (tr < ni) {
+        double acc = 0.0;
+        for (int m = c; m < i0; ++m) acc += A[(i0 + tr) + (size_t)d * m] * X[m + (size_t)d * c];
+        S[tr * (kLMax + 1) + c] = acc;
+      }
+    __syncthreads();
+    // X(i0 + r, c) = -sum_t X(i0 + r, i0 + t) T(t, c)
+    for (int c = tcg; c < i0; c += ng)
+      if (tr < ni) {
+        double acc = 0.0;
+        for (int t = 0; t <= tr; ++t) acc += X[(i0 + tr) + (size_t)d * (i0 + t)] * S[t * (kLMax + 1) + c];
+        X[(i0 + tr) + (size_t)d * c] = -acc;
+      }
     __syncthreads();
   }
-  for (int c = threadIdx.x; c < k; c += blockDim.x) X[(k - 1) + (size_t)d * c] *= pprev;
-  __syncthreads();
 }
 
 // ||M||_1, ||M||_inf and ||M||_F^2 of the k x k matrix M (ld d).
@@ -301,10 +406,11 @@ __global__ __launch_bounds__(kLT) void lk_step(LStepArgs a) {
     g1 = fmax(g1, s);
   }
   g1 = lmax(g1);
-  const bool ok = lchol(A, d);
+  __shared__ double Sbuf[kLdsB];
+  const bool ok = lchol(A, d, Sbuf);
   double kappa = 1e300, lmin_lb = 0.0;
   if (ok) {
-    linv(A, X, d, d);
+    linv(A, X, d, d, Sbuf);
     double x1, xi, xf;
     lnorms(X, d, d, &x1, &xi, &xf);
     kappa = g1 * x1 * xi;
@@ -360,8 +466,8 @@ __global__ __launch_bounds__(kLT) void lk_step(LStepArgs a) {
     const double shift = 2.0 * d * a.ugram * trG;
     for (int j = threadIdx.x; j < d; j += blockDim.x) A[j + (size_t)d * j] += shift;
     __syncthreads();
-    if (shift > 0.0 && lchol(A, d)) {
-      linv(A, X, d, d);
+    if (shift > 0.0 && lchol(A, d, Sbuf)) {
+      linv(A, X, d, d, Sbuf);
       for (int e = threadIdx.x; e < d * d; e += blockDim.x) {
         const int r = e % d, c = e / d;
         a.Fstep[r + (size_t)d * c] = X[c + (size_t)d * r];
@@ -397,7 +503,7 @@ __global__ __launch_bounds__(kLT) void lk_step(LStepArgs a) {
     }
     return;
   }
-  linv(A, X, k, d);
+  linv(A, X, k, d, Sbuf);
   double x1, xi, xf, gk = 0.0;
   lnorms(X, k, d, &x1, &xi, &xf);
   for (int c = threadIdx.x; c < k; c += blockDim.x) {
@@ -456,6 +562,7 @@ struct LTruncArgs {
 // up the one-sided Jacobi SVD of R: W0 = A = R^T (b x k), W1 = U = I (k x k),
 // and the rotation thresholds.
 __global__ __launch_bounds__(kLT) void lk_trunc_setup(LTruncArgs a) {
+  __shared__ double Sbuf[kLdsB];
   const int k = a.k, b = a.b;
   __shared__ int ident, tri_ok;
   if (threadIdx.x == 0) {
@@ -479,7 +586,7 @@ __global__ __launch_bounds__(kLT) void lk_trunc_setup(LTruncArgs a) {
       for (int j = 0; j < k; ++j) okd = okd && (a.R[j + (size_t)k * j] != 0.0);
       double xf = 0.0, rf = 0.0;
       if (okd) {
-        linv(a.W0, a.W1, k, k);
+        linv(a.W0, a.W1, k, k, Sbuf);
         for (int e = threadIdx.x; e < k * k; e += blockDim.x) xf += a.W1[e] * a.W1[e];
       }
       for (int e = threadIdx.x; e < k * k; e += blockDim.x) rf += a.R[e] * a.R[e];
