@@ -263,18 +263,26 @@ __device__ void linv(const double *A, double *X, int k, int d, double *S) {
   }
 }
 
-// ||M||_1, ||M||_inf and ||M||_F^2 of the k x k matrix M (ld d).
+// ||M||_1, ||M||_inf and ||M||_F^2 of the k x k matrix M (ld d).  Row sums
+// run one row per thread (lanes read consecutive rows of a column), column
+// sums one column per wave (lanes read down the column).
 __device__ void lnorms(const double *M, int k, int d, double *n1, double *ni, double *f2) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   double a1 = 0.0, ai = 0.0, af = 0.0;
-  for (int c = threadIdx.x; c < k; c += blockDim.x) {
-    double s = 0.0, t = 0.0;
-    for (int r = 0; r < k; ++r) {
-      s += fabs(M[r + (size_t)d * c]);
-      t += fabs(M[c + (size_t)d * r]);
-      af += M[r + (size_t)d * c] * M[r + (size_t)d * c];
+  for (int r = threadIdx.x; r < k; r += blockDim.x) {
+    double t = 0.0;
+    for (int c = 0; c < k; ++c) {
+      const double v = M[r + (size_t)d * c];
+      t += fabs(v);
+      af += v * v;
     }
-    a1 = fmax(a1, s);
     ai = fmax(ai, t);
+  }
+  for (int c = wave; c < k; c += nw) {
+    double s = 0.0;
+    for (int r = lane; r < k; r += 64) s += fabs(M[r + (size_t)d * c]);
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    a1 = fmax(a1, s);
   }
   *n1 = lmax(a1);
   *ni = lmax(ai);
@@ -357,7 +365,8 @@ struct LStepArgs {
   double *Fstep;       // d x k (ld d)
   double *Rnext;       // k x b (ld k)
   double *Tdst;        // b x k (ld b) once settled, or nullptr
-  int *dec;            // [0] k, [1] settled, [2] error flags, [5] no truncation proven
+  int *dec;            // [0] k, [1] settled, [2] error flags, [5] no truncation proven,
+                       // [8] R left to the host: 1 = L^T Rc, 2 = L(:, 0:k)^T Rp
   double tau1, tau2, ugram, gerr;
   int notrunc_check;
   const double *delta_dev;
@@ -365,6 +374,7 @@ struct LStepArgs {
   double tol2_nm1;
   double *W0, *W1;     // d x d scratch
   int *perm;           // d scratch
+  double *Rp;          // d x b scratch: permuted rows of Rc (pivoted route)
 };
 
 // One QR-by-Gram step (the d <= 64 step's Cholesky-based routes).
@@ -386,25 +396,23 @@ __global__ __launch_bounds__(kLT) void lk_step(LStepArgs a) {
       a.dec[2] |= 1;
       a.dec[0] = 1;
       a.dec[1] = 1;
+      a.dec[8] = 0;
     }
     return;
   }
-  double tp = 0.0, glo = DBL_MAX, ghi = 0.0;
+  // Gershgorin bounds and ||G||_1 (= ||G||_inf, G symmetric) from the row sums
+  double tp = 0.0, glo = DBL_MAX, ghi = 0.0, g1 = 0.0;
   for (int r = threadIdx.x; r < d; r += blockDim.x) {
     double off = 0.0;
     for (int c = 0; c < d; ++c)
       if (c != r) off += fabs(A[r + (size_t)d * c]);
-    tp += A[r + (size_t)d * r];
-    glo = fmin(glo, A[r + (size_t)d * r] - off);
-    ghi = fmax(ghi, A[r + (size_t)d * r] + off);
+    const double drr = A[r + (size_t)d * r];
+    tp += drr;
+    glo = fmin(glo, drr - off);
+    ghi = fmax(ghi, drr + off);
+    g1 = fmax(g1, fabs(drr) + off);
   }
   const double trG = lsum(tp), gmin = -lmax(-glo), gmax = lmax(ghi);
-  double g1 = 0.0;
-  for (int c = threadIdx.x; c < d; c += blockDim.x) {
-    double s = 0.0;
-    for (int r = 0; r < d; ++r) s += fabs(A[r + (size_t)d * c]);
-    g1 = fmax(g1, s);
-  }
   g1 = lmax(g1);
   __shared__ double Sbuf[kLdsB];
   const bool ok = lchol(A, d, Sbuf);
@@ -437,21 +445,19 @@ __global__ __launch_bounds__(kLT) void lk_step(LStepArgs a) {
       const int r = e % d, c = e / d;
       a.Fstep[r + (size_t)d * c] = X[c + (size_t)d * r];  // F = L^{-T}
     }
-    // R = L^T Rc (L^T at the first pass), T = R^T
-    for (int e = threadIdx.x; e < d * b; e += blockDim.x) {
-      const int r = e % d, col = e / d;
-      double v = 0.0;
-      if (a.Rc) {
-        for (int j = r; j < d; ++j) v += A[j + (size_t)d * r] * a.Rc[j + (size_t)d * col];
-      } else {
-        v = A[col + (size_t)d * r];
+    // R = L^T (first pass), T = R^T = L; at a refinement pass R = L^T Rc is
+    // left to the host (dec[8] = 1: one dgemm with L in W0)
+    if (!a.Rc)
+      for (int e = threadIdx.x; e < d * b; e += blockDim.x) {
+        const int r = e % d, col = e / d;
+        const double v = A[col + (size_t)d * r];
+        a.Rnext[r + (size_t)d * col] = v;
+        if (a.Tdst) a.Tdst[col + (size_t)b * r] = v;
       }
-      a.Rnext[r + (size_t)d * col] = v;
-      if (a.Tdst) a.Tdst[col + (size_t)b * r] = v;
-    }
     if (threadIdx.x == 0) {
       a.dec[0] = d;
       a.dec[1] = 1;
+      a.dec[8] = a.Rc ? 1 : 0;
     }
     return;
   }
@@ -477,6 +483,7 @@ __global__ __launch_bounds__(kLT) void lk_step(LStepArgs a) {
         a.dec[0] = d;
         a.dec[1] = 0;
         a.dec[5] = 0;
+        a.dec[8] = 0;
       }
       return;
     }
@@ -500,6 +507,7 @@ __global__ __launch_bounds__(kLT) void lk_step(LStepArgs a) {
       a.dec[0] = 1;
       a.dec[1] = 1;
       a.dec[5] = 0;
+      a.dec[8] = 0;
     }
     return;
   }
@@ -522,20 +530,21 @@ __global__ __launch_bounds__(kLT) void lk_step(LStepArgs a) {
     const int i = e % k, c = e / k;
     a.Fstep[a.perm[i] + (size_t)d * c] = (c >= i) ? X[c + (size_t)d * i] : 0.0;
   }
-  for (int e = threadIdx.x; e < k * b; e += blockDim.x) {
-    const int c = e % k, col = e / k;
-    double v = 0.0;
-    for (int j = c; j < d; ++j) {
-      const double rj = a.Rc ? a.Rc[a.perm[j] + (size_t)d * col] : (a.perm[j] == col ? 1.0 : 0.0);
-      v += A[j + (size_t)d * c] * rj;
-    }
-    a.Rnext[c + (size_t)k * col] = v;
-    if (dn && a.Tdst) a.Tdst[col + (size_t)b * c] = v;
+  // R' = L(:, 0:k)^T Rc(perm, :) (Rc = I at the first pass) is left to the
+  // host (dec[8] = 2: one dgemm with L in W0 and the permuted rows in Rp);
+  // the strict upper part of L's k columns still holds Schur-complement
+  // entries and is cleared first
+  for (int e = threadIdx.x; e < d * k; e += blockDim.x)
+    if (e % d < e / d) A[e] = 0.0;
+  for (int e = threadIdx.x; e < d * b; e += blockDim.x) {
+    const int j = e % d, col = e / d;
+    a.Rp[e] = a.Rc ? a.Rc[a.perm[j] + (size_t)d * col] : (a.perm[j] == col ? 1.0 : 0.0);
   }
   if (threadIdx.x == 0) {
     a.dec[0] = k;
     a.dec[1] = dn;
     a.dec[5] = 0;
+    a.dec[8] = 2;
   }
 }
 
@@ -785,6 +794,16 @@ __global__ __launch_bounds__(kLT) void lk_trunc_finish(LTruncArgs a) {
   }
 }
 
+// D (cols x rows, ld ldd) = S^T for S (rows x cols, ld lds).
+__global__ void lk_transpose(const double *__restrict__ S, int rows, int cols, int lds, double *__restrict__ D,
+                             int ldd) {
+  const long long n = (long long)rows * cols;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+    const int c = (int)(e / rows), r = (int)(e % rows);
+    D[c + (long long)ldd * r] = S[r + (long long)lds * c];
+  }
+}
+
 // --- host -------------------------------------------------------------------
 constexpr size_t kSlotL = (size_t)kLMax * kLMax;
 constexpr int kChunks = 256;  // chunk Grams per streamed Gram
@@ -915,9 +934,20 @@ struct Large {
     a.W0 = w.W0;
     a.W1 = w.W1;
     a.perm = w.perm;
+    a.Rp = w.Ap;
     hipLaunchKernelGGL(lk_step, dim3(1), dim3(kLT), 0, h->stream, a);
     h->stats.small_launches++;
-    return sync_dec();
+    int rc;
+    if ((rc = sync_dec())) return rc;
+    const int how = h->dec_host[8], kk = h->dec_host[0];
+    if (how == 0) return TTR_OK;
+    // R = L^T Rc (d x b) or R' = L(:, 0:k)^T Rp (k x b), L lower in W0 (ld d)
+    if ((rc = gemm(true, false, kk, b, d, w.W0, d, how == 1 ? Rc : w.Ap, d, Rn, kk))) return rc;
+    if (Tdst && h->dec_host[1]) {
+      hipLaunchKernelGGL(lk_transpose, dim3(64), dim3(256), 0, h->stream, Rn, kk, b, kk, Tdst, b);
+      TTR_HIPCHK(hipGetLastError());
+    }
+    return TTR_OK;
   }
 };
 
