@@ -137,6 +137,20 @@ __device__ inline void load_slice(const double *__restrict__ Xi, long long col, 
     }
 }
 
+// Loads one 16-row band t of the operand fragments of a slice:
+// buf[ks] = M(t*16 + l%16, ks*4 + l/16) (ROWS16) or M(ks*4 + l/16, t*16 + l%16),
+// zero outside the a x b slice.
+template <int KS, bool ROWS16>
+__device__ inline void load_band(const double *__restrict__ Xi, long long col, int a, int b, int g, int j, int t,
+                                 double (&buf)[KS]) {
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const int r = ROWS16 ? t * 16 + j : ks * 4 + g;
+    const int c = ROWS16 ? ks * 4 + g : t * 16 + j;
+    buf[ks] = (r < a && c < b) ? Xi[r + col * c] : 0.0;
+  }
+}
+
 // Products that contract over alpha (the fast index of a slice) take their
 // k-steps in "pair order": k-step ks covers alpha = 8 (ks/2) + 2 g + ks%2, so a
 // lane holds two consecutive alpha of one column and reads them with one
@@ -620,8 +634,10 @@ __device__ __forceinline__ void gram_fac_body(const int wg, const double *__rest
                                                        long long sQc, int tri, long long spw,
                                                        double *__restrict__ partials) {
   // two waves per SIMD without a register prefetch (NT >= 3), as the Gram
-  // kernels of the first passes
+  // kernels of the first passes; at NT = 4 only one 16-row band of the slice
+  // is held at a time (BL), which is what fits two waves
   constexpr bool PF = (NT <= 2);
+  constexpr bool BL = (NT >= 4);
   __shared__ double frag[NT * KS * 64];
   __shared__ double Gs[NT * 16 * NT * 16];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -639,7 +655,7 @@ __device__ __forceinline__ void gram_fac_body(const int wg, const double *__rest
   const long long end = std::min(beg + spw, I);
   const long long col = (long long)a * I;
   // cur[ks][t] = S(16t + j, 4ks + g)
-  double cur[KS][NT], nxt[PF ? KS : 1][NT];
+  double cur[BL ? 1 : KS][BL ? 1 : NT], nxt[PF ? KS : 1][NT];
   long long i = beg + wave;
   if constexpr (PF)
     if (i < end) load_slice<NT, KS, !TR>(X + (long long)a * i, col, a, b, g, j, cur);
@@ -647,7 +663,7 @@ __device__ __forceinline__ void gram_fac_body(const int wg, const double *__rest
     if constexpr (PF) {
       if (i + kWaves < end)
         load_slice<NT, KS, !TR>(X + (long long)a * (i + kWaves), col, a, b, g, j, nxt);
-    } else {
+    } else if constexpr (!BL) {
       load_slice<NT, KS, !TR>(X + (long long)a * i, col, a, b, g, j, cur);
     }
     // one 16-row band of W = S Q at a time: its Gram contribution is complete
@@ -655,6 +671,13 @@ __device__ __forceinline__ void gram_fac_body(const int wg, const double *__rest
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       if (t * 16 >= sa) break;
+      double sv[KS];  // band t of the slice
+      if constexpr (BL) {
+        load_band<KS, !TR>(X + (long long)a * i, col, a, b, g, j, t, sv);
+      } else {
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) sv[ks] = cur[ks][t];
+      }
       d4 w[NT];  // W(s, c), s in band t, one tile per c-tile
 #pragma unroll
       for (int cb = 0; cb < NT; ++cb) w[cb] = d4{0.0, 0.0, 0.0, 0.0};
@@ -663,7 +686,7 @@ __device__ __forceinline__ void gram_fac_body(const int wg, const double *__rest
 #pragma unroll
         for (int cb = 0; cb < NT; ++cb) {
           if ((tri && ks < 4 * cb) || (GD && (ks >= ksr || cb >= ntq))) continue;  // lower-triangular Q
-          w[cb] = mfma(cur[ks][t], frag[(cb * KS + ks) * 64 + lane], w[cb]);
+          w[cb] = mfma(sv[ks], frag[(cb * KS + ks) * 64 + lane], w[cb]);
         }
       // G(c, c') += sum_s W(s, c) W(s, c'); register r holds rows s = 16t + 4r + g;
       // rows past sa are padding
@@ -688,7 +711,7 @@ __device__ __forceinline__ void gram_fac_body(const int wg, const double *__rest
 }
 
 template <int NT, int KS, bool TR>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NT <= 3 ? 2 : 1, NT <= 3 ? 2 : 1))) void k_gram_fac(const double *__restrict__ X, int a, int b, long long I,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NT <= 3 || TR || KS <= 14 ? 2 : 1, NT <= 3 || TR || KS <= 14 ? 2 : 1))) void k_gram_fac(const double *__restrict__ X, int a, int b, long long I,
                                                        const double *__restrict__ Q, int q, long long sQr,
                                                        long long sQc, int tri, long long spw,
                                                        double *__restrict__ partials) {
@@ -701,8 +724,10 @@ __device__ __forceinline__ void apply_fac2_body(const int wg, const double *__re
                                                          long long s1c, int tri, const double *__restrict__ Q2,
                                                          int q2, long long s2r, long long s2c, long long spw,
                                                          double *__restrict__ Y) {
-  // register prefetch of the next slice where it fits without spilling
+  // register prefetch of the next slice where it fits without spilling; at
+  // NT = 4 one 16-row band of the slice is held at a time (BL)
   constexpr bool PF = (NT <= 2 || (NT == 3 && (TR || KS <= 10))) && !GD;
+  constexpr bool BL = (NT >= 4);
   constexpr int KC = NT * 4;  // k-steps over the columns of Q1 (whole tiles)
   __shared__ double frag1[NT * KS * 64];
   __shared__ double frag2[NT * KC * 64];
@@ -721,7 +746,7 @@ __device__ __forceinline__ void apply_fac2_body(const int wg, const double *__re
   const long long ostep_s = TR ? (long long)q2 * I : 1;
   const long long ostep_c = TR ? 1 : (long long)sa * I;
   const long long oslice = TR ? q2 : sa;
-  double cur[KS][NT], nxt[PF ? KS : 1][NT];
+  double cur[BL ? 1 : KS][BL ? 1 : NT], nxt[PF ? KS : 1][NT];
   long long i = beg + wave;
   if constexpr (PF)
     if (i < end) load_slice<NT, KS, !TR>(X + (long long)a * i, col, a, b, g, j, cur);
@@ -729,7 +754,7 @@ __device__ __forceinline__ void apply_fac2_body(const int wg, const double *__re
     if constexpr (PF) {
       if (i + kWaves < end)
         load_slice<NT, KS, !TR>(X + (long long)a * (i + kWaves), col, a, b, g, j, nxt);
-    } else {
+    } else if constexpr (!BL) {
       load_slice<NT, KS, !TR>(X + (long long)a * i, col, a, b, g, j, cur);
     }
     double *Yi = Y + oslice * i;
@@ -738,6 +763,13 @@ __device__ __forceinline__ void apply_fac2_body(const int wg, const double *__re
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       if (t * 16 >= sa) break;
+      double sv[KS];  // band t of the slice
+      if constexpr (BL) {
+        load_band<KS, !TR>(X + (long long)a * i, col, a, b, g, j, t, sv);
+      } else {
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) sv[ks] = cur[ks][t];
+      }
       d4 wt[NT];  // W^T = Q1^T S^T tiles (c-tile, s-band t)
 #pragma unroll
       for (int u = 0; u < NT; ++u) wt[u] = d4{0.0, 0.0, 0.0, 0.0};
@@ -746,7 +778,7 @@ __device__ __forceinline__ void apply_fac2_body(const int wg, const double *__re
 #pragma unroll
         for (int cb = 0; cb < NT; ++cb) {
           if ((tri && ks < 4 * cb) || (GD && (ks >= ksr || cb >= ntq1))) continue;
-          wt[cb] = mfma(frag1[(cb * KS + ks) * 64 + lane], cur[ks][t], wt[cb]);
+          wt[cb] = mfma(frag1[(cb * KS + ks) * 64 + lane], sv[ks], wt[cb]);
         }
       d4 yt[NT];  // Y^T = Q2^T W^T tiles (c2-tile, s-band t)
 #pragma unroll
@@ -781,7 +813,7 @@ __device__ __forceinline__ void apply_fac2_body(const int wg, const double *__re
 }
 
 template <int NT, int KS, bool TR>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NT <= 3 || (TR && KS <= 14) ? 2 : 1, NT <= 3 || (TR && KS <= 14) ? 2 : 1))) void k_apply_fac2(const double *__restrict__ X, int a, int b, long long I,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_apply_fac2(const double *__restrict__ X, int a, int b, long long I,
                                                          const double *__restrict__ Q1, int q1, long long s1r,
                                                          long long s1c, int tri, const double *__restrict__ Q2,
                                                          int q2, long long s2r, long long s2c, long long spw,
@@ -821,13 +853,13 @@ void kb_apply_mfma(const BDesc *__restrict__ d, const WGItem *__restrict__ items
                                               e.sQc, 0, e.spw, e.out)))
 }
 template <int NT, bool TR>
-__global__ __launch_bounds__(kThreads) void kb_gram_fac(const BDesc *__restrict__ d, const WGItem *__restrict__ items,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void kb_gram_fac(const BDesc *__restrict__ d, const WGItem *__restrict__ items,
                                                         int nitems) {
   TTR_ITEMS_LOOP((gram_fac_body<NT, 4 * NT, TR, true>(w.wg, e.X, e.a, e.b, e.I, e.Q, e.q, e.sQr, e.sQc, e.tri, e.spw,
                                                 e.out)))
 }
 template <int NT, bool TR>
-__global__ __launch_bounds__(kThreads) void kb_apply_fac2(const BDesc *__restrict__ d,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void kb_apply_fac2(const BDesc *__restrict__ d,
                                                           const WGItem *__restrict__ items, int nitems) {
   TTR_ITEMS_LOOP((apply_fac2_body<NT, 4 * NT, TR, true>(w.wg, e.X, e.a, e.b, e.I, e.Q, e.q, e.sQr, e.sQc, e.tri, e.Q2,
                                                   e.q2, e.s2r, e.s2c, e.spw, e.out)))
