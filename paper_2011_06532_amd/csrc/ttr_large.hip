@@ -17,9 +17,12 @@
 // measured on.
 //
 // Small factorizations (d <= 256): Cholesky with Gershgorin / norm bounds,
-// shifted Cholesky (first pass), rank-revealing pivoted Cholesky (refinement
-// passes), and a one-sided Jacobi SVD for the truncation, all in one
-// 1024-thread workgroup over device-memory scratch (L2-resident).
+// shifted Cholesky (first pass) and rank-revealing pivoted Cholesky
+// (refinement passes) run in one 1024-thread workgroup over device-memory
+// scratch (L2-resident), Cholesky and triangular inverse blocked in 16-column
+// panels; the products with the triangular factor (R = L^T Rc) are dgemm
+// calls.  The truncation SVD is a block one-sided Jacobi over many
+// workgroups, one launch per round.
 #include "ttr_host.h"
 
 #include <rocblas/rocblas.h>

@@ -1,7 +1,7 @@
-// FP64 matrix-core (MFMA) streaming kernels for the first Gram pass of each
-// QR-by-Gram factorization and for the output pass, on cores stored in the
-// paper's layout (§3.1): entry (a, i, b) of an R0 x I x R1 core at
-// a + R0*(i + I*b).
+// Matrix-core (MFMA) streaming kernels of the QR-by-Gram factorizations and
+// of the output pass (FP64, and FP32 for the mixed-precision first Gram
+// pass), on cores stored in the paper's layout (§3.1): entry (a, i, b) of an
+// R0 x I x R1 core at a + R0*(i + I*b).
 //
 // v_mfma_f64_16x16x4f64 on gfx950: lane l supplies A[l%16][k0 + l/16] and
 // B[k0 + l/16][l%16]; the 16x16 result sits in four registers per lane with
@@ -10,11 +10,15 @@
 // that contracts over the tile's row index, so the chains below
 //   Gram, right factor:  Wt = Q^T M^T,  G  += Wt^T Wt   (contract over c)
 //   Gram, left factor:   Y  = P M,      G0 += Y^T Y     (contract over rho)
-//   output:              W  = M Q,      Y   = P W       (contract over alpha)
-// feed one product's accumulators straight into the next, without LDS.
+//   output:              W  = M Q,      Y^T = W^T P^T   (contract over alpha)
+// feed one product's accumulators straight into the next, without LDS; a
+// product with its operands swapped gives bitwise the transposed result.
 // The small factors (<= 64 x 64) sit in LDS pre-arranged as per-lane
 // fragments; slices are read from HBM once, 16 consecutive rows per lane
-// group where the layout allows.
+// group, or two consecutive rows per lane (16-byte loads) where the product
+// contracts over rows.  Products accumulate one 16-row or 16-column band at a
+// time where the band's contribution is complete on its own, which keeps the
+// live accumulators to NT tiles and the FP64 kernels at two waves per SIMD.
 //
 // Each workgroup (4 waves) owns a contiguous range of slices; the waves take
 // slices round-robin, keep their own partial Gram in registers, and combine
@@ -489,8 +493,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NT <= 
 // ---------------------------------------------------------------------------
 // Output pass: Y_i = P M_i Q (p x q) written as a p x I x q core.  P == nullptr
 // means the identity (p = a); Q == nullptr means the identity (q = b).
-// KS = k-steps over b.  With NT <= 3 two waves share each SIMD, so one wave's
-// loads and stores overlap the other's matrix-core work.
+// KS = k-steps over b.  Two waves share each SIMD (NT <= 3, and NT = 4 at
+// KS = 13), so one wave's loads and stores overlap the other's matrix-core
+// work.
 // ---------------------------------------------------------------------------
 // Writes the tiles yt[u] of column band c of the transpose of an nrow x ncol
 // block of one output slice: register r of yt[u] in lane (g, j) holds
