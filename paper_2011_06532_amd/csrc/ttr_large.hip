@@ -207,16 +207,22 @@ __device__ bool lchol(double *A, int d, double *S) {
 // X = L^{-1} (k x k lower, ld d) for the lower-triangular L in A (ld d).
 // The diagonal 16-blocks are inverted by one wave each in registers (forward
 // substitution on all columns at once, rows broadcast lane by lane); then
-// block row i: X(i, 0:i) = -X_ii (L(i, 0:i) X(0:i, 0:i)), the inner product
-// staged in LDS (S, kLdsB doubles).  Two barriers per block row.
+// block row i: X(i, 0:i) = -X_ii (L(i, 0:i) X(0:i, 0:i)), 32 columns at a
+// time with the block row of L and the column panel of X staged in LDS.
+constexpr int kInvP = 32;  // columns of X per staged panel
 __device__ void linv(const double *A, double *X, int k, int d, double *S) {
+  (void)S;
+  __shared__ double Lr[kNB * kLMax];     // L(i0 + r, m) at [m * kNB + r]
+  __shared__ double Xp[kLMax * kInvP];   // X(m, c0 + c) at [m * kInvP + c]
+  __shared__ double Tp[kNB * kInvP];     // T(r, c) at [r * kInvP + c]
+  __shared__ double Xd[kNB * kNB];       // X_ii(r, t) at [r * kNB + t]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nblk = (k + kNB - 1) / kNB;
   for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
     const int r = e % k, c = e / k;
     if (r < c) X[r + (size_t)d * c] = 0.0;
   }
-  // nblk <= 16 = the waves of the workgroup: one block per wave
+  // nblk <= 16 = the waves of the workgroup: one diagonal block per wave
   if (const int bw = wave; bw < nblk) {
     const int b0 = bw * kNB, nb = min(kNB, k - b0);
     const int r = lane;
@@ -244,24 +250,39 @@ __device__ void linv(const double *A, double *X, int k, int d, double *S) {
         if (c <= r) X[(b0 + r) + (size_t)d * (b0 + c)] = x[c];
   }
   __syncthreads();
-  const int tr = threadIdx.x & 31, tcg = threadIdx.x >> 5, ng = blockDim.x >> 5;
+  const int tr = threadIdx.x & (kNB - 1), tcl = threadIdx.x / kNB;  // 16 rows x 64 columns of threads
   for (int bi = 1; bi < nblk; ++bi) {
     const int i0 = bi * kNB, ni = min(kNB, k - i0);
-    // T(r, c) = sum_{m = c}^{i0 - 1} L(i0 + r, m) X(m, c), c < i0
-    for (int c = tcg; c < i0; c += ng)
-      if (tr < ni) {
-        double acc = 0.0;
-        for (int m = c; m < i0; ++m) acc += A[(i0 + tr) + (size_t)d * m] * X[m + (size_t)d * c];
-        S[tr * (kLMax + 1) + c] = acc;
+    for (int e = threadIdx.x; e < kNB * i0; e += blockDim.x) {
+      const int r = e % kNB, m = e / kNB;
+      Lr[e] = (r < ni) ? A[(i0 + r) + (size_t)d * m] : 0.0;
+    }
+    for (int e = threadIdx.x; e < kNB * kNB; e += blockDim.x) {
+      const int r = e / kNB, t = e % kNB;
+      Xd[e] = (r < ni && t <= r) ? X[(i0 + r) + (size_t)d * (i0 + t)] : 0.0;
+    }
+    for (int c0 = 0; c0 < i0; c0 += kInvP) {
+      const int nc = min(kInvP, i0 - c0);
+      __syncthreads();  // Lr / Xd written; the previous panel's readers are done
+      for (int e = threadIdx.x; e < i0 * kInvP; e += blockDim.x) {
+        const int m = e % i0, c = e / i0;
+        Xp[m * kInvP + c] = (c < nc) ? X[m + (size_t)d * (c0 + c)] : 0.0;
       }
-    __syncthreads();
-    // X(i0 + r, c) = -sum_t X(i0 + r, i0 + t) T(t, c)
-    for (int c = tcg; c < i0; c += ng)
-      if (tr < ni) {
+      __syncthreads();
+      // T(r, c) = sum_{m >= c0 + c} L(i0 + r, m) X(m, c0 + c)  (X lower triangular)
+      if (tcl < kInvP) {
         double acc = 0.0;
-        for (int t = 0; t <= tr; ++t) acc += X[(i0 + tr) + (size_t)d * (i0 + t)] * S[t * (kLMax + 1) + c];
-        X[(i0 + tr) + (size_t)d * c] = -acc;
+        for (int m = c0 + tcl; m < i0; ++m) acc += Lr[m * kNB + tr] * Xp[m * kInvP + tcl];
+        Tp[tr * kInvP + tcl] = acc;
       }
+      __syncthreads();
+      // X(i0 + r, c0 + c) = -sum_{t <= r} X_ii(r, t) T(t, c)
+      if (tcl < nc && tr < ni) {
+        double acc = 0.0;
+        for (int t = 0; t <= tr; ++t) acc += Xd[tr * kNB + t] * Tp[t * kInvP + tcl];
+        X[(i0 + tr) + (size_t)d * (c0 + tcl)] = -acc;
+      }
+    }
     __syncthreads();
   }
 }
@@ -420,7 +441,21 @@ __global__ __launch_bounds__(kLT) void lk_step(LStepArgs a) {
   __shared__ double Sbuf[kLdsB];
   const bool ok = lchol(A, d, Sbuf);
   double kappa = 1e300, lmin_lb = 0.0;
-  if (ok) {
+  // kappa(G) = kappa(L)^2 >= (max_j L_jj / min_j L_jj)^2 (the diagonal of a
+  // triangular matrix holds its eigenvalues): when that already exceeds
+  // 1/tau1 the step is rejected without forming L^{-1}
+  double dmx = 0.0, dmn = DBL_MAX;
+  if (ok)
+    for (int j = threadIdx.x; j < d; j += blockDim.x) {
+      dmx = fmax(dmx, A[j + (size_t)d * j]);
+      dmn = fmin(dmn, A[j + (size_t)d * j]);
+    }
+  dmx = lmax(dmx);
+  dmn = -lmax(-dmn);
+  const double klow = (dmx / dmn) * (dmx / dmn);
+  if (ok && !(klow * a.tau1 <= 1.0)) {
+    kappa = klow;
+  } else if (ok) {
     linv(A, X, d, d, Sbuf);
     double x1, xi, xf;
     lnorms(X, d, d, &x1, &xi, &xf);
