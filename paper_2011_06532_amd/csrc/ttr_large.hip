@@ -105,7 +105,7 @@ __device__ void largmax(double *v, int *p) {
 }
 
 constexpr int kNB = 16;                        // panel width of the blocked factorizations (registers: 1024-thread blocks leave 128 per lane)
-constexpr int kLdsB = kLMax * (kNB + 1);       // doubles of LDS they use (panel or block row)
+constexpr int kLdsB = kLMax * (kNB + 1);       // doubles of LDS the blocked Cholesky's panel uses
 
 // v from lane `lane` (uniform) of the wave, as a wave-uniform value.
 __device__ inline double bcast(double v, int lane) {
@@ -210,8 +210,7 @@ __device__ bool lchol(double *A, int d, double *S) {
 // block row i: X(i, 0:i) = -X_ii (L(i, 0:i) X(0:i, 0:i)), 32 columns at a
 // time with the block row of L and the column panel of X staged in LDS.
 constexpr int kInvP = 32;  // columns of X per staged panel
-__device__ void linv(const double *A, double *X, int k, int d, double *S) {
-  (void)S;
+__device__ void linv(const double *A, double *X, int k, int d) {
   __shared__ double Lr[kNB * kLMax];     // L(i0 + r, m) at [m * kNB + r]
   __shared__ double Xp[kLMax * kInvP];   // X(m, c0 + c) at [m * kInvP + c]
   __shared__ double Tp[kNB * kInvP];     // T(r, c) at [r * kInvP + c]
@@ -313,17 +312,27 @@ __device__ void lnorms(const double *M, int k, int d, double *n1, double *ni, do
   *f2 = lsum(af);
 }
 
-// Rank-revealing pivoted Cholesky (as in the d <= 64 kernels), A in device memory.
+// Rank-revealing pivoted Cholesky (as in the d <= 64 kernels), A in device
+// memory: pivots in order perm[0..k), on return A(i, j) (i >= j, j < k) holds
+// L with G(perm, perm) ~= L L^T; stops once the largest remaining diagonal
+// entry is at most tau times the largest initial one.  Returns k.  Only the
+// lower triangle is kept: the symmetric interchange of rows/columns j and p
+// moves lower-triangle entries only, and step j updates the trailing lower
+// triangle with the unscaled column j (L(r,j) L(c,j) = A(r,j) A(c,j) / A(j,j)),
+// column j being scaled one step later (scaling commutes with the row
+// interchanges of the next step).
 __device__ int lpivchol(double *A, int d, double tau, int *perm) {
   __shared__ int piv, stop;
   __shared__ double dmax0;
   for (int i = threadIdx.x; i < d; i += blockDim.x) perm[i] = i;
-  double m = 0.0;
-  for (int i = threadIdx.x; i < d; i += blockDim.x) m = fmax(m, A[i + (size_t)d * i]);
-  m = lmax(m);
-  if (threadIdx.x == 0) dmax0 = m;
+  double m0 = 0.0;
+  for (int i = threadIdx.x; i < d; i += blockDim.x) m0 = fmax(m0, A[i + (size_t)d * i]);
+  m0 = lmax(m0);
+  if (threadIdx.x == 0) dmax0 = m0;
   __syncthreads();
+  const int tr = threadIdx.x & 31, tc = threadIdx.x >> 5, nc = blockDim.x >> 5;
   int k = d;
+  double lprev = 0.0;  // L(j-1, j-1), for the deferred scaling of column j-1
   for (int j = 0; j < d; ++j) {
     {
       // the largest remaining diagonal entry, the first one among ties
@@ -349,34 +358,47 @@ __device__ int lpivchol(double *A, int d, double tau, int *perm) {
     }
     const int p = piv;
     if (p != j) {
-      for (int c = threadIdx.x; c < d; c += blockDim.x) {
+      // symmetric interchange j <-> p (j < p) on the lower triangle
+      for (int c = threadIdx.x; c < j; c += blockDim.x) {  // rows of L so far
         const double t = A[j + (size_t)d * c];
         A[j + (size_t)d * c] = A[p + (size_t)d * c];
         A[p + (size_t)d * c] = t;
       }
-      __syncthreads();
-      for (int r = threadIdx.x; r < d; r += blockDim.x) {
-        const double t = A[r + (size_t)d * j];
-        A[r + (size_t)d * j] = A[r + (size_t)d * p];
-        A[r + (size_t)d * p] = t;
+      for (int m = j + 1 + threadIdx.x; m < p; m += blockDim.x) {  // column j between <-> row p
+        const double t = A[m + (size_t)d * j];
+        A[m + (size_t)d * j] = A[p + (size_t)d * m];
+        A[p + (size_t)d * m] = t;
+      }
+      for (int m = p + 1 + threadIdx.x; m < d; m += blockDim.x) {  // below p: columns j and p
+        const double t = A[m + (size_t)d * j];
+        A[m + (size_t)d * j] = A[m + (size_t)d * p];
+        A[m + (size_t)d * p] = t;
       }
       if (threadIdx.x == 0) {
-        const int t = perm[j];
+        const double t = A[j + (size_t)d * j];
+        A[j + (size_t)d * j] = A[p + (size_t)d * p];
+        A[p + (size_t)d * p] = t;
+        const int ti = perm[j];
         perm[j] = perm[p];
-        perm[p] = t;
+        perm[p] = ti;
       }
       __syncthreads();
     }
-    if (threadIdx.x == 0) A[j + (size_t)d * j] = sqrt(A[j + (size_t)d * j]);
-    __syncthreads();
-    const double ljj = A[j + (size_t)d * j];
-    for (int i = j + 1 + threadIdx.x; i < d; i += blockDim.x) A[i + (size_t)d * j] /= ljj;
-    __syncthreads();
-    const int n = d - j - 1;
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-      const int r = j + 1 + e % n, c = j + 1 + e / n;
-      A[r + (size_t)d * c] -= A[r + (size_t)d * j] * A[c + (size_t)d * j];
+    const double pv = A[j + (size_t)d * j];
+    if (j > 0)
+      for (int r = j - 1 + threadIdx.x; r < d; r += blockDim.x)
+        A[r + (size_t)d * (j - 1)] = (r == j - 1) ? lprev : A[r + (size_t)d * (j - 1)] / lprev;
+    const double rp = 1.0 / pv;
+    for (int c = j + 1 + tc; c < d; c += nc) {
+      const double acj = A[c + (size_t)d * j] * rp;
+      for (int r = c + tr; r < d; r += 32) A[r + (size_t)d * c] -= A[r + (size_t)d * j] * acj;
     }
+    lprev = sqrt(pv);
+    __syncthreads();
+  }
+  if (k > 0) {
+    for (int r = k - 1 + threadIdx.x; r < d; r += blockDim.x)
+      A[r + (size_t)d * (k - 1)] = (r == k - 1) ? lprev : A[r + (size_t)d * (k - 1)] / lprev;
     __syncthreads();
   }
   return k;
@@ -456,7 +478,7 @@ __global__ __launch_bounds__(kLT) void lk_step(LStepArgs a) {
   if (ok && !(klow * a.tau1 <= 1.0)) {
     kappa = klow;
   } else if (ok) {
-    linv(A, X, d, d, Sbuf);
+    linv(A, X, d, d);
     double x1, xi, xf;
     lnorms(X, d, d, &x1, &xi, &xf);
     kappa = g1 * x1 * xi;
@@ -511,7 +533,7 @@ __global__ __launch_bounds__(kLT) void lk_step(LStepArgs a) {
     for (int j = threadIdx.x; j < d; j += blockDim.x) A[j + (size_t)d * j] += shift;
     __syncthreads();
     if (shift > 0.0 && lchol(A, d, Sbuf)) {
-      linv(A, X, d, d, Sbuf);
+      linv(A, X, d, d);
       for (int e = threadIdx.x; e < d * d; e += blockDim.x) {
         const int r = e % d, c = e / d;
         a.Fstep[r + (size_t)d * c] = X[c + (size_t)d * r];
@@ -549,7 +571,7 @@ __global__ __launch_bounds__(kLT) void lk_step(LStepArgs a) {
     }
     return;
   }
-  linv(A, X, k, d, Sbuf);
+  linv(A, X, k, d);
   double x1, xi, xf, gk = 0.0;
   lnorms(X, k, d, &x1, &xi, &xf);
   for (int c = threadIdx.x; c < k; c += blockDim.x) {
@@ -609,7 +631,6 @@ struct LTruncArgs {
 // up the one-sided Jacobi SVD of R: W0 = A = R^T (b x k), W1 = U = I (k x k),
 // and the rotation thresholds.
 __global__ __launch_bounds__(kLT) void lk_trunc_setup(LTruncArgs a) {
-  __shared__ double Sbuf[kLdsB];
   const int k = a.k, b = a.b;
   __shared__ int ident, tri_ok;
   if (threadIdx.x == 0) {
@@ -633,7 +654,7 @@ __global__ __launch_bounds__(kLT) void lk_trunc_setup(LTruncArgs a) {
       for (int j = 0; j < k; ++j) okd = okd && (a.R[j + (size_t)k * j] != 0.0);
       double xf = 0.0, rf = 0.0;
       if (okd) {
-        linv(a.W0, a.W1, k, k, Sbuf);
+        linv(a.W0, a.W1, k, k);
         for (int e = threadIdx.x; e < k * k; e += blockDim.x) xf += a.W1[e] * a.W1[e];
       }
       for (int e = threadIdx.x; e < k * k; e += blockDim.x) rf += a.R[e] * a.R[e];
