@@ -103,7 +103,8 @@ __global__ void k_add_pairs(int n, int N, double alpha, double beta, const doubl
         v = d2{0.0, 0.0};
       }
     }
-    Zb[e] = v;
+    // written once and read by a later pass: stream past the caches
+    __builtin_nontemporal_store(v, &Zb[e]);
   }
 }
 
