@@ -297,6 +297,9 @@ __device__ __forceinline__ void gram_right_factor_body(const int wg, const doubl
   if constexpr (PF)
     if (i < end) load_slice<NT, KS, true, T>(X + (long long)a * i, col, a, b, g, j, cur);
   for (; i < end; i += kWaves) {
+    // NT = 4: keep the operand fragments in LDS rather than hoisted into
+    // registers, which is what lets two waves share a SIMD
+    if constexpr (NT == 4) __asm__ volatile("" ::: "memory");
     if constexpr (PF) {
       if (i + kWaves < end) load_slice<NT, KS, true>(X + (long long)a * (i + kWaves), col, a, b, g, j, nxt);
     } else {
@@ -343,7 +346,7 @@ __device__ __forceinline__ void gram_right_factor_body(const int wg, const doubl
 }
 
 template <int NT, int KS, class A>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NT <= 3 ? 2 : 1, NT <= 3 ? 2 : 1))) void k_gram_right_factor(const double *__restrict__ X, int a, int b, long long I,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NT <= 3 || (KS <= 13 && sizeof(typename A::T) == 8) ? 2 : 1, NT <= 3 || (KS <= 13 && sizeof(typename A::T) == 8) ? 2 : 1))) void k_gram_right_factor(const double *__restrict__ X, int a, int b, long long I,
                                                                 const double *__restrict__ Q, int q, long long sQr,
                                                                 long long sQc, int tri, long long spw,
                                                                 double *__restrict__ partials) {
@@ -401,6 +404,9 @@ __device__ __forceinline__ void gram_left_factor_body(const int wg, const double
     }
   }
   for (; i < end; i += kWaves) {
+    // NT = 4: keep the operand fragments in LDS rather than hoisted into
+    // registers, which is what lets two waves share a SIMD
+    if constexpr (NT == 4) __asm__ volatile("" ::: "memory");
     if constexpr (PF) {
       if (i + kWaves < end) {
         const double *Xn = X + (long long)a * (i + kWaves);
@@ -482,7 +488,7 @@ __device__ __forceinline__ void gram_left_factor_body(const int wg, const double
 }
 
 template <int NT, int KS, class A, bool ST = false>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NT <= 3 ? 2 : 1, NT <= 3 ? 2 : 1))) void k_gram_left_factor(const double *__restrict__ X, int a, int b, long long I,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NT <= 3 || KS <= 14 ? 2 : 1, NT <= 3 || KS <= 14 ? 2 : 1))) void k_gram_left_factor(const double *__restrict__ X, int a, int b, long long I,
                                                                const double *__restrict__ P, int p, long long sPr,
                                                                long long sPa, int tri, long long spw,
                                                                double *__restrict__ partials,
