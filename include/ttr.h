@@ -83,6 +83,20 @@ int ttr_create(ttr_handle **h, int device, void *stream);
 int ttr_destroy(ttr_handle *h);
 int ttr_set_stream(ttr_handle *h, void *stream);
 
+/* Routes the handle's device workspaces (Gram partials, small factors,
+ * materialized cores, the batched plan, the rank 65..256 scratch) through a
+ * caller allocator, e.g. a framework's caching allocator: alloc(bytes, ctx)
+ * returns device memory on the handle's device or NULL (the call that needed
+ * it then fails with TTR_ERR_ALLOC); free(ptr, ctx) takes back what alloc gave.
+ * Both NULL restores hipMalloc / hipFree.  Synchronizes the stream and returns
+ * the current workspaces to the allocator they came from first, so memory is
+ * never freed through the wrong one.  Memory is requested when a call needs
+ * more than the handle holds and kept until the next larger request, this
+ * call, or ttr_destroy.  (rocBLAS keeps its own small internal workspace.)
+ * Errors: TTR_ERR_INVALID_ARG if exactly one of alloc / free is NULL. */
+int ttr_set_allocator(ttr_handle *h, void *(*alloc)(size_t bytes, void *ctx), void (*free)(void *ptr, void *ctx),
+                      void *ctx);
+
 /* Z = alpha*X + beta*Y, slice-wise (§3.2.1): first core [alpha X_1, beta Y_1],
  * interior slices blockdiag(X_n(i), Y_n(i)) with the X block first, last core
  * [X_N; Y_N]; ranks add.  For N = 1 the single core is alpha X_1 + beta Y_1.

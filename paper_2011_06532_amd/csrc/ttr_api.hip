@@ -68,14 +68,14 @@ int ensure_ws(ttr_handle *h, size_t bytes) {
   if (bytes <= h->ws_bytes) return TTR_OK;
   if (h->ws) {
     HIPCHK(hipStreamSynchronize(h->stream));
-    HIPCHK(hipFree(h->ws));
+    ttr_dev_free(h, h->ws);
     h->ws = nullptr;
     h->ws_bytes = 0;
   }
-  if (hipMalloc(&h->ws, bytes) != hipSuccess) {
-    h->ws = nullptr;
-    return fail(TTR_ERR_ALLOC, "workspace allocation of " + std::to_string(bytes) + " bytes failed");
-  }
+  void *p = nullptr;
+  int rc;
+  if ((rc = ttr_dev_alloc(h, &p, bytes))) return rc;
+  h->ws = static_cast<double *>(p);
   h->ws_bytes = bytes;
   return TTR_OK;
 }
@@ -620,6 +620,23 @@ size_t max_core(const ttr_tt *X) {
 
 }  // namespace
 
+int ttr_dev_alloc(ttr_handle *h, void **p, size_t bytes) {
+  *p = nullptr;
+  if (h->alloc_fn) {
+    *p = h->alloc_fn(bytes, h->alloc_ctx);
+  } else if (hipMalloc(p, bytes) != hipSuccess) {
+    *p = nullptr;
+  }
+  if (!*p) return fail(TTR_ERR_ALLOC, "workspace allocation of " + std::to_string(bytes) + " bytes failed");
+  return TTR_OK;
+}
+
+void ttr_dev_free(ttr_handle *h, void *p) {
+  if (!p) return;
+  if (h->free_fn) h->free_fn(p, h->alloc_ctx);
+  else (void)hipFree(p);
+}
+
 extern "C" {
 
 int ttr_create(ttr_handle **h, int device, void *stream) {
@@ -649,7 +666,7 @@ int ttr_destroy(ttr_handle *h) {
   if (!h) return TTR_OK;
   (void)hipSetDevice(h->device);
   (void)hipStreamSynchronize(h->stream);
-  if (h->ws) (void)hipFree(h->ws);
+  if (h->ws) ttr_dev_free(h, h->ws);
   if (h->dec_dev) (void)hipFree(h->dec_dev);
   if (h->decf_dev) (void)hipFree(h->decf_dev);
   if (h->decf_host) (void)hipHostFree(h->decf_host);
@@ -669,6 +686,25 @@ int ttr_destroy(ttr_handle *h) {
 int ttr_set_stream(ttr_handle *h, void *stream) {
   if (!h) return fail(TTR_ERR_INVALID_ARG, "handle is NULL");
   h->stream = (hipStream_t)stream;
+  return TTR_OK;
+}
+
+int ttr_set_allocator(ttr_handle *h, void *(*alloc)(size_t bytes, void *ctx), void (*dealloc)(void *ptr, void *ctx),
+                      void *ctx) {
+  if (!h) return fail(TTR_ERR_INVALID_ARG, "handle is NULL");
+  if ((alloc == nullptr) != (dealloc == nullptr))
+    return fail(TTR_ERR_INVALID_ARG, "alloc and free must both be given or both be NULL");
+  HIPCHK(hipSetDevice(h->device));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  // every workspace goes back to the allocator it came from
+  if (h->ws) ttr_dev_free(h, h->ws);
+  h->ws = nullptr;
+  h->ws_bytes = 0;
+  ttr_batch_release(h);
+  ttr_large_release(h);
+  h->alloc_fn = alloc;
+  h->free_fn = dealloc;
+  h->alloc_ctx = ctx;
   return TTR_OK;
 }
 

@@ -649,12 +649,12 @@ namespace {
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
-void free_plan(BatchPlan *p) {
+void free_plan(ttr_handle *h, BatchPlan *p) {
   if (!p) return;
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
   if (p->cap) (void)hipStreamDestroy(p->cap);
-  if (p->mem) (void)hipFree(p->mem);
+  if (p->mem) ttr_dev_free(h, p->mem);
   delete p;
 }
 
@@ -835,7 +835,7 @@ int time_graph(BatchPlan *P, hipStream_t s, double *ms) {
 
 void ttr_batch_release(ttr_handle *h) {
   if (!h) return;
-  free_plan(h->plan);
+  free_plan(h, h->plan);
   h->plan = nullptr;
 }
 
@@ -883,7 +883,7 @@ int ttr_round_batched(ttr_handle *h, int count, const ttr_tt *X, const double *t
   }
   BatchPlan *P = h->plan;
   if (!P || P->sig != sig) {
-    free_plan(P);
+    free_plan(h, P);
     h->plan = nullptr;
     P = new BatchPlan();
     h->plan = P;
@@ -921,11 +921,13 @@ int ttr_round_batched(ttr_handle *h, int count, const ttr_tt *X, const double *t
                        align_up(max_items * sizeof(WGItem)) + align_up((size_t)count * 24 * sizeof(int)) +
                        align_up((size_t)count * 8 * sizeof(double));
     P->mem_bytes = hdr + total * sizeof(double);
-    if (hipMalloc(&P->mem, P->mem_bytes) != hipSuccess) {
+    void *m = nullptr;
+    if (ttr_dev_alloc(h, &m, P->mem_bytes) != TTR_OK) {
       P->mem = nullptr;
       ttr_batch_release(h);
       return ttr_fail(TTR_ERR_ALLOC, "batched workspace allocation of " + std::to_string(P->mem_bytes) + " bytes failed");
     }
+    P->mem = m;
     char *c = (char *)P->mem;
     P->St = (BState *)c; c += align_up(count * sizeof(BState));
     P->d = (BDesc *)c; c += align_up(count * sizeof(BDesc));

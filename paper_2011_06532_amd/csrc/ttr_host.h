@@ -36,7 +36,17 @@ struct ttr_handle {
   BatchPlan *plan = nullptr;
   // ranks above 64: library handle and workspace of the GEMM-based path
   LargeCtx *large = nullptr;
+  // caller-registered device allocator for the workspaces (ttr_set_allocator);
+  // nullptr: hipMalloc / hipFree
+  void *(*alloc_fn)(size_t, void *) = nullptr;
+  void (*free_fn)(void *, void *) = nullptr;
+  void *alloc_ctx = nullptr;
 };
+
+// Workspace memory through the handle's allocator: TTR_OK, or TTR_ERR_ALLOC
+// with the message recorded.
+int ttr_dev_alloc(ttr_handle *h, void **p, size_t bytes);
+void ttr_dev_free(ttr_handle *h, void *p);
 
 // Records `msg` for ttr_last_error() and returns `code`.
 int ttr_fail(int code, const std::string &msg);

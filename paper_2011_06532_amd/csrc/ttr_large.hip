@@ -888,7 +888,7 @@ void ttr_large_release(ttr_handle *h) {
   if (!h || !h->large) return;
   LargeCtx *c = h->large;
   if (c->rb) rocblas_destroy_handle(c->rb);
-  if (c->mem) (void)hipFree(c->mem);
+  if (c->mem) ttr_dev_free(h, c->mem);
   delete c;
   h->large = nullptr;
 }
@@ -1031,14 +1031,14 @@ int ttr_round_large(ttr_handle *h, const ttr_tt *X, double tol, ttr_tt *Y, doubl
   if (ctx->bytes < need * sizeof(double)) {
     if (ctx->mem) {
       TTR_HIPCHK(hipStreamSynchronize(h->stream));
-      TTR_HIPCHK(hipFree(ctx->mem));
+      ttr_dev_free(h, ctx->mem);
       ctx->mem = nullptr;
       ctx->bytes = 0;
     }
-    if (hipMalloc(&ctx->mem, need * sizeof(double)) != hipSuccess) {
-      ctx->mem = nullptr;
-      return ttr_fail(TTR_ERR_ALLOC, "workspace allocation of " + std::to_string(need * sizeof(double)) + " bytes failed");
-    }
+    void *m = nullptr;
+    int arc;
+    if ((arc = ttr_dev_alloc(h, &m, need * sizeof(double)))) return arc;
+    ctx->mem = static_cast<double *>(m);
     ctx->bytes = need * sizeof(double);
   }
   Large L;

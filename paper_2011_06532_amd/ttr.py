@@ -38,8 +38,12 @@ _PREC = {"fp64": TTR_FP64, "mixed": TTR_MIXED}
 SYMBOLS = [
     "ttr_create", "ttr_destroy", "ttr_set_stream", "ttr_add", "ttr_hadamard", "ttr_dot", "ttr_norm",
     "ttr_orthogonalize", "ttr_round", "ttr_status_string", "ttr_last_error", "ttr_get_round_stats",
-    "ttr_set_profiling", "ttr_get_profile", "ttr_round_batched", "ttr_get_batch_plan",
+    "ttr_set_profiling", "ttr_get_profile", "ttr_round_batched", "ttr_get_batch_plan", "ttr_set_allocator",
 ]
+
+# ttr_set_allocator callback types: void *alloc(size_t bytes, void *ctx), void free(void *ptr, void *ctx)
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 PROF_CLASSES = ["k_gram_right_factor", "k_gram_left_factor", "k_gram", "k_apply_mfma", "k_apply", "k_add",
                 "k_hadamard", "k_dot_step", "small", "k_gram_fac", "k_apply_fac2", "k_gram_right_factor_f32",
@@ -116,6 +120,7 @@ def load(path: str = LIB_PATH):
     lib.ttr_create.argtypes = [P(vp), ctypes.c_int, vp]
     lib.ttr_destroy.argtypes = [vp]
     lib.ttr_set_stream.argtypes = [vp, vp]
+    lib.ttr_set_allocator.argtypes = [vp, ALLOC_FN, FREE_FN, vp]
     lib.ttr_add.argtypes = [vp, ctypes.c_double, tt, ctypes.c_double, tt, tt]
     lib.ttr_hadamard.argtypes = [vp, tt, tt, tt]
     lib.ttr_dot.argtypes = [vp, tt, tt, P(ctypes.c_double)]
@@ -221,6 +226,27 @@ class Handle:
     def sync_stream(self):
         import torch
         _check(_lib.ttr_set_stream(self.h, ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)))
+
+    def set_allocator(self, alloc=None, free=None):
+        """Workspaces through alloc(nbytes) -> int pointer (0 on failure) and
+        free(pointer); both None restores hipMalloc / hipFree."""
+        if (alloc is None) != (free is None):
+            raise ValueError("give both alloc and free, or neither")
+        if alloc is None:
+            a, f = ctypes.cast(None, ALLOC_FN), ctypes.cast(None, FREE_FN)
+        else:
+            a = ALLOC_FN(lambda n, ctx: alloc(int(n)) or None)
+            f = FREE_FN(lambda p, ctx: free(int(p)))
+        _check(_lib.ttr_set_allocator(self.h, a, f, None))
+        self._alloc_cb = (a, f)  # the library keeps the function pointers
+
+    def use_torch_allocator(self):
+        """Workspaces from torch's caching allocator (on the current stream)."""
+        import torch
+        stream = torch.cuda.current_stream(self.device)
+        dev = self.device
+        self.set_allocator(lambda n: torch.cuda.caching_allocator_alloc(n, dev, stream),
+                           torch.cuda.caching_allocator_delete)
 
     def close(self):
         if self.h:

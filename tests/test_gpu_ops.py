@@ -180,3 +180,64 @@ def test_nonfinite_input_reports_numerical(ttr, h):
     with pytest.raises(ttr.TTRError) as e:
         h.round(ttr.TT.from_numpy(X), 1e-6)
     assert e.value.code == 6
+
+
+def test_workspace_through_caller_allocator(ttr):
+    # ttr_set_allocator: every workspace comes from (and goes back to) the
+    # caller's allocator -- here torch's caching allocator -- and results are
+    # those of the default allocator
+    import torch
+    print("allocator hook", flush=True)
+    rng = np.random.default_rng(110)
+    I, r = [300, 257, 129, 64], [9, 12, 7]
+    X = rand_tt(rng, I, r)
+    tol = 1e-3
+    ref_h = ttr.Handle(0)
+    ref = ref_h.round(ttr.TT.from_numpy(X), tol, "RLR").to_numpy()
+    ref_h.close()
+    calls = {"alloc": 0, "free": 0}
+    h = ttr.Handle(0)
+    stream = torch.cuda.current_stream(0)
+
+    def alloc(n):
+        calls["alloc"] += 1
+        return torch.cuda.caching_allocator_alloc(n, 0, stream)
+
+    def free(p):
+        calls["free"] += 1
+        torch.cuda.caching_allocator_delete(p)
+
+    h.set_allocator(alloc, free)
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated(0)
+    got = h.round(ttr.TT.from_numpy(X), tol, "RLR").to_numpy()
+    torch.cuda.synchronize()
+    assert calls["alloc"] >= 1
+    assert torch.cuda.memory_allocated(0) > before  # the workspace is torch memory
+    assert O.ranks(got) == O.ranks(ref)
+    assert O.diff_norm(got, ref) <= 1e-12 * O.norm_ortho(ref)
+    # back to hipMalloc: the workspace is returned to torch first
+    h.set_allocator(None, None)
+    assert calls["free"] == calls["alloc"]
+    again = h.round(ttr.TT.from_numpy(X), tol, "RLR").to_numpy()
+    assert O.diff_norm(again, ref) <= 1e-12 * O.norm_ortho(ref)
+    with pytest.raises(ValueError):
+        h.set_allocator(alloc, None)
+    h.close()
+
+
+def test_allocator_failure_reports_alloc(ttr):
+    # an allocator that returns NULL makes the call that needs memory fail
+    # with TTR_ERR_ALLOC; a later default allocator works again
+    print("allocator failure", flush=True)
+    rng = np.random.default_rng(111)
+    X = rand_tt(rng, [50, 40, 30], [6, 5])
+    h = ttr.Handle(0)
+    h.set_allocator(lambda n: 0, lambda p: None)
+    with pytest.raises(ttr.TTRError) as e:
+        h.round(ttr.TT.from_numpy(X), 1e-6, "RLR")
+    assert e.value.code == 4
+    h.set_allocator(None, None)
+    Y = h.round(ttr.TT.from_numpy(X), 1e-6, "RLR").to_numpy()
+    assert O.ranks(Y) == [1, 6, 5, 1]
+    h.close()
