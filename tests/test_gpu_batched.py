@@ -143,3 +143,34 @@ def test_batched_argument_errors(ttr, h):
     short = ttr.TT.from_numpy(g[1].to_numpy()[:5])   # N = 5 in a batch of N = 8
     short.R[-1] = 1
     assert call([g[0], short], 2) == 2
+
+
+def test_batched_workspace_through_torch_allocator(ttr):
+    # the batched plan's workspace comes from the registered allocator and the
+    # results are unchanged
+    import torch
+    print("batched allocator", flush=True)
+    Xs, rs = batch_inputs(16, 256, start=16)
+    tol = synth.TOL[3]
+    hd = ttr.Handle(0)
+    stream = torch.cuda.current_stream(0)
+    live = {}
+
+    def alloc(n):
+        p = torch.cuda.caching_allocator_alloc(n, 0, stream)
+        live[p] = n
+        return p
+
+    def free(p):
+        live.pop(p)
+        torch.cuda.caching_allocator_delete(p)
+
+    hd.set_allocator(alloc, free)
+    _, _, got = run_batched(ttr, hd, Xs, tol)
+    assert live  # the plan's workspace is held through the allocator
+    for X, r, Yg in zip(Xs, rs, got):
+        assert O.ranks(Yg) == [1] + r + [1]
+    check_against_oracle(Xs, got, tol, 1e-10)
+    hd.set_allocator(None, None)
+    assert not live  # and handed back
+    hd.close()
