@@ -86,7 +86,7 @@ def bench_batched(h, ttr, torch, steps, count=512, per_tensor=True):
     [64, 4096], ranks 2r+2 with r uniform in 1..31), tol 1e-7: one replay of the
     batched graph against one ttr_round call per tensor."""
     import synth
-    shapes = synth.cfg3_shapes(count)
+    shapes = synth.batched_shapes(count)
     log(f"batched: generating {count} tensors")
     Xs = []
     for t, (I, r) in enumerate(shapes):
@@ -145,7 +145,7 @@ def cpu_baseline(I_sample, steps=1):
     import oracle as O
     import synth
     from threadpoolctl import threadpool_info
-    d = synth.cfg1(I_override=I_sample)
+    d = synth.sum_r40(I_override=I_sample)
     t0 = time.perf_counter()
     for _ in range(steps):
         X = O.add(1.0, d["A"], 1.0, d["B"])
@@ -184,7 +184,7 @@ def bench_large(h, ttr, torch, steps):
     import synth
     torch.cuda.empty_cache()   # blocks cached by the earlier legs are returned to the device
     log("large: generating A, B (N=10, I=16384, ranks 16)")
-    d = synth.cfg4()
+    d = synth.hadamard_r256()
     A = ttr.TT.from_numpy(d["A"])
     B = ttr.TT.from_numpy(d["B"])
     tol = d["tol"]
@@ -254,8 +254,8 @@ def main():
         return
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU sharding is described in DESIGN.md but not built)", file=sys.stderr)
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
+              "(sharding over several GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -278,7 +278,7 @@ def main():
     N, r = 16, 20
     log(f"generating A, B: N={N}, I={args.I}, ranks {r} (host, seeded)")
     t = time.perf_counter()
-    d = synth.cfg1(I_override=args.I)
+    d = synth.sum_r40(I_override=args.I)
     log(f"  generated in {time.perf_counter() - t:.1f} s; uploading")
     A = ttr.TT.from_numpy(d["A"])
     B = ttr.TT.from_numpy(d["B"])

@@ -25,8 +25,7 @@ column-major views of the same buffer:
 
 The helpers ``H``/``V`` below realise exactly those reshapes (order='F').
 
-Readings of points the paper leaves open are listed in the design doc and are
-repeated where they are used:
+Readings of points the paper leaves open (repeated where they are used):
 
 * R1  "epsilon-truncated SVD" = smallest rank whose Frobenius tail is <= the
       threshold (the only reading under which Alg. 2's guarantee follows from

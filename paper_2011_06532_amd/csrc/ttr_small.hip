@@ -6,8 +6,7 @@
 //     realized with eigendecompositions.  For a tall-skinny unfolding A
 //     (accessed only through streaming passes) it yields B (b x k) and R
 //     (k x b) with A*B column-orthonormal and A = (A*B) R to rounding error.
-//     This plays the role of the tall-skinny QR of §3.3 (TSQR) in Alg. 5/6;
-//     see the design doc for the derivation and accuracy argument.
+//     This plays the role of the tall-skinny QR of §3.3 (TSQR) in Alg. 5/6.
 //   * k_trunc_step: SVD of R, truncation rank with the Frobenius-tail rule and
 //     threshold delta = tol ||X|| / sqrt(N-1) (Alg. 2), the right factor that
 //     produces the output core (U-hat, §2.4) and the matrix Sigma-hat V-hat^T

@@ -86,20 +86,20 @@ WORKLOADS = {
 TOL = {0: 1e-10, 1: 1e-8, 2: 1e-8, 3: 1e-7, 4: 1e-6}
 
 
-def cfg0(I_override: Optional[int] = None) -> Dict:
+def yy_small(I_override: Optional[int] = None) -> Dict:
     I = I_override or 64
     Y = random_tt(0, 0, "Y", [I] * 4, [5, 5, 5], scaled=False)
     return {"Y": Y, "tol": TOL[0]}
 
 
-def cfg1(I_override: Optional[int] = None, N: int = 16, r: int = 20) -> Dict:
+def sum_r40(I_override: Optional[int] = None, N: int = 16, r: int = 20) -> Dict:
     I = I_override or 262144
     A = random_tt(1, 0, "A", [I] * N, [r] * (N - 1), scaled=True)
     B = random_tt(1, 0, "B", [I] * N, [r] * (N - 1), scaled=True)
     return {"A": A, "B": B, "tol": TOL[1]}
 
 
-def cfg2(I_override: Optional[int] = None, N: int = 16) -> Dict:
+def sum_r50(I_override: Optional[int] = None, N: int = 16) -> Dict:
     I = I_override or 262144
     A = random_tt(2, 0, "A", [I] * N, [20] * (N - 1), scaled=True)
     B = random_tt(2, 0, "B", [I] * N, [20] * (N - 1), scaled=True)
@@ -107,7 +107,7 @@ def cfg2(I_override: Optional[int] = None, N: int = 16) -> Dict:
     return {"A": A, "B": B, "C": C, "tol": TOL[2]}
 
 
-def cfg3_shapes(count: int = 512, N: int = 8):
+def batched_shapes(count: int = 512, N: int = 8):
     """Per-TT mode sizes round(exp(U[ln 64, ln 4096])) and Y ranks uniform in {1..31}."""
     rng = np.random.default_rng(np.random.SeedSequence([SEED_ROOT, 3, 10**6]))
     shapes = []
@@ -118,8 +118,8 @@ def cfg3_shapes(count: int = 512, N: int = 8):
     return shapes
 
 
-def cfg3(count: int = 512, N: int = 8, I_cap: Optional[int] = None) -> Dict:
-    shapes = cfg3_shapes(count, N)
+def batched(count: int = 512, N: int = 8, I_cap: Optional[int] = None) -> Dict:
+    shapes = batched_shapes(count, N)
     Ys, Es = [], []
     for t, (I, r) in enumerate(shapes):
         if I_cap:
@@ -129,7 +129,7 @@ def cfg3(count: int = 512, N: int = 8, I_cap: Optional[int] = None) -> Dict:
     return {"Y": Ys, "E": Es, "tol": TOL[3]}
 
 
-def cfg4(I_override: Optional[int] = None, N: int = 10, r: int = 16) -> Dict:
+def hadamard_r256(I_override: Optional[int] = None, N: int = 10, r: int = 16) -> Dict:
     I = I_override or 16384
     A = random_tt(4, 0, "A", [I] * N, [r] * (N - 1), scaled=True, rank_weights=True)
     B = random_tt(4, 0, "B", [I] * N, [r] * (N - 1), scaled=True, rank_weights=True)

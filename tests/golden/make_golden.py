@@ -19,7 +19,7 @@ import synth  # noqa: E402
 
 
 def main():
-    d = synth.cfg0()
+    d = synth.yy_small()
     Y = d["Y"]
     X = O.add(1.0, Y, 1.0, Y)
     out = {}
@@ -34,7 +34,7 @@ def main():
     out["input_ranks"] = O.ranks(X)
     out["norm_gram"] = O.norm_gram(X)
     out["workload"] = synth.WORKLOADS[0]
-    with open(os.path.join(HERE, "cfg0_round.json"), "w") as f:
+    with open(os.path.join(HERE, "yy_small_round.json"), "w") as f:
         json.dump(out, f, indent=1)
 
 

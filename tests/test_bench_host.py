@@ -1,4 +1,4 @@
-"""Host-side checks of the benchmark driver and the synthetic input recipes
+"""Host-side checks of bench.py and the synthetic input recipes
 (no GPU needed)."""
 import json
 import os
@@ -36,7 +36,7 @@ def test_traffic_summary_matches_its_sources_or_is_ignored():
 
 
 def test_batched_recipe_shapes():
-    shapes = synth.cfg3_shapes(512)
+    shapes = synth.batched_shapes(512)
     assert len(shapes) == 512
     for I, r in shapes:
         assert len(I) == 8 and len(r) == 7

@@ -13,10 +13,10 @@ import synth
 HERE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
-def test_cfg0_fixture():
-    g = json.load(open(os.path.join(HERE, "cfg0_round.json")))
+def test_yy_small_fixture():
+    g = json.load(open(os.path.join(HERE, "yy_small_round.json")))
     assert g["input_ranks"] == [1, 10, 10, 10, 1]
-    d = synth.cfg0()
+    d = synth.yy_small()
     X = O.add(1.0, d["Y"], 1.0, d["Y"])
     for direction in ("RLR", "LRL"):
         Xt, info = O.round_tt(X, d["tol"], direction, return_info=True)

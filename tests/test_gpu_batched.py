@@ -24,7 +24,7 @@ def h(ttr):
 
 
 def batch_inputs(count, I_cap, start=0):
-    shapes = synth.cfg3_shapes(512)
+    shapes = synth.batched_shapes(512)
     Xs, rs = [], []
     for t in range(start, start + count):
         I, r = shapes[t]

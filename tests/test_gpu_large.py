@@ -92,7 +92,7 @@ def test_hadamard_workload_full_N_reduced_I(ttr, h):
     # the Hadamard-then-round workload at its full N = 10 and ranks 16 x 16 -> 256,
     # with I = 96 instead of 16384 so that the oracle stays within seconds
     print("hadamard workload N=10 I=96 tol 1e-6", flush=True)
-    d = synth.cfg4(I_override=96)
+    d = synth.hadamard_r256(I_override=96)
     Xg = h.hadamard(ttr.TT.from_numpy(d["A"]), ttr.TT.from_numpy(d["B"]))
     X = Xg.to_numpy()
     got, ref = check_round(ttr, h, X, d["tol"], "RLR", sig_rtol=1e-6, norm_rtol=1e-10)

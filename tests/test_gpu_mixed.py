@@ -45,9 +45,9 @@ def run(ttr, h, X, tol, direction, orth=ORTH_MIXED):
 
 
 @pytest.mark.parametrize("direction", ["RLR", "LRL"])
-def test_mixed_cfg0_y_plus_y(ttr, h, direction):
-    print(f"mixed cfg0 Y+Y {direction}", flush=True)
-    d = synth.cfg0()
+def test_mixed_yy_small_y_plus_y(ttr, h, direction):
+    print(f"mixed yy_small Y+Y {direction}", flush=True)
+    d = synth.yy_small()
     Y = d["Y"]
     X = O.add(1.0, Y, 1.0, Y)
     got, ref, _ = run(ttr, h, X, d["tol"], direction)
@@ -55,9 +55,9 @@ def test_mixed_cfg0_y_plus_y(ttr, h, direction):
 
 
 @pytest.mark.parametrize("direction", ["RLR", "LRL"])
-def test_mixed_cfg1_shape(ttr, h, direction):
+def test_mixed_sum_r40_shape(ttr, h, direction):
     print(f"mixed A+B N=16 I=512 {direction}", flush=True)
-    d = synth.cfg1(I_override=512)
+    d = synth.sum_r40(I_override=512)
     X = O.add(1.0, d["A"], 1.0, d["B"])
     got, ref, prof = run(ttr, h, X, d["tol"], direction)
     assert O.ranks(got)[1:-1] == [40] * 15
@@ -66,11 +66,11 @@ def test_mixed_cfg1_shape(ttr, h, direction):
 
 
 @pytest.mark.parametrize("direction", ["RLR", "LRL"])
-def test_mixed_cfg2_shape(ttr, h, direction):
+def test_mixed_sum_r50_shape(ttr, h, direction):
     # A + B + 1e-6 C: FP32 cannot resolve the 1e-6 part (sigma^2 ~ 1e-12), the
     # FP64 refinement pass on the materialized core recovers it
     print(f"mixed A+B+1e-6C N=16 I=400 {direction}", flush=True)
-    d = synth.cfg2(I_override=400)
+    d = synth.sum_r50(I_override=400)
     X = O.add(1.0, O.add(1.0, d["A"], 1.0, d["B"]), 1.0, d["C"])
     got, ref, prof = run(ttr, h, X, d["tol"], direction)
     assert O.ranks(got)[1:-1] == [50] * 15
@@ -82,8 +82,8 @@ def test_mixed_cfg2_shape(ttr, h, direction):
 
 
 @pytest.mark.parametrize("direction", ["RLR", "LRL"])
-def test_mixed_cfg3_members(ttr, h, direction):
-    shapes = synth.cfg3_shapes(512)
+def test_mixed_batched_members(ttr, h, direction):
+    shapes = synth.batched_shapes(512)
     for t in (0, 1, 7, 100):
         I, r = shapes[t]
         print(f"mixed Y+Y+E member {t} I={I} r={r} {direction}", flush=True)

@@ -60,9 +60,9 @@ def orthonormality(cores, direction):
 
 
 @pytest.mark.parametrize("direction", ["RLR", "LRL"])
-def test_round_cfg0_y_plus_y(ttr, h, direction):
-    print(f"round cfg0 Y+Y {direction}", flush=True)
-    d = synth.cfg0()
+def test_round_yy_small_y_plus_y(ttr, h, direction):
+    print(f"round yy_small Y+Y {direction}", flush=True)
+    d = synth.yy_small()
     Y = d["Y"]
     X = O.add(1.0, Y, 1.0, Y)
     got, ref = check_round(ttr, h, X, d["tol"], direction)
@@ -82,20 +82,20 @@ def test_round_cfg0_y_plus_y(ttr, h, direction):
 
 
 @pytest.mark.parametrize("direction", ["RLR", "LRL"])
-def test_round_cfg1_shape_small_I(ttr, h, direction):
-    # configs[1] structure (N=16, A+B ranks 20 -> 40, scaled) at I = 512
+def test_round_sum_r40_shape_small_I(ttr, h, direction):
+    # the A+B workload's structure (N=16, ranks 20 + 20 -> 40, scaled) at I = 512
     print(f"round A+B N=16 I=512 {direction}", flush=True)
-    d = synth.cfg1(I_override=512)
+    d = synth.sum_r40(I_override=512)
     X = O.add(1.0, d["A"], 1.0, d["B"])
     got, ref = check_round(ttr, h, X, d["tol"], direction)
     assert O.ranks(got)[1:-1] == [40] * 15
 
 
 @pytest.mark.parametrize("direction", ["RLR", "LRL"])
-def test_round_cfg2_shape_small_I(ttr, h, direction):
-    # configs[2] structure: A + B + 1e-6 C (ranks 50) at I = 400
+def test_round_sum_r50_shape_small_I(ttr, h, direction):
+    # the A + B + 1e-6 C workload's structure (ranks 50) at I = 400
     print(f"round A+B+1e-6C N=16 I=400 {direction}", flush=True)
-    d = synth.cfg2(I_override=400)
+    d = synth.sum_r50(I_override=400)
     X = O.add(1.0, O.add(1.0, d["A"], 1.0, d["B"]), 1.0, d["C"])
     h.set_profiling(True)
     got, ref = check_round(ttr, h, X, d["tol"], direction, sig_rtol=1e-6)
@@ -116,9 +116,9 @@ def test_round_cfg2_shape_small_I(ttr, h, direction):
 
 
 @pytest.mark.parametrize("direction", ["RLR", "LRL"])
-def test_round_cfg3_members(ttr, h, direction):
+def test_round_batched_members(ttr, h, direction):
     # a few members of the batched workload (Y + Y + 1e-9 E), full size
-    shapes = synth.cfg3_shapes(512)
+    shapes = synth.batched_shapes(512)
     for t in (0, 1, 7, 100):
         I, r = shapes[t]
         print(f"round Y+Y+E member {t} I={I} r={r} {direction}", flush=True)

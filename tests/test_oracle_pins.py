@@ -122,8 +122,8 @@ def test_thin_qr_rank_drop():
 
 # ---------------------------------------------------------------- P1: Y + Y rounds to 2Y
 @pytest.mark.parametrize("direction", ["RLR", "LRL"])
-def test_round_y_plus_y_is_2y_cfg0(direction):
-    d = synth.cfg0()
+def test_round_y_plus_y_is_2y_yy_small(direction):
+    d = synth.yy_small()
     Y = d["Y"]
     X = O.add(1.0, Y, 1.0, Y)
     assert O.ranks(X) == [1, 10, 10, 10, 1]
