@@ -38,6 +38,8 @@ Readings of points the paper leaves open (repeated where they are used):
 * R5  Alg. 2 is RLR (right-orthonormalize, truncate left to right); LRL is its
       mirror image.
 * R9  sum: X-block first; Hadamard: standard Kronecker index a_x * R^Y + a_y.
+* R17 the pivoted Cholesky of the symmetric norm stops at pivots of at most
+      d u times the largest diagonal entry (LAPACK's xPSTRF default).
 """
 
 from __future__ import annotations
@@ -51,7 +53,7 @@ TT = List[np.ndarray]
 
 __all__ = [
     "H", "V", "from_H", "from_V", "ranks", "dims", "tt_bytes",
-    "add", "hadamard", "dot", "norm_gram", "norm_ortho",
+    "add", "hadamard", "dot", "norm_gram", "norm_gram_sym", "pivoted_cholesky", "norm_ortho",
     "orthogonalize", "round_tt", "choose_rank",
     "full", "entry", "tt_svd", "diff_norm", "copy_tt",
 ]
@@ -201,6 +203,64 @@ def norm_gram(X: TT) -> float:
     """
     v = dot(X, X)
     return math.sqrt(max(v, 0.0))
+
+
+def pivoted_cholesky(W: np.ndarray, rel_tol: float | None = None):
+    """Pivoted Cholesky of a symmetric positive semi-definite W (§3.2.4 names it
+    as the triangular factorization of the inner-product matrices).
+
+    Diagonal pivoting: step j moves the largest remaining diagonal entry of the
+    Schur complement to position j (first one among ties), takes its square
+    root as L(j, j), scales the column below it and subtracts the rank-one
+    update.  It stops when that entry is at most ``rel_tol`` times the largest
+    diagonal entry of W (LAPACK's xPSTRF default ``d * u`` when None; reading
+    R17), or is not positive.  Returns ``(perm, L)`` with L (d x k) lower
+    trapezoidal and ``W[perm][:, perm] ~= L L^T``, i.e. W = P L L^T P^T with
+    P[perm[j], j] = 1.
+    """
+    W = np.array(W, dtype=np.float64)
+    d = W.shape[0]
+    if rel_tol is None:
+        rel_tol = d * (np.finfo(np.float64).eps / 2)
+    A = W.copy()
+    perm = list(range(d))
+    dmax0 = max(np.max(np.diag(A)), 0.0) if d else 0.0
+    k = d
+    for j in range(d):
+        p = j + int(np.argmax(np.diag(A)[j:]))
+        if not (A[p, p] > rel_tol * dmax0):
+            k = j
+            break
+        if p != j:
+            A[[j, p], :] = A[[p, j], :]
+            A[:, [j, p]] = A[:, [p, j]]
+            perm[j], perm[p] = perm[p], perm[j]
+        A[j, j] = math.sqrt(A[j, j])
+        A[j + 1:, j] /= A[j, j]
+        A[j + 1:, j + 1:] -= np.outer(A[j + 1:, j], A[j + 1:, j])
+    L = np.tril(A[:, :k])
+    return np.array(perm, dtype=np.int64), L
+
+
+def norm_gram_sym(X: TT) -> float:
+    """||X|| = sqrt(W_N) by the symmetric form of the inner-product recursion
+    (first approach of §3.2.4 with its structure exploited).
+
+    W_1 = V(X_1)^T V(X_1).  For n >= 2, W_{n-1} = P L L^T P^T (pivoted
+    Cholesky), H(Z_n) = L^T (P^T H(X_n)) and W_n = V(Z_n)^T V(Z_n), which
+    equals sum_i X_n(i)^T W_{n-1} X_n(i).  Like ``norm_gram`` it cancels for
+    small norms of difference tensors; a negative residue is clamped to zero.
+    """
+    _check(X)
+    W = V(X[0]).T @ V(X[0])
+    for n in range(1, len(X)):
+        r0, In, r1 = X[n].shape
+        perm, L = pivoted_cholesky(W)
+        k = L.shape[1]
+        Hz = L.T @ H(X[n])[perm, :]          # P^T H(X_n) selects rows perm[0], perm[1], ...
+        Z = from_H(Hz, k, In, r1)
+        W = V(Z).T @ V(Z)
+    return math.sqrt(max(float(W[0, 0]), 0.0))
 
 
 # ---------------------------------------------------------------------------

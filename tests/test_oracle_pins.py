@@ -76,7 +76,63 @@ def test_dot_and_norms_match_full(I, r):
     assert abs(O.dot(X, Y) - np.sum(fx * fy)) <= 1e-12 * np.linalg.norm(fx) * np.linalg.norm(fy)
     n = np.linalg.norm(fx)
     assert abs(O.norm_gram(X) - n) <= 1e-12 * n
+    assert abs(O.norm_gram_sym(X) - n) <= 1e-12 * n
     assert abs(O.norm_ortho(X) - n) <= 1e-13 * n
+
+
+# ---------------------------------------------------------------- symmetric inner-product norm
+@pytest.mark.parametrize("d,r", [(1, 1), (6, 6), (9, 4), (20, 20), (24, 7), (5, 0)])
+def test_pivoted_cholesky_factors(d, r):
+    rng = np.random.default_rng(40 + d + r)
+    B = rng.standard_normal((d, r)) * np.logspace(0, -3, r) if r else np.zeros((d, 0))
+    W = B @ B.T
+    perm, L = O.pivoted_cholesky(W)
+    k = L.shape[1]
+    assert sorted(perm.tolist()) == list(range(d))
+    assert k == r                                    # numerical rank of a rank-r PSD matrix
+    assert np.array_equal(L, np.tril(L))
+    dg = np.diag(L[:k, :k])
+    assert np.all(dg > 0) and np.all(np.diff(dg) <= 1e-12 * max(dg[0] if k else 1.0, 1e-300))
+    Wp = W[perm][:, perm]
+    assert np.linalg.norm(Wp - L @ L.T) <= 1e-13 * max(np.linalg.norm(W), 1e-300)
+    if 0 < r == d:
+        # with the pivot order fixed, the Cholesky factor is unique: LAPACK's
+        assert np.allclose(L, np.linalg.cholesky(Wp), rtol=0, atol=1e-12 * np.sqrt(np.max(np.diag(W))))
+
+
+def test_norm_sym_rank_deficient_and_degenerate():
+    rng = np.random.default_rng(44)
+    Y = rand_tt(rng, [5, 6, 4, 7], [3, 4, 2])
+    n = np.linalg.norm(O.full(Y))
+    X = O.add(1.0, Y, 1.0, Y)                        # every W_n has rank R_n / 2
+    assert abs(O.norm_gram_sym(X) - 2 * n) <= 1e-12 * n
+    D = O.add(1.0, Y, -1.0, Y)                       # zero tensor in rank-8 form: cancellation level
+    assert O.norm_gram_sym(D) <= 1e-6 * n
+    Z = [np.zeros_like(c) for c in Y]                # zero cores: W_n = 0, empty factors
+    assert O.norm_gram_sym(Z) == 0.0
+    one = rand_tt(rng, [7], [])                      # N = 1
+    assert abs(O.norm_gram_sym(one) - np.linalg.norm(one[0])) <= 1e-14 * np.linalg.norm(one[0])
+
+
+def test_norm_sym_planted_mistakes_fail():
+    rng = np.random.default_rng(45)
+    X = rand_tt(rng, [4, 5, 3, 6], [3, 4, 2])
+    n = np.linalg.norm(O.full(X))
+
+    def variant(slip):
+        W = O.V(X[0]).T @ O.V(X[0])
+        for m in range(1, len(X)):
+            r0, In, r1 = X[m].shape
+            perm, L = O.pivoted_cholesky(W)
+            Hx = O.H(X[m]) if slip == "no_perm" else O.H(X[m])[perm, :]
+            F = L if slip == "L_not_LT" else L.T
+            Z = O.from_H(F @ Hx, L.shape[1], In, r1)
+            W = O.V(Z).T @ O.V(Z)
+        return math.sqrt(max(W[0, 0], 0.0))
+
+    assert abs(variant(None) - n) <= 1e-12 * n
+    assert abs(variant("no_perm") - n) > 1e-6 * n
+    assert abs(variant("L_not_LT") - n) > 1e-6 * n
 
 
 def test_rank_one_closed_forms():
