@@ -241,6 +241,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision rounds")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched rounding of 512 tensors")
     ap.add_argument("--no-large", action="store_true", help="skip the Hadamard -> rank-256 rounding")
+    ap.add_argument("--no-norms", action="store_true", help="skip the timing of the three norm methods")
     ap.add_argument("--leg", default="all", choices=["all", "batched", "large"],
                     help="batched / large: run only that leg (for profiling) and print its JSON object")
     ap.add_argument("--no-per-tensor", action="store_true",
@@ -358,6 +359,34 @@ def main():
                  "entries_sampled": int(idx.shape[0])}
         del Ym
 
+    # the three norm methods of §3.2.4 on the same X: inner product (GRAM),
+    # its symmetric form (SYM) and orthonormalization (ORTHO)
+    norms = None
+    if not args.no_norms:
+        log("norm methods")
+        norms = {}
+        for meth in ("gram", "sym", "ortho"):
+            h.norm(Xbuf, meth)
+            torch.cuda.synchronize()
+            h.set_profiling(True)
+            evn = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                   for _ in range(args.steps)]
+            vals = []
+            for k in range(args.steps):
+                evn[k][0].record(stream)
+                vals.append(h.norm(Xbuf, meth))
+                evn[k][1].record(stream)
+            torch.cuda.synchronize()
+            pn = h.profile()
+            h.set_profiling(False)
+            ms_n = sum(a.elapsed_time(b) for a, b in evn) / args.steps
+            norms[meth] = {"ms": round(ms_n, 3), "core_GBps": round(size_x / (ms_n * 1e-3) / 1e9, 2),
+                           "norm": vals[-1],
+                           "kernel_ms": {c: round(pn[c]["ms"] / args.steps, 3) for c in pn if pn[c]["count"]}}
+        ref_n = norms["ortho"]["norm"]
+        for meth in norms:
+            norms[meth]["rel_diff_vs_ortho"] = abs(norms[meth]["norm"] - ref_n) / ref_n
+
     # dominant kernel by time
     cls = max((c for c in prof if c != "small"), key=lambda c: prof[c]["ms"])
     p = prof[cls]
@@ -408,6 +437,8 @@ def main():
     }
     if mixed:
         out["mixed"] = mixed
+    if norms:
+        out["norms"] = norms
     if not args.no_batched:
         del A, B, Xbuf, Ybuf, X, Y, Yf
         torch.cuda.empty_cache()

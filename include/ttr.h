@@ -51,7 +51,7 @@ enum ttr_status {
 
 enum { TTR_RIGHT = 0, TTR_LEFT = 1 };             /* orthonormalization side (§2.3) */
 enum { TTR_RLR = 0, TTR_LRL = 1 };                 /* rounding sweep order (§4.3.2) */
-enum { TTR_NORM_ORTHO = 0, TTR_NORM_GRAM = 1 };    /* norm method (§3.2.4) */
+enum { TTR_NORM_ORTHO = 0, TTR_NORM_GRAM = 1, TTR_NORM_SYM = 2 };    /* norm method (§3.2.4) */
 enum { TTR_FP64 = 0, TTR_MIXED = 1 };              /* arithmetic of the Gram passes */
 
 /* Largest TT rank of the matrix-core tiled kernels (every entry point). */
@@ -113,9 +113,13 @@ int ttr_hadamard(ttr_handle *h, const ttr_tt *X, const ttr_tt *Y, ttr_tt *Z);
 int ttr_dot(ttr_handle *h, const ttr_tt *X, const ttr_tt *Y, double *out);
 
 /* *out = ||X|| (§3.2.4).  TTR_NORM_GRAM: sqrt(<X, X>) (fast; cancellation for
- * small norms of difference tensors).  TTR_NORM_ORTHO: right-orthonormalization
- * sweep (implicit, X untouched) then ||X_1||_F (§2.3; accurate for small
- * norms).  Synchronizes. */
+ * small norms of difference tensors).  TTR_NORM_SYM: the same quantity with the
+ * symmetry of the inner-product matrices exploited: W_n = V(Z_n)^T V(Z_n) with
+ * Z_n(i) = F X_n(i) and F^T F = W_{n-1} from a pivoted Cholesky (§3.2.4), made
+ * upper triangular so half of each product is skipped; same cancellation as
+ * GRAM.  TTR_NORM_ORTHO: right-orthonormalization sweep (implicit, X
+ * untouched) then ||X_1||_F (§2.3; accurate for small norms).  Ranks <= 64.
+ * Non-finite data give NaN.  Synchronizes. */
 int ttr_norm(ttr_handle *h, const ttr_tt *X, int method, double *out);
 
 /* In-place orthonormalization (§2.3 Alg. 1; explicit factors as in §3.4 Alg. 5).
@@ -205,7 +209,7 @@ int ttr_get_round_stats(const ttr_handle *h, ttr_round_stats *out);
  *   2 k_gram               staged generic Gram pass (longer factor chains)
  *   3 k_apply_mfma         output pass, matrix cores
  *   4 k_apply              staged generic output pass
- *   5 k_add  6 k_hadamard  7 k_dot_step  8 small one-workgroup kernels
+ *   5 k_add  6 k_hadamard  7 k_dot (inner-product steps)  8 small one-workgroup kernels
  *   9 k_gram_fac           refinement Gram pass on a materialized core
  *  10 k_apply_fac2         output pass with two right factors (refined core)
  *  11 k_gram_right_factor  as 0, FP32 matrix cores (TTR_MIXED first pass)

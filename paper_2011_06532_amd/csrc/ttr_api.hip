@@ -788,8 +788,14 @@ int ttr_dot(ttr_handle *h, const ttr_tt *X, const ttr_tt *Y, double *out) {
       const double rx0 = X->R[n], rx1 = X->R[n + 1], ry0 = Y->R[n], ry1 = Y->R[n + 1];
       ProfScope ps(h, P_DOT, 8.0 * X->I[n] * (rx0 * rx1 + ry0 * ry1),
                    2.0 * X->I[n] * (ry0 * rx0 * rx1 + ry1 * ry0 * rx1));
-      launch_dot_step(h->stream, X->core[n], (int)X->R[n], (int)X->R[n + 1], Y->core[n], (int)Y->R[n],
-                      (int)Y->R[n + 1], X->I[n], Wp, w.partials, Wn);
+      if (g_use_mfma) {
+        const int nwg = launch_dot_mfma(h->stream, X->core[n], (int)X->R[n], (int)X->R[n + 1], Y->core[n],
+                                        (int)Y->R[n], (int)Y->R[n + 1], X->I[n], Wp, w.partials);
+        launch_reduce(h->stream, w.partials, nwg, (int)(Y->R[n + 1] * X->R[n + 1]), Wn);
+      } else {
+        launch_dot_step(h->stream, X->core[n], (int)X->R[n], (int)X->R[n + 1], Y->core[n], (int)Y->R[n],
+                        (int)Y->R[n + 1], X->I[n], Wp, w.partials, Wn);
+      }
     }
     std::swap(Wp, Wn);
   }
@@ -808,7 +814,33 @@ int ttr_norm(ttr_handle *h, const ttr_tt *X, int method, double *out) {
   if (method == TTR_NORM_GRAM) {
     double v;
     if ((rc = ttr_dot(h, X, X, &v))) return rc;
-    *out = v > 0 ? std::sqrt(v) : 0.0;
+    *out = v > 0 ? std::sqrt(v) : (v == v ? 0.0 : v);
+    return TTR_OK;
+  }
+  if (method == TTR_NORM_SYM) {
+    // W_1 = V(X_1)^T V(X_1); W_n = V(Z_n)^T V(Z_n) with Z_n(i) = F_{n-1} X_n(i)
+    // and F_{n-1} upper triangular, F^T F = W_{n-1} (§3.2.4, symmetric form):
+    // the streaming Gram kernel skips the zero half of F, the Gram itself is
+    // formed on the lower block triangle only
+    if ((rc = check_tt(X, "X", TTR_MAX_RANK))) return rc;
+    const int N = X->N;
+    if ((rc = ensure_ws(h, ws_doubles(N, 0) * sizeof(double)))) return rc;
+    WS w = carve(h, N, 0);
+    const Seq S{X, 0};
+    double *Fbuf[2] = {w.Pa, w.Pb};
+    for (int n = 0; n < N; ++n) {
+      const CoreView cv = S.view(n);
+      Stages st = no_stages();
+      if (n > 0) st.L[st.nl++] = st_plain(Fbuf[(n - 1) & 1], cv.pa, cv.pa, 2);
+      gram(h, w.partials, w.G, cv, st, GRAM_RIGHT);
+      if (n + 1 < N) launch_sym_factor(h->stream, w.G, cv.pb, Fbuf[n & 1]);
+    }
+    launch_sqrt_scalar(h->stream, w.G, w.scal);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(h->scal_host, w.scal, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    *out = h->scal_host[0];
+    prof_resolve(h);
     return TTR_OK;
   }
   if (method != TTR_NORM_ORTHO) return fail(TTR_ERR_INVALID_ARG, "unknown norm method");

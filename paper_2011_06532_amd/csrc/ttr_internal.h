@@ -84,6 +84,11 @@ void launch_apply_fac2(hipStream_t s, const double *X, int a, int b, long long I
                        long long s2c, double *Y);
 void launch_dot_step(hipStream_t s, const double *X, int rx0, int rx1, const double *Y, int ry0, int ry1,
                      long long I, const double *Wp, double *partials, double *W);
+// The same step on the FP64 matrix cores: partial W_n (e x b, ld e) of each
+// workgroup into `partials`; returns the workgroup count (launch_reduce sums
+// them).  All ranks <= TTR_RMAX; X's slices a x b, Y's c x e, W (c x a, ld c).
+int launch_dot_mfma(hipStream_t s, const double *X, int a, int b, const double *Y, int c, int e, long long I,
+                    const double *W, double *partials);
 
 // --- small dense kernels (ttr_small.hip) ----------------------------------
 // One step of QR-by-Gram.  G (d x d) is the Gram of the current staged
@@ -208,4 +213,7 @@ void launch_qr_step_batched(hipStream_t s, int count, const QrStepArgs *args, co
 void launch_trunc_step_batched(hipStream_t s, int count, const TruncArgs *args, const int *active);
 void launch_small_gemm_batched(hipStream_t s, int count, const SmallGemmArgs *args, const int *active);
 // Square root of a 1x1 device value into out (for norms).
+// F (d x d, ld d): upper triangular with F^T F = G (pivoted Cholesky, then a
+// Householder QR of L^T P^T), zero rows past the numerical rank; d <= TTR_RMAX.
+void launch_sym_factor(hipStream_t s, const double *G, int d, double *F);
 void launch_sqrt_scalar(hipStream_t s, const double *in, double *out);

@@ -497,6 +497,103 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NT <= 
 }
 
 // ---------------------------------------------------------------------------
+// One step of the inner-product recursion (§3.2.3, eq. (4)):
+//   W_n (e x b) = sum_i Y_i^T (W_{n-1} X_i),
+// X_i the a x b slices of X_n, Y_i the c x e slices of Y_n, W_{n-1} (c x a).
+// Per slice and 16-row band of Z_i = W_{n-1} X_i (rows = c): the band's result
+// registers are the B-operand fragments of the k-steps of Y_i^T Z_i over that
+// band, and Y_i is read straight into the matching A-operand layout, so the two
+// contractions chain with no LDS round trip.  KS = k-steps over a.
+// ---------------------------------------------------------------------------
+template <int NT>
+__device__ void reduce_full(const d4 (&G)[NT][NT], int rows, int cols, double *Gs, double *out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, j = lane & 15;
+  for (int e = threadIdx.x; e < rows * cols; e += blockDim.x) Gs[e] = 0.0;
+  __syncthreads();
+  for (int w = 0; w < kWaves; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int u = 0; u < NT; ++u)
+#pragma unroll
+        for (int v = 0; v < NT; ++v)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = u * 16 + F64::row(g, r), col = v * 16 + j;
+            if (row < rows && col < cols) Gs[row + rows * col] += G[u][v][r];
+          }
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < rows * cols; e += blockDim.x) out[e] = Gs[e];
+}
+
+template <int NT, int KS>
+__global__ __launch_bounds__(kThreads) void k_dot_mfma(const double *__restrict__ X, int a, int b,
+                                                       const double *__restrict__ Y, int c, int e, long long I,
+                                                       const double *__restrict__ W, long long spw,
+                                                       double *__restrict__ partials) {
+  constexpr int KP = (KS + 1) & ~1;  // k-steps over a in pair order
+  __shared__ double frag[NT * KP * 64];
+  __shared__ double Gs[NT * 16 * NT * 16];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, j = lane & 15;
+  const int ntb = (b + 15) / 16, nte = (e + 15) / 16, ntc = (c + 15) / 16;
+  const bool v2 = ((a & 1) == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
+  build_afrag_pairs<double>(frag, W, c, a, 1, c, NT, KP);
+  __syncthreads();
+  d4 acc[NT][NT];  // [e-tile][b-tile]
+#pragma unroll
+  for (int u = 0; u < NT; ++u)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[u][t] = d4{0, 0, 0, 0};
+  const long long beg = (long long)blockIdx.x * spw;
+  const long long end = std::min(beg + spw, I);
+  const long long xcol = (long long)a * I, ycol = (long long)c * I;
+  for (long long i = beg + wave; i < end; i += kWaves) {
+    double xs[KP][NT];
+    if (v2) load_slice_pairs<NT, KP, true>(X + (long long)a * i, xcol, a, b, g, j, xs);
+    else load_slice_pairs<NT, KP, false>(X + (long long)a * i, xcol, a, b, g, j, xs);
+    const double *Yi = Y + (long long)c * i;
+#pragma unroll
+    for (int rb = 0; rb < NT; ++rb) {
+      if (rb >= ntc) continue;
+      // the band's rows of Y_i, issued before the band's first product:
+      // yb[r][u] = Y_i(16 rb + 4 r + g, 16 u + j)
+      double yb[4][NT];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+          const int cr = 16 * rb + 4 * r + g, ce = 16 * u + j;
+          yb[r][u] = (cr < c && ce < e) ? Yi[cr + ycol * ce] : 0.0;
+        }
+      d4 z[NT];  // Z_i(16 rb + row(g, r), 16 t + j)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) z[t] = d4{0, 0, 0, 0};
+#pragma unroll
+      for (int ks = 0; ks < KP; ++ks) {
+        if (8 * (ks >> 1) >= a) continue;
+        const double wa = frag[(rb * KP + ks) * 64 + lane];
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+          if (t < ntb) z[t] = mfma(wa, xs[ks][t], z[t]);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (rb * 16 + 4 * r >= c) continue;
+#pragma unroll
+        for (int u = 0; u < NT; ++u)
+#pragma unroll
+          for (int t = 0; t < NT; ++t)
+            if (u < nte && t < ntb) acc[u][t] = mfma(yb[r][u], z[t][r], acc[u][t]);
+      }
+    }
+  }
+  reduce_full<NT>(acc, e, b, Gs, partials + (long long)blockIdx.x * e * b);
+}
+
+// ---------------------------------------------------------------------------
 // Output pass: Y_i = P M_i Q (p x q) written as a p x I x q core.  P == nullptr
 // means the identity (p = a); Q == nullptr means the identity (q = b).
 // KS = k-steps over b.  Two waves share each SIMD (NT <= 3, and NT = 4 at
@@ -953,6 +1050,18 @@ int launch_gram_left_factor(hipStream_t s, const double *X, int a, int b, long l
       TTR_LAUNCH(k_gram_left_factor<NTV, KSV, F64, true>) X, a, b, I, P, p, sPr, sPa, tri, gr.spw, partials, Yout);
     else
       TTR_LAUNCH(k_gram_left_factor<NTV, KSV, F64>) X, a, b, I, P, p, sPr, sPa, tri, gr.spw, partials, nullptr);
+  });
+  return gr.nwg;
+}
+
+int launch_dot_mfma(hipStream_t s, const double *X, int a, int b, const double *Y, int c, int e, long long I,
+                    const double *W, double *partials) {
+  const Grid gr = grid_of(I);
+  const int nt = std::max({tiles_for(a), tiles_for(b), tiles_for(c), tiles_for(e)});
+  const int ks = std::max((a + 3) / 4, 4 * nt - 3);
+  nt_ks(nt, ks, [&](auto NTc, auto KSc) {
+    constexpr int NTV = decltype(NTc)::value, KSV = decltype(KSc)::value;
+    TTR_LAUNCH(k_dot_mfma<NTV, KSV>) X, a, b, Y, c, e, I, W, gr.spw, partials);
   });
   return gr.nwg;
 }

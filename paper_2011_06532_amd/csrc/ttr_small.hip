@@ -925,7 +925,73 @@ __device__ void small_gemm_body(const double *A, const double *B, double *C, int
   }
 }
 
+// ---------------------------------------------------------------------------
+// Factor of the symmetric inner-product norm (§3.2.4).  G (d x d, symmetric
+// positive semi-definite, ld d) -> F (d x d, ld d) upper triangular with
+// F^T F = G to rounding error and zero rows past the numerical rank k.
+// Pivoted Cholesky gives G = P L L^T P^T (stopping at pivots <= d u max G_jj);
+// B = L^T P^T (k x d) then has B^T B = G, and Householder QR of B, B = Q F,
+// turns it into the upper-trapezoidal F with the same F^T F.  The triangle is
+// what lets the streaming pass skip the zero half of F X_n(i).  Non-finite G
+// gives an all-NaN F, so the norm comes out NaN.
+// ---------------------------------------------------------------------------
+__device__ void sym_factor_body(const double *__restrict__ G, int d, double *__restrict__ F) {
+  __shared__ double A[TTR_RMAX * TTR_RMAX];
+  __shared__ double Bm[TTR_RMAX * TTR_RMAX];
+  __shared__ double vh[TTR_RMAX];
+  __shared__ int perm[TTR_RMAX];
+  __shared__ double hbeta;
+  double bad = 0.0;
+  for (int e = threadIdx.x; e < d * d; e += blockDim.x) {
+    const double g = G[e];
+    A[e] = g;
+    if (!finite(g)) bad = 1.0;
+  }
+  bad = block_max(bad);  // also the barrier after the loads
+  if (bad > 0.0) {
+    for (int e = threadIdx.x; e < d * d; e += blockDim.x) F[e] = NAN;
+    return;
+  }
+  const int k = pivoted_chol(A, d, (double)d * kU, perm);
+  // B(r, perm[j]) = L(j, r) for j >= r, else 0 (ld TTR_RMAX)
+  for (int e = threadIdx.x; e < k * d; e += blockDim.x) {
+    const int r = e % k, j = e / k;
+    Bm[r + TTR_RMAX * perm[j]] = (j >= r) ? A[j + d * r] : 0.0;
+  }
+  __syncthreads();
+  for (int j = 0; j < k; ++j) {
+    if (threadIdx.x < kWave) {
+      // reflector of column j below the diagonal: lane l holds row j + l
+      const int i = j + threadIdx.x;
+      const double x = (i < k) ? Bm[i + TTR_RMAX * j] : 0.0;
+      double ss = x * x;
+      for (int off = kWave / 2; off >= 1; off >>= 1) ss += __shfl_xor(ss, off, kWave);
+      const double x0 = __shfl(x, 0, kWave);
+      const double nx = sqrt(ss);
+      const double alpha = (x0 >= 0.0) ? -nx : nx;
+      if (i < k) vh[i] = (i == j) ? x0 - alpha : x;
+      if (threadIdx.x == 0) hbeta = (nx > 0.0) ? 1.0 / (nx * (nx + fabs(x0))) : 0.0;  // 2 / v^T v
+    }
+    __syncthreads();
+    const double beta = hbeta;
+    for (int c = j + threadIdx.x; c < d; c += blockDim.x) {
+      double sdot = 0.0;
+      for (int i = j; i < k; ++i) sdot += vh[i] * Bm[i + TTR_RMAX * c];
+      const double f = beta * sdot;
+      for (int i = j; i < k; ++i) Bm[i + TTR_RMAX * c] -= f * vh[i];
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < d * d; e += blockDim.x) {
+    const int r = e % d, c = e / d;
+    F[e] = (r < k && c >= r) ? Bm[r + TTR_RMAX * c] : 0.0;
+  }
+}
+
 __global__ __launch_bounds__(kThreadsQR) void k_qr_step(QrStepArgs a) { qr_step_body(a); }
+__global__ __launch_bounds__(kThreadsQR) void k_sym_factor(const double *G, int d, double *F) {
+  sym_factor_body(G, d, F);
+}
 __global__ __launch_bounds__(kThreads) void k_trunc_step(TruncArgs a) { trunc_step_body(a); }
 __global__ void k_small_gemm(const double *A, const double *B, double *C, int m, int k, int n) {
   small_gemm_body(A, B, C, m, k, n);
@@ -949,7 +1015,7 @@ __global__ void kb_small_gemm(const SmallGemmArgs *args, const int *active) {
 __global__ void k_sqrt_scalar(const double *in, double *out) {
   if (threadIdx.x == 0) {
     const double v = in[0];
-    out[0] = v > 0 ? sqrt(v) : 0.0;
+    out[0] = v > 0 ? sqrt(v) : (v == v ? 0.0 : v);  // rounding residue below zero -> 0; NaN stays
   }
 }
 
@@ -977,6 +1043,9 @@ void launch_small_gemm_batched(hipStream_t s, int count, const SmallGemmArgs *ar
   hipLaunchKernelGGL(kb_small_gemm, dim3(count), dim3(kThreads), 0, s, args, active);
 }
 
+void launch_sym_factor(hipStream_t s, const double *G, int d, double *F) {
+  hipLaunchKernelGGL(k_sym_factor, dim3(1), dim3(kThreadsQR), 0, s, G, d, F);
+}
 void launch_sqrt_scalar(hipStream_t s, const double *in, double *out) {
   hipLaunchKernelGGL(k_sqrt_scalar, dim3(1), dim3(64), 0, s, in, out);
 }

@@ -24,14 +24,14 @@ LIB_PATH = os.path.join(HERE, "libttr.so")
 TTR_OK = 0
 TTR_RIGHT, TTR_LEFT = 0, 1
 TTR_RLR, TTR_LRL = 0, 1
-TTR_NORM_ORTHO, TTR_NORM_GRAM = 0, 1
+TTR_NORM_ORTHO, TTR_NORM_GRAM, TTR_NORM_SYM = 0, 1, 2
 TTR_FP64, TTR_MIXED = 0, 1
 TTR_MAX_RANK = 64
 TTR_ERR_NUMERICAL = 6
 
 _DIR = {"RLR": TTR_RLR, "LRL": TTR_LRL}
 _SIDE = {"right": TTR_RIGHT, "left": TTR_LEFT}
-_NORM = {"ortho": TTR_NORM_ORTHO, "gram": TTR_NORM_GRAM}
+_NORM = {"ortho": TTR_NORM_ORTHO, "gram": TTR_NORM_GRAM, "sym": TTR_NORM_SYM}
 _PREC = {"fp64": TTR_FP64, "mixed": TTR_MIXED}
 
 # exported symbols the header declares (checked by the CPU test suite)
@@ -46,7 +46,7 @@ ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 PROF_CLASSES = ["k_gram_right_factor", "k_gram_left_factor", "k_gram", "k_apply_mfma", "k_apply", "k_add",
-                "k_hadamard", "k_dot_step", "small", "k_gram_fac", "k_apply_fac2", "k_gram_right_factor_f32",
+                "k_hadamard", "k_dot", "small", "k_gram_fac", "k_apply_fac2", "k_gram_right_factor_f32",
                 "k_gram_left_factor_f32"]
 NPROF = len(PROF_CLASSES)  # TTR_NPROF
 

@@ -86,7 +86,71 @@ def test_dot_and_norms(ttr, h, I, r):
     assert abs(h.dot(gx, gy) - ref) <= 1e-12 * scale
     n = O.norm_ortho(X)
     assert abs(h.norm(gx, "gram") - n) <= 1e-12 * n
+    assert abs(h.norm(gx, "sym") - n) <= 1e-12 * n
     assert abs(h.norm(gx, "ortho") - n) <= 1e-12 * n
+
+
+DOT_SHAPES = [
+    ([3000, 2000, 2500], [40, 33], [64, 9]),         # different tile counts on the two sides
+    ([700, 1, 800, 2], [40, 64, 5], [3, 17, 48]),
+    ([5000, 4000], [64], [64]),
+    ([257, 129, 65, 33], [1, 16, 17], [31, 2, 1]),
+]
+
+
+@pytest.mark.parametrize("I,rx,ry", DOT_SHAPES)
+def test_dot_matrix_cores(ttr, h, I, rx, ry):
+    # the inner-product steps on the matrix cores: all rank combinations up
+    # to 64, ragged slices, both argument orders
+    print(f"dot I={I} rx={rx} ry={ry}", flush=True)
+    rng = np.random.default_rng(106)
+    X = rand_tt(rng, I, rx, scale=0.2)
+    Y = rand_tt(rng, I, ry, scale=0.2)
+    gx, gy = ttr.TT.from_numpy(X), ttr.TT.from_numpy(Y)
+    ref = O.dot(X, Y)
+    scale = O.norm_ortho(X) * O.norm_ortho(Y)
+    assert abs(h.dot(gx, gy) - ref) <= 1e-12 * scale
+    assert abs(h.dot(gy, gx) - ref) <= 1e-12 * scale
+    n = O.norm_ortho(X)
+    assert abs(h.norm(gx, "gram") - n) <= 1e-12 * n
+
+
+SYM_SHAPES = [
+    ([4000, 3000, 2500, 2000], [16, 33, 64]),      # every tile count, ragged tails
+    ([700, 1, 800, 2, 600], [40, 64, 48, 12]),     # R_n > R_{n-1} I_n: singular W_2, W_3
+    ([1000, 1200], [1]),
+    ([513, 64, 257], [64, 64]),
+]
+
+
+@pytest.mark.parametrize("I,r", SYM_SHAPES)
+def test_norm_sym_matches_oracle(ttr, h, I, r):
+    # symmetric inner-product norm: pivoted Cholesky factors made triangular,
+    # the half-skipping matrix-core Gram; parity with the oracle's form and
+    # with the other two methods
+    print(f"norm sym I={I} r={r}", flush=True)
+    rng = np.random.default_rng(104)
+    X = rand_tt(rng, I, r, scale=0.1)
+    gx = ttr.TT.from_numpy(X)
+    ref = O.norm_gram_sym(X)
+    got = h.norm(gx, "sym")
+    assert abs(got - ref) <= 1e-12 * ref
+    assert abs(h.norm(gx, "gram") - ref) <= 1e-12 * ref
+    assert abs(h.norm(gx, "ortho") - ref) <= 1e-12 * ref
+
+
+def test_norm_sym_rank_deficient_and_nonfinite(ttr, h):
+    print("norm sym of Y + Y, zero and non-finite tensors", flush=True)
+    rng = np.random.default_rng(105)
+    Y = rand_tt(rng, [300, 200, 250, 100], [9, 20, 11])
+    X = O.add(1.0, Y, 1.0, Y)                       # every W_n has half rank
+    n = np.sqrt(O.dot(Y, Y))
+    assert abs(h.norm(ttr.TT.from_numpy(X), "sym") - 2 * n) <= 1e-12 * n
+    Z = [np.zeros_like(c) for c in Y]
+    assert h.norm(ttr.TT.from_numpy(Z), "sym") == 0.0
+    Y[2][4, 17, 3] = np.inf
+    assert math.isnan(h.norm(ttr.TT.from_numpy(Y), "sym"))
+    assert not math.isfinite(h.norm(ttr.TT.from_numpy(Y), "gram"))
 
 
 def test_norm_ortho_small_difference(ttr, h):
