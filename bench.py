@@ -228,6 +228,35 @@ def bench_large(h, ttr, torch, steps):
     return out
 
 
+def bench_norms(h, torch, X, size_x, steps):
+    """The three norm methods of §3.2.4 on the same resident X: the inner
+    product (gram), its symmetric form (sym) and orthonormalization (ortho)."""
+    log("norm methods")
+    stream = torch.cuda.current_stream()
+    norms = {}
+    for meth in ("gram", "sym", "ortho"):
+        h.norm(X, meth)
+        torch.cuda.synchronize()
+        h.set_profiling(True)
+        evn = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        vals = []
+        for k in range(steps):
+            evn[k][0].record(stream)
+            vals.append(h.norm(X, meth))
+            evn[k][1].record(stream)
+        torch.cuda.synchronize()
+        pn = h.profile()
+        h.set_profiling(False)
+        ms_n = sum(a.elapsed_time(b) for a, b in evn) / steps
+        norms[meth] = {"ms": round(ms_n, 3), "core_GBps": round(size_x / (ms_n * 1e-3) / 1e9, 2),
+                       "norm": vals[-1],
+                       "kernel_ms": {c: round(pn[c]["ms"] / steps, 3) for c in pn if pn[c]["count"]}}
+    ref_n = norms["ortho"]["norm"]
+    for meth in norms:
+        norms[meth]["rel_diff_vs_ortho"] = abs(norms[meth]["norm"] - ref_n) / ref_n
+    return norms
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -242,8 +271,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched rounding of 512 tensors")
     ap.add_argument("--no-large", action="store_true", help="skip the Hadamard -> rank-256 rounding")
     ap.add_argument("--no-norms", action="store_true", help="skip the timing of the three norm methods")
-    ap.add_argument("--leg", default="all", choices=["all", "batched", "large"],
-                    help="batched / large: run only that leg (for profiling) and print its JSON object")
+    ap.add_argument("--leg", default="all", choices=["all", "batched", "large", "norms"],
+                    help="batched / large / norms: run only that leg (for profiling) and print its JSON object")
     ap.add_argument("--no-per-tensor", action="store_true",
                     help="batched leg: skip the one-ttr_round-per-tensor comparison")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
@@ -270,6 +299,14 @@ def main():
     if args.leg != "all":
         if args.leg == "batched":
             res = bench_batched(h, ttr, torch, args.steps, per_tensor=not args.no_per_tensor)
+        elif args.leg == "norms":
+            d = synth.sum_r40(I_override=args.I)
+            A, B = ttr.TT.from_numpy(d["A"]), ttr.TT.from_numpy(d["B"])
+            del d
+            X = h.add(1.0, A, 1.0, B)
+            del A, B
+            res = bench_norms(h, torch, X, sum(8 * X.R[n] * X.I[n] * X.R[n + 1] for n in range(len(X.I))),
+                              args.steps)
         else:
             res = bench_large(h, ttr, torch, args.steps)
         h.close()
@@ -359,33 +396,8 @@ def main():
                  "entries_sampled": int(idx.shape[0])}
         del Ym
 
-    # the three norm methods of §3.2.4 on the same X: inner product (GRAM),
-    # its symmetric form (SYM) and orthonormalization (ORTHO)
-    norms = None
-    if not args.no_norms:
-        log("norm methods")
-        norms = {}
-        for meth in ("gram", "sym", "ortho"):
-            h.norm(Xbuf, meth)
-            torch.cuda.synchronize()
-            h.set_profiling(True)
-            evn = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                   for _ in range(args.steps)]
-            vals = []
-            for k in range(args.steps):
-                evn[k][0].record(stream)
-                vals.append(h.norm(Xbuf, meth))
-                evn[k][1].record(stream)
-            torch.cuda.synchronize()
-            pn = h.profile()
-            h.set_profiling(False)
-            ms_n = sum(a.elapsed_time(b) for a, b in evn) / args.steps
-            norms[meth] = {"ms": round(ms_n, 3), "core_GBps": round(size_x / (ms_n * 1e-3) / 1e9, 2),
-                           "norm": vals[-1],
-                           "kernel_ms": {c: round(pn[c]["ms"] / args.steps, 3) for c in pn if pn[c]["count"]}}
-        ref_n = norms["ortho"]["norm"]
-        for meth in norms:
-            norms[meth]["rel_diff_vs_ortho"] = abs(norms[meth]["norm"] - ref_n) / ref_n
+    # the three norm methods of §3.2.4 on the same X
+    norms = None if args.no_norms else bench_norms(h, torch, Xbuf, size_x, args.steps)
 
     # dominant kernel by time
     cls = max((c for c in prof if c != "small"), key=lambda c: prof[c]["ms"])
