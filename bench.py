@@ -180,7 +180,7 @@ def copy_calibration(gib):
 def bench_large(h, ttr, torch, steps):
     """Hadamard product of two random TTs (N=10, I=16384, ranks 16 with 2^-b
     rank weights) -> formal ranks 256 (68.7 GB of cores), then ttr_round at tol
-    1e-8: the rank 65..256 path."""
+    1e-6: the rank 65..256 path."""
     import synth
     torch.cuda.empty_cache()   # blocks cached by the earlier legs are returned to the device
     log("large: generating A, B (N=10, I=16384, ranks 16)")
@@ -216,7 +216,7 @@ def bench_large(h, ttr, torch, steps):
     ey = sample_entries(Y.cores, Y.R, Y.I, idx)
     ms = sum(ts) / len(ts)
     out = {"workload": "A * B (Hadamard), N=10, I=16384, A,B random TTs of rank 16 with 2^-b rank weights, "
-                       "formal ranks 256, ttr_round tol 1e-8 RLR fp64",
+                       f"formal ranks 256, ttr_round tol {tol:g} RLR fp64",
            "core_bytes_X": nbytes, "ms_hadamard": round(ms_had, 3),
            "hadamard_GBps": round(nbytes / (ms_had * 1e-3) / 1e9, 1),
            "ms_per_round": round(ms, 3), "round_core_GBps": round(nbytes / (ms * 1e-3) / 1e9, 2),

@@ -323,25 +323,20 @@ __device__ void lower_inv(const double *A, double *X, int k, int d) {
   __syncthreads();
 }
 
-// Cholesky G = L L^T of the symmetric d x d matrix in A (LDS), in place (lower
-// triangle; the strict upper part is zeroed), then L^{-1} into Vm by forward
-// substitution; both take one barrier per column.  Returns false when a pivot
-// is not positive.  With G symmetric, ||G||_2 <= ||G||_1 and
-// ||G^{-1}||_2 <= ||G^{-1}||_1 <= ||L^{-1}||_inf ||L^{-1}||_1, so
-// *kappa = ||G||_1 ||L^{-1}||_1 ||L^{-1}||_inf bounds kappa_2(G) from above and
-// *lmin_lb = 1 / min(||L^{-1}||_F^2, ||L^{-1}||_1 ||L^{-1}||_inf) bounds
-// lambda_min(G) from below.
-__device__ bool chol_inv(double *A, double *Vm, int d, double *kappa, double *lmin_lb) {
-  const double g1 = norm1(A, d);
+// Unpivoted Cholesky G = L L^T of the symmetric d x d matrix in A (LDS), in
+// place (lower triangle; the strict upper part is zeroed), one barrier per
+// column.  Returns false, with A partly overwritten, as soon as a pivot is not
+// above `thresh`.
+__device__ bool chol_lower(double *A, int d, double thresh) {
   // threads as 16 rows x (blockDim/16) columns of the trailing updates
   const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4, nc = blockDim.x >> 4;
-  // Cholesky, one barrier per column: step j updates the trailing lower
-  // triangle with the unscaled column j (L(r,j) L(c,j) = A(r,j) A(c,j) / A(j,j))
-  // and scales column j-1, which no thread reads during step j
+  // step j updates the trailing lower triangle with the unscaled column j
+  // (L(r,j) L(c,j) = A(r,j) A(c,j) / A(j,j)) and scales column j-1, which no
+  // thread reads during step j
   double lprev = 0.0;
   for (int j = 0; j < d; ++j) {
     const double pv = A[j + d * j];
-    if (!(pv > 0.0)) return false;  // the same value in every thread
+    if (!(pv > thresh)) return false;  // the same value in every thread
     if (j > 0)
       for (int r = j - 1 + threadIdx.x; r < d; r += blockDim.x)
         A[r + d * (j - 1)] = (r == j - 1) ? lprev : A[r + d * (j - 1)] / lprev;
@@ -357,6 +352,20 @@ __device__ bool chol_inv(double *A, double *Vm, int d, double *kappa, double *lm
   for (int e = threadIdx.x; e < d * d; e += blockDim.x)
     if (e % d < e / d) A[e] = 0.0;
   __syncthreads();
+  return true;
+}
+
+// Cholesky G = L L^T of the symmetric d x d matrix in A (LDS), in place (lower
+// triangle; the strict upper part is zeroed), then L^{-1} into Vm by forward
+// substitution; both take one barrier per column.  Returns false when a pivot
+// is not positive.  With G symmetric, ||G||_2 <= ||G||_1 and
+// ||G^{-1}||_2 <= ||G^{-1}||_1 <= ||L^{-1}||_inf ||L^{-1}||_1, so
+// *kappa = ||G||_1 ||L^{-1}||_1 ||L^{-1}||_inf bounds kappa_2(G) from above and
+// *lmin_lb = 1 / min(||L^{-1}||_F^2, ||L^{-1}||_1 ||L^{-1}||_inf) bounds
+// lambda_min(G) from below.
+__device__ bool chol_inv(double *A, double *Vm, int d, double *kappa, double *lmin_lb) {
+  const double g1 = norm1(A, d);
+  if (!chol_lower(A, d, 0.0)) return false;
   lower_inv(A, Vm, d, d);
   const double lf2 = sumsq(Vm, d * d);
   const double l1 = norm1(Vm, d), li = norminf(Vm, d);
@@ -929,11 +938,13 @@ __device__ void small_gemm_body(const double *A, const double *B, double *C, int
 // Factor of the symmetric inner-product norm (§3.2.4).  G (d x d, symmetric
 // positive semi-definite, ld d) -> F (d x d, ld d) upper triangular with
 // F^T F = G to rounding error and zero rows past the numerical rank k.
-// Pivoted Cholesky gives G = P L L^T P^T (stopping at pivots <= d u max G_jj);
-// B = L^T P^T (k x d) then has B^T B = G, and Householder QR of B, B = Q F,
-// turns it into the upper-trapezoidal F with the same F^T F.  The triangle is
-// what lets the streaming pass skip the zero half of F X_n(i).  Non-finite G
-// gives an all-NaN F, so the norm comes out NaN.
+// When every pivot of the unpivoted Cholesky G = L L^T exceeds d u max G_jj,
+// F = L^T.  Otherwise (G numerically singular) pivoted Cholesky gives
+// G = P L L^T P^T, stopping at pivots <= d u max G_jj; B = L^T P^T (k x d)
+// then has B^T B = G, and Householder QR of B, B = Q F, turns it into the
+// upper-trapezoidal F with the same F^T F.  The triangle is what lets the
+// streaming pass skip the zero half of F X_n(i).  Non-finite G gives an
+// all-NaN F, so the norm comes out NaN.
 // ---------------------------------------------------------------------------
 __device__ void sym_factor_body(const double *__restrict__ G, int d, double *__restrict__ F) {
   __shared__ double A[TTR_RMAX * TTR_RMAX];
@@ -952,6 +963,19 @@ __device__ void sym_factor_body(const double *__restrict__ G, int d, double *__r
     for (int e = threadIdx.x; e < d * d; e += blockDim.x) F[e] = NAN;
     return;
   }
+  double m = 0.0;
+  for (int i = threadIdx.x; i < d; i += blockDim.x) m = fmax(m, A[i + d * i]);
+  m = block_max(m);
+  if (chol_lower(A, d, (double)d * kU * m)) {
+    for (int e = threadIdx.x; e < d * d; e += blockDim.x) {
+      const int r = e % d, c = e / d;
+      F[e] = (c >= r) ? A[c + d * r] : 0.0;
+    }
+    return;
+  }
+  __syncthreads();  // every thread has left the factorization before A is reloaded
+  for (int e = threadIdx.x; e < d * d; e += blockDim.x) A[e] = G[e];
+  __syncthreads();
   const int k = pivoted_chol(A, d, (double)d * kU, perm);
   // B(r, perm[j]) = L(j, r) for j >= r, else 0 (ld TTR_RMAX)
   for (int e = threadIdx.x; e < k * d; e += blockDim.x) {
