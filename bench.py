@@ -271,6 +271,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched rounding of 512 tensors")
     ap.add_argument("--no-large", action="store_true", help="skip the Hadamard -> rank-256 rounding")
     ap.add_argument("--no-norms", action="store_true", help="skip the timing of the three norm methods")
+    ap.add_argument("--no-mirror", action="store_true", help="skip the rounds in the mirror sweep order")
     ap.add_argument("--leg", default="all", choices=["all", "batched", "large", "norms"],
                     help="batched / large / norms: run only that leg (for profiling) and print its JSON object")
     ap.add_argument("--no-per-tensor", action="store_true",
@@ -399,6 +400,33 @@ def main():
     # the three norm methods of §3.2.4 on the same X
     norms = None if args.no_norms else bench_norms(h, torch, Xbuf, size_x, args.steps)
 
+    # the mirror sweep order (LRL: left-orthonormalize, truncate right to left)
+    # on the same X, FP64, timed the same way, with its ranks and sampled
+    # entries against the RLR result
+    mirror = None
+    if args.prec == "fp64" and not args.no_mirror:
+        other = "LRL" if args.direction == "RLR" else "RLR"
+        log(f"{other} rounds")
+        for w in range(args.warmup):
+            Yo = h.round(Xbuf, tol, other, "fp64", out=Ybuf)
+        torch.cuda.synchronize()
+        evo = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        for k in range(args.steps):
+            evo[k][0].record(stream)
+            Yo = h.round(Xbuf, tol, other, "fp64", out=Ybuf)
+            evo[k][1].record(stream)
+        torch.cuda.synchronize()
+        ms_o = sum(a.elapsed_time(b) for a, b in evo) / args.steps
+        idx = np.random.default_rng(8).integers(0, args.I, size=(256, N))
+        ef = sample_entries(Yf, ranks_fp64, I, idx)
+        eo = sample_entries(Yo.cores, list(Yo.R), I, idx)
+        mirror = {"direction": other, "ms_per_round": round(ms_o, 3),
+                  "round_core_GBps": round(size_x / (ms_o * 1e-3) / 1e9, 2),
+                  "ranks_equal": list(Yo.R) == ranks_fp64,
+                  "max_entry_diff_vs_" + args.direction: float(np.max(np.abs(eo - ef)) / np.sqrt(np.mean(ef * ef)))}
+        del Yo
+
     # dominant kernel by time
     cls = max((c for c in prof if c != "small"), key=lambda c: prof[c]["ms"])
     p = prof[cls]
@@ -451,6 +479,8 @@ def main():
         out["mixed"] = mixed
     if norms:
         out["norms"] = norms
+    if mirror:
+        out["mirror_direction"] = mirror
     if not args.no_batched:
         del A, B, Xbuf, Ybuf, X, Y, Yf
         torch.cuda.empty_cache()
