@@ -257,6 +257,59 @@ def bench_norms(h, torch, X, size_x, steps):
     return norms
 
 
+def bench_sum3(h, ttr, torch, steps, warmup, I_n):
+    """X = A + B + 1e-6 C (N=16, ranks 20 + 20 + 10 -> 50, 73.6 GB of cores at
+    I = 262144), rounded at tol 1e-8 in FP64 and in mixed precision: the
+    workload where the FP32 Gram passes must be refined to keep the 1e-6 part.
+    Ranks and sampled entries of the mixed result are compared with FP64."""
+    import synth
+    torch.cuda.empty_cache()
+    log("sum3: generating A, B, C (N=16, ranks 20, 20, 10)")
+    d = synth.sum_r50(I_override=I_n)
+    A, B, C = (ttr.TT.from_numpy(d[k]) for k in ("A", "B", "C"))
+    tol = d["tol"]
+    del d
+    AB = h.add(1.0, A, 1.0, B)
+    del A, B
+    X = h.add(1.0, AB, 1.0, C)
+    del AB, C
+    torch.cuda.empty_cache()
+    nbytes = sum(8 * X.R[n] * X.I[n] * X.R[n + 1] for n in range(X.N))
+    Y = ttr.TT.empty(X.I, [X.R[n] * X.I[n] * X.R[n + 1] for n in range(X.N)])
+    stream = torch.cuda.current_stream()
+    res = {"workload": f"X = A + B + 1e-6 C, N=16, I={I_n}, A,B random TTs of rank 20 and C of rank 10 "
+                       f"(scaled N(0,1) cores, C's first core times 1e-6), formal ranks 50, ttr_round tol {tol:g} RLR",
+           "core_bytes_X": nbytes}
+    ref = None
+    for prec in ("fp64", "mixed"):
+        for _ in range(warmup):
+            Y = h.round(X, tol, "RLR", prec, out=Y)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        for k in range(steps):
+            ev[k][0].record(stream)
+            Y = h.round(X, tol, "RLR", prec, out=Y)
+            ev[k][1].record(stream)
+        torch.cuda.synchronize()
+        ms = sum(a.elapsed_time(b) for a, b in ev) / steps
+        idx = np.random.default_rng(9).integers(0, I_n, size=(256, X.N))
+        ent = sample_entries(Y.cores, list(Y.R), X.I, idx)
+        r = {"ms_per_round": round(ms, 3), "round_core_GBps": round(nbytes / (ms * 1e-3) / 1e9, 2),
+             "ranks": list(Y.R)}
+        if ref is None:
+            ref = (list(Y.R), ent)
+            r["ranks_ok"] = Y.R[1:-1] == [50] * (X.N - 1)
+        else:
+            r["ranks_equal_fp64"] = list(Y.R) == ref[0]
+            r["max_entry_diff_vs_fp64"] = float(np.max(np.abs(ent - ref[1])) / np.sqrt(np.mean(ref[1] * ref[1])))
+        res[prec] = r
+        log(f"sum3 {prec}: {ms:.1f} ms per round")
+    res["mixed_speedup"] = round(res["fp64"]["ms_per_round"] / res["mixed"]["ms_per_round"], 3)
+    del X, Y
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -272,8 +325,9 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the Hadamard -> rank-256 rounding")
     ap.add_argument("--no-norms", action="store_true", help="skip the timing of the three norm methods")
     ap.add_argument("--no-mirror", action="store_true", help="skip the rounds in the mirror sweep order")
-    ap.add_argument("--leg", default="all", choices=["all", "batched", "large", "norms"],
-                    help="batched / large / norms: run only that leg (for profiling) and print its JSON object")
+    ap.add_argument("--no-sum3", action="store_true", help="skip the A + B + 1e-6 C rounding (ranks 50)")
+    ap.add_argument("--leg", default="all", choices=["all", "batched", "large", "norms", "sum3"],
+                    help="batched / large / norms / sum3: run only that leg (for profiling) and print its JSON object")
     ap.add_argument("--no-per-tensor", action="store_true",
                     help="batched leg: skip the one-ttr_round-per-tensor comparison")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
@@ -300,6 +354,8 @@ def main():
     if args.leg != "all":
         if args.leg == "batched":
             res = bench_batched(h, ttr, torch, args.steps, per_tensor=not args.no_per_tensor)
+        elif args.leg == "sum3":
+            res = bench_sum3(h, ttr, torch, args.steps, args.warmup, args.I)
         elif args.leg == "norms":
             d = synth.sum_r40(I_override=args.I)
             A, B = ttr.TT.from_numpy(d["A"]), ttr.TT.from_numpy(d["B"])
@@ -481,14 +537,13 @@ def main():
         out["norms"] = norms
     if mirror:
         out["mirror_direction"] = mirror
+    del A, B, Xbuf, Ybuf, X, Y, Yf
+    torch.cuda.empty_cache()
+    if not args.no_sum3:
+        out["sum3"] = bench_sum3(h, ttr, torch, args.steps, args.warmup, args.I)
     if not args.no_batched:
-        del A, B, Xbuf, Ybuf, X, Y, Yf
-        torch.cuda.empty_cache()
         out["batched"] = bench_batched(h, ttr, torch, args.steps, per_tensor=not args.no_per_tensor)
     if not args.no_large:
-        if args.no_batched:
-            del A, B, Xbuf, Ybuf, X, Y, Yf
-            torch.cuda.empty_cache()
         out["large"] = bench_large(h, ttr, torch, args.steps)
     if not args.no_cpu_baseline:
         log(f"cpu_baseline: oracle on I={args.cpu_sample_I}")
