@@ -58,3 +58,12 @@ def test_generators_are_seeded():
     assert [x.shape for x in a] == [(1, 8, 3), (3, 9, 4), (4, 10, 1)]
     assert all(np.array_equal(x, y) for x, y in zip(a, b))
     assert not all(np.array_equal(x, y) for x, y in zip(a, c))
+
+
+def test_every_leg_and_switch_parses():
+    # the switches parse before the GPU-count check, which then exits with 2
+    for extra in (["--leg", "norms"], ["--leg", "sum3"], ["--leg", "batched", "--no-per-tensor"],
+                  ["--no-norms", "--no-mirror", "--no-sum3", "--no-batched", "--no-large", "--no-cpu-baseline"]):
+        r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"] + extra,
+                           capture_output=True, text=True, timeout=120)
+        assert r.returncode == 2 and "one GPU" in r.stderr, (extra, r.stderr)
