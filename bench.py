@@ -483,6 +483,20 @@ def main():
                   "max_entry_diff_vs_" + args.direction: float(np.max(np.abs(eo - ef)) / np.sqrt(np.mean(ef * ef)))}
         del Yo
 
+    # HBM fractions of the round against 8 TB/s: algorithmic bytes (X read
+    # twice, the result written once) and, when the counter summary matches
+    # the kernel sources, the measured bytes of the streaming kernels summed
+    # over their launches
+    size_y = sum(8 * ranks_fp64[n] * I[n] * ranks_fp64[n + 1] for n in range(N))
+    hbm_frac = {"algorithmic": round((2 * size_x + size_y) / (ms_round * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+                "achieved": None}
+    streamed = ("k_gram_right_factor", "k_gram_left_factor", "k_apply_mfma")
+    per_launch = {c: pmc_traffic(c, 0.0) for c in streamed}
+    if all(per_launch[c] is not None for c in streamed):
+        tb = sum(per_launch[c] * prof[c]["count"] / args.steps for c in streamed)
+        hbm_frac["achieved"] = round(tb / (ms_round * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)
+        hbm_frac["achieved_bytes_per_round"] = round(tb)
+
     # dominant kernel by time
     cls = max((c for c in prof if c != "small"), key=lambda c: prof[c]["ms"])
     p = prof[cls]
@@ -524,6 +538,7 @@ def main():
         "ms_per_round": round(ms_round, 3),
         "ms_per_add": round(ms_add, 3),
         "round_core_GBps": round(size_x / (ms_round * 1e-3) / 1e9, 2),
+        "hbm_fraction": hbm_frac,
         "wall_ms_per_step": round(wall * 1e3, 3),
         "ranks_ok": ranks_ok,
         "gram_passes": st["gram_passes"],
