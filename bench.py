@@ -323,7 +323,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision rounds")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched rounding of 512 tensors")
     ap.add_argument("--no-large", action="store_true", help="skip the Hadamard -> rank-256 rounding")
-    ap.add_argument("--no-norms", action="store_true", help="skip the timing of the three norm methods")
+    ap.add_argument("--no-norms", action="store_true", help="skip the timing of the three norm methods and of the explicit orthonormalization")
     ap.add_argument("--no-mirror", action="store_true", help="skip the rounds in the mirror sweep order")
     ap.add_argument("--no-sum3", action="store_true", help="skip the A + B + 1e-6 C rounding (ranks 50)")
     ap.add_argument("--leg", default="all", choices=["all", "batched", "large", "norms", "sum3"],
@@ -483,6 +483,32 @@ def main():
                   "max_entry_diff_vs_" + args.direction: float(np.max(np.abs(eo - ef)) / np.sqrt(np.mean(ef * ef)))}
         del Yo
 
+    # explicit orthonormalization (orthonormal cores written, the §3.4 Alg. 5
+    # form) of a copy of X, both sides; the implicit form is the first sweep
+    # of every round (and the orthonormalization norm above)
+    orth = None
+    if not args.no_norms:
+        log("explicit orthonormalization")
+        orth = {}
+        for side in ("right", "left"):
+            ts, T = [], None
+            for k in range(args.warmup + args.steps):
+                for n in range(N):
+                    m = RX[n] * I[n] * RX[n + 1]
+                    Ybuf.cores[n][:m].copy_(Xbuf.cores[n][:m])
+                T = ttr.TT(Ybuf.cores, I, RX)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                h.orthogonalize(T, side)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                if k >= args.warmup:
+                    ts.append(e0.elapsed_time(e1))
+            ms_t = sum(ts) / len(ts)
+            orth[side] = {"ms": round(ms_t, 3), "core_GBps": round(size_x / (ms_t * 1e-3) / 1e9, 2),
+                          "ranks_kept": T.R == RX}
+
     # HBM fractions of the round against 8 TB/s: algorithmic bytes (X read
     # twice, the result written once) and, when the counter summary matches
     # the kernel sources, the measured bytes of the streaming kernels summed
@@ -552,6 +578,8 @@ def main():
         out["norms"] = norms
     if mirror:
         out["mirror_direction"] = mirror
+    if orth:
+        out["orthogonalize_explicit"] = orth
     del A, B, Xbuf, Ybuf, X, Y, Yf
     torch.cuda.empty_cache()
     if not args.no_sum3:
