@@ -508,6 +508,7 @@ def main():
             ms_t = sum(ts) / len(ts)
             orth[side] = {"ms": round(ms_t, 3), "core_GBps": round(size_x / (ms_t * 1e-3) / 1e9, 2),
                           "ranks_kept": T.R == RX}
+            del T  # it holds Ybuf's cores, which the later legs free
 
     # HBM fractions of the round against 8 TB/s: algorithmic bytes (X read
     # twice, the result written once) and, when the counter summary matches
