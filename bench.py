@@ -4,8 +4,9 @@ one MI355X.
 
 One step = the whole path for this workload on inputs resident in HBM:
 ttr_add(A, B) -> X, then ttr_round(X) (orthonormalization sweep, norm and
-threshold, truncation sweep).  `value` is core-GB/s = bytes of X's cores per
-second of step time.  The JSON line also carries round-only timing, the
+threshold, truncation sweep).  `value` is the rounding's core-GB/s = bytes of
+X's cores per second of ttr_round time (HIP events around the call inside each
+step); `ms_per_step` is the whole step.  The JSON line also carries the
 dominant kernel's roofline position (measured with HIP events on the library's
 stream during the timed steps) and the FP64 CPU oracle timed on a bounded
 sample of the same workload.
@@ -81,6 +82,26 @@ def sample_entries(cores, R, I, idx):
     return v[:, 0]
 
 
+def error_bound_figures(h, torch, Y, tol):
+    """Two device-side figures of ||X - X~|| / ||X|| for the last RLR rounding
+    on the handle, against Alg. 2's guarantee (<= tol):
+    * tail: sqrt(sum over links of the discarded singular values squared) /
+      ||X|| -- the truncation steps' own sums (every discarded direction is
+      orthogonal to the kept ones and to each other);
+    * pythagoras: sqrt(||X||^2 - ||X~||^2) / ||X||, with ||X~|| = ||X~_N||_F
+      because the output cores 1..N-1 are left-orthonormal.
+    ||X|| is the norm the rounding computed for its threshold."""
+    st = h.round_stats()
+    nrm = st["norm"]
+    tail = math.sqrt(sum(st["tail2"])) / nrm if nrm > 0 else 0.0
+    n_last = Y.R[-2] * Y.I[-1] * Y.R[-1]
+    ny = float(torch.linalg.vector_norm(Y.cores[-1][:n_last]).item())
+    pyth = math.sqrt(max(nrm * nrm - ny * ny, 0.0)) / nrm if nrm > 0 else 0.0
+    return {"tol": tol, "rel_err_tail": tail, "rel_err_pythagoras": pyth,
+            "within_tol": bool(tail <= tol and pyth <= tol * (1 + 1e-6)),
+            "jacobi_sweeps": st["sweeps"]}
+
+
 def bench_batched(h, ttr, torch, steps, count=512, per_tensor=True):
     """512 independent Y + Y + 1e-9 E tensors (N=8, I_n log-uniform in
     [64, 4096], ranks 2r+2 with r uniform in 1..31), tol 1e-7: one replay of the
@@ -140,27 +161,51 @@ def bench_batched(h, ttr, torch, steps, count=512, per_tensor=True):
     return out
 
 
-def cpu_baseline(I_sample, steps=1):
-    """FP64 CPU oracle on a bounded sample: the same workload with I reduced."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(I_sample, I_sample_1t=4096):
+    """FP64 CPU oracle on bounded samples of the same workload (I reduced):
+    the rounding alone (inputs in RAM), with the BLAS on all its threads and
+    on one thread."""
     import oracle as O
     import synth
-    from threadpoolctl import threadpool_info
-    d = synth.sum_r40(I_override=I_sample)
-    t0 = time.perf_counter()
-    for _ in range(steps):
+    from threadpoolctl import threadpool_info, threadpool_limits
+
+    def timed(I_s):
+        d = synth.sum_r40(I_override=I_s)
         X = O.add(1.0, d["A"], 1.0, d["B"])
-        O.round_tt(X, d["tol"], "RLR")
-    dt = (time.perf_counter() - t0) / steps
-    nbytes = O.tt_bytes(X)
-    threads = max([x.get("num_threads", 1) for x in threadpool_info()] or [1])
+        del d
+        t0 = time.perf_counter()
+        O.round_tt(X, synth.TOL[1], "RLR")
+        return O.tt_bytes(X), time.perf_counter() - t0
+
+    info = threadpool_info()
+    threads = max([x.get("num_threads", 1) for x in info] or [1])
+    blas = ", ".join(sorted({f"{x.get('internal_api', '?')} {x.get('version', '')}".strip() for x in info
+                             if x.get("user_api") == "blas"})) or "unknown"
+    nbytes, dt = timed(I_sample)
+    with threadpool_limits(limits=1):
+        nbytes1, dt1 = timed(I_sample_1t)
     return {
         "value": round(nbytes / dt / 1e9, 5),
         "unit": "GB/s",
         "cores": int(threads),
         "kind": "oracle",
         "sample": f"same workload with I={I_sample} instead of 262144 ({nbytes / 1e9:.3f} GB of cores), "
-                  f"add + RLR round, NumPy/OpenBLAS FP64, {dt:.2f} s per step",
-        "ms_per_step": round(dt * 1e3, 2),
+                  f"RLR round of X = A + B, NumPy FP64 on {blas}, {threads} threads, {dt:.2f} s",
+        "ms_per_round": round(dt * 1e3, 2),
+        "one_thread": {"value": round(nbytes1 / dt1 / 1e9, 5), "unit": "GB/s", "I": I_sample_1t,
+                       "core_bytes": nbytes1, "ms_per_round": round(dt1 * 1e3, 2)},
+        "cpu_model": cpu_model(),
+        "nproc": os.cpu_count(),
     }
 
 
@@ -211,9 +256,7 @@ def bench_large(h, ttr, torch, steps):
         ts.append(e0.elapsed_time(e1))
         log(f"large: round {k + 1}: {ts[-1]:.1f} ms")
     st = h.round_stats()
-    idx = np.random.default_rng(5).integers(0, X.I[0], size=(128, X.N))
-    ex = sample_entries(X.cores, X.R, X.I, idx)
-    ey = sample_entries(Y.cores, Y.R, Y.I, idx)
+    bound = error_bound_figures(h, torch, Y, tol)
     ms = sum(ts) / len(ts)
     out = {"workload": "A * B (Hadamard), N=10, I=16384, A,B random TTs of rank 16 with 2^-b rank weights, "
                        f"formal ranks 256, ttr_round tol {tol:g} RLR fp64",
@@ -221,8 +264,7 @@ def bench_large(h, ttr, torch, steps):
            "hadamard_GBps": round(nbytes / (ms_had * 1e-3) / 1e9, 1),
            "ms_per_round": round(ms, 3), "round_core_GBps": round(nbytes / (ms * 1e-3) / 1e9, 2),
            "rounds": len(ts), "ranks": list(Y.R), "gram_passes": st["gram_passes"],
-           "rel_rms_entry_diff_vs_X": float(np.sqrt(np.mean((ex - ey) ** 2) / np.mean(ex ** 2))),
-           "entries_sampled": int(idx.shape[0])}
+           "error_bound": bound}
     del X, Y, A, B
     torch.cuda.empty_cache()
     return out
@@ -295,7 +337,7 @@ def bench_sum3(h, ttr, torch, steps, warmup, I_n):
         idx = np.random.default_rng(9).integers(0, I_n, size=(256, X.N))
         ent = sample_entries(Y.cores, list(Y.R), X.I, idx)
         r = {"ms_per_round": round(ms, 3), "round_core_GBps": round(nbytes / (ms * 1e-3) / 1e9, 2),
-             "ranks": list(Y.R)}
+             "ranks": list(Y.R), "error_bound": error_bound_figures(h, torch, Y, tol)}
         if ref is None:
             ref = (list(Y.R), ent)
             r["ranks_ok"] = Y.R[1:-1] == [50] * (X.N - 1)
@@ -419,6 +461,7 @@ def main():
     ms_round = sum(e1.elapsed_time(e2) for _, e1, e2 in ev) / args.steps
     ms_add = sum(e0.elapsed_time(e1) for e0, e1, _ in ev) / args.steps
     ranks_ok = Y.R[1:-1] == [2 * r] * (N - 1)
+    bound = error_bound_figures(h, torch, Y, tol) if args.direction == "RLR" else None
     Yf = [c.clone() for c in Y.cores]
     ranks_fp64 = list(Y.R)
 
@@ -446,6 +489,7 @@ def main():
         em = sample_entries(Ym.cores, list(Ym.R), I, idx)
         rel = float(np.max(np.abs(em - ef)) / np.sqrt(np.mean(ef * ef)))
         mixed = {"ms_per_round": round(ms_mixed, 3),
+                 "error_bound": error_bound_figures(h, torch, Ym, tol) if args.direction == "RLR" else None,
                  "round_core_GBps": round(size_x / (ms_mixed * 1e-3) / 1e9, 2),
                  "speedup_vs_fp64": round(ms_round / ms_mixed, 3),
                  "ranks_equal": list(Ym.R) == ranks_fp64,
@@ -506,8 +550,27 @@ def main():
                 if k >= args.warmup:
                     ts.append(e0.elapsed_time(e1))
             ms_t = sum(ts) / len(ts)
+            # checks of the written cores: the core that carries the norm has
+            # ||.||_F = the orthonormalization norm, and one interior core is
+            # orthonormal (H H^T = I on the right side, V^T V = I on the left)
+            nref = norms["ortho"]["norm"] if norms else h.norm(Xbuf, "ortho")
+            c0 = 0 if side == "right" else N - 1
+            m0 = T.R[c0] * I[c0] * T.R[c0 + 1]
+            nc = float(torch.linalg.vector_norm(T.cores[c0][:m0]).item())
+            mid = N // 2
+            a, b = T.R[mid], T.R[mid + 1]
+            core = T.cores[mid][:a * I[mid] * b]
+            if side == "right":
+                Hm = core.view(b * I[mid], a).t()          # H(X_n): a x (I b), column-major buffer
+                gram = Hm @ Hm.t()
+            else:
+                Vm = core.view(b, a * I[mid]).t()          # V(X_n): (a I) x b
+                gram = Vm.t() @ Vm
+            orth_err = float(torch.linalg.matrix_norm(gram - torch.eye(gram.shape[0], dtype=gram.dtype,
+                                                                          device=gram.device)).item())
             orth[side] = {"ms": round(ms_t, 3), "core_GBps": round(size_x / (ms_t * 1e-3) / 1e9, 2),
-                          "ranks_kept": T.R == RX}
+                          "ranks_kept": T.R == RX, "norm_core_rel_diff": abs(nc - nref) / nref,
+                          "interior_core": mid, "interior_orthonormality": orth_err}
             del T  # it holds Ybuf's cores, which the later legs free
 
     # HBM fractions of the round against 8 TB/s: algorithmic bytes (X read
@@ -547,7 +610,7 @@ def main():
 
     out = {
         "metric": "TT-round core-GB/s and ms/round, FP64 vs mixed at rel.err <=1e-8, 1 GPU",
-        "value": round(size_x / (ms_step * 1e-3) / 1e9, 2),
+        "value": round(size_x / (ms_round * 1e-3) / 1e9, 2),
         "unit": "GB/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -564,6 +627,8 @@ def main():
                    "core_bytes_X": size_x},
         "ms_per_round": round(ms_round, 3),
         "ms_per_add": round(ms_add, 3),
+        "step_core_GBps": round(size_x / (ms_step * 1e-3) / 1e9, 2),
+        "error_bound": bound,
         "round_core_GBps": round(size_x / (ms_round * 1e-3) / 1e9, 2),
         "hbm_fraction": hbm_frac,
         "wall_ms_per_step": round(wall * 1e3, 3),

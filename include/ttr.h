@@ -186,8 +186,18 @@ const char *ttr_last_error(void);
 
 /* Per-call statistics of the last ttr_round on this handle (host memory):
  * number of streaming Gram passes, materialization passes, small-factorization
- * launches, and the singular values met at each link (N-1 links, up to
- * TTR_MAX_RANK each, descending, zero padded). */
+ * launches, and for each of the first TTR_STATS_LINKS links (physical link
+ * order, link l between cores l and l+1):
+ *   sigma     the singular values of the truncation step (descending, up to
+ *             TTR_STATS_SIGMA, zero padded; all zero when the step proved that
+ *             nothing can be dropped and skipped the SVD)
+ *   nsigma    how many of them are nonzero
+ *   tail2     the sum of squares of the singular values the truncation
+ *             discarded (Alg. 2: sqrt(tail2) <= delta at every link, so
+ *             sqrt(sum of tail2) <= tol ||X||)
+ *   sweeps    Jacobi sweeps of the truncation SVD (0: no SVD was needed) */
+#define TTR_STATS_LINKS 64
+#define TTR_STATS_SIGMA 256
 typedef struct ttr_round_stats {
   int32_t gram_passes;
   int32_t apply_passes;
@@ -195,8 +205,10 @@ typedef struct ttr_round_stats {
   int32_t links;
   double norm;
   double delta;
-  double sigma[TTR_MAX_RANK * 64];
-  int32_t nsigma[64];
+  double sigma[TTR_STATS_LINKS * TTR_STATS_SIGMA];
+  int32_t nsigma[TTR_STATS_LINKS];
+  double tail2[TTR_STATS_LINKS];
+  int32_t sweeps[TTR_STATS_LINKS];
 } ttr_round_stats;
 
 int ttr_get_round_stats(const ttr_handle *h, ttr_round_stats *out);

@@ -311,8 +311,20 @@ def orthogonalize(X: TT, side: str = "right") -> TT:
 
 def norm_ortho(X: TT) -> float:
     """||X|| = ||X_1||_F after right-orthonormalization (end of §2.3; second
-    approach of §3.2.4, accurate for small norms)."""
-    Y = orthogonalize(X, "right")
+    approach of §3.2.4, accurate for small norms).
+
+    Alg. 1's sweep, keeping only what reaches the first core: for n = N..2 the
+    triangular factor R of H(X_n)^T = QR and V(X_{n-1}) <- V(X_{n-1}) R^T.  The
+    orthonormal cores Q^T do not enter ||X_1||_F, so they are not formed (the
+    R of LAPACK's Householder QR is the same with or without Q)."""
+    _check(X)
+    Y = copy_tt(X)
+    for n in range(len(Y) - 1, 0, -1):
+        R = np.linalg.qr(H(Y[n]).T, mode="r")
+        k = R.shape[0]
+        p0, Ip, _ = Y[n - 1].shape
+        Y[n - 1] = np.asfortranarray(from_V(V(Y[n - 1]) @ R.T, p0, Ip, k))
+        Y[n] = None
     return float(np.linalg.norm(Y[0]))
 
 

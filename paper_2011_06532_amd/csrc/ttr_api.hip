@@ -84,7 +84,7 @@ int ensure_ws(ttr_handle *h, size_t bytes) {
 constexpr size_t kSlot = (size_t)TTR_RMAX * TTR_RMAX;
 constexpr int kStagesPerCore = 3;
 struct WS {
-  double *partials, *G, *Ra, *Rb, *Gst[3], *Pa, *Pb, *GU, *Wa, *Wb, *scal, *sigma, *Tn, *Bst, *tmp, *matA, *matB;
+  double *partials, *G, *Ra, *Rb, *Gst[3], *Pa, *Pb, *GU, *Wa, *Wb, *scal, *sigma, *tails, *Tn, *Bst, *tmp, *matA, *matB;
   int *dec;
   double *T(int n) const { return Tn + (size_t)n * kSlot; }
   double *B(int n, int j) const { return Bst + ((size_t)n * kStagesPerCore + j) * kSlot; }
@@ -92,7 +92,7 @@ struct WS {
 // tmp: staging for an explicit output core; mat: each of the two buffers that
 // hold materialized cores of ill-conditioned factorizations
 size_t ws_doubles(int N, size_t tmp, size_t mat = 0) {
-  return (size_t)TTR_MAXWG * kSlot + 12 * kSlot + 64 + (size_t)(N + 1) * TTR_RMAX +
+  return (size_t)TTR_MAXWG * kSlot + 12 * kSlot + 64 + (size_t)(N + 1) * (TTR_RMAX + 1) +
          (size_t)(N + 2) * (1 + kStagesPerCore) * kSlot + tmp + 2 * mat + 64;
 }
 WS carve(ttr_handle *h, int N, size_t tmp, size_t mat = 0) {
@@ -111,6 +111,7 @@ WS carve(ttr_handle *h, int N, size_t tmp, size_t mat = 0) {
   p += kSlot;  // spare
   w.scal = p; p += 64;
   w.sigma = p; p += (size_t)(N + 1) * TTR_RMAX;
+  w.tails = p; p += (size_t)(N + 1);
   w.Tn = p; p += (size_t)(N + 2) * kSlot;
   w.Bst = p; p += (size_t)(N + 2) * kStagesPerCore * kSlot;
   w.tmp = p; p += tmp;
@@ -191,8 +192,6 @@ double chain_flops(const CoreView &cv, const Stages &st, int *zr, int *zc) {
   return f;
 }
 
-const bool g_use_mfma = (std::getenv("TTR_GENERIC_KERNELS") == nullptr);
-
 // A stage on the physical core: transposed views swap roles (Z^T = R^T X L^T).
 // transposes swap lower <-> upper: "lower" 1 = lower, 2 = upper
 Stage st_transpose(const Stage &a) {
@@ -212,8 +211,9 @@ Stage st_transpose(const Stage &a) {
 // the one-right-factor RIGHT form of a materialized core (refinement passes)
 // runs on the FP64 matrix cores; longer chains run on the staged generic
 // kernel.
-void gram(ttr_handle *h, double *partials, double *G, const CoreView &cv, const Stages &st, int mode, int f32 = 0,
-          bool *ran_f32 = nullptr, double *ystore = nullptr, bool *stored = nullptr) {
+// Returns the number of workgroups (partial Grams) the pass used.
+int gram(ttr_handle *h, double *partials, double *G, const CoreView &cv, const Stages &st, int mode, int f32 = 0,
+         bool *ran_f32 = nullptr, double *ystore = nullptr, bool *stored = nullptr) {
   int zr, zc;
   const double cf = chain_flops(cv, st, &zr, &zc);
   const double gf = (mode == GRAM_LEFT) ? (double)zr * (zr + 1) * zc : (double)zc * (zc + 1) * zr;
@@ -229,7 +229,7 @@ void gram(ttr_handle *h, double *partials, double *G, const CoreView &cv, const 
   bool done = false;
   if (ran_f32) *ran_f32 = false;
   if (stored) *stored = false;
-  if (g_use_mfma) {
+  {
     if (pmode == GRAM_LEFT && pnl == 0 && pnr <= 1) {
       // sum (X Q)(X Q)^T
       const Stage *q = pnr ? (tr ? &st.L[0] : &st.R[0]) : nullptr;
@@ -277,6 +277,7 @@ void gram(ttr_handle *h, double *partials, double *G, const CoreView &cv, const 
     nwg = launch_gram(h->stream, cv, st, mode, partials, G, 0);
   }
   launch_reduce(h->stream, partials, nwg, gd * gd, G);
+  return nwg;
 }
 
 // Output pass Y(i) = lefts M(i) rights, on the matrix cores when the chain has
@@ -287,7 +288,7 @@ void apply(ttr_handle *h, const CoreView &cv, const Stages &st, double *Y, int t
   const double cf = chain_flops(cv, st, &zr, &zc);
   const double abytes = 8.0 * ((double)cv.pa * cv.pb + (double)zr * zc) * (double)cv.I;
   const bool tr = cv.trans != 0;
-  if (g_use_mfma && st.nl <= 1 && st.nr <= 1 && trans_out == cv.trans) {
+  if (st.nl <= 1 && st.nr <= 1 && trans_out == cv.trans) {
     ProfScope ps(h, P_APPLY, abytes, cf * (double)cv.I);
     // physical: Y_phys = Pp X Qp; trans views: (L M' R)^T = R^T X L^T
     const Stage *L = st.nl ? &st.L[0] : nullptr;
@@ -303,14 +304,14 @@ void apply(ttr_handle *h, const CoreView &cv, const Stages &st, double *Y, int t
                       pr ? Q.sc : cv.pb, tri, Y);
     return;
   }
-  if (g_use_mfma && st.nl == 0 && st.nr == 2 && trans_out == cv.trans) {
+  if (st.nl == 0 && st.nr == 2 && trans_out == cv.trans) {
     ProfScope ps(h, P_APPLY_FAC2, abytes, cf * (double)cv.I);
     const Stage &q1 = st.R[0], &q2 = st.R[1];
     launch_apply_fac2(h->stream, cv.X, cv.pa, cv.pb, cv.I, cv.trans, q1.S, q1.cols, q1.sr, q1.sc,
                       q1.lower == 1 ? 1 : 0, q2.S, q2.cols, q2.sr, q2.sc, Y);
     return;
   }
-  if (g_use_mfma && st.nl == 2 && st.nr == 0 && trans_out == cv.trans) {
+  if (st.nl == 2 && st.nr == 0 && trans_out == cv.trans) {
     // L2 L1 M = (M^T L1^T L2^T)^T: the transposed slice with Q1 = L1^T, Q2 = L2^T,
     // written transposed back
     ProfScope ps(h, P_APPLY_FAC2, abytes, cf * (double)cv.I);
@@ -435,9 +436,11 @@ const double kTauMix = 1e-5;
 
 // Bound on the rounding error of a streamed Gram, relative to its trace:
 // sequential accumulations per entry (slices per wave times the contracted
-// length), the fixed-order cross-wave/workgroup sums and the products.
-double gram_err(const CoreView &cv, int contracted, double u) {
-  const long long nwg = std::min<long long>(TTR_MAXWG, std::max<long long>(1, (cv.I + 63) / 64));
+// length), the fixed-order cross-wave/workgroup sums and the products.  `nwg`
+// is the number of workgroups the pass ran with (each takes a contiguous run
+// of ceil(I / nwg) slices, split over its four waves).
+double gram_err(const CoreView &cv, int contracted, double u, long long nwg) {
+  nwg = std::max<long long>(1, nwg);
   const long long spw = (cv.I + nwg - 1) / nwg;
   const double nacc = (double)((spw + 3) / 4) * contracted + 4.0 + (double)nwg + 2.0;
   return 2.0 * nacc * u;
@@ -465,14 +468,15 @@ int qr_by_gram(ttr_handle *h, WS &w, const CoreView &cv, int mode, const Stages 
     qa.tsr = qa.tsc = 0;
     qa.cond_scale = 1.0;
     qa.ratio_out = (pass == 1) ? h->decf_dev : nullptr;
-    const bool post = (pass == 1 && mode == GRAM_RIGHT && tcond > 0.0 && base.nr == 1 && base.nl <= 1 && g_use_mfma);
+    const bool post = (pass == 1 && mode == GRAM_RIGHT && tcond > 0.0 && base.nr == 1 && base.nl <= 1);
     bool f32 = false;
     int zr, zc;
     bool ys = false;
+    int gnwg = 1;
     if (post) {
       Stages s1 = base;
       s1.nr = 0;
-      gram(h, w.partials, w.G, cvp, s1, mode, pr.mixed, &f32, ystore, &ys);
+      gnwg = gram(h, w.partials, w.G, cvp, s1, mode, pr.mixed, &f32, ystore, &ys);
       if (ystored) *ystored = ys ? 1 : 0;
       qa.Tpost = base.R[0].S;
       qa.tpr = base.R[0].rows;
@@ -482,7 +486,7 @@ int qr_by_gram(ttr_handle *h, WS &w, const CoreView &cv, int mode, const Stages 
       qa.cond_scale = tcond;
       chain_flops(cvp, s1, &zr, &zc);
     } else {
-      gram(h, w.partials, w.G, cvp, st, mode, (pass == 1) ? pr.mixed : 0, &f32);
+      gnwg = gram(h, w.partials, w.G, cvp, st, mode, (pass == 1) ? pr.mixed : 0, &f32);
       chain_flops(cvp, st, &zr, &zc);
     }
     ++*passes;
@@ -499,7 +503,7 @@ int qr_by_gram(ttr_handle *h, WS &w, const CoreView &cv, int mode, const Stages 
     qa.tau1 = pr.mixed ? u / kTauMix : kTau1;
     qa.tau2 = kTau2;
     qa.ugram = u;
-    qa.gerr = gram_err(cvp, mode == GRAM_LEFT ? zc : zr, u);
+    qa.gerr = gram_err(cvp, mode == GRAM_LEFT ? zc : zr, u, gnwg);
     qa.try_chol = 1;
     qa.notrunc_check = (tc && tc->check) ? 1 : 0;
     qa.delta_dev = tc ? tc->delta_dev : nullptr;
@@ -521,7 +525,7 @@ int qr_by_gram(ttr_handle *h, WS &w, const CoreView &cv, int mode, const Stages 
     f->nst = pass;
     f->dim[pass] = k;
     const bool can_mat = (mode == GRAM_RIGHT) ? (base.nl <= 1 && base.nr <= 1) : (base.nl == 0 && base.nr <= 1);
-    if (!done && pass == 1 && mat && base.nl + base.nr > 0 && can_mat && g_use_mfma) {
+    if (!done && pass == 1 && mat && base.nl + base.nr > 0 && can_mat) {
       // The first pass did not settle: materialize the base chain once, so
       // that the refinement Gram passes and the output pass read one core
       // and apply the refinement stages to bitwise the same data.
@@ -788,14 +792,9 @@ int ttr_dot(ttr_handle *h, const ttr_tt *X, const ttr_tt *Y, double *out) {
       const double rx0 = X->R[n], rx1 = X->R[n + 1], ry0 = Y->R[n], ry1 = Y->R[n + 1];
       ProfScope ps(h, P_DOT, 8.0 * X->I[n] * (rx0 * rx1 + ry0 * ry1),
                    2.0 * X->I[n] * (ry0 * rx0 * rx1 + ry1 * ry0 * rx1));
-      if (g_use_mfma) {
-        const int nwg = launch_dot_mfma(h->stream, X->core[n], (int)X->R[n], (int)X->R[n + 1], Y->core[n],
-                                        (int)Y->R[n], (int)Y->R[n + 1], X->I[n], Wp, w.partials);
-        launch_reduce(h->stream, w.partials, nwg, (int)(Y->R[n + 1] * X->R[n + 1]), Wn);
-      } else {
-        launch_dot_step(h->stream, X->core[n], (int)X->R[n], (int)X->R[n + 1], Y->core[n], (int)Y->R[n],
-                        (int)Y->R[n + 1], X->I[n], Wp, w.partials, Wn);
-      }
+      const int nwg = launch_dot_mfma(h->stream, X->core[n], (int)X->R[n], (int)X->R[n + 1], Y->core[n],
+                                      (int)Y->R[n], (int)Y->R[n + 1], X->I[n], Wp, w.partials);
+      launch_reduce(h->stream, w.partials, nwg, (int)(Y->R[n + 1] * X->R[n + 1]), Wn);
     }
     std::swap(Wp, Wn);
   }
@@ -953,7 +952,7 @@ int ttr_round(ttr_handle *h, const ttr_tt *X, double tol, int direction, int pre
   // Sweep 2: truncation (Alg. 2 loop / Alg. 6 second loop).  The current core
   // n is C'_n(i) = [P_n B_n^T] M_n(i) T_{n+1}; its left stages are the
   // orthonormalization stages of core n with the last one merged into P_n.
-  std::vector<int> L(N + 1, 1);
+  std::vector<int> L(N + 1, 1), sweeps(N, 0);
   double *Pbuf[2] = {w.Pa, w.Pb};
   bool prev_refined = false;
   const double *Pcur = nullptr;  // merged last left stage (Lprev x dim)
@@ -1031,6 +1030,7 @@ int ttr_round(ttr_handle *h, const ttr_tt *X, double tol, int direction, int pre
     ta.tol = tol;
     ta.Nm1 = N - 1;
     ta.sigma_out = w.sigma + (size_t)n * TTR_RMAX;
+    ta.tail_out = w.tails + n;
     ta.dec = w.dec;
     ta.identity = tcx.notrunc;              // proved L = k: no SVD needed
     ta.r_orth = (g.nst == 1 && !tcx.notrunc && g.rorth) ? 1 : 0;  // one-pass eigen route: R = t^{1/2} W^T
@@ -1042,6 +1042,7 @@ int ttr_round(ttr_handle *h, const ttr_tt *X, double tol, int direction, int pre
     if ((rc = sync_dec(h))) return rc;
     const int Ln = h->dec_host[3];
     L[n + 1] = Ln;
+    sweeps[n] = h->dec_host[9];
     // output core n: the same staged chain as the Gram passes, the last
     // refinement stage merged with U_R[:, :L]
     Stages st = materialized ? no_stages() : base;
@@ -1088,6 +1089,8 @@ int ttr_round(ttr_handle *h, const ttr_tt *X, double tol, int direction, int pre
   const int nsig = (N - 1) * TTR_RMAX;
   std::vector<double> sig(nsig);
   HIPCHK(hipMemcpyAsync(sig.data(), w.sigma, nsig * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  std::vector<double> tails(N - 1);
+  HIPCHK(hipMemcpyAsync(tails.data(), w.tails, (N - 1) * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   HIPCHK(hipGetLastError());
   for (int l = 0; l <= N; ++l) {
@@ -1099,16 +1102,19 @@ int ttr_round(ttr_handle *h, const ttr_tt *X, double tol, int direction, int pre
   h->stats.links = N - 1;
   h->stats.norm = h->scal_host[2];
   h->stats.delta = h->scal_host[1];
-  const int nl = (N - 1) < 64 ? (N - 1) : 64;
-  for (int l = 0; l < nl; ++l) {
-    // logical link l+1; stats are reported in physical link order
+  for (int l = 0; l < N - 1; ++l) {
+    // logical link l+1; stats are reported in physical link order, for the
+    // first TTR_STATS_LINKS physical links
     const int pl = S.rev ? (N - 1 - l) - 1 : l;
+    if (pl >= TTR_STATS_LINKS) continue;
     int cnt = 0;
     for (int j = 0; j < TTR_RMAX; ++j) {
-      h->stats.sigma[pl * TTR_RMAX + j] = sig[(size_t)l * TTR_RMAX + j];
+      h->stats.sigma[(size_t)pl * TTR_STATS_SIGMA + j] = sig[(size_t)l * TTR_RMAX + j];
       if (sig[(size_t)l * TTR_RMAX + j] > 0) cnt = j + 1;
     }
     h->stats.nsigma[pl] = cnt;
+    h->stats.tail2[pl] = tails[l];
+    h->stats.sweeps[pl] = sweeps[l];
   }
   if (norm_out) *norm_out = h->scal_host[2];
   prof_resolve(h);

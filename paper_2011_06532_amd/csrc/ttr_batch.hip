@@ -449,6 +449,7 @@ __global__ void kp_plan(BState *St, int count, int op, int n, BDesc *d, BDesc *d
       a.tol = S.tol;
       a.Nm1 = N - 1;
       a.sigma_out = S.sigma + (size_t)n * TTR_RMAX;
+      a.tail_out = nullptr;
       a.dec = S.dec;
       a.r_orth = (S.gnst == 1 && !S.notrunc && S.rorth) ? 1 : 0;
       a.identity = S.notrunc;
@@ -883,6 +884,9 @@ int ttr_round_batched(ttr_handle *h, int count, const ttr_tt *X, const double *t
   }
   BatchPlan *P = h->plan;
   if (!P || P->sig != sig) {
+    // the previous plan's graph may still be replaying on the stream: wait
+    // before its workspace goes back to the allocator
+    if (P) TTR_HIPCHK(hipStreamSynchronize(h->stream));
     free_plan(h, P);
     h->plan = nullptr;
     P = new BatchPlan();

@@ -59,7 +59,6 @@ int launch_gram(hipStream_t s, const CoreView &cv, const Stages &st, int mode, d
 // transpose q x I x p (trans_out = 1).
 void launch_reduce(hipStream_t s, const double *partials, int nwg, int ne, double *G);
 void launch_apply(hipStream_t s, const CoreView &cv, const Stages &st, double *Y, int trans_out);
-// W (ry1 x rx1) = sum_i Y(i)^T Wp X(i), Wp is ry0 x rx0 col-major.
 // Matrix-core paths (ttr_mfma.hip) on physical cores (a x I x b), dims <= 64.
 // tri: the factor is triangular (Q lower / P upper), zero fragments are skipped.
 // f32: the mixed-precision first pass (FP32 products and accumulation).
@@ -82,8 +81,6 @@ int launch_gram_fac(hipStream_t s, const double *X, int a, int b, long long I, i
 void launch_apply_fac2(hipStream_t s, const double *X, int a, int b, long long I, int trans, const double *Q1,
                        int q1, long long s1r, long long s1c, int tri, const double *Q2, int q2, long long s2r,
                        long long s2c, double *Y);
-void launch_dot_step(hipStream_t s, const double *X, int rx0, int rx1, const double *Y, int ry0, int ry1,
-                     long long I, const double *Wp, double *partials, double *W);
 // The same step on the FP64 matrix cores: partial W_n (e x b, ld e) of each
 // workgroup into `partials`; returns the workgroup count (launch_reduce sums
 // them).  All ranks <= TTR_RMAX; X's slices a x b, Y's c x e, W (c x a, ld c).
@@ -152,7 +149,8 @@ struct TruncArgs {
   double tol;
   int Nm1;
   double *sigma_out; // TTR_RMAX values (descending, zero padded)
-  int *dec;          // [3] L, [2] error flags
+  double *tail_out;  // nullable: sum of squares of the discarded singular values
+  int *dec;          // [3] L, [2] error flags, [9] Jacobi sweeps (0: no SVD)
   int r_orth;        // rows of R are known to be orthogonal (skip the rotations)
   int identity;      // the step proved L = k: U = I and Sigma V^T = R (no SVD)
 };

@@ -615,7 +615,8 @@ struct LTruncArgs {
   int first;
   double tol;
   int Nm1;
-  double *sigma_out;    // TTR_RMAX values
+  double *sigma_out;    // kLMax values (descending, zero padded)
+  double *tail_out;     // sum of squares of the discarded singular values
   int *dec;             // [3] L, [2] error flags, [7] no truncation (set by lk_trunc_setup)
   int identity;         // no truncation already proven by the first Gram pass
   double *W0, *W1;      // scratch: W0 b x k (R^T, then A), W1 k x k (U)
@@ -677,7 +678,8 @@ __global__ __launch_bounds__(kLT) void lk_trunc_setup(LTruncArgs a) {
         *a.norm = nrm;
         *a.delta = (a.Nm1 > 0) ? a.tol * nrm / sqrt((double)a.Nm1) : 0.0;
       }
-      for (int j = 0; j < TTR_RMAX; ++j) a.sigma_out[j] = 0.0;
+      for (int j = 0; j < kLMax; ++j) a.sigma_out[j] = 0.0;
+      *a.tail_out = 0.0;
       a.dec[3] = k;
       a.dec[7] = 1;
     }
@@ -838,7 +840,10 @@ __global__ __launch_bounds__(kLT) void lk_trunc_finish(LTruncArgs a) {
       else break;
     }
     LL = L;
-    for (int j = 0; j < TTR_RMAX; ++j) a.sigma_out[j] = (j < k) ? a.sv[a.perm[j]] : 0.0;
+    for (int j = 0; j < kLMax; ++j) a.sigma_out[j] = (j < k) ? a.sv[a.perm[j]] : 0.0;
+    double t2 = 0.0;
+    for (int j = k - 1; j >= L; --j) t2 += a.sv[a.perm[j]] * a.sv[a.perm[j]];
+    *a.tail_out = t2;
     a.dec[3] = L;
   }
   __syncthreads();
@@ -869,7 +874,7 @@ constexpr int kChunks = 256;  // chunk Grams per streamed Gram
 
 struct LWS {
   double *tC, *tA, *tB;  // materialized cores (max core each)
-  double *G, *Ra, *Rb, *Gst[3], *P[2], *GU, *W0, *W1, *Up, *Ap, *scal, *sigma, *sv;
+  double *G, *Ra, *Rb, *Gst[3], *P[2], *GU, *W0, *W1, *Up, *Ap, *scal, *sigma, *tails, *sv;
   double *part;  // kChunks chunk Grams
   std::vector<double *> T;                 // N+1 slots
   std::vector<std::array<double *, 3>> B;  // N x 3 slots
@@ -953,6 +958,7 @@ struct Large {
   }
   // One-sided Jacobi SVD of A = W0 (b x k) with U = W1: sweeps of block
   // rounds until a sweep applies no rotation.
+  int sweeps = 0;  // of the last jacobi() call
   int jacobi(long long b, int k) {
     int *flag = reinterpret_cast<int *>(w.scal + 16);
     const int nbp = std::max(2, 2 * ((k + 2 * kJW - 1) / (2 * kJW)));
@@ -966,6 +972,7 @@ struct Large {
       int f = 0;
       TTR_HIPCHK(hipMemcpyAsync(&f, flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
       TTR_HIPCHK(hipStreamSynchronize(h->stream));
+      sweeps = sweep + 1;
       if (!f) return TTR_OK;
     }
     return ttr_fail(TTR_ERR_NUMERICAL, "the truncation SVD did not converge");
@@ -1021,7 +1028,7 @@ int ttr_round_large(ttr_handle *h, const ttr_tt *X, double tol, ttr_tt *Y, doubl
   size_t mc = 0;
   for (int n = 0; n < N; ++n) mc = std::max(mc, (size_t)(X->R[n] * X->I[n] * X->R[n + 1]));
   mc = (mc + 63) & ~(size_t)63;
-  const size_t need = ((size_t)(N + 1) + 3 * (size_t)N + 15 + kChunks) * kSlotL + 64 + (size_t)(N + 1) * TTR_RMAX +
+  const size_t need = ((size_t)(N + 1) + 3 * (size_t)N + 15 + kChunks) * kSlotL + 64 + (size_t)(N + 1) * (kLMax + 1) +
                       kLMax + kLMax + 3 * mc + 64;
   if (!h->large) h->large = new LargeCtx();
   LargeCtx *ctx = h->large;
@@ -1062,7 +1069,8 @@ int ttr_round_large(ttr_handle *h, const ttr_tt *X, double tol, ttr_tt *Y, doubl
   w.Up = take(kSlotL);
   w.Ap = take(kSlotL);
   w.scal = take(64);
-  w.sigma = take((size_t)(N + 1) * TTR_RMAX);
+  w.sigma = take((size_t)(N + 1) * kLMax);
+  w.tails = take((size_t)(N + 1));
   w.sv = take(kLMax);
   w.perm = reinterpret_cast<int *>(take(kLMax));
   w.T.resize(N + 1);
@@ -1116,7 +1124,7 @@ int ttr_round_large(ttr_handle *h, const ttr_tt *X, double tol, ttr_tt *Y, doubl
     k[n] = dim[n][pass];
   }
   // ---- sweep 2: left-to-right truncation --------------------------------------
-  std::vector<int> Lr(N + 1, 1);
+  std::vector<int> Lr(N + 1, 1), sweeps(N, 0);
   const double *Pcur = nullptr;
   int Lprev = 1;
   for (int n = 0; n < N - 1; ++n) {
@@ -1181,7 +1189,8 @@ int ttr_round_large(ttr_handle *h, const ttr_tt *X, double tol, ttr_tt *Y, doubl
     ta.first = (n == 0);
     ta.tol = tol;
     ta.Nm1 = N - 1;
-    ta.sigma_out = w.sigma + (size_t)n * TTR_RMAX;
+    ta.sigma_out = w.sigma + (size_t)n * kLMax;
+    ta.tail_out = w.tails + n;
     ta.dec = h->dec_dev;
     ta.identity = (g == 1) ? notrunc : 0;
     ta.W0 = w.W0;
@@ -1203,6 +1212,7 @@ int ttr_round_large(ttr_handle *h, const ttr_tt *X, double tol, ttr_tt *Y, doubl
       if ((rc = L.gemm(false, true, kq, dn, cc, Rq, kq, Fn, dn, Pn, kq))) return rc;
     } else {
       if ((rc = L.jacobi(cc, kq))) return rc;
+      sweeps[n] = L.sweeps;
       hipLaunchKernelGGL(lk_trunc_finish, dim3(1), dim3(kLT), 0, h->stream, ta);
       h->stats.small_launches++;
       if ((rc = L.sync_dec())) return rc;
@@ -1239,9 +1249,10 @@ int ttr_round_large(ttr_handle *h, const ttr_tt *X, double tol, ttr_tt *Y, doubl
   }
   TTR_HIPCHK(hipGetLastError());
   TTR_HIPCHK(hipMemcpyAsync(h->scal_host, w.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-  const int nsig = (N - 1) * TTR_RMAX;
-  std::vector<double> sig(nsig);
+  const int nsig = (N - 1) * kLMax;
+  std::vector<double> sig(nsig), tails(N - 1);
   TTR_HIPCHK(hipMemcpyAsync(sig.data(), w.sigma, nsig * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  TTR_HIPCHK(hipMemcpyAsync(tails.data(), w.tails, (N - 1) * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   TTR_HIPCHK(hipStreamSynchronize(h->stream));
   for (int l = 0; l <= N; ++l) Y->R[l] = (l == 0 || l == N) ? 1 : Lr[l];
   h->stats.gram_passes = L.passes;
@@ -1249,14 +1260,16 @@ int ttr_round_large(ttr_handle *h, const ttr_tt *X, double tol, ttr_tt *Y, doubl
   h->stats.links = N - 1;
   h->stats.norm = h->scal_host[2];
   h->stats.delta = h->scal_host[1];
-  const int nl = (N - 1) < 64 ? (N - 1) : 64;
+  const int nl = (N - 1) < TTR_STATS_LINKS ? (N - 1) : TTR_STATS_LINKS;
   for (int l = 0; l < nl; ++l) {
     int cnt = 0;
-    for (int j = 0; j < TTR_RMAX; ++j) {
-      h->stats.sigma[l * TTR_RMAX + j] = sig[(size_t)l * TTR_RMAX + j];
-      if (sig[(size_t)l * TTR_RMAX + j] > 0) cnt = j + 1;
+    for (int j = 0; j < kLMax; ++j) {
+      h->stats.sigma[(size_t)l * TTR_STATS_SIGMA + j] = sig[(size_t)l * kLMax + j];
+      if (sig[(size_t)l * kLMax + j] > 0) cnt = j + 1;
     }
     h->stats.nsigma[l] = cnt;
+    h->stats.tail2[l] = tails[l];
+    h->stats.sweeps[l] = sweeps[l];
   }
   if (norm_out) *norm_out = h->scal_host[2];
   return TTR_OK;

@@ -847,7 +847,9 @@ __device__ void trunc_step_body(const TruncArgs a) {
         *a.delta = (a.Nm1 > 0) ? a.tol * nrm / sqrt((double)a.Nm1) : 0.0;
       }
       for (int j = 0; j < TTR_RMAX; ++j) a.sigma_out[j] = 0.0;
+      if (a.tail_out) *a.tail_out = 0.0;
       a.dec[3] = k;
+      a.dec[9] = 0;
     }
     const int d = a.d;
     for (int e = threadIdx.x; e < d * k; e += blockDim.x) a.GU[e] = a.Glast[e];
@@ -899,7 +901,13 @@ __device__ void trunc_step_body(const TruncArgs a) {
     }
     LL = L;
     for (int j = 0; j < TTR_RMAX; ++j) a.sigma_out[j] = (j < k) ? ss[j] : 0.0;
+    if (a.tail_out) {
+      double t2 = 0.0;
+      for (int j = k - 1; j >= L; --j) t2 += ss[j] * ss[j];
+      *a.tail_out = t2;
+    }
     a.dec[3] = L;
+    a.dec[9] = sweeps < 0 ? -sweeps : sweeps;
   }
   __syncthreads();
   const int L = LL;

@@ -385,68 +385,6 @@ __global__ __launch_bounds__(kThreads) void k_apply(CoreView cv, Stages st, int 
   }
 }
 
-// ---------------------------------------------------------------------------
-// Inner-product step: partial W = sum_i Y(i)^T Wp X(i) (eq. (4)).
-// ---------------------------------------------------------------------------
-constexpr int kMaxOwnFull = (TTR_RMAX * TTR_RMAX + kThreads - 1) / kThreads;
-
-__global__ __launch_bounds__(kThreads) void k_dot_step(const double *__restrict__ X, int rx0, int rx1,
-                                                      const double *__restrict__ Y, int ry0, int ry1, long long I,
-                                                      const double *__restrict__ Wp, int T, long long spw,
-                                                      double *__restrict__ partials) {
-  HIP_DYNAMIC_SHARED(double, smem);
-  double *Xs = smem;                              // T x (rx0 x rx1)
-  double *Ys = Xs + (long long)T * rx0 * rx1;     // T x (ry0 x ry1)
-  double *Zs = Ys + (long long)T * ry0 * ry1;     // T x (ry0 x rx1)
-  const int ne = ry1 * rx1;
-  double acc[kMaxOwnFull];
-#pragma unroll
-  for (int j = 0; j < kMaxOwnFull; ++j) acc[j] = 0.0;
-  CoreView cx{X, I, rx0, rx1, 0};
-  CoreView cy{Y, I, ry0, ry1, 0};
-  const long long beg = (long long)blockIdx.x * spw;
-  const long long end = std::min(beg + spw, I);
-  for (long long i0 = beg; i0 < end; i0 += T) {
-    const int nt = (int)std::min((long long)T, end - i0);
-    stage_chunk(cx, i0, nt, T, Xs);
-    stage_chunk(cy, i0, nt, T, Ys);
-    __syncthreads();
-    const int tz = nt * ry0 * rx1;
-    for (int e = threadIdx.x; e < tz; e += blockDim.x) {
-      const int t = e / (ry0 * rx1);
-      const int rem = e - t * ry0 * rx1;
-      const int c = rem / ry0;
-      const int r = rem - c * ry0;
-      const double *x = Xs + (long long)t * rx0 * rx1 + (long long)rx0 * c;
-      double s = 0.0;
-      for (int k = 0; k < rx0; ++k) s += Wp[r + ry0 * k] * x[k];
-      Zs[(long long)t * ry0 * rx1 + r + ry0 * c] = s;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < kMaxOwnFull; ++j) {
-      const int e = threadIdx.x + j * kThreads;
-      if (e < ne) {
-        const int v = e / ry1;
-        const int u = e - v * ry1;
-        double s = acc[j];
-        for (int t = 0; t < nt; ++t) {
-          const double *y = Ys + (long long)t * ry0 * ry1 + (long long)ry0 * u;
-          const double *z = Zs + (long long)t * ry0 * rx1 + (long long)ry0 * v;
-          for (int r = 0; r < ry0; ++r) s += y[r] * z[r];
-        }
-        acc[j] = s;
-      }
-    }
-    __syncthreads();
-  }
-  double *out = partials + (long long)blockIdx.x * ne;
-#pragma unroll
-  for (int j = 0; j < kMaxOwnFull; ++j) {
-    const int e = threadIdx.x + j * kThreads;
-    if (e < ne) out[e] = acc[j];
-  }
-}
 
 int grid_for(long long I, int T) {
   const long long chunks = (I + T - 1) / T;
@@ -518,17 +456,3 @@ void launch_apply(hipStream_t s, const CoreView &cv, const Stages &st, double *Y
   hipLaunchKernelGGL(k_apply, dim3(nwg_used), dim3(kThreads), lds, s, cv, st, T, spw, buf, Y, trans_out);
 }
 
-void launch_dot_step(hipStream_t s, const double *X, int rx0, int rx1, const double *Y, int ry0, int ry1, long long I,
-                     const double *Wp, double *partials, double *W) {
-  const long long per = (long long)rx0 * rx1 + (long long)ry0 * ry1 + (long long)ry0 * rx1;
-  long long T = (long long)(kLdsBudget / sizeof(double)) / std::max(per, 1LL);
-  T = std::max(1LL, std::min(T, 64LL));
-  T = std::min(T, std::max(I, 1LL));
-  const int nwg = grid_for(I, (int)T);
-  const long long spw = slices_per_wg(I, (int)T, nwg);
-  const int nwg_used = (int)((I + spw - 1) / spw);
-  const size_t lds = (size_t)(per * T) * sizeof(double);
-  hipLaunchKernelGGL(k_dot_step, dim3(nwg_used), dim3(kThreads), lds, s, X, rx0, rx1, Y, ry0, ry1, I, Wp, (int)T, spw,
-                     partials);
-  launch_reduce(s, partials, nwg_used, ry1 * rx1, W);
-}

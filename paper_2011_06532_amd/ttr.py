@@ -27,6 +27,7 @@ TTR_RLR, TTR_LRL = 0, 1
 TTR_NORM_ORTHO, TTR_NORM_GRAM, TTR_NORM_SYM = 0, 1, 2
 TTR_FP64, TTR_MIXED = 0, 1
 TTR_MAX_RANK = 64
+TTR_STATS_LINKS, TTR_STATS_SIGMA = 64, 256
 TTR_ERR_NUMERICAL = 6
 
 _DIR = {"RLR": TTR_RLR, "LRL": TTR_LRL}
@@ -83,8 +84,10 @@ class RoundStats(ctypes.Structure):
         ("links", ctypes.c_int32),
         ("norm", ctypes.c_double),
         ("delta", ctypes.c_double),
-        ("sigma", ctypes.c_double * (TTR_MAX_RANK * 64)),
-        ("nsigma", ctypes.c_int32 * 64),
+        ("sigma", ctypes.c_double * (TTR_STATS_LINKS * TTR_STATS_SIGMA)),
+        ("nsigma", ctypes.c_int32 * TTR_STATS_LINKS),
+        ("tail2", ctypes.c_double * TTR_STATS_LINKS),
+        ("sweeps", ctypes.c_int32 * TTR_STATS_LINKS),
     ]
 
 
@@ -361,8 +364,8 @@ class Handle:
     def round_stats(self) -> dict:
         st = RoundStats()
         _check(_lib.ttr_get_round_stats(self.h, ctypes.byref(st)))
-        sig = []
-        for l in range(min(st.links, 64)):
-            sig.append([st.sigma[l * TTR_MAX_RANK + j] for j in range(st.nsigma[l])])
+        nl = min(st.links, TTR_STATS_LINKS)
+        sig = [[st.sigma[l * TTR_STATS_SIGMA + j] for j in range(st.nsigma[l])] for l in range(nl)]
         return {"gram_passes": st.gram_passes, "apply_passes": st.apply_passes,
-                "small_launches": st.small_launches, "norm": st.norm, "delta": st.delta, "sigmas": sig}
+                "small_launches": st.small_launches, "norm": st.norm, "delta": st.delta, "sigmas": sig,
+                "tail2": [st.tail2[l] for l in range(nl)], "sweeps": [st.sweeps[l] for l in range(nl)]}
