@@ -78,6 +78,9 @@ def test_dot_and_norms_match_full(I, r):
     assert abs(O.norm_gram(X) - n) <= 1e-12 * n
     assert abs(O.norm_gram_sym(X) - n) <= 1e-12 * n
     assert abs(O.norm_ortho(X) - n) <= 1e-13 * n
+    # the norm sweep keeps only the triangular factors of Alg. 1: the same
+    # value as ||X_1||_F of the explicitly orthonormalized train
+    assert O.norm_ortho(X) == float(np.linalg.norm(O.orthogonalize(X, "right")[0]))
 
 
 # ---------------------------------------------------------------- symmetric inner-product norm
