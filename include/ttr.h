@@ -112,6 +112,20 @@ int ttr_hadamard(ttr_handle *h, const ttr_tt *X, const ttr_tt *Y, ttr_tt *Z);
  * (§3.2.3, eq. (4)).  `out` is host memory.  Synchronizes. */
 int ttr_dot(ttr_handle *h, const ttr_tt *X, const ttr_tt *Y, double *out);
 
+/* ttr_dot for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and summation order as ttr_dot, so the same value bit for bit,
+ * but it allocates nothing and does not synchronize.  The partial sums live
+ * in a fixed device array of the library (512 * 64 * 64 + 2 * 64 * 64
+ * doubles, about 16.8 MB), one copy per device, held until the process ends.
+ *   out_dev  DEVICE pointer to one double on the handle's device; receives
+ *            <X, Y> when the stream reaches the end of the call.
+ * Ranks <= TTR_MAX_RANK (TTR_ERR_UNSUPPORTED above, or if a step's partial
+ * sums would not fit the array).  Every call on one device uses that
+ * device's array and leaves it holding the last call's partial sums: calls
+ * that overlap on one device (other streams or handles) race. */
+int ttr_dot_noalloc(ttr_handle *h, const ttr_tt *X, const ttr_tt *Y, double *out_dev);
+
 /* *out = ||X|| (§3.2.4).  TTR_NORM_GRAM: sqrt(<X, X>) (fast; cancellation for
  * small norms of difference tensors).  TTR_NORM_SYM: the same quantity with the
  * symmetry of the inner-product matrices exploited: W_n = V(Z_n)^T V(Z_n) with

@@ -10,8 +10,22 @@
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
+
+// Scratch of ttr_dot_noalloc: the partial inner-product matrices of one step
+// (at most 512 workgroups x 64 x 64 doubles) and the two W matrices of the
+// recursion.  One copy per device, held until the process ends.  Host code
+// never uses this name as an address: it uses the pointer that
+// hipGetSymbolAddress returned on the device (noalloc_scratch_of).
+constexpr size_t kNoAllocPartials = (size_t)512 * TTR_RMAX * TTR_RMAX;
+constexpr size_t kNoAllocDoubles = kNoAllocPartials + 2 * (size_t)TTR_RMAX * TTR_RMAX;
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+__global__ void k_set_one(double *p) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = 1.0;
+}
 
 namespace {
 
@@ -624,6 +638,24 @@ size_t max_core(const ttr_tt *X) {
 
 }  // namespace
 
+// The device address of `scratch` on `device` (the current device), looked
+// up once per device.
+int noalloc_scratch_of(int device, double **out) {
+  static std::mutex mu;
+  static std::vector<double *> addr;
+  std::lock_guard<std::mutex> lock(mu);
+  if ((int)addr.size() <= device) addr.resize(device + 1, nullptr);
+  if (!addr[device]) {
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(TTR_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    addr[device] = static_cast<double *>(p);
+  }
+  *out = addr[device];
+  return TTR_OK;
+}
+
 int ttr_dev_alloc(ttr_handle *h, void **p, size_t bytes) {
   *p = nullptr;
   if (h->alloc_fn) {
@@ -661,6 +693,16 @@ int ttr_create(ttr_handle **h, int device, void *stream) {
       hipMalloc((void **)&p->decf_dev, 8 * sizeof(double)) != hipSuccess) {
     delete p;
     return fail(TTR_ERR_ALLOC, "handle allocation failed");
+  }
+  int rc = noalloc_scratch_of(device, &p->noalloc_scratch);
+  if (rc) {
+    (void)hipFree(p->dec_dev);
+    (void)hipFree(p->decf_dev);
+    (void)hipHostFree(p->decf_host);
+    (void)hipHostFree(p->dec_host);
+    (void)hipHostFree(p->scal_host);
+    delete p;
+    return rc;
   }
   *h = p;
   return TTR_OK;
@@ -803,6 +845,38 @@ int ttr_dot(ttr_handle *h, const ttr_tt *X, const ttr_tt *Y, double *out) {
   HIPCHK(hipStreamSynchronize(h->stream));
   *out = h->scal_host[1];
   prof_resolve(h);
+  return TTR_OK;
+}
+
+int ttr_dot_noalloc(ttr_handle *h, const ttr_tt *X, const ttr_tt *Y, double *out_dev) {
+  int rc;
+  if ((rc = handle_ok(h))) return rc;
+  if (!out_dev) return fail(TTR_ERR_INVALID_ARG, "out_dev is NULL");
+  if ((rc = check_tt(X, "X", TTR_MAX_RANK))) return rc;
+  if ((rc = check_tt(Y, "Y", TTR_MAX_RANK))) return rc;
+  if (X->N != Y->N) return fail(TTR_ERR_SHAPE, "X and Y differ in N");
+  for (int n = 0; n < X->N; ++n)
+    if (X->I[n] != Y->I[n]) return fail(TTR_ERR_SHAPE, "X and Y differ in mode sizes");
+  const int N = X->N;
+  // every step's partials must fit the fixed scratch (ranks <= 64 always do;
+  // checked here so that a change of the launch grid cannot overrun it)
+  for (int n = 0; n < N; ++n) {
+    const size_t need = (size_t)dot_mfma_workgroups(X->I[n]) * (size_t)(Y->R[n + 1] * X->R[n + 1]);
+    if (need > kNoAllocPartials)
+      return fail(TTR_ERR_UNSUPPORTED, "ttr_dot_noalloc: partial sums need " + std::to_string(need) +
+                                           " doubles, above its fixed scratch of " + std::to_string(kNoAllocPartials));
+  }
+  double *partials = h->noalloc_scratch;
+  double *Wp = partials + kNoAllocPartials, *Wn = Wp + (size_t)TTR_RMAX * TTR_RMAX;
+  hipLaunchKernelGGL(k_set_one, dim3(1), dim3(64), 0, h->stream, Wp);
+  for (int n = 0; n < N; ++n) {
+    const int nwg = launch_dot_mfma(h->stream, X->core[n], (int)X->R[n], (int)X->R[n + 1], Y->core[n], (int)Y->R[n],
+                                    (int)Y->R[n + 1], X->I[n], Wp, partials);
+    // the last step's 1 x 1 result goes straight to the caller's buffer
+    launch_reduce(h->stream, partials, nwg, (int)(Y->R[n + 1] * X->R[n + 1]), n == N - 1 ? out_dev : Wn);
+    std::swap(Wp, Wn);
+  }
+  HIPCHK(hipGetLastError());
   return TTR_OK;
 }
 

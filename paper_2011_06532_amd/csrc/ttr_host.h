@@ -41,6 +41,9 @@ struct ttr_handle {
   void *(*alloc_fn)(size_t, void *) = nullptr;
   void (*free_fn)(void *, void *) = nullptr;
   void *alloc_ctx = nullptr;
+  // this device's copy of the fixed scratch array of ttr_dot_noalloc (its
+  // address from hipGetSymbolAddress, taken in ttr_create)
+  double *noalloc_scratch = nullptr;
 };
 
 // Workspace memory through the handle's allocator: TTR_OK, or TTR_ERR_ALLOC

@@ -84,6 +84,8 @@ void launch_apply_fac2(hipStream_t s, const double *X, int a, int b, long long I
 // The same step on the FP64 matrix cores: partial W_n (e x b, ld e) of each
 // workgroup into `partials`; returns the workgroup count (launch_reduce sums
 // them).  All ranks <= TTR_RMAX; X's slices a x b, Y's c x e, W (c x a, ld c).
+// Workgroups (= partial matrices) launch_dot_mfma uses for I slices.
+int dot_mfma_workgroups(long long I);
 int launch_dot_mfma(hipStream_t s, const double *X, int a, int b, const double *Y, int c, int e, long long I,
                     const double *W, double *partials);
 

@@ -1054,6 +1054,8 @@ int launch_gram_left_factor(hipStream_t s, const double *X, int a, int b, long l
   return gr.nwg;
 }
 
+int dot_mfma_workgroups(long long I) { return grid_of(I).nwg; }
+
 int launch_dot_mfma(hipStream_t s, const double *X, int a, int b, const double *Y, int c, int e, long long I,
                     const double *W, double *partials) {
   const Grid gr = grid_of(I);

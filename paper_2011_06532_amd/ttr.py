@@ -40,6 +40,7 @@ SYMBOLS = [
     "ttr_create", "ttr_destroy", "ttr_set_stream", "ttr_add", "ttr_hadamard", "ttr_dot", "ttr_norm",
     "ttr_orthogonalize", "ttr_round", "ttr_status_string", "ttr_last_error", "ttr_get_round_stats",
     "ttr_set_profiling", "ttr_get_profile", "ttr_round_batched", "ttr_get_batch_plan", "ttr_set_allocator",
+    "ttr_dot_noalloc",
 ]
 
 # ttr_set_allocator callback types: void *alloc(size_t bytes, void *ctx), void free(void *ptr, void *ctx)
@@ -127,6 +128,7 @@ def load(path: str = LIB_PATH):
     lib.ttr_add.argtypes = [vp, ctypes.c_double, tt, ctypes.c_double, tt, tt]
     lib.ttr_hadamard.argtypes = [vp, tt, tt, tt]
     lib.ttr_dot.argtypes = [vp, tt, tt, P(ctypes.c_double)]
+    lib.ttr_dot_noalloc.argtypes = [vp, tt, tt, vp]
     lib.ttr_norm.argtypes = [vp, tt, ctypes.c_int, P(ctypes.c_double)]
     lib.ttr_orthogonalize.argtypes = [vp, tt, ctypes.c_int, ctypes.c_int]
     lib.ttr_round.argtypes = [vp, tt, ctypes.c_double, ctypes.c_int, ctypes.c_int, tt, P(ctypes.c_double)]
@@ -288,6 +290,17 @@ class Handle:
         sx, sy = X._struct(), Y._struct()
         _check(_lib.ttr_dot(self.h, ctypes.byref(sx), ctypes.byref(sy), ctypes.byref(out)))
         return out.value
+
+    def dot_noalloc(self, X: TT, Y: TT, out=None):
+        """<X, Y> into a one-element float64 device tensor, without any
+        allocation in the library (ttr_dot_noalloc); asynchronous on the
+        handle's stream."""
+        import torch
+        if out is None:
+            out = torch.empty(1, dtype=torch.float64, device=X.cores[0].device)
+        sx, sy = X._struct(), Y._struct()
+        _check(_lib.ttr_dot_noalloc(self.h, ctypes.byref(sx), ctypes.byref(sy), ctypes.c_void_p(out.data_ptr())))
+        return out
 
     def norm(self, X: TT, method: str = "ortho") -> float:
         out = ctypes.c_double()
