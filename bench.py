@@ -89,16 +89,22 @@ def error_bound_figures(h, torch, Y, tol):
       ||X|| -- the truncation steps' own sums (every discarded direction is
       orthogonal to the kept ones and to each other);
     * pythagoras: sqrt(||X||^2 - ||X~||^2) / ||X||, with ||X~|| = ||X~_N||_F
-      because the output cores 1..N-1 are left-orthonormal.
-    ||X|| is the norm the rounding computed for its threshold."""
+      because the output cores 1..N-1 are left-orthonormal.  The difference
+      of two squared norms that agree to rounding leaves this figure a floor
+      of about sqrt(8 N u) (~1e-7 at N = 16): below it, it only says "no
+      larger than the floor".
+    ||X|| is the norm the rounding computed for its threshold.  `within_tol`
+    takes the tail figure, and the Pythagoras figure where it is above its
+    floor."""
     st = h.round_stats()
     nrm = st["norm"]
     tail = math.sqrt(sum(st["tail2"])) / nrm if nrm > 0 else 0.0
     n_last = Y.R[-2] * Y.I[-1] * Y.R[-1]
     ny = float(torch.linalg.vector_norm(Y.cores[-1][:n_last]).item())
     pyth = math.sqrt(max(nrm * nrm - ny * ny, 0.0)) / nrm if nrm > 0 else 0.0
-    return {"tol": tol, "rel_err_tail": tail, "rel_err_pythagoras": pyth,
-            "within_tol": bool(tail <= tol and pyth <= tol * (1 + 1e-6)),
+    floor = math.sqrt(8.0 * len(Y.I) * 2.0 ** -53)
+    return {"tol": tol, "rel_err_tail": tail, "rel_err_pythagoras": pyth, "pythagoras_floor": floor,
+            "within_tol": bool(tail <= tol and pyth <= max(tol * (1 + 1e-6), floor)),
             "jacobi_sweeps": st["sweeps"]}
 
 
