@@ -7,7 +7,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libttr.so")
-SOURCES = ["ttr_api.hip", "ttr_stream.hip", "ttr_small.hip", "ttr_mfma.hip", "ttr_batch.hip", "ttr_large.hip"]
+SOURCES = ["ttr_api.hip", "ttr_stream.hip", "ttr_small.hip", "ttr_mfma.hip", "ttr_batch.hip", "ttr_large.hip",
+           "ttr_lstream.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -42,7 +43,7 @@ def build(verbose: bool = True) -> str:
             sys.stderr.write(r.stdout + r.stderr)
             raise subprocess.CalledProcessError(r.returncode, cmd)
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lrocblas"]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -519,6 +519,7 @@ int qr_by_gram(ttr_handle *h, WS &w, const CoreView &cv, int mode, const Stages 
     qa.ugram = u;
     qa.gerr = gram_err(cvp, mode == GRAM_LEFT ? zc : zr, u, gnwg);
     qa.try_chol = 1;
+    qa.shift_pass = pr.mixed ? 2 : 1;
     qa.notrunc_check = (tc && tc->check) ? 1 : 0;
     qa.delta_dev = tc ? tc->delta_dev : nullptr;
     qa.first = tc ? tc->first : 0;
@@ -814,16 +815,27 @@ int ttr_hadamard(ttr_handle *h, const ttr_tt *X, const ttr_tt *Y, ttr_tt *Z) {
   return TTR_OK;
 }
 
+static bool any_rank_above(const ttr_tt *X, int64_t r) {
+  for (int n = 0; n <= X->N; ++n)
+    if (X->R[n] > r) return true;
+  return false;
+}
+
 int ttr_dot(ttr_handle *h, const ttr_tt *X, const ttr_tt *Y, double *out) {
   int rc;
   if ((rc = handle_ok(h))) return rc;
   if (!out) return fail(TTR_ERR_INVALID_ARG, "out is NULL");
-  if ((rc = check_tt(X, "X", TTR_MAX_RANK))) return rc;
-  if ((rc = check_tt(Y, "Y", TTR_MAX_RANK))) return rc;
+  if ((rc = check_tt(X, "X", TTR_MAX_RANK_LARGE))) return rc;
+  if ((rc = check_tt(Y, "Y", TTR_MAX_RANK_LARGE))) return rc;
   if (X->N != Y->N) return fail(TTR_ERR_SHAPE, "X and Y differ in N");
   for (int n = 0; n < X->N; ++n)
     if (X->I[n] != Y->I[n]) return fail(TTR_ERR_SHAPE, "X and Y differ in mode sizes");
   const int N = X->N;
+  if (any_rank_above(X, TTR_MAX_RANK) || any_rank_above(Y, TTR_MAX_RANK)) {
+    rc = ttr_dot_large(h, X, Y, out);
+    prof_resolve(h);
+    return rc;
+  }
   if ((rc = ensure_ws(h, ws_doubles(N, 0) * sizeof(double)))) return rc;
   WS w = carve(h, N, 0);
   h->scal_host[0] = 1.0;
@@ -895,7 +907,9 @@ int ttr_norm(ttr_handle *h, const ttr_tt *X, int method, double *out) {
     // and F_{n-1} upper triangular, F^T F = W_{n-1} (§3.2.4, symmetric form):
     // the streaming Gram kernel skips the zero half of F, the Gram itself is
     // formed on the lower block triangle only
-    if ((rc = check_tt(X, "X", TTR_MAX_RANK))) return rc;
+    if ((rc = check_tt(X, "X", TTR_MAX_RANK_LARGE))) return rc;
+    if (any_rank_above(X, TTR_MAX_RANK))
+      return fail(TTR_ERR_UNSUPPORTED, "TTR_NORM_SYM supports ranks up to TTR_MAX_RANK");
     const int N = X->N;
     if ((rc = ensure_ws(h, ws_doubles(N, 0) * sizeof(double)))) return rc;
     WS w = carve(h, N, 0);
@@ -917,8 +931,14 @@ int ttr_norm(ttr_handle *h, const ttr_tt *X, int method, double *out) {
     return TTR_OK;
   }
   if (method != TTR_NORM_ORTHO) return fail(TTR_ERR_INVALID_ARG, "unknown norm method");
-  if ((rc = check_tt(X, "X", TTR_MAX_RANK))) return rc;
+  if ((rc = check_tt(X, "X", TTR_MAX_RANK_LARGE))) return rc;
   const int N = X->N;
+  if (any_rank_above(X, TTR_MAX_RANK)) {
+    if ((rc = reset_dec(h))) return rc;
+    rc = ttr_norm_ortho_large(h, X, out);
+    prof_resolve(h);
+    return rc;
+  }
   const size_t mat = max_core(X);
   if ((rc = ensure_ws(h, ws_doubles(N, 0, mat) * sizeof(double)))) return rc;
   WS w = carve(h, N, 0, mat);
@@ -947,9 +967,15 @@ int ttr_orthogonalize(ttr_handle *h, ttr_tt *X, int side, int prec) {
   if ((rc = handle_ok(h))) return rc;
   if (side != TTR_RIGHT && side != TTR_LEFT) return fail(TTR_ERR_INVALID_ARG, "side must be TTR_RIGHT or TTR_LEFT");
   if (prec != TTR_FP64) return fail(TTR_ERR_INVALID_ARG, "ttr_orthogonalize supports TTR_FP64");
-  if ((rc = check_tt(X, "X", TTR_MAX_RANK))) return rc;
+  if ((rc = check_tt(X, "X", TTR_MAX_RANK_LARGE))) return rc;
   const int N = X->N;
   if (N == 1) return TTR_OK;
+  if (any_rank_above(X, TTR_MAX_RANK)) {
+    if ((rc = reset_dec(h))) return rc;
+    rc = ttr_orthogonalize_large(h, X, side);
+    prof_resolve(h);
+    return rc;
+  }
   const size_t tmp = max_core(X);
   if ((rc = ensure_ws(h, ws_doubles(N, tmp, tmp) * sizeof(double)))) return rc;
   WS w = carve(h, N, tmp, tmp);
@@ -994,10 +1020,9 @@ int ttr_round(ttr_handle *h, const ttr_tt *X, double tol, int direction, int pre
   }
   std::memset(&h->stats, 0, sizeof(h->stats));
   if (rmax > TTR_MAX_RANK && N > 1) {
-    // ranks above the tiled kernels' range: the GEMM-based path (RLR, FP64)
-    if (direction != TTR_RLR) return fail(TTR_ERR_UNSUPPORTED, "ranks above TTR_MAX_RANK support TTR_RLR");
+    // ranks above the register-tiled kernels' range: the unfolding-based path
     if ((rc = reset_dec(h))) return rc;
-    rc = ttr_round_large(h, X, tol, Y, norm_out);
+    rc = ttr_round_large(h, X, tol, direction, prec, Y, norm_out);
     prof_resolve(h);
     return rc;
   }

@@ -123,6 +123,7 @@ __device__ QrStepArgs qr_args(const BState &S, int pass, int d, int b, const dou
   q.ugram = u;
   q.gerr = gram_err_dev(S.spw[n], contracted, u, S.nwg[n]);
   q.try_chol = 1;
+  q.shift_pass = S.f32 ? 2 : 1;
   q.notrunc_check = 0;
   q.delta_dev = nullptr;
   q.first = 0;

@@ -89,6 +89,29 @@ int dot_mfma_workgroups(long long I);
 int launch_dot_mfma(hipStream_t s, const double *X, int a, int b, const double *Y, int c, int e, long long I,
                     const double *W, double *partials);
 
+// --- rank 65..256 streaming kernels (ttr_lstream.hip) ----------------------
+// Z (M x N) = X (M x K) B (K x N), K, N <= 256.  X: column-major (xcol, element
+// (r, k) at X[r + ldx k]) or row-major (X[r ldx + k]); Z likewise (zcol, ldz).
+// B(k, c) = B[k bsr + c bsc]; tri: B lower triangular.  Bp: scratch of
+// lg_packed_doubles(K, N) doubles for B in fragment order.
+size_t lg_packed_doubles(int K, int N);
+void launch_lg_gemm(hipStream_t s, const double *X, long long M, int K, long long ldx, int xcol, const double *B,
+                    long long bsr, long long bsc, int N, int tri, double *Bp, double *Z, long long ldz, int zcol);
+struct LGramGrid {
+  int nwg;
+  long long rpw;  // rows per workgroup (multiple of 16)
+};
+LGramGrid lg_gram_grid(long long M, int f32);
+// Partial matrices of X1^T X2 (K1 x K2, column-major) over row ranges of
+// lg_gram_grid(M, f32).rpw rows into part (nwg x K1 K2 doubles); X2 == nullptr:
+// the Gram of X1 (symmetric; f32: FP32 products and accumulation).  Both
+// operands share the layout xcol and have M rows.  Returns nwg.
+int launch_lg_gram(hipStream_t s, const double *X1, const double *X2, long long M, int K1, int K2, long long ld1,
+                   long long ld2, int xcol, int f32, double *part);
+// C (m x n, ld ldc) = A B, A(i, k) = A[i ar + k ac], B(k, j) = B[k br + j bc].
+void launch_lg_sgemm(hipStream_t s, const double *A, long long ar, long long ac, const double *B, long long br,
+                     long long bc, int m, int n, int k, double *C, long long ldc);
+
 // --- small dense kernels (ttr_small.hip) ----------------------------------
 // One step of QR-by-Gram.  G (d x d) is the Gram of the current staged
 // unfolding A*F_1*...*F_{j-1} (j = pass).  Writes the next stage F_j
@@ -120,6 +143,9 @@ struct QrStepArgs {
   double ugram;        // unit roundoff of the arithmetic that formed G (FP64 or FP32)
   double gerr;         // |G_computed - G| <= gerr * trace(G), for the no-truncation proof
   int try_chol;        // pass 1: try the Cholesky route first
+  int shift_pass;      // last pass that may take the shifted route (1; 2 in mixed
+                       // precision, where pass 1's FP32 shift leaves directions
+                       // below ~u32 that one FP64 pass cannot resolve)
   // truncation sweep only: with the Cholesky route, also prove that no
   // singular value can be dropped at this link (lambda_min(G) >= 1/||L^{-1}||_F^2
   // > margin * delta^2); delta is *delta_dev, or at the first link

@@ -25,8 +25,6 @@
 // workgroups, one launch per round.
 #include "ttr_host.h"
 
-#include <rocblas/rocblas.h>
-
 #include <algorithm>
 #include <array>
 #include <cfloat>
@@ -414,6 +412,7 @@ struct LStepArgs {
   int *dec;            // [0] k, [1] settled, [2] error flags, [5] no truncation proven,
                        // [8] R left to the host: 1 = L^T Rc, 2 = L(:, 0:k)^T Rp
   double tau1, tau2, ugram, gerr;
+  int shift_pass;      // last pass that may take the shifted route (2 in mixed precision)
   int notrunc_check;
   const double *delta_dev;
   int first;
@@ -527,7 +526,7 @@ __global__ __launch_bounds__(kLT) void lk_step(LStepArgs a) {
     A[e] = (r >= c) ? a.G[e] : a.G[c + (size_t)d * r];
   }
   __syncthreads();
-  if (a.pass == 1) {
+  if (a.pass <= a.shift_pass) {
     // shifted CholeskyQR: the next pass refines
     const double shift = 2.0 * d * a.ugram * trG;
     for (int j = threadIdx.x; j < d; j += blockDim.x) A[j + (size_t)d * j] += shift;
@@ -537,13 +536,13 @@ __global__ __launch_bounds__(kLT) void lk_step(LStepArgs a) {
       for (int e = threadIdx.x; e < d * d; e += blockDim.x) {
         const int r = e % d, c = e / d;
         a.Fstep[r + (size_t)d * c] = X[c + (size_t)d * r];
-        a.Rnext[r + (size_t)d * c] = A[c + (size_t)d * r];
+        if (!a.Rc) a.Rnext[r + (size_t)d * c] = A[c + (size_t)d * r];  // R = L^T (Rc = I)
       }
       if (threadIdx.x == 0) {
         a.dec[0] = d;
         a.dec[1] = 0;
         a.dec[5] = 0;
-        a.dec[8] = 0;
+        a.dec[8] = a.Rc ? 1 : 0;  // a refinement pass: R = L^T Rc by the host's product
       }
       return;
     }
@@ -714,90 +713,82 @@ __device__ inline void lrr_pair(int r, int kq, int nn, int *p, int *q) {
 // One round of the block one-sided Jacobi SVD of A (b x k): the k columns form
 // nbp (even) blocks of kJW; round `round` of the round-robin pairs block P
 // with block Q in workgroup `pair`, which runs one one-sided Jacobi sweep over
-// the 2 kJW columns in LDS (rotations also applied to the same columns of U)
-// and writes them back.  A pair of columns is rotated
-// when |a_p^T a_q| > thr[0] ||a_p|| ||a_q|| and both squared norms exceed
-// thr[1].  *flag is set when any rotation was applied.
-constexpr int kJW = 8;
-constexpr int kJT = 256;
+// the 2 kJW columns held in LDS (rotations also applied to the same columns of
+// U) and writes them back.  Each inner step rotates 2 kJW / 2 disjoint column
+// pairs at once, one wave per pair: the wave's lanes hold rows l, l + 64, ...,
+// and the three inner products are wave sums.  A pair is rotated when
+// |a_p^T a_q| > thr[0] ||a_p|| ||a_q|| and both squared norms exceed thr[1].
+// flags[sweep] is set when any rotation was applied; a launch of sweep s > 0
+// returns at once when sweep s - 1 applied none (converged), so the host can
+// queue several sweeps before it looks.
+constexpr int kJW = 16;
+constexpr int kJT = kJW * 64;  // one wave per column pair of the block pair
+__device__ inline void lwave_sum3(double &a, double &b, double &c) {
+  for (int off = 32; off >= 1; off >>= 1) {
+    a += __shfl_xor(a, off, 64);
+    b += __shfl_xor(b, off, 64);
+    c += __shfl_xor(c, off, 64);
+  }
+}
 __global__ __launch_bounds__(kJT) void lk_jacobi_round(double *__restrict__ A, double *__restrict__ U, int b, int k,
                                                        int nbp, int round, const double *__restrict__ thr,
-                                                       int *__restrict__ flag) {
+                                                       int *__restrict__ flags, int sweep) {
+  if (sweep > 0 && flags[sweep - 1] == 0) return;
   constexpr int NC = 2 * kJW;
   __shared__ double As[NC][kLMax];
   __shared__ double Us[NC][kLMax];
-  __shared__ int rotated, any;
   int P, Q;
   lrr_pair(round, blockIdx.x, nbp, &P, &Q);
   auto gcol = [&](int l) { return l < kJW ? P * kJW + l : Q * kJW + (l - kJW); };
-  for (int e = threadIdx.x; e < NC * b; e += blockDim.x) {
-    const int l = e / b, r = e % b, c = gcol(l);
-    As[l][r] = (c < k) ? A[r + (size_t)b * c] : 0.0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // column l of the pair is loaded by wave l % 16 (two columns per wave)
+  for (int l = wave; l < NC; l += kJW) {
+    const int c = gcol(l);
+    for (int r = lane; r < b; r += 64) As[l][r] = (c < k) ? A[r + (size_t)b * c] : 0.0;
+    for (int r = lane; r < k; r += 64) Us[l][r] = (c < k) ? U[r + (size_t)k * c] : 0.0;
   }
-  for (int e = threadIdx.x; e < NC * k; e += blockDim.x) {
-    const int l = e / k, r = e % k, c = gcol(l);
-    Us[l][r] = (c < k) ? U[r + (size_t)k * c] : 0.0;
-  }
-  if (threadIdx.x == 0) any = 0;
   const double tol = thr[0], floor2 = thr[1];
-  // 8 column pairs per inner round, 32 threads per pair
-  const int lp = threadIdx.x >> 5, sub = threadIdx.x & 31;
+  int rotated = 0;
   __syncthreads();
-  // one inner sweep per block pair (measured fastest: the outer sweeps
-  // converge at the same rate with more inner sweeps)
-  for (int sw = 0; sw < 1; ++sw) {
-    if (threadIdx.x == 0) rotated = 0;
-    __syncthreads();
-    for (int rr = 0; rr < NC - 1; ++rr) {
-      int p, q;
-      lrr_pair(rr, lp, NC, &p, &q);
-      const bool act = gcol(p) < k && gcol(q) < k;
+  for (int rr = 0; rr < NC - 1; ++rr) {
+    int p, q;
+    lrr_pair(rr, wave, NC, &p, &q);
+    if (gcol(p) < k && gcol(q) < k) {
       double al = 0.0, be = 0.0, ga = 0.0;
-      if (act)
-        for (int r = sub; r < b; r += 32) {
-          const double x = As[p][r], y = As[q][r];
-          al += x * x;
-          be += y * y;
-          ga += x * y;
-        }
-      for (int off = 1; off < 32; off <<= 1) {
-        al += __shfl_xor(al, off, 64);
-        be += __shfl_xor(be, off, 64);
-        ga += __shfl_xor(ga, off, 64);
+      for (int r = lane; r < b; r += 64) {
+        const double x = As[p][r], y = As[q][r];
+        al += x * x;
+        be += y * y;
+        ga += x * y;
       }
-      if (act && al > floor2 && be > floor2 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
+      lwave_sum3(al, be, ga);
+      if (al > floor2 && be > floor2 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
         const double zeta = (be - al) / (2.0 * ga);
         const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
         const double c = 1.0 / sqrt(1.0 + t * t);
         const double sn = c * t;
-        for (int r = sub; r < b; r += 32) {
+        for (int r = lane; r < b; r += 64) {
           const double x = As[p][r], y = As[q][r];
           As[p][r] = c * x - sn * y;
           As[q][r] = sn * x + c * y;
         }
-        for (int r = sub; r < k; r += 32) {
+        for (int r = lane; r < k; r += 64) {
           const double x = Us[p][r], y = Us[q][r];
           Us[p][r] = c * x - sn * y;
           Us[q][r] = sn * x + c * y;
         }
-        if (sub == 0) rotated = 1;
+        rotated = 1;
       }
-      __syncthreads();
     }
-    const int rot = rotated;
-    if (rot && threadIdx.x == 0) any = 1;
     __syncthreads();
-    if (!rot) break;
   }
-  for (int e = threadIdx.x; e < NC * b; e += blockDim.x) {
-    const int l = e / b, r = e % b, c = gcol(l);
-    if (c < k) A[r + (size_t)b * c] = As[l][r];
+  for (int l = wave; l < NC; l += kJW) {
+    const int c = gcol(l);
+    if (c >= k) continue;
+    for (int r = lane; r < b; r += 64) A[r + (size_t)b * c] = As[l][r];
+    for (int r = lane; r < k; r += 64) U[r + (size_t)k * c] = Us[l][r];
   }
-  for (int e = threadIdx.x; e < NC * k; e += blockDim.x) {
-    const int l = e / k, r = e % k, c = gcol(l);
-    if (c < k) U[r + (size_t)k * c] = Us[l][r];
-  }
-  if (threadIdx.x == 0 && any) *flag = 1;
+  if (rotated && lane == 0) flags[sweep] = 1;
 }
 
 // Truncation, part 3 (after the Jacobi sweeps): singular values (column norms
@@ -870,21 +861,23 @@ __global__ void lk_transpose(const double *__restrict__ S, int rows, int cols, i
 
 // --- host -------------------------------------------------------------------
 constexpr size_t kSlotL = (size_t)kLMax * kLMax;
-constexpr int kChunks = 256;  // chunk Grams per streamed Gram
+constexpr int kMaxSweeps = 60;
+constexpr int kSweepGroup = 4;  // Jacobi sweeps queued between host checks
 
-struct LWS {
-  double *tC, *tA, *tB;  // materialized cores (max core each)
-  double *G, *Ra, *Rb, *Gst[3], *P[2], *GU, *W0, *W1, *Up, *Ap, *scal, *sigma, *tails, *sv;
-  double *part;  // kChunks chunk Grams
-  std::vector<double *> T;                 // N+1 slots
-  std::vector<std::array<double *, 3>> B;  // N x 3 slots
-  int *perm;
+// A logical core: slice M'(i) = M(i) (trans = 0) or M(i)^T (trans = 1) of the
+// physical pa x I x pb core at X.  LRL rounding and left orthonormalization
+// run the RLR / right algorithm on the reversed train of transposed slices.
+struct LView {
+  const double *X;
+  long long I;
+  int pa, pb, trans;
+  int ea() const { return trans ? pb : pa; }
+  int eb() const { return trans ? pa : pb; }
 };
 
 }  // namespace
 
 struct LargeCtx {
-  rocblas_handle rb = nullptr;
   double *mem = nullptr;
   size_t bytes = 0;
 };
@@ -892,7 +885,6 @@ struct LargeCtx {
 void ttr_large_release(ttr_handle *h) {
   if (!h || !h->large) return;
   LargeCtx *c = h->large;
-  if (c->rb) rocblas_destroy_handle(c->rb);
   if (c->mem) ttr_dev_free(h, c->mem);
   delete c;
   h->large = nullptr;
@@ -900,53 +892,127 @@ void ttr_large_release(ttr_handle *h) {
 
 namespace {
 
-#define RBCHK(expr)                                                                           \
-  do {                                                                                        \
-    rocblas_status s_ = (expr);                                                               \
-    if (s_ != rocblas_status_success)                                                         \
-      return ttr_fail(TTR_ERR_HIP, std::string(#expr) + ": " + rocblas_status_to_string(s_)); \
-  } while (0)
+constexpr double kU32 = 5.9604644775390625e-08;  // 2^-24
+constexpr double kTauMix = 1e-5;
 
 struct Large {
-  ttr_handle *h;
-  rocblas_handle rb;
-  LWS w;
-  int passes = 0, applies = 0;
+  ttr_handle *h = nullptr;
+  // workspace
+  double *G, *Ra, *Rb, *Gst[3], *P[2], *GU, *W0, *W1, *Up, *Ap, *scal, *sigma, *tails, *sv, *Bp, *part;
+  double *tC, *tA, *tB;
+  int *perm, *flags;
+  std::vector<double *> T;                 // N+1 slots
+  std::vector<std::array<double *, 3>> B;  // N x 3 slots
+  int passes = 0, applies = 0, sweeps = 0;
 
-  // C (m x n, ld ldc) = op(A) op(B), op(A) m x k
-  int gemm(bool ta, bool tb, long long m, long long n, long long k, const double *A, long long lda, const double *B,
-           long long ldb, double *C, long long ldc) {
-    const double one = 1.0, zero = 0.0;
-    RBCHK(rocblas_dgemm(rb, ta ? rocblas_operation_transpose : rocblas_operation_none,
-                        tb ? rocblas_operation_transpose : rocblas_operation_none, (rocblas_int)m, (rocblas_int)n,
-                        (rocblas_int)k, &one, A, (rocblas_int)lda, B, (rocblas_int)ldb, &zero, C, (rocblas_int)ldc));
+  int setup(int N, size_t mc) {
+    mc = (mc + 63) & ~(size_t)63;
+    const size_t need = (14 + (size_t)(N + 1) + 3 * (size_t)N) * kSlotL + 64 + (size_t)(N + 1) * (kLMax + 1) +
+                        3 * (size_t)kLMax + lg_packed_doubles(kLMax, kLMax) + (size_t)512 * kSlotL + 3 * mc + 256;
+    if (!h->large) h->large = new LargeCtx();
+    LargeCtx *ctx = h->large;
+    if (ctx->bytes < need * sizeof(double)) {
+      if (ctx->mem) {
+        TTR_HIPCHK(hipStreamSynchronize(h->stream));
+        ttr_dev_free(h, ctx->mem);
+        ctx->mem = nullptr;
+        ctx->bytes = 0;
+      }
+      void *m = nullptr;
+      int arc;
+      if ((arc = ttr_dev_alloc(h, &m, need * sizeof(double)))) return arc;
+      ctx->mem = static_cast<double *>(m);
+      ctx->bytes = need * sizeof(double);
+    }
+    double *p = ctx->mem;
+    auto take = [&](size_t n) {
+      double *q = p;
+      p += (n + 31) & ~(size_t)31;
+      return q;
+    };
+    G = take(kSlotL);
+    Ra = take(kSlotL);
+    Rb = take(kSlotL);
+    for (int j = 0; j < 3; ++j) Gst[j] = take(kSlotL);
+    for (int j = 0; j < 2; ++j) P[j] = take(kSlotL);
+    GU = take(kSlotL);
+    W0 = take(kSlotL);
+    W1 = take(kSlotL);
+    Up = take(kSlotL);
+    Ap = take(kSlotL);
+    scal = take(64);
+    sigma = take((size_t)(N + 1) * kLMax);
+    tails = take((size_t)(N + 1));
+    sv = take(kLMax);
+    perm = reinterpret_cast<int *>(take(kLMax));
+    flags = reinterpret_cast<int *>(take(kLMax));
+    Bp = take(lg_packed_doubles(kLMax, kLMax));
+    T.resize(N + 1);
+    B.resize(N);
+    for (int n = 0; n <= N; ++n) T[n] = take(kSlotL);
+    for (int n = 0; n < N; ++n)
+      for (int j = 0; j < 3; ++j) B[n][j] = take(kSlotL);
+    part = take((size_t)512 * kSlotL);
+    tC = take(mc);
+    tA = take(mc);
+    tB = take(mc);
+    for (int i = 0; i < 16; ++i) h->dec_host[i] = 0;
+    TTR_HIPCHK(hipMemcpyAsync(h->dec_dev, h->dec_host, 16 * sizeof(int), hipMemcpyHostToDevice, h->stream));
     return TTR_OK;
   }
-  // G (n x n) = Z Z^T (trans = false: Z n x k, ld ldz) or Z^T Z (trans = true:
-  // Z k x n, ld ldz).  k is in the millions and n <= 256, so the sum over k is
-  // split into chunks: one strided-batched GEMM gives the chunk Grams, and the
-  // fixed-order reduction adds them.
-  int gram(bool trans, long long n, long long k, const double *Z, long long ldz, double *G) {
-    const double one = 1.0, zero = 0.0;
-    long long S = std::min<long long>(kChunks, std::max<long long>(1, k / 2048));
-    const long long ks = (k + S - 1) / S;
-    const long long full = k / ks, rem = k - full * ks;
-    const long long nn = n * n;
-    const rocblas_operation tA = trans ? rocblas_operation_transpose : rocblas_operation_none;
-    const rocblas_operation tB = trans ? rocblas_operation_none : rocblas_operation_transpose;
-    const long long step = trans ? ks : ks * ldz;  // offset between chunks
-    if (full > 0)
-      RBCHK(rocblas_dgemm_strided_batched(rb, tA, tB, (rocblas_int)n, (rocblas_int)n, (rocblas_int)ks, &one, Z,
-                                          (rocblas_int)ldz, step, Z, (rocblas_int)ldz, step, &zero, w.part,
-                                          (rocblas_int)n, nn, (rocblas_int)full));
-    if (rem > 0) {
-      const double *Zr = Z + full * step;
-      RBCHK(rocblas_dgemm(rb, tA, tB, (rocblas_int)n, (rocblas_int)n, (rocblas_int)rem, &one, Zr, (rocblas_int)ldz, Zr,
-                          (rocblas_int)ldz, &zero, w.part + full * nn, (rocblas_int)n));
+
+  // C (m x n, ld ldc) = op(A) op(B), op(A) m x k, A and B column-major
+  void sgemm(bool ta, bool tb, int m, int n, int k, const double *A, long long lda, const double *Bm, long long ldb,
+             double *C, long long ldc) {
+    launch_lg_sgemm(h->stream, A, ta ? lda : 1, ta ? 1 : lda, Bm, tb ? ldb : 1, tb ? 1 : ldb, m, n, k, C, ldc);
+  }
+  // Z'(i) = M'(i) B (B(k, c) = B[k bsr + c bsc], eb x n) into `out`, in the
+  // view's orientation; tri: B lower triangular.
+  LView right(const LView &v, const double *Bm, long long bsr, long long bsc, int n, int tri, double *out) {
+    if (!v.trans) {
+      // V(Z) = V(M) B
+      launch_lg_gemm(h->stream, v.X, (long long)v.pa * v.I, v.pb, (long long)v.pa * v.I, 1, Bm, bsr, bsc, n, tri, Bp,
+                     out, (long long)v.pa * v.I, 1);
+      return LView{out, v.I, v.pa, n, 0};
     }
-    launch_reduce(h->stream, w.part, (int)(full + (rem > 0)), (int)nn, G);
+    // Z(i) = B^T M(i): H(Z)^T = H(M)^T B
+    launch_lg_gemm(h->stream, v.X, v.I * v.pb, v.pa, v.pa, 0, Bm, bsr, bsc, n, tri, Bp, out, n, 0);
+    return LView{out, v.I, n, v.pb, 1};
+  }
+  // Z'(i) = A M'(i) (A(r, c) = A[r asr + c asc], m x ea) into `out`.
+  LView left(const LView &v, const double *Am, long long asr, long long asc, int m, double *out) {
+    if (!v.trans) {
+      // H(Z)^T = H(M)^T A^T
+      launch_lg_gemm(h->stream, v.X, v.I * v.pb, v.pa, v.pa, 0, Am, asc, asr, m, 0, Bp, out, m, 0);
+      return LView{out, v.I, m, v.pb, 0};
+    }
+    // Z(i) = M(i) A^T: V(Z) = V(M) A^T
+    launch_lg_gemm(h->stream, v.X, (long long)v.pa * v.I, v.pb, (long long)v.pa * v.I, 1, Am, asc, asr, m, 0, Bp, out,
+                   (long long)v.pa * v.I, 1);
+    return LView{out, v.I, v.pa, m, 1};
+  }
+  // G (ea x ea) = sum_i M'(i) M'(i)^T (left) or (eb x eb) = sum_i M'(i)^T M'(i)
+  // (right); *gerr = bound on the rounding error relative to the trace
+  void gram(const LView &v, bool left_side, int f32, double *Gout, double *gerr) {
+    // physical: H(M) H(M)^T (row-major H(M)^T) or V(M)^T V(M) (column-major V(M))
+    const bool use_h = (left_side != (v.trans != 0));
+    long long M;
+    int K, nwg;
+    if (use_h) {
+      M = v.I * v.pb;
+      K = v.pa;
+      nwg = launch_lg_gram(h->stream, v.X, nullptr, M, K, K, v.pa, v.pa, 0, f32, part);
+    } else {
+      M = (long long)v.pa * v.I;
+      K = v.pb;
+      nwg = launch_lg_gram(h->stream, v.X, nullptr, M, K, K, M, M, 1, f32, part);
+    }
+    launch_reduce(h->stream, part, nwg, K * K, Gout);
+    const LGramGrid g = lg_gram_grid(M, f32);
+    // per entry: the workgroup's sequential sum over its rows, then the
+    // fixed-order sum of the partials (FP32: inputs rounded too)
+    *gerr = 2.0 * ((double)g.rpw + (double)nwg + 18.0) * (f32 ? kU32 : kU);
     ++passes;
-    return TTR_OK;
   }
   int sync_dec() {
     TTR_HIPCHK(hipMemcpyAsync(h->dec_host, h->dec_dev, 16 * sizeof(int), hipMemcpyDeviceToHost, h->stream));
@@ -957,30 +1023,37 @@ struct Large {
     return TTR_OK;
   }
   // One-sided Jacobi SVD of A = W0 (b x k) with U = W1: sweeps of block
-  // rounds until a sweep applies no rotation.
-  int sweeps = 0;  // of the last jacobi() call
+  // rounds until a sweep applies no rotation, checked on the device (a sweep
+  // after the converged one returns at once); the host looks every few sweeps.
   int jacobi(long long b, int k) {
-    int *flag = reinterpret_cast<int *>(w.scal + 16);
     const int nbp = std::max(2, 2 * ((k + 2 * kJW - 1) / (2 * kJW)));
-    for (int sweep = 0; sweep < 60; ++sweep) {
-      TTR_HIPCHK(hipMemsetAsync(flag, 0, sizeof(int), h->stream));
-      for (int r = 0; r < nbp - 1; ++r)
-        hipLaunchKernelGGL(lk_jacobi_round, dim3(nbp / 2), dim3(kJT), 0, h->stream, w.W0, w.W1, (int)b, k, nbp, r,
-                           w.scal + 8, flag);
+    TTR_HIPCHK(hipMemsetAsync(flags, 0, kMaxSweeps * sizeof(int), h->stream));
+    int hf[kMaxSweeps];
+    for (int sweep = 0; sweep < kMaxSweeps;) {
+      const int end = std::min(kMaxSweeps, sweep + kSweepGroup);
+      for (; sweep < end; ++sweep)
+        for (int r = 0; r < nbp - 1; ++r)
+          hipLaunchKernelGGL(lk_jacobi_round, dim3(nbp / 2), dim3(kJT), 0, h->stream, W0, W1, (int)b, k, nbp, r,
+                             scal + 8, flags, sweep);
       TTR_HIPCHK(hipGetLastError());
-      h->stats.small_launches += nbp - 1;
-      int f = 0;
-      TTR_HIPCHK(hipMemcpyAsync(&f, flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+      h->stats.small_launches += (nbp - 1) * kSweepGroup;
+      TTR_HIPCHK(hipMemcpyAsync(hf, flags, sweep * sizeof(int), hipMemcpyDeviceToHost, h->stream));
       TTR_HIPCHK(hipStreamSynchronize(h->stream));
-      sweeps = sweep + 1;
-      if (!f) return TTR_OK;
+      for (int s = 0; s < sweep; ++s)
+        if (!hf[s]) {
+          sweeps = s + 1;
+          return TTR_OK;
+        }
     }
     return ttr_fail(TTR_ERR_NUMERICAL, "the truncation SVD did not converge");
   }
+  // One QR-by-Gram step on the Gram in G (d x d).  *pivoted is set when the
+  // step took the pivoted route (its factor is not triangular).
+  int mixed = 0;  // TTR_MIXED: FP32 first passes
   int step(const double *Rc, int d, int b, int pass, double *F, double *Rn, double *Tdst, double gerr, int check,
-           int first, double tol2_nm1) {
+           int first, double tol2_nm1, int f32, int *pivoted) {
     LStepArgs a;
-    a.G = w.G;
+    a.G = G;
     a.d = d;
     a.pass = pass;
     a.b = b;
@@ -989,26 +1062,29 @@ struct Large {
     a.Rnext = Rn;
     a.Tdst = Tdst;
     a.dec = h->dec_dev;
-    a.tau1 = kTau1;
+    const double u = f32 ? kU32 : kU;
+    a.tau1 = f32 ? u / kTauMix : kTau1;
     a.tau2 = kTau2;
-    a.ugram = kU;
+    a.ugram = u;
     a.gerr = gerr;
+    a.shift_pass = mixed ? 2 : 1;
     a.notrunc_check = check;
-    a.delta_dev = w.scal + 1;
+    a.delta_dev = scal + 1;
     a.first = first;
     a.tol2_nm1 = tol2_nm1;
-    a.W0 = w.W0;
-    a.W1 = w.W1;
-    a.perm = w.perm;
-    a.Rp = w.Ap;
+    a.W0 = W0;
+    a.W1 = W1;
+    a.perm = perm;
+    a.Rp = Ap;
     hipLaunchKernelGGL(lk_step, dim3(1), dim3(kLT), 0, h->stream, a);
     h->stats.small_launches++;
     int rc;
     if ((rc = sync_dec())) return rc;
     const int how = h->dec_host[8], kk = h->dec_host[0];
+    if (pivoted && (how == 2 || kk < d)) *pivoted = 1;
     if (how == 0) return TTR_OK;
     // R = L^T Rc (d x b) or R' = L(:, 0:k)^T Rp (k x b), L lower in W0 (ld d)
-    if ((rc = gemm(true, false, kk, b, d, w.W0, d, how == 1 ? Rc : w.Ap, d, Rn, kk))) return rc;
+    sgemm(true, false, kk, b, d, W0, d, how == 1 ? Rc : Ap, d, Rn, kk);
     if (Tdst && h->dec_host[1]) {
       hipLaunchKernelGGL(lk_transpose, dim3(64), dim3(256), 0, h->stream, Rn, kk, b, kk, Tdst, b);
       TTR_HIPCHK(hipGetLastError());
@@ -1017,189 +1093,182 @@ struct Large {
   }
 };
 
-// rounding of a Gram entry summed over nacc products (any summation order)
-double gerr_of(long long nacc) { return 2.0 * ((double)nacc + 16.0) * kU; }
+// Per-core factorization record of the orthonormalization sweep.
+struct LFac {
+  int nst = 1;
+  int dim[4] = {0, 0, 0, 0};
+  int tri = 0;  // T_n = R^T is lower triangular (no pivoted pass)
+};
+
+// Orthonormalization sweep over logical cores N-1..1 (§2.3 Alg. 1 order)
+// with implicit factors (§3.5 Alg. 6): core n's QR-by-Gram of H(C_n)^T,
+// C_n(i) = M_n(i) T_{n+1}; the stages F_j (slots B[n][j]) and T_n = R^T
+// (slot T[n]) are kept.  `rev`: the mirror image (reversed train of
+// transposed slices).  When `out` is given, each orthonormal core
+// F_nst^T .. F_1^T C_n is written to out->core (in the view's orientation,
+// §3.4 Alg. 5).
+int orth_sweep_large(Large &L, const ttr_tt *X, int rev, int prec, std::vector<int> &k, std::vector<LFac> &fac,
+                     ttr_tt *out) {
+  ttr_handle *h = L.h;
+  const int N = X->N;
+  auto phys = [&](int n) { return rev ? N - 1 - n : n; };
+  auto view = [&](int n) {
+    const int p = phys(n);
+    return LView{X->core[p], X->I[p], (int)X->R[p], (int)X->R[p + 1], rev};
+  };
+  k.assign(N + 1, 1);
+  fac.assign(N + 1, LFac());
+  for (int n = 0; n <= N; ++n) k[n] = (int)(rev ? X->R[N - n] : X->R[n]);
+  int rc;
+  for (int n = N - 1; n >= 1; --n) {
+    const LView v = view(n);
+    const int a = v.ea(), b = v.eb();
+    LView cur = v;
+    if (n < N - 1) cur = L.right(v, L.T[n + 1], 1, b, k[n + 1], fac[n + 1].tri, L.tC);
+    double *bufs[2] = {L.tA, L.tB};
+    double *R[2] = {L.Ra, L.Rb};
+    fac[n].dim[0] = a;
+    int pass = 1, pivoted = 0;
+    for (;; ++pass) {
+      double gerr;
+      const int f32 = (prec == TTR_MIXED && pass == 1);
+      L.gram(cur, true, f32, L.G, &gerr);
+      if ((rc = L.step(pass == 1 ? nullptr : R[pass & 1], cur.ea(), a, pass, L.B[n][pass - 1], R[(pass - 1) & 1],
+                       L.T[n], gerr, 0, 0, 0.0, f32, &pivoted)))
+        return rc;
+      const int kk = h->dec_host[0];
+      fac[n].dim[pass] = kk;
+      if (h->dec_host[1]) break;
+      if (pass >= 3) return ttr_fail(TTR_ERR_NUMERICAL, "QR-by-Gram did not settle in three passes");
+      // D = F_pass^T C (materialized; the next pass measures its Gram)
+      cur = L.left(cur, L.B[n][pass - 1], cur.ea(), 1, kk, bufs[(pass - 1) & 1]);
+    }
+    fac[n].nst = pass;
+    fac[n].tri = !pivoted;
+    k[n] = fac[n].dim[pass];
+    if (out) {
+      // the orthonormal core: the last stage applied to what its Gram measured
+      const int p = phys(n);
+      L.left(cur, L.B[n][pass - 1], cur.ea(), 1, k[n], L.tB == cur.X ? L.tA : L.tB);
+      const double *src = (L.tB == cur.X) ? L.tA : L.tB;
+      TTR_HIPCHK(hipMemcpyAsync(out->core[p], src, (size_t)k[n] * v.I * k[n + 1] * sizeof(double),
+                                hipMemcpyDeviceToDevice, h->stream));
+      ++L.applies;
+    }
+  }
+  return TTR_OK;
+}
+
+void fill_stats(ttr_handle *h, int N, int rev, const std::vector<double> &sig, const std::vector<double> &tails,
+                const std::vector<int> &sweeps) {
+  for (int l = 0; l < N - 1; ++l) {
+    const int pl = rev ? (N - 1 - l) - 1 : l;
+    if (pl >= TTR_STATS_LINKS) continue;
+    int cnt = 0;
+    for (int j = 0; j < kLMax; ++j) {
+      h->stats.sigma[(size_t)pl * TTR_STATS_SIGMA + j] = sig[(size_t)l * kLMax + j];
+      if (sig[(size_t)l * kLMax + j] > 0) cnt = j + 1;
+    }
+    h->stats.nsigma[pl] = cnt;
+    h->stats.tail2[pl] = tails[l];
+    h->stats.sweeps[pl] = sweeps[l];
+  }
+}
+
+size_t max_core_of(const ttr_tt *X) {
+  size_t mc = 0;
+  for (int n = 0; n < X->N; ++n) mc = std::max(mc, (size_t)(X->R[n] * X->I[n] * X->R[n + 1]));
+  return mc;
+}
 
 }  // namespace
 
-// Rounding of X (ranks up to 256, RLR) into Y; arithmetic in FP64.
-int ttr_round_large(ttr_handle *h, const ttr_tt *X, double tol, ttr_tt *Y, double *norm_out) {
+// Rounding of X (ranks up to 256) into Y (§2.4 Alg. 2; implicit factors of
+// §3.5 Alg. 6); RLR or its mirror LRL; prec TTR_MIXED runs the first Gram
+// pass of every factorization in FP32.
+int ttr_round_large(ttr_handle *h, const ttr_tt *X, double tol, int direction, int prec, ttr_tt *Y,
+                    double *norm_out) {
   const int N = X->N;
-  size_t mc = 0;
-  for (int n = 0; n < N; ++n) mc = std::max(mc, (size_t)(X->R[n] * X->I[n] * X->R[n + 1]));
-  mc = (mc + 63) & ~(size_t)63;
-  const size_t need = ((size_t)(N + 1) + 3 * (size_t)N + 15 + kChunks) * kSlotL + 64 + (size_t)(N + 1) * (kLMax + 1) +
-                      kLMax + kLMax + 3 * mc + 64;
-  if (!h->large) h->large = new LargeCtx();
-  LargeCtx *ctx = h->large;
-  if (!ctx->rb) RBCHK(rocblas_create_handle(&ctx->rb));
-  RBCHK(rocblas_set_stream(ctx->rb, h->stream));
-  RBCHK(rocblas_set_pointer_mode(ctx->rb, rocblas_pointer_mode_host));
-  if (ctx->bytes < need * sizeof(double)) {
-    if (ctx->mem) {
-      TTR_HIPCHK(hipStreamSynchronize(h->stream));
-      ttr_dev_free(h, ctx->mem);
-      ctx->mem = nullptr;
-      ctx->bytes = 0;
-    }
-    void *m = nullptr;
-    int arc;
-    if ((arc = ttr_dev_alloc(h, &m, need * sizeof(double)))) return arc;
-    ctx->mem = static_cast<double *>(m);
-    ctx->bytes = need * sizeof(double);
-  }
+  const int rev = (direction == TTR_LRL);
   Large L;
   L.h = h;
-  L.rb = ctx->rb;
-  LWS &w = L.w;
-  double *p = ctx->mem;
-  auto take = [&](size_t n) {
-    double *q = p;
-    p += n;
-    return q;
-  };
-  w.G = take(kSlotL);
-  w.Ra = take(kSlotL);
-  w.Rb = take(kSlotL);
-  for (int j = 0; j < 3; ++j) w.Gst[j] = take(kSlotL);
-  for (int j = 0; j < 2; ++j) w.P[j] = take(kSlotL);
-  w.GU = take(kSlotL);
-  w.W0 = take(kSlotL);
-  w.W1 = take(kSlotL);
-  w.Up = take(kSlotL);
-  w.Ap = take(kSlotL);
-  w.scal = take(64);
-  w.sigma = take((size_t)(N + 1) * kLMax);
-  w.tails = take((size_t)(N + 1));
-  w.sv = take(kLMax);
-  w.perm = reinterpret_cast<int *>(take(kLMax));
-  w.T.resize(N + 1);
-  w.B.resize(N);
-  for (int n = 0; n <= N; ++n) w.T[n] = take(kSlotL);
-  for (int n = 0; n < N; ++n)
-    for (int j = 0; j < 3; ++j) w.B[n][j] = take(kSlotL);
-  w.part = take((size_t)kChunks * kSlotL);
-  w.tC = take(mc);
-  w.tA = take(mc);
-  w.tB = take(mc);
-  for (int i = 0; i < 16; ++i) h->dec_host[i] = 0;
-  TTR_HIPCHK(hipMemcpyAsync(h->dec_dev, h->dec_host, 16 * sizeof(int), hipMemcpyHostToDevice, h->stream));
-
-  std::vector<int> k(N + 1), nst(N, 1);
-  std::vector<std::array<int, 4>> dim(N);
-  for (int n = 0; n <= N; ++n) k[n] = (int)X->R[n];
+  L.mixed = (prec == TTR_MIXED);
   int rc;
-  // ---- sweep 1: right-to-left orthonormalization with implicit factors ----
-  for (int n = N - 1; n >= 1; --n) {
-    const long long a = X->R[n], b = X->R[n + 1], In = X->I[n];
-    const double *src = X->core[n];
-    long long sc = b;
-    if (n < N - 1) {  // C = M x_3 T_{n+1}^T
-      if ((rc = L.gemm(false, false, a * In, k[n + 1], b, X->core[n], a * In, w.T[n + 1], b, w.tC, a * In))) return rc;
-      src = w.tC;
-      sc = k[n + 1];
-    }
-    double *bufs[2] = {w.tA, w.tB};
-    double *R[2] = {w.Ra, w.Rb};
-    const double *cur = src;
-    long long crow = a;
-    dim[n][0] = (int)a;
-    int pass = 1;
-    for (;; ++pass) {
-      if ((rc = L.gram(false, crow, In * sc, cur, crow, w.G))) return rc;
-      const double ge = gerr_of(In * sc);
-      if ((rc = L.step(pass == 1 ? nullptr : R[pass & 1], (int)crow, (int)a, pass, w.B[n][pass - 1],
-                       R[(pass - 1) & 1], w.T[n], ge, 0, 0, 0.0)))
-        return rc;
-      const int kk = h->dec_host[0];
-      dim[n][pass] = kk;
-      if (h->dec_host[1]) break;
-      // D = F_pass^T H(cur)
-      if ((rc = L.gemm(true, false, kk, In * sc, crow, w.B[n][pass - 1], crow, cur, crow, bufs[(pass - 1) & 1], kk)))
-        return rc;
-      cur = bufs[(pass - 1) & 1];
-      crow = kk;
-    }
-    nst[n] = pass;
-    k[n] = dim[n][pass];
-  }
-  // ---- sweep 2: left-to-right truncation --------------------------------------
+  if ((rc = L.setup(N, max_core_of(X)))) return rc;
+  auto phys = [&](int n) { return rev ? N - 1 - n : n; };
+  auto view = [&](int n) {
+    const int p = phys(n);
+    return LView{X->core[p], X->I[p], (int)X->R[p], (int)X->R[p + 1], rev};
+  };
+  std::vector<int> k;
+  std::vector<LFac> fac;
+  // ---- sweep 1: orthonormalization with implicit factors ----
+  if ((rc = orth_sweep_large(L, X, rev, prec, k, fac, nullptr))) return rc;
+  // ---- sweep 2: truncation ----
   std::vector<int> Lr(N + 1, 1), sweeps(N, 0);
   const double *Pcur = nullptr;
   int Lprev = 1;
   for (int n = 0; n < N - 1; ++n) {
-    const long long a = X->R[n], b = X->R[n + 1], In = X->I[n];
-    // C_n = M_n x_3 T_{n+1}^T, then the left stages F_1^T .. F_{nst-1}^T and P
-    if ((rc = L.gemm(false, false, a * In, k[n + 1], b, X->core[n], a * In, w.T[n + 1], b, w.tC, a * In))) return rc;
-    const long long cc = k[n + 1];
-    const double *cur = w.tC;
-    long long crow = a;
-    double *bufs[2] = {w.tA, w.tB};
-    int nb = 0;  // next buffer index (matches the orthonormalization sweep's order)
+    const LView v = view(n);
+    // C_n = M_n T_{n+1}, then the left stages F_1^T .. F_{nst-1}^T and P
+    // (the same calls as sweep 1, so each stage meets bitwise the data its
+    // Gram was measured on)
+    LView cur = L.right(v, L.T[n + 1], 1, v.eb(), k[n + 1], fac[n + 1].tri, L.tC);
+    const int cc = k[n + 1];
+    double *bufs[2] = {L.tA, L.tB};
     if (n >= 1) {
-      for (int j = 1; j < nst[n]; ++j) {
-        if ((rc = L.gemm(true, false, dim[n][j], In * cc, crow, w.B[n][j - 1], crow, cur, crow, bufs[(j - 1) & 1],
-                         dim[n][j])))
-          return rc;
-        cur = bufs[(j - 1) & 1];
-        crow = dim[n][j];
-        nb = j & 1;
-      }
-      double *out = (cur == w.tC) ? w.tA : ((cur == w.tA) ? w.tB : w.tA);
-      if ((rc = L.gemm(false, false, Lprev, In * cc, crow, Pcur, Lprev, cur, crow, out, Lprev))) return rc;
-      cur = out;
-      crow = Lprev;
+      for (int j = 1; j < fac[n].nst; ++j)
+        cur = L.left(cur, L.B[n][j - 1], cur.ea(), 1, fac[n].dim[j], bufs[(j - 1) & 1]);
+      double *o = (cur.X == L.tC) ? L.tA : ((cur.X == L.tA) ? L.tB : L.tA);
+      cur = L.left(cur, Pcur, 1, Lprev, Lprev, o);
     }
-    (void)nb;
-    // QR-by-Gram of V(C'_n) ((crow I) x cc)
-    double *R[2] = {w.Ra, w.Rb};
-    int g = 1;
-    int gd[4];
-    gd[0] = (int)cc;
-    const double *E = cur;
-    int notrunc = 0;
+    const int crow = cur.ea();
+    // QR-by-Gram of V(C'_n)
+    double *R[2] = {L.Ra, L.Rb};
+    int g = 1, gd[4], notrunc = 0;
+    gd[0] = cc;
+    LView E = cur;
     for (;; ++g) {
-      if ((rc = L.gram(true, gd[g - 1], crow * In, E, crow * In, w.G))) return rc;
-      const double ge = gerr_of(crow * In);
-      if ((rc = L.step(g == 1 ? nullptr : R[g & 1], gd[g - 1], (int)cc, g, w.Gst[g - 1], R[(g - 1) & 1], nullptr, ge,
-                       1, n == 0, tol * tol / (double)(N - 1))))
+      double gerr;
+      const int f32 = (prec == TTR_MIXED && g == 1);
+      L.gram(E, false, f32, L.G, &gerr);
+      if ((rc = L.step(g == 1 ? nullptr : R[g & 1], gd[g - 1], cc, g, L.Gst[g - 1], R[(g - 1) & 1], nullptr, gerr, 1,
+                       n == 0, tol * tol / (double)(N - 1), f32, nullptr)))
         return rc;
       gd[g] = h->dec_host[0];
       if (g == 1) notrunc = h->dec_host[5];
       if (h->dec_host[1]) break;
-      // E <- V(E) G_g
-      double *out = (E == w.tA) ? w.tB : w.tA;
-      if (E == w.tC) out = w.tA;
-      if ((rc = L.gemm(false, false, crow * In, gd[g], gd[g - 1], E, crow * In, w.Gst[g - 1], gd[g - 1], out, crow * In)))
-        return rc;
-      E = out;
+      if (g >= 3) return ttr_fail(TTR_ERR_NUMERICAL, "QR-by-Gram did not settle in three passes");
+      double *o = (E.X == L.tA) ? L.tB : L.tA;
+      if (E.X == L.tC) o = L.tA;
+      E = L.right(E, L.Gst[g - 1], 1, gd[g - 1], gd[g], 0, o);
     }
     // truncation: SVD of R (k x cc) unless no singular value can fall below delta
     const int kq = gd[g], dq = gd[g - 1];
     const double *Rq = R[(g - 1) & 1];
-    const double *Fn = w.B[n + 1][nst[n + 1] - 1];
-    const int dn = dim[n + 1][nst[n + 1] - 1];
-    double *Pn = w.P[n & 1];
+    const double *Fn = L.B[n + 1][fac[n + 1].nst - 1];
+    const int dn = fac[n + 1].dim[fac[n + 1].nst - 1];
+    double *Pn = L.P[n & 1];
     LTruncArgs ta;
     ta.R = Rq;
     ta.k = kq;
-    ta.b = (int)cc;
-    ta.delta = w.scal + 1;
-    ta.norm = w.scal + 2;
+    ta.b = cc;
+    ta.delta = L.scal + 1;
+    ta.norm = L.scal + 2;
     ta.first = (n == 0);
     ta.tol = tol;
     ta.Nm1 = N - 1;
-    ta.sigma_out = w.sigma + (size_t)n * kLMax;
-    ta.tail_out = w.tails + n;
+    ta.sigma_out = L.sigma + (size_t)n * kLMax;
+    ta.tail_out = L.tails + n;
     ta.dec = h->dec_dev;
     ta.identity = (g == 1) ? notrunc : 0;
-    ta.W0 = w.W0;
-    ta.W1 = w.W1;
-    ta.thr = w.scal + 8;
-    ta.sv = w.sv;
-    ta.perm = w.perm;
-    ta.Up = w.Up;
-    ta.Ap = w.Ap;
+    ta.W0 = L.W0;
+    ta.W1 = L.W1;
+    ta.thr = L.scal + 8;
+    ta.sv = L.sv;
+    ta.perm = L.perm;
+    ta.Up = L.Up;
+    ta.Ap = L.Ap;
     hipLaunchKernelGGL(lk_trunc_setup, dim3(1), dim3(kLT), 0, h->stream, ta);
     h->stats.small_launches++;
     if ((rc = L.sync_dec())) return rc;
@@ -1208,8 +1277,8 @@ int ttr_round_large(ttr_handle *h, const ttr_tt *X, double tol, ttr_tt *Y, doubl
     if (h->dec_host[7]) {
       // L = k: U = I, Pnext = R Fn^T
       Ln = kq;
-      GU = w.Gst[g - 1];
-      if ((rc = L.gemm(false, true, kq, dn, cc, Rq, kq, Fn, dn, Pn, kq))) return rc;
+      GU = L.Gst[g - 1];
+      L.sgemm(false, true, kq, dn, cc, Rq, kq, Fn, dn, Pn, kq);
     } else {
       if ((rc = L.jacobi(cc, kq))) return rc;
       sweeps[n] = L.sweeps;
@@ -1218,59 +1287,127 @@ int ttr_round_large(ttr_handle *h, const ttr_tt *X, double tol, ttr_tt *Y, doubl
       if ((rc = L.sync_dec())) return rc;
       Ln = h->dec_host[3];
       // GU = Glast U(:, perm[0:L]) (dq x L); Pnext = Sigma_L V_L^T Fn^T = A(:, perm[0:L])^T Fn^T
-      if ((rc = L.gemm(false, false, dq, Ln, kq, w.Gst[g - 1], dq, w.Up, kq, w.GU, dq))) return rc;
-      if ((rc = L.gemm(true, true, Ln, dn, cc, w.Ap, cc, Fn, dn, Pn, Ln))) return rc;
-      GU = w.GU;
+      L.sgemm(false, false, dq, Ln, kq, L.Gst[g - 1], dq, L.Up, kq, L.GU, dq);
+      L.sgemm(true, true, Ln, dn, cc, L.Ap, cc, Fn, dn, Pn, Ln);
+      GU = L.GU;
     }
     Lr[n + 1] = Ln;
-    // output core n: V(Y_n) = V(E) GU
-    if ((rc = L.gemm(false, false, crow * In, Ln, dq, E, crow * In, GU, dq, Y->core[n], crow * In)))
-      return rc;
+    // output core n: Y_n(i) = E(i) GU
+    L.right(E, GU, 1, dq, Ln, 0, Y->core[phys(n)]);
     ++L.applies;
-    Pcur = w.P[n & 1];
+    (void)crow;
+    Pcur = L.P[n & 1];
     Lprev = Ln;
   }
   {
-    // last core: P F_{nst-1}^T .. F_1^T H(M_N)
+    // last core: P F_{nst-1}^T .. F_1^T M_N
     const int n = N - 1;
-    const long long a = X->R[n], In = X->I[n], cc = X->R[n + 1];
-    const double *cur = X->core[n];
-    long long crow = a;
-    double *bufs[2] = {w.tA, w.tB};
-    for (int j = 1; j < nst[n]; ++j) {
-      if ((rc = L.gemm(true, false, dim[n][j], In * cc, crow, w.B[n][j - 1], crow, cur, crow, bufs[(j - 1) & 1],
-                       dim[n][j])))
-        return rc;
-      cur = bufs[(j - 1) & 1];
-      crow = dim[n][j];
-    }
-    if ((rc = L.gemm(false, false, Lprev, In * cc, crow, Pcur, Lprev, cur, crow, Y->core[n], Lprev))) return rc;
+    LView cur = view(n);
+    double *bufs[2] = {L.tA, L.tB};
+    for (int j = 1; j < fac[n].nst; ++j)
+      cur = L.left(cur, L.B[n][j - 1], cur.ea(), 1, fac[n].dim[j], bufs[(j - 1) & 1]);
+    L.left(cur, Pcur, 1, Lprev, Lprev, Y->core[phys(n)]);
     ++L.applies;
   }
   TTR_HIPCHK(hipGetLastError());
-  TTR_HIPCHK(hipMemcpyAsync(h->scal_host, w.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  TTR_HIPCHK(hipMemcpyAsync(h->scal_host, L.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   const int nsig = (N - 1) * kLMax;
   std::vector<double> sig(nsig), tails(N - 1);
-  TTR_HIPCHK(hipMemcpyAsync(sig.data(), w.sigma, nsig * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-  TTR_HIPCHK(hipMemcpyAsync(tails.data(), w.tails, (N - 1) * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  TTR_HIPCHK(hipMemcpyAsync(sig.data(), L.sigma, nsig * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  TTR_HIPCHK(hipMemcpyAsync(tails.data(), L.tails, (N - 1) * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   TTR_HIPCHK(hipStreamSynchronize(h->stream));
-  for (int l = 0; l <= N; ++l) Y->R[l] = (l == 0 || l == N) ? 1 : Lr[l];
+  for (int l = 0; l <= N; ++l) {
+    const int pl = rev ? N - l : l;
+    Y->R[pl] = (l == 0 || l == N) ? 1 : Lr[l];
+  }
   h->stats.gram_passes = L.passes;
   h->stats.apply_passes = L.applies;
   h->stats.links = N - 1;
   h->stats.norm = h->scal_host[2];
   h->stats.delta = h->scal_host[1];
-  const int nl = (N - 1) < TTR_STATS_LINKS ? (N - 1) : TTR_STATS_LINKS;
-  for (int l = 0; l < nl; ++l) {
-    int cnt = 0;
-    for (int j = 0; j < kLMax; ++j) {
-      h->stats.sigma[(size_t)l * TTR_STATS_SIGMA + j] = sig[(size_t)l * kLMax + j];
-      if (sig[(size_t)l * kLMax + j] > 0) cnt = j + 1;
-    }
-    h->stats.nsigma[l] = cnt;
-    h->stats.tail2[l] = tails[l];
-    h->stats.sweeps[l] = sweeps[l];
-  }
+  fill_stats(h, N, rev, sig, tails, sweeps);
   if (norm_out) *norm_out = h->scal_host[2];
+  return TTR_OK;
+}
+
+// In-place orthonormalization at ranks above 64 (§2.3 Alg. 1; written cores
+// as in §3.4 Alg. 5).  side TTR_LEFT runs the mirror image.
+int ttr_orthogonalize_large(ttr_handle *h, ttr_tt *X, int side) {
+  const int N = X->N;
+  const int rev = (side == TTR_LEFT);
+  Large L;
+  L.h = h;
+  int rc;
+  if ((rc = L.setup(N, max_core_of(X)))) return rc;
+  std::vector<int> k;
+  std::vector<LFac> fac;
+  if ((rc = orth_sweep_large(L, X, rev, TTR_FP64, k, fac, X))) return rc;
+  // the first logical core absorbs T_2: C_1(i) = M_1(i) T_2
+  const int p0 = rev ? N - 1 : 0;
+  const LView v{X->core[p0], X->I[p0], (int)X->R[p0], (int)X->R[p0 + 1], rev};
+  L.right(v, L.T[1], 1, v.eb(), k[1], fac[1].tri, L.tC);
+  TTR_HIPCHK(hipMemcpyAsync(X->core[p0], L.tC, (size_t)X->I[p0] * k[1] * sizeof(double), hipMemcpyDeviceToDevice,
+                            h->stream));
+  TTR_HIPCHK(hipStreamSynchronize(h->stream));
+  TTR_HIPCHK(hipGetLastError());
+  for (int l = 0; l <= N; ++l) {
+    const int pl = rev ? N - l : l;
+    X->R[pl] = k[l];
+  }
+  return TTR_OK;
+}
+
+// ||X|| by the orthonormalization sweep (implicit factors) and ||X_1 T_2||_F
+// (end of §2.3; the second method of §3.2.4), ranks above 64.
+int ttr_norm_ortho_large(ttr_handle *h, const ttr_tt *X, double *out) {
+  const int N = X->N;
+  Large L;
+  L.h = h;
+  int rc;
+  if ((rc = L.setup(N, max_core_of(X)))) return rc;
+  std::vector<int> k;
+  std::vector<LFac> fac;
+  if ((rc = orth_sweep_large(L, X, 0, TTR_FP64, k, fac, nullptr))) return rc;
+  const LView v{X->core[0], X->I[0], 1, (int)X->R[1], 0};
+  LView c0 = v;
+  if (N > 1) c0 = L.right(v, L.T[1], 1, v.eb(), k[1], fac[1].tri, L.tC);
+  double gerr;
+  L.gram(c0, true, 0, L.G, &gerr);  // 1 x 1: ||C_1||_F^2
+  launch_sqrt_scalar(h->stream, L.G, L.scal);
+  TTR_HIPCHK(hipGetLastError());
+  TTR_HIPCHK(hipMemcpyAsync(h->scal_host, L.scal, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  TTR_HIPCHK(hipStreamSynchronize(h->stream));
+  *out = h->scal_host[0];
+  return TTR_OK;
+}
+
+// <X, Y> by the recursion W_n = sum_i Y_n(i)^T W_{n-1} X_n(i) (§3.2.3, eq. (4))
+// at ranks above 64: Z_n(i) = W_{n-1} X_n(i) is formed as a core, then
+// W_n = V(Y_n)^T V(Z_n).
+int ttr_dot_large(ttr_handle *h, const ttr_tt *X, const ttr_tt *Y, double *out) {
+  const int N = X->N;
+  size_t mz = 0;
+  for (int n = 0; n < N; ++n) mz = std::max(mz, (size_t)(Y->R[n] * X->I[n] * X->R[n + 1]));
+  Large L;
+  L.h = h;
+  int rc;
+  if ((rc = L.setup(N, std::max(mz, max_core_of(X))))) return rc;
+  double *Wb[2] = {L.P[0], L.P[1]};
+  h->scal_host[0] = 1.0;
+  TTR_HIPCHK(hipMemcpyAsync(Wb[0], h->scal_host, sizeof(double), hipMemcpyHostToDevice, h->stream));
+  for (int n = 0; n < N; ++n) {
+    const int rx0 = (int)X->R[n], rx1 = (int)X->R[n + 1], ry0 = (int)Y->R[n], ry1 = (int)Y->R[n + 1];
+    const LView vx{X->core[n], X->I[n], rx0, rx1, 0};
+    // Z_n(i) = W (ry0 x rx0, ld ry0) X_n(i)
+    const LView z = L.left(vx, Wb[n & 1], 1, ry0, ry0, L.tA);
+    // W_n (ry1 x rx1) = V(Y_n)^T V(Z_n)
+    const long long M = (long long)ry0 * X->I[n];
+    const int nwg = launch_lg_gram(h->stream, Y->core[n], z.X, M, ry1, rx1, M, M, 1, 0, L.part);
+    launch_reduce(h->stream, L.part, nwg, ry1 * rx1, Wb[(n + 1) & 1]);
+  }
+  TTR_HIPCHK(hipGetLastError());
+  TTR_HIPCHK(hipMemcpyAsync(h->scal_host + 1, Wb[N & 1], sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  TTR_HIPCHK(hipStreamSynchronize(h->stream));
+  *out = h->scal_host[1];
   return TTR_OK;
 }

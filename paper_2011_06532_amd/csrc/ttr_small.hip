@@ -609,7 +609,7 @@ __device__ void qr_step_body(const QrStepArgs a) {
       }
       return;
     }
-    if (!kap_ok && a.pass == 1) {
+    if (!kap_ok && a.pass <= a.shift_pass) {
       // Shifted CholeskyQR: G + sI = L L^T with s ~ d u trace(G) gives A L^{-T}
       // the singular values sqrt(lambda / (lambda + s)), as the shifted eigen
       // route would, at the cost of one factorization; the next pass refines.
@@ -625,7 +625,18 @@ __device__ void qr_step_body(const QrStepArgs a) {
         for (int e = threadIdx.x; e < d * d; e += blockDim.x) {
           const int r = e % d, c = e / d;
           a.Fstep[r + d * c] = Vm[c + d * r];  // F = L^{-T}
-          a.Rnext[r + d * c] = A[c + d * r];   // R = L^T (Rc = I at the first pass)
+          if (!a.Rc) a.Rnext[r + d * c] = A[c + d * r];   // R = L^T (Rc = I at the first pass)
+        }
+        if (a.Rc) {
+          // a shifted refinement pass (mixed precision): R = L^T Rc (d x b)
+          __syncthreads();
+          const int b = a.b;
+          for (int e = threadIdx.x; e < d * b; e += blockDim.x) {
+            const int r = e % d, c = e / d;
+            double v = 0.0;
+            for (int j = r; j < d; ++j) v += A[j + d * r] * a.Rc[j + d * c];
+            a.Rnext[r + d * c] = v;
+          }
         }
         if (threadIdx.x == 0) {
           if (a.ratio_out) *a.ratio_out = 1e300;

@@ -1,7 +1,8 @@
-"""GPU parity of TT rounding at ranks above 64 (the GEMM-based path, up to
-256) against the FP64 oracle: the Hadamard-then-round workload at reduced mode
-sizes (A, B rank 16 with slice weights 2^-b, X = A * B of rank 256), sums of
-ranks 65..100, and the rank-deficient Y + Y.
+"""GPU parity at ranks above 64 (the unfolding-based path, up to 256) against
+the FP64 oracle: rounding of the Hadamard-then-round workload at reduced mode
+sizes (A, B rank 16 with slice weights 2^-b, X = A * B of rank 256) in both
+sweep orders and both precisions, sums of ranks 65..100, the rank-deficient
+Y + Y; inner product, norms and orthonormalization at ranks up to 256.
 """
 import numpy as np
 import pytest
@@ -72,20 +73,105 @@ def test_thin_unfoldings(ttr, h):
     check_round(ttr, h, X, 1e-10, "RLR", norm_rtol=1e-10)
 
 
-def test_large_rank_mixed_runs_fp64(ttr, h):
-    print("ranks > 64 with prec mixed", flush=True)
+@pytest.mark.parametrize("direction", ["RLR", "LRL"])
+def test_large_rank_mixed(ttr, h, direction):
+    # FP32 first Gram passes, FP64 refinement and small factorizations
+    print(f"ranks > 64 in mixed precision {direction}", flush=True)
     rng = np.random.default_rng(903)
     I = [30, 25, 40, 35]
     X = O.add(1.0, rand_tt(rng, I, [40, 45, 30]), 1.0, rand_tt(rng, I, [35, 40, 45]))
-    check_round(ttr, h, X, 1e-8, "RLR", prec="mixed", norm_rtol=1e-10)
+    check_round(ttr, h, X, 1e-8, direction, rel=1e-8, prec="mixed", norm_rtol=1e-6, sig_rtol=1e-6)
 
 
-def test_large_rank_lrl_unsupported(ttr, h):
+@pytest.mark.parametrize("direction", ["RLR", "LRL"])
+def test_large_rank_mirror_order(ttr, h, direction):
+    # the mirror sweep order (LRL) at ranks above 64, against the oracle's LRL
+    print(f"ranks 70..100 {direction}", flush=True)
     rng = np.random.default_rng(904)
-    X = rand_tt(rng, [10, 10, 10], [70, 70])
+    I = [12, 20, 15, 18, 10]
+    X = O.add(1.0, rand_tt(rng, I, [70, 50, 60, 40], scale=0.5), 1.0, rand_tt(rng, I, [30, 45, 20, 35], scale=0.5))
+    Z = rand_tt(rng, I, [5, 5, 5, 5], scale=0.5)
+    Z[0] *= 1e-5
+    X = O.add(1.0, X, 1.0, Z)
+    got, ref = check_round(ttr, h, X, 1e-4, direction, norm_rtol=1e-10, sig_rtol=1e-6)
+    assert max(O.ranks(X)) > 64
+
+
+@pytest.mark.parametrize("direction", ["RLR", "LRL"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_hadamard_rank256_both_orders(ttr, h, direction, prec):
+    N, I = 4, 40
+    print(f"hadamard rank 256, N={N} I={I}, {direction} {prec}", flush=True)
+    A = synth.random_tt(4, 1, "A", [I] * N, [16] * (N - 1), scaled=True, rank_weights=True)
+    B = synth.random_tt(4, 1, "B", [I] * N, [16] * (N - 1), scaled=True, rank_weights=True)
+    X = h.hadamard(ttr.TT.from_numpy(A), ttr.TT.from_numpy(B)).to_numpy()
+    rel = 1e-10 if prec == "fp64" else 1e-8
+    got, ref = check_round(ttr, h, X, 1e-6, direction, rel=rel, prec=prec, sig_rtol=1e-6,
+                           norm_rtol=1e-10 if prec == "fp64" else 1e-6)
+    assert max(O.ranks(got)) < 256
+
+
+LARGE_SHAPES = [
+    ([30, 25, 40, 35], [80, 100, 70]),
+    ([9, 300, 200, 7], [9, 256, 7]),          # rank 256 between thin end cores
+    ([50, 40, 60], [65, 120]),
+]
+
+
+@pytest.mark.parametrize("I,r", LARGE_SHAPES)
+def test_large_rank_dot_and_norms(ttr, h, I, r):
+    print(f"dot / norms at ranks {r}", flush=True)
+    rng = np.random.default_rng(905)
+    X = rand_tt(rng, I, r, scale=0.1)
+    Y = rand_tt(rng, I, [max(1, x // 2) for x in r], scale=0.1)
+    gx, gy = ttr.TT.from_numpy(X), ttr.TT.from_numpy(Y)
+    ref = O.dot(X, Y)
+    scale = O.norm_ortho(X) * O.norm_ortho(Y)
+    assert abs(h.dot(gx, gy) - ref) <= 1e-12 * scale
+    assert abs(h.dot(gy, gx) - ref) <= 1e-12 * scale
+    n = O.norm_ortho(X)
+    assert abs(h.norm(gx, "gram") - n) <= 1e-12 * n
+    assert abs(h.norm(gx, "ortho") - n) <= 1e-12 * n
     with pytest.raises(ttr.TTRError) as e:
-        h.round(ttr.TT.from_numpy(X), 1e-8, "LRL")
+        h.norm(gx, "sym")
     assert e.value.code == 7
+
+
+def test_large_rank_norm_small_difference(ttr, h):
+    # the orthonormalization norm resolves ||(X + 1e-9 Z) - X|| at ranks > 64
+    print("norm of a difference tensor at ranks > 64", flush=True)
+    rng = np.random.default_rng(906)
+    I = [20, 30, 25, 15]
+    X = rand_tt(rng, I, [40, 50, 35])
+    Z = rand_tt(rng, I, [3, 3, 3])
+    D = O.add(1.0, O.add(1.0, X, 1e-9, Z), -1.0, X)
+    assert max(O.ranks(D)) > 64
+    ref = 1e-9 * O.norm_ortho(Z)
+    assert abs(h.norm(ttr.TT.from_numpy(D), "ortho") - ref) <= 1e-6 * ref
+
+
+@pytest.mark.parametrize("side", ["right", "left"])
+@pytest.mark.parametrize("I,r", LARGE_SHAPES)
+def test_large_rank_orthogonalize(ttr, h, side, I, r):
+    print(f"orthogonalize {side} ranks {r}", flush=True)
+    rng = np.random.default_rng(907)
+    X = rand_tt(rng, I, r, scale=2.0)
+    g = ttr.TT.from_numpy(X)
+    h.orthogonalize(g, side)
+    Y = g.to_numpy()
+    N = len(Y)
+    nrm = O.norm_ortho(X)
+    assert O.diff_norm(Y, X) <= 1e-13 * nrm * max(1, N)
+    if side == "right":
+        for n in range(1, N):
+            Hn = O.H(Y[n])
+            assert np.linalg.norm(Hn @ Hn.T - np.eye(Hn.shape[0])) < 1e-13 * Hn.shape[0]
+    else:
+        for n in range(N - 1):
+            Vn = O.V(Y[n])
+            assert np.linalg.norm(Vn.T @ Vn - np.eye(Vn.shape[1])) < 1e-13 * Vn.shape[1]
+    # the oracle's Householder sweep gives the same ranks on generic inputs
+    assert O.ranks(Y) == O.ranks(O.orthogonalize(X, side))
 
 
 def test_hadamard_workload_full_N_reduced_I(ttr, h):

@@ -226,14 +226,19 @@ def test_argument_errors(ttr, h):
     with pytest.raises(ttr.TTRError) as e:
         h.round(X, 1e-3, out=small)
     assert e.value.code == 3  # capacity
-    # ranks above TTR_MAX_RANK_LARGE (round) / TTR_MAX_RANK (orthogonalize)
+    # ranks above TTR_MAX_RANK_LARGE: every entry point that takes ranks
     big = ttr.TT.from_numpy(rand_tt(rng, [3, 3], [257]))
     with pytest.raises(ttr.TTRError) as e:
         h.round(big, 1e-3)
     assert e.value.code == 7
-    mid = ttr.TT.from_numpy(rand_tt(rng, [3, 3], [65]))
     with pytest.raises(ttr.TTRError) as e:
-        h.orthogonalize(mid, "right")
+        h.orthogonalize(big, "right")
+    assert e.value.code == 7
+    with pytest.raises(ttr.TTRError) as e:
+        h.dot(big, big)
+    assert e.value.code == 7
+    with pytest.raises(ttr.TTRError) as e:
+        h.norm(big, "ortho")
     assert e.value.code == 7
 
 
