@@ -250,27 +250,38 @@ def bench_large(h, ttr, torch, steps):
     torch.cuda.synchronize()
     ms_had = e0.elapsed_time(e1)
     nbytes = sum(8 * X.R[n] * X.I[n] * X.R[n + 1] for n in range(X.N))
-    log("large: warm-up round")
-    Y = h.round(X, tol, "RLR", "fp64")
-    torch.cuda.synchronize()
-    ts = []
-    for k in range(max(1, min(steps, 3))):
-        e0.record(stream)
-        Y = h.round(X, tol, "RLR", "fp64", out=Y)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ts.append(e0.elapsed_time(e1))
-        log(f"large: round {k + 1}: {ts[-1]:.1f} ms")
-    st = h.round_stats()
-    bound = error_bound_figures(h, torch, Y, tol)
-    ms = sum(ts) / len(ts)
     out = {"workload": "A * B (Hadamard), N=10, I=16384, A,B random TTs of rank 16 with 2^-b rank weights, "
-                       f"formal ranks 256, ttr_round tol {tol:g} RLR fp64",
+                       f"formal ranks 256, ttr_round tol {tol:g}",
            "core_bytes_X": nbytes, "ms_hadamard": round(ms_had, 3),
-           "hadamard_GBps": round(nbytes / (ms_had * 1e-3) / 1e9, 1),
-           "ms_per_round": round(ms, 3), "round_core_GBps": round(nbytes / (ms * 1e-3) / 1e9, 2),
-           "rounds": len(ts), "ranks": list(Y.R), "gram_passes": st["gram_passes"],
-           "error_bound": bound}
+           "hadamard_GBps": round(nbytes / (ms_had * 1e-3) / 1e9, 1)}
+    Y = None
+    ranks64 = None
+    for prec, direction in (("fp64", "RLR"), ("mixed", "RLR"), ("fp64", "LRL")):
+        log(f"large: warm-up round {prec} {direction}")
+        Y = h.round(X, tol, direction, prec, out=Y)
+        torch.cuda.synchronize()
+        ts = []
+        for k in range(max(1, min(steps, 3)) if direction == "RLR" else 1):
+            e0.record(stream)
+            Y = h.round(X, tol, direction, prec, out=Y)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+            log(f"large {prec} {direction}: round {k + 1}: {ts[-1]:.1f} ms")
+        st = h.round_stats()
+        ms = sum(ts) / len(ts)
+        r = {"ms_per_round": round(ms, 3), "round_core_GBps": round(nbytes / (ms * 1e-3) / 1e9, 2),
+             "rounds": len(ts), "ranks": list(Y.R), "gram_passes": st["gram_passes"]}
+        if direction == "RLR":
+            r["error_bound"] = error_bound_figures(h, torch, Y, tol)
+        else:
+            r["jacobi_sweeps"] = st["sweeps"]
+        if ranks64 is None:
+            ranks64 = list(Y.R)
+        else:
+            r["ranks_equal_fp64_rlr"] = list(Y.R) == ranks64
+        out[f"{prec}_{direction}"] = r
+    out["mixed_speedup"] = round(out["fp64_RLR"]["ms_per_round"] / out["mixed_RLR"]["ms_per_round"], 3)
     del X, Y, A, B
     torch.cuda.empty_cache()
     return out
