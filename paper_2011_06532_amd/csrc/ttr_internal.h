@@ -106,8 +106,11 @@ LGramGrid lg_gram_grid(long long M, int f32);
 // lg_gram_grid(M, f32).rpw rows into part (nwg x K1 K2 doubles); X2 == nullptr:
 // the Gram of X1 (symmetric; f32: FP32 products and accumulation).  Both
 // operands share the layout xcol and have M rows.  Returns nwg.
+// fscale (FP32 only, device): the scale pair of launch_lg_scale_probe.
 int launch_lg_gram(hipStream_t s, const double *X1, const double *X2, long long M, int K1, int K2, long long ld1,
-                   long long ld2, int xcol, int f32, double *part);
+                   long long ld2, int xcol, int f32, double *part, const double *fscale = nullptr);
+// out[0] = 2^-e, out[1] = 2^2e from the largest sampled |x| of X (n doubles).
+void launch_lg_scale_probe(hipStream_t s, const double *X, long long n, double *out);
 // C (m x n, ld ldc) = A B, A(i, k) = A[i ar + k ac], B(k, j) = B[k br + j bc].
 void launch_lg_sgemm(hipStream_t s, const double *A, long long ar, long long ac, const double *B, long long br,
                      long long bc, int m, int n, int k, double *C, long long ldc);

@@ -993,26 +993,30 @@ struct Large {
   }
   // G (ea x ea) = sum_i M'(i) M'(i)^T (left) or (eb x eb) = sum_i M'(i)^T M'(i)
   // (right); *gerr = bound on the rounding error relative to the trace
-  void gram(const LView &v, bool left_side, int f32, double *Gout, double *gerr) {
+  int gram(const LView &v, bool left_side, int f32, double *Gout, double *gerr) {
     // physical: H(M) H(M)^T (row-major H(M)^T) or V(M)^T V(M) (column-major V(M))
     const bool use_h = (left_side != (v.trans != 0));
     long long M;
     int K, nwg;
+    double *fs = scal + 32;
+    if (f32) launch_lg_scale_probe(h->stream, v.X, (long long)v.pa * v.I * v.pb, fs);
     if (use_h) {
       M = v.I * v.pb;
       K = v.pa;
-      nwg = launch_lg_gram(h->stream, v.X, nullptr, M, K, K, v.pa, v.pa, 0, f32, part);
+      nwg = launch_lg_gram(h->stream, v.X, nullptr, M, K, K, v.pa, v.pa, 0, f32, part, fs);
     } else {
       M = (long long)v.pa * v.I;
       K = v.pb;
-      nwg = launch_lg_gram(h->stream, v.X, nullptr, M, K, K, M, M, 1, f32, part);
+      nwg = launch_lg_gram(h->stream, v.X, nullptr, M, K, K, M, M, 1, f32, part, fs);
     }
+    if (nwg > 512) return ttr_fail(TTR_ERR_HIP, "Gram partials exceed the workspace");
     launch_reduce(h->stream, part, nwg, K * K, Gout);
     const LGramGrid g = lg_gram_grid(M, f32);
     // per entry: the workgroup's sequential sum over its rows, then the
     // fixed-order sum of the partials (FP32: inputs rounded too)
     *gerr = 2.0 * ((double)g.rpw + (double)nwg + 18.0) * (f32 ? kU32 : kU);
     ++passes;
+    return TTR_OK;
   }
   int sync_dec() {
     TTR_HIPCHK(hipMemcpyAsync(h->dec_host, h->dec_dev, 16 * sizeof(int), hipMemcpyDeviceToHost, h->stream));
@@ -1132,7 +1136,7 @@ int orth_sweep_large(Large &L, const ttr_tt *X, int rev, int prec, std::vector<i
     for (;; ++pass) {
       double gerr;
       const int f32 = (prec == TTR_MIXED && pass == 1);
-      L.gram(cur, true, f32, L.G, &gerr);
+      if ((rc = L.gram(cur, true, f32, L.G, &gerr))) return rc;
       if ((rc = L.step(pass == 1 ? nullptr : R[pass & 1], cur.ea(), a, pass, L.B[n][pass - 1], R[(pass - 1) & 1],
                        L.T[n], gerr, 0, 0, 0.0, f32, &pivoted)))
         return rc;
@@ -1231,7 +1235,7 @@ int ttr_round_large(ttr_handle *h, const ttr_tt *X, double tol, int direction, i
     for (;; ++g) {
       double gerr;
       const int f32 = (prec == TTR_MIXED && g == 1);
-      L.gram(E, false, f32, L.G, &gerr);
+      if ((rc = L.gram(E, false, f32, L.G, &gerr))) return rc;
       if ((rc = L.step(g == 1 ? nullptr : R[g & 1], gd[g - 1], cc, g, L.Gst[g - 1], R[(g - 1) & 1], nullptr, gerr, 1,
                        n == 0, tol * tol / (double)(N - 1), f32, nullptr)))
         return rc;
@@ -1372,7 +1376,7 @@ int ttr_norm_ortho_large(ttr_handle *h, const ttr_tt *X, double *out) {
   LView c0 = v;
   if (N > 1) c0 = L.right(v, L.T[1], 1, v.eb(), k[1], fac[1].tri, L.tC);
   double gerr;
-  L.gram(c0, true, 0, L.G, &gerr);  // 1 x 1: ||C_1||_F^2
+  if ((rc = L.gram(c0, true, 0, L.G, &gerr))) return rc;  // 1 x 1: ||C_1||_F^2
   launch_sqrt_scalar(h->stream, L.G, L.scal);
   TTR_HIPCHK(hipGetLastError());
   TTR_HIPCHK(hipMemcpyAsync(h->scal_host, L.scal, sizeof(double), hipMemcpyDeviceToHost, h->stream));

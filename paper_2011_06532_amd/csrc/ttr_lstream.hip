@@ -244,10 +244,15 @@ struct AccOf<float> {
 
 __host__ __device__ inline int lg_nblocks(int nb1, int nb2, bool sym) { return sym ? nb1 * (nb1 + 1) / 2 : nb1 * nb2; }
 
+// fscale (FP32 only): fscale[0] = 2^-e multiplies every element before it is
+// rounded to FP32 (keeps tiny or huge data inside FP32's range), fscale[1] =
+// 2^2e multiplies the FP64 partials (exact: powers of two).
 template <class T, bool XCOL, bool SYM, bool VEC>
 __global__ __launch_bounds__(kGrT) void lg_gram(const double *__restrict__ X1, const double *__restrict__ X2,
                                                 long long M, int K1, int K2, long long ld1, long long ld2,
-                                                long long rpw, double *__restrict__ part) {
+                                                long long rpw, double *__restrict__ part,
+                                                const double *__restrict__ fscale) {
+  const double sin = (sizeof(T) == 4) ? fscale[0] : 1.0, sout = (sizeof(T) == 4) ? fscale[1] : 1.0;
   typedef typename AccOf<T>::type V;
   constexpr int NOP = SYM ? 1 : 2;
   __shared__ T S[NOP][2][kRC][kRP];
@@ -313,11 +318,11 @@ __global__ __launch_bounds__(kGrT) void lg_gram(const double *__restrict__ X1, c
       pair_of(tid + j * kGrT, &r, &k);
       if (k < Kp[o]) {
         if (XCOL) {
-          S[o][buf][r][k] = (T)pre[o][j][0];
-          S[o][buf][r + 1][k] = (T)pre[o][j][1];
+          S[o][buf][r][k] = (T)(sin * pre[o][j][0]);
+          S[o][buf][r + 1][k] = (T)(sin * pre[o][j][1]);
         } else {
-          S[o][buf][r][k] = (T)pre[o][j][0];
-          S[o][buf][r][k + 1] = (T)pre[o][j][1];
+          S[o][buf][r][k] = (T)(sin * pre[o][j][0]);
+          S[o][buf][r][k + 1] = (T)(sin * pre[o][j][1]);
         }
       }
     }
@@ -384,7 +389,7 @@ __global__ __launch_bounds__(kGrT) void lg_gram(const double *__restrict__ X1, c
           p = 64 * pb + 16 * pt + 4 * (lane / 16) + j;
           q = q0 + 16 * qt + lane % 16;
         }
-        const double v = (double)acc[pt][qt][j];
+        const double v = sout * (double)acc[pt][qt][j];
         if (p < K1 && q < K2) {
           P[p + (long long)K1 * q] = v;
           if (SYM && pb != qb) P[q + (long long)K1 * p] = v;
@@ -445,9 +450,10 @@ void launch_lg_gemm(hipStream_t s, const double *X, long long M, int K, long lon
 }
 
 LGramGrid lg_gram_grid(long long M, int f32) {
-  // about 1024 rows per workgroup at least; at most 512 (FP64) or 1024 (FP32)
-  // workgroups
-  const long long cap = f32 ? 1024 : 512;
+  // about 1024 rows per workgroup at least, at most 512 workgroups (FP64 and
+  // FP32 alike: the callers' partial-matrix workspaces hold 512)
+  (void)f32;
+  const long long cap = 512;
   long long nwg = std::max(1LL, std::min(cap, (M + 1023) / 1024));
   LGramGrid g;
   g.rpw = (M + nwg - 1) / nwg;
@@ -456,8 +462,47 @@ LGramGrid lg_gram_grid(long long M, int f32) {
   return g;
 }
 
+namespace {
+
+// Scale of an FP32 Gram: the largest finite |x| over up to 65536 evenly
+// spaced samples of the n doubles at X, m, gives out[0] = 2^-e with
+// 2^e <= m < 2^(e+1) and out[1] = 2^(2e) (1 and 1 when m = 0).
+__global__ __launch_bounds__(256) void lg_scale_probe(const double *__restrict__ X, long long n, double *out) {
+  __shared__ double red[256];
+  const long long ns = std::min(n, 65536LL);
+  const long long stride = std::max(1LL, n / std::max(ns, 1LL));
+  double m = 0.0;
+  for (long long j = threadIdx.x; j < ns; j += 256) {
+    const double v = fabs(X[j * stride]);
+    if (v <= 1.7976931348623157e308) m = fmax(m, v);
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double mx = red[0];
+    if (mx > 0.0) {
+      const int e = ilogb(mx);
+      out[0] = ldexp(1.0, -e);
+      out[1] = ldexp(1.0, 2 * e);
+    } else {
+      out[0] = 1.0;
+      out[1] = 1.0;
+    }
+  }
+}
+
+}  // namespace
+
+void launch_lg_scale_probe(hipStream_t s, const double *X, long long n, double *out) {
+  hipLaunchKernelGGL(lg_scale_probe, dim3(1), dim3(256), 0, s, X, n, out);
+}
+
 int launch_lg_gram(hipStream_t s, const double *X1, const double *X2, long long M, int K1, int K2, long long ld1,
-                   long long ld2, int xcol, int f32, double *part) {
+                   long long ld2, int xcol, int f32, double *part, const double *fscale) {
   const LGramGrid g = lg_gram_grid(M, f32);
   const bool sym = (X2 == nullptr);
   const int nb1 = (K1 + 63) / 64, nb2 = (K2 + 63) / 64;
@@ -471,10 +516,10 @@ int launch_lg_gram(hipStream_t s, const double *X1, const double *X2, long long 
   do {                                                                                                           \
     if (vec)                                                                                                     \
       hipLaunchKernelGGL((lg_gram<T, XC, SY, true>), grid, block, 0, s, X1, sym ? X1 : X2, M, K1, sym ? K1 : K2, \
-                         ld1, sym ? ld1 : ld2, g.rpw, part);                                                     \
+                         ld1, sym ? ld1 : ld2, g.rpw, part, fscale);                                             \
     else                                                                                                         \
       hipLaunchKernelGGL((lg_gram<T, XC, SY, false>), grid, block, 0, s, X1, sym ? X1 : X2, M, K1,               \
-                         sym ? K1 : K2, ld1, sym ? ld1 : ld2, g.rpw, part);                                      \
+                         sym ? K1 : K2, ld1, sym ? ld1 : ld2, g.rpw, part, fscale);                              \
   } while (0)
   if (sym) {
     if (f32) {

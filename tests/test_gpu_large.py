@@ -83,6 +83,21 @@ def test_large_rank_mixed(ttr, h, direction):
     check_round(ttr, h, X, 1e-8, direction, rel=1e-8, prec="mixed", norm_rtol=1e-6, sig_rtol=1e-6)
 
 
+@pytest.mark.parametrize("scale", [1e-30, 1e30])
+def test_large_rank_mixed_far_from_unit_norm(ttr, h, scale):
+    # the FP32 Gram passes rescale their data by a power of two, so tensors
+    # whose entries square below or above FP32's range round as in FP64
+    print(f"ranks > 64 in mixed precision, tensor scaled by {scale:g}", flush=True)
+    rng = np.random.default_rng(908)
+    I = [30, 25, 40, 35]
+    X = O.add(1.0, rand_tt(rng, I, [40, 45, 30]), 1.0, rand_tt(rng, I, [35, 40, 45]))
+    Z = rand_tt(rng, I, [3, 3, 3])
+    Z[0] *= 1e-5
+    X = O.add(1.0, X, 1.0, Z)
+    X[0] = X[0] * scale
+    check_round(ttr, h, X, 1e-4, "RLR", rel=1e-8, prec="mixed", norm_rtol=1e-6, sig_rtol=1e-6)
+
+
 @pytest.mark.parametrize("direction", ["RLR", "LRL"])
 def test_large_rank_mirror_order(ttr, h, direction):
     # the mirror sweep order (LRL) at ranks above 64, against the oracle's LRL
