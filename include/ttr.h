@@ -50,7 +50,11 @@ enum ttr_status {
 };
 
 enum { TTR_RIGHT = 0, TTR_LEFT = 1 };             /* orthonormalization side (§2.3) */
-enum { TTR_RLR = 0, TTR_LRL = 1 };                 /* rounding sweep order (§4.3.2) */
+/* rounding sweep order and orthonormal factors (§4.3.2): RLR / LRL keep the
+ * first sweep's orthonormal factors implicit (§3.5 Alg. 6); the _EXPLICIT
+ * variants write the orthonormal cores first (§3.4 Alg. 5) and truncate over
+ * the written cores */
+enum { TTR_RLR = 0, TTR_LRL = 1, TTR_RLR_EXPLICIT = 2, TTR_LRL_EXPLICIT = 3 };
 enum { TTR_NORM_ORTHO = 0, TTR_NORM_GRAM = 1, TTR_NORM_SYM = 2 };    /* norm method (§3.2.4) */
 enum { TTR_FP64 = 0, TTR_MIXED = 1 };              /* arithmetic of the Gram passes */
 

@@ -1003,11 +1003,170 @@ int ttr_orthogonalize(ttr_handle *h, ttr_tt *X, int side, int prec) {
   return TTR_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Rounding with explicit orthonormal factors (the explicit variant of
+// §4.3.2, the orthonormalization of §3.4 Alg. 5): Y <- X, Y is orthonormalized
+// in place with its cores written (right for RLR, left for LRL), then the
+// truncation sweep of Alg. 2 runs over the written cores, C'_n(i) = P_n Y_n(i)
+// with no factor of the first sweep left to apply.  Ranks <= 64.
+int round_explicit_small(ttr_handle *h, const ttr_tt *X, double tol, int rev, int prec, ttr_tt *Y, double *norm_out) {
+  const int N = X->N;
+  int rc;
+  for (int n = 0; n < N; ++n) {
+    HIPCHK(hipMemcpyAsync(Y->core[n], X->core[n], (size_t)X->R[n] * X->I[n] * X->R[n + 1] * sizeof(double),
+                          hipMemcpyDeviceToDevice, h->stream));
+    Y->R[n] = X->R[n];
+  }
+  Y->R[N] = 1;
+  const size_t tmp = max_core(X);
+  if ((rc = ensure_ws(h, ws_doubles(N, tmp, tmp) * sizeof(double)))) return rc;
+  WS w = carve(h, N, tmp, tmp);
+  if ((rc = reset_dec(h))) return rc;
+  Prec pr;
+  pr.mixed = (prec == TTR_MIXED);
+  const Seq S{Y, rev};
+  std::vector<int> k;
+  std::vector<Factor> fac;
+  int passes = 0, applies = 0;
+  // sweep 1: orthonormal cores written into Y (the first core absorbs T_2)
+  if ((rc = orth_sweep(h, w, S, k, fac, Y, &passes, nullptr, pr))) return rc;
+  {
+    const CoreView cv = S.view(0);
+    Stages st = no_stages();
+    st.R[st.nr++] = st_plain(w.T(1), cv.eb(), k[1]);
+    apply(h, cv, st, w.tmp, S.rev);
+    HIPCHK(hipMemcpyAsync(Y->core[S.phys(0)], w.tmp, (size_t)cv.I * k[1] * sizeof(double), hipMemcpyDeviceToDevice,
+                          h->stream));
+    ++applies;
+  }
+  for (int l = 0; l <= N; ++l) Y->R[rev ? N - l : l] = k[l];
+  // sweep 2: truncation over the written cores
+  std::vector<int> L(N + 1, 1), sweeps(N, 0);
+  double *Pbuf[2] = {w.Pa, w.Pb};
+  const double *Pcur = nullptr;
+  int Lprev = 1;
+  for (int n = 0; n < N - 1; ++n) {
+    const CoreView cv = S.view(n);
+    const int b = cv.eb();
+    Stages base = no_stages();
+    if (n > 0) base.L[base.nl++] = st_plain(Pcur, Lprev, cv.ea());
+    double *Rq;
+    int kq;
+    Factor g;
+    auto slot = [&](int j) { return w.Gst[j]; };
+    TruncCtx tcx;
+    tcx.check = 1;
+    tcx.delta_dev = w.scal + 1;
+    tcx.first = (n == 0);
+    tcx.tol2_nm1 = tol * tol / (double)(N - 1);
+    CoreView cvm;
+    int materialized = 0;
+    if ((rc = qr_by_gram(h, w, cv, GRAM_RIGHT, base, b, slot, nullptr, &g, &Rq, &kq, &passes, -1.0, nullptr, &tcx, pr,
+                         w.matA, &cvm, &materialized)))
+      return rc;
+    // the next core's orthonormal factor is written into it: Fn = I (b x b)
+    double *Id = w.Wb;
+    {
+      std::vector<double> id((size_t)b * b, 0.0);
+      for (int j = 0; j < b; ++j) id[(size_t)j * b + j] = 1.0;
+      HIPCHK(hipMemcpy(Id, id.data(), id.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+    TruncArgs ta;
+    ta.R = Rq;
+    ta.k = kq;
+    ta.b = b;
+    ta.Glast = w.Gst[g.nst - 1];
+    ta.d = g.dim[g.nst - 1];
+    ta.Fn = Id;
+    ta.dn = b;
+    ta.GU = w.GU;
+    ta.Pnext = Pbuf[n & 1];
+    ta.delta = w.scal + 1;
+    ta.norm = w.scal + 2;
+    ta.first = (n == 0);
+    ta.tol = tol;
+    ta.Nm1 = N - 1;
+    ta.sigma_out = w.sigma + (size_t)n * TTR_RMAX;
+    ta.tail_out = w.tails + n;
+    ta.dec = w.dec;
+    ta.identity = tcx.notrunc;
+    ta.r_orth = (g.nst == 1 && !tcx.notrunc && g.rorth) ? 1 : 0;
+    {
+      ProfScope ps(h, P_SMALL, 0.0, 0.0);
+      launch_trunc_step(h->stream, ta);
+    }
+    h->stats.small_launches++;
+    if ((rc = sync_dec(h))) return rc;
+    const int Ln = h->dec_host[3];
+    L[n + 1] = Ln;
+    sweeps[n] = h->dec_host[9];
+    Stages st = materialized ? no_stages() : base;
+    for (int j = 0; j + 1 < g.nst; ++j) st.R[st.nr++] = st_plain(w.Gst[j], g.dim[j], g.dim[j + 1]);
+    st.R[st.nr++] = st_plain(w.GU, ta.d, Ln);
+    apply(h, materialized ? cvm : cv, st, w.tmp, S.rev);
+    const int zr = (n > 0) ? Lprev : cv.ea();
+    HIPCHK(hipMemcpyAsync(Y->core[S.phys(n)], w.tmp, (size_t)zr * cv.I * Ln * sizeof(double),
+                          hipMemcpyDeviceToDevice, h->stream));
+    ++applies;
+    Pcur = ta.Pnext;
+    Lprev = Ln;
+  }
+  {
+    const int n = N - 1;
+    const CoreView cv = S.view(n);
+    Stages st = no_stages();
+    st.L[st.nl++] = st_plain(Pcur, Lprev, cv.ea());
+    apply(h, cv, st, w.tmp, S.rev);
+    HIPCHK(hipMemcpyAsync(Y->core[S.phys(n)], w.tmp, (size_t)Lprev * cv.I * cv.eb() * sizeof(double),
+                          hipMemcpyDeviceToDevice, h->stream));
+    ++applies;
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(h->scal_host, w.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  const int nsig = (N - 1) * TTR_RMAX;
+  std::vector<double> sig(nsig), tails(N - 1);
+  HIPCHK(hipMemcpyAsync(sig.data(), w.sigma, nsig * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipMemcpyAsync(tails.data(), w.tails, (N - 1) * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  HIPCHK(hipGetLastError());
+  for (int l = 0; l <= N; ++l) Y->R[rev ? N - l : l] = (l == 0 || l == N) ? 1 : L[l];
+  h->stats.gram_passes = passes;
+  h->stats.apply_passes = applies;
+  h->stats.links = N - 1;
+  h->stats.norm = h->scal_host[2];
+  h->stats.delta = h->scal_host[1];
+  for (int l = 0; l < N - 1; ++l) {
+    const int pl = rev ? (N - 1 - l) - 1 : l;
+    if (pl >= TTR_STATS_LINKS) continue;
+    int cnt = 0;
+    for (int j = 0; j < TTR_RMAX; ++j) {
+      h->stats.sigma[(size_t)pl * TTR_STATS_SIGMA + j] = sig[(size_t)l * TTR_RMAX + j];
+      if (sig[(size_t)l * TTR_RMAX + j] > 0) cnt = j + 1;
+    }
+    h->stats.nsigma[pl] = cnt;
+    h->stats.tail2[pl] = tails[l];
+    h->stats.sweeps[pl] = sweeps[l];
+  }
+  if (norm_out) *norm_out = h->scal_host[2];
+  prof_resolve(h);
+  return TTR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int ttr_round(ttr_handle *h, const ttr_tt *X, double tol, int direction, int prec, ttr_tt *Y, double *norm_out) {
   int rc;
   if ((rc = handle_ok(h))) return rc;
   if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(TTR_ERR_INVALID_ARG, "tol must be finite and >= 0");
-  if (direction != TTR_RLR && direction != TTR_LRL) return fail(TTR_ERR_INVALID_ARG, "unknown direction");
+  if (direction != TTR_RLR && direction != TTR_LRL && direction != TTR_RLR_EXPLICIT && direction != TTR_LRL_EXPLICIT)
+    return fail(TTR_ERR_INVALID_ARG, "unknown direction");
+  const int explicit_f = (direction == TTR_RLR_EXPLICIT || direction == TTR_LRL_EXPLICIT);
+  direction = (direction == TTR_LRL || direction == TTR_LRL_EXPLICIT) ? TTR_LRL : TTR_RLR;
   if (prec != TTR_FP64 && prec != TTR_MIXED) return fail(TTR_ERR_INVALID_ARG, "unknown precision");
   if ((rc = check_tt(X, "X", TTR_MAX_RANK_LARGE))) return rc;
   if ((rc = check_out(Y, "Y", X->N, X->I))) return rc;
@@ -1022,10 +1181,11 @@ int ttr_round(ttr_handle *h, const ttr_tt *X, double tol, int direction, int pre
   if (rmax > TTR_MAX_RANK && N > 1) {
     // ranks above the register-tiled kernels' range: the unfolding-based path
     if ((rc = reset_dec(h))) return rc;
-    rc = ttr_round_large(h, X, tol, direction, prec, Y, norm_out);
+    rc = ttr_round_large(h, X, tol, direction, prec, explicit_f, Y, norm_out);
     prof_resolve(h);
     return rc;
   }
+  if (explicit_f && N > 1) return round_explicit_small(h, X, tol, direction == TTR_LRL, prec, Y, norm_out);
   if (N == 1) {
     HIPCHK(hipMemcpyAsync(Y->core[0], X->core[0], (size_t)X->I[0] * sizeof(double), hipMemcpyDeviceToDevice,
                           h->stream));

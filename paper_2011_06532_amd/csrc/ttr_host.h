@@ -60,8 +60,8 @@ void ttr_large_release(ttr_handle *h);
 // Ranks 65..256 (ttr_large.hip): rounding (RLR or LRL, FP64 or mixed),
 // in-place orthonormalization, the orthonormalization norm and the inner
 // product.  Arguments are checked by the callers.
-int ttr_round_large(ttr_handle *h, const ttr_tt *X, double tol, int direction, int prec, ttr_tt *Y,
-                    double *norm_out);
+int ttr_round_large(ttr_handle *h, const ttr_tt *X, double tol, int direction, int prec, int explicit_factors,
+                    ttr_tt *Y, double *norm_out);
 int ttr_orthogonalize_large(ttr_handle *h, ttr_tt *X, int side);
 int ttr_norm_ortho_large(ttr_handle *h, const ttr_tt *X, double *out);
 int ttr_dot_large(ttr_handle *h, const ttr_tt *X, const ttr_tt *Y, double *out);

@@ -898,7 +898,7 @@ constexpr double kTauMix = 1e-5;
 struct Large {
   ttr_handle *h = nullptr;
   // workspace
-  double *G, *Ra, *Rb, *Gst[3], *P[2], *GU, *W0, *W1, *Up, *Ap, *scal, *sigma, *tails, *sv, *Bp, *part;
+  double *G, *Ra, *Rb, *Gst[3], *P[2], *GU, *W0, *W1, *Up, *Ap, *Id, *scal, *sigma, *tails, *sv, *Bp, *part;
   double *tC, *tA, *tB;
   int *perm, *flags;
   std::vector<double *> T;                 // N+1 slots
@@ -907,7 +907,7 @@ struct Large {
 
   int setup(int N, size_t mc) {
     mc = (mc + 63) & ~(size_t)63;
-    const size_t need = (14 + (size_t)(N + 1) + 3 * (size_t)N) * kSlotL + 64 + (size_t)(N + 1) * (kLMax + 1) +
+    const size_t need = (15 + (size_t)(N + 1) + 3 * (size_t)N) * kSlotL + 64 + (size_t)(N + 1) * (kLMax + 1) +
                         3 * (size_t)kLMax + lg_packed_doubles(kLMax, kLMax) + (size_t)512 * kSlotL + 3 * mc + 256;
     if (!h->large) h->large = new LargeCtx();
     LargeCtx *ctx = h->large;
@@ -940,6 +940,7 @@ struct Large {
     W1 = take(kSlotL);
     Up = take(kSlotL);
     Ap = take(kSlotL);
+    Id = take(kSlotL);
     scal = take(64);
     sigma = take((size_t)(N + 1) * kLMax);
     tails = take((size_t)(N + 1));
@@ -1188,10 +1189,11 @@ size_t max_core_of(const ttr_tt *X) {
 }  // namespace
 
 // Rounding of X (ranks up to 256) into Y (§2.4 Alg. 2; implicit factors of
-// §3.5 Alg. 6); RLR or its mirror LRL; prec TTR_MIXED runs the first Gram
-// pass of every factorization in FP32.
-int ttr_round_large(ttr_handle *h, const ttr_tt *X, double tol, int direction, int prec, ttr_tt *Y,
-                    double *norm_out) {
+// §3.5 Alg. 6, or with explicit_factors the orthonormal cores written first,
+// §3.4 Alg. 5, and the truncation sweep run over them); RLR or its mirror
+// LRL; prec TTR_MIXED runs the first Gram pass of every factorization in FP32.
+int ttr_round_large(ttr_handle *h, const ttr_tt *X, double tol, int direction, int prec, int explicit_factors,
+                    ttr_tt *Y, double *norm_out) {
   const int N = X->N;
   const int rev = (direction == TTR_LRL);
   Large L;
@@ -1206,25 +1208,66 @@ int ttr_round_large(ttr_handle *h, const ttr_tt *X, double tol, int direction, i
   };
   std::vector<int> k;
   std::vector<LFac> fac;
-  // ---- sweep 1: orthonormalization with implicit factors ----
-  if ((rc = orth_sweep_large(L, X, rev, prec, k, fac, nullptr))) return rc;
+  const bool ex = explicit_factors != 0;
+  if (ex) {
+    // ---- sweep 1, explicit: Y <- X, orthonormal cores written into Y ----
+    for (int n = 0; n < N; ++n) {
+      TTR_HIPCHK(hipMemcpyAsync(Y->core[n], X->core[n], (size_t)X->R[n] * X->I[n] * X->R[n + 1] * sizeof(double),
+                                hipMemcpyDeviceToDevice, h->stream));
+      Y->R[n] = X->R[n];
+    }
+    Y->R[N] = 1;
+    if ((rc = orth_sweep_large(L, Y, rev, prec, k, fac, Y))) return rc;
+    const int p0 = phys(0);
+    const LView v0{Y->core[p0], Y->I[p0], (int)Y->R[p0], (int)Y->R[p0 + 1], rev};
+    L.right(v0, L.T[1], 1, v0.eb(), k[1], fac[1].tri, L.tC);
+    TTR_HIPCHK(hipMemcpyAsync(Y->core[p0], L.tC, (size_t)Y->I[p0] * k[1] * sizeof(double), hipMemcpyDeviceToDevice,
+                              h->stream));
+    for (int l = 0; l <= N; ++l) Y->R[rev ? N - l : l] = k[l];
+  } else {
+    // ---- sweep 1: orthonormalization with implicit factors ----
+    if ((rc = orth_sweep_large(L, X, rev, prec, k, fac, nullptr))) return rc;
+  }
+  auto yview = [&](int n) {
+    const int p = phys(n);
+    return LView{Y->core[p], Y->I[p], (int)Y->R[p], (int)Y->R[p + 1], rev};
+  };
+  // explicit: the next core's orthonormal factor is written into it, Fn = I
+  double *Id = L.Id;  // cc x cc identity, built per link
+  auto identity = [&](int m) -> int {
+    std::vector<double> id((size_t)m * m, 0.0);
+    for (int j = 0; j < m; ++j) id[(size_t)j * m + j] = 1.0;
+    TTR_HIPCHK(hipStreamSynchronize(h->stream));
+    TTR_HIPCHK(hipMemcpy(Id, id.data(), id.size() * sizeof(double), hipMemcpyHostToDevice));
+    return TTR_OK;
+  };
   // ---- sweep 2: truncation ----
   std::vector<int> Lr(N + 1, 1), sweeps(N, 0);
   const double *Pcur = nullptr;
   int Lprev = 1;
   for (int n = 0; n < N - 1; ++n) {
     const LView v = view(n);
-    // C_n = M_n T_{n+1}, then the left stages F_1^T .. F_{nst-1}^T and P
-    // (the same calls as sweep 1, so each stage meets bitwise the data its
-    // Gram was measured on)
-    LView cur = L.right(v, L.T[n + 1], 1, v.eb(), k[n + 1], fac[n + 1].tri, L.tC);
-    const int cc = k[n + 1];
-    double *bufs[2] = {L.tA, L.tB};
-    if (n >= 1) {
-      for (int j = 1; j < fac[n].nst; ++j)
-        cur = L.left(cur, L.B[n][j - 1], cur.ea(), 1, fac[n].dim[j], bufs[(j - 1) & 1]);
-      double *o = (cur.X == L.tC) ? L.tA : ((cur.X == L.tA) ? L.tB : L.tA);
-      cur = L.left(cur, Pcur, 1, Lprev, Lprev, o);
+    LView cur;
+    int cc;
+    if (ex) {
+      // C'_n = P Y_n with the written orthonormal core Y_n
+      cur = yview(n);
+      cc = cur.eb();
+      if (n >= 1) cur = L.left(cur, Pcur, 1, Lprev, Lprev, L.tA);
+      if ((rc = identity(cc))) return rc;
+    } else {
+      // C_n = M_n T_{n+1}, then the left stages F_1^T .. F_{nst-1}^T and P
+      // (the same calls as sweep 1, so each stage meets bitwise the data its
+      // Gram was measured on)
+      cur = L.right(v, L.T[n + 1], 1, v.eb(), k[n + 1], fac[n + 1].tri, L.tC);
+      cc = k[n + 1];
+      double *bufs[2] = {L.tA, L.tB};
+      if (n >= 1) {
+        for (int j = 1; j < fac[n].nst; ++j)
+          cur = L.left(cur, L.B[n][j - 1], cur.ea(), 1, fac[n].dim[j], bufs[(j - 1) & 1]);
+        double *o = (cur.X == L.tC) ? L.tA : ((cur.X == L.tA) ? L.tB : L.tA);
+        cur = L.left(cur, Pcur, 1, Lprev, Lprev, o);
+      }
     }
     const int crow = cur.ea();
     // QR-by-Gram of V(C'_n)
@@ -1250,8 +1293,8 @@ int ttr_round_large(ttr_handle *h, const ttr_tt *X, double tol, int direction, i
     // truncation: SVD of R (k x cc) unless no singular value can fall below delta
     const int kq = gd[g], dq = gd[g - 1];
     const double *Rq = R[(g - 1) & 1];
-    const double *Fn = L.B[n + 1][fac[n + 1].nst - 1];
-    const int dn = fac[n + 1].dim[fac[n + 1].nst - 1];
+    const double *Fn = ex ? Id : L.B[n + 1][fac[n + 1].nst - 1];
+    const int dn = ex ? cc : fac[n + 1].dim[fac[n + 1].nst - 1];
     double *Pn = L.P[n & 1];
     LTruncArgs ta;
     ta.R = Rq;
@@ -1292,18 +1335,32 @@ int ttr_round_large(ttr_handle *h, const ttr_tt *X, double tol, int direction, i
       Ln = h->dec_host[3];
       // GU = Glast U(:, perm[0:L]) (dq x L); Pnext = Sigma_L V_L^T Fn^T = A(:, perm[0:L])^T Fn^T
       L.sgemm(false, false, dq, Ln, kq, L.Gst[g - 1], dq, L.Up, kq, L.GU, dq);
-      L.sgemm(true, true, Ln, dn, cc, L.Ap, cc, Fn, dn, Pn, Ln);
+      if (ex) L.sgemm(true, false, Ln, cc, cc, L.Ap, cc, Id, cc, Pn, Ln);  // Fn = I
+      else L.sgemm(true, true, Ln, dn, cc, L.Ap, cc, Fn, dn, Pn, Ln);
       GU = L.GU;
     }
     Lr[n + 1] = Ln;
-    // output core n: Y_n(i) = E(i) GU
-    L.right(E, GU, 1, dq, Ln, 0, Y->core[phys(n)]);
+    // output core n: Y_n(i) = E(i) GU (explicit: through tC, Y_n is read)
+    if (ex) {
+      L.right(E, GU, 1, dq, Ln, 0, L.tC);
+      TTR_HIPCHK(hipMemcpyAsync(Y->core[phys(n)], L.tC, (size_t)E.ea() * E.I * Ln * sizeof(double),
+                                hipMemcpyDeviceToDevice, h->stream));
+    } else {
+      L.right(E, GU, 1, dq, Ln, 0, Y->core[phys(n)]);
+    }
     ++L.applies;
     (void)crow;
     Pcur = L.P[n & 1];
     Lprev = Ln;
   }
-  {
+  if (ex) {
+    // last core: P Y_N
+    const LView cur = yview(N - 1);
+    L.left(cur, Pcur, 1, Lprev, Lprev, L.tC);
+    TTR_HIPCHK(hipMemcpyAsync(Y->core[phys(N - 1)], L.tC, (size_t)Lprev * cur.I * cur.eb() * sizeof(double),
+                              hipMemcpyDeviceToDevice, h->stream));
+    ++L.applies;
+  } else {
     // last core: P F_{nst-1}^T .. F_1^T M_N
     const int n = N - 1;
     LView cur = view(n);

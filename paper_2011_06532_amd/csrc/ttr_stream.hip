@@ -8,6 +8,8 @@
 // of T slices is read as R1 coalesced panels and staged in LDS.
 #include "ttr_internal.h"
 
+#include <cstdint>
+
 #include <algorithm>
 
 namespace {
@@ -126,6 +128,52 @@ __global__ void k_hadamard(const double *__restrict__ X, int rx0, int rx1, const
     const int a = e - i * zr0;
     const int ax = a / ry0, ay = a - ax * ry0;
     Z[zoff + e] = Xb[ax + rx0 * (long long)i] * Yb[ay + ry0 * (long long)i];
+  }
+}
+
+// The same product for even R^Y (ry0) with aligned buffers: output column b =
+// (bx, by) of Z is I runs of zr0 = rx0 ry0 doubles, run i being the
+// Kronecker product X(:, i, bx) (x) Y(:, i, by).  A thread takes a pair
+// (ax, 2 ayp), (ax, 2 ayp + 1) of a run: one 16-byte load of Y, one reused
+// X entry, one 16-byte streaming store.  Workgroup (x, b) covers runs
+// [x iper, (x+1) iper) of column b; the (run, ax, ayp) position of a thread
+// advances by fixed increments with carries (no divisions in the loop).
+__global__ __launch_bounds__(256) void k_hadamard_pairs(const double *__restrict__ X, int rx0, int rx1,
+                                                        const double *__restrict__ Y, int ry0, int ry1, int I,
+                                                        int iper, double *__restrict__ Z) {
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  const int hp = ry0 / 2;       // pairs per X entry
+  const int P = rx0 * hp;       // pairs per run
+  const int zr0 = rx0 * ry0;
+  const int b = blockIdx.y;
+  const int bx = b / ry1, by = b - bx * ry1;
+  const int i0 = blockIdx.x * iper;
+  const int i1 = min(I, i0 + iper);
+  const double *Xb = X + (long long)rx0 * I * bx;
+  const double *Yb = Y + (long long)ry0 * I * by;
+  double *Zb = Z + (long long)zr0 * I * b;
+  // starting position of this thread and the increments of a 256-pair step
+  int il = threadIdx.x / P, q = threadIdx.x - il * P;
+  int ax = q / hp, ayp = q - ax * hp;
+  const int di = 256 / P, dq = 256 - di * P;
+  const int dax = dq / hp, dayp = dq - dax * hp;
+  for (int i = i0 + il; i < i1;) {
+    const double x = Xb[ax + (long long)rx0 * i];
+    const d2 y = *reinterpret_cast<const d2 *>(Yb + 2 * ayp + (long long)ry0 * i);
+    const d2 z = {x * y.x, x * y.y};
+    // written once and read by a later pass: stream past the caches
+    __builtin_nontemporal_store(z, reinterpret_cast<d2 *>(Zb + (long long)zr0 * i + ax * ry0 + 2 * ayp));
+    i += di;
+    ax += dax;
+    ayp += dayp;
+    if (ayp >= hp) {
+      ayp -= hp;
+      ++ax;
+    }
+    if (ax >= rx0) {
+      ax -= rx0;
+      ++i;
+    }
   }
 }
 
@@ -422,6 +470,16 @@ void launch_add(hipStream_t s, int n, int N, double alpha, double beta, const do
 void launch_hadamard(hipStream_t s, const double *X, int rx0, int rx1, const double *Y, int ry0, int ry1, long long I,
                      double *Z) {
   const long long colsz = (long long)rx0 * ry0 * I;
+  const bool aligned = ((uintptr_t)Y % 16 == 0) && ((uintptr_t)Z % 16 == 0);
+  if (ry0 % 2 == 0 && aligned && I < (1LL << 31)) {
+    // runs per workgroup: about 64 K pairs of a column per workgroup
+    const long long P = (long long)rx0 * (ry0 / 2);
+    const long long iper = std::max(1LL, std::min(I, (65536 + P - 1) / P));
+    const long long gx = (I + iper - 1) / iper;
+    hipLaunchKernelGGL(k_hadamard_pairs, dim3((unsigned)gx, (unsigned)(rx1 * ry1)), dim3(256), 0, s, X, rx0, rx1, Y,
+                       ry0, ry1, (int)I, (int)iper, Z);
+    return;
+  }
   const long long bx = std::min((colsz + kThreads - 1) / kThreads, 4096LL);
   hipLaunchKernelGGL(k_hadamard, dim3((unsigned)std::max(bx, 1LL), (unsigned)(rx1 * ry1)), dim3(kThreads), 0, s, X,
                      rx0, rx1, Y, ry0, ry1, (int)I, Z);

@@ -30,7 +30,7 @@ TTR_MAX_RANK = 64
 TTR_STATS_LINKS, TTR_STATS_SIGMA = 64, 256
 TTR_ERR_NUMERICAL = 6
 
-_DIR = {"RLR": TTR_RLR, "LRL": TTR_LRL}
+_DIR = {"RLR": TTR_RLR, "LRL": TTR_LRL, "RLR_EXPLICIT": 2, "LRL_EXPLICIT": 3}
 _SIDE = {"right": TTR_RIGHT, "left": TTR_LEFT}
 _NORM = {"ortho": TTR_NORM_ORTHO, "gram": TTR_NORM_GRAM, "sym": TTR_NORM_SYM}
 _PREC = {"fp64": TTR_FP64, "mixed": TTR_MIXED}

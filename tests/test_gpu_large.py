@@ -198,3 +198,22 @@ def test_hadamard_workload_full_N_reduced_I(ttr, h):
     X = Xg.to_numpy()
     got, ref = check_round(ttr, h, X, d["tol"], "RLR", sig_rtol=1e-6, norm_rtol=1e-10)
     print(f"  ranks {O.ranks(got)}", flush=True)
+
+
+@pytest.mark.parametrize("direction", ["RLR", "LRL"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_large_rank_explicit_factors(ttr, h, direction, prec):
+    # explicit orthonormal factors (§3.4 Alg. 5, §4.3.2) at rank 256
+    N, I = 4, 40
+    print(f"hadamard rank 256, explicit factors, {direction} {prec}", flush=True)
+    A = synth.random_tt(4, 2, "A", [I] * N, [16] * (N - 1), scaled=True, rank_weights=True)
+    B = synth.random_tt(4, 2, "B", [I] * N, [16] * (N - 1), scaled=True, rank_weights=True)
+    X = h.hadamard(ttr.TT.from_numpy(A), ttr.TT.from_numpy(B)).to_numpy()
+    g = ttr.TT.from_numpy(X)
+    Yg = h.round(g, 1e-6, direction + "_EXPLICIT", prec)
+    got = Yg.to_numpy()
+    ref = O.round_tt(X, 1e-6, direction)
+    assert O.ranks(got) == O.ranks(ref), (O.ranks(got), O.ranks(ref))
+    rel = O.diff_norm(got, ref) / O.norm_ortho(ref)
+    print(f"  ranks {O.ranks(got)[1:-1]} rel diff {rel:.3e}", flush=True)
+    assert rel <= (1e-10 if prec == "fp64" else 1e-8)

@@ -183,3 +183,29 @@ def test_round_error_bound_and_idempotence(ttr, h):
     Y2 = h.round(Yg, 0.0).to_numpy()
     assert O.ranks(Y2) == O.ranks(Y)
     assert O.diff_norm(Y2, Y) <= 1e-13 * O.norm_ortho(Y)
+
+
+@pytest.mark.parametrize("direction", ["RLR", "LRL"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_round_explicit_factors(ttr, h, direction, prec):
+    # the explicit variants of §4.3.2: orthonormal cores written first (§3.4
+    # Alg. 5), truncation over the written cores; same result as the oracle's
+    # rounding in the same sweep order
+    print(f"round, explicit orthonormal factors, {direction} {prec}", flush=True)
+    rng = np.random.default_rng(210)
+    I = [300, 250, 400, 280, 350]
+    X = O.add(1.0, rand_tt(rng, I, [20, 25, 18, 22], scale=0.2), 1.0, rand_tt(rng, I, [15, 10, 20, 12], scale=0.2))
+    Z = rand_tt(rng, I, [4, 4, 4, 4], scale=0.2)
+    Z[0] *= 1e-6
+    X = O.add(1.0, X, 1.0, Z)
+    g = ttr.TT.from_numpy(X)
+    Yg, nrm = h.round(g, 1e-5, direction + "_EXPLICIT", prec, return_norm=True)
+    got = Yg.to_numpy()
+    ref, info = O.round_tt(X, 1e-5, direction, return_info=True)
+    assert O.ranks(got) == O.ranks(ref), (O.ranks(got), O.ranks(ref))
+    rel = O.diff_norm(got, ref) / O.norm_ortho(ref)
+    print(f"  ranks {O.ranks(got)[1:-1]} rel diff {rel:.3e}", flush=True)
+    assert rel <= (1e-10 if prec == "fp64" else 1e-8)
+    assert math.isclose(nrm, info["norm"], rel_tol=1e-12 if prec == "fp64" else 1e-6)
+    # output orthonormality as for the implicit variant
+    assert orthonormality(got, direction) < (1e-12 if prec == "fp64" else 1e-6)
