@@ -383,7 +383,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched rounding of 512 tensors")
     ap.add_argument("--no-large", action="store_true", help="skip the Hadamard -> rank-256 rounding")
     ap.add_argument("--no-norms", action="store_true", help="skip the timing of the three norm methods and of the explicit orthonormalization")
-    ap.add_argument("--no-mirror", action="store_true", help="skip the rounds in the mirror sweep order")
+    ap.add_argument("--no-mirror", action="store_true",
+                    help="skip the other rounding variants (mirror order, explicit orthonormal factors)")
     ap.add_argument("--no-sum3", action="store_true", help="skip the A + B + 1e-6 C rounding (ranks 50)")
     ap.add_argument("--leg", default="all", choices=["all", "batched", "large", "norms", "sum3"],
                     help="batched / large / norms / sum3: run only that leg (for profiling) and print its JSON object")
@@ -517,32 +518,36 @@ def main():
     # the three norm methods of §3.2.4 on the same X
     norms = None if args.no_norms else bench_norms(h, torch, Xbuf, size_x, args.steps)
 
-    # the mirror sweep order (LRL: left-orthonormalize, truncate right to left)
-    # on the same X, FP64, timed the same way, with its ranks and sampled
-    # entries against the RLR result
+    # the other three rounding variants of §4.3.2 on the same X, FP64, timed
+    # the same way: the mirror sweep order (LRL) and the explicit orthonormal
+    # factors (cores written first, §3.4 Alg. 5) in both orders, with ranks
+    # and sampled entries against this run's rounding
     mirror = None
     if args.prec == "fp64" and not args.no_mirror:
+        mirror = {}
         other = "LRL" if args.direction == "RLR" else "RLR"
-        log(f"{other} rounds")
-        for w in range(args.warmup):
-            Yo = h.round(Xbuf, tol, other, "fp64", out=Ybuf)
-        torch.cuda.synchronize()
-        evo = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-               for _ in range(args.steps)]
-        for k in range(args.steps):
-            evo[k][0].record(stream)
-            Yo = h.round(Xbuf, tol, other, "fp64", out=Ybuf)
-            evo[k][1].record(stream)
-        torch.cuda.synchronize()
-        ms_o = sum(a.elapsed_time(b) for a, b in evo) / args.steps
-        idx = np.random.default_rng(8).integers(0, args.I, size=(256, N))
-        ef = sample_entries(Yf, ranks_fp64, I, idx)
-        eo = sample_entries(Yo.cores, list(Yo.R), I, idx)
-        mirror = {"direction": other, "ms_per_round": round(ms_o, 3),
-                  "round_core_GBps": round(size_x / (ms_o * 1e-3) / 1e9, 2),
-                  "ranks_equal": list(Yo.R) == ranks_fp64,
-                  "max_entry_diff_vs_" + args.direction: float(np.max(np.abs(eo - ef)) / np.sqrt(np.mean(ef * ef)))}
-        del Yo
+        for variant in (other, args.direction + "_EXPLICIT", other + "_EXPLICIT"):
+            log(f"{variant} rounds")
+            for w in range(args.warmup):
+                Yo = h.round(Xbuf, tol, variant, "fp64", out=Ybuf)
+            torch.cuda.synchronize()
+            evo = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                   for _ in range(args.steps)]
+            for k in range(args.steps):
+                evo[k][0].record(stream)
+                Yo = h.round(Xbuf, tol, variant, "fp64", out=Ybuf)
+                evo[k][1].record(stream)
+            torch.cuda.synchronize()
+            ms_o = sum(a.elapsed_time(b) for a, b in evo) / args.steps
+            idx = np.random.default_rng(8).integers(0, args.I, size=(256, N))
+            ef = sample_entries(Yf, ranks_fp64, I, idx)
+            eo = sample_entries(Yo.cores, list(Yo.R), I, idx)
+            mirror[variant] = {"ms_per_round": round(ms_o, 3),
+                               "round_core_GBps": round(size_x / (ms_o * 1e-3) / 1e9, 2),
+                               "ranks_equal": list(Yo.R) == ranks_fp64,
+                               "max_entry_diff_vs_" + args.direction:
+                                   float(np.max(np.abs(eo - ef)) / np.sqrt(np.mean(ef * ef)))}
+            del Yo
 
     # explicit orthonormalization (orthonormal cores written, the §3.4 Alg. 5
     # form) of a copy of X, both sides; the implicit form is the first sweep
@@ -660,7 +665,7 @@ def main():
     if norms:
         out["norms"] = norms
     if mirror:
-        out["mirror_direction"] = mirror
+        out["rounding_variants"] = mirror
     if orth:
         out["orthogonalize_explicit"] = orth
     del A, B, Xbuf, Ybuf, X, Y, Yf

@@ -53,7 +53,7 @@ TT = List[np.ndarray]
 
 __all__ = [
     "H", "V", "from_H", "from_V", "ranks", "dims", "tt_bytes",
-    "add", "hadamard", "dot", "norm_gram", "norm_gram_sym", "pivoted_cholesky", "norm_ortho",
+    "add", "hadamard", "apply_kron", "dot", "norm_gram", "norm_gram_sym", "pivoted_cholesky", "norm_ortho",
     "orthogonalize", "round_tt", "choose_rank",
     "full", "entry", "tt_svd", "diff_norm", "copy_tt",
 ]
@@ -173,6 +173,26 @@ def hadamard(X: TT, Y: TT) -> TT:
             z[:, i, :] = np.kron(x[:, i, :], y[:, i, :])
         Z.append(z)
     return Z
+
+
+def apply_kron(A: Sequence[np.ndarray], X: TT) -> TT:
+    """Matrix-vector product with a Kronecker product of matrices (§3.2.5):
+    vec(Y) = (A_1 (x) ... (x) A_N) vec(X) in TT form, Y_n = X_n x_2 A_n, i.e.
+    Y_n(a, :, b) = A_n X_n(a, :, b) for every a, b; ranks are unchanged.
+    A_n is a dense I_n x I_n array."""
+    _check(X)
+    if len(A) != len(X):
+        raise ValueError("one matrix per mode")
+    Y: TT = []
+    for a_n, x in zip(A, X):
+        r0, In, r1 = x.shape
+        if a_n.shape != (In, In):
+            raise ValueError("A_n must be I_n x I_n")
+        y = np.empty((r0, In, r1), order="F")
+        for b in range(r1):
+            y[:, :, b] = x[:, :, b] @ a_n.T      # rows: (A_n X_n(a, :, b))^T
+        Y.append(y)
+    return Y
 
 
 def dot(X: TT, Y: TT) -> float:

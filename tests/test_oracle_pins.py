@@ -408,3 +408,47 @@ def test_planted_mistakes_fail_pins(monkeypatch):
     def no_split(X, tol):
         return O.round_tt(X, tol * math.sqrt(len(X) - 1))
     assert fails(no_split)
+
+
+# ---------------------------------------------------------------- Kronecker operator (§3.2.5)
+def _kron_vec_full(A, X):
+    """(A_1 (x) ... (x) A_N) applied to the full tensor, by brute force: the
+    Kronecker product acts on vec(X) with the first index slowest, which is
+    numpy's C order of full(X) (index order = mode order)."""
+    T = O.full(X)
+    K = A[0]
+    for a in A[1:]:
+        K = np.kron(K, a)
+    return (K @ T.reshape(-1)).reshape(T.shape)
+
+
+@pytest.mark.parametrize("I,r", SHAPES)
+def test_apply_kron_matches_kronecker_product(I, r):
+    rng = np.random.default_rng(31)
+    X = rand_tt(rng, I, r)
+    A = [rng.standard_normal((n, n)) for n in I]
+    Y = O.apply_kron(A, X)
+    assert O.ranks(Y) == O.ranks(X)
+    ref = _kron_vec_full(A, X)
+    assert rel(O.full(Y), ref) <= 1e-13
+
+
+def test_apply_kron_identities():
+    rng = np.random.default_rng(32)
+    I = [5, 6, 4]
+    X = rand_tt(rng, I, [3, 2])
+    # identity operator; a scaled identity on one mode scales the tensor
+    Y = O.apply_kron([np.eye(n) for n in I], X)
+    assert all(np.array_equal(y, x) for y, x in zip(Y, X))
+    A = [np.eye(n) for n in I]
+    A[1] = 3.0 * np.eye(I[1])
+    assert rel(O.full(O.apply_kron(A, X)), 3.0 * O.full(X)) <= 1e-15
+    # (A (x) B)(C (x) D) = AC (x) BD: two applications equal one with the products
+    A1 = [rng.standard_normal((n, n)) for n in I]
+    A2 = [rng.standard_normal((n, n)) for n in I]
+    two = O.apply_kron(A2, O.apply_kron(A1, X))
+    one = O.apply_kron([b @ a for a, b in zip(A1, A2)], X)
+    assert rel(O.full(two), O.full(one)) <= 1e-13
+    # a transposed operator (the planted slip X_n A_n instead of A_n X_n) fails
+    At = [a.T for a in A1]
+    assert rel(O.full(O.apply_kron(At, X)), _kron_vec_full(A1, X)) > 1e-3
