@@ -112,6 +112,20 @@ int ttr_add(ttr_handle *h, double alpha, const ttr_tt *X, double beta, const ttr
  * ranks multiply.  Z->R is written.  Asynchronous. */
 int ttr_hadamard(ttr_handle *h, const ttr_tt *X, const ttr_tt *Y, ttr_tt *Z);
 
+/* Matrix-vector product with a Kronecker product of matrices (§3.2.5):
+ * vec(Y) = (A_1 (x) ... (x) A_N) vec(X), computed core by core as the mode-2
+ * products Y_n(a, :, b) = A_n X_n(a, :, b); ranks are unchanged (Y->R = X->R).
+ * A_n (I_n x I_n) is given in band storage with kl[n] sub- and ku[n]
+ * super-diagonals: A_n(i, j) = A[n][(ku[n] + i - j) + (kl[n] + ku[n] + 1) j]
+ * for max(0, j - ku[n]) <= i <= min(I_n - 1, j + kl[n]) (a dense A_n is the
+ * band kl = ku = I_n - 1, whose cost grows with I_n^2).  A: N DEVICE pointers
+ * (array in host memory); kl, ku: host arrays.  Y's cores need
+ * cap[n] >= R[n] I[n] R[n+1] of X and must not alias X's.  Left ranks up to
+ * 4096.  A sum of Kronecker products is applied term by term, then summed with
+ * ttr_add and rounded with ttr_round.  Asynchronous. */
+int ttr_apply_kron(ttr_handle *h, const double *const *A, const int64_t *kl, const int64_t *ku, const ttr_tt *X,
+                   ttr_tt *Y);
+
 /* *out = <X, Y> by the recursion W_n = sum_i Y_n(i)^T W_{n-1} X_n(i), W_0 = 1
  * (§3.2.3, eq. (4)).  `out` is host memory.  Synchronizes. */
 int ttr_dot(ttr_handle *h, const ttr_tt *X, const ttr_tt *Y, double *out);
@@ -244,13 +258,16 @@ int ttr_get_round_stats(const ttr_handle *h, ttr_round_stats *out);
  *  10 k_apply_fac2         output pass with two right factors (refined core)
  *  11 k_gram_right_factor  as 0, FP32 matrix cores (TTR_MIXED first pass)
  *  12 k_gram_left_factor   as 1, FP32 matrix cores (TTR_MIXED first pass)
+ *  13 k_kron_apply         mode-2 products of ttr_apply_kron (bytes: core
+ *                          read + written, band read; flops: 2 per band entry
+ *                          and output)
  * Gram passes: bytes = the core read once, flops = the slice products plus the
  * symmetric Gram accumulation; output passes: bytes = core read + output
  * written, flops = the slice products; sum/Hadamard: bytes = inputs read +
  * output written.  Durations are resolved at the end of each synchronizing
  * call and by ttr_get_profile, which waits for the stream.
  * ttr_set_profiling(h, 1) also clears the accumulators. */
-#define TTR_NPROF 13
+#define TTR_NPROF 14
 typedef struct ttr_profile {
   int64_t count[TTR_NPROF];
   double ms[TTR_NPROF];

@@ -138,7 +138,7 @@ WS carve(ttr_handle *h, int N, size_t tmp, size_t mat = 0) {
 // --- opt-in kernel timing ------------------------------------------------
 enum {
   P_GRAM_R = 0, P_GRAM_L = 1, P_GRAM_G = 2, P_APPLY = 3, P_APPLY_G = 4, P_ADD = 5, P_HAD = 6, P_DOT = 7, P_SMALL = 8,
-  P_GRAM_FAC = 9, P_APPLY_FAC2 = 10, P_GRAM_R32 = 11, P_GRAM_L32 = 12
+  P_GRAM_FAC = 9, P_APPLY_FAC2 = 10, P_GRAM_R32 = 11, P_GRAM_L32 = 12, P_KRON = 13
 };
 
 hipEvent_t take_event(ttr_handle *h) {
@@ -819,6 +819,35 @@ static bool any_rank_above(const ttr_tt *X, int64_t r) {
   for (int n = 0; n <= X->N; ++n)
     if (X->R[n] > r) return true;
   return false;
+}
+
+int ttr_apply_kron(ttr_handle *h, const double *const *A, const int64_t *kl, const int64_t *ku, const ttr_tt *X,
+                   ttr_tt *Y) {
+  int rc;
+  if ((rc = handle_ok(h))) return rc;
+  if (!A || !kl || !ku) return fail(TTR_ERR_INVALID_ARG, "A, kl or ku is NULL");
+  if ((rc = check_tt(X, "X", 0))) return rc;
+  if ((rc = check_out(Y, "Y", X->N, X->I))) return rc;
+  const int N = X->N;
+  for (int n = 0; n < N; ++n) {
+    if (!A[n]) return fail(TTR_ERR_INVALID_ARG, "NULL operator matrix");
+    if (kl[n] < 0 || ku[n] < 0 || kl[n] >= X->I[n] || ku[n] >= X->I[n])
+      return fail(TTR_ERR_INVALID_ARG, "bandwidths must satisfy 0 <= kl, ku < I_n");
+    if (Y->core[n] == X->core[n]) return fail(TTR_ERR_INVALID_ARG, "Y aliases X");
+    if (Y->cap[n] < X->R[n] * X->I[n] * X->R[n + 1]) return fail(TTR_ERR_CAPACITY, "Y core capacity too small");
+    if (X->R[n] > 4096 || X->R[n + 1] >= 65536 || X->I[n] >= ((int64_t)1 << 40))
+      return fail(TTR_ERR_UNSUPPORTED, "rank above 4096 (left) or 65535 (right)");
+  }
+  for (int n = 0; n < N; ++n) {
+    const double elems = (double)X->R[n] * X->I[n] * X->R[n + 1];
+    ProfScope ps(h, P_KRON, 16.0 * elems + 8.0 * (double)(kl[n] + ku[n] + 1) * X->I[n],
+                 2.0 * elems * (double)(kl[n] + ku[n] + 1));
+    launch_kron_apply(h->stream, X->core[n], (int)X->R[n], (int)X->R[n + 1], X->I[n], A[n], (int)kl[n], (int)ku[n],
+                      Y->core[n]);
+  }
+  HIPCHK(hipGetLastError());
+  for (int n = 0; n <= N; ++n) Y->R[n] = X->R[n];
+  return TTR_OK;
 }
 
 int ttr_dot(ttr_handle *h, const ttr_tt *X, const ttr_tt *Y, double *out) {

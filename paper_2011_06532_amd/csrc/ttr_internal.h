@@ -49,6 +49,10 @@ void launch_add(hipStream_t s, int n, int N, double alpha, double beta, const do
                 const double *Y, int ry0, int ry1, long long I, double *Z);
 void launch_hadamard(hipStream_t s, const double *X, int rx0, int rx1, const double *Y, int ry0, int ry1,
                      long long I, double *Z);
+// Y = X x_2 A for one core (a x I x b): A banded (kl, ku), band storage
+// A(i, j) = AB[(ku + i - j) + (kl + ku + 1) j].  a <= 4096.
+void launch_kron_apply(hipStream_t s, const double *X, int r0, int r1, long long I, const double *AB, int kl, int ku,
+                       double *Y);
 // Per-workgroup partial Grams sum_i Z(i) Z(i)^T (LEFT, gd = rows of Z) or
 // Z(i)^T Z(i) (RIGHT, gd = cols of Z) into `partials` (TTR_MAXWG * gd * gd
 // doubles).  Returns the workgroup count; launch_reduce then sums the partials

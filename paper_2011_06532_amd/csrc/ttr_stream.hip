@@ -178,6 +178,60 @@ __global__ __launch_bounds__(256) void k_hadamard_pairs(const double *__restrict
 }
 
 // ---------------------------------------------------------------------------
+// Mode-2 product with a banded matrix (one core of the Kronecker-operator
+// matrix-vector product, §3.2.5): Y(a, i, b) = sum_j A(i, j) X(a, j, b) over
+// max(0, i - kl) <= j <= min(I - 1, i + ku), A in band storage
+// A(i, j) = AB[(ku + i - j) + (kl + ku + 1) j].  For fixed b the runs
+// X(:, j, b) are contiguous, so workgroup (x, b) produces the TI runs
+// i0 .. i0 + TI - 1 of column b (TI r0 <= 4096 outputs, 16 per thread) from
+// the runs its band reaches, staged in LDS JC at a time with contiguous loads;
+// each output sums its band in increasing j.
+// ---------------------------------------------------------------------------
+constexpr int kKronOut = 16;  // outputs per thread
+__global__ __launch_bounds__(256) void k_kron_apply(const double *__restrict__ X, int r0, long long I,
+                                                    const double *__restrict__ AB, int kl, int ku, int TI, int JC,
+                                                    double *__restrict__ Y) {
+  HIP_DYNAMIC_SHARED(double, Xs);
+  const int b = blockIdx.y;
+  const long long i0 = (long long)blockIdx.x * TI;
+  const int ti = (int)std::min<long long>(TI, I - i0);
+  const int nout = ti * r0;
+  const long long ld = (long long)kl + ku + 1;
+  const double *Xb = X + (long long)r0 * I * b;
+  double *Yb = Y + (long long)r0 * I * b;
+  int oi[kKronOut], oa[kKronOut];
+  double acc[kKronOut];
+#pragma unroll
+  for (int k = 0; k < kKronOut; ++k) {
+    const int e = threadIdx.x + 256 * k;
+    oi[k] = e / r0;
+    oa[k] = e - oi[k] * r0;
+    acc[k] = 0.0;
+  }
+  const long long jlo = std::max(0LL, i0 - kl), jhi = std::min(I, i0 + ti + ku);
+  for (long long j0 = jlo; j0 < jhi; j0 += JC) {
+    const int jc = (int)std::min<long long>(JC, jhi - j0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < jc * r0; e += 256) Xs[e] = Xb[(long long)r0 * j0 + e];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kKronOut; ++k) {
+      if (threadIdx.x + 256 * k >= nout) break;
+      const long long i = i0 + oi[k];
+      const long long ja = std::max(j0, i - kl), jb = std::min(j0 + jc, i + ku + 1);
+      double s = acc[k];
+      for (long long j = ja; j < jb; ++j) s += AB[(ku + i - j) + ld * j] * Xs[(j - j0) * r0 + oa[k]];
+      acc[k] = s;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kKronOut; ++k) {
+    const int e = threadIdx.x + 256 * k;
+    if (e < nout) Yb[(long long)r0 * i0 + e] = acc[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Chunk staging and the small transforms, shared by the Gram and apply passes.
 // ---------------------------------------------------------------------------
 struct Chunk {
@@ -465,6 +519,15 @@ void launch_add(hipStream_t s, int n, int N, double alpha, double beta, const do
   const long long bx = std::min((colsz + kThreads - 1) / kThreads, 4096LL);
   hipLaunchKernelGGL(k_add, dim3((unsigned)std::max(bx, 1LL), (unsigned)zr1), dim3(kThreads), 0, s, n, N, alpha, beta,
                      X, rx0, rx1, Y, ry0, ry1, (int)I, Z);
+}
+
+void launch_kron_apply(hipStream_t s, const double *X, int r0, int r1, long long I, const double *AB, int kl, int ku,
+                       double *Y) {
+  const int TI = (int)std::max(1LL, std::min<long long>(I, (256LL * kKronOut) / r0));
+  const int JC = std::max(1, 8192 / r0);
+  const long long gx = (I + TI - 1) / TI;
+  hipLaunchKernelGGL(k_kron_apply, dim3((unsigned)gx, (unsigned)r1), dim3(256), (size_t)JC * r0 * sizeof(double), s, X,
+                     r0, I, AB, kl, ku, TI, JC, Y);
 }
 
 void launch_hadamard(hipStream_t s, const double *X, int rx0, int rx1, const double *Y, int ry0, int ry1, long long I,

@@ -40,7 +40,7 @@ SYMBOLS = [
     "ttr_create", "ttr_destroy", "ttr_set_stream", "ttr_add", "ttr_hadamard", "ttr_dot", "ttr_norm",
     "ttr_orthogonalize", "ttr_round", "ttr_status_string", "ttr_last_error", "ttr_get_round_stats",
     "ttr_set_profiling", "ttr_get_profile", "ttr_round_batched", "ttr_get_batch_plan", "ttr_set_allocator",
-    "ttr_dot_noalloc",
+    "ttr_dot_noalloc", "ttr_apply_kron",
 ]
 
 # ttr_set_allocator callback types: void *alloc(size_t bytes, void *ctx), void free(void *ptr, void *ctx)
@@ -49,7 +49,7 @@ FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 PROF_CLASSES = ["k_gram_right_factor", "k_gram_left_factor", "k_gram", "k_apply_mfma", "k_apply", "k_add",
                 "k_hadamard", "k_dot", "small", "k_gram_fac", "k_apply_fac2", "k_gram_right_factor_f32",
-                "k_gram_left_factor_f32"]
+                "k_gram_left_factor_f32", "k_kron_apply"]
 NPROF = len(PROF_CLASSES)  # TTR_NPROF
 
 
@@ -129,6 +129,7 @@ def load(path: str = LIB_PATH):
     lib.ttr_hadamard.argtypes = [vp, tt, tt, tt]
     lib.ttr_dot.argtypes = [vp, tt, tt, P(ctypes.c_double)]
     lib.ttr_dot_noalloc.argtypes = [vp, tt, tt, vp]
+    lib.ttr_apply_kron.argtypes = [vp, P(ctypes.c_void_p), P(ctypes.c_int64), P(ctypes.c_int64), tt, tt]
     lib.ttr_norm.argtypes = [vp, tt, ctypes.c_int, P(ctypes.c_double)]
     lib.ttr_orthogonalize.argtypes = [vp, tt, ctypes.c_int, ctypes.c_int]
     lib.ttr_round.argtypes = [vp, tt, ctypes.c_double, ctypes.c_int, ctypes.c_int, tt, P(ctypes.c_double)]
@@ -301,6 +302,21 @@ class Handle:
         sx, sy = X._struct(), Y._struct()
         _check(_lib.ttr_dot_noalloc(self.h, ctypes.byref(sx), ctypes.byref(sy), ctypes.c_void_p(out.data_ptr())))
         return out
+
+    def apply_kron(self, A_band, kl, ku, X: TT, out: Optional[TT] = None) -> TT:
+        """Y = (A_1 (x) ... (x) A_N) X (ttr_apply_kron).  A_band: N float64
+        device tensors in band storage ((kl + ku + 1) x I_n, column-major, i.e.
+        torch shape (I_n, kl + ku + 1) row-major); kl, ku: bandwidths."""
+        N = X.N
+        caps = [X.R[n] * X.I[n] * X.R[n + 1] for n in range(N)]
+        Y = out if out is not None else TT.empty(X.I, caps, X.cores[0].device)
+        ptrs = (ctypes.c_void_p * N)(*[a.data_ptr() for a in A_band])
+        kla = (ctypes.c_int64 * N)(*[int(v) for v in kl])
+        kua = (ctypes.c_int64 * N)(*[int(v) for v in ku])
+        sx, sy = X._struct(), Y._struct()
+        _check(_lib.ttr_apply_kron(self.h, ptrs, kla, kua, ctypes.byref(sx), ctypes.byref(sy)))
+        Y._read_ranks()
+        return Y
 
     def norm(self, X: TT, method: str = "ortho") -> float:
         out = ctypes.c_double()

@@ -310,3 +310,68 @@ def test_allocator_failure_reports_alloc(ttr):
     Y = h.round(ttr.TT.from_numpy(X), 1e-6, "RLR").to_numpy()
     assert O.ranks(Y) == [1, 6, 5, 1]
     h.close()
+
+
+def _band(rng, n, kl, ku):
+    """A random n x n matrix with kl sub- and ku super-diagonals, dense and in
+    band storage (torch shape (n, kl + ku + 1): row j holds column j)."""
+    A = rng.standard_normal((n, n))
+    i, j = np.indices((n, n))
+    A[(i - j > kl) | (j - i > ku)] = 0.0
+    ld = kl + ku + 1
+    AB = np.zeros((n, ld))
+    for jj in range(n):
+        for ii in range(max(0, jj - ku), min(n, jj + kl + 1)):
+            AB[jj, ku + ii - jj] = A[ii, jj]
+    return A, AB
+
+
+KRON_CASES = [
+    ([300, 257, 129, 64], [9, 33, 7], [(1, 1), (0, 2), (3, 0), (1, 1)]),
+    ([40, 35, 50], [64, 64], [(39, 39), (2, 5), (49, 49)]),          # dense A_1 and A_3
+    ([1000, 20, 800], [5, 256], [(1, 1), (19, 0), (2, 2)]),           # a rank-256 core
+    ([7, 1, 9], [3, 3], [(6, 6), (0, 0), (1, 3)]),                    # I_n = 1
+]
+
+
+@pytest.mark.parametrize("I,r,bands", KRON_CASES)
+def test_apply_kron_matches_oracle(ttr, h, I, r, bands):
+    import torch
+    print(f"Kronecker operator I={I} r={r} bands={bands}", flush=True)
+    rng = np.random.default_rng(120)
+    X = rand_tt(rng, I, r)
+    dense, band = zip(*[_band(rng, n, kl, ku) for n, (kl, ku) in zip(I, bands)])
+    AB = [torch.from_numpy(np.ascontiguousarray(b)).cuda() for b in band]
+    Y = h.apply_kron(AB, [b[0] for b in bands], [b[1] for b in bands], ttr.TT.from_numpy(X)).to_numpy()
+    ref = O.apply_kron(list(dense), X)
+    assert O.ranks(Y) == O.ranks(X)
+    for n, (y, yr) in enumerate(zip(Y, ref)):
+        assert np.max(np.abs(y - yr)) <= 1e-13 * max(np.max(np.abs(yr)), 1e-300), n
+
+
+def test_apply_kron_sum_and_round(ttr, h):
+    # the Krylov building block: Y = (A_1 (x) ... (x) A_N) X + X, then rounding,
+    # against the oracle's same three steps
+    print("Kronecker operator, sum and rounding", flush=True)
+    rng = np.random.default_rng(121)
+    I = [200, 150, 180, 120]
+    X = rand_tt(rng, I, [6, 8, 5])
+    lap = []
+    for n in I:   # 1-D Laplacian stencil (tridiagonal)
+        A = 2.0 * np.eye(n) - np.eye(n, k=1) - np.eye(n, k=-1)
+        lap.append(A)
+    band = [np.stack([-np.ones(n), 2.0 * np.ones(n), -np.ones(n)], axis=1) for n in I]  # (ku=1: row j = [A(j-1,j), A(j,j), A(j+1,j)])
+    AB = [torch_tensor(b) for b in band]
+    gX = ttr.TT.from_numpy(X)
+    gY = h.apply_kron(AB, [1] * len(I), [1] * len(I), gX)
+    gS = h.add(1.0, gY, 1.0, gX)
+    got = h.round(gS, 1e-10).to_numpy()
+    S = O.add(1.0, O.apply_kron(lap, X), 1.0, X)
+    ref = O.round_tt(S, 1e-10)
+    assert O.ranks(got) == O.ranks(ref)
+    assert O.diff_norm(got, ref) <= 1e-10 * O.norm_ortho(ref)
+
+
+def torch_tensor(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
