@@ -282,6 +282,28 @@ def bench_large(h, ttr, torch, steps):
             r["ranks_equal_fp64_rlr"] = list(Y.R) == ranks64
         out[f"{prec}_{direction}"] = r
     out["mixed_speedup"] = round(out["fp64_RLR"]["ms_per_round"] / out["mixed_RLR"]["ms_per_round"], 3)
+    # the same rounding with the Hadamard product kept implicit (A * B never
+    # formed, §3.2.2), FP64 RLR, against the formed path's ranks
+    del X
+    torch.cuda.empty_cache()
+    log("large: implicit Hadamard rounding")
+    Yi = h.round_hadamard(A, B, tol, "RLR", "fp64", out=Y)
+    torch.cuda.synchronize()
+    ts = []
+    for k in range(max(1, min(steps, 3))):
+        e0.record(stream)
+        Yi = h.round_hadamard(A, B, tol, "RLR", "fp64", out=Y)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+        log(f"large implicit: round {k + 1}: {ts[-1]:.1f} ms")
+    ms_i = sum(ts) / len(ts)
+    out["implicit_hadamard_RLR"] = {"ms_per_round": round(ms_i, 3), "ranks": list(Yi.R),
+                                    "ranks_equal_fp64_rlr": list(Yi.R) == ranks64,
+                                    "error_bound": error_bound_figures(h, torch, Yi, tol),
+                                    "speedup_vs_hadamard_then_round":
+                                        round((out["fp64_RLR"]["ms_per_round"] + ms_had) / ms_i, 3)}
+    X = None
     del X, Y, A, B
     torch.cuda.empty_cache()
     return out

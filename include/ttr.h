@@ -177,6 +177,19 @@ int ttr_orthogonalize(ttr_handle *h, ttr_tt *X, int side, int prec);
 int ttr_round(ttr_handle *h, const ttr_tt *X, double tol, int direction, int prec,
               ttr_tt *Y, double *norm_out);
 
+/* Y = rounding of the Hadamard product A * B (§3.2.2) to relative accuracy
+ * tol, without forming A * B: the closing remark of §3.2.2 (keep the product
+ * implicit for the rounding that follows).  The result is that of
+ * ttr_hadamard followed by ttr_round(TTR_RLR): every product of a core of
+ * A * B with a small matrix, (A_n(i) (x) B_n(i)) T, is formed from the
+ * factors' slices (two 16 x 16 products per slice and column instead of one
+ * with the Kronecker slice), and only the last core A_N (x) B_N is formed.
+ * Ranks of A and B <= 16 (so ranks of A * B <= 256); direction TTR_RLR
+ * (TTR_ERR_UNSUPPORTED otherwise); prec TTR_FP64 or TTR_MIXED.  Y's cores need
+ * cap[n] >= R^A_n R^B_n I_n R^A_{n+1} R^B_{n+1}.  Synchronizes. */
+int ttr_round_hadamard(ttr_handle *h, const ttr_tt *A, const ttr_tt *B, double tol, int direction, int prec,
+                       ttr_tt *Y, double *norm_out);
+
 /* Batched rounding (the batched form of §2.4 Alg. 2): Y[t] = rounding of X[t]
  * to relative accuracy tol[t], t = 0..count-1, for tensors of uneven mode
  * sizes and ranks that share the number of cores N (2 <= N <= 16), RLR order.

@@ -1409,6 +1409,41 @@ int ttr_round(ttr_handle *h, const ttr_tt *X, double tol, int direction, int pre
   return TTR_OK;
 }
 
+int ttr_round_hadamard(ttr_handle *h, const ttr_tt *A, const ttr_tt *B, double tol, int direction, int prec,
+                       ttr_tt *Y, double *norm_out) {
+  int rc;
+  if ((rc = handle_ok(h))) return rc;
+  if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(TTR_ERR_INVALID_ARG, "tol must be finite and >= 0");
+  if (prec != TTR_FP64 && prec != TTR_MIXED) return fail(TTR_ERR_INVALID_ARG, "unknown precision");
+  if (direction != TTR_RLR) return fail(TTR_ERR_UNSUPPORTED, "ttr_round_hadamard supports TTR_RLR");
+  if ((rc = check_tt(A, "A", 16))) return rc;
+  if ((rc = check_tt(B, "B", 16))) return rc;
+  if (A->N != B->N) return fail(TTR_ERR_SHAPE, "A and B differ in N");
+  for (int n = 0; n < A->N; ++n)
+    if (A->I[n] != B->I[n]) return fail(TTR_ERR_SHAPE, "A and B differ in mode sizes");
+  if ((rc = check_out(Y, "Y", A->N, A->I))) return rc;
+  const int N = A->N;
+  for (int n = 0; n < N; ++n) {
+    const int64_t need = A->R[n] * B->R[n] * A->I[n] * A->R[n + 1] * B->R[n + 1];
+    if (Y->cap[n] < need) return fail(TTR_ERR_CAPACITY, "Y core capacity too small");
+    if (Y->core[n] == A->core[n] || Y->core[n] == B->core[n]) return fail(TTR_ERR_INVALID_ARG, "Y aliases A or B");
+  }
+  std::memset(&h->stats, 0, sizeof(h->stats));
+  if (N == 1) {
+    // a single core: the product itself
+    launch_hadamard(h->stream, A->core[0], 1, 1, B->core[0], 1, 1, A->I[0], Y->core[0]);
+    HIPCHK(hipStreamSynchronize(h->stream));
+    HIPCHK(hipGetLastError());
+    Y->R[0] = Y->R[1] = 1;
+    if (norm_out) *norm_out = NAN;
+    return TTR_OK;
+  }
+  if ((rc = reset_dec(h))) return rc;
+  rc = ttr_round_hadamard_large(h, A, B, tol, prec, Y, norm_out);
+  prof_resolve(h);
+  return rc;
+}
+
 const char *ttr_status_string(int status) {
   switch (status) {
     case TTR_OK: return "ok";

@@ -65,6 +65,8 @@ int ttr_round_large(ttr_handle *h, const ttr_tt *X, double tol, int direction, i
 int ttr_orthogonalize_large(ttr_handle *h, ttr_tt *X, int side);
 int ttr_norm_ortho_large(ttr_handle *h, const ttr_tt *X, double *out);
 int ttr_dot_large(ttr_handle *h, const ttr_tt *X, const ttr_tt *Y, double *out);
+int ttr_round_hadamard_large(ttr_handle *h, const ttr_tt *A, const ttr_tt *B, double tol, int prec, ttr_tt *Y,
+                             double *norm_out);
 
 #define TTR_HIPCHK(expr)                                                                              \
   do {                                                                                                \

@@ -113,6 +113,11 @@ LGramGrid lg_gram_grid(long long M, int f32);
 // fscale (FP32 only, device): the scale pair of launch_lg_scale_probe.
 int launch_lg_gram(hipStream_t s, const double *X1, const double *X2, long long M, int K1, int K2, long long ld1,
                    long long ld2, int xcol, int f32, double *part, const double *fscale = nullptr);
+// C(i) = (A(i) (x) B(i)) T for every slice (Kronecker index a_x rB + a_y):
+// A a0 x I x a1, B b0 x I x b1 (all <= 16), T (a1 b1) x k (ld ldt); C is the
+// (a0 b0) x I x k core.
+void launch_lg_kron_right(hipStream_t s, const double *A, int a0, int a1, const double *B, int b0, int b1, long long I,
+                          const double *T, long long ldt, int k, double *C);
 // out[0] = 2^-e, out[1] = 2^2e from the largest sampled |x| of X (n doubles).
 void launch_lg_scale_probe(hipStream_t s, const double *X, long long n, double *out);
 // C (m x n, ld ldc) = A B, A(i, k) = A[i ar + k ac], B(k, j) = B[k br + j bc].

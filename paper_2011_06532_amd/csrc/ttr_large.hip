@@ -904,11 +904,16 @@ struct Large {
   std::vector<double *> T;                 // N+1 slots
   std::vector<std::array<double *, 3>> B;  // N x 3 slots
   int passes = 0, applies = 0, sweeps = 0;
+  // implicit Hadamard product: the cores n < N-1 of X are A_n (x) B_n,
+  // never formed (right products through launch_lg_kron_right)
+  const ttr_tt *KA = nullptr, *KB = nullptr;
+  double *xlast = nullptr;  // the formed last core of A * B
 
-  int setup(int N, size_t mc) {
+  int setup(int N, size_t mc, size_t extra = 0) {
     mc = (mc + 63) & ~(size_t)63;
     const size_t need = (15 + (size_t)(N + 1) + 3 * (size_t)N) * kSlotL + 64 + (size_t)(N + 1) * (kLMax + 1) +
-                        3 * (size_t)kLMax + lg_packed_doubles(kLMax, kLMax) + (size_t)512 * kSlotL + 3 * mc + 256;
+                        3 * (size_t)kLMax + lg_packed_doubles(kLMax, kLMax) + (size_t)512 * kSlotL + 3 * mc + extra +
+                        256;
     if (!h->large) h->large = new LargeCtx();
     LargeCtx *ctx = h->large;
     if (ctx->bytes < need * sizeof(double)) {
@@ -957,6 +962,7 @@ struct Large {
     tC = take(mc);
     tA = take(mc);
     tB = take(mc);
+    xlast = extra ? take(extra) : nullptr;
     for (int i = 0; i < 16; ++i) h->dec_host[i] = 0;
     TTR_HIPCHK(hipMemcpyAsync(h->dec_dev, h->dec_host, 16 * sizeof(int), hipMemcpyHostToDevice, h->stream));
     return TTR_OK;
@@ -979,6 +985,17 @@ struct Large {
     // Z(i) = B^T M(i): H(Z)^T = H(M)^T B
     launch_lg_gemm(h->stream, v.X, v.I * v.pb, v.pa, v.pa, 0, Bm, bsr, bsc, n, tri, Bp, out, n, 0);
     return LView{out, v.I, n, v.pb, 1};
+  }
+  // Z'(i) = M'(i) T for core n of the tensor being rounded: for an implicit
+  // Hadamard product (cores n < N-1) C(i) = (A_n(i) (x) B_n(i)) T formed
+  // straight from the factors, otherwise right().
+  LView right_core(int n, int N, const LView &v, const double *Tm, long long ldt, int k, int tri, double *out) {
+    if (KA && n < N - 1 && !v.trans) {
+      launch_lg_kron_right(h->stream, KA->core[n], (int)KA->R[n], (int)KA->R[n + 1], KB->core[n], (int)KB->R[n],
+                           (int)KB->R[n + 1], v.I, Tm, ldt, k, out);
+      return LView{out, v.I, v.pa, k, 0};
+    }
+    return right(v, Tm, 1, ldt, k, tri, out);
   }
   // Z'(i) = A M'(i) (A(r, c) = A[r asr + c asc], m x ea) into `out`.
   LView left(const LView &v, const double *Am, long long asr, long long asc, int m, double *out) {
@@ -1129,7 +1146,7 @@ int orth_sweep_large(Large &L, const ttr_tt *X, int rev, int prec, std::vector<i
     const LView v = view(n);
     const int a = v.ea(), b = v.eb();
     LView cur = v;
-    if (n < N - 1) cur = L.right(v, L.T[n + 1], 1, b, k[n + 1], fac[n + 1].tri, L.tC);
+    if (n < N - 1) cur = L.right_core(n, N, v, L.T[n + 1], b, k[n + 1], fac[n + 1].tri, L.tC);
     double *bufs[2] = {L.tA, L.tB};
     double *R[2] = {L.Ra, L.Rb};
     fac[n].dim[0] = a;
@@ -1192,15 +1209,27 @@ size_t max_core_of(const ttr_tt *X) {
 // §3.5 Alg. 6, or with explicit_factors the orthonormal cores written first,
 // §3.4 Alg. 5, and the truncation sweep run over them); RLR or its mirror
 // LRL; prec TTR_MIXED runs the first Gram pass of every factorization in FP32.
+namespace {
+int round_large_with(Large &L, ttr_handle *h, const ttr_tt *X, double tol, int direction, int prec,
+                     int explicit_factors, ttr_tt *Y, double *norm_out);
+}  // namespace
+
 int ttr_round_large(ttr_handle *h, const ttr_tt *X, double tol, int direction, int prec, int explicit_factors,
                     ttr_tt *Y, double *norm_out) {
-  const int N = X->N;
-  const int rev = (direction == TTR_LRL);
   Large L;
   L.h = h;
   L.mixed = (prec == TTR_MIXED);
   int rc;
-  if ((rc = L.setup(N, max_core_of(X)))) return rc;
+  if ((rc = L.setup(X->N, max_core_of(X)))) return rc;
+  return round_large_with(L, h, X, tol, direction, prec, explicit_factors, Y, norm_out);
+}
+
+namespace {
+int round_large_with(Large &L, ttr_handle *h, const ttr_tt *X, double tol, int direction, int prec,
+                     int explicit_factors, ttr_tt *Y, double *norm_out) {
+  const int N = X->N;
+  const int rev = (direction == TTR_LRL);
+  int rc;
   auto phys = [&](int n) { return rev ? N - 1 - n : n; };
   auto view = [&](int n) {
     const int p = phys(n);
@@ -1259,7 +1288,7 @@ int ttr_round_large(ttr_handle *h, const ttr_tt *X, double tol, int direction, i
       // C_n = M_n T_{n+1}, then the left stages F_1^T .. F_{nst-1}^T and P
       // (the same calls as sweep 1, so each stage meets bitwise the data its
       // Gram was measured on)
-      cur = L.right(v, L.T[n + 1], 1, v.eb(), k[n + 1], fac[n + 1].tri, L.tC);
+      cur = L.right_core(n, N, v, L.T[n + 1], v.eb(), k[n + 1], fac[n + 1].tri, L.tC);
       cc = k[n + 1];
       double *bufs[2] = {L.tA, L.tB};
       if (n >= 1) {
@@ -1391,6 +1420,8 @@ int ttr_round_large(ttr_handle *h, const ttr_tt *X, double tol, int direction, i
   return TTR_OK;
 }
 
+}  // namespace
+
 // In-place orthonormalization at ranks above 64 (§2.3 Alg. 1; written cores
 // as in §3.4 Alg. 5).  side TTR_LEFT runs the mirror image.
 int ttr_orthogonalize_large(ttr_handle *h, ttr_tt *X, int side) {
@@ -1471,4 +1502,40 @@ int ttr_dot_large(ttr_handle *h, const ttr_tt *X, const ttr_tt *Y, double *out) 
   TTR_HIPCHK(hipStreamSynchronize(h->stream));
   *out = h->scal_host[1];
   return TTR_OK;
+}
+
+// Rounding of the Hadamard product A * B without forming it (the closing
+// remark of §3.2.2: keep the product implicit for rounding): RLR rounding of
+// X = A * B (§2.4 Alg. 2) where every product of an original core with a
+// small matrix, C_n(i) = (A_n(i) (x) B_n(i)) T_{n+1}, runs on the factors'
+// slices (launch_lg_kron_right); only the last core A_N (x) B_N is formed.
+// Factor ranks <= 16, ranks of A * B <= 256; RLR only.
+int ttr_round_hadamard_large(ttr_handle *h, const ttr_tt *A, const ttr_tt *B, double tol, int prec, ttr_tt *Y,
+                             double *norm_out) {
+  const int N = A->N;
+  std::vector<int64_t> R(N + 1), I(N);
+  for (int n = 0; n <= N; ++n) R[n] = A->R[n] * B->R[n];
+  for (int n = 0; n < N; ++n) I[n] = A->I[n];
+  size_t mc = 0;
+  for (int n = 0; n < N; ++n) mc = std::max(mc, (size_t)(R[n] * I[n] * R[n + 1]));
+  const size_t last = (size_t)R[N - 1] * I[N - 1];
+  Large L;
+  L.h = h;
+  L.mixed = (prec == TTR_MIXED);
+  L.KA = A;
+  L.KB = B;
+  int rc;
+  if ((rc = L.setup(N, mc, (last + 63) & ~(size_t)63))) return rc;
+  // a shape-only description of X = A * B; only its last core is formed
+  std::vector<double *> cores(N, nullptr);
+  launch_hadamard(h->stream, A->core[N - 1], (int)A->R[N - 1], 1, B->core[N - 1], (int)B->R[N - 1], 1, I[N - 1],
+                  L.xlast);
+  cores[N - 1] = L.xlast;
+  ttr_tt X;
+  X.N = N;
+  X.I = I.data();
+  X.R = R.data();
+  X.core = cores.data();
+  X.cap = nullptr;
+  return round_large_with(L, h, &X, tol, TTR_RLR, prec, 0, Y, norm_out);
 }

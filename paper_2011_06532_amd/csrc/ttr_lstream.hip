@@ -422,7 +422,83 @@ __global__ __launch_bounds__(64) void lg_sgemm(const double *__restrict__ A, lon
   }
 }
 
+// ---------------------------------------------------------------------------
+// Right product of a slice-wise Kronecker product (the implicit Hadamard
+// product of §3.2.2): C(i) = (A(i) (x) B(i)) T for every slice i, with
+// A(i) rA0 x rA1, B(i) rB0 x rB1 (all <= 16) and T (rA1 rB1) x k, never
+// forming A(i) (x) B(i).  Column t of C(i) is vec(B(i) T_t A(i)^T), T_t the
+// rB1 x rA1 reshape of T(:, t) (T_t(by, bx) = T(bx rB1 + by, t)), so per slice
+// and column two 16 x 16 x 16 products replace a (rA0 rB0) x (rA1 rB1) one:
+//   D1 = T_t^T B(i)^T = W_t^T   (rA1 x rB0; its result registers are the
+//                                operand fragments of the next product)
+//   D2 = A(i) W_t^T  = O_t^T    (rA0 x rB0): C(ax rB0 + ay, i, t) = D2(ax, ay)
+// Wave = four columns t (their T fragments held in registers) over the
+// workgroup's run of slices; the slices' A and B fragments are read once per
+// slice and wave (L2-shared by the waves of other columns).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void lg_kron_right(const double *__restrict__ A, int a0, int a1,
+                                                     const double *__restrict__ B, int b0, int b1, long long I,
+                                                     const double *__restrict__ T, long long ldt, int k, long long spw,
+                                                     double *__restrict__ C) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int t0 = (blockIdx.y * 4 + w) * 4;  // this wave's four columns
+  if (t0 >= k) return;
+  const int r16 = lane % 16, g = lane / 16;
+  // T_t^T fragments: A-operand rows bx = r16, k-step s covers by = 4s + g
+  double tf[4][4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int t = t0 + j, bx = r16, by = 4 * s + g;
+      tf[j][s] = (t < k && bx < a1 && by < b1) ? T[(bx * b1 + by) + ldt * t] : 0.0;
+    }
+  const long long i0 = (long long)blockIdx.x * spw, i1 = std::min(I, i0 + spw);
+  const long long cs = (long long)a0 * b0;  // rows of C
+  for (long long i = i0; i < i1; ++i) {
+    // B(i)^T as B-operand of D1: rows by = 4s + g (k), columns ay = r16
+    // A(i) as A-operand of D2: rows ax = r16, k-step s covers bx = 4s + g
+    double bf[4], af[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int by = 4 * s + g, bx = 4 * s + g;
+      bf[s] = (r16 < b0 && by < b1) ? B[r16 + (long long)b0 * (i + I * by)] : 0.0;
+      af[s] = (r16 < a0 && bx < a1) ? A[r16 + (long long)a0 * (i + I * bx)] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int t = t0 + j;
+      if (t >= k) break;
+      d4 d1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < 4; ++s) d1 = mma(tf[j][s], bf[s], d1);
+      // d1 register s = W_t^T(bx = 4s + g, ay = r16): the B-operand of k-step s
+      d4 d2 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < 4; ++s) d2 = mma(af[s], d1[s], d2);
+      // d2 register r = O_t^T(ax = 4r + g, ay = r16)
+      double *Ct = C + cs * (i + I * t);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ax = 4 * r + g;
+        if (ax < a0 && r16 < b0) Ct[ax * b0 + r16] = d2[r];
+      }
+    }
+  }
+}
+
 }  // namespace
+
+void launch_lg_kron_right(hipStream_t s, const double *A, int a0, int a1, const double *B, int b0, int b1, long long I,
+                          const double *T, long long ldt, int k, double *C) {
+  // about 16 waves' worth of slices per workgroup column group, >= 1024 workgroups
+  const long long gy = (k + 15) / 16;
+  long long gx = std::max(1LL, std::min(I, (4096 + gy - 1) / gy));
+  const long long spw = (I + gx - 1) / gx;
+  gx = (I + spw - 1) / spw;
+  hipLaunchKernelGGL(lg_kron_right, dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, s, A, a0, a1, B, b0, b1, I, T, ldt,
+                     k, spw, C);
+}
 
 size_t lg_packed_doubles(int K, int N) { return (size_t)((K + 3) / 4) * ((N + 15) / 16) * 64; }
 

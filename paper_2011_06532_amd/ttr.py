@@ -40,7 +40,7 @@ SYMBOLS = [
     "ttr_create", "ttr_destroy", "ttr_set_stream", "ttr_add", "ttr_hadamard", "ttr_dot", "ttr_norm",
     "ttr_orthogonalize", "ttr_round", "ttr_status_string", "ttr_last_error", "ttr_get_round_stats",
     "ttr_set_profiling", "ttr_get_profile", "ttr_round_batched", "ttr_get_batch_plan", "ttr_set_allocator",
-    "ttr_dot_noalloc", "ttr_apply_kron",
+    "ttr_dot_noalloc", "ttr_apply_kron", "ttr_round_hadamard",
 ]
 
 # ttr_set_allocator callback types: void *alloc(size_t bytes, void *ctx), void free(void *ptr, void *ctx)
@@ -130,6 +130,8 @@ def load(path: str = LIB_PATH):
     lib.ttr_dot.argtypes = [vp, tt, tt, P(ctypes.c_double)]
     lib.ttr_dot_noalloc.argtypes = [vp, tt, tt, vp]
     lib.ttr_apply_kron.argtypes = [vp, P(ctypes.c_void_p), P(ctypes.c_int64), P(ctypes.c_int64), tt, tt]
+    lib.ttr_round_hadamard.argtypes = [vp, tt, tt, ctypes.c_double, ctypes.c_int, ctypes.c_int, tt,
+                                       P(ctypes.c_double)]
     lib.ttr_norm.argtypes = [vp, tt, ctypes.c_int, P(ctypes.c_double)]
     lib.ttr_orthogonalize.argtypes = [vp, tt, ctypes.c_int, ctypes.c_int]
     lib.ttr_round.argtypes = [vp, tt, ctypes.c_double, ctypes.c_int, ctypes.c_int, tt, P(ctypes.c_double)]
@@ -338,6 +340,19 @@ class Handle:
         sx, sy = X._struct(), Y._struct()
         _check(_lib.ttr_round(self.h, ctypes.byref(sx), float(tol), _DIR[direction], _PREC[prec],
                               ctypes.byref(sy), ctypes.byref(nrm)))
+        Y._read_ranks()
+        return (Y, nrm.value) if return_norm else Y
+
+    def round_hadamard(self, A: TT, B: TT, tol: float, direction: str = "RLR", prec: str = "fp64",
+                       out: Optional[TT] = None, return_norm: bool = False):
+        """Rounding of A * B without forming it (ttr_round_hadamard)."""
+        R = [A.R[n] * B.R[n] for n in range(A.N + 1)]
+        caps = [R[n] * A.I[n] * R[n + 1] for n in range(A.N)]
+        Y = out if out is not None else TT.empty(A.I, caps, A.cores[0].device)
+        nrm = ctypes.c_double()
+        sa, sb, sy = A._struct(), B._struct(), Y._struct()
+        _check(_lib.ttr_round_hadamard(self.h, ctypes.byref(sa), ctypes.byref(sb), float(tol), _DIR[direction],
+                                       _PREC[prec], ctypes.byref(sy), ctypes.byref(nrm)))
         Y._read_ranks()
         return (Y, nrm.value) if return_norm else Y
 

@@ -171,6 +171,29 @@ def test_hadamard_rank256_I512(ttr, h):
     assert math.sqrt(sum(st["tail2"])) <= d["tol"] * nrm
 
 
+def test_round_hadamard_implicit_I512(ttr, h):
+    # the Hadamard workload's factors (N = 6, I = 512) rounded without forming
+    # A * B: ranks, tensor and singular values against the oracle
+    N, I = 6, 512
+    print(f"implicit Hadamard rounding N={N} I={I}", flush=True)
+    d = synth.hadamard_r256(I_override=I, N=N)
+    Yg = h.round_hadamard(ttr.TT.from_numpy(d["A"]), ttr.TT.from_numpy(d["B"]), d["tol"])
+    got = Yg.to_numpy()
+    X = O.hadamard(d["A"], d["B"])
+    ref, info = O.round_tt(X, d["tol"], "RLR", return_info=True)
+    assert O.ranks(got) == O.ranks(ref)
+    rel = O.diff_norm(got, ref) / O.norm_ortho(ref)
+    print(f"  rel diff {rel:.3e}", flush=True)
+    assert rel <= 1e-10
+    st = h.round_stats()
+    for l, (s_gpu, s_ref) in enumerate(zip(st["sigmas"], info["sigmas"])):
+        k = min(len(s_gpu), len(s_ref))
+        if k == 0:
+            continue
+        big = np.asarray(s_ref[:k]) > 1e-6 * s_ref[0]
+        assert np.allclose(np.asarray(s_gpu[:k])[big], np.asarray(s_ref[:k])[big], rtol=1e-6), l
+
+
 @pytest.mark.parametrize("part", [0, 1, 2, 3])
 def test_batched_members_full_size(ttr, h, part):
     # 64 members of the batched workload, full mode sizes (64..4096), rounded in

@@ -217,3 +217,27 @@ def test_large_rank_explicit_factors(ttr, h, direction, prec):
     rel = O.diff_norm(got, ref) / O.norm_ortho(ref)
     print(f"  ranks {O.ranks(got)[1:-1]} rel diff {rel:.3e}", flush=True)
     assert rel <= (1e-10 if prec == "fp64" else 1e-8)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("ra,rb", [(16, 16), (7, 9), (3, 16)])
+def test_round_hadamard_implicit(ttr, h, prec, ra, rb):
+    # rounding of A * B without forming it (§3.2.2, closing remark) against the
+    # oracle's rounding of the formed product
+    N, I = 5, 30
+    print(f"implicit Hadamard rounding, ranks {ra} x {rb}, {prec}", flush=True)
+    A = synth.random_tt(4, 3, "A", [I] * N, [ra] * (N - 1), scaled=True, rank_weights=True)
+    B = synth.random_tt(4, 3, "B", [I] * N, [rb] * (N - 1), scaled=True, rank_weights=True)
+    gA, gB = ttr.TT.from_numpy(A), ttr.TT.from_numpy(B)
+    Yg, nrm = h.round_hadamard(gA, gB, 1e-6, "RLR", prec, return_norm=True)
+    got = Yg.to_numpy()
+    X = O.hadamard(A, B)
+    ref, info = O.round_tt(X, 1e-6, "RLR", return_info=True)
+    assert O.ranks(got) == O.ranks(ref), (O.ranks(got), O.ranks(ref))
+    rel = O.diff_norm(got, ref) / O.norm_ortho(ref)
+    print(f"  ranks {O.ranks(got)[1:-1]} rel diff {rel:.3e}", flush=True)
+    assert rel <= (1e-10 if prec == "fp64" else 1e-8)
+    assert abs(nrm - info["norm"]) <= (1e-10 if prec == "fp64" else 1e-6) * info["norm"]
+    with pytest.raises(ttr.TTRError) as e:
+        h.round_hadamard(gA, gB, 1e-6, "LRL", prec)
+    assert e.value.code == 7
