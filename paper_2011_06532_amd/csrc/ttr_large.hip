@@ -710,85 +710,223 @@ __device__ inline void lrr_pair(int r, int kq, int nn, int *p, int *q) {
   }
 }
 
-// One round of the block one-sided Jacobi SVD of A (b x k): the k columns form
-// nbp (even) blocks of kJW; round `round` of the round-robin pairs block P
-// with block Q in workgroup `pair`, which runs one one-sided Jacobi sweep over
-// the 2 kJW columns held in LDS (rotations also applied to the same columns of
-// U) and writes them back.  Each inner step rotates 2 kJW / 2 disjoint column
-// pairs at once, one wave per pair: the wave's lanes hold rows l, l + 64, ...,
-// and the three inner products are wave sums.  A pair is rotated when
-// |a_p^T a_q| > thr[0] ||a_p|| ||a_q|| and both squared norms exceed thr[1].
-// flags[sweep] is set when any rotation was applied; a launch of sweep s > 0
-// returns at once when sweep s - 1 applied none (converged), so the host can
-// queue several sweeps before it looks.
-constexpr int kJW = 16;
-constexpr int kJT = kJW * 64;  // one wave per column pair of the block pair
-__device__ inline void lwave_sum3(double &a, double &b, double &c) {
-  for (int off = 32; off >= 1; off >>= 1) {
-    a += __shfl_xor(a, off, 64);
-    b += __shfl_xor(b, off, 64);
-    c += __shfl_xor(c, off, 64);
-  }
+// One round of the block one-sided Jacobi SVD of A (b x k, b, k <= 256): the
+// k columns form nbp (even) blocks of kJW; in round `round` workgroup `pair`
+// holds block P and block Q of the round-robin pairing, and each 16-lane row
+// of its waves one column pair (lane j: rows j, j + 16, ...), so a wave
+// rotates four pairs at once.  The P columns stay; in kJW steps every (P, Q)
+// column pair is rotated once, the Q columns moving one pair down through LDS
+// after each step.  Round 0 of a sweep first rotates the pairs inside P and
+// inside Q (kJW - 1 steps in LDS), so a sweep of nbp - 1 rounds rotates each
+// of the k(k-1)/2 pairs once.  The three inner products of a pair are row
+// sums by DPP (bitwise the same in the row's 16 lanes, so the rotation
+// decision is uniform over the pair).  A pair is rotated when |a_p^T a_q| >
+// thr[0] ||a_p|| ||a_q|| and both squared norms exceed thr[1].  The rotations
+// are accumulated in a 2 kJW x 2 kJW orthogonal J (column c of J beside
+// column c of A, rows j and j + 16 in lane j), and the round ends with
+// U(:, P u Q) = U(:, P u Q) J on the matrix cores.  flags[sweep] is set when
+// any rotation was applied; a launch of sweep s > 0 returns at once when sweep
+// s - 1 applied none (converged), so the host can queue several sweeps before
+// it looks.
+constexpr int kJW = 16;             // columns per block
+constexpr int kJC = 2 * kJW;        // columns held by a workgroup
+constexpr int kJT = 256;            // kJW pairs, one per 16-lane row
+constexpr int kJR = kLMax / 16;     // rows of a column per lane
+
+template <int CTRL>
+__device__ __forceinline__ double ldpp(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
 }
+
+// Sum over the 16 lanes of a DPP row, the same value (bitwise) in each.
+__device__ __forceinline__ double lrow_total(double x) {
+  x += ldpp<0xB1>(x);   // quad_perm [1,0,3,2]
+  x += ldpp<0x4E>(x);   // quad_perm [2,3,0,1]
+  x += ldpp<0x141>(x);  // row_half_mirror
+  x += ldpp<0x140>(x);  // row_mirror
+  return x;
+}
+
+__device__ __forceinline__ bool ljac_rotate(double *x, double *y, double *jx, double *jy, double tol,
+                                            double floor2) {
+  double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+  for (int m = 0; m < kJR; ++m) {
+    al += x[m] * x[m];
+    be += y[m] * y[m];
+    ga += x[m] * y[m];
+  }
+  al = lrow_total(al);
+  be = lrow_total(be);
+  ga = lrow_total(ga);
+  if (!(al > floor2 && be > floor2 && fabs(ga) > tol * sqrt(al) * sqrt(be))) return false;
+  const double zeta = (be - al) / (2.0 * ga);
+  const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  const double c = 1.0 / sqrt(1.0 + t * t);
+  const double sn = c * t;
+#pragma unroll
+  for (int m = 0; m < kJR; ++m) {
+    const double u = x[m], v = y[m];
+    x[m] = c * u - sn * v;
+    y[m] = sn * u + c * v;
+  }
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    const double u = jx[m], v = jy[m];
+    jx[m] = c * u - sn * v;
+    jy[m] = sn * u + c * v;
+  }
+  return true;
+}
+
+typedef double ld4 __attribute__((ext_vector_type(4)));
+
 __global__ __launch_bounds__(kJT) void lk_jacobi_round(double *__restrict__ A, double *__restrict__ U, int b, int k,
                                                        int nbp, int round, const double *__restrict__ thr,
                                                        int *__restrict__ flags, int sweep) {
   if (sweep > 0 && flags[sweep - 1] == 0) return;
-  constexpr int NC = 2 * kJW;
-  __shared__ double As[NC][kLMax];
-  __shared__ double Us[NC][kLMax];
+  // hA: the 2 kJW columns in the within-block steps, then the exchange buffers
+  // of the cross steps ([2][kJW][kLMax]); hJ likewise for J, then J itself
+  // (hJ[column][row])
+  __shared__ double hA[kJC][kLMax];
+  __shared__ double hJ[kJC][kJC];
   int P, Q;
   lrr_pair(round, blockIdx.x, nbp, &P, &Q);
-  auto gcol = [&](int l) { return l < kJW ? P * kJW + l : Q * kJW + (l - kJW); };
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  // column l of the pair is loaded by wave l % 16 (two columns per wave)
-  for (int l = wave; l < NC; l += kJW) {
-    const int c = gcol(l);
-    for (int r = lane; r < b; r += 64) As[l][r] = (c < k) ? A[r + (size_t)b * c] : 0.0;
-    for (int r = lane; r < k; r += 64) Us[l][r] = (c < k) ? U[r + (size_t)k * c] : 0.0;
-  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int j = lane & 15, g = lane >> 4;
+  const int pr = 4 * wv + g;  // the pair of this 16-lane row
   const double tol = thr[0], floor2 = thr[1];
+  auto gcol = [&](int l) { return l < kJW ? P * kJW + l : Q * kJW + (l - kJW); };
   int rotated = 0;
-  __syncthreads();
-  for (int rr = 0; rr < NC - 1; ++rr) {
-    int p, q;
-    lrr_pair(rr, wave, NC, &p, &q);
-    if (gcol(p) < k && gcol(q) < k) {
-      double al = 0.0, be = 0.0, ga = 0.0;
-      for (int r = lane; r < b; r += 64) {
-        const double x = As[p][r], y = As[q][r];
-        al += x * x;
-        be += y * y;
-        ga += x * y;
+  double ap[kJR], aq[kJR], jp[2], jq[2];
+  if (round == 0) {
+    for (int e = threadIdx.x; e < kJC * kLMax; e += kJT) {
+      const int l = e / kLMax, r = e % kLMax, c = gcol(l);
+      hA[l][r] = (c < k && r < b) ? A[r + (size_t)b * c] : 0.0;
+    }
+    for (int e = threadIdx.x; e < kJC * kJC; e += kJT) hJ[e / kJC][e % kJC] = (e / kJC == e % kJC) ? 1.0 : 0.0;
+    __syncthreads();
+    // pairs inside P (rows 0..kJW/2-1) and inside Q (the others)
+    const int off = (pr < kJW / 2) ? 0 : kJW;
+    for (int st = 0; st < kJW - 1; ++st) {
+      int p, q;
+      lrr_pair(st, pr % (kJW / 2), kJW, &p, &q);
+      p += off;
+      q += off;
+#pragma unroll
+      for (int m = 0; m < kJR; ++m) {
+        ap[m] = hA[p][j + 16 * m];
+        aq[m] = hA[q][j + 16 * m];
       }
-      lwave_sum3(al, be, ga);
-      if (al > floor2 && be > floor2 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
-        const double zeta = (be - al) / (2.0 * ga);
-        const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double c = 1.0 / sqrt(1.0 + t * t);
-        const double sn = c * t;
-        for (int r = lane; r < b; r += 64) {
-          const double x = As[p][r], y = As[q][r];
-          As[p][r] = c * x - sn * y;
-          As[q][r] = sn * x + c * y;
-        }
-        for (int r = lane; r < k; r += 64) {
-          const double x = Us[p][r], y = Us[q][r];
-          Us[p][r] = c * x - sn * y;
-          Us[q][r] = sn * x + c * y;
-        }
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        jp[m] = hJ[p][j + 16 * m];
+        jq[m] = hJ[q][j + 16 * m];
+      }
+      if (ljac_rotate(ap, aq, jp, jq, tol, floor2)) {
         rotated = 1;
+#pragma unroll
+        for (int m = 0; m < kJR; ++m) {
+          hA[p][j + 16 * m] = ap[m];
+          hA[q][j + 16 * m] = aq[m];
+        }
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+          hJ[p][j + 16 * m] = jp[m];
+          hJ[q][j + 16 * m] = jq[m];
+        }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int m = 0; m < kJR; ++m) {
+      ap[m] = hA[pr][j + 16 * m];
+      aq[m] = hA[kJW + pr][j + 16 * m];
+    }
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      jp[m] = hJ[pr][j + 16 * m];
+      jq[m] = hJ[kJW + pr][j + 16 * m];
+    }
+    __syncthreads();  // hA and hJ become the exchange buffers
+  } else {
+    const int c0 = gcol(pr), c1 = gcol(kJW + pr);
+#pragma unroll
+    for (int m = 0; m < kJR; ++m) {
+      const int r = j + 16 * m;
+      ap[m] = (c0 < k && r < b) ? A[r + (size_t)b * c0] : 0.0;
+      aq[m] = (c1 < k && r < b) ? A[r + (size_t)b * c1] : 0.0;
+    }
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      jp[m] = (j + 16 * m == pr) ? 1.0 : 0.0;
+      jq[m] = (j + 16 * m == kJW + pr) ? 1.0 : 0.0;
+    }
+  }
+  // cross steps: at step s pair pr holds P column pr and Q column (pr + s) % kJW
+  double(*xA)[kJW][kLMax] = reinterpret_cast<double(*)[kJW][kLMax]>(&hA[0][0]);
+  double(*xJ)[kJW][kJC] = reinterpret_cast<double(*)[kJW][kJC]>(&hJ[0][0]);
+  for (int s = 0; s < kJW; ++s) {
+    if (ljac_rotate(ap, aq, jp, jq, tol, floor2)) rotated = 1;
+    if (s + 1 < kJW) {
+      const int buf = s & 1, src = (pr + 1) % kJW;
+#pragma unroll
+      for (int m = 0; m < kJR; ++m) xA[buf][pr][j + 16 * m] = aq[m];
+#pragma unroll
+      for (int m = 0; m < 2; ++m) xJ[buf][pr][j + 16 * m] = jq[m];
+      __syncthreads();
+#pragma unroll
+      for (int m = 0; m < kJR; ++m) aq[m] = xA[buf][src][j + 16 * m];
+#pragma unroll
+      for (int m = 0; m < 2; ++m) jq[m] = xJ[buf][src][j + 16 * m];
+    }
+  }
+  const int qw = kJW + (pr + kJW - 1) % kJW;  // local index of the Q column held at the end
+  {
+    const int c0 = gcol(pr), c1 = gcol(qw);
+#pragma unroll
+    for (int m = 0; m < kJR; ++m) {
+      const int r = j + 16 * m;
+      if (r < b) {
+        if (c0 < k) A[r + (size_t)b * c0] = ap[m];
+        if (c1 < k) A[r + (size_t)b * c1] = aq[m];
       }
     }
-    __syncthreads();
   }
-  for (int l = wave; l < NC; l += kJW) {
-    const int c = gcol(l);
-    if (c >= k) continue;
-    for (int r = lane; r < b; r += 64) A[r + (size_t)b * c] = As[l][r];
-    for (int r = lane; r < k; r += 64) U[r + (size_t)k * c] = Us[l][r];
+  __syncthreads();  // the last exchange has been read: hJ takes J
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    hJ[pr][j + 16 * m] = jp[m];
+    hJ[qw][j + 16 * m] = jq[m];
   }
-  if (rotated && lane == 0) flags[sweep] = 1;
+  if (rotated && j == 0) flags[sweep] = 1;
+  if (!__syncthreads_or(rotated)) return;  // J = I: U unchanged
+  // U(:, P u Q) = U(:, P u Q) J, computed as its transpose J^T U^T; wave wv
+  // takes the 16-row tiles wv, wv + 4, ... of U (k x k, ld k)
+  for (int t = wv; 16 * t < k; t += kJT / 64) {
+    const int row = 16 * t + j;
+    double bf[kJC / 4];  // bf[ks] = U(row, held column 4 ks + g)
+#pragma unroll
+    for (int ks = 0; ks < kJC / 4; ++ks) {
+      const int c = gcol(4 * ks + g);
+      bf[ks] = (c < k && row < k) ? U[row + (size_t)k * c] : 0.0;
+    }
+#pragma unroll
+    for (int ct = 0; ct < kJC / 16; ++ct) {
+      ld4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int ks = 0; ks < kJC / 4; ++ks)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(hJ[16 * ct + j][4 * ks + g], bf[ks], acc, 0, 0, 0);
+      // register r: U(row, held column 16 ct + 4 r + g)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int c = gcol(16 * ct + 4 * r + g);
+        if (c < k && row < k) U[row + (size_t)k * c] = acc[r];
+      }
+    }
+  }
 }
 
 // Truncation, part 3 (after the Jacobi sweeps): singular values (column norms
