@@ -749,7 +749,7 @@ __device__ __forceinline__ double lrow_total(double x) {
   return x;
 }
 
-__device__ __forceinline__ bool ljac_rotate(double *x, double *y, double *jx, double *jy, double tol,
+__device__ __forceinline__ bool ljac_rotate(double *x, double *y, double *jx, double *jy, double tol2,
                                             double floor2) {
   double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
@@ -761,10 +761,14 @@ __device__ __forceinline__ bool ljac_rotate(double *x, double *y, double *jx, do
   al = lrow_total(al);
   be = lrow_total(be);
   ga = lrow_total(ga);
-  if (!(al > floor2 && be > floor2 && fabs(ga) > tol * sqrt(al) * sqrt(be))) return false;
-  const double zeta = (be - al) / (2.0 * ga);
-  const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-  const double c = 1.0 / sqrt(1.0 + t * t);
+  // |ga| > tol sqrt(al be), squared (the Gram passes bound the data's range
+  // well inside the squares' range)
+  if (!(al > floor2 && be > floor2 && ga * ga > tol2 * (al * be))) return false;
+  // the smaller rotation angle: t = tan(theta) = sign(zeta) / (|zeta| +
+  // sqrt(1 + zeta^2)), zeta = (be - al) / (2 ga), without forming zeta
+  const double df = be - al, ga2 = 2.0 * ga;
+  const double t = (df >= 0 ? ga2 : -ga2) / (fabs(df) + sqrt(df * df + ga2 * ga2));
+  const double c = rsqrt(1.0 + t * t);
   const double sn = c * t;
 #pragma unroll
   for (int m = 0; m < kJR; ++m) {
@@ -797,7 +801,7 @@ __global__ __launch_bounds__(kJT) void lk_jacobi_round(double *__restrict__ A, d
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int j = lane & 15, g = lane >> 4;
   const int pr = 4 * wv + g;  // the pair of this 16-lane row
-  const double tol = thr[0], floor2 = thr[1];
+  const double tol2 = thr[0] * thr[0], floor2 = thr[1];
   auto gcol = [&](int l) { return l < kJW ? P * kJW + l : Q * kJW + (l - kJW); };
   int rotated = 0;
   double ap[kJR], aq[kJR], jp[2], jq[2];
@@ -825,7 +829,7 @@ __global__ __launch_bounds__(kJT) void lk_jacobi_round(double *__restrict__ A, d
         jp[m] = hJ[p][j + 16 * m];
         jq[m] = hJ[q][j + 16 * m];
       }
-      if (ljac_rotate(ap, aq, jp, jq, tol, floor2)) {
+      if (ljac_rotate(ap, aq, jp, jq, tol2, floor2)) {
         rotated = 1;
 #pragma unroll
         for (int m = 0; m < kJR; ++m) {
@@ -869,7 +873,7 @@ __global__ __launch_bounds__(kJT) void lk_jacobi_round(double *__restrict__ A, d
   double(*xA)[kJW][kLMax] = reinterpret_cast<double(*)[kJW][kLMax]>(&hA[0][0]);
   double(*xJ)[kJW][kJC] = reinterpret_cast<double(*)[kJW][kJC]>(&hJ[0][0]);
   for (int s = 0; s < kJW; ++s) {
-    if (ljac_rotate(ap, aq, jp, jq, tol, floor2)) rotated = 1;
+    if (ljac_rotate(ap, aq, jp, jq, tol2, floor2)) rotated = 1;
     if (s + 1 < kJW) {
       const int buf = s & 1, src = (pr + 1) % kJW;
 #pragma unroll
