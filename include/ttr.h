@@ -58,10 +58,15 @@ enum { TTR_RLR = 0, TTR_LRL = 1, TTR_RLR_EXPLICIT = 2, TTR_LRL_EXPLICIT = 3 };
 enum { TTR_NORM_ORTHO = 0, TTR_NORM_GRAM = 1, TTR_NORM_SYM = 2 };    /* norm method (§3.2.4) */
 enum { TTR_FP64 = 0, TTR_MIXED = 1 };              /* arithmetic of the Gram passes */
 
-/* Largest TT rank of the matrix-core tiled kernels (every entry point). */
+/* Largest TT rank of the register/LDS-tiled matrix-core kernels.  Every entry
+ * point accepts it; ttr_norm(TTR_NORM_SYM), ttr_dot_noalloc and
+ * ttr_round_batched stop there (ttr_add, ttr_hadamard and ttr_apply_kron
+ * state their own limits). */
 #define TTR_MAX_RANK 64
-/* Largest rank ttr_round accepts: ranks 65..256 take a GEMM-based path
- * (TTR_RLR only; FP64 arithmetic also for TTR_MIXED). */
+/* Largest rank of ttr_round (every direction, TTR_FP64 and TTR_MIXED),
+ * ttr_dot, ttr_norm (TTR_NORM_ORTHO, TTR_NORM_GRAM) and ttr_orthogonalize:
+ * ranks 65..256 take the GEMM-shaped matrix-core path (one unfolding times a
+ * small matrix per product, Gram matrices of whole unfoldings). */
 #define TTR_MAX_RANK_LARGE 256
 
 /* A TT tensor.  All arrays are HOST memory; core[n] are DEVICE pointers.
@@ -127,7 +132,8 @@ int ttr_apply_kron(ttr_handle *h, const double *const *A, const int64_t *kl, con
                    ttr_tt *Y);
 
 /* *out = <X, Y> by the recursion W_n = sum_i Y_n(i)^T W_{n-1} X_n(i), W_0 = 1
- * (§3.2.3, eq. (4)).  `out` is host memory.  Synchronizes. */
+ * (§3.2.3, eq. (4)).  `out` is host memory.  Ranks <= TTR_MAX_RANK_LARGE.
+ * Synchronizes. */
 int ttr_dot(ttr_handle *h, const ttr_tt *X, const ttr_tt *Y, double *out);
 
 /* ttr_dot for callers that cannot allocate device memory (code under HIP
@@ -150,17 +156,21 @@ int ttr_dot_noalloc(ttr_handle *h, const ttr_tt *X, const ttr_tt *Y, double *out
  * Z_n(i) = F X_n(i) and F^T F = W_{n-1} from a pivoted Cholesky (§3.2.4), made
  * upper triangular so half of each product is skipped; same cancellation as
  * GRAM.  TTR_NORM_ORTHO: right-orthonormalization sweep (implicit, X
- * untouched) then ||X_1||_F (§2.3; accurate for small norms).  Ranks <= 64.
- * Non-finite data give NaN.  Synchronizes. */
+ * untouched) then ||X_1||_F (§2.3; accurate for small norms).  Ranks <=
+ * TTR_MAX_RANK_LARGE (TTR_NORM_SYM: <= TTR_MAX_RANK, TTR_ERR_UNSUPPORTED
+ * above).  Non-finite data give NaN.  Synchronizes. */
 int ttr_norm(ttr_handle *h, const ttr_tt *X, int method, double *out);
 
 /* In-place orthonormalization (§2.3 Alg. 1; explicit factors as in §3.4 Alg. 5).
  * TTR_RIGHT: H(X_n) row-orthonormal for n >= 2 and core 1 carries the norm;
  * TTR_LEFT: V(X_n) column-orthonormal for n <= N-1 and core N carries the norm.
  * The factorizations reveal numerical rank: a link whose unfolding is
- * numerically rank-deficient (e.g. Y + Y) gets the smaller rank, and X->R is
- * updated; the tensor is preserved to rounding error.  `prec` is TTR_FP64.
- * Synchronizes. */
+ * numerically rank-deficient (e.g. Y + Y) gets its numerical rank (the
+ * number of singular values above rounding level of the unfolding being
+ * factored), where a Householder QR would keep the formal rank with
+ * rounding-level diagonal entries; X->R is updated and the tensor is
+ * preserved to rounding error.  Ranks <= TTR_MAX_RANK_LARGE.  `prec` is
+ * TTR_FP64.  Synchronizes. */
 int ttr_orthogonalize(ttr_handle *h, ttr_tt *X, int side, int prec);
 
 /* Y = rounding of X to relative accuracy tol (§2.4 Alg. 2): ||X - Y|| <= tol ||X||.
@@ -169,10 +179,11 @@ int ttr_orthogonalize(ttr_handle *h, ttr_tt *X, int side, int prec);
  * with the smallest rank whose Frobenius tail of singular values is <= delta;
  * output cores 1..N-1 are left-orthonormal.  TTR_LRL: the mirror image.
  * X is read only; Y's cores need cap[n] >= R[n]*I[n]*R[n+1] of X (always
- * enough, ranks never grow).  Ranks up to TTR_MAX_RANK_LARGE; above
- * TTR_MAX_RANK only TTR_RLR (TTR_ERR_UNSUPPORTED otherwise).  Y->R receives the new ranks; *norm_out (host,
- * nullable) receives the ||X|| used for delta.  tol = 0 keeps every direction
- * above rounding level; N = 1 copies.  `prec`: TTR_FP64 or TTR_MIXED.
+ * enough, ranks never grow).  Ranks up to TTR_MAX_RANK_LARGE, every direction.
+ * Y->R receives the new ranks; *norm_out (host, nullable) receives the ||X||
+ * used for delta.  tol = 0 keeps every direction above rounding level, so a
+ * numerically rank-deficient input (Y + Y) gets its numerical ranks, as in
+ * ttr_orthogonalize; N = 1 copies.  `prec`: TTR_FP64 or TTR_MIXED.
  * Synchronizes. */
 int ttr_round(ttr_handle *h, const ttr_tt *X, double tol, int direction, int prec,
               ttr_tt *Y, double *norm_out);

@@ -1,28 +1,33 @@
 // TT rounding for ranks above the register/LDS-tiled range (64 < R <= 256):
-// the same algorithm as the single-tensor path (§2.4 Alg. 2, RLR; QR-by-Gram
-// for the tall-skinny QRs of §3.3-§3.5), with every streaming product written
-// as a plain GEMM on a contiguous unfolding and every small
-// factorization done by one workgroup on matrices held in device memory.
+// the same algorithm as the single-tensor path (§2.4 Alg. 2, both sweep
+// orders; QR-by-Gram for the tall-skinny QRs of §3.3-§3.5), with every
+// streaming product a matrix-core GEMM on an unfolding (ttr_lstream.hip) and
+// every small factorization done by one workgroup on matrices held in device
+// memory.  Also the inner product, the orthonormalization norm, explicit
+// orthonormalization and the rounding of an implicit Hadamard product at
+// these ranks.
 //
 // Unfoldings of a core M (a x I x b, entry (i1, i, i2) at i1 + a*(i + I*i2)):
 //   V(M) = (a*I) x b, H(M) = a x (I*b), both column-major views of the buffer.
-// Products used:
-//   C = M x_3 T^T        V(C) = V(M) T              (dgemm)
-//   D = F^T x_1 C        H(D) = F^T H(C)            (dgemm)
-//   LEFT Gram            H(Z) H(Z)^T                (chunked dgemm + reduction)
-//   RIGHT Gram           V(Z)^T V(Z)                (chunked dgemm + reduction)
-// Every refinement stage is applied to a materialized core, and the
-// truncation sweep rebuilds the orthonormalization sweep's intermediates with
-// the same calls, so each stage is applied to bitwise the data its Gram was
-// measured on.
+// Products used (lg_gemm, B packed into fragment order once per call):
+//   C = M x_3 T^T        V(C) = V(M) T
+//   D = F^T x_1 C        H(D)^T = H(C)^T F
+//   LEFT Gram            H(Z) H(Z)^T    (lg_gram over the row-major H(Z)^T)
+//   RIGHT Gram           V(Z)^T V(Z)    (lg_gram over the column-major V(Z))
+// Gram passes keep per-workgroup partial matrices summed in a fixed order.
+// LRL rounding and left orthonormalization run the same code on the reversed
+// train of transposed slices (LView).  Every refinement stage is applied to a
+// materialized core, and the truncation sweep rebuilds the orthonormalization
+// sweep's intermediates with the same calls, so each stage is applied to
+// bitwise the data its Gram was measured on.
 //
 // Small factorizations (d <= 256): Cholesky with Gershgorin / norm bounds,
-// shifted Cholesky (first pass) and rank-revealing pivoted Cholesky
-// (refinement passes) run in one 1024-thread workgroup over device-memory
-// scratch (L2-resident), Cholesky and triangular inverse blocked in 16-column
-// panels; the products with the triangular factor (R = L^T Rc) are dgemm
-// calls.  The truncation SVD is a block one-sided Jacobi over many
-// workgroups, one launch per round.
+// shifted Cholesky and rank-revealing pivoted Cholesky run in one 1024-thread
+// workgroup over device-memory scratch (L2-resident), Cholesky and triangular
+// inverse blocked in 16-column panels; the products with the triangular
+// factor (R = L^T Rc) are small matrix-core products (lg_sgemm).  The
+// truncation SVD is a block one-sided Jacobi over many workgroups, one launch
+// per round, converged when a sweep rotates nothing (checked on the device).
 #include "ttr_host.h"
 
 #include <algorithm>
