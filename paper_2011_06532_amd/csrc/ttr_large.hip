@@ -1027,12 +1027,15 @@ struct LView {
 struct LargeCtx {
   double *mem = nullptr;
   size_t bytes = 0;
+  double *keep = nullptr;  // the orthonormalization sweep's products kept for the truncation sweep
+  size_t keep_bytes = 0;
 };
 
 void ttr_large_release(ttr_handle *h) {
   if (!h || !h->large) return;
   LargeCtx *c = h->large;
   if (c->mem) ttr_dev_free(h, c->mem);
+  if (c->keep) ttr_dev_free(h, c->keep);
   delete c;
   h->large = nullptr;
 }
@@ -1055,6 +1058,36 @@ struct Large {
   // never formed (right products through launch_lg_kron_right)
   const ttr_tt *KA = nullptr, *KB = nullptr;
   double *xlast = nullptr;  // the formed last core of A * B
+
+  // Room for the products C_n = M_n T_{n+1}, n = 1..N-2, of the
+  // orthonormalization sweep, so that the truncation sweep reads them instead
+  // of forming them again (one GEMM per link fewer).  Held by the handle like
+  // the workspace; when the allocation fails they are formed again.
+  std::vector<double *> keepC;
+  void setup_keep(int N, size_t mc) {
+    keepC.assign(N, nullptr);
+    if (N < 3) return;
+    mc = (mc + 63) & ~(size_t)63;
+    const size_t need = (size_t)(N - 2) * mc * sizeof(double);
+    LargeCtx *ctx = h->large;
+    if (ctx->keep_bytes < need) {
+      if (ctx->keep) {
+        if (hipStreamSynchronize(h->stream) != hipSuccess) return;
+        ttr_dev_free(h, ctx->keep);
+        ctx->keep = nullptr;
+        ctx->keep_bytes = 0;
+      }
+      void *m = nullptr;
+      if (ttr_dev_alloc(h, &m, need) != TTR_OK) {
+        (void)hipGetLastError();  // an out-of-memory result is not an error here
+        return;
+      }
+      ctx->keep = static_cast<double *>(m);
+      ctx->keep_bytes = need;
+    }
+    for (int n = 1; n <= N - 2; ++n) keepC[n] = ctx->keep + (size_t)(n - 1) * mc;
+  }
+  double *keep_slot(int n) const { return (n < (int)keepC.size()) ? keepC[n] : nullptr; }
 
   int setup(int N, size_t mc, size_t extra = 0) {
     mc = (mc + 63) & ~(size_t)63;
@@ -1145,14 +1178,15 @@ struct Large {
     return right(v, Tm, 1, ldt, k, tri, out);
   }
   // Z'(i) = A M'(i) (A(r, c) = A[r asr + c asc], m x ea) into `out`.
-  LView left(const LView &v, const double *Am, long long asr, long long asc, int m, double *out) {
+  // tri = 2: A^T is upper triangular (a Cholesky-route stage factor F, A = F^T).
+  LView left(const LView &v, const double *Am, long long asr, long long asc, int m, double *out, int tri = 0) {
     if (!v.trans) {
       // H(Z)^T = H(M)^T A^T
-      launch_lg_gemm(h->stream, v.X, v.I * v.pb, v.pa, v.pa, 0, Am, asc, asr, m, 0, Bp, out, m, 0);
+      launch_lg_gemm(h->stream, v.X, v.I * v.pb, v.pa, v.pa, 0, Am, asc, asr, m, tri, Bp, out, m, 0);
       return LView{out, v.I, m, v.pb, 0};
     }
     // Z(i) = M(i) A^T: V(Z) = V(M) A^T
-    launch_lg_gemm(h->stream, v.X, (long long)v.pa * v.I, v.pb, (long long)v.pa * v.I, 1, Am, asc, asr, m, 0, Bp, out,
+    launch_lg_gemm(h->stream, v.X, (long long)v.pa * v.I, v.pb, (long long)v.pa * v.I, 1, Am, asc, asr, m, tri, Bp, out,
                    (long long)v.pa * v.I, 1);
     return LView{out, v.I, v.pa, m, 1};
   }
@@ -1266,7 +1300,8 @@ struct Large {
 struct LFac {
   int nst = 1;
   int dim[4] = {0, 0, 0, 0};
-  int tri = 0;  // T_n = R^T is lower triangular (no pivoted pass)
+  int tri = 0;                // T_n = R^T is lower triangular (no pivoted pass)
+  int stri[4] = {0, 0, 0, 0};  // lg_gemm tri flag of stage j's F (2: upper triangular)
 };
 
 // Orthonormalization sweep over logical cores N-1..1 (§2.3 Alg. 1 order)
@@ -1277,7 +1312,7 @@ struct LFac {
 // F_nst^T .. F_1^T C_n is written to out->core (in the view's orientation,
 // §3.4 Alg. 5).
 int orth_sweep_large(Large &L, const ttr_tt *X, int rev, int prec, std::vector<int> &k, std::vector<LFac> &fac,
-                     ttr_tt *out) {
+                     ttr_tt *out, std::vector<LView> *kept = nullptr) {
   ttr_handle *h = L.h;
   const int N = X->N;
   auto phys = [&](int n) { return rev ? N - 1 - n : n; };
@@ -1293,7 +1328,11 @@ int orth_sweep_large(Large &L, const ttr_tt *X, int rev, int prec, std::vector<i
     const LView v = view(n);
     const int a = v.ea(), b = v.eb();
     LView cur = v;
-    if (n < N - 1) cur = L.right_core(n, N, v, L.T[n + 1], b, k[n + 1], fac[n + 1].tri, L.tC);
+    if (n < N - 1) {
+      double *dst = (kept && L.keep_slot(n)) ? L.keep_slot(n) : L.tC;
+      cur = L.right_core(n, N, v, L.T[n + 1], b, k[n + 1], fac[n + 1].tri, dst);
+      if (kept && dst != L.tC) (*kept)[n] = cur;
+    }
     double *bufs[2] = {L.tA, L.tB};
     double *R[2] = {L.Ra, L.Rb};
     fac[n].dim[0] = a;
@@ -1302,15 +1341,18 @@ int orth_sweep_large(Large &L, const ttr_tt *X, int rev, int prec, std::vector<i
       double gerr;
       const int f32 = (prec == TTR_MIXED && pass == 1);
       if ((rc = L.gram(cur, true, f32, L.G, &gerr))) return rc;
+      int pv = 0;
       if ((rc = L.step(pass == 1 ? nullptr : R[pass & 1], cur.ea(), a, pass, L.B[n][pass - 1], R[(pass - 1) & 1],
-                       L.T[n], gerr, 0, 0, 0.0, f32, &pivoted)))
+                       L.T[n], gerr, 0, 0, 0.0, f32, &pv)))
         return rc;
+      pivoted |= pv;
+      fac[n].stri[pass - 1] = pv ? 0 : 2;
       const int kk = h->dec_host[0];
       fac[n].dim[pass] = kk;
       if (h->dec_host[1]) break;
       if (pass >= 3) return ttr_fail(TTR_ERR_NUMERICAL, "QR-by-Gram did not settle in three passes");
       // D = F_pass^T C (materialized; the next pass measures its Gram)
-      cur = L.left(cur, L.B[n][pass - 1], cur.ea(), 1, kk, bufs[(pass - 1) & 1]);
+      cur = L.left(cur, L.B[n][pass - 1], cur.ea(), 1, kk, bufs[(pass - 1) & 1], fac[n].stri[pass - 1]);
     }
     fac[n].nst = pass;
     fac[n].tri = !pivoted;
@@ -1318,7 +1360,7 @@ int orth_sweep_large(Large &L, const ttr_tt *X, int rev, int prec, std::vector<i
     if (out) {
       // the orthonormal core: the last stage applied to what its Gram measured
       const int p = phys(n);
-      L.left(cur, L.B[n][pass - 1], cur.ea(), 1, k[n], L.tB == cur.X ? L.tA : L.tB);
+      L.left(cur, L.B[n][pass - 1], cur.ea(), 1, k[n], L.tB == cur.X ? L.tA : L.tB, fac[n].stri[pass - 1]);
       const double *src = (L.tB == cur.X) ? L.tA : L.tB;
       TTR_HIPCHK(hipMemcpyAsync(out->core[p], src, (size_t)k[n] * v.I * k[n + 1] * sizeof(double),
                                 hipMemcpyDeviceToDevice, h->stream));
@@ -1384,6 +1426,7 @@ int round_large_with(Large &L, ttr_handle *h, const ttr_tt *X, double tol, int d
   };
   std::vector<int> k;
   std::vector<LFac> fac;
+  std::vector<LView> kept;  // C_n of sweep 1 kept for sweep 2 (X == nullptr: form it again)
   const bool ex = explicit_factors != 0;
   if (ex) {
     // ---- sweep 1, explicit: Y <- X, orthonormal cores written into Y ----
@@ -1402,7 +1445,9 @@ int round_large_with(Large &L, ttr_handle *h, const ttr_tt *X, double tol, int d
     for (int l = 0; l <= N; ++l) Y->R[rev ? N - l : l] = k[l];
   } else {
     // ---- sweep 1: orthonormalization with implicit factors ----
-    if ((rc = orth_sweep_large(L, X, rev, prec, k, fac, nullptr))) return rc;
+    if (!L.KA) L.setup_keep(N, max_core_of(X));
+    kept.assign(N, LView{nullptr, 0, 0, 0, 0});
+    if ((rc = orth_sweep_large(L, X, rev, prec, k, fac, nullptr, &kept))) return rc;
   }
   auto yview = [&](int n) {
     const int p = phys(n);
@@ -1435,12 +1480,13 @@ int round_large_with(Large &L, ttr_handle *h, const ttr_tt *X, double tol, int d
       // C_n = M_n T_{n+1}, then the left stages F_1^T .. F_{nst-1}^T and P
       // (the same calls as sweep 1, so each stage meets bitwise the data its
       // Gram was measured on)
-      cur = L.right_core(n, N, v, L.T[n + 1], v.eb(), k[n + 1], fac[n + 1].tri, L.tC);
+      if (n < (int)kept.size() && kept[n].X) cur = kept[n];
+      else cur = L.right_core(n, N, v, L.T[n + 1], v.eb(), k[n + 1], fac[n + 1].tri, L.tC);
       cc = k[n + 1];
       double *bufs[2] = {L.tA, L.tB};
       if (n >= 1) {
         for (int j = 1; j < fac[n].nst; ++j)
-          cur = L.left(cur, L.B[n][j - 1], cur.ea(), 1, fac[n].dim[j], bufs[(j - 1) & 1]);
+          cur = L.left(cur, L.B[n][j - 1], cur.ea(), 1, fac[n].dim[j], bufs[(j - 1) & 1], fac[n].stri[j - 1]);
         double *o = (cur.X == L.tC) ? L.tA : ((cur.X == L.tA) ? L.tB : L.tA);
         cur = L.left(cur, Pcur, 1, Lprev, Lprev, o);
       }
@@ -1455,8 +1501,9 @@ int round_large_with(Large &L, ttr_handle *h, const ttr_tt *X, double tol, int d
       double gerr;
       const int f32 = (prec == TTR_MIXED && g == 1);
       if ((rc = L.gram(E, false, f32, L.G, &gerr))) return rc;
+      int pv = 0;
       if ((rc = L.step(g == 1 ? nullptr : R[g & 1], gd[g - 1], cc, g, L.Gst[g - 1], R[(g - 1) & 1], nullptr, gerr, 1,
-                       n == 0, tol * tol / (double)(N - 1), f32, nullptr)))
+                       n == 0, tol * tol / (double)(N - 1), f32, &pv)))
         return rc;
       gd[g] = h->dec_host[0];
       if (g == 1) notrunc = h->dec_host[5];
@@ -1464,7 +1511,7 @@ int round_large_with(Large &L, ttr_handle *h, const ttr_tt *X, double tol, int d
       if (g >= 3) return ttr_fail(TTR_ERR_NUMERICAL, "QR-by-Gram did not settle in three passes");
       double *o = (E.X == L.tA) ? L.tB : L.tA;
       if (E.X == L.tC) o = L.tA;
-      E = L.right(E, L.Gst[g - 1], 1, gd[g - 1], gd[g], 0, o);
+      E = L.right(E, L.Gst[g - 1], 1, gd[g - 1], gd[g], pv ? 0 : 2, o);
     }
     // truncation: SVD of R (k x cc) unless no singular value can fall below delta
     const int kq = gd[g], dq = gd[g - 1];
@@ -1542,7 +1589,7 @@ int round_large_with(Large &L, ttr_handle *h, const ttr_tt *X, double tol, int d
     LView cur = view(n);
     double *bufs[2] = {L.tA, L.tB};
     for (int j = 1; j < fac[n].nst; ++j)
-      cur = L.left(cur, L.B[n][j - 1], cur.ea(), 1, fac[n].dim[j], bufs[(j - 1) & 1]);
+      cur = L.left(cur, L.B[n][j - 1], cur.ea(), 1, fac[n].dim[j], bufs[(j - 1) & 1], fac[n].stri[j - 1]);
     L.left(cur, Pcur, 1, Lprev, Lprev, Y->core[phys(n)]);
     ++L.applies;
   }

@@ -81,8 +81,9 @@ __device__ inline d2 load2(const double *__restrict__ p, int n) {
 // row), double buffered, the next chunk's loads in flight during the current
 // products; B's fragments come from the packed copy (L2), one k-step ahead.
 // VEC: X is 16-byte aligned with an even leading dimension.
-// tri: B is lower triangular (B(k, c) = 0 for k < c), its zero k-steps are
-// skipped.
+// tri: 1 = B is lower triangular (B(k, c) = 0 for k < c), 2 = upper
+// triangular (B(k, c) = 0 for k > c); its zero k-steps are skipped (adding
+// the zero products changes no bit of a finite result).
 // ---------------------------------------------------------------------------
 constexpr int kGT = 1024;      // threads
 constexpr int kGM = 128;       // rows per workgroup
@@ -176,7 +177,8 @@ __global__ __launch_bounds__(kGT) void lg_gemm(const double *__restrict__ X, lon
         for (int ct = 0; ct < 2; ++ct) {
           const int t = cb * 2 + ct;
           if (t >= NT) continue;
-          if (tri && 4 * ks + 3 < 16 * t) continue;  // B(k, c) = 0 for k < c
+          if (tri == 1 && 4 * ks + 3 < 16 * t) continue;   // B(k, c) = 0 for k < c
+          if (tri == 2 && 4 * ks > 16 * t + 15) continue;  // B(k, c) = 0 for k > c
 #pragma unroll
           for (int rt = 0; rt < 4; ++rt)
             acc[rt][ct] = ZCOL ? mma(bcur[ct], af[rt], acc[rt][ct]) : mma(af[rt], bcur[ct], acc[rt][ct]);
