@@ -96,11 +96,14 @@ int launch_dot_mfma(hipStream_t s, const double *X, int a, int b, const double *
 // --- rank 65..256 streaming kernels (ttr_lstream.hip) ----------------------
 // Z (M x N) = X (M x K) B (K x N), K, N <= 256.  X: column-major (xcol, element
 // (r, k) at X[r + ldx k]) or row-major (X[r ldx + k]); Z likewise (zcol, ldz).
-// B(k, c) = B[k bsr + c bsc]; tri: B lower triangular.  Bp: scratch of
-// lg_packed_doubles(K, N) doubles for B in fragment order.
+// B(k, c) = B[k bsr + c bsc]; tri: 1 = B lower triangular, 2 = upper.  Bp:
+// scratch of lg_packed_doubles(K, N) doubles for B in fragment order.  perm
+// (device, K ints, nullable; xcol only): Z = X(:, perm) B(perm, :)-rows, i.e.
+// column k of the operand is X(:, perm[k]) and row k of B is B(perm[k], :).
 size_t lg_packed_doubles(int K, int N);
 void launch_lg_gemm(hipStream_t s, const double *X, long long M, int K, long long ldx, int xcol, const double *B,
-                    long long bsr, long long bsc, int N, int tri, double *Bp, double *Z, long long ldz, int zcol);
+                    long long bsr, long long bsc, int N, int tri, double *Bp, double *Z, long long ldz, int zcol,
+                    const int *perm = nullptr);
 struct LGramGrid {
   int nwg;
   long long rpw;  // rows per workgroup (multiple of 16)

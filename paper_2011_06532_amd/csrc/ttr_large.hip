@@ -1155,7 +1155,16 @@ struct Large {
   }
   // Z'(i) = M'(i) B (B(k, c) = B[k bsr + c bsc], eb x n) into `out`, in the
   // view's orientation; tri: B lower triangular.
-  LView right(const LView &v, const double *Bm, long long bsr, long long bsc, int n, int tri, double *out) {
+  // perm (nullable, column-major views only): the product V(M)(:, perm) B(perm, :)
+  // over the first n entries of perm (a pivoted factor F = P U: the gathered
+  // columns times its upper-triangular rows).
+  LView right(const LView &v, const double *Bm, long long bsr, long long bsc, int n, int tri, double *out,
+              const int *perm = nullptr) {
+    if (perm && !v.trans) {
+      launch_lg_gemm(h->stream, v.X, (long long)v.pa * v.I, n, (long long)v.pa * v.I, 1, Bm, bsr, bsc, n, tri, Bp,
+                     out, (long long)v.pa * v.I, 1, perm);
+      return LView{out, v.I, v.pa, n, 0};
+    }
     if (!v.trans) {
       // V(Z) = V(M) B
       launch_lg_gemm(h->stream, v.X, (long long)v.pa * v.I, v.pb, (long long)v.pa * v.I, 1, Bm, bsr, bsc, n, tri, Bp,
@@ -1254,7 +1263,7 @@ struct Large {
   // step took the pivoted route (its factor is not triangular).
   int mixed = 0;  // TTR_MIXED: FP32 first passes
   int step(const double *Rc, int d, int b, int pass, double *F, double *Rn, double *Tdst, double gerr, int check,
-           int first, double tol2_nm1, int f32, int *pivoted) {
+           int first, double tol2_nm1, int f32, int *pivoted, int *permuted = nullptr) {
     LStepArgs a;
     a.G = G;
     a.d = d;
@@ -1285,6 +1294,7 @@ struct Large {
     if ((rc = sync_dec())) return rc;
     const int how = h->dec_host[8], kk = h->dec_host[0];
     if (pivoted && (how == 2 || kk < d)) *pivoted = 1;
+    if (permuted) *permuted = (how == 2);  // F = P U with P in `perm`, U upper triangular
     if (how == 0) return TTR_OK;
     // R = L^T Rc (d x b) or R' = L(:, 0:k)^T Rp (k x b), L lower in W0 (ld d)
     sgemm(true, false, kk, b, d, W0, d, how == 1 ? Rc : Ap, d, Rn, kk);
@@ -1501,9 +1511,9 @@ int round_large_with(Large &L, ttr_handle *h, const ttr_tt *X, double tol, int d
       double gerr;
       const int f32 = (prec == TTR_MIXED && g == 1);
       if ((rc = L.gram(E, false, f32, L.G, &gerr))) return rc;
-      int pv = 0;
+      int pv = 0, pm = 0;
       if ((rc = L.step(g == 1 ? nullptr : R[g & 1], gd[g - 1], cc, g, L.Gst[g - 1], R[(g - 1) & 1], nullptr, gerr, 1,
-                       n == 0, tol * tol / (double)(N - 1), f32, &pv)))
+                       n == 0, tol * tol / (double)(N - 1), f32, &pv, &pm)))
         return rc;
       gd[g] = h->dec_host[0];
       if (g == 1) notrunc = h->dec_host[5];
@@ -1511,7 +1521,10 @@ int round_large_with(Large &L, ttr_handle *h, const ttr_tt *X, double tol, int d
       if (g >= 3) return ttr_fail(TTR_ERR_NUMERICAL, "QR-by-Gram did not settle in three passes");
       double *o = (E.X == L.tA) ? L.tB : L.tA;
       if (E.X == L.tC) o = L.tA;
-      E = L.right(E, L.Gst[g - 1], 1, gd[g - 1], gd[g], pv ? 0 : 2, o);
+      // a Cholesky-route factor is upper triangular; a pivoted one is P U:
+      // gathered columns of E times U (the step's permutation is still in perm)
+      if (pm && !E.trans) E = L.right(E, L.Gst[g - 1], 1, gd[g - 1], gd[g], 2, o, L.perm);
+      else E = L.right(E, L.Gst[g - 1], 1, gd[g - 1], gd[g], pv ? 0 : 2, o);
     }
     // truncation: SVD of R (k x cc) unless no singular value can fall below delta
     const int kq = gd[g], dq = gd[g - 1];

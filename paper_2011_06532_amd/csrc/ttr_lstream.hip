@@ -42,10 +42,11 @@ __device__ inline f4 mma(float a, float b, f4 c) { return __builtin_amdgcn_mfma_
 // ---------------------------------------------------------------------------
 // B packed into fragment order: k-step s (rows 4s..4s+3), column tile t
 // (columns 16t..16t+15): Bp[(s * NT + t) * 64 + l] = B(4s + l/16, 16t + l%16),
-// zero outside K x N.  B(k, c) = B[k * sr + c * sc].
+// zero outside K x N.  B(k, c) = B[k' * sr + c * sc], k' = rperm[k] when a
+// row permutation is given, else k.
 // ---------------------------------------------------------------------------
 __global__ void lg_pack_b(const double *__restrict__ B, int K, int N, long long sr, long long sc,
-                          double *__restrict__ Bp) {
+                          const int *__restrict__ rperm, double *__restrict__ Bp) {
   const int KS = (K + 3) / 4, NT = (N + 15) / 16;
   const long long total = (long long)KS * NT * 64;
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
@@ -54,7 +55,7 @@ __global__ void lg_pack_b(const double *__restrict__ B, int K, int N, long long 
     const long long st = e >> 6;
     const int t = (int)(st % NT), s = (int)(st / NT);
     const int k = 4 * s + l / 16, c = 16 * t + l % 16;
-    Bp[e] = (k < K && c < N) ? B[k * sr + c * sc] : 0.0;
+    Bp[e] = (k < K && c < N) ? B[(rperm ? rperm[k] : k) * sr + c * sc] : 0.0;
   }
 }
 
@@ -81,6 +82,8 @@ __device__ inline d2 load2(const double *__restrict__ p, int n) {
 // row), double buffered, the next chunk's loads in flight during the current
 // products; B's fragments come from the packed copy (L2), one k-step ahead.
 // VEC: X is 16-byte aligned with an even leading dimension.
+// kperm (XCOL only, nullable): column k of the operand is column kperm[k] of
+// X (a gathered operand: X(:, kperm) B).
 // tri: 1 = B is lower triangular (B(k, c) = 0 for k < c), 2 = upper
 // triangular (B(k, c) = 0 for k > c); its zero k-steps are skipped (adding
 // the zero products changes no bit of a finite result).
@@ -89,12 +92,15 @@ constexpr int kGT = 1024;      // threads
 constexpr int kGM = 128;       // rows per workgroup
 constexpr int kGC = 16;        // k per chunk
 constexpr int kGP = kGM + 2;   // LDS pitch (doubles) of a k row
+constexpr int kLMaxG = 256;    // largest K
 
 template <bool XCOL, bool ZCOL, bool VEC>
 __global__ __launch_bounds__(kGT) void lg_gemm(const double *__restrict__ X, long long M, int K, long long ldx,
                                                const double *__restrict__ Bp, int N, int tri,
-                                               double *__restrict__ Z, long long ldz) {
+                                               double *__restrict__ Z, long long ldz,
+                                               const int *__restrict__ kperm) {
   __shared__ double Xs[2][kGC][kGP];
+  __shared__ int kp[kLMaxG + kGC];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int rh = w >> 3, cbi = w & 7, cb = rh ? 7 - cbi : cbi;
   const int NT = (N + 15) / 16;
@@ -119,6 +125,10 @@ __global__ __launch_bounds__(kGT) void lg_gemm(const double *__restrict__ X, lon
     }
   }
   const long long rows_left = M - row0;
+  if (XCOL && kperm) {
+    for (int e = tid; e < kLMaxG + kGC; e += kGT) kp[e] = (e < K) ? kperm[e] : 0;
+    __syncthreads();
+  }
   d2 pre[NJ];
   auto load = [&](int c) {
     const int k0 = c * kGC;
@@ -127,7 +137,7 @@ __global__ __launch_bounds__(kGT) void lg_gemm(const double *__restrict__ X, lon
     for (int j = 0; j < NJ; ++j) {
       const long long gr = row0 + sr[j];
       const int gk = k0 + sk[j];
-      const double *p = XCOL ? X + gr + ldx * gk : X + gr * ldx + gk;
+      const double *p = XCOL ? X + gr + ldx * (kperm ? kp[gk] : gk) : X + gr * ldx + gk;
       int n;
       if (full) n = 2;
       else if (XCOL) n = (gk < K) ? (int)std::max(0LL, std::min(2LL, M - gr)) : 0;
@@ -505,14 +515,16 @@ void launch_lg_kron_right(hipStream_t s, const double *A, int a0, int a1, const 
 size_t lg_packed_doubles(int K, int N) { return (size_t)((K + 3) / 4) * ((N + 15) / 16) * 64; }
 
 void launch_lg_gemm(hipStream_t s, const double *X, long long M, int K, long long ldx, int xcol, const double *B,
-                    long long bsr, long long bsc, int N, int tri, double *Bp, double *Z, long long ldz, int zcol) {
+                    long long bsr, long long bsc, int N, int tri, double *Bp, double *Z, long long ldz, int zcol,
+                    const int *perm) {
   const long long np = (long long)lg_packed_doubles(K, N);
   hipLaunchKernelGGL(lg_pack_b, dim3((unsigned)std::min<long long>(1024, (np + 255) / 256)), dim3(256), 0, s, B, K,
-                     N, bsr, bsc, Bp);
+                     N, bsr, bsc, perm, Bp);
+  if (!xcol) perm = nullptr;  // the gathered form is column-major only (callers check)
   const dim3 grid((unsigned)((M + kGM - 1) / kGM));
   const bool vec = ((uintptr_t)X % 16 == 0) && (ldx % 2 == 0);
 #define TTR_GEMM(XC, ZC, V) \
-  hipLaunchKernelGGL((lg_gemm<XC, ZC, V>), grid, dim3(kGT), 0, s, X, M, K, ldx, Bp, N, tri, Z, ldz)
+  hipLaunchKernelGGL((lg_gemm<XC, ZC, V>), grid, dim3(kGT), 0, s, X, M, K, ldx, Bp, N, tri, Z, ldz, perm)
   if (vec) {
     if (xcol && zcol) TTR_GEMM(true, true, true);
     else if (xcol) TTR_GEMM(true, false, true);
