@@ -204,6 +204,18 @@ def test_orthogonalize_rank_deficient(ttr, h):
     Y = g.to_numpy()
     assert O.ranks(Y) == [1, 4, 6, 3, 1]
     assert O.diff_norm(Y, X) <= 1e-13 * O.norm_ortho(X) * 4
+    # against the oracle's orthonormalization (Householder, formal ranks 8, 12,
+    # 6 with rounding-level directions): the same tensor, and the GPU's ranks
+    # are the numerical ranks of the tensor's unfoldings (the TT ranks, §2.1)
+    ref = O.orthogonalize(X, "right")
+    assert O.ranks(ref) == [1, 8, 12, 6, 1]
+    assert O.diff_norm(Y, ref) <= 1e-12 * O.norm_ortho(ref)
+    full = O.full(X)
+    num = [1]
+    for n in range(1, 4):
+        s = np.linalg.svd(full.reshape(int(np.prod(full.shape[:n])), -1), compute_uv=False)
+        num.append(int(np.sum(s > 1e-12 * s[0])))
+    assert O.ranks(Y) == num + [1]
     for n in range(1, 4):
         Hn = O.H(Y[n])
         assert np.linalg.norm(Hn @ Hn.T - np.eye(Hn.shape[0])) < 1e-12

@@ -209,3 +209,24 @@ def test_round_explicit_factors(ttr, h, direction, prec):
     assert math.isclose(nrm, info["norm"], rel_tol=1e-12 if prec == "fp64" else 1e-6)
     # output orthonormality as for the implicit variant
     assert orthonormality(got, direction) < (1e-12 if prec == "fp64" else 1e-6)
+
+
+@pytest.mark.parametrize("direction", ["RLR", "LRL"])
+@pytest.mark.parametrize("rank", [5, 80])
+def test_round_tol0_rank_deficient_against_oracle(ttr, h, direction, rank):
+    # tol = 0 on Y + Y (every unfolding exactly rank deficient): the oracle's
+    # Householder QR keeps the formal ranks with rounding-level singular
+    # values, the GPU keeps the numerical ranks.  Both must give the same
+    # tensor (2Y), and the GPU's ranks must be the oracle's count of singular
+    # values above rounding level (1e-12 sigma_1) at each link.
+    print(f"round tol=0 Y+Y rank {rank} {direction}", flush=True)
+    rng = np.random.default_rng(211 + rank)
+    I = [30, 40, 35, 25] if rank == 5 else [12, 10, 9, 11]
+    Yc = rand_tt(rng, I, [rank] * 3)
+    X = O.add(1.0, Yc, 1.0, Yc)
+    Yg = h.round(ttr.TT.from_numpy(X), 0.0, direction).to_numpy()
+    ref, info = O.round_tt(X, 0.0, direction, return_info=True)
+    num = [1] + [int(np.sum(np.asarray(s) > 1e-12 * s[0])) for s in info["sigmas"]] + [1]
+    assert O.ranks(ref) != num  # the oracle keeps rounding-level directions
+    assert O.ranks(Yg) == num, (O.ranks(Yg), num, O.ranks(ref))
+    assert O.diff_norm(Yg, ref) <= 1e-12 * O.norm_ortho(ref)
