@@ -97,6 +97,7 @@ int ensure_ws(ttr_handle *h, size_t bytes) {
 // Workspace carve-up (in doubles).  Every small matrix slot holds RMAX^2.
 constexpr size_t kSlot = (size_t)TTR_RMAX * TTR_RMAX;
 constexpr int kStagesPerCore = 3;
+constexpr int kScalF32 = 16;  // w.scal[16..18]: the scales of an FP32 Gram pass
 struct WS {
   double *partials, *G, *Ra, *Rb, *Gst[3], *Pa, *Pb, *GU, *Wa, *Wb, *scal, *sigma, *tails, *Tn, *Bst, *tmp, *matA, *matB;
   int *dec;
@@ -227,7 +228,7 @@ Stage st_transpose(const Stage &a) {
 // kernel.
 // Returns the number of workgroups (partial Grams) the pass used.
 int gram(ttr_handle *h, double *partials, double *G, const CoreView &cv, const Stages &st, int mode, int f32 = 0,
-         bool *ran_f32 = nullptr, double *ystore = nullptr, bool *stored = nullptr) {
+         bool *ran_f32 = nullptr, double *ystore = nullptr, bool *stored = nullptr, double *fscale = nullptr) {
   int zr, zc;
   const double cf = chain_flops(cv, st, &zr, &zc);
   const double gf = (mode == GRAM_LEFT) ? (double)zr * (zr + 1) * zc : (double)zc * (zc + 1) * zr;
@@ -251,7 +252,8 @@ int gram(ttr_handle *h, double *partials, double *G, const CoreView &cv, const S
       if (q) qq = tr ? st_transpose(*q) : *q;
       ProfScope ps(h, f32 ? P_GRAM_R32 : P_GRAM_R, bytes, flops);
       nwg = launch_gram_right_factor(h->stream, X, cv.pa, cv.pb, cv.I, q ? qq.S : nullptr, q ? qq.cols : cv.pb,
-                                     q ? qq.sr : 1, q ? qq.sc : cv.pb, (q && qq.lower == 1) ? 1 : 0, f32, partials);
+                                     q ? qq.sr : 1, q ? qq.sc : cv.pb, (q && qq.lower == 1) ? 1 : 0, f32, partials,
+                                     fscale);
       done = true;
       if (ran_f32) *ran_f32 = f32 != 0;
     } else if (pmode == GRAM_RIGHT && pnl <= 1 && pnr == 0) {
@@ -265,7 +267,7 @@ int gram(ttr_handle *h, double *partials, double *G, const CoreView &cv, const S
       ProfScope ps(h, f32 ? P_GRAM_L32 : P_GRAM_L, bytes + yb, flops);
       nwg = launch_gram_left_factor(h->stream, X, cv.pa, cv.pb, cv.I, pp ? ps_.S : nullptr, pp ? ps_.rows : cv.pa,
                                     pp ? ps_.sr : 1, pp ? ps_.sc : cv.pa, (pp && ps_.lower == 2) ? 1 : 0, f32,
-                                    partials, ys);
+                                    partials, ys, fscale);
       done = true;
       if (ran_f32) *ran_f32 = f32 != 0;
       if (stored) *stored = ys != nullptr;
@@ -490,7 +492,7 @@ int qr_by_gram(ttr_handle *h, WS &w, const CoreView &cv, int mode, const Stages 
     if (post) {
       Stages s1 = base;
       s1.nr = 0;
-      gnwg = gram(h, w.partials, w.G, cvp, s1, mode, pr.mixed, &f32, ystore, &ys);
+      gnwg = gram(h, w.partials, w.G, cvp, s1, mode, pr.mixed, &f32, ystore, &ys, w.scal + kScalF32);
       if (ystored) *ystored = ys ? 1 : 0;
       qa.Tpost = base.R[0].S;
       qa.tpr = base.R[0].rows;
@@ -500,7 +502,8 @@ int qr_by_gram(ttr_handle *h, WS &w, const CoreView &cv, int mode, const Stages 
       qa.cond_scale = tcond;
       chain_flops(cvp, s1, &zr, &zc);
     } else {
-      gnwg = gram(h, w.partials, w.G, cvp, st, mode, (pass == 1) ? pr.mixed : 0, &f32);
+      gnwg = gram(h, w.partials, w.G, cvp, st, mode, (pass == 1) ? pr.mixed : 0, &f32, nullptr, nullptr,
+                  w.scal + kScalF32);
       chain_flops(cvp, st, &zr, &zc);
     }
     ++*passes;

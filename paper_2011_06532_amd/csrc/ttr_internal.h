@@ -66,11 +66,17 @@ void launch_apply(hipStream_t s, const CoreView &cv, const Stages &st, double *Y
 // Matrix-core paths (ttr_mfma.hip) on physical cores (a x I x b), dims <= 64.
 // tri: the factor is triangular (Q lower / P upper), zero fragments are skipped.
 // f32: the mixed-precision first pass (FP32 products and accumulation).
+// fscale (f32, device, 3 doubles, nullable): the data and the factor are
+// scaled by powers of two chosen from their largest entries before they are
+// rounded to FP32, and the Gram is scaled back exactly (without it, FP32's
+// range bounds the data).
 int launch_gram_right_factor(hipStream_t s, const double *X, int a, int b, long long I, const double *Q, int q,
-                             long long sQr, long long sQc, int tri, int f32, double *partials);
+                             long long sQr, long long sQc, int tri, int f32, double *partials,
+                             double *fscale = nullptr);
 // Yout (FP64 only, may be nullptr): also writes P X_i as a p x I x b core.
 int launch_gram_left_factor(hipStream_t s, const double *X, int a, int b, long long I, const double *P, int p,
-                            long long sPr, long long sPa, int tri, int f32, double *partials, double *Yout = nullptr);
+                            long long sPr, long long sPa, int tri, int f32, double *partials, double *Yout = nullptr,
+                            double *fscale = nullptr);
 // tri: bit 0 = Q lower triangular, bit 1 = P upper triangular (their
 // vanishing k-steps are skipped).
 void launch_apply_mfma(hipStream_t s, const double *X, int a, int b, long long I, const double *P, int p,

@@ -59,7 +59,7 @@ __device__ inline d4 mfma(double a, double b, d4 c) { return F64::mma(a, b, c); 
 // S(r, c) = S[r*sr + c*sc]; S == nullptr means the identity.  Zero outside.
 template <class T = double>
 __device__ void build_afrag(T *frag, const double *S, int rows, int cols, long long sr, long long sc, int nt,
-                            int KS) {
+                            int KS, double scale = 1.0) {
   const int total = nt * KS * 64;
   for (int e = threadIdx.x; e < total; e += blockDim.x) {
     const int l = e & 63;
@@ -69,7 +69,7 @@ __device__ void build_afrag(T *frag, const double *S, int rows, int cols, long l
     const int c = ks * 4 + (l >> 4);
     double v = 0.0;
     if (r < rows && c < cols) v = S ? S[r * sr + c * sc] : (r == c ? 1.0 : 0.0);
-    frag[e] = (T)v;
+    frag[e] = (sizeof(T) == 4) ? (T)(v * scale) : (T)v;
   }
 }
 
@@ -94,7 +94,8 @@ __device__ void build_bfrag(T *frag, const double *S, int rows, int cols, long l
 // into the workgroup's dense gd x gd matrix in LDS (FP64), waves in a fixed
 // order.
 template <int NT, class A>
-__device__ void reduce_gram(const typename A::V (&G)[NT][NT], int nt, int gd, double *Gs, double *out) {
+__device__ void reduce_gram(const typename A::V (&G)[NT][NT], int nt, int gd, double *Gs, double *out,
+                            double post = 1.0) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, j = lane & 15;
   for (int e = threadIdx.x; e < gd * gd; e += blockDim.x) Gs[e] = 0.0;
@@ -118,7 +119,8 @@ __device__ void reduce_gram(const typename A::V (&G)[NT][NT], int nt, int gd, do
   }
   for (int e = threadIdx.x; e < gd * gd; e += blockDim.x) {
     const int row = e % gd, col = e / gd;
-    out[e] = (row >= col) ? Gs[row + gd * col] : Gs[col + gd * row];
+    const double v = (row >= col) ? Gs[row + gd * col] : Gs[col + gd * row];
+    out[e] = (sizeof(typename A::T) == 4) ? v * post : v;
   }
 }
 
@@ -192,7 +194,7 @@ __device__ inline void load_slice_pairs(const double *__restrict__ Xi, long long
 // frag[(t*KP + ks)*64 + l] = S(t*16 + l%16, pair_alpha(ks, l/16)).
 template <class T = double>
 __device__ void build_afrag_pairs(T *frag, const double *S, int rows, int cols, long long sr, long long sc, int nt,
-                                  int KP) {
+                                  int KP, double scale = 1.0) {
   const int total = nt * KP * 64;
   for (int e = threadIdx.x; e < total; e += blockDim.x) {
     const int l = e & 63;
@@ -202,7 +204,7 @@ __device__ void build_afrag_pairs(T *frag, const double *S, int rows, int cols, 
     const int c = pair_alpha(ks, l >> 4);
     double v = 0.0;
     if (r < rows && c < cols) v = S ? S[r * sr + c * sc] : (r == c ? 1.0 : 0.0);
-    frag[e] = (T)v;
+    frag[e] = (sizeof(T) == 4) ? (T)(v * scale) : (T)v;
   }
 }
 
@@ -264,9 +266,15 @@ template <int NT, int KS, class A, bool GD = false>
 __device__ __forceinline__ void gram_right_factor_body(const int wg, const double *__restrict__ X, int a, int b, long long I,
                                                                 const double *__restrict__ Q, int q, long long sQr,
                                                                 long long sQc, int tri, long long spw,
-                                                                double *__restrict__ partials) {
+                                                                double *__restrict__ partials,
+                                                                const double *__restrict__ fscale = nullptr) {
   using T = typename A::T;
   using V = typename A::V;
+  // FP32 (fscale given): slices and Q are multiplied by powers of two before
+  // they are rounded to FP32 and the Gram is scaled back (exactly) at the end
+  const double sM = (sizeof(T) == 4 && fscale) ? fscale[0] : 1.0;
+  const double sF = (sizeof(T) == 4 && fscale) ? fscale[1] : 1.0;
+  const double post = (sizeof(T) == 4 && fscale) ? fscale[2] : 1.0;
   __shared__ T frag[NT * KS * 64];
   __shared__ double Gs[NT * 16 * NT * 16];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -275,7 +283,7 @@ __device__ __forceinline__ void gram_right_factor_body(const int wg, const doubl
   // k-steps and 16-tiles past them
   const int ksr = (b + 3) / 4, ntq = (q + 15) / 16, nta = (a + 15) / 16;
   // A operand: Q^T (q x b), Q^T(c, beta) = Q(beta, c)
-  build_afrag<T>(frag, Q, q, b, sQc, sQr, NT, KS);
+  build_afrag<T>(frag, Q, q, b, sQc, sQr, NT, KS, sF);
   __syncthreads();
   V G[NT][NT];
 #pragma unroll
@@ -295,7 +303,13 @@ __device__ __forceinline__ void gram_right_factor_body(const int wg, const doubl
   double nxt[KS][NT];  // used only with PF
   long long i = beg + wave;
   if constexpr (PF)
-    if (i < end) load_slice<NT, KS, true, T>(X + (long long)a * i, col, a, b, g, j, cur);
+    if (i < end) {
+      load_slice<NT, KS, true>(X + (long long)a * i, col, a, b, g, j, nxt);
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) cur[ks][t] = (sizeof(T) == 4) ? (T)(nxt[ks][t] * sM) : (T)nxt[ks][t];
+    }
   for (; i < end; i += kWaves) {
     // NT = 4: keep the operand fragments in LDS rather than hoisted into
     // registers, which is what lets two waves share a SIMD
@@ -339,18 +353,19 @@ __device__ __forceinline__ void gram_right_factor_body(const int wg, const doubl
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
-        for (int t = 0; t < NT; ++t) cur[ks][t] = (T)nxt[ks][t];
+        for (int t = 0; t < NT; ++t) cur[ks][t] = (sizeof(T) == 4) ? (T)(nxt[ks][t] * sM) : (T)nxt[ks][t];
     }
   }
-  reduce_gram<NT, A>(G, NT, a, Gs, partials + (long long)wg * a * a);
+  reduce_gram<NT, A>(G, NT, a, Gs, partials + (long long)wg * a * a, post);
 }
 
 template <int NT, int KS, class A>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NT <= 3 || (KS <= 13 && sizeof(typename A::T) == 8) ? 2 : 1, NT <= 3 || (KS <= 13 && sizeof(typename A::T) == 8) ? 2 : 1))) void k_gram_right_factor(const double *__restrict__ X, int a, int b, long long I,
                                                                 const double *__restrict__ Q, int q, long long sQr,
                                                                 long long sQc, int tri, long long spw,
-                                                                double *__restrict__ partials) {
-  gram_right_factor_body<NT, KS, A>(blockIdx.x, X, a, b, I, Q, q, sQr, sQc, tri, spw, partials);
+                                                                double *__restrict__ partials,
+                                                                const double *__restrict__ fscale) {
+  gram_right_factor_body<NT, KS, A>(blockIdx.x, X, a, b, I, Q, q, sQr, sQc, tri, spw, partials, fscale);
 }
 
 // ---------------------------------------------------------------------------
@@ -363,9 +378,15 @@ __device__ __forceinline__ void gram_left_factor_body(const int wg, const double
                                                                const double *__restrict__ P, int p, long long sPr,
                                                                long long sPa, int tri, long long spw,
                                                                double *__restrict__ partials,
-                                                               double *__restrict__ Yout = nullptr) {
+                                                               double *__restrict__ Yout = nullptr,
+                                                               const double *__restrict__ fscale = nullptr) {
   using T = typename A::T;
   using V = typename A::V;
+  // FP32 (fscale given): slices and P scaled by powers of two before the
+  // rounding to FP32, the Gram scaled back at the end
+  const double sM = (sizeof(T) == 4 && fscale) ? fscale[0] : 1.0;
+  const double sF = (sizeof(T) == 4 && fscale) ? fscale[1] : 1.0;
+  const double post = (sizeof(T) == 4 && fscale) ? fscale[2] : 1.0;
   // ST: the product Y_i = P M_i is also written, as a p x I x b core (FP64), for
   // the output pass that follows to reuse.
   // The product contracts over alpha, the fast index of a slice: its k-steps
@@ -380,7 +401,7 @@ __device__ __forceinline__ void gram_left_factor_body(const int wg, const double
   const int g = lane >> 4, j = lane & 15;
   const int kpr = 2 * ((a + 7) / 8), ntp = (p + 15) / 16, ntb = (b + 15) / 16;  // GD: run-time extents
   const bool v2 = ((a & 1) == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
-  build_afrag_pairs<T>(frag, P, p, a, sPr, sPa, NT, KP);
+  build_afrag_pairs<T>(frag, P, p, a, sPr, sPa, NT, KP, sF);
   __syncthreads();
   V G[NT][NT];
 #pragma unroll
@@ -399,8 +420,12 @@ __device__ __forceinline__ void gram_left_factor_body(const int wg, const double
   long long i = beg + wave;
   if constexpr (PF) {
     if (i < end) {
-      if (v2) load_slice_pairs<NT, KP, true, T>(X + (long long)a * i, col, a, b, g, j, cur);
-      else load_slice_pairs<NT, KP, false, T>(X + (long long)a * i, col, a, b, g, j, cur);
+      if (v2) load_slice_pairs<NT, KP, true>(X + (long long)a * i, col, a, b, g, j, nxt);
+      else load_slice_pairs<NT, KP, false>(X + (long long)a * i, col, a, b, g, j, nxt);
+#pragma unroll
+      for (int ks = 0; ks < KP; ++ks)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) cur[ks][t] = (sizeof(T) == 4) ? (T)(nxt[ks][t] * sM) : (T)nxt[ks][t];
     }
   }
   for (; i < end; i += kWaves) {
@@ -481,10 +506,10 @@ __device__ __forceinline__ void gram_left_factor_body(const int wg, const double
 #pragma unroll
       for (int ks = 0; ks < KP; ++ks)
 #pragma unroll
-        for (int t = 0; t < NT; ++t) cur[ks][t] = (T)nxt[ks][t];
+        for (int t = 0; t < NT; ++t) cur[ks][t] = (sizeof(T) == 4) ? (T)(nxt[ks][t] * sM) : (T)nxt[ks][t];
     }
   }
-  reduce_gram<NT, A>(G, NT, b, Gs, partials + (long long)wg * b * b);
+  reduce_gram<NT, A>(G, NT, b, Gs, partials + (long long)wg * b * b, post);
 }
 
 template <int NT, int KS, class A, bool ST = false>
@@ -492,8 +517,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NT <= 
                                                                const double *__restrict__ P, int p, long long sPr,
                                                                long long sPa, int tri, long long spw,
                                                                double *__restrict__ partials,
-                                                               double *__restrict__ Yout) {
-  gram_left_factor_body<NT, KS, A, false, ST>(blockIdx.x, X, a, b, I, P, p, sPr, sPa, tri, spw, partials, Yout);
+                                                               double *__restrict__ Yout,
+                                                               const double *__restrict__ fscale) {
+  gram_left_factor_body<NT, KS, A, false, ST>(blockIdx.x, X, a, b, I, P, p, sPr, sPa, tri, spw, partials, Yout,
+                                              fscale);
 }
 
 // ---------------------------------------------------------------------------
@@ -1022,34 +1049,91 @@ void nt_ks(int nt, int ks, F &&f) {
 }
 #define TTR_LAUNCH(...) hipLaunchKernelGGL((__VA_ARGS__), dim3(gr.nwg), dim3(kThreads), 0, s,
 
+namespace {
+// Scales of an FP32 Gram pass, powers of two: out[0] = 2^-e for the largest
+// finite |x| over up to 65536 evenly spaced samples of the n doubles at X
+// (2^e <= max < 2^(e+1)), out[1] = 2^-f likewise for every entry of the small
+// factor F (rows x cols, F(r, c) = F[r sr + c sc]; 1 when F is absent), and
+// out[2] = 2^(2(e + f)), which undoes both in the Gram.  A zero maximum gives
+// the scale 1.
+__global__ __launch_bounds__(256) void k_f32_scale(const double *__restrict__ X, long long n,
+                                                   const double *__restrict__ F, int rows, int cols, long long sr,
+                                                   long long sc, double *__restrict__ out) {
+  __shared__ double red[2][256];
+  const long long ns = std::min(n, 65536LL);
+  const long long stride = std::max(1LL, n / std::max(ns, 1LL));
+  double mx = 0.0, mf = 0.0;
+  for (long long j = threadIdx.x; j < ns; j += 256) {
+    const double v = fabs(X[j * stride]);
+    if (v <= 1.7976931348623157e308) mx = fmax(mx, v);
+  }
+  if (F)
+    for (int e = threadIdx.x; e < rows * cols; e += 256) {
+      const double v = fabs(F[(long long)(e % rows) * sr + (long long)(e / rows) * sc]);
+      if (v <= 1.7976931348623157e308) mf = fmax(mf, v);
+    }
+  red[0][threadIdx.x] = mx;
+  red[1][threadIdx.x] = mf;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      red[0][threadIdx.x] = fmax(red[0][threadIdx.x], red[0][threadIdx.x + off]);
+      red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + off]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int e = (red[0][0] > 0.0) ? ilogb(red[0][0]) : 0;
+    const int f = (red[1][0] > 0.0) ? ilogb(red[1][0]) : 0;
+    out[0] = ldexp(1.0, -e);
+    out[1] = ldexp(1.0, -f);
+    out[2] = ldexp(1.0, 2 * (e + f));
+  }
+}
+}  // namespace
+
 int launch_gram_right_factor(hipStream_t s, const double *X, int a, int b, long long I, const double *Q, int q,
-                             long long sQr, long long sQc, int tri, int f32, double *partials) {
+                             long long sQr, long long sQc, int tri, int f32, double *partials, double *fscale) {
   const Grid gr = grid_of(I, f32 ? TTR_MAXWG : kWgF64);
+  if (f32 && fscale)
+    hipLaunchKernelGGL(k_f32_scale, dim3(1), dim3(256), 0, s, X, (long long)a * I * b, Q, Q ? b : 0, Q ? q : 0, sQr,
+                       sQc, fscale);
+  else
+    fscale = nullptr;
   const int nt = std::max({tiles_for(a), tiles_for(b), tiles_for(q)});
   const int ks = std::max((b + 3) / 4, 4 * nt - 3);
   nt_ks(nt, ks, [&](auto NTc, auto KSc) {
     constexpr int NTV = decltype(NTc)::value, KSV = decltype(KSc)::value;
     if (f32)
-      TTR_LAUNCH(k_gram_right_factor<NTV, KSV, F32>) X, a, b, I, Q, q, sQr, sQc, tri, gr.spw, partials);
+      TTR_LAUNCH(k_gram_right_factor<NTV, KSV, F32>) X, a, b, I, Q, q, sQr, sQc, tri, gr.spw, partials, fscale);
     else
-      TTR_LAUNCH(k_gram_right_factor<NTV, KSV, F64>) X, a, b, I, Q, q, sQr, sQc, tri, gr.spw, partials);
+      TTR_LAUNCH(k_gram_right_factor<NTV, KSV, F64>) X, a, b, I, Q, q, sQr, sQc, tri, gr.spw, partials, nullptr);
   });
   return gr.nwg;
 }
 
 int launch_gram_left_factor(hipStream_t s, const double *X, int a, int b, long long I, const double *P, int p,
-                            long long sPr, long long sPa, int tri, int f32, double *partials, double *Yout) {
+                            long long sPr, long long sPa, int tri, int f32, double *partials, double *Yout,
+                            double *fscale) {
   const Grid gr = grid_of(I, f32 ? TTR_MAXWG : kWgF64);
+  if (f32 && fscale)
+    hipLaunchKernelGGL(k_f32_scale, dim3(1), dim3(256), 0, s, X, (long long)a * I * b, P, P ? p : 0, P ? a : 0, sPr,
+                       sPa, fscale);
+  else
+    fscale = nullptr;
   const int nt = std::max({tiles_for(a), tiles_for(b), tiles_for(p)});
   const int ks = std::max((a + 3) / 4, 4 * nt - 3);
   nt_ks(nt, ks, [&](auto NTc, auto KSc) {
     constexpr int NTV = decltype(NTc)::value, KSV = decltype(KSc)::value;
     if (f32)
-      TTR_LAUNCH(k_gram_left_factor<NTV, KSV, F32>) X, a, b, I, P, p, sPr, sPa, tri, gr.spw, partials, nullptr);
+      TTR_LAUNCH(k_gram_left_factor<NTV, KSV, F32>) X, a, b, I, P, p, sPr, sPa, tri, gr.spw, partials, nullptr,
+                                                     fscale);
     else if (Yout)
-      TTR_LAUNCH(k_gram_left_factor<NTV, KSV, F64, true>) X, a, b, I, P, p, sPr, sPa, tri, gr.spw, partials, Yout);
+      TTR_LAUNCH(k_gram_left_factor<NTV, KSV, F64, true>) X, a, b, I, P, p, sPr, sPa, tri, gr.spw, partials, Yout,
+                                                           nullptr);
     else
-      TTR_LAUNCH(k_gram_left_factor<NTV, KSV, F64>) X, a, b, I, P, p, sPr, sPa, tri, gr.spw, partials, nullptr);
+      TTR_LAUNCH(k_gram_left_factor<NTV, KSV, F64>) X, a, b, I, P, p, sPr, sPa, tri, gr.spw, partials, nullptr,
+                                                     nullptr);
   });
   return gr.nwg;
 }

@@ -106,3 +106,25 @@ def test_mixed_graded_spectrum(ttr, h, tol, direction):
         Z[0] = Z[0] * eps
         X = O.add(1.0, X, 1.0, Z)
     run(ttr, h, X, tol, direction)
+
+
+@pytest.mark.parametrize("direction", ["RLR", "LRL"])
+@pytest.mark.parametrize("scale", [1e-30, 1e30, 1e-100])
+def test_mixed_far_from_unit_norm(ttr, h, direction, scale):
+    # the FP32 Gram passes scale their data and factor by powers of two chosen
+    # from the largest entries, so products whose squares leave FP32's range
+    # round as in FP64.  1e+-30 is spread over the cores (the triangular
+    # factors passed between cores carry the tensor's scale into the products
+    # C = M T); 1e-100 sits in one core.
+    print(f"mixed precision, tensor scaled by {scale:g} {direction}", flush=True)
+    rng = np.random.default_rng(909)
+    I = [40, 30, 50, 35]
+    X = O.add(1.0, rand_tt(rng, I, [7, 9, 8]), 1.0, rand_tt(rng, I, [6, 5, 7]))
+    Z = rand_tt(rng, I, [2, 2, 2])
+    Z[0] *= 1e-6
+    X = O.add(1.0, X, 1.0, Z)
+    if scale > 1e-50:
+        X = [c * scale ** (1.0 / len(X)) for c in X]
+    else:
+        X[0] = X[0] * scale
+    run(ttr, h, X, 1e-8, direction)
