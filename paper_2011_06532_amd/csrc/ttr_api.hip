@@ -228,7 +228,7 @@ Stage st_transpose(const Stage &a) {
 // kernel.
 // Returns the number of workgroups (partial Grams) the pass used.
 int gram(ttr_handle *h, double *partials, double *G, const CoreView &cv, const Stages &st, int mode, int f32 = 0,
-         bool *ran_f32 = nullptr, double *ystore = nullptr, bool *stored = nullptr, double *fscale = nullptr) {
+         bool *ran_f32 = nullptr, double *fscale = nullptr) {
   int zr, zc;
   const double cf = chain_flops(cv, st, &zr, &zc);
   const double gf = (mode == GRAM_LEFT) ? (double)zr * (zr + 1) * zc : (double)zc * (zc + 1) * zr;
@@ -243,7 +243,6 @@ int gram(ttr_handle *h, double *partials, double *G, const CoreView &cv, const S
   int nwg = 0;
   bool done = false;
   if (ran_f32) *ran_f32 = false;
-  if (stored) *stored = false;
   {
     if (pmode == GRAM_LEFT && pnl == 0 && pnr <= 1) {
       // sum (X Q)(X Q)^T
@@ -261,16 +260,12 @@ int gram(ttr_handle *h, double *partials, double *G, const CoreView &cv, const S
       const Stage *pp = pnl ? (tr ? &st.R[0] : &st.L[0]) : nullptr;
       Stage ps_;
       if (pp) ps_ = tr ? st_transpose(*pp) : *pp;
-      // the FP64 form on a plain view can also write the product P M it forms
-      double *ys = (!f32 && !tr) ? ystore : nullptr;
-      const double yb = ys ? 8.0 * (double)(pp ? ps_.rows : cv.pa) * cv.pb * (double)cv.I : 0.0;
-      ProfScope ps(h, f32 ? P_GRAM_L32 : P_GRAM_L, bytes + yb, flops);
+      ProfScope ps(h, f32 ? P_GRAM_L32 : P_GRAM_L, bytes, flops);
       nwg = launch_gram_left_factor(h->stream, X, cv.pa, cv.pb, cv.I, pp ? ps_.S : nullptr, pp ? ps_.rows : cv.pa,
                                     pp ? ps_.sr : 1, pp ? ps_.sc : cv.pa, (pp && ps_.lower == 2) ? 1 : 0, f32,
-                                    partials, ys, fscale);
+                                    partials, fscale);
       done = true;
       if (ran_f32) *ran_f32 = f32 != 0;
-      if (stored) *stored = ys != nullptr;
     } else if (mode == GRAM_RIGHT && st.nl == 0 && st.nr == 1) {
       // logical sum (M Q)^T (M Q), M the (possibly transposed) slice
       const Stage &q = st.R[0];
@@ -466,8 +461,7 @@ template <class SlotFn>
 int qr_by_gram(ttr_handle *h, WS &w, const CoreView &cv, int mode, const Stages &base, int b, SlotFn slot,
                double *Tdst, Factor *f, double **Rout, int *kout, int *passes, double tcond = -1.0,
                double *ratio = nullptr, TruncCtx *tc = nullptr, Prec pr = Prec(), double *mat = nullptr,
-               CoreView *cv_out = nullptr, int *materialized = nullptr, double *ystore = nullptr,
-               int *ystored = nullptr) {
+               CoreView *cv_out = nullptr, int *materialized = nullptr) {
   double *R[2] = {w.Ra, w.Rb};
   const double *Rc = nullptr;
   int d = b;
@@ -487,13 +481,11 @@ int qr_by_gram(ttr_handle *h, WS &w, const CoreView &cv, int mode, const Stages 
     const bool post = (pass == 1 && mode == GRAM_RIGHT && tcond > 0.0 && base.nr == 1 && base.nl <= 1);
     bool f32 = false;
     int zr, zc;
-    bool ys = false;
     int gnwg = 1;
     if (post) {
       Stages s1 = base;
       s1.nr = 0;
-      gnwg = gram(h, w.partials, w.G, cvp, s1, mode, pr.mixed, &f32, ystore, &ys, w.scal + kScalF32);
-      if (ystored) *ystored = ys ? 1 : 0;
+      gnwg = gram(h, w.partials, w.G, cvp, s1, mode, pr.mixed, &f32, w.scal + kScalF32);
       qa.Tpost = base.R[0].S;
       qa.tpr = base.R[0].rows;
       qa.tpc = base.R[0].cols;
@@ -502,8 +494,7 @@ int qr_by_gram(ttr_handle *h, WS &w, const CoreView &cv, int mode, const Stages 
       qa.cond_scale = tcond;
       chain_flops(cvp, s1, &zr, &zc);
     } else {
-      gnwg = gram(h, w.partials, w.G, cvp, st, mode, (pass == 1) ? pr.mixed : 0, &f32, nullptr, nullptr,
-                  w.scal + kScalF32);
+      gnwg = gram(h, w.partials, w.G, cvp, st, mode, (pass == 1) ? pr.mixed : 0, &f32, w.scal + kScalF32);
       chain_flops(cvp, st, &zr, &zc);
     }
     ++*passes;
@@ -548,18 +539,7 @@ int qr_by_gram(ttr_handle *h, WS &w, const CoreView &cv, int mode, const Stages 
       // that the refinement Gram passes and the output pass read one core
       // and apply the refinement stages to bitwise the same data.
       Stages sb = base;
-      if (ys) {
-        // C' = (P M) T from the product the Gram pass wrote
-        CoreView cy = cv;
-        cy.X = ystore;
-        cy.pa = base.nl ? base.L[0].rows : cv.pa;
-        Stages sy = no_stages();
-        sy.R[sy.nr++] = base.R[0];
-        apply(h, cy, sy, mat, 0);
-        if (ystored) *ystored = 0;  // overwritten roles: the output uses C'
-      } else {
-        apply(h, cv, sb, mat, cv.trans);
-      }
+      apply(h, cv, sb, mat, cv.trans);
       int mr, mc;
       chain_flops(cv, base, &mr, &mc);
       cvp.X = mat;
@@ -1245,7 +1225,6 @@ int ttr_round(ttr_handle *h, const ttr_tt *X, double tol, int direction, int pre
   // orthonormalization stages of core n with the last one merged into P_n.
   std::vector<int> L(N + 1, 1), sweeps(N, 0);
   double *Pbuf[2] = {w.Pa, w.Pb};
-  bool prev_refined = false;
   const double *Pcur = nullptr;  // merged last left stage (Lprev x dim)
   int Lprev = 1;
   int applies = 0;
@@ -1295,14 +1274,8 @@ int ttr_round(ttr_handle *h, const ttr_tt *X, double tol, int direction, int pre
     tcx.tol2_nm1 = tol * tol / (double)(N - 1);
     CoreView cvm;
     int materialized = 0;
-    // The first Gram pass also writes P M_n when the previous link needed a
-    // refinement pass (then this one likely does too, and C' = (P M_n) T_{n+1}
-    // costs one product); a one-pass link is cheaper without the extra write.
-    int ystored = 0;
-    double *ystore = (!tfold && prev_refined) ? w.matB : nullptr;
     rc = qr_by_gram(h, w, cv, GRAM_RIGHT, base, b, slot, nullptr, &g, &Rq, &kq, &passes, tcond, nullptr, &tcx, pr,
-                    tfold ? nullptr : w.matA, &cvm, &materialized, ystore, &ystored);
-    prev_refined = (g.nst >= 2);
+                    tfold ? nullptr : w.matA, &cvm, &materialized);
     if (rc) return rc;
     const Factor &fn = fac[n + 1];
     TruncArgs ta;
@@ -1344,18 +1317,6 @@ int ttr_round(ttr_handle *h, const ttr_tt *X, double tol, int direction, int pre
       launch_small_gemm(h->stream, w.T(n + 1), w.GU, w.Gst[1], tr, b, Ln);
       st.nr = 0;
       st.R[st.nr++] = st_plain(w.Gst[1], tr, Ln);
-      if (ystored) {
-        // the Gram pass wrote P M_n: one product left
-        CoreView cy = cv;
-        cy.X = w.matB;
-        cy.pa = st.nl ? st.L[0].rows : cv.pa;
-        st.nl = 0;
-        apply(h, cy, st, Y->core[S.phys(n)], 0);
-        ++applies;
-        Pcur = ta.Pnext;
-        Lprev = Ln;
-        continue;
-      }
     } else {
       for (int j = 0; j + 1 < g.nst; ++j) st.R[st.nr++] = st_plain(w.Gst[j], g.dim[j], g.dim[j + 1]);
       st.R[st.nr++] = st_plain(w.GU, ta.d, Ln);

@@ -73,9 +73,8 @@ void launch_apply(hipStream_t s, const CoreView &cv, const Stages &st, double *Y
 int launch_gram_right_factor(hipStream_t s, const double *X, int a, int b, long long I, const double *Q, int q,
                              long long sQr, long long sQc, int tri, int f32, double *partials,
                              double *fscale = nullptr);
-// Yout (FP64 only, may be nullptr): also writes P X_i as a p x I x b core.
 int launch_gram_left_factor(hipStream_t s, const double *X, int a, int b, long long I, const double *P, int p,
-                            long long sPr, long long sPa, int tri, int f32, double *partials, double *Yout = nullptr,
+                            long long sPr, long long sPa, int tri, int f32, double *partials,
                             double *fscale = nullptr);
 // tri: bit 0 = Q lower triangular, bit 1 = P upper triangular (their
 // vanishing k-steps are skipped).

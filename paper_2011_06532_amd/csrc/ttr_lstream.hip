@@ -554,18 +554,26 @@ LGramGrid lg_gram_grid(long long M, int f32) {
 
 namespace {
 
-// Scale of an FP32 Gram: the largest finite |x| over up to 65536 evenly
+// Scale of an FP32 Gram: the largest finite |x| over up to 4096 evenly
 // spaced samples of the n doubles at X, m, gives out[0] = 2^-e with
-// 2^e <= m < 2^(e+1) and out[1] = 2^(2e) (1 and 1 when m = 0).
+// 2^e <= m < 2^(e+1) and out[1] = 2^(2e) (1 and 1 when m = 0).  Only the
+// exponent matters, so a sample suffices; each thread issues its 16 loads
+// at once.
 __global__ __launch_bounds__(256) void lg_scale_probe(const double *__restrict__ X, long long n, double *out) {
   __shared__ double red[256];
-  const long long ns = std::min(n, 65536LL);
+  constexpr int kPer = 16;
+  const long long ns = std::min(n, 256LL * kPer);
   const long long stride = std::max(1LL, n / std::max(ns, 1LL));
   double m = 0.0;
-  for (long long j = threadIdx.x; j < ns; j += 256) {
-    const double v = fabs(X[j * stride]);
-    if (v <= 1.7976931348623157e308) m = fmax(m, v);
+  double v[kPer];
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const long long j = threadIdx.x + 256LL * q;
+    v[q] = (j < ns) ? fabs(X[j * stride]) : 0.0;
   }
+#pragma unroll
+  for (int q = 0; q < kPer; ++q)
+    if (v[q] <= 1.7976931348623157e308) m = fmax(m, v[q]);
   red[threadIdx.x] = m;
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {

@@ -241,19 +241,6 @@ __device__ inline void store_col(const VT (&yc)[NT], int c, int nrow, int ncol, 
   __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
 }
 
-// All column tiles of an nrow x ncol result y[u][c], one after the other.
-template <int NT, class A, class VT>
-__device__ inline void store_tiles(const VT (&y)[NT][NT], int nrow, int ncol, double *__restrict__ Yi, long long ocol,
-                                   double *Lw, int LDP, int lane, int g, int j) {
-#pragma unroll
-  for (int c = 0; c < NT; ++c) {
-    if (c * 16 >= ncol) break;
-    VT yc[NT];
-#pragma unroll
-    for (int u = 0; u < NT; ++u) yc[u] = y[u][c];
-    store_col<NT, A>(yc, c, nrow, ncol, Yi, ocol, Lw, LDP, lane, g, j);
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Gram with a right factor: G (a x a) = sum_i (M_i Q)(M_i Q)^T, M_i = X(:, i, :)
@@ -373,12 +360,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NT <= 
 // The Gram of the vertical unfolding of P x_1 X (truncation sweep, §2.4).
 // KS = k-steps over a (ceil(a/4)).
 // ---------------------------------------------------------------------------
-template <int NT, int KS, class A, bool GD = false, bool ST = false>
+template <int NT, int KS, class A, bool GD = false>
 __device__ __forceinline__ void gram_left_factor_body(const int wg, const double *__restrict__ X, int a, int b, long long I,
                                                                const double *__restrict__ P, int p, long long sPr,
                                                                long long sPa, int tri, long long spw,
                                                                double *__restrict__ partials,
-                                                               double *__restrict__ Yout = nullptr,
                                                                const double *__restrict__ fscale = nullptr) {
   using T = typename A::T;
   using V = typename A::V;
@@ -387,16 +373,12 @@ __device__ __forceinline__ void gram_left_factor_body(const int wg, const double
   const double sM = (sizeof(T) == 4 && fscale) ? fscale[0] : 1.0;
   const double sF = (sizeof(T) == 4 && fscale) ? fscale[1] : 1.0;
   const double post = (sizeof(T) == 4 && fscale) ? fscale[2] : 1.0;
-  // ST: the product Y_i = P M_i is also written, as a p x I x b core (FP64), for
-  // the output pass that follows to reuse.
   // The product contracts over alpha, the fast index of a slice: its k-steps
   // run in pair order, so the slices are read with 16-byte loads straight
   // into the operand layout.
   constexpr int KP = (KS + 1) & ~1;   // k-steps over alpha (pair order covers 8 alpha per two steps)
-  constexpr int LDT = NT * 16 + 1;    // product staging tile leading dimension (ST)
   __shared__ T frag[NT * KP * 64];
   __shared__ double Gs[NT * 16 * NT * 16];
-  __shared__ double Lys[ST ? kWaves * LDT * 16 : 1];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, j = lane & 15;
   const int kpr = 2 * ((a + 7) / 8), ntp = (p + 15) / 16, ntb = (b + 15) / 16;  // GD: run-time extents
@@ -442,64 +424,31 @@ __device__ __forceinline__ void gram_left_factor_body(const int wg, const double
       if (v2) load_slice_pairs<NT, KP, true, T>(X + (long long)a * i, col, a, b, g, j, cur);
       else load_slice_pairs<NT, KP, false, T>(X + (long long)a * i, col, a, b, g, j, cur);
     }
-    if constexpr (ST) {
-      // the whole product is kept for the store
-      V y[NT][NT];  // [rho-tile][beta-tile]
+    // one 16-row band of Y = P M at a time: its Gram contribution is
+    // complete on its own, so only NT accumulator tiles of Y are live
 #pragma unroll
-      for (int u = 0; u < NT; ++u)
+    for (int rb = 0; rb < NT; ++rb) {
+      if (GD && rb >= ntp) continue;
+      V y[NT];  // Y(rho, beta), rho in band rb, one tile per beta-tile
 #pragma unroll
-        for (int v = 0; v < NT; ++v) y[u][v] = V{0, 0, 0, 0};
+      for (int t = 0; t < NT; ++t) y[t] = V{0, 0, 0, 0};
 #pragma unroll
-      for (int ks = 0; ks < KP; ++ks)
+      for (int ks = 0; ks < KP; ++ks) {
+        // upper-triangular P: P(rho, alpha) = 0 for alpha < rho
+        if ((tri && ks < 4 * rb) || (GD && ks >= kpr)) continue;
+        const T pa = frag[(rb * KP + ks) * 64 + lane];
 #pragma unroll
-        for (int rb = 0; rb < NT; ++rb) {
-          // upper-triangular P: P(rho, alpha) = 0 for alpha < rho
-          if ((tri && ks < 4 * rb) || (GD && (ks >= kpr || rb >= ntp))) continue;
-          const T pa = frag[(rb * KP + ks) * 64 + lane];
+        for (int t = 0; t < NT; ++t)
+          if (!GD || t < ntb) y[t] = A::mma(pa, cur[ks][t], y[t]);
+      }
 #pragma unroll
-          for (int t = 0; t < NT; ++t)
-            if (!GD || t < ntb) y[rb][t] = A::mma(pa, cur[ks][t], y[rb][t]);
-        }
-      store_tiles<NT, A>(y, p, b, Yout + (long long)p * i, (long long)p * I, Lys + wave * LDT * 16, LDT, lane, g, j);
-      // G0(beta, beta') += sum_rho Y(rho, beta) Y(rho, beta'); rows past p are padding
+      for (int r = 0; r < 4; ++r) {
+        if (rb * 16 + A::row(0, r) >= p) continue;
 #pragma unroll
-      for (int rb = 0; rb < NT; ++rb)
+        for (int u = 0; u < NT; ++u)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          if (rb * 16 + A::row(0, r) >= p) continue;
-#pragma unroll
-          for (int u = 0; u < NT; ++u)
-#pragma unroll
-            for (int v = 0; v <= u; ++v)
-              if (!GD || u < ntb) G[u][v] = A::mma(y[rb][u][r], y[rb][v][r], G[u][v]);
-        }
-    } else {
-      // one 16-row band of Y = P M at a time: its Gram contribution is
-      // complete on its own, so only NT accumulator tiles of Y are live
-#pragma unroll
-      for (int rb = 0; rb < NT; ++rb) {
-        if (GD && rb >= ntp) continue;
-        V y[NT];  // Y(rho, beta), rho in band rb, one tile per beta-tile
-#pragma unroll
-        for (int t = 0; t < NT; ++t) y[t] = V{0, 0, 0, 0};
-#pragma unroll
-        for (int ks = 0; ks < KP; ++ks) {
-          // upper-triangular P: P(rho, alpha) = 0 for alpha < rho
-          if ((tri && ks < 4 * rb) || (GD && ks >= kpr)) continue;
-          const T pa = frag[(rb * KP + ks) * 64 + lane];
-#pragma unroll
-          for (int t = 0; t < NT; ++t)
-            if (!GD || t < ntb) y[t] = A::mma(pa, cur[ks][t], y[t]);
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          if (rb * 16 + A::row(0, r) >= p) continue;
-#pragma unroll
-          for (int u = 0; u < NT; ++u)
-#pragma unroll
-            for (int v = 0; v <= u; ++v)
-              if (!GD || u < ntb) G[u][v] = A::mma(y[u][r], y[v][r], G[u][v]);
-        }
+          for (int v = 0; v <= u; ++v)
+            if (!GD || u < ntb) G[u][v] = A::mma(y[u][r], y[v][r], G[u][v]);
       }
     }
     if constexpr (PF) {
@@ -512,15 +461,13 @@ __device__ __forceinline__ void gram_left_factor_body(const int wg, const double
   reduce_gram<NT, A>(G, NT, b, Gs, partials + (long long)wg * b * b, post);
 }
 
-template <int NT, int KS, class A, bool ST = false>
+template <int NT, int KS, class A>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NT <= 3 || KS <= 14 ? 2 : 1, NT <= 3 || KS <= 14 ? 2 : 1))) void k_gram_left_factor(const double *__restrict__ X, int a, int b, long long I,
                                                                const double *__restrict__ P, int p, long long sPr,
                                                                long long sPa, int tri, long long spw,
                                                                double *__restrict__ partials,
-                                                               double *__restrict__ Yout,
                                                                const double *__restrict__ fscale) {
-  gram_left_factor_body<NT, KS, A, false, ST>(blockIdx.x, X, a, b, I, P, p, sPr, sPa, tri, spw, partials, Yout,
-                                              fscale);
+  gram_left_factor_body<NT, KS, A>(blockIdx.x, X, a, b, I, P, p, sPr, sPa, tri, spw, partials, fscale);
 }
 
 // ---------------------------------------------------------------------------
@@ -1051,27 +998,34 @@ void nt_ks(int nt, int ks, F &&f) {
 
 namespace {
 // Scales of an FP32 Gram pass, powers of two: out[0] = 2^-e for the largest
-// finite |x| over up to 65536 evenly spaced samples of the n doubles at X
+// finite |x| over up to 4096 evenly spaced samples of the n doubles at X
 // (2^e <= max < 2^(e+1)), out[1] = 2^-f likewise for every entry of the small
-// factor F (rows x cols, F(r, c) = F[r sr + c sc]; 1 when F is absent), and
-// out[2] = 2^(2(e + f)), which undoes both in the Gram.  A zero maximum gives
-// the scale 1.
+// factor F (rows x cols <= 4096 entries, F(r, c) = F[r sr + c sc]; 1 when F
+// is absent), and out[2] = 2^(2(e + f)), which undoes both in the Gram.  A
+// zero maximum gives the scale 1.  Only the exponent matters (FP32's range
+// leaves decades of room either side), so a sample suffices; each thread
+// issues its 16 loads at once.
 __global__ __launch_bounds__(256) void k_f32_scale(const double *__restrict__ X, long long n,
                                                    const double *__restrict__ F, int rows, int cols, long long sr,
                                                    long long sc, double *__restrict__ out) {
   __shared__ double red[2][256];
-  const long long ns = std::min(n, 65536LL);
+  constexpr int kPer = 16;
+  const long long ns = std::min(n, 256LL * kPer);
   const long long stride = std::max(1LL, n / std::max(ns, 1LL));
   double mx = 0.0, mf = 0.0;
-  for (long long j = threadIdx.x; j < ns; j += 256) {
-    const double v = fabs(X[j * stride]);
-    if (v <= 1.7976931348623157e308) mx = fmax(mx, v);
+  double v[kPer], f[kPer];
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const long long j = threadIdx.x + 256LL * q;
+    v[q] = (j < ns) ? fabs(X[j * stride]) : 0.0;
+    const int e = threadIdx.x + 256 * q;
+    f[q] = (F && e < rows * cols) ? fabs(F[(long long)(e % rows) * sr + (long long)(e / rows) * sc]) : 0.0;
   }
-  if (F)
-    for (int e = threadIdx.x; e < rows * cols; e += 256) {
-      const double v = fabs(F[(long long)(e % rows) * sr + (long long)(e / rows) * sc]);
-      if (v <= 1.7976931348623157e308) mf = fmax(mf, v);
-    }
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    if (v[q] <= 1.7976931348623157e308) mx = fmax(mx, v[q]);
+    if (f[q] <= 1.7976931348623157e308) mf = fmax(mf, f[q]);
+  }
   red[0][threadIdx.x] = mx;
   red[1][threadIdx.x] = mf;
   __syncthreads();
@@ -1113,8 +1067,7 @@ int launch_gram_right_factor(hipStream_t s, const double *X, int a, int b, long 
 }
 
 int launch_gram_left_factor(hipStream_t s, const double *X, int a, int b, long long I, const double *P, int p,
-                            long long sPr, long long sPa, int tri, int f32, double *partials, double *Yout,
-                            double *fscale) {
+                            long long sPr, long long sPa, int tri, int f32, double *partials, double *fscale) {
   const Grid gr = grid_of(I, f32 ? TTR_MAXWG : kWgF64);
   if (f32 && fscale)
     hipLaunchKernelGGL(k_f32_scale, dim3(1), dim3(256), 0, s, X, (long long)a * I * b, P, P ? p : 0, P ? a : 0, sPr,
@@ -1126,14 +1079,9 @@ int launch_gram_left_factor(hipStream_t s, const double *X, int a, int b, long l
   nt_ks(nt, ks, [&](auto NTc, auto KSc) {
     constexpr int NTV = decltype(NTc)::value, KSV = decltype(KSc)::value;
     if (f32)
-      TTR_LAUNCH(k_gram_left_factor<NTV, KSV, F32>) X, a, b, I, P, p, sPr, sPa, tri, gr.spw, partials, nullptr,
-                                                     fscale);
-    else if (Yout)
-      TTR_LAUNCH(k_gram_left_factor<NTV, KSV, F64, true>) X, a, b, I, P, p, sPr, sPa, tri, gr.spw, partials, Yout,
-                                                           nullptr);
+      TTR_LAUNCH(k_gram_left_factor<NTV, KSV, F32>) X, a, b, I, P, p, sPr, sPa, tri, gr.spw, partials, fscale);
     else
-      TTR_LAUNCH(k_gram_left_factor<NTV, KSV, F64>) X, a, b, I, P, p, sPr, sPa, tri, gr.spw, partials, nullptr,
-                                                     nullptr);
+      TTR_LAUNCH(k_gram_left_factor<NTV, KSV, F64>) X, a, b, I, P, p, sPr, sPa, tri, gr.spw, partials, nullptr);
   });
   return gr.nwg;
 }

@@ -27,6 +27,9 @@ constexpr int kThreadsQR = 256;  // two-sided Jacobi: cheap barriers matter more
 constexpr int kRows = 8;
 constexpr int kWave = 64;
 constexpr double kU = DBL_EPSILON / 2;  // unit roundoff 2^-53
+// A pivoted cut falls off a clear gap when the last kept pivot is at least
+// this many times the largest dropped one (a factor 1e3 in singular values).
+constexpr double kPivGap = 1e6;
 
 // Sums of three values over the wave; every lane gets lane 0's result so
 // that branch decisions taken on them are uniform across the wave.
@@ -378,9 +381,13 @@ __device__ bool chol_inv(double *A, double *Vm, int d, double *kappa, double *lm
 // rank-revealing form: pivots in order perm[0..k), A(i, j) (i >= j, j < k)
 // holds L with G(perm, perm) ~= L L^T; stops once the largest remaining
 // diagonal entry is at most tau times the largest initial one.  Returns k.
-__device__ int pivoted_chol(double *A, int d, double tau, int *perm) {
+// gap (nullable, every thread): the last kept pivot over the largest
+// remaining diagonal entry at the stop (+inf when nothing was dropped); the
+// pivots never grow, so a large ratio separates the kept directions from the
+// dropped ones.
+__device__ int pivoted_chol(double *A, int d, double tau, int *perm, double *gap = nullptr) {
   __shared__ int piv, stop;
-  __shared__ double dmax0;
+  __shared__ double dmax0, pkeep, pdrop;
   for (int i = threadIdx.x; i < d; i += blockDim.x) perm[i] = i;
   double m = 0.0;
   for (int i = threadIdx.x; i < d; i += blockDim.x) m = fmax(m, A[i + d * i]);
@@ -406,6 +413,9 @@ __device__ int pivoted_chol(double *A, int d, double tau, int *perm) {
       if (threadIdx.x == 0) {
         piv = p;
         stop = !(v > tau * dmax0) || p >= d;
+        if (j == 0) pkeep = pdrop = 0.0;
+        if (stop) pdrop = (p < d && v > 0.0) ? v : 0.0;
+        else pkeep = v;
       }
     }
     __syncthreads();
@@ -446,6 +456,7 @@ __device__ int pivoted_chol(double *A, int d, double tau, int *perm) {
     }
     __syncthreads();
   }
+  if (gap) *gap = (k < d && pdrop > 0.0) ? pkeep / pdrop : INFINITY;
   return k;
 }
 
@@ -609,7 +620,20 @@ __device__ void qr_step_body(const QrStepArgs a) {
       }
       return;
     }
-    if (!kap_ok && a.pass <= a.shift_pass) {
+    bool shift_it = !kap_ok && a.pass <= a.shift_pass;
+    if (shift_it && a.pass >= 2) {
+      // A second shifted pass (mixed precision, after the FP32 one) is for a
+      // spectrum graded across the pivoted cut; when the pivots fall off a
+      // clear gap instead (an exactly rank-deficient unfolding such as Y + Y)
+      // the cut drops only null directions and this pass takes it.
+      for (int e = threadIdx.x; e < d * d; e += blockDim.x) A[e] = Bf[e];
+      __syncthreads();
+      double gap;
+      pivoted_chol(A, d, a.tau2, perm, &gap);
+      shift_it = !(gap >= kPivGap);
+      __syncthreads();
+    }
+    if (shift_it) {
       // Shifted CholeskyQR: G + sI = L L^T with s ~ d u trace(G) gives A L^{-T}
       // the singular values sqrt(lambda / (lambda + s)), as the shifted eigen
       // route would, at the cost of one factorization; the next pass refines.
