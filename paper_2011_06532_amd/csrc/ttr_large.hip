@@ -464,8 +464,18 @@ __global__ __launch_bounds__(kLT) void lk_step(LStepArgs a) {
   }
   const double trG = lsum(tp), gmin = -lmax(-glo), gmax = lmax(ghi);
   g1 = lmax(g1);
+  // kappa(G) >= max_j G_jj / min_j G_jj (each G_jj is a Rayleigh quotient):
+  // when that already exceeds 1/tau1 the Cholesky route cannot be taken and
+  // is not tried
+  double gdx = 0.0, gdn = DBL_MAX;
+  for (int j = threadIdx.x; j < d; j += blockDim.x) {
+    gdx = fmax(gdx, A[j + (size_t)d * j]);
+    gdn = fmin(gdn, A[j + (size_t)d * j]);
+  }
+  gdx = lmax(gdx);
+  gdn = -lmax(-gdn);
   __shared__ double Sbuf[kLdsB];
-  const bool ok = lchol(A, d, Sbuf);
+  const bool ok = (gdn > 0.0 && gdx * a.tau1 <= gdn) && lchol(A, d, Sbuf);
   double kappa = 1e300, lmin_lb = 0.0;
   // kappa(G) = kappa(L)^2 >= (max_j L_jj / min_j L_jj)^2 (the diagonal of a
   // triangular matrix holds its eigenvalues): when that already exceeds
