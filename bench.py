@@ -697,6 +697,12 @@ def main():
     if not args.no_batched:
         out["batched"] = bench_batched(h, ttr, torch, args.steps, per_tensor=not args.no_per_tensor)
     if not args.no_large:
+        # a fresh handle: the workspaces the earlier legs grew (materialized
+        # cores, batched plans) go back to the device, so this leg has the
+        # memory a run of its own has (the rank-256 rounding keeps the first
+        # sweep's products when they fit)
+        h.close()
+        h = ttr.Handle(0)
         out["large"] = bench_large(h, ttr, torch, args.steps)
     if not args.no_cpu_baseline:
         log(f"cpu_baseline: oracle on I={args.cpu_sample_I}")

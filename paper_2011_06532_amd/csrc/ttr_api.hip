@@ -99,7 +99,8 @@ constexpr size_t kSlot = (size_t)TTR_RMAX * TTR_RMAX;
 constexpr int kStagesPerCore = 3;
 constexpr int kScalF32 = 16;  // w.scal[16..18]: the scales of an FP32 Gram pass
 struct WS {
-  double *partials, *G, *Ra, *Rb, *Gst[3], *Pa, *Pb, *GU, *Wa, *Wb, *scal, *sigma, *tails, *Tn, *Bst, *tmp, *matA, *matB;
+  double *partials, *G, *Ra, *Rb, *Gst[3], *Pa, *Pb, *GU, *Wa, *Wb, *Fp, *scal, *sigma, *tails, *Tn, *Bst, *tmp, *matA,
+      *matB;
   int *dec;
   double *T(int n) const { return Tn + (size_t)n * kSlot; }
   double *B(int n, int j) const { return Bst + ((size_t)n * kStagesPerCore + j) * kSlot; }
@@ -123,7 +124,7 @@ WS carve(ttr_handle *h, int N, size_t tmp, size_t mat = 0) {
   w.GU = p; p += kSlot;
   w.Wa = p; p += kSlot;
   w.Wb = p; p += kSlot;
-  p += kSlot;  // spare
+  w.Fp = p; p += kSlot;
   w.scal = p; p += 64;
   w.sigma = p; p += (size_t)(N + 1) * TTR_RMAX;
   w.tails = p; p += (size_t)(N + 1);
@@ -461,7 +462,7 @@ template <class SlotFn>
 int qr_by_gram(ttr_handle *h, WS &w, const CoreView &cv, int mode, const Stages &base, int b, SlotFn slot,
                double *Tdst, Factor *f, double **Rout, int *kout, int *passes, double tcond = -1.0,
                double *ratio = nullptr, TruncCtx *tc = nullptr, Prec pr = Prec(), double *mat = nullptr,
-               CoreView *cv_out = nullptr, int *materialized = nullptr) {
+               CoreView *cv_out = nullptr, int *materialized = nullptr, const Stage *gram_left = nullptr) {
   double *R[2] = {w.Ra, w.Rb};
   const double *Rc = nullptr;
   int d = b;
@@ -485,6 +486,9 @@ int qr_by_gram(ttr_handle *h, WS &w, const CoreView &cv, int mode, const Stages 
     if (post) {
       Stages s1 = base;
       s1.nr = 0;
+      // a triangular F with F^T F = P^T P in place of the left factor P: the
+      // same Gram, with the zero half of F skipped
+      if (gram_left && s1.nl == 1) s1.L[0] = *gram_left;
       gnwg = gram(h, w.partials, w.G, cvp, s1, mode, pr.mixed, &f32, w.scal + kScalF32);
       qa.Tpost = base.R[0].S;
       qa.tpr = base.R[0].rows;
@@ -1225,6 +1229,9 @@ int ttr_round(ttr_handle *h, const ttr_tt *X, double tol, int direction, int pre
   // orthonormalization stages of core n with the last one merged into P_n.
   std::vector<int> L(N + 1, 1), sweeps(N, 0);
   double *Pbuf[2] = {w.Pa, w.Pb};
+  // F (upper triangular, F^T F = P^T P) for the next link's first Gram pass
+  Stage fp_stage{};
+  bool have_fp = false;
   const double *Pcur = nullptr;  // merged last left stage (Lprev x dim)
   int Lprev = 1;
   int applies = 0;
@@ -1275,7 +1282,7 @@ int ttr_round(ttr_handle *h, const ttr_tt *X, double tol, int direction, int pre
     CoreView cvm;
     int materialized = 0;
     rc = qr_by_gram(h, w, cv, GRAM_RIGHT, base, b, slot, nullptr, &g, &Rq, &kq, &passes, tcond, nullptr, &tcx, pr,
-                    tfold ? nullptr : w.matA, &cvm, &materialized);
+                    tfold ? nullptr : w.matA, &cvm, &materialized, have_fp ? &fp_stage : nullptr);
     if (rc) return rc;
     const Factor &fn = fac[n + 1];
     TruncArgs ta;
@@ -1307,6 +1314,22 @@ int ttr_round(ttr_handle *h, const ttr_tt *X, double tol, int direction, int pre
     const int Ln = h->dec_host[3];
     L[n + 1] = Ln;
     sweeps[n] = h->dec_host[9];
+    // The next link's first Gram pass, sum_i (P M_i)^T (P M_i), is the same
+    // with any F of F^T F = P^T P in place of P: the upper-triangular F of
+    // the symmetric-norm factorization skips half of the product's k-steps.
+    // (FP64 only: the FP32 pass is bound by its loads, not its products.)
+    have_fp = false;
+    if (!pr.mixed && n + 1 < N - 1 && fac[n + 1].nst == 1 && !fac[n + 1].mat && Ln <= ta.dn) {
+      launch_ptp(h->stream, ta.Pnext, Ln, ta.dn, w.G);
+      launch_sym_factor(h->stream, w.G, ta.dn, w.Fp);
+      fp_stage.S = w.Fp;
+      fp_stage.rows = Ln;  // rows past the rank of P are zero
+      fp_stage.cols = ta.dn;
+      fp_stage.sr = 1;
+      fp_stage.sc = ta.dn;
+      fp_stage.lower = 2;  // upper triangular
+      have_fp = true;
+    }
     // output core n: the same staged chain as the Gram passes, the last
     // refinement stage merged with U_R[:, :L]
     Stages st = materialized ? no_stages() : base;

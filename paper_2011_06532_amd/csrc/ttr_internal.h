@@ -262,4 +262,6 @@ void launch_small_gemm_batched(hipStream_t s, int count, const SmallGemmArgs *ar
 // F (d x d, ld d): upper triangular with F^T F = G (pivoted Cholesky, then a
 // Householder QR of L^T P^T), zero rows past the numerical rank; d <= TTR_RMAX.
 void launch_sym_factor(hipStream_t s, const double *G, int d, double *F);
+// W (a x a) = P^T P for P (p x a, ld p), a, p <= TTR_RMAX.
+void launch_ptp(hipStream_t s, const double *P, int p, int a, double *W);
 void launch_sqrt_scalar(hipStream_t s, const double *in, double *out);

@@ -1060,6 +1060,18 @@ __global__ __launch_bounds__(kThreadsQR) void k_sym_factor(const double *G, int 
   sym_factor_body(G, d, F);
 }
 __global__ __launch_bounds__(kThreads) void k_trunc_step(TruncArgs a) { trunc_step_body(a); }
+// W (a x a) = P^T P for P (p x a, ld p), one workgroup: the Gram of a small
+// left factor (its triangular factor F, F^T F = W, replaces P in a Gram pass).
+__global__ __launch_bounds__(kThreadsQR) void k_ptp(const double *__restrict__ P, int p, int a,
+                                                    double *__restrict__ W) {
+  for (int e = threadIdx.x; e < a * a; e += blockDim.x) {
+    const int r = e % a, c = e / a;
+    double v = 0.0;
+    for (int i = 0; i < p; ++i) v += P[i + (size_t)p * r] * P[i + (size_t)p * c];
+    W[e] = v;
+  }
+}
+
 __global__ void k_small_gemm(const double *A, const double *B, double *C, int m, int k, int n) {
   small_gemm_body(A, B, C, m, k, n);
 }
@@ -1112,6 +1124,9 @@ void launch_small_gemm_batched(hipStream_t s, int count, const SmallGemmArgs *ar
 
 void launch_sym_factor(hipStream_t s, const double *G, int d, double *F) {
   hipLaunchKernelGGL(k_sym_factor, dim3(1), dim3(kThreadsQR), 0, s, G, d, F);
+}
+void launch_ptp(hipStream_t s, const double *P, int p, int a, double *W) {
+  hipLaunchKernelGGL(k_ptp, dim3(1), dim3(kThreadsQR), 0, s, P, p, a, W);
 }
 void launch_sqrt_scalar(hipStream_t s, const double *in, double *out) {
   hipLaunchKernelGGL(k_sqrt_scalar, dim3(1), dim3(64), 0, s, in, out);
