@@ -20,8 +20,11 @@
  * Ownership.  The library never frees caller memory and keeps no caller
  * pointer after a call returns.  It owns a device workspace attached to the
  * handle (allocated with hipMalloc on first need, grown on demand, released by
- * ttr_destroy).  A handle is bound to one device and one stream; use one
- * handle per host thread.
+ * ttr_destroy).  A rounding at ranks above 64 also keeps the products
+ * C_n = X_n T_{n+1} of its orthonormalization sweep for the truncation sweep
+ * (about the size of X more device memory, held like the workspace) when
+ * that allocation succeeds, and forms them again when it does not.  A handle
+ * is bound to one device and one stream; use one handle per host thread.
  *
  * Errors.  Every call returns TTR_OK (0) or a TTR_ERR_* code and records a
  * message readable with ttr_last_error().  Argument errors are detected on the
@@ -101,7 +104,7 @@ int ttr_set_stream(ttr_handle *h, void *stream);
  * the current workspaces to the allocator they came from first, so memory is
  * never freed through the wrong one.  Memory is requested when a call needs
  * more than the handle holds and kept until the next larger request, this
- * call, or ttr_destroy.  (rocBLAS keeps its own small internal workspace.)
+ * call, or ttr_destroy.
  * Errors: TTR_ERR_INVALID_ARG if exactly one of alloc / free is NULL. */
 int ttr_set_allocator(ttr_handle *h, void *(*alloc)(size_t bytes, void *ctx), void (*free)(void *ptr, void *ctx),
                       void *ctx);
