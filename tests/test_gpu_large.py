@@ -241,3 +241,20 @@ def test_round_hadamard_implicit(ttr, h, prec, ra, rb):
     with pytest.raises(ttr.TTRError) as e:
         h.round_hadamard(gA, gB, 1e-6, "LRL", prec)
     assert e.value.code == 7
+
+
+@pytest.mark.parametrize("N", [1, 2, 3])
+def test_round_hadamard_implicit_short_trains(ttr, h, N):
+    # the boundary cases of the implicit product: N = 1 (the product itself),
+    # N = 2 (one link: only the last core is formed), N = 3, at tol 0 and 1e-3
+    rng = np.random.default_rng(940 + N)
+    I = [23, 17, 29][:N]
+    A = rand_tt(rng, I, [5, 4][: N - 1])
+    B = rand_tt(rng, I, [3, 6][: N - 1])
+    X = O.hadamard(A, B)
+    for tol in (0.0, 1e-3):
+        print(f"implicit Hadamard rounding N={N} tol={tol}", flush=True)
+        got = h.round_hadamard(ttr.TT.from_numpy(A), ttr.TT.from_numpy(B), tol).to_numpy()
+        ref = O.round_tt(X, tol, "RLR")
+        assert O.ranks(got) == O.ranks(ref), (O.ranks(got), O.ranks(ref))
+        assert O.diff_norm(got, ref) <= 1e-10 * O.norm_ortho(ref)
