@@ -230,3 +230,31 @@ def test_round_tol0_rank_deficient_against_oracle(ttr, h, direction, rank):
     assert O.ranks(ref) != num  # the oracle keeps rounding-level directions
     assert O.ranks(Yg) == num, (O.ranks(Yg), num, O.ranks(ref))
     assert O.diff_norm(Yg, ref) <= 1e-12 * O.norm_ortho(ref)
+
+
+@pytest.mark.parametrize("direction", ["RLR", "LRL"])
+def test_round_long_train_stats(ttr, h, direction):
+    # N = 70 cores: more links than the per-link statistics hold (64); links
+    # past that are not reported and nothing past the statistics is written
+    # (the handle keeps working)
+    print(f"round N=70 {direction}", flush=True)
+    rng = np.random.default_rng(230)
+    N = 70
+    I = [2] * N
+    Yc = rand_tt(rng, I, [2] * (N - 1))
+    X = O.add(1.0, Yc, 1.0, rand_tt(rng, I, [2] * (N - 1), scale=1e-3))
+    got = h.round(ttr.TT.from_numpy(X), 1e-2, direction).to_numpy()
+    ref, info = O.round_tt(X, 1e-2, direction, return_info=True)
+    assert O.ranks(got) == O.ranks(ref)
+    assert O.diff_norm(got, ref) <= 1e-10 * O.norm_ortho(ref)
+    st = h.round_stats()
+    assert len(st["sigmas"]) == 64 and len(st["tail2"]) == 64
+    for l in range(64):
+        s_ref = np.asarray(info["sigmas"][l])
+        s_gpu = np.asarray(st["sigmas"][l])
+        k = min(len(s_gpu), len(s_ref))
+        if k:
+            big = s_ref[:k] > 1e-6 * s_ref[0]
+            assert np.allclose(s_gpu[:k][big], s_ref[:k][big], rtol=1e-9), l
+    # the handle still works
+    check_round(ttr, h, rand_tt(rng, [20, 30, 25], [4, 5]), 1e-3, direction)
