@@ -174,3 +174,31 @@ def test_batched_workspace_through_torch_allocator(ttr):
     hd.set_allocator(None, None)
     assert not live  # and handed back
     hd.close()
+
+
+def test_batched_replan_while_previous_batch_runs(ttr):
+    # batch A is enqueued and, without waiting, a different batch B is
+    # submitted on the same handle under the torch allocator: building B's plan
+    # frees A's plan, which must wait for A's replay first.  Both results
+    # against the oracle.
+    import torch
+    print("batched re-plan while a replay runs", flush=True)
+    XA, rA = batch_inputs(12, 200, start=40)
+    XB, rB = batch_inputs(9, 150, start=60)
+    tol = synth.TOL[3]
+    hd = ttr.Handle(0)
+    hd.use_torch_allocator()
+    gA = [ttr.TT.from_numpy(X) for X in XA]
+    gB = [ttr.TT.from_numpy(X) for X in XB]
+    YA, ranksA = hd.round_batched(gA, tol)   # asynchronous
+    YB, ranksB = hd.round_batched(gB, tol)   # a new plan at once
+    torch.cuda.synchronize()
+    ttr.Handle.sync_ranks(YA, ranksA)
+    ttr.Handle.sync_ranks(YB, ranksB)
+    for Y, r in zip(YA, rA):
+        assert Y.R == [1] + r + [1]
+    for Y, r in zip(YB, rB):
+        assert Y.R == [1] + r + [1]
+    check_against_oracle(XA, [Y.to_numpy() for Y in YA], tol, 1e-10)
+    check_against_oracle(XB, [Y.to_numpy() for Y in YB], tol, 1e-10)
+    hd.close()
