@@ -210,15 +210,14 @@ __device__ bool lchol(double *A, int d, double *S) {
 // X = L^{-1} (k x k lower, ld d) for the lower-triangular L in A (ld d).
 // The diagonal 16-blocks are inverted by one wave each in registers (forward
 // substitution on all columns at once, rows broadcast lane by lane); then
-// block row i: X(i, 0:i) = -X_ii (L(i, 0:i) X(0:i, 0:i)), 32 columns at a
-// time with the block row of L and the column panel of X staged in LDS.
-constexpr int kInvP = 32;  // columns of X per staged panel
+// blocks are paired and doubled, 16 -> 32 -> ... -> k: for L = [L00 0; L10
+// L11] with X00, X11 known, X10 = -X11 (L10 X00), two products on the matrix
+// cores per level.  W = L10 X00 is kept (transposed) in the strictly upper
+// block X(B0, B1), which is cleared after the level, so X stays lower
+// triangular between levels and the products skip its zero k-steps.
+typedef double lv4 __attribute__((ext_vector_type(4)));
 __device__ void linv(const double *A, double *X, int k, int d) {
-  __shared__ double Lr[kNB * kLMax];     // L(i0 + r, m) at [m * kNB + r]
-  __shared__ double Xp[kLMax * kInvP];   // X(m, c0 + c) at [m * kInvP + c]
-  __shared__ double Tp[kNB * kInvP];     // T(r, c) at [r * kInvP + c]
-  __shared__ double Xd[kNB * kNB];       // X_ii(r, t) at [r * kNB + t]
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int nblk = (k + kNB - 1) / kNB;
   for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
     const int r = e % k, c = e / k;
@@ -252,38 +251,51 @@ __device__ void linv(const double *A, double *X, int k, int d) {
         if (c <= r) X[(b0 + r) + (size_t)d * (b0 + c)] = x[c];
   }
   __syncthreads();
-  const int tr = threadIdx.x & (kNB - 1), tcl = threadIdx.x / kNB;  // 16 rows x 64 columns of threads
-  for (int bi = 1; bi < nblk; ++bi) {
-    const int i0 = bi * kNB, ni = min(kNB, k - i0);
-    for (int e = threadIdx.x; e < kNB * i0; e += blockDim.x) {
-      const int r = e % kNB, m = e / kNB;
-      Lr[e] = (r < ni) ? A[(i0 + r) + (size_t)d * m] : 0.0;
+  const int g = lane >> 4, jj = lane & 15;
+  auto lget = [&](int r, int c) { return (r < k && c < k) ? A[r + (size_t)d * c] : 0.0; };
+  auto xget = [&](int r, int c) { return (r < k && c < k) ? X[r + (size_t)d * c] : 0.0; };
+  for (int m = kNB; m < k; m *= 2) {
+    const int tm = m / 16;                          // 16-tiles per block side
+    const int npair = (k - m + 2 * m - 1) / (2 * m);  // pairs whose B1 = [i0 + m, i0 + 2m) is not empty
+    const int ntile = npair * tm * tm;
+    // W (B1 rows x B0 columns) = L(B1, B0) X(B0, B0): tile (tr, tc) of W
+    for (int tix = wave; tix < ntile; tix += nw) {
+      const int pr = tix / (tm * tm), tr = (tix % (tm * tm)) / tm, tc = tix % tm;
+      const int i0 = 2 * m * pr, b1 = i0 + m;
+      if (b1 + 16 * tr >= k) continue;
+      lv4 acc = {0.0, 0.0, 0.0, 0.0};
+      // X(B0, B0)(kk, c) = 0 for kk < c: k-steps from the tile's first column
+#pragma unroll 4
+      for (int ks = 4 * tc; ks < m / 4; ++ks)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(lget(b1 + 16 * tr + jj, i0 + 4 * ks + g),
+                                                   xget(i0 + 4 * ks + g, i0 + 16 * tc + jj), acc, 0, 0, 0);
+      // register r: W(16 tr + 4 r + g, 16 tc + jj), kept as X(i0 + 16 tc + jj, b1 + 16 tr + 4 r + g)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (b1 + 16 * tr + 4 * r + g < k) X[(i0 + 16 * tc + jj) + (size_t)d * (b1 + 16 * tr + 4 * r + g)] = acc[r];
     }
-    for (int e = threadIdx.x; e < kNB * kNB; e += blockDim.x) {
-      const int r = e / kNB, t = e % kNB;
-      Xd[e] = (r < ni && t <= r) ? X[(i0 + r) + (size_t)d * (i0 + t)] : 0.0;
+    __syncthreads();
+    // X(B1, B0) = -X(B1, B1) W
+    for (int tix = wave; tix < ntile; tix += nw) {
+      const int pr = tix / (tm * tm), tr = (tix % (tm * tm)) / tm, tc = tix % tm;
+      const int i0 = 2 * m * pr, b1 = i0 + m;
+      if (b1 + 16 * tr >= k) continue;
+      lv4 acc = {0.0, 0.0, 0.0, 0.0};
+      // X(B1, B1)(r, kk) = 0 for kk > r: k-steps up to the tile's last row
+#pragma unroll 4
+      for (int ks = 0; ks < 4 * (tr + 1); ++ks)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xget(b1 + 16 * tr + jj, b1 + 4 * ks + g),
+                                                   xget(i0 + 16 * tc + jj, b1 + 4 * ks + g), acc, 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (b1 + 16 * tr + 4 * r + g < k) X[(b1 + 16 * tr + 4 * r + g) + (size_t)d * (i0 + 16 * tc + jj)] = -acc[r];
     }
-    for (int c0 = 0; c0 < i0; c0 += kInvP) {
-      const int nc = min(kInvP, i0 - c0);
-      __syncthreads();  // Lr / Xd written; the previous panel's readers are done
-      for (int e = threadIdx.x; e < i0 * kInvP; e += blockDim.x) {
-        const int m = e % i0, c = e / i0;
-        Xp[m * kInvP + c] = (c < nc) ? X[m + (size_t)d * (c0 + c)] : 0.0;
-      }
-      __syncthreads();
-      // T(r, c) = sum_{m >= c0 + c} L(i0 + r, m) X(m, c0 + c)  (X lower triangular)
-      if (tcl < kInvP) {
-        double acc = 0.0;
-        for (int m = c0 + tcl; m < i0; ++m) acc += Lr[m * kNB + tr] * Xp[m * kInvP + tcl];
-        Tp[tr * kInvP + tcl] = acc;
-      }
-      __syncthreads();
-      // X(i0 + r, c0 + c) = -sum_{t <= r} X_ii(r, t) T(t, c)
-      if (tcl < nc && tr < ni) {
-        double acc = 0.0;
-        for (int t = 0; t <= tr; ++t) acc += Xd[tr * kNB + t] * Tp[t * kInvP + tcl];
-        X[(i0 + tr) + (size_t)d * (c0 + tcl)] = -acc;
-      }
+    __syncthreads();
+    // clear the kept W: X(B0, B1) back to the zero upper part
+    for (int e = threadIdx.x; e < npair * m * m; e += blockDim.x) {
+      const int pr = e / (m * m), r = (e % (m * m)) % m, c = (e % (m * m)) / m;
+      const int i0 = 2 * m * pr;
+      if (i0 + m + c < k) X[(i0 + r) + (size_t)d * (i0 + m + c)] = 0.0;
     }
     __syncthreads();
   }
@@ -805,7 +817,6 @@ typedef double ld4 __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(kJT) void lk_jacobi_round(double *__restrict__ A, double *__restrict__ U, int b, int k,
                                                        int nbp, int round, const double *__restrict__ thr,
                                                        int *__restrict__ flags, int sweep) {
-  if (sweep > 0 && flags[sweep - 1] == 0) return;
   // hA: the 2 kJW columns in the within-block steps, then the exchange buffers
   // of the cross steps ([2][kJW][kLMax]); hJ likewise for J, then J itself
   // (hJ[column][row])
@@ -818,6 +829,7 @@ __global__ __launch_bounds__(kJT) void lk_jacobi_round(double *__restrict__ A, d
   const int pr = 4 * wv + g;  // the pair of this 16-lane row
   const double tol2 = thr[0] * thr[0], floor2 = thr[1];
   auto gcol = [&](int l) { return l < kJW ? P * kJW + l : Q * kJW + (l - kJW); };
+  if (sweep > 0 && flags[sweep - 1] == 0) return;
   int rotated = 0;
   double ap[kJR], aq[kJR], jp[2], jq[2];
   if (round == 0) {
