@@ -124,6 +124,7 @@ __device__ inline double bcast(double v, int lane) {
 // by lane), the rows below solve against it in parallel (one row per
 // thread), and the trailing lower triangle takes the panel's rank-16 update
 // with the panel held in LDS (S, kLdsB doubles).  Three barriers per panel.
+typedef double lv4 __attribute__((ext_vector_type(4)));
 __device__ bool lchol(double *A, int d, double *S) {
   __shared__ double Dk[kNB * kNB];
   __shared__ int okf;
@@ -183,19 +184,33 @@ __device__ bool lchol(double *A, int d, double *S) {
       }
     }
     __syncthreads();
-    // trailing update of the lower triangle: A(r, c) -= L(r, panel) L(c, panel)^T
+    // trailing update of the lower triangle, A(r, c) -= L(r, panel) L(c, panel)^T,
+    // on the matrix cores: 16 x 16 tiles (ti >= tj) of the trailing matrix,
+    // each the transposed product L(tj rows) (-L(ti rows))^T added to its
+    // transposed tile, so that the 16 lanes of a row group hold 16
+    // consecutive rows of one column (coalesced loads and stores)
     {
-      const int tr = threadIdx.x & 31, tc = threadIdx.x >> 5, nc = blockDim.x >> 5;
-      for (int c = k1 + tc; c < d; c += nc) {
-        double pc[kNB];
+      const int g = lane >> 4, jj = lane & 15, nw = blockDim.x >> 6;
+      const int T = (d - k1 + 15) / 16;
+      for (int tix = wave; tix < T * T; tix += nw) {
+        const int ti = tix / T, tj = tix % T;
+        if (tj > ti) continue;
+        const int row = k1 + 16 * ti + jj;
+        lv4 acc;
 #pragma unroll
-        for (int t = 0; t < kNB; ++t) pc[t] = S[(c - k1) * (kNB + 1) + t];
-        for (int r = c + tr; r < d; r += 32) {
-          const double *pr = S + (r - k1) * (kNB + 1);
-          double acc = 0.0;
+        for (int r = 0; r < 4; ++r) {
+          const int col = k1 + 16 * tj + 4 * r + g;
+          acc[r] = (row < d && col < d) ? A[row + (size_t)d * col] : 0.0;
+        }
 #pragma unroll
-          for (int t = 0; t < kNB; ++t) acc += pr[t] * pc[t];
-          A[r + (size_t)d * c] -= acc;
+        for (int ks = 0; ks < kNB / 4; ++ks)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(S[(16 * tj + jj) * (kNB + 1) + 4 * ks + g],
+                                                     -S[(16 * ti + jj) * (kNB + 1) + 4 * ks + g], acc, 0, 0, 0);
+        // register r: element (row, k1 + 16 tj + 4 r + g)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int col = k1 + 16 * tj + 4 * r + g;
+          if (row < d && col < d && row >= col) A[row + (size_t)d * col] = acc[r];
         }
       }
     }
@@ -215,7 +230,6 @@ __device__ bool lchol(double *A, int d, double *S) {
 // cores per level.  W = L10 X00 is kept (transposed) in the strictly upper
 // block X(B0, B1), which is cleared after the level, so X stays lower
 // triangular between levels and the products skip its zero k-steps.
-typedef double lv4 __attribute__((ext_vector_type(4)));
 __device__ void linv(const double *A, double *X, int k, int d) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int nblk = (k + kNB - 1) / kNB;
