@@ -107,9 +107,12 @@ struct WS {
 };
 // tmp: staging for an explicit output core; mat: each of the two buffers that
 // hold materialized cores of ill-conditioned factorizations
+// every segment of the workspace starts on a 256-byte boundary: the sizes
+// that are not multiples of 32 doubles are rounded up
+size_t r32(size_t n) { return (n + 31) / 32 * 32; }
 size_t ws_doubles(int N, size_t tmp, size_t mat = 0) {
-  return (size_t)TTR_MAXWG * kSlot + 12 * kSlot + 64 + (size_t)(N + 1) * (TTR_RMAX + 1) +
-         (size_t)(N + 2) * (1 + kStagesPerCore) * kSlot + tmp + 2 * mat + 64;
+  return (size_t)TTR_MAXWG * kSlot + 12 * kSlot + 64 + (size_t)(N + 1) * TTR_RMAX + r32(N + 1) +
+         (size_t)(N + 2) * (1 + kStagesPerCore) * kSlot + r32(tmp) + 2 * r32(mat) + 64;
 }
 WS carve(ttr_handle *h, int N, size_t tmp, size_t mat = 0) {
   WS w;
@@ -127,12 +130,12 @@ WS carve(ttr_handle *h, int N, size_t tmp, size_t mat = 0) {
   w.Fp = p; p += kSlot;
   w.scal = p; p += 64;
   w.sigma = p; p += (size_t)(N + 1) * TTR_RMAX;
-  w.tails = p; p += (size_t)(N + 1);
+  w.tails = p; p += r32(N + 1);
   w.Tn = p; p += (size_t)(N + 2) * kSlot;
   w.Bst = p; p += (size_t)(N + 2) * kStagesPerCore * kSlot;
-  w.tmp = p; p += tmp;
-  w.matA = mat ? p : nullptr; p += mat;
-  w.matB = mat ? p : nullptr; p += mat;
+  w.tmp = p; p += r32(tmp);
+  w.matA = mat ? p : nullptr; p += r32(mat);
+  w.matB = mat ? p : nullptr; p += r32(mat);
   w.dec = h->dec_dev;
   return w;
 }
@@ -600,10 +603,11 @@ int orth_sweep(ttr_handle *h, WS &w, const Seq &S, std::vector<int> &k, std::vec
       Stages st = no_stages();
       for (int j = 0; j < fac[n].nst; ++j) st.L[st.nl++] = st_trans(w.B(n, j), fac[n].dim[j + 1], fac[n].dim[j]);
       if (n < N - 1 && !materialized) st.R[st.nr++] = st_plain(w.T(n + 1), cv.eb(), k[n + 1]);
-      apply(h, materialized ? cvm : cv, st, w.tmp, S.rev);
+      // in place (Out is the source) through scratch, else straight into Out
       const int pn = S.phys(n);
-      const size_t cnt = (size_t)kn * cv.I * k[n + 1];
-      HIPCHK(hipMemcpyAsync(Out->core[pn], w.tmp, cnt * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+      const bool direct = Out->core[pn] != cv.X;
+      apply(h, materialized ? cvm : cv, st, direct ? Out->core[pn] : w.tmp, S.rev);
+      if (!direct) launch_copy(h->stream, w.tmp, (long long)kn * cv.I * k[n + 1], Out->core[pn]);
     }
   }
   return TTR_OK;
@@ -1006,9 +1010,7 @@ int ttr_orthogonalize(ttr_handle *h, ttr_tt *X, int side, int prec) {
   Stages st = no_stages();
   st.R[st.nr++] = st_plain(w.T(1), cv.eb(), k[1]);
   apply(h, cv, st, w.tmp, S.rev);
-  const int p0 = S.phys(0);
-  HIPCHK(hipMemcpyAsync(X->core[p0], w.tmp, (size_t)cv.I * k[1] * sizeof(double), hipMemcpyDeviceToDevice,
-                        h->stream));
+  launch_copy(h->stream, w.tmp, (long long)cv.I * k[1], X->core[S.phys(0)]);
   HIPCHK(hipStreamSynchronize(h->stream));
   HIPCHK(hipGetLastError());
   for (int l = 0; l <= N; ++l) {
@@ -1031,11 +1033,7 @@ namespace {
 int round_explicit_small(ttr_handle *h, const ttr_tt *X, double tol, int rev, int prec, ttr_tt *Y, double *norm_out) {
   const int N = X->N;
   int rc;
-  for (int n = 0; n < N; ++n) {
-    HIPCHK(hipMemcpyAsync(Y->core[n], X->core[n], (size_t)X->R[n] * X->I[n] * X->R[n + 1] * sizeof(double),
-                          hipMemcpyDeviceToDevice, h->stream));
-    Y->R[n] = X->R[n];
-  }
+  for (int n = 0; n < N; ++n) Y->R[n] = X->R[n];
   Y->R[N] = 1;
   const size_t tmp = max_core(X);
   if ((rc = ensure_ws(h, ws_doubles(N, tmp, tmp) * sizeof(double)))) return rc;
@@ -1043,19 +1041,19 @@ int round_explicit_small(ttr_handle *h, const ttr_tt *X, double tol, int rev, in
   if ((rc = reset_dec(h))) return rc;
   Prec pr;
   pr.mixed = (prec == TTR_MIXED);
+  const Seq SX{X, rev};
   const Seq S{Y, rev};
   std::vector<int> k;
   std::vector<Factor> fac;
   int passes = 0, applies = 0;
-  // sweep 1: orthonormal cores written into Y (the first core absorbs T_2)
-  if ((rc = orth_sweep(h, w, S, k, fac, Y, &passes, nullptr, pr))) return rc;
+  // sweep 1: the orthonormal cores of X written into Y (the first core
+  // absorbs T_2); X is only read
+  if ((rc = orth_sweep(h, w, SX, k, fac, Y, &passes, nullptr, pr))) return rc;
   {
-    const CoreView cv = S.view(0);
+    const CoreView cv = SX.view(0);
     Stages st = no_stages();
     st.R[st.nr++] = st_plain(w.T(1), cv.eb(), k[1]);
-    apply(h, cv, st, w.tmp, S.rev);
-    HIPCHK(hipMemcpyAsync(Y->core[S.phys(0)], w.tmp, (size_t)cv.I * k[1] * sizeof(double), hipMemcpyDeviceToDevice,
-                          h->stream));
+    apply(h, cv, st, Y->core[S.phys(0)], S.rev);
     ++applies;
   }
   for (int l = 0; l <= N; ++l) Y->R[rev ? N - l : l] = k[l];
@@ -1124,8 +1122,7 @@ int round_explicit_small(ttr_handle *h, const ttr_tt *X, double tol, int rev, in
     st.R[st.nr++] = st_plain(w.GU, ta.d, Ln);
     apply(h, materialized ? cvm : cv, st, w.tmp, S.rev);
     const int zr = (n > 0) ? Lprev : cv.ea();
-    HIPCHK(hipMemcpyAsync(Y->core[S.phys(n)], w.tmp, (size_t)zr * cv.I * Ln * sizeof(double),
-                          hipMemcpyDeviceToDevice, h->stream));
+    launch_copy(h->stream, w.tmp, (long long)zr * cv.I * Ln, Y->core[S.phys(n)]);
     ++applies;
     Pcur = ta.Pnext;
     Lprev = Ln;
@@ -1136,8 +1133,7 @@ int round_explicit_small(ttr_handle *h, const ttr_tt *X, double tol, int rev, in
     Stages st = no_stages();
     st.L[st.nl++] = st_plain(Pcur, Lprev, cv.ea());
     apply(h, cv, st, w.tmp, S.rev);
-    HIPCHK(hipMemcpyAsync(Y->core[S.phys(n)], w.tmp, (size_t)Lprev * cv.I * cv.eb() * sizeof(double),
-                          hipMemcpyDeviceToDevice, h->stream));
+    launch_copy(h->stream, w.tmp, (long long)Lprev * cv.I * cv.eb(), Y->core[S.phys(n)]);
     ++applies;
   }
   HIPCHK(hipGetLastError());

@@ -49,6 +49,9 @@ void launch_add(hipStream_t s, int n, int N, double alpha, double beta, const do
                 const double *Y, int ry0, int ry1, long long I, double *Z);
 void launch_hadamard(hipStream_t s, const double *X, int rx0, int rx1, const double *Y, int ry0, int ry1,
                      long long I, double *Z);
+// Y = X for n doubles on stream s (16-byte loads, streaming stores; a plain
+// device copy when a pointer is not 16-byte aligned).
+void launch_copy(hipStream_t s, const double *X, long long n, double *Y);
 // Y = X x_2 A for one core (a x I x b): A banded (kl, ku), band storage
 // A(i, j) = AB[(ku + i - j) + (kl + ku + 1) j].  a <= 4096.
 void launch_kron_apply(hipStream_t s, const double *X, int r0, int r1, long long I, const double *AB, int kl, int ku,

@@ -1408,8 +1408,7 @@ int orth_sweep_large(Large &L, const ttr_tt *X, int rev, int prec, std::vector<i
       const int p = phys(n);
       L.left(cur, L.B[n][pass - 1], cur.ea(), 1, k[n], L.tB == cur.X ? L.tA : L.tB, fac[n].stri[pass - 1]);
       const double *src = (L.tB == cur.X) ? L.tA : L.tB;
-      TTR_HIPCHK(hipMemcpyAsync(out->core[p], src, (size_t)k[n] * v.I * k[n + 1] * sizeof(double),
-                                hipMemcpyDeviceToDevice, h->stream));
+      launch_copy(h->stream, src, (long long)k[n] * v.I * k[n + 1], out->core[p]);
       ++L.applies;
     }
   }
@@ -1477,8 +1476,7 @@ int round_large_with(Large &L, ttr_handle *h, const ttr_tt *X, double tol, int d
   if (ex) {
     // ---- sweep 1, explicit: Y <- X, orthonormal cores written into Y ----
     for (int n = 0; n < N; ++n) {
-      TTR_HIPCHK(hipMemcpyAsync(Y->core[n], X->core[n], (size_t)X->R[n] * X->I[n] * X->R[n + 1] * sizeof(double),
-                                hipMemcpyDeviceToDevice, h->stream));
+      launch_copy(h->stream, X->core[n], (long long)X->R[n] * X->I[n] * X->R[n + 1], Y->core[n]);
       Y->R[n] = X->R[n];
     }
     Y->R[N] = 1;
@@ -1486,8 +1484,7 @@ int round_large_with(Large &L, ttr_handle *h, const ttr_tt *X, double tol, int d
     const int p0 = phys(0);
     const LView v0{Y->core[p0], Y->I[p0], (int)Y->R[p0], (int)Y->R[p0 + 1], rev};
     L.right(v0, L.T[1], 1, v0.eb(), k[1], fac[1].tri, L.tC);
-    TTR_HIPCHK(hipMemcpyAsync(Y->core[p0], L.tC, (size_t)Y->I[p0] * k[1] * sizeof(double), hipMemcpyDeviceToDevice,
-                              h->stream));
+    launch_copy(h->stream, L.tC, (long long)Y->I[p0] * k[1], Y->core[p0]);
     for (int l = 0; l <= N; ++l) Y->R[rev ? N - l : l] = k[l];
   } else {
     // ---- sweep 1: orthonormalization with implicit factors ----
@@ -1615,8 +1612,7 @@ int round_large_with(Large &L, ttr_handle *h, const ttr_tt *X, double tol, int d
     // output core n: Y_n(i) = E(i) GU (explicit: through tC, Y_n is read)
     if (ex) {
       L.right(E, GU, 1, dq, Ln, 0, L.tC);
-      TTR_HIPCHK(hipMemcpyAsync(Y->core[phys(n)], L.tC, (size_t)E.ea() * E.I * Ln * sizeof(double),
-                                hipMemcpyDeviceToDevice, h->stream));
+      launch_copy(h->stream, L.tC, (long long)E.ea() * E.I * Ln, Y->core[phys(n)]);
     } else {
       L.right(E, GU, 1, dq, Ln, 0, Y->core[phys(n)]);
     }
@@ -1629,8 +1625,7 @@ int round_large_with(Large &L, ttr_handle *h, const ttr_tt *X, double tol, int d
     // last core: P Y_N
     const LView cur = yview(N - 1);
     L.left(cur, Pcur, 1, Lprev, Lprev, L.tC);
-    TTR_HIPCHK(hipMemcpyAsync(Y->core[phys(N - 1)], L.tC, (size_t)Lprev * cur.I * cur.eb() * sizeof(double),
-                              hipMemcpyDeviceToDevice, h->stream));
+    launch_copy(h->stream, L.tC, (long long)Lprev * cur.I * cur.eb(), Y->core[phys(N - 1)]);
     ++L.applies;
   } else {
     // last core: P F_{nst-1}^T .. F_1^T M_N
@@ -1681,8 +1676,7 @@ int ttr_orthogonalize_large(ttr_handle *h, ttr_tt *X, int side) {
   const int p0 = rev ? N - 1 : 0;
   const LView v{X->core[p0], X->I[p0], (int)X->R[p0], (int)X->R[p0 + 1], rev};
   L.right(v, L.T[1], 1, v.eb(), k[1], fac[1].tri, L.tC);
-  TTR_HIPCHK(hipMemcpyAsync(X->core[p0], L.tC, (size_t)X->I[p0] * k[1] * sizeof(double), hipMemcpyDeviceToDevice,
-                            h->stream));
+  launch_copy(h->stream, L.tC, (long long)X->I[p0] * k[1], X->core[p0]);
   TTR_HIPCHK(hipStreamSynchronize(h->stream));
   TTR_HIPCHK(hipGetLastError());
   for (int l = 0; l <= N; ++l) {

@@ -110,6 +110,21 @@ __global__ void k_add_pairs(int n, int N, double alpha, double beta, const doubl
   }
 }
 
+// Device copy of n doubles (a core written back from scratch): 16-byte loads
+// and streaming stores over the pairs, the odd last element by one thread.
+// Both pointers are 16-byte aligned (checked by the launcher).
+__global__ __launch_bounds__(kThreads) void k_copy_pairs(const double *__restrict__ X, long long n,
+                                                         double *__restrict__ Y) {
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  const d2 *X2 = reinterpret_cast<const d2 *>(X);
+  d2 *Y2 = reinterpret_cast<d2 *>(Y);
+  const long long np = n / 2;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < np; e += stride)
+    __builtin_nontemporal_store(X2[e], &Y2[e]);
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) Y[n - 1] = X[n - 1];
+}
+
 // ---------------------------------------------------------------------------
 // Hadamard: Z(ax*ry0 + ay, i, bx*ry1 + by) = X(ax, i, bx) * Y(ay, i, by);
 // output column b = bx*ry1 + by per blockIdx.y.
@@ -519,6 +534,17 @@ void launch_add(hipStream_t s, int n, int N, double alpha, double beta, const do
   const long long bx = std::min((colsz + kThreads - 1) / kThreads, 4096LL);
   hipLaunchKernelGGL(k_add, dim3((unsigned)std::max(bx, 1LL), (unsigned)zr1), dim3(kThreads), 0, s, n, N, alpha, beta,
                      X, rx0, rx1, Y, ry0, ry1, (int)I, Z);
+}
+
+void launch_copy(hipStream_t s, const double *X, long long n, double *Y) {
+  if (n <= 0) return;
+  if ((uintptr_t)X % 16 != 0 || (uintptr_t)Y % 16 != 0) {
+    (void)hipMemcpyAsync(Y, X, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s);
+    return;
+  }
+  // about eight pairs per thread, at most 8192 workgroups
+  const long long bx = std::min((n / 2 + 8LL * kThreads - 1) / (8LL * kThreads), 8192LL);
+  hipLaunchKernelGGL(k_copy_pairs, dim3((unsigned)std::max(bx, 1LL)), dim3(kThreads), 0, s, X, n, Y);
 }
 
 void launch_kron_apply(hipStream_t s, const double *X, int r0, int r1, long long I, const double *AB, int kl, int ku,
