@@ -48,30 +48,93 @@ constexpr double kTau2 = 1e-12;
 
 __device__ inline bool lfinite(double x) { return x == x && fabs(x) <= DBL_MAX; }
 
+// Block-wide sum and maximum: a butterfly within each wave (every lane ends
+// with the same value), then the wave results added in wave order, so every
+// thread returns the same value.
 __device__ double lsum(double v) {
-  __shared__ double red[kLT];
-  red[threadIdx.x] = v;
+  __shared__ double part[kLT / 64];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-    __syncthreads();
-  }
-  const double r = red[0];
+  double r = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r += part[w];
   __syncthreads();
   return r;
 }
 
 __device__ double lmax(double v) {
-  __shared__ double red[kLT];
-  red[threadIdx.x] = v;
+  __shared__ double part[kLT / 64];
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-    if (threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
-    __syncthreads();
-  }
-  const double r = red[0];
+  double r = part[0];
+  for (int w = 1; w < (int)(blockDim.x >> 6); ++w) r = fmax(r, part[w]);
   __syncthreads();
   return r;
+}
+
+// A (d x d, ld d) = the symmetric matrix whose lower triangle is that of G:
+// each wave reads whole columns of G from the diagonal down (all its loads of
+// a column in flight at once) and writes them and their mirror.  Returns true
+// in every thread when an entry read was not finite.
+__device__ bool lload_sym(const double *__restrict__ G, int d, double *__restrict__ A) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  int bad = 0;
+  for (int c = wave; c < d; c += nw) {
+    double g[kLMax / 64];
+#pragma unroll
+    for (int m = 0; m < kLMax / 64; ++m) {
+      const int r = c + lane + 64 * m;
+      g[m] = (r < d) ? G[r + (size_t)d * c] : 0.0;
+    }
+#pragma unroll
+    for (int m = 0; m < kLMax / 64; ++m) {
+      const int r = c + lane + 64 * m;
+      if (r < d) {
+        if (!lfinite(g[m])) bad = 1;
+        A[r + (size_t)d * c] = g[m];
+        A[c + (size_t)d * r] = g[m];
+      }
+    }
+  }
+  return __syncthreads_or(bad) != 0;
+}
+
+// Y(j, i) = X(i, j) for X n x m (ld ldx) into Y (ld ldy): X read in order,
+// four loads in flight per thread.
+__device__ void ltrans(const double *__restrict__ X, int n, int m, int ldx, double *__restrict__ Y, int ldy) {
+  const int tot = n * m, nt = blockDim.x;
+  for (int e0 = threadIdx.x; e0 < tot; e0 += 4 * nt) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u * nt;
+      v[u] = (e < tot) ? X[e % n + (size_t)ldx * (e / n)] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u * nt;
+      if (e < tot) Y[e / n + (size_t)ldy * (e % n)] = v[u];
+    }
+  }
+}
+
+// Y = X for X n x m (ld ldx) into Y (ld ldy), four loads in flight per thread.
+__device__ void lcopy(const double *__restrict__ X, int n, int m, int ldx, double *__restrict__ Y, int ldy) {
+  const int tot = n * m, nt = blockDim.x;
+  for (int e0 = threadIdx.x; e0 < tot; e0 += 4 * nt) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u * nt;
+      v[u] = (e < tot) ? X[e % n + (size_t)ldx * (e / n)] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u * nt;
+      if (e < tot) Y[e % n + (size_t)ldy * (e / n)] = v[u];
+    }
+  }
 }
 
 // Block-wide argmax: the largest v, the smallest p among equal v; the result
@@ -457,17 +520,9 @@ struct LStepArgs {
 __global__ __launch_bounds__(kLT) void lk_step(LStepArgs a) {
   const int d = a.d;
   double *A = a.W0, *X = a.W1;
-  __shared__ int bad, accept;
-  if (threadIdx.x == 0) bad = 0;
-  __syncthreads();
-  for (int e = threadIdx.x; e < d * d; e += blockDim.x) {
-    const int r = e % d, c = e / d;
-    const double g = (r >= c) ? a.G[e] : a.G[c + (size_t)d * r];
-    if (!lfinite(g)) bad = 1;
-    A[e] = g;
-  }
-  __syncthreads();
-  if (bad) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __shared__ int accept;
+  if (lload_sym(a.G, d, A)) {
     if (threadIdx.x == 0) {
       a.dec[2] |= 1;
       a.dec[0] = 1;
@@ -476,28 +531,35 @@ __global__ __launch_bounds__(kLT) void lk_step(LStepArgs a) {
     }
     return;
   }
-  // Gershgorin bounds and ||G||_1 (= ||G||_inf, G symmetric) from the row sums
-  double tp = 0.0, glo = DBL_MAX, ghi = 0.0, g1 = 0.0;
-  for (int r = threadIdx.x; r < d; r += blockDim.x) {
+  // Gershgorin bounds and ||G||_1 (= ||G||_inf) from the off-diagonal
+  // absolute sums of the rows, which are those of the columns (G symmetric):
+  // one wave per column, its loads in flight at once.  kappa(G) >= max_j G_jj
+  // / min_j G_jj (each G_jj is a Rayleigh quotient): when that already
+  // exceeds 1/tau1 the Cholesky route cannot be taken and is not tried.
+  double tp = 0.0, glo = DBL_MAX, ghi = 0.0, g1 = 0.0, gdx = 0.0, gdn = DBL_MAX;
+  for (int c = wave; c < d; c += nw) {
+    double v[kLMax / 64];
+#pragma unroll
+    for (int m = 0; m < kLMax / 64; ++m) {
+      const int r = lane + 64 * m;
+      v[m] = (r < d && r != c) ? fabs(A[r + (size_t)d * c]) : 0.0;
+    }
     double off = 0.0;
-    for (int c = 0; c < d; ++c)
-      if (c != r) off += fabs(A[r + (size_t)d * c]);
-    const double drr = A[r + (size_t)d * r];
-    tp += drr;
-    glo = fmin(glo, drr - off);
-    ghi = fmax(ghi, drr + off);
-    g1 = fmax(g1, fabs(drr) + off);
+#pragma unroll
+    for (int m = 0; m < kLMax / 64; ++m) off += v[m];
+    for (int o = 32; o > 0; o >>= 1) off += __shfl_xor(off, o, 64);
+    const double drr = A[c + (size_t)d * c];
+    if (lane == 0) {
+      tp += drr;
+      glo = fmin(glo, drr - off);
+      ghi = fmax(ghi, drr + off);
+      g1 = fmax(g1, fabs(drr) + off);
+      gdx = fmax(gdx, drr);
+      gdn = fmin(gdn, drr);
+    }
   }
   const double trG = lsum(tp), gmin = -lmax(-glo), gmax = lmax(ghi);
   g1 = lmax(g1);
-  // kappa(G) >= max_j G_jj / min_j G_jj (each G_jj is a Rayleigh quotient):
-  // when that already exceeds 1/tau1 the Cholesky route cannot be taken and
-  // is not tried
-  double gdx = 0.0, gdn = DBL_MAX;
-  for (int j = threadIdx.x; j < d; j += blockDim.x) {
-    gdx = fmax(gdx, A[j + (size_t)d * j]);
-    gdn = fmin(gdn, A[j + (size_t)d * j]);
-  }
   gdx = lmax(gdx);
   gdn = -lmax(-gdn);
   __shared__ double Sbuf[kLdsB];
@@ -541,19 +603,13 @@ __global__ __launch_bounds__(kLT) void lk_step(LStepArgs a) {
   __syncthreads();
   const int b = a.b;
   if (accept) {
-    for (int e = threadIdx.x; e < d * d; e += blockDim.x) {
-      const int r = e % d, c = e / d;
-      a.Fstep[r + (size_t)d * c] = X[c + (size_t)d * r];  // F = L^{-T}
-    }
+    ltrans(X, d, d, d, a.Fstep, d);  // F = L^{-T}
     // R = L^T (first pass), T = R^T = L; at a refinement pass R = L^T Rc is
     // left to the host (dec[8] = 1: one dgemm with L in W0)
-    if (!a.Rc)
-      for (int e = threadIdx.x; e < d * b; e += blockDim.x) {
-        const int r = e % d, col = e / d;
-        const double v = A[col + (size_t)d * r];
-        a.Rnext[r + (size_t)d * col] = v;
-        if (a.Tdst) a.Tdst[col + (size_t)b * r] = v;
-      }
+    if (!a.Rc) {
+      ltrans(A, b, d, d, a.Rnext, d);
+      if (a.Tdst) lcopy(A, b, d, d, a.Tdst, b);
+    }
     if (threadIdx.x == 0) {
       a.dec[0] = d;
       a.dec[1] = 1;
@@ -562,11 +618,7 @@ __global__ __launch_bounds__(kLT) void lk_step(LStepArgs a) {
     return;
   }
   // restore G
-  for (int e = threadIdx.x; e < d * d; e += blockDim.x) {
-    const int r = e % d, c = e / d;
-    A[e] = (r >= c) ? a.G[e] : a.G[c + (size_t)d * r];
-  }
-  __syncthreads();
+  lload_sym(a.G, d, A);
   if (a.pass <= a.shift_pass) {
     // shifted CholeskyQR: the next pass refines
     const double shift = 2.0 * d * a.ugram * trG;
@@ -574,11 +626,8 @@ __global__ __launch_bounds__(kLT) void lk_step(LStepArgs a) {
     __syncthreads();
     if (shift > 0.0 && lchol(A, d, Sbuf)) {
       linv(A, X, d, d);
-      for (int e = threadIdx.x; e < d * d; e += blockDim.x) {
-        const int r = e % d, c = e / d;
-        a.Fstep[r + (size_t)d * c] = X[c + (size_t)d * r];
-        if (!a.Rc) a.Rnext[r + (size_t)d * c] = A[c + (size_t)d * r];  // R = L^T (Rc = I)
-      }
+      ltrans(X, d, d, d, a.Fstep, d);
+      if (!a.Rc) ltrans(A, d, d, d, a.Rnext, d);  // R = L^T (Rc = I)
       if (threadIdx.x == 0) {
         a.dec[0] = d;
         a.dec[1] = 0;
@@ -588,11 +637,7 @@ __global__ __launch_bounds__(kLT) void lk_step(LStepArgs a) {
       return;
     }
     // a Gram too far from positive definite for the shift: pivoted below
-    for (int e = threadIdx.x; e < d * d; e += blockDim.x) {
-      const int r = e % d, c = e / d;
-      A[e] = (r >= c) ? a.G[e] : a.G[c + (size_t)d * r];
-    }
-    __syncthreads();
+    lload_sym(a.G, d, A);
   }
   // rank-revealing pivoted Cholesky
   int k = lpivchol(A, d, a.tau2, a.perm);
@@ -614,21 +659,39 @@ __global__ __launch_bounds__(kLT) void lk_step(LStepArgs a) {
   linv(A, X, k, d);
   double x1, xi, xf, gk = 0.0;
   lnorms(X, k, d, &x1, &xi, &xf);
-  for (int c = threadIdx.x; c < k; c += blockDim.x) {
-    double s = 0.0;
-    for (int r = 0; r < k; ++r) {
-      const int pr = a.perm[r], pc = a.perm[c];
-      s += fabs((pr >= pc) ? a.G[pr + (size_t)d * pc] : a.G[pc + (size_t)d * pr]);
+  // ||G(perm, perm)(0:k, 0:k)||_1, one wave per column
+  for (int c = wave; c < k; c += nw) {
+    const int pc = a.perm[c];
+    double v[kLMax / 64];
+#pragma unroll
+    for (int m = 0; m < kLMax / 64; ++m) {
+      const int r = lane + 64 * m;
+      const int pr = (r < k) ? a.perm[r] : 0;
+      v[m] = (r < k) ? fabs((pr >= pc) ? a.G[pr + (size_t)d * pc] : a.G[pc + (size_t)d * pr]) : 0.0;
     }
+    double s = 0.0;
+#pragma unroll
+    for (int m = 0; m < kLMax / 64; ++m) s += v[m];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
     gk = fmax(gk, s);
   }
   gk = lmax(gk);
   const int dn = (a.pass >= 3 || (a.pass >= 2 && gk * x1 * xi * a.tau1 <= 1.0)) ? 1 : 0;
   for (int e = threadIdx.x; e < d * k; e += blockDim.x) a.Fstep[e] = 0.0;
   __syncthreads();
-  for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
-    const int i = e % k, c = e / k;
-    a.Fstep[a.perm[i] + (size_t)d * c] = (c >= i) ? X[c + (size_t)d * i] : 0.0;
+  // F(perm[i], c) = X(c, i) for c >= i (the rest stays zero), X read in order
+  for (int e0 = threadIdx.x; e0 < k * k; e0 += 4 * (int)blockDim.x) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u * (int)blockDim.x, c = e % k, i = e / k;
+      v[u] = (e < k * k && c >= i) ? X[c + (size_t)d * i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u * (int)blockDim.x, c = e % k, i = e / k;
+      if (e < k * k && c >= i) a.Fstep[a.perm[i] + (size_t)d * c] = v[u];
+    }
   }
   // R' = L(:, 0:k)^T Rc(perm, :) (Rc = I at the first pass) is left to the
   // host (dec[8] = 2: one dgemm with L in W0 and the permuted rows in Rp);
@@ -636,9 +699,18 @@ __global__ __launch_bounds__(kLT) void lk_step(LStepArgs a) {
   // entries and is cleared first
   for (int e = threadIdx.x; e < d * k; e += blockDim.x)
     if (e % d < e / d) A[e] = 0.0;
-  for (int e = threadIdx.x; e < d * b; e += blockDim.x) {
-    const int j = e % d, col = e / d;
-    a.Rp[e] = a.Rc ? a.Rc[a.perm[j] + (size_t)d * col] : (a.perm[j] == col ? 1.0 : 0.0);
+  for (int e0 = threadIdx.x; e0 < d * b; e0 += 4 * (int)blockDim.x) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u * (int)blockDim.x, j = e % d, col = e / d;
+      v[u] = (e < d * b) ? (a.Rc ? a.Rc[a.perm[j] + (size_t)d * col] : (a.perm[j] == col ? 1.0 : 0.0)) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u * (int)blockDim.x;
+      if (e < d * b) a.Rp[e] = v[u];
+    }
   }
   if (threadIdx.x == 0) {
     a.dec[0] = k;
@@ -844,6 +916,21 @@ __global__ __launch_bounds__(kJT) void lk_jacobi_round(double *__restrict__ A, d
   const double tol2 = thr[0] * thr[0], floor2 = thr[1];
   auto gcol = [&](int l) { return l < kJW ? P * kJW + l : Q * kJW + (l - kJW); };
   if (sweep > 0 && flags[sweep - 1] == 0) return;
+  // U(:, P u Q) is read now, in flight during the rotations (only this
+  // workgroup touches these columns in this round): wave wv takes the
+  // 16-row tiles wv, wv + 4, ... of U (k x k, ld k); bf[ti][ks] = U(row, held
+  // column 4 ks + g)
+  constexpr int kTU = kLMax / 16 / (kJT / 64);
+  double bf[kTU][kJC / 4];
+#pragma unroll
+  for (int ti = 0; ti < kTU; ++ti) {
+    const int row = 16 * (wv + 4 * ti) + j;
+#pragma unroll
+    for (int ks = 0; ks < kJC / 4; ++ks) {
+      const int c = gcol(4 * ks + g);
+      bf[ti][ks] = (c < k && row < k) ? U[row + (size_t)k * c] : 0.0;
+    }
+  }
   int rotated = 0;
   double ap[kJR], aq[kJR], jp[2], jq[2];
   if (round == 0) {
@@ -948,22 +1035,17 @@ __global__ __launch_bounds__(kJT) void lk_jacobi_round(double *__restrict__ A, d
   }
   if (rotated && j == 0) flags[sweep] = 1;
   if (!__syncthreads_or(rotated)) return;  // J = I: U unchanged
-  // U(:, P u Q) = U(:, P u Q) J, computed as its transpose J^T U^T; wave wv
-  // takes the 16-row tiles wv, wv + 4, ... of U (k x k, ld k)
-  for (int t = wv; 16 * t < k; t += kJT / 64) {
-    const int row = 16 * t + j;
-    double bf[kJC / 4];  // bf[ks] = U(row, held column 4 ks + g)
+  // U(:, P u Q) = U(:, P u Q) J, computed as its transpose J^T U^T
 #pragma unroll
-    for (int ks = 0; ks < kJC / 4; ++ks) {
-      const int c = gcol(4 * ks + g);
-      bf[ks] = (c < k && row < k) ? U[row + (size_t)k * c] : 0.0;
-    }
+  for (int ti = 0; ti < kTU; ++ti) {
+    const int row = 16 * (wv + 4 * ti) + j;
+    if (16 * (wv + 4 * ti) >= k) break;
 #pragma unroll
     for (int ct = 0; ct < kJC / 16; ++ct) {
       ld4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int ks = 0; ks < kJC / 4; ++ks)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(hJ[16 * ct + j][4 * ks + g], bf[ks], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(hJ[16 * ct + j][4 * ks + g], bf[ti][ks], acc, 0, 0, 0);
       // register r: U(row, held column 16 ct + 4 r + g)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
