@@ -605,7 +605,7 @@ __global__ __launch_bounds__(kLT) void lk_step(LStepArgs a) {
   if (accept) {
     ltrans(X, d, d, d, a.Fstep, d);  // F = L^{-T}
     // R = L^T (first pass), T = R^T = L; at a refinement pass R = L^T Rc is
-    // left to the host (dec[8] = 1: one dgemm with L in W0)
+    // left to the host (dec[8] = 1: one small product with L in W0)
     if (!a.Rc) {
       ltrans(A, b, d, d, a.Rnext, d);
       if (a.Tdst) lcopy(A, b, d, d, a.Tdst, b);
@@ -694,7 +694,7 @@ __global__ __launch_bounds__(kLT) void lk_step(LStepArgs a) {
     }
   }
   // R' = L(:, 0:k)^T Rc(perm, :) (Rc = I at the first pass) is left to the
-  // host (dec[8] = 2: one dgemm with L in W0 and the permuted rows in Rp);
+  // host (dec[8] = 2: one small product with L in W0 and the permuted rows in Rp);
   // the strict upper part of L's k columns still holds Schur-complement
   // entries and is cleared first
   for (int e = threadIdx.x; e < d * k; e += blockDim.x)
