@@ -828,10 +828,11 @@ __device__ inline void lrr_pair(int r, int kq, int nn, int *p, int *q) {
 // holds block P and block Q of the round-robin pairing, and each 16-lane row
 // of its waves one column pair (lane j: rows j, j + 16, ...), so a wave
 // rotates four pairs at once.  The P columns stay; in kJW steps every (P, Q)
-// column pair is rotated once, the Q columns moving one pair down through LDS
-// after each step.  Round 0 of a sweep first rotates the pairs inside P and
-// inside Q (kJW - 1 steps in LDS), so a sweep of nbp - 1 rounds rotates each
-// of the k(k-1)/2 pairs once.  The three inner products of a pair are row
+// column pair is rotated once, the Q columns moving between the rows of a
+// wave by lane shuffles and between waves through LDS every fourth step.
+// Round 0 of a sweep first rotates the pairs inside P and inside Q (kJW - 1
+// steps in LDS), so a sweep of nbp - 1 rounds rotates each of the k(k-1)/2
+// pairs once.  The three inner products of a pair are row
 // sums by DPP (bitwise the same in the row's 16 lanes, so the rotation
 // decision is uniform over the pair).  A pair is rotated when |a_p^T a_q| >
 // thr[0] ||a_p|| ||a_q|| and both squared norms exceed thr[1].  The rotations
@@ -997,25 +998,38 @@ __global__ __launch_bounds__(kJT) void lk_jacobi_round(double *__restrict__ A, d
       jq[m] = (j + 16 * m == kJW + pr) ? 1.0 : 0.0;
     }
   }
-  // cross steps: at step s pair pr holds P column pr and Q column (pr + s) % kJW
+  // cross steps, four phases of four: in phase ph, step sg, pair pr = 4 wv + g
+  // holds P column pr and Q column 4 ((wv + ph) & 3) + ((g + sg) & 3).  Within
+  // a phase the Q columns move one 16-lane row up inside the wave (lane
+  // shuffles, no barrier); between phases each wave takes the next wave's Q
+  // columns through LDS, one row further on, so each (P, Q) pair meets once.
+  static_assert(kJW == 16 && kJT == 256, "four waves of four pairs");
   double(*xA)[kJW][kLMax] = reinterpret_cast<double(*)[kJW][kLMax]>(&hA[0][0]);
   double(*xJ)[kJW][kJC] = reinterpret_cast<double(*)[kJW][kJC]>(&hJ[0][0]);
-  for (int s = 0; s < kJW; ++s) {
-    if (ljac_rotate(ap, aq, jp, jq, tol2, floor2)) rotated = 1;
-    if (s + 1 < kJW) {
-      const int buf = s & 1, src = (pr + 1) % kJW;
+  for (int ph = 0; ph < 4; ++ph) {
+    for (int sg = 0; sg < 4; ++sg) {
+      if (ljac_rotate(ap, aq, jp, jq, tol2, floor2)) rotated = 1;
+      if (sg < 3) {
+        const int src = (lane + 16) & 63;
 #pragma unroll
-      for (int m = 0; m < kJR; ++m) xA[buf][pr][j + 16 * m] = aq[m];
+        for (int m = 0; m < kJR; ++m) aq[m] = __shfl(aq[m], src, 64);
 #pragma unroll
-      for (int m = 0; m < 2; ++m) xJ[buf][pr][j + 16 * m] = jq[m];
-      __syncthreads();
+        for (int m = 0; m < 2; ++m) jq[m] = __shfl(jq[m], src, 64);
+      } else if (ph < 3) {
+        const int buf = ph & 1, from = 4 * ((wv + 1) & 3) + ((g + 1) & 3);
 #pragma unroll
-      for (int m = 0; m < kJR; ++m) aq[m] = xA[buf][src][j + 16 * m];
+        for (int m = 0; m < kJR; ++m) xA[buf][pr][j + 16 * m] = aq[m];
 #pragma unroll
-      for (int m = 0; m < 2; ++m) jq[m] = xJ[buf][src][j + 16 * m];
+        for (int m = 0; m < 2; ++m) xJ[buf][pr][j + 16 * m] = jq[m];
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < kJR; ++m) aq[m] = xA[buf][from][j + 16 * m];
+#pragma unroll
+        for (int m = 0; m < 2; ++m) jq[m] = xJ[buf][from][j + 16 * m];
+      }
     }
   }
-  const int qw = kJW + (pr + kJW - 1) % kJW;  // local index of the Q column held at the end
+  const int qw = kJW + 4 * ((wv + 3) & 3) + ((g + 3) & 3);  // local index of the Q column held at the end
   {
     const int c0 = gcol(pr), c1 = gcol(qw);
 #pragma unroll
