@@ -865,13 +865,18 @@ __device__ __forceinline__ double lrow_total(double x) {
 
 __device__ __forceinline__ bool ljac_rotate(double *x, double *y, double *jx, double *jy, double tol2,
                                             double floor2) {
-  double al = 0.0, be = 0.0, ga = 0.0;
+  // two partial sums per product: half the dependent chain
+  double al0 = 0.0, be0 = 0.0, ga0 = 0.0, al1 = 0.0, be1 = 0.0, ga1 = 0.0;
 #pragma unroll
-  for (int m = 0; m < kJR; ++m) {
-    al += x[m] * x[m];
-    be += y[m] * y[m];
-    ga += x[m] * y[m];
+  for (int m = 0; m < kJR; m += 2) {
+    al0 += x[m] * x[m];
+    be0 += y[m] * y[m];
+    ga0 += x[m] * y[m];
+    al1 += x[m + 1] * x[m + 1];
+    be1 += y[m + 1] * y[m + 1];
+    ga1 += x[m + 1] * y[m + 1];
   }
+  double al = al0 + al1, be = be0 + be1, ga = ga0 + ga1;
   al = lrow_total(al);
   be = lrow_total(be);
   ga = lrow_total(ga);
