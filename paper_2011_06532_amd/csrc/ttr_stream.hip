@@ -55,8 +55,9 @@ __global__ void k_add(int n, int N, double alpha, double beta, const double *__r
   }
 }
 
-// The same sum for even ranks (and even I on the first core), two
-// consecutive rows at a time with 16-byte loads and stores.  A pair never
+// The same sum for even ranks (and even I on the first core) and 16-byte
+// aligned cores, two consecutive rows at a time with 16-byte loads and
+// stores.  A pair never
 // straddles the X / Y / zero blocks because the block sizes are even.  The
 // row/slice split of the pair index uses a float reciprocal with an exact
 // integer correction (pair counts per column stay below 2^24).
@@ -524,7 +525,10 @@ void launch_add(hipStream_t s, int n, int N, double alpha, double beta, const do
   else if (n == N - 1) { zr0 = rx0 + ry0; zr1 = 1; }
   else { zr0 = rx0 + ry0; zr1 = rx1 + ry1; }
   const long long colsz = (long long)zr0 * I;
-  const bool pairs = N > 1 && (n == 0 ? (I % 2 == 0) : (rx0 % 2 == 0 && ry0 % 2 == 0)) && colsz / 2 < (1LL << 24);
+  // 16-byte accesses: even extents and 16-byte aligned cores
+  const bool aligned = (((uintptr_t)X | (uintptr_t)Y | (uintptr_t)Z) % 16) == 0;
+  const bool pairs = N > 1 && aligned && (n == 0 ? (I % 2 == 0) : (rx0 % 2 == 0 && ry0 % 2 == 0)) &&
+                     colsz / 2 < (1LL << 24);
   if (pairs) {
     const long long bx = std::min((colsz / 2 + kThreads - 1) / kThreads, 4096LL);
     hipLaunchKernelGGL(k_add_pairs, dim3((unsigned)std::max(bx, 1LL), (unsigned)zr1), dim3(kThreads), 0, s, n, N,

@@ -221,6 +221,63 @@ def test_orthogonalize_rank_deficient(ttr, h):
         assert np.linalg.norm(Hn @ Hn.T - np.eye(Hn.shape[0])) < 1e-12
 
 
+def _offset_tt(ttr, cores_np=None, I=None, caps=None):
+    """A TT whose device cores start 8 bytes into their allocations (8-byte
+    aligned, not 16): from host cores, or empty with the given capacities."""
+    import torch
+    cores = []
+    if cores_np is not None:
+        R = [1]
+        for c in cores_np:
+            flat = torch.from_numpy(np.ascontiguousarray(np.asarray(c).reshape(-1, order="F")))
+            buf = torch.empty(flat.numel() + 1, dtype=torch.float64, device="cuda")
+            buf[1:].copy_(flat)
+            cores.append(buf[1:])
+            R.append(int(c.shape[2]))
+        return ttr.TT(cores, [int(c.shape[1]) for c in cores_np], R)
+    for c in caps:
+        cores.append(torch.empty(int(c) + 1, dtype=torch.float64, device="cuda")[1:])
+    return ttr.TT(cores, I, [1] * (len(I) + 1))
+
+
+@pytest.mark.parametrize("rank", [6, 80])
+def test_cores_not_16_byte_aligned(ttr, h, rank):
+    # inputs and outputs 8 bytes into their allocations: the 16-byte access
+    # paths (paired sums, paired Gram loads, streaming copies) must take their
+    # scalar forms; every result against the oracle
+    print(f"cores at 8-byte offsets, sum ranks {rank}", flush=True)
+    rng = np.random.default_rng(108)
+    I = [40, 30, 50, 20]
+    N = len(I)
+    A = rand_tt(rng, I, [rank // 2] * (N - 1))
+    B = rand_tt(rng, I, [rank // 2] * (N - 1))
+    gA, gB = _offset_tt(ttr, A), _offset_tt(ttr, B)
+    assert all(c.data_ptr() % 16 == 8 for c in gA.cores)
+    Rs = [1] + [rank] * (N - 1) + [1]
+    caps = [Rs[n] * I[n] * Rs[n + 1] for n in range(N)]
+    out = _offset_tt(ttr, I=I, caps=caps)
+    Z = h.add(1.0, gA, -0.5, gB, out=out)
+    X = O.add(1.0, A, -0.5, B)
+    for g, e in zip(Z.to_numpy(), X):
+        assert np.array_equal(g, e)
+    if rank <= 16:
+        Hc = [R0 * R1 for R0, R1 in zip([1] + [rank // 2] * (N - 1) + [1], [1] + [rank // 2] * (N - 1) + [1])]
+        hcaps = [Hc[n] * I[n] * Hc[n + 1] for n in range(N)]
+        Hg = h.hadamard(gA, gB, out=_offset_tt(ttr, I=I, caps=hcaps))
+        for g, e in zip(Hg.to_numpy(), O.hadamard(A, B)):
+            assert np.array_equal(g, e)
+    nrm2 = O.dot(X, X)
+    assert math.isclose(h.dot(Z, Z), nrm2, rel_tol=1e-12)
+    for direction in ("RLR", "LRL", "RLR_EXPLICIT"):
+        Y = h.round(Z, 1e-8, direction, out=_offset_tt(ttr, I=I, caps=caps))
+        ref = O.round_tt(X, 1e-8, "LRL" if direction == "LRL" else "RLR")
+        got = Y.to_numpy()
+        assert O.ranks(got) == O.ranks(ref), direction
+        assert O.diff_norm(got, ref) <= 1e-10 * O.norm_ortho(ref), direction
+    T = h.orthogonalize(_offset_tt(ttr, X), "right")
+    assert O.diff_norm(T.to_numpy(), X) <= 1e-12 * math.sqrt(nrm2) * N
+
+
 def test_argument_errors(ttr, h):
     rng = np.random.default_rng(106)
     X = ttr.TT.from_numpy(rand_tt(rng, [5, 6], [3]))
