@@ -202,3 +202,33 @@ def test_batched_replan_while_previous_batch_runs(ttr):
     check_against_oracle(XA, [Y.to_numpy() for Y in YA], tol, 1e-10)
     check_against_oracle(XB, [Y.to_numpy() for Y in YB], tol, 1e-10)
     hd.close()
+
+
+def test_batched_cores_not_16_byte_aligned(ttr, h):
+    # inputs and outputs that start 8 bytes into their allocations: the paired
+    # 16-byte loads of the batched kernels check each tensor's alignment
+    import torch
+    print("batched, cores at 8-byte offsets", flush=True)
+    Xs, _ = batch_inputs(12, 96, start=40)
+
+    def offset_tt(cores_np=None, I=None, caps=None):
+        cores = []
+        if cores_np is not None:
+            R = [1]
+            for c in cores_np:
+                flat = torch.from_numpy(np.ascontiguousarray(np.asarray(c).reshape(-1, order="F")))
+                buf = torch.empty(flat.numel() + 1, dtype=torch.float64, device="cuda")
+                buf[1:].copy_(flat)
+                cores.append(buf[1:])
+                R.append(int(c.shape[2]))
+            return ttr.TT(cores, [int(c.shape[1]) for c in cores_np], R)
+        for c in caps:
+            cores.append(torch.empty(int(c) + 1, dtype=torch.float64, device="cuda")[1:])
+        return ttr.TT(cores, I, [1] * (len(I) + 1))
+
+    g = [offset_tt(X) for X in Xs]
+    outs = [offset_tt(I=X.I, caps=[X.R[n] * X.I[n] * X.R[n + 1] for n in range(X.N)]) for X in g]
+    assert all(c.data_ptr() % 16 == 8 for X in g + outs for c in X.cores)
+    Ys, ranks = h.round_batched(g, synth.TOL[3], "fp64", outs=outs)
+    ttr.Handle.sync_ranks(Ys, ranks)
+    check_against_oracle(Xs, [Y.to_numpy() for Y in Ys], synth.TOL[3], 1e-10)
